@@ -1,0 +1,254 @@
+/*
+ * chromstrip.h -- C ABI of the MI355X chromatic-strip library.
+ *
+ * Computes the chromatic polynomial Z = P_G(q) of m x r rectangles of the
+ * square or triangular lattice (free boundaries), r = 1..n_max, at integer
+ * points q modulo primes p < 2^31, by the sparse transfer-matrix
+ * factorisation of J. L. Jacobsen, arXiv 1005.3609:
+ *   - Z = <e0| T_last T^{r-1} |e0>                      (Sec. 3, eq. Z_from_T)
+ *   - square:     T = T_m ... T_1, T_i = (prod_{j!=i} P_{j,j+1}) V_i H_{i,i+1},
+ *                 T_m = (prod_j P_{j,j+1}) V_m          (Sec. 3.2, eqs. T_sq_decomp, T_sq_proj)
+ *   - triangular: T_i = P_all V_i H_{i-1,i} H_{i,i+1}   (Sec. 3.3)
+ *   - T_last = T_m^last ... T_1^last,
+ *     T_i^last = (prod_{j>i} P_{j,j+1}) D_i H_{i,i+1}   (Sec. 3.2, eqs. T_last, T_last_i)
+ *   - states: non-crossing non-nearest-neighbour partitions, ranked by the
+ *     ordering of Sec. 3.4 (eq. M_recurs); residues mod p < 2^31 (Sec. 3.5).
+ * The weights are evaluated at integer q in un-normalised form (a component
+ * pays its factor q when it leaves the layer), which equals the paper's
+ * normalised P-tilde times q^{|V|} and allows q = 0.
+ *
+ * Conventions for every call:
+ *   - Return value: 0 on success, a negative CHROM_E* code on failure; then
+ *     chromatic_last_error() describes it (thread-local, valid until the
+ *     next call on the same thread).  No C++ exception crosses this ABI.
+ *   - lattice is CHROM_SQUARE or CHROM_TRIANGULAR; 1 <= m <= CHROM_MAX_M;
+ *     n_max >= 1 (n_max = 0 is accepted and writes nothing).
+ *   - Instances are (q_points[a], primes[b]), a < nq, b < np; results are
+ *     laid out out[(r-1)*nq*np + a*np + b] = P_{m x r}(q_a) mod p_b.
+ *     Each prime must satisfy 2 < p < 2^31 (not checked for primality);
+ *     q is reduced mod p.
+ *   - The caller owns every input and output buffer.  The library owns only
+ *     its cache of factor maps (host and device copies, per lattice, m and
+ *     device), kept until chromatic_release_maps() or process exit.
+ *   - Host-pointer arguments are read before the call returns.  Device
+ *     pointers must stay valid until the work queued on `stream` finishes.
+ */
+#ifndef CHROMSTRIP_H
+#define CHROMSTRIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CHROM_MAX_M 20
+
+enum {
+  CHROM_OK = 0,
+  CHROM_EINVAL = -1,        /* bad argument */
+  CHROM_ENOMEM = -2,        /* host or device allocation failed / workspace too small */
+  CHROM_EDEVICE = -3,       /* a HIP call failed */
+  CHROM_EUNSUPPORTED = -4,  /* size beyond what the library handles */
+  CHROM_EBUSY = -5,         /* a device-side wait exceeded its spin limit */
+};
+
+enum { CHROM_SQUARE = 0, CHROM_TRIANGULAR = 1 };
+
+/* Execution modes of chromatic_strip_async. */
+enum {
+  CHROM_MODE_PLAIN = 0,      /* per-instance vectors [S], one launch per factor per instance */
+  CHROM_MODE_BATCHED = 1,    /* instance-minor vectors, one launch per factor for all instances */
+  CHROM_MODE_GRAPH = 2,      /* as BATCHED, one row captured in a hipGraph and replayed */
+  CHROM_MODE_PERSISTENT = 3, /* one persistent launch runs the whole sweep */
+};
+
+/* Launch shape of the batched and persistent kernels.  Zero fields take
+ * the library's defaults.  Every choice gives bit-identical results. */
+typedef struct chrom_tuning {
+  int lanes_v;          /* instances per lane: 1, 2 or 4 (chunk width W = 64 * lanes_v) */
+  int targets_per_wave; /* consecutive target states handled by one wavefront, 1..64 */
+  int waves_per_block;  /* wavefronts per workgroup: 1, 2, 4 or 8 */
+  int grid_blocks;      /* persistent mode: workgroups in the grid (0 = fill the device) */
+  int readout_blocks;   /* read-out: workgroups per chunk for the dot product (0 = auto) */
+} chrom_tuning;
+
+/* ------------------------------------------------------------------------
+ * Whole-strip calls
+ * ---------------------------------------------------------------------- */
+
+/* Plain per-instance path, synchronous.  q_points[nq], primes[np] and
+ * out[n_max*nq*np] are host memory.  Allocates device memory internally and
+ * runs on the null stream of the current device. */
+int chromatic_strip(int lattice, int m, int n_max,
+                    const uint32_t* q_points, int nq,
+                    const uint32_t* primes, int np,
+                    uint32_t* out);
+
+/* Same result through the batched path (mode CHROM_MODE_BATCHED, GRAPH or
+ * PERSISTENT), synchronous, host buffers, internal allocation.  tune may be
+ * NULL. */
+int chromatic_strip_batched(int lattice, int m, int n_max,
+                            const uint32_t* q_points, int nq,
+                            const uint32_t* primes, int np,
+                            int mode, const chrom_tuning* tune,
+                            uint32_t* out);
+
+/* Device-workspace size in bytes needed by chromatic_strip_async for the
+ * same arguments (the persistent mode's work queue grows with n_max).
+ * Returns 0 on bad arguments. */
+size_t chromatic_workspace_bytes(int lattice, int m, int n_max, int nq, int np,
+                                 int mode, const chrom_tuning* tune);
+
+/* Asynchronous strip on `stream` (a hipStream_t; NULL = null stream).
+ * q_points/primes: host memory, read before return.  d_workspace: device
+ * memory of at least chromatic_workspace_bytes(...) bytes, 256-byte
+ * aligned, owned by the caller and not used by anything else until the
+ * stream has finished.  d_out: device memory [n_max][nq][np].  Builds and
+ * uploads the factor maps on first use of (lattice, m) on this device
+ * (synchronously).  Returns CHROM_ENOMEM if ws_bytes is too small. */
+int chromatic_strip_async(int lattice, int m, int n_max,
+                          const uint32_t* q_points, int nq,
+                          const uint32_t* primes, int np,
+                          int mode, const chrom_tuning* tune,
+                          void* d_workspace, size_t ws_bytes,
+                          void* stream, uint32_t* d_out);
+
+/* Measurement hook: queues `rows` rows of the per-site factor kernel
+ * (T_1..T_m of eq. T_sq_decomp, read-out fused into T_m) on `stream`, on a
+ * workspace that chromatic_strip_async has already run on in
+ * CHROM_MODE_BATCHED with the same lattice, m, instances and tuning.  Only
+ * the factor launches are queued, so a caller can bracket them with events.
+ * The vectors' contents are overwritten (the results are not meaningful). */
+int chromatic_factor_launches(int lattice, int m,
+                              const uint32_t* q_points, int nq,
+                              const uint32_t* primes, int np,
+                              int rows, const chrom_tuning* tune,
+                              void* d_workspace, size_t ws_bytes, void* stream);
+
+/* Builds (host) and uploads (current device) the factor maps of
+ * (lattice, m) ahead of time, so that later calls do no host work. */
+int chromatic_prepare(int lattice, int m);
+
+/* Frees every cached map on host and devices. */
+void chromatic_release_maps(void);
+
+/* ------------------------------------------------------------------------
+ * Many strips of uneven size in one persistent launch
+ * ---------------------------------------------------------------------- */
+typedef struct chrom_job {
+  int lattice;
+  int m;
+  int n_max;
+  const uint32_t* q_points;  /* host, nq entries */
+  int nq;
+  const uint32_t* primes;    /* host, np entries */
+  int np;
+  uint32_t* d_out;           /* device, [n_max][nq][np] */
+} chrom_job;
+
+/* Workspace bytes for chromatic_batch over these jobs. */
+size_t chromatic_batch_workspace_bytes(const chrom_job* jobs, int njobs,
+                                       const chrom_tuning* tune);
+
+/* Runs every job to completion in ONE persistent kernel launch on
+ * `stream`: each job is split into instance chunks of width 64*lanes_v,
+ * every (job, chunk) item walks its sweep step by step, and workgroups take
+ * (item, step, tile) tasks from a device queue ordered so that independent
+ * items overlap.  Same results as chromatic_strip for each job. */
+int chromatic_batch(const chrom_job* jobs, int njobs, const chrom_tuning* tune,
+                    void* d_workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Continuous-batching server step
+ * ---------------------------------------------------------------------- */
+typedef struct chrom_slot {
+  int lattice;
+  int m;
+  int n_max;
+  int rows_done;             /* in: rows already read out (0 for a new job); out: updated */
+  int nq, np;
+  const uint32_t* q_points;  /* host (read only when rows_done == 0) */
+  const uint32_t* primes;    /* host (read only when rows_done == 0) */
+  void* d_state;             /* device, chromatic_slot_state_bytes(...) bytes, kept between steps */
+  size_t state_bytes;
+  uint32_t* d_out;           /* device, [n_max][nq][np] */
+} chrom_slot;
+
+/* Device bytes a job keeps resident between server steps (two state
+ * vectors, the read-out vector, coefficient tables, scratch). */
+size_t chromatic_slot_state_bytes(int lattice, int m, int nq, int np,
+                                  const chrom_tuning* tune);
+
+/* Advances every slot by up to `rows` rows (a new slot first runs its
+ * set-up and reads out r = 1) in ONE persistent launch on `stream`, and
+ * updates rows_done.  Slots may differ in lattice, m and instance count. */
+int chromatic_server_step(chrom_slot* slots, int nslots, int rows,
+                          const chrom_tuning* tune, void* stream);
+
+/* Synchronises `stream` and reports whether a persistent launch on the
+ * current device had a dependency wait exceed its spin limit since the last
+ * check (CHROM_EBUSY; the flag is then cleared) -- a safety net that turns a
+ * would-be hang into an error.  The synchronous calls check it themselves. */
+int chromatic_device_status(void* stream);
+
+/* ------------------------------------------------------------------------
+ * Host-side introspection (no GPU needed): states and factor maps
+ * ---------------------------------------------------------------------- */
+
+/* Motzkin number M_k (eq. M_recurs), 0 <= k <= 40; -1 if out of range. */
+int64_t chromatic_motzkin(int k);
+
+/* Spaces: CHROM_SPACE_NCNNN (i ignored), CHROM_SPACE_SQ_INTER (square
+ * states after T_i, 1 <= i < m: NCNNN plus i~i+1, Sec. 3.4 last paragraph),
+ * CHROM_SPACE_LAST (states after T_i^last, 0 <= i <= m: points 1..i
+ * singletons, the rest NCNNN). */
+enum { CHROM_SPACE_NCNNN = 0, CHROM_SPACE_SQ_INTER = 1, CHROM_SPACE_LAST = 2 };
+
+/* Number of states of a space; < 0 on bad arguments. */
+int64_t chromatic_space_size(int m, int space, int i);
+
+/* Rank (0-based, in the paper's order) of the partition given by block
+ * labels lab[m] (any labelling; equal labels = same block).  Returns -1 if
+ * the partition is not in the space, < -1 on bad arguments. */
+int64_t chromatic_rank(int m, int space, int i, const uint8_t* lab);
+
+/* Writes the canonical block labels (first-appearance numbering) of the
+ * state of rank r into lab[m]. */
+int chromatic_unrank(int m, int space, int i, int64_t r, uint8_t* lab);
+
+/* Summary of the factor maps of (lattice, m), building them if needed. */
+typedef struct chrom_maps_info {
+  int n_factors;            /* m forward factors T_1..T_m */
+  int n_last;               /* m read-out factors (T_1^last..T_m^last, transposed) */
+  int n_codes;              /* coefficient codes in use */
+  int code_a[16], code_b[16]; /* code k means the coefficient a + b q */
+  int64_t total_nnz;
+  int64_t max_states;
+} chrom_maps_info;
+
+int chromatic_maps_info(int lattice, int m, chrom_maps_info* info);
+
+/* Copies one factor's map to caller buffers.  which = 0: forward factor
+ * T_{idx+1} as target-major CSR (rows = states after the factor, entries =
+ * source states before it).  which = 1: read-out factor T_{idx+1}^last,
+ * transposed (rows = states before it, entries = states after it).
+ * Entry word: bits 0..27 = column state rank, bits 28..31 = coefficient
+ * code.  Sizes are returned through n_rows, n_cols, nnz; pass NULL buffers
+ * to query sizes only.  row_ptr has n_rows+1 entries. */
+int chromatic_map_export(int lattice, int m, int which, int idx,
+                         int64_t* n_rows, int64_t* n_cols, int64_t* nnz,
+                         int32_t* row_ptr, uint32_t* entries);
+
+/* Thread-local description of the last error. */
+const char* chromatic_last_error(void);
+
+/* Library version string. */
+const char* chromatic_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHROMSTRIP_H */

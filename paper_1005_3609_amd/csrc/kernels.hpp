@@ -1,0 +1,483 @@
+// HIP kernels (gfx950, wave64) applying the per-site transfer-matrix
+// factors of arXiv 1005.3609 to residue vectors.
+//
+// Layouts.
+//   plain    one instance (q, p): vector [S] of uint32 residues.
+//   batched  instances in chunks of W = 64 V: [chunk][S][W]; a wavefront owns
+//            one chunk's row of a state, lane l holding instances l V .. l V+V-1,
+//            so every row read or written is one coalesced W*4-byte segment.
+// A factor is a target-major CSR matrix (gather form): out[t] = sum over the
+// row's entries of coef(code) * in[src].  Every lane of a wavefront works on
+// the same row and entry, so the row bounds and entry words are scalar loads
+// and the branch on the coefficient code is uniform.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "modarith.hpp"
+
+namespace cs {
+
+constexpr uint32_t kEntSrcMask = (1u << 28) - 1;
+constexpr int kCodes = 16;
+
+// ---------------------------------------------------------------------------
+// Vector helpers
+// ---------------------------------------------------------------------------
+template <int V>
+__device__ __forceinline__ void load_v(const uint32_t* ptr, uint32_t (&x)[V]) {
+  if constexpr (V == 1) {
+    x[0] = *ptr;
+  } else if constexpr (V == 2) {
+    uint2 t = *reinterpret_cast<const uint2*>(ptr);
+    x[0] = t.x;
+    x[1] = t.y;
+  } else {
+    uint4 t = *reinterpret_cast<const uint4*>(ptr);
+    x[0] = t.x;
+    x[1] = t.y;
+    x[2] = t.z;
+    x[3] = t.w;
+  }
+}
+
+template <int V>
+__device__ __forceinline__ void store_v(uint32_t* ptr, const uint32_t (&x)[V]) {
+  if constexpr (V == 1) {
+    *ptr = x[0];
+  } else if constexpr (V == 2) {
+    *reinterpret_cast<uint2*>(ptr) = make_uint2(x[0], x[1]);
+  } else {
+    *reinterpret_cast<uint4*>(ptr) = make_uint4(x[0], x[1], x[2], x[3]);
+  }
+}
+
+__device__ __forceinline__ int wave_id() {
+  return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+}
+__device__ __forceinline__ int lane_id() { return static_cast<int>(threadIdx.x) & 63; }
+
+// ---------------------------------------------------------------------------
+// Argument blocks
+// ---------------------------------------------------------------------------
+struct DevCsr {
+  const int32_t* row_ptr;
+  const uint32_t* ent;
+  int n_rows;
+  int n_cols;
+};
+
+// Per-instance constants of a batch, instance index inst = chunk W + lane V + j.
+//   p[inst], pinv[inst] = -p^{-1} mod 2^32, cval[k*ipad + inst] = code k's
+//   coefficient mod p, cshp[...] = floor(cval 2^32 / p).
+struct InstConsts {
+  const uint32_t* p;
+  const uint32_t* pinv;
+  const uint32_t* cval;
+  const uint32_t* cshp;
+  int ipad;
+};
+
+struct GatherArgs {
+  DevCsr csr;
+  const uint32_t* in;      // chunk 0, row 0
+  uint32_t* out;
+  long in_cstride;         // elements from one chunk to the next
+  long out_cstride;
+  InstConsts ic;
+  // Fused read-out (w == nullptr: none): partial[chunk*pc_stride + tile*W + lane V + j]
+  // = sum over the tile's rows of out * w (w in Montgomery form).
+  const uint32_t* w;
+  long w_cstride;
+  uint32_t* partial;
+  long p_cstride;
+  int rows_per_wave;
+};
+
+struct DotArgs {
+  const uint32_t* x;
+  const uint32_t* w;
+  long x_cstride;
+  long w_cstride;
+  int n_rows;
+  InstConsts ic;
+  uint32_t* partial;
+  long p_cstride;
+  int rows_per_wave;
+};
+
+struct FillArgs {
+  uint32_t* x;
+  long cstride;
+  int n_rows;              // rows to write: row 0 = v0, the rest 0
+  const uint32_t* v0;      // per instance (nullptr: 1)
+  int rows_per_wave;
+};
+
+struct ReduceArgs {
+  const uint32_t* partial;
+  long p_cstride;
+  int n_parts;
+  InstConsts ic;
+  uint32_t* out;           // out[inst] for inst < n_valid (this row)
+  int n_valid;
+};
+
+// ---------------------------------------------------------------------------
+// Tile bodies (one workgroup, rows [row0, row0 + waves*rows_per_wave))
+// ---------------------------------------------------------------------------
+template <int V>
+__device__ __forceinline__ void block_reduce_store(uint32_t (&red)[V], const uint32_t (&p)[V],
+                                                   uint32_t* dst, uint32_t* lds) {
+  const int lane = lane_id(), wave = wave_id(), nw = blockDim.x >> 6;
+  constexpr int W = 64 * V;
+#pragma unroll
+  for (int j = 0; j < V; ++j) lds[wave * W + lane * V + j] = red[j];
+  __syncthreads();
+  if (wave == 0) {
+    for (int k = 1; k < nw; ++k)
+#pragma unroll
+      for (int j = 0; j < V; ++j) red[j] = add_mod(red[j], lds[k * W + lane * V + j], p[j]);
+    store_v<V>(dst + lane * V, red);
+  }
+  __syncthreads();
+}
+
+template <int V>
+__device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* lds) {
+  constexpr int W = 64 * V;
+  const int lane = lane_id(), wave = wave_id();
+  const int inst0 = chunk * W + lane * V;
+  uint32_t p[V];
+  load_v<V>(a.ic.p + inst0, p);
+  const uint32_t* in = a.in + chunk * a.in_cstride + lane * V;
+  uint32_t* out = a.out + chunk * a.out_cstride + lane * V;
+  const int32_t* row_ptr = a.csr.row_ptr;
+  const uint32_t* ent = a.csr.ent;
+  const int nw = blockDim.x >> 6;
+  int r0 = (tile * nw + wave) * a.rows_per_wave;
+  int r1 = min(r0 + a.rows_per_wave, a.csr.n_rows);
+  uint32_t red[V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) red[j] = 0;
+  const bool fused = a.w != nullptr;
+  const uint32_t* wv = fused ? a.w + chunk * a.w_cstride + lane * V : nullptr;
+  uint32_t pinv[V];
+  if (fused) load_v<V>(a.ic.pinv + inst0, pinv);
+  for (int r = r0; r < r1; ++r) {
+    const int beg = row_ptr[r], end = row_ptr[r + 1];
+    uint32_t acc[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) acc[j] = 0;
+    int e = beg;
+    // Two entries per pass so that two row loads are in flight.
+    for (; e + 1 < end; e += 2) {
+      const uint32_t w0 = ent[e], w1 = ent[e + 1];
+      uint32_t x0[V], x1[V];
+      load_v<V>(in + static_cast<size_t>(w0 & kEntSrcMask) * W, x0);
+      load_v<V>(in + static_cast<size_t>(w1 & kEntSrcMask) * W, x1);
+      const uint32_t c0 = w0 >> 28, c1 = w1 >> 28;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint32_t c = h ? c1 : c0;
+        uint32_t* x = h ? x1 : x0;
+        if (c == 0) {
+#pragma unroll
+          for (int j = 0; j < V; ++j) acc[j] = add_mod(acc[j], x[j], p[j]);
+        } else if (c == 1) {
+#pragma unroll
+          for (int j = 0; j < V; ++j) acc[j] = sub_mod(acc[j], x[j], p[j]);
+        } else {
+          uint32_t cv[V], cs[V];
+          load_v<V>(a.ic.cval + c * a.ic.ipad + inst0, cv);
+          load_v<V>(a.ic.cshp + c * a.ic.ipad + inst0, cs);
+#pragma unroll
+          for (int j = 0; j < V; ++j) acc[j] = add_mod(acc[j], mul_shoup(x[j], cv[j], cs[j], p[j]), p[j]);
+        }
+      }
+    }
+    if (e < end) {
+      const uint32_t w0 = ent[e];
+      uint32_t x0[V];
+      load_v<V>(in + static_cast<size_t>(w0 & kEntSrcMask) * W, x0);
+      const uint32_t c = w0 >> 28;
+      if (c == 0) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) acc[j] = add_mod(acc[j], x0[j], p[j]);
+      } else if (c == 1) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) acc[j] = sub_mod(acc[j], x0[j], p[j]);
+      } else {
+        uint32_t cv[V], cs[V];
+        load_v<V>(a.ic.cval + c * a.ic.ipad + inst0, cv);
+        load_v<V>(a.ic.cshp + c * a.ic.ipad + inst0, cs);
+#pragma unroll
+        for (int j = 0; j < V; ++j) acc[j] = add_mod(acc[j], mul_shoup(x0[j], cv[j], cs[j], p[j]), p[j]);
+      }
+    }
+    store_v<V>(out + static_cast<size_t>(r) * W, acc);
+    if (fused) {
+      uint32_t wr[V];
+      load_v<V>(wv + static_cast<size_t>(r) * W, wr);
+#pragma unroll
+      for (int j = 0; j < V; ++j) red[j] = add_mod(red[j], mul_redc(acc[j], wr[j], p[j], pinv[j]), p[j]);
+    }
+  }
+  if (fused) block_reduce_store<V>(red, p, a.partial + chunk * a.p_cstride + static_cast<long>(tile) * W, lds);
+}
+
+template <int V>
+__device__ void dot_tile(const DotArgs& a, int chunk, int tile, uint32_t* lds) {
+  constexpr int W = 64 * V;
+  const int lane = lane_id(), wave = wave_id();
+  const int inst0 = chunk * W + lane * V;
+  uint32_t p[V], pinv[V];
+  load_v<V>(a.ic.p + inst0, p);
+  load_v<V>(a.ic.pinv + inst0, pinv);
+  const uint32_t* x = a.x + chunk * a.x_cstride + lane * V;
+  const uint32_t* w = a.w + chunk * a.w_cstride + lane * V;
+  const int nw = blockDim.x >> 6;
+  int r0 = (tile * nw + wave) * a.rows_per_wave;
+  int r1 = min(r0 + a.rows_per_wave, a.n_rows);
+  uint32_t red[V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) red[j] = 0;
+  for (int r = r0; r < r1; ++r) {
+    uint32_t xv[V], wv[V];
+    load_v<V>(x + static_cast<size_t>(r) * W, xv);
+    load_v<V>(w + static_cast<size_t>(r) * W, wv);
+#pragma unroll
+    for (int j = 0; j < V; ++j) red[j] = add_mod(red[j], mul_redc(xv[j], wv[j], p[j], pinv[j]), p[j]);
+  }
+  block_reduce_store<V>(red, p, a.partial + chunk * a.p_cstride + static_cast<long>(tile) * W, lds);
+}
+
+template <int V>
+__device__ void fill_tile(const FillArgs& a, int chunk, int tile) {
+  constexpr int W = 64 * V;
+  const int lane = lane_id(), wave = wave_id();
+  const int nw = blockDim.x >> 6;
+  uint32_t* x = a.x + chunk * a.cstride + lane * V;
+  int r0 = (tile * nw + wave) * a.rows_per_wave;
+  int r1 = min(r0 + a.rows_per_wave, a.n_rows);
+  for (int r = r0; r < r1; ++r) {
+    uint32_t v[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) v[j] = 0;
+    if (r == 0) {
+      if (a.v0)
+        load_v<V>(a.v0 + chunk * W + lane * V, v);
+      else
+#pragma unroll
+        for (int j = 0; j < V; ++j) v[j] = 1;
+    }
+    store_v<V>(x + static_cast<size_t>(r) * W, v);
+  }
+}
+
+// One workgroup per chunk; thread j < W sums instance j over the parts.
+template <int V>
+__device__ void reduce_tile(const ReduceArgs& a, int chunk) {
+  constexpr int W = 64 * V;
+  for (int j = threadIdx.x; j < W; j += blockDim.x) {
+    const int inst = chunk * W + j;
+    const uint32_t p = a.ic.p[inst];
+    const uint32_t* src = a.partial + chunk * a.p_cstride + j;
+    uint32_t s = 0;
+    for (int k = 0; k < a.n_parts; ++k) s = add_mod(s, src[static_cast<long>(k) * W], p);
+    if (inst < a.n_valid) a.out[inst] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Eager kernels: grid.x = tiles, grid.y = chunks
+// ---------------------------------------------------------------------------
+template <int V>
+__global__ void __launch_bounds__(512) k_gather(GatherArgs a) {
+  __shared__ uint32_t lds[8 * 64 * V];
+  gather_tile<V>(a, blockIdx.y, blockIdx.x, lds);
+}
+
+template <int V>
+__global__ void __launch_bounds__(512) k_dot(DotArgs a) {
+  __shared__ uint32_t lds[8 * 64 * V];
+  dot_tile<V>(a, blockIdx.y, blockIdx.x, lds);
+}
+
+template <int V>
+__global__ void __launch_bounds__(512) k_fill(FillArgs a) {
+  fill_tile<V>(a, blockIdx.y, blockIdx.x);
+}
+
+template <int V>
+__global__ void __launch_bounds__(512) k_reduce(ReduceArgs a) {
+  reduce_tile<V>(a, blockIdx.x);
+}
+
+// Reduce whose output row is taken from a device counter (hipGraph replays
+// write successive rows); thread 0 of block 0 does not bump the counter --
+// k_bump does, after every block has read it.
+template <int V>
+__global__ void __launch_bounds__(512) k_reduce_counted(ReduceArgs a, const int* row, long row_stride) {
+  ReduceArgs b = a;
+  b.out = a.out + static_cast<long>(*row) * row_stride;
+  reduce_tile<V>(b, blockIdx.x);
+}
+
+__global__ void k_bump(int* row) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *row += 1;
+}
+
+__global__ void k_set_int(int* dst, int value) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = value;
+}
+
+// ---------------------------------------------------------------------------
+// Plain (one instance) kernels
+// ---------------------------------------------------------------------------
+struct PlainConsts {
+  uint32_t p, pinv;
+  uint32_t cval[kCodes];
+  uint32_t cshp[kCodes];
+};
+
+__global__ void __launch_bounds__(256) k_gather_plain(DevCsr csr, const uint32_t* __restrict__ in,
+                                                      uint32_t* __restrict__ out, PlainConsts c) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= csr.n_rows) return;
+  const int beg = csr.row_ptr[r], end = csr.row_ptr[r + 1];
+  uint32_t acc = 0;
+  for (int e = beg; e < end; ++e) {
+    const uint32_t w = csr.ent[e];
+    const uint32_t x = in[w & kEntSrcMask];
+    const uint32_t code = w >> 28;
+    if (code == 0)
+      acc = add_mod(acc, x, c.p);
+    else if (code == 1)
+      acc = sub_mod(acc, x, c.p);
+    else
+      acc = add_mod(acc, mul_shoup(x, c.cval[code], c.cshp[code], c.p), c.p);
+  }
+  out[r] = acc;
+}
+
+__global__ void __launch_bounds__(256) k_fill_plain(uint32_t* x, int n, uint32_t v0) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) x[r] = (r == 0) ? v0 : 0u;
+}
+
+// Z = sum_s x[s] w[s] mod p with w in Montgomery form; one workgroup of
+// 256 threads.  Each lane strides over the states, then the wavefront folds
+// its 64 partial sums with cross-lane shuffles, and the four wavefront sums
+// meet in LDS.  The ragged tail is masked by a ballot of the lanes that own
+// a state.
+__global__ void __launch_bounds__(256) k_dot_plain(const uint32_t* __restrict__ x,
+                                                   const uint32_t* __restrict__ w, int n,
+                                                   uint32_t p, uint32_t pinv, uint32_t* out) {
+  __shared__ uint32_t part[4];
+  uint32_t s = 0;
+  const int base_full = (n / blockDim.x) * blockDim.x;
+  for (int i = threadIdx.x; i < base_full; i += blockDim.x) s = add_mod(s, mul_redc(x[i], w[i], p, pinv), p);
+  const int i = base_full + threadIdx.x;
+  const unsigned long long owners = __ballot(i < n);
+  if (owners != 0ull && i < n) s = add_mod(s, mul_redc(x[i], w[i], p, pinv), p);
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s = add_mod(s, __shfl_xor(s, off, 64), p);
+  if (lane_id() == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int k = 0; k < static_cast<int>(blockDim.x >> 6); ++k) t = add_mod(t, part[k], p);
+    *out = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent work-queue kernel
+// ---------------------------------------------------------------------------
+enum StepOp : int { kOpFill = 0, kOpGather = 1, kOpDot = 2, kOpReduce = 3 };
+
+struct Step {
+  int op;
+  int ntiles;
+  int dep0, dep1;          // global step indices that must be complete (-1: none)
+  int chunk;               // chunk index handed to the tile body
+  int pad_;
+  union {
+    GatherArgs g;
+    DotArgs d;
+    FillArgs f;
+    ReduceArgs r;
+  } u;
+};
+
+struct QueueArgs {
+  const Step* steps;
+  const int* order;        // task order: steps by order[k]
+  const long* start;       // start[k] = first task id of order[k]; start[nsteps] = total
+  int nsteps;
+  unsigned* done;          // completed tiles per global step index
+  unsigned* counter;       // next task id
+  unsigned* error;         // set to 1 when a wait exceeds its spin limit
+  long spin_limit;
+};
+
+__device__ __forceinline__ bool wait_done(const QueueArgs& q, int dep, unsigned need) {
+  if (dep < 0) return true;
+  long spins = 0;
+  while (__hip_atomic_load(q.done + dep, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+    __builtin_amdgcn_s_sleep(2);
+    if (++spins > q.spin_limit ||
+        __hip_atomic_load(q.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+      __hip_atomic_store(q.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+  }
+  return true;
+}
+
+template <int V>
+__global__ void __launch_bounds__(256) k_persistent(QueueArgs q) {
+  __shared__ uint32_t lds[4 * 64 * V];
+  __shared__ long s_task;
+  __shared__ int s_ok;
+  const long total = q.start[q.nsteps];
+  while (true) {
+    if (threadIdx.x == 0) s_task = static_cast<long>(atomicAdd(q.counter, 1u));
+    __syncthreads();
+    const long t = s_task;
+    if (t >= total) break;
+    // locate the step: largest k with start[k] <= t
+    int lo = 0, hi = q.nsteps - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (q.start[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const int sidx = __builtin_amdgcn_readfirstlane(q.order[lo]);
+    const Step& st = q.steps[sidx];
+    const int tile = __builtin_amdgcn_readfirstlane(static_cast<int>(t - q.start[lo]));
+    if (threadIdx.x == 0) {
+      bool ok = true;
+      if (st.dep0 >= 0) ok = wait_done(q, st.dep0, static_cast<unsigned>(q.steps[st.dep0].ntiles));
+      if (ok && st.dep1 >= 0) ok = wait_done(q, st.dep1, static_cast<unsigned>(q.steps[st.dep1].ntiles));
+      s_ok = ok ? 1 : 0;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (s_ok) {
+      switch (st.op) {
+        case kOpGather: gather_tile<V>(st.u.g, st.chunk, tile, lds); break;
+        case kOpDot: dot_tile<V>(st.u.d, st.chunk, tile, lds); break;
+        case kOpFill: fill_tile<V>(st.u.f, st.chunk, tile); break;
+        case kOpReduce: reduce_tile<V>(st.u.r, st.chunk); break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_add(q.done + sidx, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+}  // namespace cs

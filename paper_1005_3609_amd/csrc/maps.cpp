@@ -1,0 +1,380 @@
+// Factor-map builder.
+//
+// Every per-site factor of arXiv 1005.3609 is expanded on each source state
+// with the single-edge operators of Sec. 3.1 at v = -1, evaluated at integer
+// q in un-normalised form (a component pays q when it leaves the layer):
+//   H_{a,b} s = s - J_{a,b} s          (0 if a, b already share a block)
+//   V_i s     = -s + D_i s             ((q-1) s if i is alone in s)
+//   D_i s     = i made a singleton     (q s if i is alone in s)
+//   P         = drop states whose listed neighbour pairs share a block
+// Factors (1-based site i, Sec. 3.2 - 3.3):
+//   square      T_i = P_{j != i} V_i H_{i,i+1} (i < m),  T_m = P_all V_m
+//   triangular  T_i = P_all V_i H_{i-1,i} H_{i,i+1}  (H's omitted at the ends)
+//   read-out    T_i^last = P_{j > i} D_i H_{i,i+1}   (H omitted for i = m)
+// Every coefficient is a + b q with small integers a, b; it is stored as a
+// code into a per-map-set table.
+#include "maps.hpp"
+
+#include <algorithm>
+#include <atomic>
+#include <cstring>
+#include <exception>
+#include <map>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <thread>
+
+namespace cs {
+
+namespace {
+
+// Coefficient key for a in [-16,16], b in [-2,2].
+constexpr int kKeyA = 16, kKeyB = 2, kKeys = 33 * 5;
+inline int coef_key(int a, int b) {
+  if (a < -kKeyA || a > kKeyA || b < -kKeyB || b > kKeyB)
+    throw std::runtime_error("coefficient out of the supported range");
+  return (a + kKeyA) + 33 * (b + kKeyB);
+}
+
+struct Term {
+  Part p;
+  int a, b;  // coefficient a + b q
+};
+
+// Applies single-edge operators to a short list of terms.
+class Expander {
+ public:
+  explicit Expander(int m) : m_(m) {}
+  void reset(const Part& p) {
+    terms_.clear();
+    terms_.push_back({p, 1, 0});
+  }
+  // H_{x,y} = 1 - J_{x,y}
+  void H(int x, int y) {
+    tmp_.clear();
+    for (const Term& t : terms_) {
+      if (same_block(t.p, x, y)) continue;
+      tmp_.push_back(t);
+      Term j = t;
+      join(j.p, m_, x, y);
+      j.a = -t.a;
+      j.b = -t.b;
+      tmp_.push_back(j);
+    }
+    terms_.swap(tmp_);
+  }
+  // V_i = -1 + D_i
+  void V(int i) {
+    tmp_.clear();
+    for (const Term& t : terms_) {
+      if (is_alone(t.p, m_, i)) {
+        if (t.b != 0) throw std::runtime_error("q^2 coefficient");
+        tmp_.push_back({t.p, -t.a, t.a});  // (q - 1) a
+      } else {
+        tmp_.push_back({t.p, -t.a, -t.b});
+        Term d = t;
+        detach(d.p, m_, i);
+        tmp_.push_back(d);
+      }
+    }
+    terms_.swap(tmp_);
+  }
+  // D_i
+  void D(int i) {
+    for (Term& t : terms_) {
+      if (is_alone(t.p, m_, i)) {
+        if (t.b != 0) throw std::runtime_error("q^2 coefficient");
+        t.b = t.a;
+        t.a = 0;
+      } else {
+        detach(t.p, m_, i);
+      }
+    }
+  }
+  // Projectors P_{x,x+1} for every x with bit x set in `forbid`.
+  void P(uint32_t forbid) {
+    tmp_.clear();
+    for (const Term& t : terms_) {
+      bool ok = true;
+      for (int x = 0; x + 1 < m_; ++x)
+        if (((forbid >> x) & 1u) && t.p.lab[x] == t.p.lab[x + 1]) {
+          ok = false;
+          break;
+        }
+      if (ok) tmp_.push_back(t);
+    }
+    terms_.swap(tmp_);
+  }
+  // Combines equal states and drops zero coefficients.
+  void merge() {
+    tmp_.clear();
+    for (const Term& t : terms_) {
+      bool found = false;
+      for (Term& u : tmp_)
+        if (std::memcmp(u.p.lab, t.p.lab, m_) == 0) {
+          u.a += t.a;
+          u.b += t.b;
+          found = true;
+          break;
+        }
+      if (!found) tmp_.push_back(t);
+    }
+    terms_.clear();
+    for (const Term& t : tmp_)
+      if (t.a != 0 || t.b != 0) terms_.push_back(t);
+  }
+  const std::vector<Term>& terms() const { return terms_; }
+
+ private:
+  int m_;
+  std::vector<Term> terms_, tmp_;
+};
+
+uint32_t all_pairs(int m) { return m >= 2 ? ((1u << (m - 1)) - 1u) : 0u; }
+
+// One factor's definition: spaces and the operator sequence.
+struct FactorDef {
+  Space in, out;
+  int lattice, m, site;  // site: 1-based i
+  bool last;
+
+  void expand(Expander& e) const {
+    const int s = site - 1;  // 0-based point of site i
+    if (last) {
+      if (site < m) e.H(s, s + 1);
+      e.D(s);
+      uint32_t forbid = 0;
+      for (int x = s + 1; x + 1 < m; ++x) forbid |= 1u << x;
+      e.P(forbid);
+    } else if (lattice == kSquare) {
+      if (site < m) e.H(s, s + 1);
+      e.V(s);
+      uint32_t forbid = all_pairs(m);
+      if (site < m) forbid &= ~(1u << s);
+      e.P(forbid);
+    } else {
+      if (site < m) e.H(s, s + 1);
+      if (site > 1) e.H(s - 1, s);
+      e.V(s);
+      e.P(all_pairs(m));
+    }
+    e.merge();
+  }
+};
+
+FactorDef forward_def(int lattice, int m, int i) {
+  FactorDef d;
+  d.lattice = lattice;
+  d.m = m;
+  d.site = i;
+  d.last = false;
+  if (lattice == kSquare) {
+    d.in = (i == 1) ? Space{kNcnnn, m, 0} : Space{kSqInter, m, i - 1};
+    d.out = (i == m) ? Space{kNcnnn, m, 0} : Space{kSqInter, m, i};
+  } else {
+    d.in = Space{kNcnnn, m, 0};
+    d.out = Space{kNcnnn, m, 0};
+  }
+  return d;
+}
+
+FactorDef last_def(int lattice, int m, int i) {
+  FactorDef d;
+  d.lattice = lattice;
+  d.m = m;
+  d.site = i;
+  d.last = true;
+  d.in = (i == 1) ? Space{kNcnnn, m, 0} : Space{kLast, m, i - 1};
+  d.out = Space{kLast, m, i};
+  return d;
+}
+
+// Runs f(thread, lo, hi) over contiguous ascending ranges; the first
+// exception thrown by any worker is rethrown here.
+template <class F>
+void parallel_for(int64_t n, int threads, F&& f) {
+  if (threads <= 1 || n < 4096) {
+    f(0, int64_t(0), n);
+    return;
+  }
+  std::vector<std::thread> pool;
+  std::exception_ptr err;
+  std::mutex err_mu;
+  int64_t chunk = (n + threads - 1) / threads;
+  for (int t = 0; t < threads; ++t) {
+    int64_t lo = t * chunk, hi = std::min(n, lo + chunk);
+    if (lo >= hi) break;
+    pool.emplace_back([&, t, lo, hi] {
+      try {
+        f(t, lo, hi);
+      } catch (...) {
+        std::lock_guard<std::mutex> lk(err_mu);
+        if (!err) err = std::current_exception();
+      }
+    });
+  }
+  for (auto& th : pool) th.join();
+  if (err) std::rethrow_exception(err);
+}
+
+struct Triple {
+  int32_t row, col;
+  int16_t key;
+};
+
+// Builds one factor with coefficient keys in place of codes (resolved later).
+void build_factor(const FactorDef& d, bool gather_form, int threads, Csr& csr,
+                  std::vector<uint16_t>& keys, std::atomic<uint64_t>* seen) {
+  const int64_t nin = d.in.size(), nout = d.out.size();
+  if (nin > int64_t(kSrcMask) || nout > int64_t(kSrcMask))
+    throw std::runtime_error("state space too large for 28-bit ranks");
+  std::vector<std::vector<Triple>> buf(std::max(threads, 1));
+  parallel_for(nin, threads, [&](int t, int64_t lo, int64_t hi) {
+    Expander e(d.m);
+    auto& out = buf[t];
+    out.reserve(static_cast<size_t>((hi - lo) * 4));
+    uint64_t local_seen[(kKeys + 63) / 64] = {0};
+    for (int64_t r = lo; r < hi; ++r) {
+      Part p;
+      d.in.unrank(r, p);
+      e.reset(p);
+      d.expand(e);
+      for (const Term& term : e.terms()) {
+        int64_t tr = d.out.rank(term.p);
+        if (tr < 0) throw std::runtime_error("target outside its space: " + to_string(term.p, d.m));
+        int key = coef_key(term.a, term.b);
+        local_seen[key / 64] |= 1ull << (key % 64);
+        if (gather_form)
+          out.push_back({static_cast<int32_t>(tr), static_cast<int32_t>(r), static_cast<int16_t>(key)});
+        else
+          out.push_back({static_cast<int32_t>(r), static_cast<int32_t>(tr), static_cast<int16_t>(key)});
+      }
+    }
+    for (int w = 0; w < (kKeys + 63) / 64; ++w) seen[w].fetch_or(local_seen[w]);
+  });
+  const int64_t nrows = gather_form ? nout : nin;
+  csr.n_rows = nrows;
+  csr.n_cols = gather_form ? nin : nout;
+  std::vector<int64_t> count(nrows + 1, 0);
+  int64_t nnz = 0;
+  for (auto& b : buf)
+    for (const Triple& x : b) ++count[x.row + 1], ++nnz;
+  if (nnz > INT32_MAX) throw std::runtime_error("too many map entries for 32-bit row pointers");
+  csr.row_ptr.assign(nrows + 1, 0);
+  for (int64_t r = 0; r < nrows; ++r) count[r + 1] += count[r];
+  for (int64_t r = 0; r <= nrows; ++r) csr.row_ptr[r] = static_cast<int32_t>(count[r]);
+  csr.ent.assign(nnz, 0);
+  keys.assign(nnz, 0);
+  // Sources are visited in increasing order (thread ranges ascend), so each
+  // row's entries come out sorted by column in the gather form; the
+  // scatter form is sorted per row below.
+  std::vector<int64_t> cur(count.begin(), count.end() - 1);
+  for (auto& b : buf)
+    for (const Triple& x : b) {
+      int64_t at = cur[x.row]++;
+      csr.ent[at] = static_cast<uint32_t>(x.col);
+      keys[at] = static_cast<uint16_t>(x.key);
+    }
+  if (!gather_form) {
+    for (int64_t r = 0; r < nrows; ++r) {
+      int64_t lo = csr.row_ptr[r], hi = csr.row_ptr[r + 1];
+      // tiny rows: insertion sort of (col, key) pairs
+      for (int64_t a = lo + 1; a < hi; ++a)
+        for (int64_t b = a; b > lo && csr.ent[b - 1] > csr.ent[b]; --b) {
+          std::swap(csr.ent[b - 1], csr.ent[b]);
+          std::swap(keys[b - 1], keys[b]);
+        }
+    }
+  }
+}
+
+}  // namespace
+
+int64_t MapSet::total_nnz() const {
+  int64_t s = 0;
+  for (auto& c : fwd) s += c.nnz();
+  for (auto& c : last) s += c.nnz();
+  return s;
+}
+
+int64_t MapSet::max_states() const {
+  int64_t s = 0;
+  for (auto& c : fwd) s = std::max({s, c.n_rows, c.n_cols});
+  for (auto& c : last) s = std::max({s, c.n_rows, c.n_cols});
+  return s;
+}
+
+size_t MapSet::host_bytes() const {
+  size_t s = 0;
+  for (auto& c : fwd) s += c.row_ptr.size() * 4 + c.ent.size() * 4;
+  for (auto& c : last) s += c.row_ptr.size() * 4 + c.ent.size() * 4;
+  return s;
+}
+
+std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads) {
+  if (lattice != kSquare && lattice != kTriangular) throw std::runtime_error("bad lattice");
+  if (m < 1 || m > kMaxM) throw std::runtime_error("m out of range");
+  if (threads <= 0) threads = std::max(1u, std::thread::hardware_concurrency());
+  auto ms = std::make_unique<MapSet>();
+  ms->lattice = lattice;
+  ms->m = m;
+  ms->fwd.resize(m);
+  ms->last.resize(m);
+  std::vector<std::vector<uint16_t>> fkeys(m), lkeys(m);
+  std::atomic<uint64_t> seen[(kKeys + 63) / 64];
+  for (auto& s : seen) s = 0;
+  for (int i = 1; i <= m; ++i) {
+    build_factor(forward_def(lattice, m, i), true, threads, ms->fwd[i - 1], fkeys[i - 1], seen);
+    build_factor(last_def(lattice, m, i), false, threads, ms->last[i - 1], lkeys[i - 1], seen);
+  }
+  // Codes: +1 -> 0, -1 -> 1, then every other coefficient in key order.
+  int key_to_code[kKeys];
+  std::fill(key_to_code, key_to_code + kKeys, -1);
+  int n = 0;
+  auto add = [&](int key) {
+    if (key_to_code[key] >= 0) return;
+    if (n >= kMaxCodes) throw std::runtime_error("more than 16 distinct coefficients");
+    key_to_code[key] = n;
+    ms->code_a[n] = key % 33 - kKeyA;
+    ms->code_b[n] = key / 33 - kKeyB;
+    ++n;
+  };
+  add(coef_key(1, 0));
+  add(coef_key(-1, 0));
+  for (int k = 0; k < kKeys; ++k)
+    if ((seen[k / 64].load() >> (k % 64)) & 1ull) add(k);
+  ms->n_codes = n;
+  auto finish = [&](Csr& c, const std::vector<uint16_t>& keys) {
+    for (size_t e = 0; e < c.ent.size(); ++e)
+      c.ent[e] |= static_cast<uint32_t>(key_to_code[keys[e]]) << kSrcBits;
+  };
+  for (int i = 0; i < m; ++i) {
+    finish(ms->fwd[i], fkeys[i]);
+    finish(ms->last[i], lkeys[i]);
+  }
+  return ms;
+}
+
+namespace {
+std::mutex g_cache_mu;
+std::map<std::pair<int, int>, std::unique_ptr<MapSet>> g_cache;
+}  // namespace
+
+const MapSet& get_maps(int lattice, int m) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  auto key = std::make_pair(lattice, m);
+  auto it = g_cache.find(key);
+  if (it != g_cache.end()) return *it->second;
+  auto ms = build_maps(lattice, m);
+  const MapSet& ref = *ms;
+  g_cache.emplace(key, std::move(ms));
+  return ref;
+}
+
+void release_host_maps() {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_cache.clear();
+}
+
+}  // namespace cs

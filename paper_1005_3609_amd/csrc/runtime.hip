@@ -1,0 +1,1280 @@
+// Runtime and C ABI of the chromatic-strip library.
+//
+// The sweep computes P of the m x r rectangles, r = 1..n_max, as
+// Z_r = <w, x_r>, x_1 = e_0, x_{r+1} = T_m ... T_1 x_r, and
+// w = (T_1^last)^T ... (T_m^last)^T e_0 (arXiv 1005.3609, eqs. Z_from_T,
+// T_sq_decomp, T_last).  w is built once per instance set on the device and
+// kept in Montgomery form so the read-out is a plain dot product.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/chromstrip.h"
+#include "kernels.hpp"
+#include "maps.hpp"
+#include "states.hpp"
+
+namespace cs {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct ArgError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct MemError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct BusyError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+#define HIPX(expr)                                                                  \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      throw HipError(std::string(#expr) + ": " + hipGetErrorString(e_));            \
+  } while (0)
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const ArgError& e) {
+    return fail(CHROM_EINVAL, e.what());
+  } catch (const MemError& e) {
+    return fail(CHROM_ENOMEM, e.what());
+  } catch (const BusyError& e) {
+    return fail(CHROM_EBUSY, e.what());
+  } catch (const HipError& e) {
+    return fail(CHROM_EDEVICE, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(CHROM_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(CHROM_EUNSUPPORTED, e.what());
+  }
+}
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------------------------------
+// Device copies of the factor maps, one per (device, lattice, m)
+// ---------------------------------------------------------------------------
+struct DevMaps {
+  void* base = nullptr;
+  size_t bytes = 0;
+  DevCsr fwd[kMaxM];
+  DevCsr last[kMaxM];
+  int n_codes = 0;
+  int code_a[kMaxCodes], code_b[kMaxCodes];
+  int64_t s_nc = 0;    // NCNNN states
+  int64_t s_max = 0;   // largest space
+};
+
+std::mutex g_dev_mu;
+std::map<std::tuple<int, int, int>, std::unique_ptr<DevMaps>> g_dev;
+
+const DevMaps& dev_maps(int lattice, int m) {
+  int dev = 0;
+  HIPX(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  auto key = std::make_tuple(dev, lattice, m);
+  auto it = g_dev.find(key);
+  if (it != g_dev.end()) return *it->second;
+  const MapSet& ms = get_maps(lattice, m);
+  auto dm = std::make_unique<DevMaps>();
+  size_t bytes = 0;
+  auto sz = [&](const Csr& c) { return align_up(c.row_ptr.size() * 4) + align_up(std::max<size_t>(c.ent.size(), 1) * 4); };
+  for (int i = 0; i < m; ++i) bytes += sz(ms.fwd[i]) + sz(ms.last[i]);
+  void* base = nullptr;
+  if (hipMalloc(&base, bytes) != hipSuccess) throw MemError("device allocation of factor maps failed");
+  char* cur = static_cast<char*>(base);
+  auto up = [&](const Csr& c, DevCsr& d) {
+    int32_t* rp = reinterpret_cast<int32_t*>(cur);
+    HIPX(hipMemcpy(rp, c.row_ptr.data(), c.row_ptr.size() * 4, hipMemcpyHostToDevice));
+    cur += align_up(c.row_ptr.size() * 4);
+    uint32_t* en = reinterpret_cast<uint32_t*>(cur);
+    if (!c.ent.empty()) HIPX(hipMemcpy(en, c.ent.data(), c.ent.size() * 4, hipMemcpyHostToDevice));
+    cur += align_up(std::max<size_t>(c.ent.size(), 1) * 4);
+    d.row_ptr = rp;
+    d.ent = en;
+    d.n_rows = static_cast<int>(c.n_rows);
+    d.n_cols = static_cast<int>(c.n_cols);
+  };
+  for (int i = 0; i < m; ++i) {
+    up(ms.fwd[i], dm->fwd[i]);
+    up(ms.last[i], dm->last[i]);
+  }
+  dm->base = base;
+  dm->bytes = bytes;
+  dm->n_codes = ms.n_codes;
+  std::copy(ms.code_a, ms.code_a + kMaxCodes, dm->code_a);
+  std::copy(ms.code_b, ms.code_b + kMaxCodes, dm->code_b);
+  dm->s_nc = ncnnn_count(m);
+  dm->s_max = ms.max_states();
+  const DevMaps& ref = *dm;
+  g_dev.emplace(key, std::move(dm));
+  return ref;
+}
+
+// Host-side sizes without building device copies.
+struct Sizes {
+  int64_t s_nc, s_max;
+};
+Sizes space_sizes(int lattice, int m) {
+  Sizes s;
+  s.s_nc = ncnnn_count(m);
+  s.s_max = (lattice == kSquare && m >= 2) ? ncnnn_count(m) + ncnnn_count(m - 1) : ncnnn_count(m);
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Pinned staging buffers for host-to-device uploads on a stream
+// ---------------------------------------------------------------------------
+struct StageBuf {
+  void* host = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;
+  bool in_use = false;
+};
+std::mutex g_stage_mu;
+std::vector<std::unique_ptr<StageBuf>> g_stage;
+
+// Copies `bytes` from `src` to device `dst` on `stream` through a pinned
+// buffer that is recycled once the copy has completed.
+void upload(void* dst, const void* src, size_t bytes, hipStream_t stream) {
+  if (bytes == 0) return;
+  StageBuf* sb = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    for (auto& b : g_stage) {
+      if (b->bytes < bytes) continue;
+      if (b->in_use && hipEventQuery(b->done) != hipSuccess) continue;
+      sb = b.get();
+      break;
+    }
+    if (!sb) {
+      auto nb = std::make_unique<StageBuf>();
+      nb->bytes = std::max<size_t>(align_up(bytes, 1 << 16), 1 << 20);
+      HIPX(hipHostMalloc(&nb->host, nb->bytes, hipHostMallocDefault));
+      HIPX(hipEventCreateWithFlags(&nb->done, hipEventDisableTiming));
+      sb = nb.get();
+      g_stage.push_back(std::move(nb));
+    }
+    sb->in_use = true;
+  }
+  std::memcpy(sb->host, src, bytes);
+  HIPX(hipMemcpyAsync(dst, sb->host, bytes, hipMemcpyHostToDevice, stream));
+  HIPX(hipEventRecord(sb->done, stream));
+}
+
+// ---------------------------------------------------------------------------
+// Per-instance constants
+// ---------------------------------------------------------------------------
+uint32_t neg_inv_2_32(uint32_t p) {
+  uint32_t inv = p;  // correct to 3 bits for odd p
+  for (int k = 0; k < 5; ++k) inv *= 2u - p * inv;
+  return 0u - inv;
+}
+
+struct Inst {
+  uint32_t q, p;
+};
+
+std::vector<Inst> make_instances(const uint32_t* q, int nq, const uint32_t* p, int np) {
+  if (nq < 1 || np < 1) throw ArgError("need at least one q point and one prime");
+  if (!q || !p) throw ArgError("null q_points or primes");
+  std::vector<Inst> v;
+  v.reserve(static_cast<size_t>(nq) * np);
+  for (int b = 0; b < np; ++b)
+    if (p[b] <= 2u || p[b] >= (1u << 31) || (p[b] & 1u) == 0u)
+      throw ArgError("each prime must be odd with 2 < p < 2^31");
+  for (int a = 0; a < nq; ++a)
+    for (int b = 0; b < np; ++b) v.push_back({q[a] % p[b], p[b]});
+  return v;
+}
+
+uint32_t coef_mod(int a, int b, uint32_t q, uint32_t p) {
+  int64_t am = a % static_cast<int64_t>(p);
+  if (am < 0) am += p;
+  int64_t bm = b % static_cast<int64_t>(p);
+  if (bm < 0) bm += p;
+  return static_cast<uint32_t>((static_cast<uint64_t>(am) + static_cast<uint64_t>(bm) * q) % p);
+}
+
+uint32_t shoup_of(uint32_t c, uint32_t p) {
+  return static_cast<uint32_t>((static_cast<uint64_t>(c) << 32) / p);
+}
+
+// ---------------------------------------------------------------------------
+// Tuning and workspace layout
+// ---------------------------------------------------------------------------
+struct Tune {
+  int V = 2, rpw = 8, wpb = 4, grid = 0, readout_blocks = 0;
+};
+
+Tune resolve(const chrom_tuning* t) {
+  Tune r;
+  if (!t) return r;
+  if (t->lanes_v) r.V = t->lanes_v;
+  if (t->targets_per_wave) r.rpw = t->targets_per_wave;
+  if (t->waves_per_block) r.wpb = t->waves_per_block;
+  r.grid = t->grid_blocks;
+  r.readout_blocks = t->readout_blocks;
+  if (r.V != 1 && r.V != 2 && r.V != 4) throw ArgError("lanes_v must be 1, 2 or 4");
+  if (r.rpw < 1 || r.rpw > 64) throw ArgError("targets_per_wave must be in 1..64");
+  if (r.wpb != 1 && r.wpb != 2 && r.wpb != 4 && r.wpb != 8) throw ArgError("waves_per_block must be 1, 2, 4 or 8");
+  if (r.grid < 0) throw ArgError("grid_blocks must be >= 0");
+  return r;
+}
+
+// Batched layout of one strip's device state.
+struct JobLayout {
+  int lattice = 0, m = 0, I = 0, V = 2, W = 128, nchunk = 0, ipad = 0, ncodes = 0;
+  int rows_tile = 32;    // rows per workgroup tile
+  int64_t s_nc = 0, s_max = 0;
+  int nparts = 0;        // read-out partial tiles per chunk
+  size_t x0 = 0, x1 = 0, w = 0, part = 0, p = 0, pinv = 0, r1 = 0, cval = 0, cshp = 0, bytes = 0;
+};
+
+JobLayout job_layout(int lattice, int m, int I, const Tune& t, int ncodes, int rows_tile) {
+  JobLayout L;
+  L.lattice = lattice;
+  L.m = m;
+  L.I = I;
+  L.V = t.V;
+  L.W = 64 * t.V;
+  L.nchunk = (I + L.W - 1) / L.W;
+  L.ipad = L.nchunk * L.W;
+  L.ncodes = ncodes;
+  L.rows_tile = rows_tile;
+  Sizes s = space_sizes(lattice, m);
+  L.s_nc = s.s_nc;
+  L.s_max = s.s_max;
+  L.nparts = static_cast<int>((L.s_nc + rows_tile - 1) / rows_tile);
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    size_t o = off;
+    off += align_up(b);
+    return o;
+  };
+  const size_t vec = static_cast<size_t>(L.nchunk) * L.s_max * L.W * 4;
+  L.x0 = take(vec);
+  L.x1 = take(vec);
+  L.w = take(static_cast<size_t>(L.nchunk) * L.s_nc * L.W * 4);
+  L.part = take(static_cast<size_t>(L.nchunk) * L.nparts * L.W * 4);
+  L.p = take(L.ipad * 4);
+  L.pinv = take(L.ipad * 4);
+  L.r1 = take(L.ipad * 4);
+  L.cval = take(static_cast<size_t>(kMaxCodes) * L.ipad * 4);
+  L.cshp = take(static_cast<size_t>(kMaxCodes) * L.ipad * 4);
+  L.bytes = off;
+  return L;
+}
+
+// Constants of a job: p, pinv, r1, cval[ncodes][ipad], cshp[...] as one
+// host image laid out like the workspace region [p .. cshp].
+std::vector<uint32_t> const_image(const JobLayout& L, const std::vector<Inst>& inst, const DevMaps& dm) {
+  const size_t base = L.p;
+  std::vector<uint32_t> img((L.cshp + static_cast<size_t>(kMaxCodes) * L.ipad * 4 - base) / 4, 0);
+  auto at = [&](size_t off) { return img.data() + (off - base) / 4; };
+  uint32_t* p = at(L.p);
+  uint32_t* pinv = at(L.pinv);
+  uint32_t* r1 = at(L.r1);
+  uint32_t* cv = at(L.cval);
+  uint32_t* cs = at(L.cshp);
+  for (int k = 0; k < L.ipad; ++k) {
+    const Inst& in = inst[k < L.I ? k : 0];
+    p[k] = in.p;
+    pinv[k] = neg_inv_2_32(in.p);
+    r1[k] = static_cast<uint32_t>((uint64_t(1) << 32) % in.p);
+    for (int c = 0; c < dm.n_codes; ++c) {
+      uint32_t v = coef_mod(dm.code_a[c], dm.code_b[c], in.q, in.p);
+      cv[static_cast<size_t>(c) * L.ipad + k] = v;
+      cs[static_cast<size_t>(c) * L.ipad + k] = shoup_of(v, in.p);
+    }
+  }
+  return img;
+}
+
+// Pointers of one job's device state.
+struct JobPtrs {
+  uint32_t *x0, *x1, *w, *part, *p, *pinv, *r1, *cval, *cshp;
+  InstConsts ic() const { return InstConsts{p, pinv, cval, cshp, 0}; }
+};
+
+JobPtrs job_ptrs(const JobLayout& L, void* base) {
+  char* b = static_cast<char*>(base);
+  JobPtrs j;
+  j.x0 = reinterpret_cast<uint32_t*>(b + L.x0);
+  j.x1 = reinterpret_cast<uint32_t*>(b + L.x1);
+  j.w = reinterpret_cast<uint32_t*>(b + L.w);
+  j.part = reinterpret_cast<uint32_t*>(b + L.part);
+  j.p = reinterpret_cast<uint32_t*>(b + L.p);
+  j.pinv = reinterpret_cast<uint32_t*>(b + L.pinv);
+  j.r1 = reinterpret_cast<uint32_t*>(b + L.r1);
+  j.cval = reinterpret_cast<uint32_t*>(b + L.cval);
+  j.cshp = reinterpret_cast<uint32_t*>(b + L.cshp);
+  return j;
+}
+
+InstConsts inst_consts(const JobLayout& L, const JobPtrs& j) {
+  return InstConsts{j.p, j.pinv, j.cval, j.cshp, L.ipad};
+}
+
+void check_args(int lattice, int m, int n_max) {
+  if (lattice != CHROM_SQUARE && lattice != CHROM_TRIANGULAR) throw ArgError("lattice must be CHROM_SQUARE or CHROM_TRIANGULAR");
+  if (m < 1 || m > CHROM_MAX_M) throw ArgError("m must be in 1..CHROM_MAX_M");
+  if (n_max < 0) throw ArgError("n_max must be >= 0");
+}
+
+
+// ---------------------------------------------------------------------------
+// Programs: a strip's work as an ordered list of steps over one job's buffers
+// ---------------------------------------------------------------------------
+struct PStep {
+  Step s;       // op, ntiles, args (chunk filled in per item)
+  int dep[2];   // local indices of steps that must be complete (-1: none)
+};
+
+struct Program {
+  std::vector<PStep> steps;
+  int nchunk = 0;
+};
+
+struct JobCtx {
+  const DevMaps* dm;
+  JobLayout L;
+  JobPtrs P;
+  Tune t;
+  uint32_t* d_out;   // [n_max][I]
+};
+
+int tiles_for(int64_t rows, int rows_tile) {
+  return static_cast<int>(std::max<int64_t>(1, (rows + rows_tile - 1) / rows_tile));
+}
+
+int push(Program& pg, const Step& s, int d0, int d1) {
+  PStep ps;
+  ps.s = s;
+  ps.dep[0] = d0;
+  ps.dep[1] = d1;
+  pg.steps.push_back(ps);
+  return static_cast<int>(pg.steps.size()) - 1;
+}
+
+Step gather_step(const JobCtx& j, const DevCsr& c, const uint32_t* in, uint32_t* out, long out_cstride, bool fused) {
+  Step s{};
+  s.op = kOpGather;
+  s.ntiles = tiles_for(c.n_rows, j.L.rows_tile);
+  GatherArgs& a = s.u.g;
+  a.csr = c;
+  a.in = in;
+  a.out = out;
+  a.in_cstride = static_cast<long>(j.L.s_max) * j.L.W;
+  a.out_cstride = out_cstride;
+  a.ic = inst_consts(j.L, j.P);
+  a.rows_per_wave = j.t.rpw;
+  if (fused) {
+    a.w = j.P.w;
+    a.w_cstride = static_cast<long>(j.L.s_nc) * j.L.W;
+    a.partial = j.P.part;
+    a.p_cstride = static_cast<long>(j.L.nparts) * j.L.W;
+  }
+  return s;
+}
+
+Step reduce_step(const JobCtx& j, int out_row) {
+  Step s{};
+  s.op = kOpReduce;
+  s.ntiles = 1;
+  s.u.r = ReduceArgs{j.P.part, static_cast<long>(j.L.nparts) * j.L.W, j.L.nparts, inst_consts(j.L, j.P),
+                     j.d_out + static_cast<long>(out_row) * j.L.I, j.L.I};
+  return s;
+}
+
+// Set-up: w = (T_1^last)^T ... (T_m^last)^T (R e_0) built in x0/x1 and
+// written to w, then x = e_0 in x0 and Z_1 = <w, e_0>.  Linear chain.
+int add_setup(Program& pg, const JobCtx& j) {
+  const JobLayout& L = j.L;
+  const long cs_x = static_cast<long>(L.s_max) * L.W;
+  const long cs_w = static_cast<long>(L.s_nc) * L.W;
+  Step s{};
+  s.op = kOpFill;
+  s.ntiles = 1;
+  s.u.f = FillArgs{j.P.x0, cs_x, 1, j.P.r1, j.t.rpw};
+  int last = push(pg, s, -1, -1);
+  uint32_t* cur = j.P.x0;
+  uint32_t* oth = j.P.x1;
+  for (int i = L.m; i >= 1; --i) {
+    const bool to_w = (i == 1);
+    Step g = gather_step(j, j.dm->last[i - 1], cur, to_w ? j.P.w : oth, to_w ? cs_w : cs_x, false);
+    last = push(pg, g, last, -1);
+    std::swap(cur, oth);
+  }
+  s = Step{};
+  s.op = kOpFill;
+  s.ntiles = tiles_for(L.s_nc, L.rows_tile);
+  s.u.f = FillArgs{j.P.x0, cs_x, static_cast<int>(L.s_nc), nullptr, j.t.rpw};
+  last = push(pg, s, last, -1);
+  s = Step{};
+  s.op = kOpDot;
+  s.ntiles = L.nparts;
+  s.u.d = DotArgs{j.P.x0, j.P.w, cs_x, cs_w, static_cast<int>(L.s_nc), inst_consts(L, j.P), j.P.part,
+                  static_cast<long>(L.nparts) * L.W, j.t.rpw};
+  last = push(pg, s, last, -1);
+  return push(pg, reduce_step(j, 0), last, -1);
+}
+
+// Rows: out rows r = r_first..r_last (0-based; row r holds P of m x (r+1)),
+// each x <- T_m ... T_1 x with the read-out fused into T_m, then a reduce.
+// `after` is the step the first factor waits for; `prev_reduce` the last
+// reduce issued before (its partials are overwritten by the next T_m).
+void add_rows(Program& pg, const JobCtx& j, int r_first, int r_last, int after, int prev_reduce) {
+  const JobLayout& L = j.L;
+  const long cs_x = static_cast<long>(L.s_max) * L.W;
+  for (int r = r_first; r <= r_last; ++r) {
+    const long done_gathers = static_cast<long>(r - 1) * L.m;
+    uint32_t* cur = (done_gathers % 2 == 0) ? j.P.x0 : j.P.x1;
+    uint32_t* oth = (cur == j.P.x0) ? j.P.x1 : j.P.x0;
+    int tm = -1;
+    for (int i = 1; i <= L.m; ++i) {
+      const bool fused = (i == L.m);
+      Step g = gather_step(j, j.dm->fwd[i - 1], cur, oth, cs_x, fused);
+      tm = push(pg, g, after, fused ? prev_reduce : -1);
+      after = tm;
+      std::swap(cur, oth);
+    }
+    prev_reduce = push(pg, reduce_step(j, r), tm, -1);
+  }
+}
+
+Program strip_program(const JobCtx& j, int n_max) {
+  Program pg;
+  pg.nchunk = j.L.nchunk;
+  if (n_max < 1) return pg;
+  int red = add_setup(pg, j);
+  if (n_max > 1) add_rows(pg, j, 1, n_max - 1, red, red);
+  return pg;
+}
+
+// ---------------------------------------------------------------------------
+// Eager execution of a program: one launch per step, grid (ntiles, nchunk)
+// ---------------------------------------------------------------------------
+template <int V>
+void launch_step_v(const Step& s, int nchunk, int wpb, hipStream_t st, const int* row_ctr, long row_stride) {
+  dim3 grid(s.ntiles, nchunk), block(64 * wpb);
+  switch (s.op) {
+    case kOpGather: hipLaunchKernelGGL(k_gather<V>, grid, block, 0, st, s.u.g); break;
+    case kOpDot: hipLaunchKernelGGL(k_dot<V>, grid, block, 0, st, s.u.d); break;
+    case kOpFill: hipLaunchKernelGGL(k_fill<V>, grid, block, 0, st, s.u.f); break;
+    case kOpReduce:
+      if (row_ctr)
+        hipLaunchKernelGGL(k_reduce_counted<V>, dim3(nchunk), dim3(256), 0, st, s.u.r, row_ctr, row_stride);
+      else
+        hipLaunchKernelGGL(k_reduce<V>, dim3(nchunk), dim3(256), 0, st, s.u.r);
+      break;
+  }
+  HIPX(hipGetLastError());
+}
+
+void launch_step(const Step& s, int V, int nchunk, int wpb, hipStream_t st, const int* row_ctr = nullptr,
+                 long row_stride = 0) {
+  switch (V) {
+    case 1: launch_step_v<1>(s, nchunk, wpb, st, row_ctr, row_stride); break;
+    case 2: launch_step_v<2>(s, nchunk, wpb, st, row_ctr, row_stride); break;
+    default: launch_step_v<4>(s, nchunk, wpb, st, row_ctr, row_stride); break;
+  }
+}
+
+void run_eager(const Program& pg, const Tune& t, hipStream_t st) {
+  for (const PStep& ps : pg.steps) launch_step(ps.s, t.V, pg.nchunk, t.wpb, st);
+}
+
+// ---------------------------------------------------------------------------
+// hipGraph row sweep: one row (two when m is odd, so the ping-pong buffers
+// return to their start) captured once and replayed
+// ---------------------------------------------------------------------------
+struct GraphKey {
+  void* ws;
+  uint32_t* out;
+  int lattice, m, I, V, rpw, wpb, rows_per_graph;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(ws, out, lattice, m, I, V, rpw, wpb, rows_per_graph) <
+           std::tie(o.ws, o.out, o.lattice, o.m, o.I, o.V, o.rpw, o.wpb, o.rows_per_graph);
+  }
+};
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+  int dev = -1;
+};
+std::mutex g_graph_mu;
+std::map<GraphKey, GraphEntry> g_graphs;
+hipStream_t g_capture_stream[64] = {nullptr};
+
+hipStream_t capture_stream() {
+  int dev = 0;
+  HIPX(hipGetDevice(&dev));
+  if (!g_capture_stream[dev]) HIPX(hipStreamCreateWithFlags(&g_capture_stream[dev], hipStreamNonBlocking));
+  return g_capture_stream[dev];
+}
+
+void run_graph(const JobCtx& j, int n_max, int* row_ctr, void* ws, hipStream_t st) {
+  Program setup;
+  setup.nchunk = j.L.nchunk;
+  int red = add_setup(setup, j);
+  (void)red;
+  run_eager(setup, j.t, st);
+  if (n_max <= 1) return;
+  const int per = (j.L.m % 2 == 1) ? 2 : 1;
+  const int rows = n_max - 1;
+  const int replays = rows / per;
+  const int tail = rows - replays * per;
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, row_ctr, 1);
+  HIPX(hipGetLastError());
+  if (replays > 0) {
+    GraphKey key{ws, j.d_out, j.L.lattice, j.L.m, j.L.I, j.t.V, j.t.rpw, j.t.wpb, per};
+    hipGraphExec_t exec = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(g_graph_mu);
+      auto it = g_graphs.find(key);
+      if (it != g_graphs.end()) exec = it->second.exec;
+    }
+    if (!exec) {
+      Program rows_pg;
+      rows_pg.nchunk = j.L.nchunk;
+      // rows 1..per starting from the parity of row 1 (x in x0)
+      add_rows(rows_pg, j, 1, per, -1, -1);
+      hipStream_t cs = capture_stream();
+      HIPX(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      for (const PStep& ps : rows_pg.steps) {
+        if (ps.s.op == kOpReduce) {
+          Step counted = ps.s;
+          counted.u.r.out = j.d_out;  // row offset comes from the device counter
+          launch_step(counted, j.t.V, rows_pg.nchunk, j.t.wpb, cs, row_ctr, j.L.I);
+          hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, cs, row_ctr);
+        } else {
+          launch_step(ps.s, j.t.V, rows_pg.nchunk, j.t.wpb, cs);
+        }
+      }
+      hipGraph_t graph = nullptr;
+      HIPX(hipStreamEndCapture(cs, &graph));
+      HIPX(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+      HIPX(hipGraphDestroy(graph));
+      std::lock_guard<std::mutex> lk(g_graph_mu);
+      g_graphs[key] = GraphEntry{exec, 0};
+    }
+    for (int k = 0; k < replays; ++k) HIPX(hipGraphLaunch(exec, st));
+  }
+  if (tail > 0) {
+    Program tail_pg;
+    tail_pg.nchunk = j.L.nchunk;
+    add_rows(tail_pg, j, n_max - tail, n_max - 1, -1, -1);
+    run_eager(tail_pg, j.t, st);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent execution: every (program, chunk) item in one launch
+// ---------------------------------------------------------------------------
+struct QueueLayout {
+  size_t steps = 0, order = 0, start = 0, done = 0, counter = 0, bytes = 0;
+  int nsteps = 0;
+};
+
+QueueLayout queue_layout(int nsteps, size_t base) {
+  QueueLayout q;
+  q.nsteps = nsteps;
+  size_t off = base;
+  auto take = [&](size_t b) {
+    size_t o = off;
+    off += align_up(b);
+    return o;
+  };
+  q.steps = take(std::max(nsteps, 1) * sizeof(Step));
+  q.order = take(std::max(nsteps, 1) * sizeof(int));
+  q.start = take((nsteps + 1) * sizeof(long));
+  q.done = take(std::max(nsteps, 1) * sizeof(unsigned));
+  q.counter = take(2 * sizeof(unsigned));
+  q.bytes = off - base;
+  return q;
+}
+
+// Per-device flag set by a persistent wait that ran out of spins.
+std::mutex g_flag_mu;
+unsigned* g_err_flag[64] = {nullptr};
+
+unsigned* device_error_flag() {
+  int dev = 0;
+  HIPX(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_flag_mu);
+  if (!g_err_flag[dev]) {
+    HIPX(hipMalloc(&g_err_flag[dev], 256));
+    HIPX(hipMemset(g_err_flag[dev], 0, 256));
+  }
+  return g_err_flag[dev];
+}
+
+int persistent_grid(int V) {
+  int dev = 0;
+  HIPX(hipGetDevice(&dev));
+  static int cache[64][5] = {{0}};
+  if (cache[dev][V]) return cache[dev][V];
+  int cus = 0, per = 0;
+  HIPX(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  switch (V) {
+    case 1: HIPX(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<1>, 256, 0)); break;
+    case 2: HIPX(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<2>, 256, 0)); break;
+    default: HIPX(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<4>, 256, 0)); break;
+  }
+  cache[dev][V] = std::max(1, cus * std::max(per, 1));
+  return cache[dev][V];
+}
+
+const long kSpinLimit = 1L << 24;
+
+// Interleaves the items round-robin by step index and launches once.
+void run_persistent(const std::vector<const Program*>& progs, const Tune& t, void* qbase, hipStream_t st) {
+  // items: (program, chunk)
+  struct Item {
+    const Program* pg;
+    int chunk;
+    int base;
+  };
+  std::vector<Item> items;
+  int nsteps = 0;
+  size_t maxlen = 0;
+  for (const Program* pg : progs)
+    for (int c = 0; c < pg->nchunk; ++c) {
+      items.push_back({pg, c, nsteps});
+      nsteps += static_cast<int>(pg->steps.size());
+      maxlen = std::max(maxlen, pg->steps.size());
+    }
+  if (nsteps == 0) return;
+  std::vector<Step> steps(nsteps);
+  for (const Item& it : items)
+    for (size_t k = 0; k < it.pg->steps.size(); ++k) {
+      Step s = it.pg->steps[k].s;
+      s.chunk = it.chunk;
+      s.dep0 = it.pg->steps[k].dep[0] < 0 ? -1 : it.base + it.pg->steps[k].dep[0];
+      s.dep1 = it.pg->steps[k].dep[1] < 0 ? -1 : it.base + it.pg->steps[k].dep[1];
+      steps[it.base + k] = s;
+    }
+  std::vector<int> order;
+  std::vector<long> start;
+  order.reserve(nsteps);
+  start.reserve(nsteps + 1);
+  long total = 0;
+  for (size_t k = 0; k < maxlen; ++k)
+    for (const Item& it : items)
+      if (k < it.pg->steps.size()) {
+        order.push_back(it.base + static_cast<int>(k));
+        start.push_back(total);
+        total += steps[it.base + k].ntiles;
+      }
+  start.push_back(total);
+  QueueLayout q = queue_layout(nsteps, 0);
+  char* b = static_cast<char*>(qbase);
+  upload(b + q.steps, steps.data(), steps.size() * sizeof(Step), st);
+  upload(b + q.order, order.data(), order.size() * sizeof(int), st);
+  upload(b + q.start, start.data(), start.size() * sizeof(long), st);
+  HIPX(hipMemsetAsync(b + q.done, 0, nsteps * sizeof(unsigned), st));
+  HIPX(hipMemsetAsync(b + q.counter, 0, 2 * sizeof(unsigned), st));
+  QueueArgs qa;
+  qa.steps = reinterpret_cast<const Step*>(b + q.steps);
+  qa.order = reinterpret_cast<const int*>(b + q.order);
+  qa.start = reinterpret_cast<const long*>(b + q.start);
+  qa.nsteps = nsteps;
+  qa.done = reinterpret_cast<unsigned*>(b + q.done);
+  qa.counter = reinterpret_cast<unsigned*>(b + q.counter);
+  qa.error = device_error_flag();
+  qa.spin_limit = kSpinLimit;
+  int grid = t.grid > 0 ? t.grid : persistent_grid(t.V);
+  grid = static_cast<int>(std::min<long>(grid, total));
+  switch (t.V) {
+    case 1: hipLaunchKernelGGL(k_persistent<1>, dim3(grid), dim3(256), 0, st, qa); break;
+    case 2: hipLaunchKernelGGL(k_persistent<2>, dim3(grid), dim3(256), 0, st, qa); break;
+    default: hipLaunchKernelGGL(k_persistent<4>, dim3(grid), dim3(256), 0, st, qa); break;
+  }
+  HIPX(hipGetLastError());
+}
+
+size_t program_queue_bytes(int nsteps) { return queue_layout(nsteps, 0).bytes; }
+
+int strip_program_len(int m, int n_max) { return n_max < 1 ? 0 : (m + 4) + (n_max - 1) * (m + 1); }
+
+// ---------------------------------------------------------------------------
+// Plain per-instance path
+// ---------------------------------------------------------------------------
+struct PlainLayout {
+  size_t x0, x1, w, bytes;
+  int64_t s_nc, s_max;
+};
+
+PlainLayout plain_layout(int lattice, int m) {
+  Sizes s = space_sizes(lattice, m);
+  PlainLayout L;
+  L.s_nc = s.s_nc;
+  L.s_max = s.s_max;
+  L.x0 = 0;
+  L.x1 = align_up(s.s_max * 4);
+  L.w = L.x1 + align_up(s.s_max * 4);
+  L.bytes = L.w + align_up(s.s_nc * 4);
+  return L;
+}
+
+void run_plain(const DevMaps& dm, int lattice, int m, int n_max, const std::vector<Inst>& inst, void* ws,
+               hipStream_t st, uint32_t* d_out) {
+  const PlainLayout L = plain_layout(lattice, m);
+  char* b = static_cast<char*>(ws);
+  uint32_t* x0 = reinterpret_cast<uint32_t*>(b + L.x0);
+  uint32_t* x1 = reinterpret_cast<uint32_t*>(b + L.x1);
+  uint32_t* w = reinterpret_cast<uint32_t*>(b + L.w);
+  const int I = static_cast<int>(inst.size());
+  auto g = [](int64_t n) { return dim3(static_cast<unsigned>((n + 255) / 256)); };
+  for (int k = 0; k < I; ++k) {
+    PlainConsts c{};
+    c.p = inst[k].p;
+    c.pinv = neg_inv_2_32(c.p);
+    for (int code = 0; code < dm.n_codes; ++code) {
+      c.cval[code] = coef_mod(dm.code_a[code], dm.code_b[code], inst[k].q, c.p);
+      c.cshp[code] = shoup_of(c.cval[code], c.p);
+    }
+    const uint32_t r1 = static_cast<uint32_t>((uint64_t(1) << 32) % c.p);
+    hipLaunchKernelGGL(k_fill_plain, dim3(1), dim3(256), 0, st, x0, 1, r1);
+    uint32_t* cur = x0;
+    uint32_t* oth = x1;
+    for (int i = m; i >= 1; --i) {
+      const DevCsr& csr = dm.last[i - 1];
+      uint32_t* dst = (i == 1) ? w : oth;
+      hipLaunchKernelGGL(k_gather_plain, g(csr.n_rows), dim3(256), 0, st, csr, cur, dst, c);
+      std::swap(cur, oth);
+    }
+    hipLaunchKernelGGL(k_fill_plain, g(L.s_nc), dim3(256), 0, st, x0, static_cast<int>(L.s_nc), 1u);
+    hipLaunchKernelGGL(k_dot_plain, dim3(1), dim3(256), 0, st, x0, w, static_cast<int>(L.s_nc), c.p, c.pinv,
+                       d_out + k);
+    cur = x0;
+    oth = x1;
+    for (int r = 1; r < n_max; ++r) {
+      for (int i = 1; i <= m; ++i) {
+        const DevCsr& csr = dm.fwd[i - 1];
+        hipLaunchKernelGGL(k_gather_plain, g(csr.n_rows), dim3(256), 0, st, csr, cur, oth, c);
+        std::swap(cur, oth);
+      }
+      hipLaunchKernelGGL(k_dot_plain, dim3(1), dim3(256), 0, st, cur, w, static_cast<int>(L.s_nc), c.p, c.pinv,
+                         d_out + static_cast<long>(r) * I + k);
+    }
+    HIPX(hipGetLastError());
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Strip front end shared by the sync and async calls
+// ---------------------------------------------------------------------------
+int rows_tile_of(const Tune& t) { return t.rpw * t.wpb; }
+
+size_t workspace_bytes(int lattice, int m, int I, int n_max_hint, int mode, const Tune& t) {
+  if (mode == CHROM_MODE_PLAIN) return plain_layout(lattice, m).bytes;
+  JobLayout L = job_layout(lattice, m, I, t, kMaxCodes, rows_tile_of(t));
+  size_t b = L.bytes + 256;  // + graph row counter
+  if (mode == CHROM_MODE_PERSISTENT) b += program_queue_bytes(L.nchunk * strip_program_len(m, n_max_hint));
+  return b;
+}
+
+int strip_async_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, const uint32_t* p, int np, int mode,
+                     const chrom_tuning* tune, void* ws, size_t ws_bytes, hipStream_t st, uint32_t* d_out) {
+  check_args(lattice, m, n_max);
+  if (mode < CHROM_MODE_PLAIN || mode > CHROM_MODE_PERSISTENT) throw ArgError("unknown mode");
+  std::vector<Inst> inst = make_instances(q, nq, p, np);
+  Tune t = resolve(tune);
+  if (mode == CHROM_MODE_PERSISTENT) t.wpb = 4;
+  if (n_max == 0) return CHROM_OK;
+  if (!ws || !d_out) throw ArgError("null workspace or output");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) throw ArgError("workspace must be 256-byte aligned");
+  const int I = static_cast<int>(inst.size());
+  const size_t need = (mode == CHROM_MODE_PLAIN) ? plain_layout(lattice, m).bytes
+                                                 : workspace_bytes(lattice, m, I, n_max, mode, t);
+  if (ws_bytes < need) throw MemError("workspace too small: need " + std::to_string(need) + " bytes");
+  const DevMaps& dm = dev_maps(lattice, m);
+  if (mode == CHROM_MODE_PLAIN) {
+    run_plain(dm, lattice, m, n_max, inst, ws, st, d_out);
+    return CHROM_OK;
+  }
+  JobCtx j;
+  j.dm = &dm;
+  j.t = t;
+  j.L = job_layout(lattice, m, I, t, kMaxCodes, rows_tile_of(t));
+  j.P = job_ptrs(j.L, ws);
+  j.d_out = d_out;
+  std::vector<uint32_t> img = const_image(j.L, inst, dm);
+  upload(static_cast<char*>(ws) + j.L.p, img.data(), img.size() * 4, st);
+  int* row_ctr = reinterpret_cast<int*>(static_cast<char*>(ws) + j.L.bytes);
+  if (mode == CHROM_MODE_BATCHED) {
+    Program pg = strip_program(j, n_max);
+    run_eager(pg, t, st);
+  } else if (mode == CHROM_MODE_GRAPH) {
+    run_graph(j, n_max, row_ctr, ws, st);
+  } else {
+    Program pg = strip_program(j, n_max);
+    run_persistent({&pg}, t, static_cast<char*>(ws) + j.L.bytes + 256, st);
+  }
+  return CHROM_OK;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  explicit DevBuf(size_t n) {
+    if (n && hipMalloc(&p, n) != hipSuccess) throw MemError("device allocation of " + std::to_string(n) + " bytes failed");
+  }
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+int check_device_flag() {
+  unsigned* f = device_error_flag();
+  unsigned v = 0;
+  HIPX(hipMemcpy(&v, f, sizeof(v), hipMemcpyDeviceToHost));
+  if (v) {
+    HIPX(hipMemset(f, 0, sizeof(unsigned)));
+    throw BusyError("a persistent-kernel wait exceeded its spin limit");
+  }
+  return CHROM_OK;
+}
+
+int strip_sync_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, const uint32_t* p, int np, int mode,
+                    const chrom_tuning* tune, uint32_t* out) {
+  check_args(lattice, m, n_max);
+  std::vector<Inst> inst = make_instances(q, nq, p, np);
+  if (n_max == 0) return CHROM_OK;
+  if (!out) throw ArgError("null output");
+  Tune t = resolve(tune);
+  if (mode == CHROM_MODE_PERSISTENT) t.wpb = 4;
+  const int I = static_cast<int>(inst.size());
+  const size_t wsb = workspace_bytes(lattice, m, I, n_max, mode, t);
+  DevBuf ws(wsb);
+  const size_t outb = static_cast<size_t>(n_max) * I * 4;
+  DevBuf dout(outb);
+  HIPX(hipMemset(dout.p, 0, outb));
+  int rc = strip_async_impl(lattice, m, n_max, q, nq, p, np, mode, tune, ws.p, wsb, nullptr,
+                            static_cast<uint32_t*>(dout.p));
+  if (rc != CHROM_OK) return rc;
+  HIPX(hipDeviceSynchronize());
+  if (mode == CHROM_MODE_PERSISTENT) check_device_flag();
+  HIPX(hipMemcpy(out, dout.p, outb, hipMemcpyDeviceToHost));
+  if (mode == CHROM_MODE_GRAPH) {
+    // graphs captured on this workspace are invalid once it is freed
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+      if (it->first.ws == ws.p) {
+        (void)hipGraphExecDestroy(it->second.exec);
+        it = g_graphs.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  return CHROM_OK;
+}
+
+// Queues rows x m gather launches (T_1..T_m, read-out fused into T_m) on a
+// workspace that chromatic_strip_async (batched mode, same tuning) has set
+// up; nothing else.  Lets a caller time the factor kernel alone.
+int factor_launches_impl(int lattice, int m, const uint32_t* q, int nq, const uint32_t* p, int np, int rows,
+                         const chrom_tuning* tune, void* ws, size_t ws_bytes, hipStream_t st) {
+  check_args(lattice, m, 1);
+  if (rows < 1) throw ArgError("rows must be >= 1");
+  std::vector<Inst> inst = make_instances(q, nq, p, np);
+  Tune t = resolve(tune);
+  const int I = static_cast<int>(inst.size());
+  if (!ws || ws_bytes < workspace_bytes(lattice, m, I, 1, CHROM_MODE_BATCHED, t))
+    throw MemError("workspace missing or too small");
+  const DevMaps& dm = dev_maps(lattice, m);
+  JobCtx j;
+  j.dm = &dm;
+  j.t = t;
+  j.L = job_layout(lattice, m, I, t, kMaxCodes, rows_tile_of(t));
+  j.P = job_ptrs(j.L, ws);
+  j.d_out = nullptr;
+  Program pg;
+  pg.nchunk = j.L.nchunk;
+  add_rows(pg, j, 1, rows, -1, -1);
+  for (const PStep& ps : pg.steps)
+    if (ps.s.op == kOpGather) launch_step(ps.s, t.V, pg.nchunk, t.wpb, st);
+  return CHROM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Many jobs in one persistent launch
+// ---------------------------------------------------------------------------
+struct BatchPlan {
+  std::vector<size_t> job_off;
+  std::vector<JobLayout> layouts;
+  size_t queue_off = 0, bytes = 0;
+  int nsteps = 0;
+};
+
+BatchPlan batch_plan(const chrom_job* jobs, int njobs, const Tune& t) {
+  if (njobs < 0 || (njobs > 0 && !jobs)) throw ArgError("bad job list");
+  BatchPlan bp;
+  size_t off = 0;
+  for (int k = 0; k < njobs; ++k) {
+    const chrom_job& jb = jobs[k];
+    check_args(jb.lattice, jb.m, jb.n_max);
+    if (jb.nq < 1 || jb.np < 1) throw ArgError("job needs q points and primes");
+    JobLayout L = job_layout(jb.lattice, jb.m, jb.nq * jb.np, t, kMaxCodes, rows_tile_of(t));
+    bp.layouts.push_back(L);
+    bp.job_off.push_back(off);
+    off += align_up(L.bytes);
+    bp.nsteps += L.nchunk * strip_program_len(jb.m, jb.n_max);
+  }
+  bp.queue_off = off;
+  bp.bytes = off + program_queue_bytes(bp.nsteps);
+  return bp;
+}
+
+int batch_impl(const chrom_job* jobs, int njobs, const chrom_tuning* tune, void* ws, size_t ws_bytes, hipStream_t st) {
+  Tune t = resolve(tune);
+  t.wpb = 4;
+  BatchPlan bp = batch_plan(jobs, njobs, t);
+  if (njobs == 0) return CHROM_OK;
+  if (!ws) throw ArgError("null workspace");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) throw ArgError("workspace must be 256-byte aligned");
+  if (ws_bytes < bp.bytes) throw MemError("workspace too small: need " + std::to_string(bp.bytes) + " bytes");
+  std::vector<Program> progs(njobs);
+  std::vector<const Program*> pp;
+  for (int k = 0; k < njobs; ++k) {
+    const chrom_job& jb = jobs[k];
+    std::vector<Inst> inst = make_instances(jb.q_points, jb.nq, jb.primes, jb.np);
+    if (jb.n_max > 0 && !jb.d_out) throw ArgError("null job output");
+    const DevMaps& dm = dev_maps(jb.lattice, jb.m);
+    JobCtx j;
+    j.dm = &dm;
+    j.t = t;
+    j.L = bp.layouts[k];
+    void* base = static_cast<char*>(ws) + bp.job_off[k];
+    j.P = job_ptrs(j.L, base);
+    j.d_out = jb.d_out;
+    if (jb.n_max > 0) {
+      std::vector<uint32_t> img = const_image(j.L, inst, dm);
+      upload(static_cast<char*>(base) + j.L.p, img.data(), img.size() * 4, st);
+    }
+    progs[k] = strip_program(j, jb.n_max);
+    pp.push_back(&progs[k]);
+  }
+  run_persistent(pp, t, static_cast<char*>(ws) + bp.queue_off, st);
+  return CHROM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Server step
+// ---------------------------------------------------------------------------
+std::mutex g_srv_mu;
+void* g_srv_queue[64] = {nullptr};
+size_t g_srv_queue_bytes[64] = {0};
+
+void* server_queue(size_t bytes) {
+  int dev = 0;
+  HIPX(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_srv_mu);
+  if (g_srv_queue_bytes[dev] < bytes) {
+    if (g_srv_queue[dev]) {
+      HIPX(hipDeviceSynchronize());
+      HIPX(hipFree(g_srv_queue[dev]));
+    }
+    size_t nb = std::max(bytes, size_t(1) << 22);
+    if (hipMalloc(&g_srv_queue[dev], nb) != hipSuccess) throw MemError("server queue allocation failed");
+    g_srv_queue_bytes[dev] = nb;
+  }
+  return g_srv_queue[dev];
+}
+
+int server_step_impl(chrom_slot* slots, int nslots, int rows, const chrom_tuning* tune, hipStream_t st) {
+  if (nslots < 0 || (nslots > 0 && !slots)) throw ArgError("bad slot list");
+  if (rows < 1) throw ArgError("rows must be >= 1");
+  Tune t = resolve(tune);
+  t.wpb = 4;
+  std::vector<Program> progs(nslots);
+  std::vector<const Program*> pp;
+  std::vector<int> new_done(nslots);
+  for (int k = 0; k < nslots; ++k) {
+    chrom_slot& sl = slots[k];
+    check_args(sl.lattice, sl.m, sl.n_max);
+    new_done[k] = sl.rows_done;
+    if (sl.rows_done >= sl.n_max) continue;
+    if (sl.rows_done < 0) throw ArgError("rows_done must be >= 0");
+    const int I = sl.nq * sl.np;
+    if (I < 1) throw ArgError("slot needs q points and primes");
+    JobLayout L = job_layout(sl.lattice, sl.m, I, t, kMaxCodes, rows_tile_of(t));
+    if (!sl.d_state || sl.state_bytes < L.bytes) throw MemError("slot state buffer too small");
+    if (reinterpret_cast<uintptr_t>(sl.d_state) % 256 != 0) throw ArgError("slot state must be 256-byte aligned");
+    if (!sl.d_out) throw ArgError("null slot output");
+    const DevMaps& dm = dev_maps(sl.lattice, sl.m);
+    JobCtx j;
+    j.dm = &dm;
+    j.t = t;
+    j.L = L;
+    j.P = job_ptrs(L, sl.d_state);
+    j.d_out = sl.d_out;
+    progs[k].nchunk = L.nchunk;
+    int first = sl.rows_done;
+    int last_row = std::min(sl.n_max - 1, first + rows - 1);  // 0-based out rows to produce
+    if (first == 0) {
+      std::vector<Inst> inst = make_instances(sl.q_points, sl.nq, sl.primes, sl.np);
+      std::vector<uint32_t> img = const_image(L, inst, dm);
+      upload(static_cast<char*>(sl.d_state) + L.p, img.data(), img.size() * 4, st);
+      int red = add_setup(progs[k], j);
+      if (last_row >= 1) add_rows(progs[k], j, 1, last_row, red, red);
+    } else {
+      add_rows(progs[k], j, first, last_row, -1, -1);
+    }
+    new_done[k] = last_row + 1;
+    pp.push_back(&progs[k]);
+  }
+  int nsteps = 0;
+  for (const Program* pg : pp) nsteps += pg->nchunk * static_cast<int>(pg->steps.size());
+  if (nsteps > 0) {
+    void* q = server_queue(program_queue_bytes(nsteps));
+    run_persistent(pp, t, q, st);
+  }
+  for (int k = 0; k < nslots; ++k) slots[k].rows_done = new_done[k];
+  return CHROM_OK;
+}
+
+}  // namespace
+}  // namespace cs
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+using namespace cs;
+
+extern "C" {
+
+const char* chromatic_last_error(void) { return g_err.c_str(); }
+
+const char* chromatic_version(void) { return "chromstrip 0.1 (gfx950)"; }
+
+int chromatic_strip(int lattice, int m, int n_max, const uint32_t* q_points, int nq, const uint32_t* primes, int np,
+                    uint32_t* out) {
+  return guarded([&] { return strip_sync_impl(lattice, m, n_max, q_points, nq, primes, np, CHROM_MODE_PLAIN, nullptr, out); });
+}
+
+int chromatic_strip_batched(int lattice, int m, int n_max, const uint32_t* q_points, int nq, const uint32_t* primes,
+                            int np, int mode, const chrom_tuning* tune, uint32_t* out) {
+  return guarded([&] {
+    if (mode != CHROM_MODE_BATCHED && mode != CHROM_MODE_GRAPH && mode != CHROM_MODE_PERSISTENT)
+      throw ArgError("mode must be BATCHED, GRAPH or PERSISTENT");
+    return strip_sync_impl(lattice, m, n_max, q_points, nq, primes, np, mode, tune, out);
+  });
+}
+
+size_t chromatic_workspace_bytes(int lattice, int m, int n_max, int nq, int np, int mode, const chrom_tuning* tune) {
+  size_t r = 0;
+  int rc = guarded([&] {
+    check_args(lattice, m, n_max);
+    if (nq < 1 || np < 1) throw ArgError("need nq, np >= 1");
+    if (mode < CHROM_MODE_PLAIN || mode > CHROM_MODE_PERSISTENT) throw ArgError("unknown mode");
+    Tune t = resolve(tune);
+    if (mode == CHROM_MODE_PERSISTENT) t.wpb = 4;
+    r = workspace_bytes(lattice, m, nq * np, n_max, mode, t);
+    return CHROM_OK;
+  });
+  return rc == CHROM_OK ? r : 0;
+}
+
+int chromatic_strip_async(int lattice, int m, int n_max, const uint32_t* q_points, int nq, const uint32_t* primes,
+                          int np, int mode, const chrom_tuning* tune, void* d_workspace, size_t ws_bytes, void* stream,
+                          uint32_t* d_out) {
+  return guarded([&] {
+    return strip_async_impl(lattice, m, n_max, q_points, nq, primes, np, mode, tune, d_workspace, ws_bytes,
+                            static_cast<hipStream_t>(stream), d_out);
+  });
+}
+
+int chromatic_factor_launches(int lattice, int m, const uint32_t* q_points, int nq, const uint32_t* primes, int np,
+                              int rows, const chrom_tuning* tune, void* d_workspace, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    return factor_launches_impl(lattice, m, q_points, nq, primes, np, rows, tune, d_workspace, ws_bytes,
+                                static_cast<hipStream_t>(stream));
+  });
+}
+
+int chromatic_prepare(int lattice, int m) {
+  return guarded([&] {
+    check_args(lattice, m, 0);
+    (void)dev_maps(lattice, m);
+    return CHROM_OK;
+  });
+}
+
+void chromatic_release_maps(void) {
+  (void)guarded([&] {
+    {
+      std::lock_guard<std::mutex> lk(g_graph_mu);
+      for (auto& kv : g_graphs) (void)hipGraphExecDestroy(kv.second.exec);
+      g_graphs.clear();
+    }
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    for (auto& kv : g_dev) {
+      int cur = 0;
+      (void)hipGetDevice(&cur);
+      (void)hipSetDevice(std::get<0>(kv.first));
+      (void)hipFree(kv.second->base);
+      (void)hipSetDevice(cur);
+    }
+    g_dev.clear();
+    release_host_maps();
+    return CHROM_OK;
+  });
+}
+
+size_t chromatic_batch_workspace_bytes(const chrom_job* jobs, int njobs, const chrom_tuning* tune) {
+  size_t r = 0;
+  int rc = guarded([&] {
+    Tune t = resolve(tune);
+    t.wpb = 4;
+    r = batch_plan(jobs, njobs, t).bytes;
+    return CHROM_OK;
+  });
+  return rc == CHROM_OK ? r : 0;
+}
+
+int chromatic_batch(const chrom_job* jobs, int njobs, const chrom_tuning* tune, void* d_workspace, size_t ws_bytes,
+                    void* stream) {
+  return guarded([&] { return batch_impl(jobs, njobs, tune, d_workspace, ws_bytes, static_cast<hipStream_t>(stream)); });
+}
+
+size_t chromatic_slot_state_bytes(int lattice, int m, int nq, int np, const chrom_tuning* tune) {
+  size_t r = 0;
+  int rc = guarded([&] {
+    check_args(lattice, m, 0);
+    if (nq < 1 || np < 1) throw ArgError("need nq, np >= 1");
+    Tune t = resolve(tune);
+    t.wpb = 4;
+    r = job_layout(lattice, m, nq * np, t, kMaxCodes, rows_tile_of(t)).bytes;
+    return CHROM_OK;
+  });
+  return rc == CHROM_OK ? r : 0;
+}
+
+int chromatic_server_step(chrom_slot* slots, int nslots, int rows, const chrom_tuning* tune, void* stream) {
+  return guarded([&] { return server_step_impl(slots, nslots, rows, tune, static_cast<hipStream_t>(stream)); });
+}
+
+int chromatic_device_status(void* stream) {
+  return guarded([&] {
+    HIPX(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    return check_device_flag();
+  });
+}
+
+int64_t chromatic_motzkin(int k) { return motzkin(k); }
+
+int64_t chromatic_space_size(int m, int space, int i) {
+  if (m < 1 || m > CHROM_MAX_M) return fail(CHROM_EINVAL, "m out of range");
+  if (space == CHROM_SPACE_NCNNN) return Space{kNcnnn, m, 0}.size();
+  if (space == CHROM_SPACE_SQ_INTER) {
+    if (i < 1 || i >= m) return fail(CHROM_EINVAL, "i must be in 1..m-1");
+    return Space{kSqInter, m, i}.size();
+  }
+  if (space == CHROM_SPACE_LAST) {
+    if (i < 0 || i > m) return fail(CHROM_EINVAL, "i must be in 0..m");
+    return i == 0 ? Space{kNcnnn, m, 0}.size() : Space{kLast, m, i}.size();
+  }
+  return fail(CHROM_EINVAL, "unknown space");
+}
+
+static bool space_of(int m, int space, int i, Space* sp) {
+  if (m < 1 || m > CHROM_MAX_M) return false;
+  if (space == CHROM_SPACE_NCNNN) {
+    *sp = Space{kNcnnn, m, 0};
+    return true;
+  }
+  if (space == CHROM_SPACE_SQ_INTER && i >= 1 && i < m) {
+    *sp = Space{kSqInter, m, i};
+    return true;
+  }
+  if (space == CHROM_SPACE_LAST && i >= 0 && i <= m) {
+    *sp = i == 0 ? Space{kNcnnn, m, 0} : Space{kLast, m, i};
+    return true;
+  }
+  return false;
+}
+
+int64_t chromatic_rank(int m, int space, int i, const uint8_t* lab) {
+  Space sp;
+  if (!lab || !space_of(m, space, i, &sp)) return fail(CHROM_EINVAL, "bad space or labels") - 1;
+  Part p;
+  std::memcpy(p.lab, lab, m);
+  canonicalize(p, m);
+  if (!is_noncrossing(p, m)) return -1;
+  return sp.rank(p);
+}
+
+int chromatic_unrank(int m, int space, int i, int64_t r, uint8_t* lab) {
+  Space sp;
+  if (!lab || !space_of(m, space, i, &sp)) return fail(CHROM_EINVAL, "bad space or labels");
+  if (r < 0 || r >= sp.size()) return fail(CHROM_EINVAL, "rank out of range");
+  Part p;
+  sp.unrank(r, p);
+  std::memcpy(lab, p.lab, m);
+  return CHROM_OK;
+}
+
+int chromatic_maps_info(int lattice, int m, chrom_maps_info* info) {
+  return guarded([&] {
+    check_args(lattice, m, 0);
+    if (!info) throw ArgError("null info");
+    const MapSet& ms = get_maps(lattice, m);
+    info->n_factors = m;
+    info->n_last = m;
+    info->n_codes = ms.n_codes;
+    for (int k = 0; k < 16; ++k) {
+      info->code_a[k] = ms.code_a[k];
+      info->code_b[k] = ms.code_b[k];
+    }
+    info->total_nnz = ms.total_nnz();
+    info->max_states = ms.max_states();
+    return CHROM_OK;
+  });
+}
+
+int chromatic_map_export(int lattice, int m, int which, int idx, int64_t* n_rows, int64_t* n_cols, int64_t* nnz,
+                         int32_t* row_ptr, uint32_t* entries) {
+  return guarded([&] {
+    check_args(lattice, m, 0);
+    if (which != 0 && which != 1) throw ArgError("which must be 0 or 1");
+    if (idx < 0 || idx >= m) throw ArgError("idx out of range");
+    const MapSet& ms = get_maps(lattice, m);
+    const Csr& c = which == 0 ? ms.fwd[idx] : ms.last[idx];
+    if (n_rows) *n_rows = c.n_rows;
+    if (n_cols) *n_cols = c.n_cols;
+    if (nnz) *nnz = c.nnz();
+    if (row_ptr) std::memcpy(row_ptr, c.row_ptr.data(), c.row_ptr.size() * 4);
+    if (entries && !c.ent.empty()) std::memcpy(entries, c.ent.data(), c.ent.size() * 4);
+    return CHROM_OK;
+  });
+}
+
+}  // extern "C"

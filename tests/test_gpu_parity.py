@@ -1,0 +1,189 @@
+"""GPU parity: every execution path of the native library against the CPU
+oracle, bit for bit (the arithmetic is exact, so the tolerance is zero).
+
+Small cases run the oracle live; full-size workloads compare against stored
+oracle values written by tests/golden/make_golden.py on sampled instances,
+plus invariants that hold at any size."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import graphs as OG
+from oracle import transfer as OT
+from paper_1005_3609_amd import api, host
+from paper_1005_3609_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+P31 = 2 ** 31 - 1
+HERE = os.path.dirname(os.path.abspath(__file__))
+MODES = ["plain", "batched", "graph", "persistent"]
+
+
+def _golden(name):
+    with open(os.path.join(HERE, "golden", name)) as f:
+        return json.load(f)
+
+
+def _sampled(res, g):
+    """res [n][nq][np] -> [n][len(sample)] for the golden file's instances."""
+    flat = res.reshape(res.shape[0], -1)
+    return flat[:, g["instance_index"]].astype(np.int64)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    yield
+
+
+# ---------------------------------------------------------------------------
+# The 4 x 5 square rectangle, q = 0..20, p = 2^31 - 1
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", MODES)
+def test_square_4x5_all_q(mode):
+    q = list(range(21))
+    got = api.strip("square", 4, 5, q, [P31], mode=mode).astype(np.int64)
+    np.testing.assert_array_equal(got, OT.chromatic_grid("square", 4, 5, q, [P31]))
+    exact = OG.chromatic_by_colour_classes("square", 4, 5)
+    V, E = OG.lattice_graph("square", 4, 5)
+    assert [int(x) for x in got[-1, :, 0]] == [OG.poly_eval(exact, qq) % P31 for qq in q]
+    # brute-force colour counts where they are cheap
+    V3, E3 = OG.lattice_graph("square", 4, 3)
+    for qq in range(4):
+        assert int(got[2, qq, 0]) == OG.count_colourings(V3, E3, qq) % P31
+
+
+def test_square_4x5_interpolates_to_the_exact_polynomial():
+    q = list(range(21))
+    got = api.strip("square", 4, 5, q, [P31], mode="batched")
+    coeffs, _ = host.exact_polynomial(q, got[-1], [P31])
+    assert coeffs == OT.chromatic_exact("square", 4, 5)[-1]
+    assert coeffs[20] == 1 and coeffs[19] == -31 and coeffs[18] == 465 and coeffs[0] == 0
+
+
+# ---------------------------------------------------------------------------
+# Small widths, every path, ragged instance counts
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("lat", ["square", "triangular"])
+@pytest.mark.parametrize("m", [1, 2, 3, 5, 8])
+def test_small_widths_all_paths(lat, m):
+    q = list(range(0, 35))                      # 35 x 2 = 70 instances: ragged chunks
+    p = [P31, 1000000007]
+    want = OT.chromatic_grid(lat, m, 6, q, p)
+    for mode in MODES:
+        got = api.strip(lat, m, 6, q, p, mode=mode).astype(np.int64)
+        np.testing.assert_array_equal(got, want, err_msg=mode)
+
+
+@pytest.mark.parametrize("tune", [
+    dict(lanes_v=1, targets_per_wave=1, waves_per_block=1),
+    dict(lanes_v=1, targets_per_wave=16, waves_per_block=8),
+    dict(lanes_v=2, targets_per_wave=4, waves_per_block=2),
+    dict(lanes_v=4, targets_per_wave=8, waves_per_block=4),
+    dict(lanes_v=4, targets_per_wave=64, waves_per_block=1),
+])
+def test_tuning_choices_are_bit_identical(tune):
+    q = list(range(1, 66))                      # 65 q x 2 p = 130 instances
+    p = [P31, 998244353]
+    want = OT.chromatic_grid("square", 7, 5, q, p)
+    for mode in ("batched", "graph", "persistent"):
+        got = api.strip("square", 7, 5, q, p, mode=mode, tuning=tune).astype(np.int64)
+        np.testing.assert_array_equal(got, want, err_msg=f"{mode} {tune}")
+
+
+def test_edge_cases():
+    # m = 1 paths, n_max = 1, one instance, q >= p, q = 0
+    for lat in ("square", "triangular"):
+        for mode in MODES:
+            got = api.strip(lat, 1, 7, [0, 3, P31 + 5], [P31], mode=mode).astype(np.int64)
+            np.testing.assert_array_equal(got, OT.chromatic_grid(lat, 1, 7, [0, 3, 5], [P31]))
+            got = api.strip(lat, 6, 1, [4], [101], mode=mode).astype(np.int64)
+            np.testing.assert_array_equal(got, OT.chromatic_grid(lat, 6, 1, [4], [101]))
+    assert api.strip("square", 5, 0, [3], [P31], mode="batched").shape == (0, 1, 1)
+
+
+def test_repeat_runs_identical():
+    q, p = list(range(1, 40)), [P31]
+    a = api.strip("triangular", 9, 7, q, p, mode="persistent")
+    for _ in range(3):
+        assert np.array_equal(api.strip("triangular", 9, 7, q, p, mode="persistent"), a)
+        assert np.array_equal(api.strip("triangular", 9, 7, q, p, mode="graph"), a)
+
+
+# ---------------------------------------------------------------------------
+# Workload: square m = 10, n = 1..11, q = 1..80 x 4 primes (plain path)
+# ---------------------------------------------------------------------------
+def test_square_m10_plain_and_batched():
+    w = W.workload("square_m10")
+    lat, m, n = w["strips"][0]
+    want = OT.chromatic_grid(lat, m, n, w["q_points"], w["primes"])
+    for mode in ("plain", "batched"):
+        got = api.strip(lat, m, n, w["q_points"], w["primes"], mode=mode).astype(np.int64)
+        np.testing.assert_array_equal(got, want, err_msg=mode)
+
+
+# ---------------------------------------------------------------------------
+# Workload: triangular m = 12, n = 1..13, 48 q x 6 primes (graph + persistent)
+# ---------------------------------------------------------------------------
+def test_triangular_m12_against_stored_oracle():
+    w = W.workload("triangular_m12")
+    g = _golden("oracle_triangular_12x13.json")
+    for mode in ("graph", "persistent"):
+        got = api.strip("triangular", 12, 13, w["q_points"], w["primes"], mode=mode)
+        np.testing.assert_array_equal(_sampled(got, g), np.array(g["z"], dtype=np.int64), err_msg=mode)
+        # invariants at every length: P(1) = 0; P(2) = 0 and P(3) = 6 for r >= 2
+        flat = got.reshape(13, 48, 6).astype(np.int64)
+        assert (flat[:, 0, :] == 0).all()
+        assert (flat[1:, 1, :] == 0).all() and (flat[1:, 2, :] == 6).all()
+
+
+# ---------------------------------------------------------------------------
+# Workload: square m = 2..14, n <= m+1, 80 q x 8 primes, one persistent launch
+# ---------------------------------------------------------------------------
+def test_square_sweep_one_launch():
+    import torch
+    w = W.workload("square_sweep_2_14")
+    jobs = [dict(lattice=lat, m=m, n_max=n, q_points=w["q_points"], primes=w["primes"])
+            for lat, m, n in w["strips"]]
+    outs, ws = api.batch(jobs)
+    torch.cuda.synchronize()
+    api.device_status()
+    res = {jb["m"]: api.to_u32(o).astype(np.int64) for jb, o in zip(jobs, outs)}
+    sample = W.sample_instances(640, 24, 5)
+    qs = [w["q_points"][k // 8] for k in sample]
+    ps = [w["primes"][k % 8] for k in sample]
+    for m in range(2, 11):
+        want = OT.chromatic_residues("square", m, m + 1, qs, ps)
+        got = res[m].reshape(m + 1, -1)[:, sample]
+        np.testing.assert_array_equal(got, want, err_msg=f"m={m}")
+    for m in range(11, 15):
+        g = _golden(f"oracle_square_{m}x{m + 1}.json")
+        np.testing.assert_array_equal(_sampled(res[m], g), np.array(g["z"], dtype=np.int64), err_msg=f"m={m}")
+    for m in range(2, 15):
+        z = res[m].reshape(m + 1, 80, 8)
+        assert (z[:, 0, :] == 0).all() and (z[:, 1, :] == 2).all()   # P(1) = 0, P(2) = 2
+    # transposition: P(m x (m+1)) from width m equals P((m+1) x m) from width m+1
+    for m in range(2, 14):
+        np.testing.assert_array_equal(res[m][m], res[m + 1][m - 1])
+
+
+# ---------------------------------------------------------------------------
+# Square 18 x 19 (the large-state run), 640 instances
+# ---------------------------------------------------------------------------
+def test_square_18x19_against_transposed_oracle():
+    import torch
+    w = W.workload("square_18x19")
+    g = _golden("oracle_square_18x19.json")
+    out, ws = api.strip_async("square", 18, 19, w["q_points"], w["primes"], mode="batched")
+    torch.cuda.synchronize()
+    res = api.to_u32(out).astype(np.int64)
+    rows = g["rows_present"]
+    np.testing.assert_array_equal(_sampled(res, g)[:rows], np.array(g["z"], dtype=np.int64))
+    z = res.reshape(19, 80, 8)
+    assert (z[:, 0, :] == 0).all() and (z[:, 1, :] == 2).all()
+    del ws
