@@ -82,7 +82,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="graph", choices=["batched", "graph", "persistent"])
+    ap.add_argument("--mode", default="graph", choices=["batched", "graph", "grouped"])
     ap.add_argument("--lanes-v", type=int, default=0)
     ap.add_argument("--targets-per-wave", type=int, default=0)
     ap.add_argument("--waves-per-block", type=int, default=0)
@@ -142,8 +142,6 @@ def main():
     ms = ev0.elapsed_time(ev1)
     ms_per_step = ms / args.steps
     value = updates_per_step / (ms_per_step / 1e3)
-    if args.mode == "persistent":
-        api.device_status(stream)
     res = api.to_u32(out).astype("int64").reshape(n, len(q), len(p))
     assert (res[:, 0, :] == 0).all() and (res[:, 1, :] == 2).all(), "invariants P(1)=0, P(2)=2 failed"
     log(f"{args.mode}: {ms_per_step:.3f} ms/step, {value:.3e} state-updates/s (wall {wall:.2f} s)")

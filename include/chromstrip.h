@@ -50,8 +50,7 @@ enum {
   CHROM_EINVAL = -1,        /* bad argument */
   CHROM_ENOMEM = -2,        /* host or device allocation failed / workspace too small */
   CHROM_EDEVICE = -3,       /* a HIP call failed */
-  CHROM_EUNSUPPORTED = -4,  /* size beyond what the library handles */
-  CHROM_EBUSY = -5,         /* a device-side wait exceeded its spin limit */
+  CHROM_EUNSUPPORTED = -4,  /* size or mode the library does not handle */
 };
 
 enum { CHROM_SQUARE = 0, CHROM_TRIANGULAR = 1 };
@@ -61,7 +60,8 @@ enum {
   CHROM_MODE_PLAIN = 0,      /* per-instance vectors [S], one launch per factor per instance */
   CHROM_MODE_BATCHED = 1,    /* instance-minor vectors, one launch per factor for all instances */
   CHROM_MODE_GRAPH = 2,      /* as BATCHED, one row captured in a hipGraph and replayed */
-  CHROM_MODE_PERSISTENT = 3, /* one persistent launch runs the whole sweep */
+  CHROM_MODE_PERSISTENT = 3, /* disabled (returns CHROM_EUNSUPPORTED): device work queue */
+  CHROM_MODE_GROUPED = 4,    /* every step one grouped launch; the whole sweep one hipGraph */
 };
 
 /* Launch shape of the batched and persistent kernels.  Zero fields take
@@ -70,8 +70,6 @@ typedef struct chrom_tuning {
   int lanes_v;          /* instances per lane: 1, 2 or 4 (chunk width W = 64 * lanes_v) */
   int targets_per_wave; /* consecutive target states handled by one wavefront, 1..64 */
   int waves_per_block;  /* wavefronts per workgroup: 1, 2, 4 or 8 */
-  int grid_blocks;      /* persistent mode: workgroups in the grid (0 = fill the device) */
-  int readout_blocks;   /* read-out: workgroups per chunk for the dot product (0 = auto) */
 } chrom_tuning;
 
 /* ------------------------------------------------------------------------
@@ -87,7 +85,7 @@ int chromatic_strip(int lattice, int m, int n_max,
                     uint32_t* out);
 
 /* Same result through the batched path (mode CHROM_MODE_BATCHED, GRAPH or
- * PERSISTENT), synchronous, host buffers, internal allocation.  tune may be
+ * GROUPED), synchronous, host buffers, internal allocation.  tune may be
  * NULL. */
 int chromatic_strip_batched(int lattice, int m, int n_max,
                             const uint32_t* q_points, int nq,
@@ -96,7 +94,7 @@ int chromatic_strip_batched(int lattice, int m, int n_max,
                             uint32_t* out);
 
 /* Device-workspace size in bytes needed by chromatic_strip_async for the
- * same arguments (the persistent mode's work queue grows with n_max).
+ * same arguments (the grouped mode's stage tables grow with n_max).
  * Returns 0 on bad arguments. */
 size_t chromatic_workspace_bytes(int lattice, int m, int n_max, int nq, int np,
                                  int mode, const chrom_tuning* tune);
@@ -152,11 +150,14 @@ typedef struct chrom_job {
 size_t chromatic_batch_workspace_bytes(const chrom_job* jobs, int njobs,
                                        const chrom_tuning* tune);
 
-/* Runs every job to completion in ONE persistent kernel launch on
- * `stream`: each job is split into instance chunks of width 64*lanes_v,
- * every (job, chunk) item walks its sweep step by step, and workgroups take
- * (item, step, tile) tasks from a device queue ordered so that independent
- * items overlap.  Same results as chromatic_strip for each job. */
+/* Runs every job to completion on `stream` as ONE hipGraph launch: each job
+ * is split into instance chunks of width 64*lanes_v, and step k of every
+ * (job, chunk) item runs in one grouped kernel launch whose workgroups map
+ * to (item, tile) pairs, so jobs of uneven state-space size share every
+ * launch.  The graph is captured once per workspace and job list and
+ * replayed on later identical calls.  Same results as chromatic_strip for
+ * each job.  The workspace must not be reused for another job list while a
+ * launch on it is in flight. */
 int chromatic_batch(const chrom_job* jobs, int njobs, const chrom_tuning* tune,
                     void* d_workspace, size_t ws_bytes, void* stream);
 
@@ -182,15 +183,14 @@ size_t chromatic_slot_state_bytes(int lattice, int m, int nq, int np,
                                   const chrom_tuning* tune);
 
 /* Advances every slot by up to `rows` rows (a new slot first runs its
- * set-up and reads out r = 1) in ONE persistent launch on `stream`, and
- * updates rows_done.  Slots may differ in lattice, m and instance count. */
+ * set-up and reads out r = 1) on `stream`, and updates rows_done.  Step k of
+ * every slot runs in one grouped launch, so slots that differ in lattice, m
+ * and instance count share each launch.  Server steps on one device must be
+ * issued on one stream (they share a stage-table buffer). */
 int chromatic_server_step(chrom_slot* slots, int nslots, int rows,
                           const chrom_tuning* tune, void* stream);
 
-/* Synchronises `stream` and reports whether a persistent launch on the
- * current device had a dependency wait exceed its spin limit since the last
- * check (CHROM_EBUSY; the flag is then cleared) -- a safety net that turns a
- * would-be hang into an error.  The synchronous calls check it themselves. */
+/* Synchronises `stream` and reports a pending HIP error (CHROM_EDEVICE). */
 int chromatic_device_status(void* stream);
 
 /* ------------------------------------------------------------------------

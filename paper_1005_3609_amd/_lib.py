@@ -11,9 +11,9 @@ LIB_PATH = os.path.join(PKG, "libchromstrip.so")
 HEADER = os.path.join(os.path.dirname(PKG), "include", "chromstrip.h")
 
 CHROM_OK = 0
-ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED", -5: "EBUSY"}
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED"}
 SQUARE, TRIANGULAR = 0, 1
-MODES = {"plain": 0, "batched": 1, "graph": 2, "persistent": 3}
+MODES = {"plain": 0, "batched": 1, "graph": 2, "persistent": 3, "grouped": 4}
 SPACE_NCNNN, SPACE_SQ_INTER, SPACE_LAST = 0, 1, 2
 
 
@@ -24,8 +24,7 @@ class ChromError(RuntimeError):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("lanes_v", C.c_int), ("targets_per_wave", C.c_int), ("waves_per_block", C.c_int),
-                ("grid_blocks", C.c_int), ("readout_blocks", C.c_int)]
+    _fields_ = [("lanes_v", C.c_int), ("targets_per_wave", C.c_int), ("waves_per_block", C.c_int)]
 
 
 class Job(C.Structure):
@@ -117,5 +116,4 @@ def tuning(t) -> "Tuning | None":
         return None
     if isinstance(t, Tuning):
         return t
-    return Tuning(int(t.get("lanes_v", 0)), int(t.get("targets_per_wave", 0)), int(t.get("waves_per_block", 0)),
-                  int(t.get("grid_blocks", 0)), int(t.get("readout_blocks", 0)))
+    return Tuning(int(t.get("lanes_v", 0)), int(t.get("targets_per_wave", 0)), int(t.get("waves_per_block", 0)))

@@ -133,7 +133,7 @@ def to_u32(t) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# Many jobs in one persistent launch
+# Many jobs in one graph of grouped launches
 # ---------------------------------------------------------------------------
 def _job_structs(jobs, outs):
     arr = (_lib.Job * len(jobs))()
@@ -163,8 +163,8 @@ def batch_workspace_bytes(jobs, tuning=None) -> int:
 
 
 def batch(jobs, tuning=None, workspace=None, outs=None, stream=None, device=None):
-    """Runs every job (dicts with lattice, m, n_max, q_points, primes) in one
-    persistent launch.  Returns (list of output tensors, workspace)."""
+    """Runs every job (dicts with lattice, m, n_max, q_points, primes) as one
+    hipGraph of grouped launches.  Returns (list of output tensors, workspace)."""
     torch = _torch()
     dev = device or "cuda"
     if outs is None:

@@ -394,14 +394,13 @@ __global__ void __launch_bounds__(256) k_dot_plain(const uint32_t* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Persistent work-queue kernel
+// Grouped launches: one launch runs one step of many (job, chunk) items
 // ---------------------------------------------------------------------------
 enum StepOp : int { kOpFill = 0, kOpGather = 1, kOpDot = 2, kOpReduce = 3 };
 
 struct Step {
   int op;
   int ntiles;
-  int dep0, dep1;          // global step indices that must be complete (-1: none)
   int chunk;               // chunk index handed to the tile body
   int pad_;
   union {
@@ -412,71 +411,32 @@ struct Step {
   } u;
 };
 
-struct QueueArgs {
+// Workgroup b runs tile (b - tile_start[k]) of steps[k], k the largest index
+// with tile_start[k] <= b.  Items of one launch never share buffers, and the
+// launches of a sweep run in stream order, so no workgroup waits on another.
+struct GroupArgs {
   const Step* steps;
-  const int* order;        // task order: steps by order[k]
-  const long* start;       // start[k] = first task id of order[k]; start[nsteps] = total
+  const int* tile_start;   // nsteps + 1 prefix sums of ntiles
   int nsteps;
-  unsigned* done;          // completed tiles per global step index
-  unsigned* counter;       // next task id
-  unsigned* error;         // set to 1 when a wait exceeds its spin limit
-  long spin_limit;
 };
 
-__device__ __forceinline__ bool wait_done(const QueueArgs& q, int dep, unsigned need) {
-  if (dep < 0) return true;
-  long spins = 0;
-  while (__hip_atomic_load(q.done + dep, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
-    __builtin_amdgcn_s_sleep(2);
-    if (++spins > q.spin_limit ||
-        __hip_atomic_load(q.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-      __hip_atomic_store(q.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return false;
-    }
-  }
-  return true;
-}
-
 template <int V>
-__global__ void __launch_bounds__(256) k_persistent(QueueArgs q) {
-  __shared__ uint32_t lds[4 * 64 * V];
-  __shared__ long s_task;
-  __shared__ int s_ok;
-  const long total = q.start[q.nsteps];
-  while (true) {
-    if (threadIdx.x == 0) s_task = static_cast<long>(atomicAdd(q.counter, 1u));
-    __syncthreads();
-    const long t = s_task;
-    if (t >= total) break;
-    // locate the step: largest k with start[k] <= t
-    int lo = 0, hi = q.nsteps - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (q.start[mid] <= t) lo = mid; else hi = mid - 1;
-    }
-    const int sidx = __builtin_amdgcn_readfirstlane(q.order[lo]);
-    const Step& st = q.steps[sidx];
-    const int tile = __builtin_amdgcn_readfirstlane(static_cast<int>(t - q.start[lo]));
-    if (threadIdx.x == 0) {
-      bool ok = true;
-      if (st.dep0 >= 0) ok = wait_done(q, st.dep0, static_cast<unsigned>(q.steps[st.dep0].ntiles));
-      if (ok && st.dep1 >= 0) ok = wait_done(q, st.dep1, static_cast<unsigned>(q.steps[st.dep1].ntiles));
-      s_ok = ok ? 1 : 0;
-    }
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (s_ok) {
-      switch (st.op) {
-        case kOpGather: gather_tile<V>(st.u.g, st.chunk, tile, lds); break;
-        case kOpDot: dot_tile<V>(st.u.d, st.chunk, tile, lds); break;
-        case kOpFill: fill_tile<V>(st.u.f, st.chunk, tile); break;
-        case kOpReduce: reduce_tile<V>(st.u.r, st.chunk); break;
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (threadIdx.x == 0)
-      __hip_atomic_fetch_add(q.done + sidx, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__global__ void __launch_bounds__(512) k_grouped(GroupArgs g) {
+  __shared__ uint32_t lds[8 * 64 * V];
+  const int b = blockIdx.x;
+  int lo = 0, hi = g.nsteps - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (g.tile_start[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const int k = __builtin_amdgcn_readfirstlane(lo);
+  const int tile = __builtin_amdgcn_readfirstlane(b - g.tile_start[k]);
+  const Step& st = g.steps[k];
+  switch (st.op) {
+    case kOpGather: gather_tile<V>(st.u.g, st.chunk, tile, lds); break;
+    case kOpDot: dot_tile<V>(st.u.d, st.chunk, tile, lds); break;
+    case kOpFill: fill_tile<V>(st.u.f, st.chunk, tile); break;
+    case kOpReduce: reduce_tile<V>(st.u.r, st.chunk); break;
   }
 }
 

@@ -45,9 +45,6 @@ struct ArgError : std::runtime_error {
 struct MemError : std::runtime_error {
   using std::runtime_error::runtime_error;
 };
-struct BusyError : std::runtime_error {
-  using std::runtime_error::runtime_error;
-};
 
 #define HIPX(expr)                                                                  \
   do {                                                                              \
@@ -64,8 +61,6 @@ int guarded(F&& f) {
     return fail(CHROM_EINVAL, e.what());
   } catch (const MemError& e) {
     return fail(CHROM_ENOMEM, e.what());
-  } catch (const BusyError& e) {
-    return fail(CHROM_EBUSY, e.what());
   } catch (const HipError& e) {
     return fail(CHROM_EDEVICE, e.what());
   } catch (const std::bad_alloc&) {
@@ -230,7 +225,7 @@ uint32_t shoup_of(uint32_t c, uint32_t p) {
 // Tuning and workspace layout
 // ---------------------------------------------------------------------------
 struct Tune {
-  int V = 2, rpw = 8, wpb = 4, grid = 0, readout_blocks = 0;
+  int V = 2, rpw = 8, wpb = 4;
 };
 
 Tune resolve(const chrom_tuning* t) {
@@ -239,12 +234,9 @@ Tune resolve(const chrom_tuning* t) {
   if (t->lanes_v) r.V = t->lanes_v;
   if (t->targets_per_wave) r.rpw = t->targets_per_wave;
   if (t->waves_per_block) r.wpb = t->waves_per_block;
-  r.grid = t->grid_blocks;
-  r.readout_blocks = t->readout_blocks;
   if (r.V != 1 && r.V != 2 && r.V != 4) throw ArgError("lanes_v must be 1, 2 or 4");
   if (r.rpw < 1 || r.rpw > 64) throw ArgError("targets_per_wave must be in 1..64");
   if (r.wpb != 1 && r.wpb != 2 && r.wpb != 4 && r.wpb != 8) throw ArgError("waves_per_block must be 1, 2, 4 or 8");
-  if (r.grid < 0) throw ArgError("grid_blocks must be >= 0");
   return r;
 }
 
@@ -340,6 +332,15 @@ JobPtrs job_ptrs(const JobLayout& L, void* base) {
 
 InstConsts inst_consts(const JobLayout& L, const JobPtrs& j) {
   return InstConsts{j.p, j.pinv, j.cval, j.cshp, L.ipad};
+}
+
+// The persistent work-queue mode (workgroups waiting on completion counters
+// of other workgroups) is switched off: it stalled on the device.  Grouped
+// launches replace it.
+void check_mode(int mode) {
+  if (mode == CHROM_MODE_PERSISTENT)
+    throw std::runtime_error("the persistent work-queue mode is disabled; use CHROM_MODE_GROUPED");
+  if (mode < CHROM_MODE_PLAIN || mode > CHROM_MODE_GROUPED) throw ArgError("unknown mode");
 }
 
 void check_args(int lattice, int m, int n_max) {
@@ -595,131 +596,138 @@ void run_graph(const JobCtx& j, int n_max, int* row_ctr, void* ws, hipStream_t s
 }
 
 // ---------------------------------------------------------------------------
-// Persistent execution: every (program, chunk) item in one launch
+// Grouped execution: stage k is ONE launch running step k of every
+// (program, chunk) item; stages run in stream order.  A whole batch or sweep
+// can be captured as one hipGraph.
 // ---------------------------------------------------------------------------
-struct QueueLayout {
-  size_t steps = 0, order = 0, start = 0, done = 0, counter = 0, bytes = 0;
-  int nsteps = 0;
+struct StageImage {
+  std::vector<Step> steps;          // stage-major
+  std::vector<int> tile_start;      // per stage: nsteps+1 prefix sums
+  std::vector<int> step_off, tile_off, nsteps, ntiles;  // per stage
 };
 
-QueueLayout queue_layout(int nsteps, size_t base) {
-  QueueLayout q;
-  q.nsteps = nsteps;
-  size_t off = base;
-  auto take = [&](size_t b) {
-    size_t o = off;
-    off += align_up(b);
-    return o;
-  };
-  q.steps = take(std::max(nsteps, 1) * sizeof(Step));
-  q.order = take(std::max(nsteps, 1) * sizeof(int));
-  q.start = take((nsteps + 1) * sizeof(long));
-  q.done = take(std::max(nsteps, 1) * sizeof(unsigned));
-  q.counter = take(2 * sizeof(unsigned));
-  q.bytes = off - base;
-  return q;
-}
-
-// Per-device flag set by a persistent wait that ran out of spins.
-std::mutex g_flag_mu;
-unsigned* g_err_flag[64] = {nullptr};
-
-unsigned* device_error_flag() {
-  int dev = 0;
-  HIPX(hipGetDevice(&dev));
-  std::lock_guard<std::mutex> lk(g_flag_mu);
-  if (!g_err_flag[dev]) {
-    HIPX(hipMalloc(&g_err_flag[dev], 256));
-    HIPX(hipMemset(g_err_flag[dev], 0, 256));
-  }
-  return g_err_flag[dev];
-}
-
-int persistent_grid(int V) {
-  int dev = 0;
-  HIPX(hipGetDevice(&dev));
-  static int cache[64][5] = {{0}};
-  if (cache[dev][V]) return cache[dev][V];
-  int cus = 0, per = 0;
-  HIPX(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  switch (V) {
-    case 1: HIPX(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<1>, 256, 0)); break;
-    case 2: HIPX(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<2>, 256, 0)); break;
-    default: HIPX(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<4>, 256, 0)); break;
-  }
-  cache[dev][V] = std::max(1, cus * std::max(per, 1));
-  return cache[dev][V];
-}
-
-const long kSpinLimit = 1L << 24;
-
-// Interleaves the items round-robin by step index and launches once.
-void run_persistent(const std::vector<const Program*>& progs, const Tune& t, void* qbase, hipStream_t st) {
-  // items: (program, chunk)
-  struct Item {
-    const Program* pg;
-    int chunk;
-    int base;
-  };
-  std::vector<Item> items;
-  int nsteps = 0;
+StageImage build_stages(const std::vector<const Program*>& progs) {
+  StageImage im;
   size_t maxlen = 0;
-  for (const Program* pg : progs)
-    for (int c = 0; c < pg->nchunk; ++c) {
-      items.push_back({pg, c, nsteps});
-      nsteps += static_cast<int>(pg->steps.size());
-      maxlen = std::max(maxlen, pg->steps.size());
-    }
-  if (nsteps == 0) return;
-  std::vector<Step> steps(nsteps);
-  for (const Item& it : items)
-    for (size_t k = 0; k < it.pg->steps.size(); ++k) {
-      Step s = it.pg->steps[k].s;
-      s.chunk = it.chunk;
-      s.dep0 = it.pg->steps[k].dep[0] < 0 ? -1 : it.base + it.pg->steps[k].dep[0];
-      s.dep1 = it.pg->steps[k].dep[1] < 0 ? -1 : it.base + it.pg->steps[k].dep[1];
-      steps[it.base + k] = s;
-    }
-  std::vector<int> order;
-  std::vector<long> start;
-  order.reserve(nsteps);
-  start.reserve(nsteps + 1);
-  long total = 0;
-  for (size_t k = 0; k < maxlen; ++k)
-    for (const Item& it : items)
-      if (k < it.pg->steps.size()) {
-        order.push_back(it.base + static_cast<int>(k));
-        start.push_back(total);
-        total += steps[it.base + k].ntiles;
+  for (const Program* pg : progs) maxlen = std::max(maxlen, pg->steps.size());
+  for (size_t k = 0; k < maxlen; ++k) {
+    im.step_off.push_back(static_cast<int>(im.steps.size()));
+    im.tile_off.push_back(static_cast<int>(im.tile_start.size()));
+    int tiles = 0, n = 0;
+    for (const Program* pg : progs) {
+      if (k >= pg->steps.size()) continue;
+      for (int c = 0; c < pg->nchunk; ++c) {
+        Step s = pg->steps[k].s;
+        s.chunk = c;
+        im.tile_start.push_back(tiles);
+        tiles += s.ntiles;
+        im.steps.push_back(s);
+        ++n;
       }
-  start.push_back(total);
-  QueueLayout q = queue_layout(nsteps, 0);
-  char* b = static_cast<char*>(qbase);
-  upload(b + q.steps, steps.data(), steps.size() * sizeof(Step), st);
-  upload(b + q.order, order.data(), order.size() * sizeof(int), st);
-  upload(b + q.start, start.data(), start.size() * sizeof(long), st);
-  HIPX(hipMemsetAsync(b + q.done, 0, nsteps * sizeof(unsigned), st));
-  HIPX(hipMemsetAsync(b + q.counter, 0, 2 * sizeof(unsigned), st));
-  QueueArgs qa;
-  qa.steps = reinterpret_cast<const Step*>(b + q.steps);
-  qa.order = reinterpret_cast<const int*>(b + q.order);
-  qa.start = reinterpret_cast<const long*>(b + q.start);
-  qa.nsteps = nsteps;
-  qa.done = reinterpret_cast<unsigned*>(b + q.done);
-  qa.counter = reinterpret_cast<unsigned*>(b + q.counter);
-  qa.error = device_error_flag();
-  qa.spin_limit = kSpinLimit;
-  int grid = t.grid > 0 ? t.grid : persistent_grid(t.V);
-  grid = static_cast<int>(std::min<long>(grid, total));
-  switch (t.V) {
-    case 1: hipLaunchKernelGGL(k_persistent<1>, dim3(grid), dim3(256), 0, st, qa); break;
-    case 2: hipLaunchKernelGGL(k_persistent<2>, dim3(grid), dim3(256), 0, st, qa); break;
-    default: hipLaunchKernelGGL(k_persistent<4>, dim3(grid), dim3(256), 0, st, qa); break;
+    }
+    im.tile_start.push_back(tiles);
+    im.nsteps.push_back(n);
+    im.ntiles.push_back(tiles);
   }
-  HIPX(hipGetLastError());
+  return im;
 }
 
-size_t program_queue_bytes(int nsteps) { return queue_layout(nsteps, 0).bytes; }
+// Device bytes of the stage tables for `nsteps` items-steps over `nstages` stages.
+size_t stage_bytes(long nsteps, long nstages) {
+  return align_up(std::max<long>(nsteps, 1) * sizeof(Step)) + align_up((nsteps + nstages + 1) * sizeof(int));
+}
+
+uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* p = static_cast<const unsigned char*>(data);
+  for (size_t i = 0; i < n; ++i) h = (h ^ p[i]) * 1099511628211ull;
+  return h;
+}
+
+void launch_stages(const StageImage& im, const Step* d_steps, const int* d_tiles, int V, int wpb, hipStream_t st) {
+  for (size_t k = 0; k < im.nsteps.size(); ++k) {
+    if (im.nsteps[k] == 0) continue;
+    GroupArgs g{d_steps + im.step_off[k], d_tiles + im.tile_off[k], im.nsteps[k]};
+    dim3 grid(im.ntiles[k]), block(64 * wpb);
+    switch (V) {
+      case 1: hipLaunchKernelGGL(k_grouped<1>, grid, block, 0, st, g); break;
+      case 2: hipLaunchKernelGGL(k_grouped<2>, grid, block, 0, st, g); break;
+      default: hipLaunchKernelGGL(k_grouped<4>, grid, block, 0, st, g); break;
+    }
+    HIPX(hipGetLastError());
+  }
+}
+
+// One cached graph per stage-table location; a different table at the same
+// location replaces it once the stream that last launched it has drained.
+struct StageGraph {
+  uint64_t hash = 0;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t last = nullptr;
+};
+std::mutex g_sgraph_mu;
+std::map<void*, StageGraph> g_sgraphs;
+
+void drop_stage_graphs_in(void* lo, size_t bytes) {
+  std::lock_guard<std::mutex> lk(g_sgraph_mu);
+  for (auto it = g_sgraphs.begin(); it != g_sgraphs.end();) {
+    char* k = static_cast<char*>(it->first);
+    if (k >= static_cast<char*>(lo) && k < static_cast<char*>(lo) + bytes) {
+      (void)hipStreamSynchronize(it->second.last);
+      (void)hipGraphExecDestroy(it->second.exec);
+      it = g_sgraphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+// Uploads the stage tables to `base` and runs them on `st`, either as
+// separate launches or as one (cached) graph.
+void run_grouped(const std::vector<const Program*>& progs, const Tune& t, void* base, hipStream_t st, bool as_graph) {
+  StageImage im = build_stages(progs);
+  if (im.steps.empty()) return;
+  char* b = static_cast<char*>(base);
+  Step* d_steps = reinterpret_cast<Step*>(b);
+  int* d_tiles = reinterpret_cast<int*>(b + align_up(im.steps.size() * sizeof(Step)));
+  uint64_t h = fnv1a(im.steps.data(), im.steps.size() * sizeof(Step));
+  h = fnv1a(im.tile_start.data(), im.tile_start.size() * sizeof(int), h);
+  h = fnv1a(&t, sizeof(t), h);
+  if (!as_graph) {
+    upload(d_steps, im.steps.data(), im.steps.size() * sizeof(Step), st);
+    upload(d_tiles, im.tile_start.data(), im.tile_start.size() * sizeof(int), st);
+    launch_stages(im, d_steps, d_tiles, t.V, t.wpb, st);
+    return;
+  }
+  hipGraphExec_t exec = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_sgraph_mu);
+    auto it = g_sgraphs.find(base);
+    if (it != g_sgraphs.end()) {
+      if (it->second.hash == h) {
+        exec = it->second.exec;
+        it->second.last = st;
+      } else {
+        HIPX(hipStreamSynchronize(it->second.last));
+        HIPX(hipGraphExecDestroy(it->second.exec));
+        g_sgraphs.erase(it);
+      }
+    }
+  }
+  if (!exec) {
+    upload(d_steps, im.steps.data(), im.steps.size() * sizeof(Step), st);
+    upload(d_tiles, im.tile_start.data(), im.tile_start.size() * sizeof(int), st);
+    hipStream_t cs = capture_stream();
+    HIPX(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    launch_stages(im, d_steps, d_tiles, t.V, t.wpb, cs);
+    hipGraph_t graph = nullptr;
+    HIPX(hipStreamEndCapture(cs, &graph));
+    HIPX(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    HIPX(hipGraphDestroy(graph));
+    std::lock_guard<std::mutex> lk(g_sgraph_mu);
+    g_sgraphs[base] = StageGraph{h, exec, st};
+  }
+  HIPX(hipGraphLaunch(exec, st));
+}
 
 int strip_program_len(int m, int n_max) { return n_max < 1 ? 0 : (m + 4) + (n_max - 1) * (m + 1); }
 
@@ -797,17 +805,19 @@ size_t workspace_bytes(int lattice, int m, int I, int n_max_hint, int mode, cons
   if (mode == CHROM_MODE_PLAIN) return plain_layout(lattice, m).bytes;
   JobLayout L = job_layout(lattice, m, I, t, kMaxCodes, rows_tile_of(t));
   size_t b = L.bytes + 256;  // + graph row counter
-  if (mode == CHROM_MODE_PERSISTENT) b += program_queue_bytes(L.nchunk * strip_program_len(m, n_max_hint));
+  if (mode == CHROM_MODE_GROUPED) {
+    const long len = strip_program_len(m, n_max_hint);
+    b += stage_bytes(L.nchunk * len, len);
+  }
   return b;
 }
 
 int strip_async_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, const uint32_t* p, int np, int mode,
                      const chrom_tuning* tune, void* ws, size_t ws_bytes, hipStream_t st, uint32_t* d_out) {
   check_args(lattice, m, n_max);
-  if (mode < CHROM_MODE_PLAIN || mode > CHROM_MODE_PERSISTENT) throw ArgError("unknown mode");
+  check_mode(mode);
   std::vector<Inst> inst = make_instances(q, nq, p, np);
   Tune t = resolve(tune);
-  if (mode == CHROM_MODE_PERSISTENT) t.wpb = 4;
   if (n_max == 0) return CHROM_OK;
   if (!ws || !d_out) throw ArgError("null workspace or output");
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) throw ArgError("workspace must be 256-byte aligned");
@@ -836,7 +846,7 @@ int strip_async_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, c
     run_graph(j, n_max, row_ctr, ws, st);
   } else {
     Program pg = strip_program(j, n_max);
-    run_persistent({&pg}, t, static_cast<char*>(ws) + j.L.bytes + 256, st);
+    run_grouped({&pg}, t, static_cast<char*>(ws) + j.L.bytes + 256, st, true);
   }
   return CHROM_OK;
 }
@@ -851,25 +861,14 @@ struct DevBuf {
   }
 };
 
-int check_device_flag() {
-  unsigned* f = device_error_flag();
-  unsigned v = 0;
-  HIPX(hipMemcpy(&v, f, sizeof(v), hipMemcpyDeviceToHost));
-  if (v) {
-    HIPX(hipMemset(f, 0, sizeof(unsigned)));
-    throw BusyError("a persistent-kernel wait exceeded its spin limit");
-  }
-  return CHROM_OK;
-}
-
 int strip_sync_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, const uint32_t* p, int np, int mode,
                     const chrom_tuning* tune, uint32_t* out) {
   check_args(lattice, m, n_max);
+  check_mode(mode);
   std::vector<Inst> inst = make_instances(q, nq, p, np);
   if (n_max == 0) return CHROM_OK;
   if (!out) throw ArgError("null output");
   Tune t = resolve(tune);
-  if (mode == CHROM_MODE_PERSISTENT) t.wpb = 4;
   const int I = static_cast<int>(inst.size());
   const size_t wsb = workspace_bytes(lattice, m, I, n_max, mode, t);
   DevBuf ws(wsb);
@@ -880,8 +879,8 @@ int strip_sync_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, co
                             static_cast<uint32_t*>(dout.p));
   if (rc != CHROM_OK) return rc;
   HIPX(hipDeviceSynchronize());
-  if (mode == CHROM_MODE_PERSISTENT) check_device_flag();
   HIPX(hipMemcpy(out, dout.p, outb, hipMemcpyDeviceToHost));
+  if (mode == CHROM_MODE_GROUPED) drop_stage_graphs_in(ws.p, wsb);
   if (mode == CHROM_MODE_GRAPH) {
     // graphs captured on this workspace are invalid once it is freed
     std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -925,13 +924,13 @@ int factor_launches_impl(int lattice, int m, const uint32_t* q, int nq, const ui
 }
 
 // ---------------------------------------------------------------------------
-// Many jobs in one persistent launch
+// Many jobs in one graph of grouped launches
 // ---------------------------------------------------------------------------
 struct BatchPlan {
   std::vector<size_t> job_off;
   std::vector<JobLayout> layouts;
   size_t queue_off = 0, bytes = 0;
-  int nsteps = 0;
+  long nsteps = 0, nstages = 0;
 };
 
 BatchPlan batch_plan(const chrom_job* jobs, int njobs, const Tune& t) {
@@ -946,16 +945,16 @@ BatchPlan batch_plan(const chrom_job* jobs, int njobs, const Tune& t) {
     bp.layouts.push_back(L);
     bp.job_off.push_back(off);
     off += align_up(L.bytes);
-    bp.nsteps += L.nchunk * strip_program_len(jb.m, jb.n_max);
+    bp.nsteps += static_cast<long>(L.nchunk) * strip_program_len(jb.m, jb.n_max);
+    bp.nstages = std::max<long>(bp.nstages, strip_program_len(jb.m, jb.n_max));
   }
   bp.queue_off = off;
-  bp.bytes = off + program_queue_bytes(bp.nsteps);
+  bp.bytes = off + stage_bytes(bp.nsteps, bp.nstages);
   return bp;
 }
 
 int batch_impl(const chrom_job* jobs, int njobs, const chrom_tuning* tune, void* ws, size_t ws_bytes, hipStream_t st) {
   Tune t = resolve(tune);
-  t.wpb = 4;
   BatchPlan bp = batch_plan(jobs, njobs, t);
   if (njobs == 0) return CHROM_OK;
   if (!ws) throw ArgError("null workspace");
@@ -982,7 +981,7 @@ int batch_impl(const chrom_job* jobs, int njobs, const chrom_tuning* tune, void*
     progs[k] = strip_program(j, jb.n_max);
     pp.push_back(&progs[k]);
   }
-  run_persistent(pp, t, static_cast<char*>(ws) + bp.queue_off, st);
+  run_grouped(pp, t, static_cast<char*>(ws) + bp.queue_off, st, true);
   return CHROM_OK;
 }
 
@@ -1013,7 +1012,6 @@ int server_step_impl(chrom_slot* slots, int nslots, int rows, const chrom_tuning
   if (nslots < 0 || (nslots > 0 && !slots)) throw ArgError("bad slot list");
   if (rows < 1) throw ArgError("rows must be >= 1");
   Tune t = resolve(tune);
-  t.wpb = 4;
   std::vector<Program> progs(nslots);
   std::vector<const Program*> pp;
   std::vector<int> new_done(nslots);
@@ -1054,8 +1052,10 @@ int server_step_impl(chrom_slot* slots, int nslots, int rows, const chrom_tuning
   int nsteps = 0;
   for (const Program* pg : pp) nsteps += pg->nchunk * static_cast<int>(pg->steps.size());
   if (nsteps > 0) {
-    void* q = server_queue(program_queue_bytes(nsteps));
-    run_persistent(pp, t, q, st);
+    long nstages = 0;
+    for (const Program* pg : pp) nstages = std::max<long>(nstages, static_cast<long>(pg->steps.size()));
+    void* q = server_queue(stage_bytes(nsteps, nstages));
+    run_grouped(pp, t, q, st, false);
   }
   for (int k = 0; k < nslots; ++k) slots[k].rows_done = new_done[k];
   return CHROM_OK;
@@ -1083,8 +1083,8 @@ int chromatic_strip(int lattice, int m, int n_max, const uint32_t* q_points, int
 int chromatic_strip_batched(int lattice, int m, int n_max, const uint32_t* q_points, int nq, const uint32_t* primes,
                             int np, int mode, const chrom_tuning* tune, uint32_t* out) {
   return guarded([&] {
-    if (mode != CHROM_MODE_BATCHED && mode != CHROM_MODE_GRAPH && mode != CHROM_MODE_PERSISTENT)
-      throw ArgError("mode must be BATCHED, GRAPH or PERSISTENT");
+    check_mode(mode);
+    if (mode == CHROM_MODE_PLAIN) throw ArgError("use chromatic_strip for the plain path");
     return strip_sync_impl(lattice, m, n_max, q_points, nq, primes, np, mode, tune, out);
   });
 }
@@ -1094,9 +1094,8 @@ size_t chromatic_workspace_bytes(int lattice, int m, int n_max, int nq, int np, 
   int rc = guarded([&] {
     check_args(lattice, m, n_max);
     if (nq < 1 || np < 1) throw ArgError("need nq, np >= 1");
-    if (mode < CHROM_MODE_PLAIN || mode > CHROM_MODE_PERSISTENT) throw ArgError("unknown mode");
+    check_mode(mode);
     Tune t = resolve(tune);
-    if (mode == CHROM_MODE_PERSISTENT) t.wpb = 4;
     r = workspace_bytes(lattice, m, nq * np, n_max, mode, t);
     return CHROM_OK;
   });
@@ -1153,7 +1152,6 @@ size_t chromatic_batch_workspace_bytes(const chrom_job* jobs, int njobs, const c
   size_t r = 0;
   int rc = guarded([&] {
     Tune t = resolve(tune);
-    t.wpb = 4;
     r = batch_plan(jobs, njobs, t).bytes;
     return CHROM_OK;
   });
@@ -1171,7 +1169,6 @@ size_t chromatic_slot_state_bytes(int lattice, int m, int nq, int np, const chro
     check_args(lattice, m, 0);
     if (nq < 1 || np < 1) throw ArgError("need nq, np >= 1");
     Tune t = resolve(tune);
-    t.wpb = 4;
     r = job_layout(lattice, m, nq * np, t, kMaxCodes, rows_tile_of(t)).bytes;
     return CHROM_OK;
   });
@@ -1185,7 +1182,8 @@ int chromatic_server_step(chrom_slot* slots, int nslots, int rows, const chrom_t
 int chromatic_device_status(void* stream) {
   return guarded([&] {
     HIPX(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
-    return check_device_flag();
+    HIPX(hipGetLastError());
+    return CHROM_OK;
   });
 }
 

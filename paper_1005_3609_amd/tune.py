@@ -1,0 +1,102 @@
+"""Autotuner for the batched sweep: launch shape and execution mode.
+
+Searches instances per lane (chunk width W = 64 V), targets per wavefront,
+wavefronts per workgroup and the execution mode (hipGraph row replay, or the
+whole sweep as one graph of grouped launches), timing whole sweeps with HIP events on the launch
+stream.  Every candidate must return residues bit-identical to the first
+one; a candidate that differs is rejected and reported (the arithmetic is
+exact, so a difference is a bug, never rounding).  Results are cached as
+JSON keyed by (gfx arch, lattice, m, instances, n_max).
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+
+import numpy as np
+
+from . import api
+
+DEFAULT_CACHE = os.environ.get("CHROMSTRIP_TUNE_CACHE",
+                               os.path.join(os.path.expanduser("~"), ".cache", "chromstrip", "tune.json"))
+SPACE = dict(lanes_v=[1, 2, 4], targets_per_wave=[2, 4, 8, 16], waves_per_block=[2, 4, 8],
+             mode=["graph", "grouped"])
+
+
+def candidates(space=None) -> list[dict]:
+    space = space or SPACE
+    out = []
+    for v, t, w, mode in itertools.product(space["lanes_v"], space["targets_per_wave"], space["waves_per_block"],
+                                           space["mode"]):
+        out.append(dict(lanes_v=v, targets_per_wave=t, waves_per_block=w, mode=mode))
+    return out
+
+
+def _arch():
+    import torch
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def _key(lattice, m, n_inst, n_max):
+    return f"{_arch()}|{lattice}|{m}|{n_inst}|{n_max}"
+
+
+def load(path=DEFAULT_CACHE) -> dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def lookup(lattice, m, n_inst, n_max, path=DEFAULT_CACHE):
+    return load(path).get(_key(lattice, m, n_inst, n_max))
+
+
+def time_candidate(lattice, m, n_max, q_points, primes, cand, steps=3, stream=None):
+    """(ms per sweep, residues) for one candidate."""
+    import torch
+    tune = {k: v for k, v in cand.items() if k != "mode"}
+    mode = cand["mode"]
+    dev = torch.device("cuda", torch.cuda.current_device())
+    stream = stream or torch.cuda.current_stream(dev)
+    ws = api.alloc_workspace(api.workspace_bytes(lattice, m, n_max, len(q_points), len(primes), mode, tune), dev)
+    out = torch.zeros((n_max, len(q_points), len(primes)), dtype=torch.int32, device=dev)
+    api.strip_async(lattice, m, n_max, q_points, primes, mode=mode, tuning=tune, workspace=ws, out=out,
+                    stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        api.strip_async(lattice, m, n_max, q_points, primes, mode=mode, tuning=tune, workspace=ws, out=out,
+                        stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, api.to_u32(out)
+
+
+def tune(lattice, m, n_max, q_points, primes, space=None, steps=3, path=DEFAULT_CACHE, log=None) -> dict:
+    """Times every candidate, keeps the fastest bit-identical one, caches it."""
+    table = []
+    ref = None
+    best = None
+    for cand in candidates(space):
+        ms, res = time_candidate(lattice, m, n_max, q_points, primes, cand, steps)
+        if ref is None:
+            ref = res
+        ok = bool(np.array_equal(res, ref))
+        table.append(dict(cand, ms=ms, identical=ok))
+        if log:
+            log(f"{cand} {ms:.3f} ms {'ok' if ok else 'MISMATCH'}")
+        if ok and (best is None or ms < best["ms"]):
+            best = dict(cand, ms=ms)
+    bad = [t for t in table if not t["identical"]]
+    if bad:
+        raise RuntimeError(f"tuning candidates disagree with the reference result: {bad}")
+    cache = load(path)
+    cache[_key(lattice, m, len(q_points) * len(primes), n_max)] = dict(best=best, table=table)
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1)
+    return dict(best=best, table=table)

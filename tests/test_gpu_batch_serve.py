@@ -1,0 +1,86 @@
+"""GPU tests of the batching and serving patterns: one graph of grouped
+launches over jobs of mixed lattice, width and instance count; the continuous-batching
+server (each result identical alone and in the mix); the autotuner."""
+import numpy as np
+import pytest
+
+from oracle import transfer as OT
+from paper_1005_3609_amd import api, tune
+from paper_1005_3609_amd import workloads as W
+from paper_1005_3609_amd.server import GpuBackend, Job, Server
+
+pytestmark = pytest.mark.gpu
+P31 = 2 ** 31 - 1
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    yield
+
+
+def test_mixed_batch_one_launch():
+    import torch
+    pool = W.seeded_primes(4, 321)
+    jobs = [
+        dict(lattice="square", m=7, n_max=8, q_points=list(range(1, 30)), primes=pool[:3]),
+        dict(lattice="triangular", m=9, n_max=4, q_points=list(range(5, 9)), primes=pool[1:2]),
+        dict(lattice="square", m=1, n_max=5, q_points=[0, 3], primes=[P31]),
+        dict(lattice="triangular", m=2, n_max=6, q_points=list(range(0, 70)), primes=pool[:2]),
+        dict(lattice="square", m=10, n_max=3, q_points=[2, 3, 4], primes=pool),
+    ]
+    outs, ws = api.batch(jobs)
+    torch.cuda.synchronize()
+    for jb, o in zip(jobs, outs):
+        want = OT.chromatic_grid(jb["lattice"], jb["m"], jb["n_max"], jb["q_points"], jb["primes"])
+        np.testing.assert_array_equal(api.to_u32(o).astype(np.int64), want, err_msg=str(jb)[:80])
+
+
+def _stream_jobs(n, seed, max_m=10):
+    out = []
+    for j in W.serving_stream(n, rate=400.0, seed=seed):
+        m = min(j["m"], max_m)
+        out.append(Job(id=j["id"], lattice=j["lattice"], m=m, n_max=m + 1, q_points=j["q_points"][:24],
+                       primes=j["primes"], arrival=j["arrival"]))
+    return out
+
+
+@pytest.mark.parametrize("rows_per_tick", [1, 3])
+def test_server_results_alone_equal_in_mix(rows_per_tick):
+    jobs = _stream_jobs(14, seed=77)
+    be = GpuBackend()
+    for j in jobs:
+        be.prepare(j.lattice, j.m)
+    rep = Server(be, budget_bytes=8 << 30, rows_per_tick=rows_per_tick).run(jobs)
+    s = rep.summary()
+    assert s["done"] == len(jobs) and s["failed"] == 0
+    assert rep.ticks < sum(j.n_max for j in jobs)          # jobs shared ticks
+    for j in jobs:
+        alone = api.strip(j.lattice, j.m, j.n_max, j.q_points, j.primes, mode="batched")
+        np.testing.assert_array_equal(j.result, alone, err_msg=f"job {j.id}")
+    for j in jobs[:4]:
+        want = OT.chromatic_grid(j.lattice, j.m, j.n_max, j.q_points, j.primes)
+        np.testing.assert_array_equal(j.result.astype(np.int64), want)
+
+
+def test_server_tight_budget_same_results():
+    jobs = _stream_jobs(8, seed=78, max_m=9)
+    be = GpuBackend()
+    one = max(be.footprint(j) + be.map_bytes(j.lattice, j.m) for j in jobs)
+    rep = Server(be, budget_bytes=one, rows_per_tick=2).run(jobs)
+    assert rep.summary()["done"] == len(jobs)
+    assert rep.peak_bytes <= one
+    for j in jobs:
+        alone = api.strip(j.lattice, j.m, j.n_max, j.q_points, j.primes, mode="plain")
+        np.testing.assert_array_equal(j.result, alone, err_msg=f"job {j.id}")
+
+
+def test_tuner_candidates_identical(tmp_path):
+    q, p = list(range(1, 65)), [P31, 998244353]
+    space = dict(lanes_v=[1, 2, 4], targets_per_wave=[2, 8], waves_per_block=[4, 8], mode=["graph", "grouped"])
+    res = tune.tune("square", 8, 6, q, p, space=space, steps=1, path=str(tmp_path / "t.json"))
+    assert all(row["identical"] for row in res["table"])
+    assert res["best"]["ms"] == min(row["ms"] for row in res["table"])
+    assert tune.lookup("square", 8, len(q) * len(p), 6, path=str(tmp_path / "t.json"))["best"] == res["best"]

@@ -19,7 +19,13 @@ pytestmark = pytest.mark.gpu
 
 P31 = 2 ** 31 - 1
 HERE = os.path.dirname(os.path.abspath(__file__))
-MODES = ["plain", "batched", "graph", "persistent"]
+MODES = ["plain", "batched", "graph", "grouped"]
+# The persistent work-queue path stalled on the GPU twice (the smoke check,
+# square 4x5, 21 instances) and its cause was not found; the path is
+# switched off (the library returns CHROM_EUNSUPPORTED) and its cases stay
+# here, skipped.
+PERSISTENT_OFF = pytest.mark.skip(reason="persistent work-queue path switched off after it stalled on the GPU "
+                                         "(square 4x5 smoke); cause not found")
 
 
 def _golden(name):
@@ -91,7 +97,7 @@ def test_tuning_choices_are_bit_identical(tune):
     q = list(range(1, 66))                      # 65 q x 2 p = 130 instances
     p = [P31, 998244353]
     want = OT.chromatic_grid("square", 7, 5, q, p)
-    for mode in ("batched", "graph", "persistent"):
+    for mode in ("batched", "graph", "grouped"):
         got = api.strip("square", 7, 5, q, p, mode=mode, tuning=tune).astype(np.int64)
         np.testing.assert_array_equal(got, want, err_msg=f"{mode} {tune}")
 
@@ -109,9 +115,9 @@ def test_edge_cases():
 
 def test_repeat_runs_identical():
     q, p = list(range(1, 40)), [P31]
-    a = api.strip("triangular", 9, 7, q, p, mode="persistent")
+    a = api.strip("triangular", 9, 7, q, p, mode="grouped")
     for _ in range(3):
-        assert np.array_equal(api.strip("triangular", 9, 7, q, p, mode="persistent"), a)
+        assert np.array_equal(api.strip("triangular", 9, 7, q, p, mode="grouped"), a)
         assert np.array_equal(api.strip("triangular", 9, 7, q, p, mode="graph"), a)
 
 
@@ -128,12 +134,12 @@ def test_square_m10_plain_and_batched():
 
 
 # ---------------------------------------------------------------------------
-# Workload: triangular m = 12, n = 1..13, 48 q x 6 primes (graph + persistent)
+# Workload: triangular m = 12, n = 1..13, 48 q x 6 primes (graph + grouped)
 # ---------------------------------------------------------------------------
 def test_triangular_m12_against_stored_oracle():
     w = W.workload("triangular_m12")
     g = _golden("oracle_triangular_12x13.json")
-    for mode in ("graph", "persistent"):
+    for mode in ("graph", "grouped"):
         got = api.strip("triangular", 12, 13, w["q_points"], w["primes"], mode=mode)
         np.testing.assert_array_equal(_sampled(got, g), np.array(g["z"], dtype=np.int64), err_msg=mode)
         # invariants at every length: P(1) = 0; P(2) = 0 and P(3) = 6 for r >= 2
@@ -143,7 +149,7 @@ def test_triangular_m12_against_stored_oracle():
 
 
 # ---------------------------------------------------------------------------
-# Workload: square m = 2..14, n <= m+1, 80 q x 8 primes, one persistent launch
+# Workload: square m = 2..14, n <= m+1, 80 q x 8 primes, one graph of grouped launches
 # ---------------------------------------------------------------------------
 def test_square_sweep_one_launch():
     import torch
@@ -152,7 +158,6 @@ def test_square_sweep_one_launch():
             for lat, m, n in w["strips"]]
     outs, ws = api.batch(jobs)
     torch.cuda.synchronize()
-    api.device_status()
     res = {jb["m"]: api.to_u32(o).astype(np.int64) for jb, o in zip(jobs, outs)}
     sample = W.sample_instances(640, 24, 5)
     qs = [w["q_points"][k // 8] for k in sample]
@@ -187,3 +192,21 @@ def test_square_18x19_against_transposed_oracle():
     z = res.reshape(19, 80, 8)
     assert (z[:, 0, :] == 0).all() and (z[:, 1, :] == 2).all()
     del ws
+
+
+# ---------------------------------------------------------------------------
+# Persistent work-queue path: switched off, cases kept
+# ---------------------------------------------------------------------------
+@PERSISTENT_OFF
+def test_persistent_square_4x5():
+    q = list(range(21))
+    got = api.strip("square", 4, 5, q, [P31], mode="persistent").astype(np.int64)
+    np.testing.assert_array_equal(got, OT.chromatic_grid("square", 4, 5, q, [P31]))
+
+
+@PERSISTENT_OFF
+@pytest.mark.parametrize("lat", ["square", "triangular"])
+def test_persistent_small_widths(lat):
+    q, p = list(range(0, 35)), [P31, 1000000007]
+    got = api.strip(lat, 5, 6, q, p, mode="persistent").astype(np.int64)
+    np.testing.assert_array_equal(got, OT.chromatic_grid(lat, 5, 6, q, p))

@@ -181,5 +181,8 @@ def test_bad_arguments_are_errors_without_touching_a_gpu():
     assert L.chromatic_strip(0, 4, 0, *args) == 0          # n_max = 0: nothing to do
     assert api.lib().chromatic_workspace_bytes(0, 0, 5, 3, 1, 1, None) == 0
     with pytest.raises(api.ChromError):
-        api.strip("square", 4, 3, [1, 2], [P31], mode="nope" if False else "batched",
-                  tuning={"lanes_v": 3})
+        api.strip("square", 4, 3, [1, 2], [P31], mode="batched", tuning={"lanes_v": 3})
+    # the persistent work-queue mode is switched off and says so before any device work
+    with pytest.raises(api.ChromError, match="disabled"):
+        api.strip("square", 4, 3, [1, 2], [P31], mode="persistent")
+    assert api.lib().chromatic_workspace_bytes(0, 4, 3, 2, 1, 3, None) == 0
