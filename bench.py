@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--plain-instances", type=int, default=16)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -198,6 +200,15 @@ def main():
                          f"vector over all {s_nc} NCNNN states, first {ninst} of the 640 instances, "
                          f"{dt:.1f} s single-threaded Python"}
         log(f"cpu oracle: {cpu['value']:.3e} state-updates/s")
+
+    if args.copy_mib:
+        nel = args.copy_mib * (1 << 20) // 4
+        src = torch.randint(0, 1 << 30, (nel,), dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {args.copy_mib} MiB three times (counter calibration)")
 
     line = {
         "metric": "state-updates/s, square lattice m=14 (14x15 strip), batched",
