@@ -68,8 +68,9 @@ enum {
  * the library's defaults.  Every choice gives bit-identical results. */
 typedef struct chrom_tuning {
   int lanes_v;          /* instances per lane: 1, 2 or 4 (chunk width W = 64 * lanes_v) */
-  int targets_per_wave; /* consecutive target states handled by one wavefront, 1..64 */
+  int targets_per_wave; /* consecutive target states handled by one wavefront, 1..63 */
   int waves_per_block;  /* wavefronts per workgroup: 1, 2, 4 or 8 */
+  int xcd_order;        /* 0 = default, 1 = hardware round-robin, 2 = contiguous tile range per XCD */
 } chrom_tuning;
 
 /* ------------------------------------------------------------------------

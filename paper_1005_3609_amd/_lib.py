@@ -24,7 +24,8 @@ class ChromError(RuntimeError):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("lanes_v", C.c_int), ("targets_per_wave", C.c_int), ("waves_per_block", C.c_int)]
+    _fields_ = [("lanes_v", C.c_int), ("targets_per_wave", C.c_int), ("waves_per_block", C.c_int),
+                ("xcd_order", C.c_int)]
 
 
 class Job(C.Structure):
@@ -88,6 +89,13 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1005_3609_amd.build` "
                           "(there is no fallback implementation)")
+    # torch ships its own HIP runtime.  Import it first so that the library
+    # binds to that same runtime (one runtime per process; torch's streams and
+    # allocations are then valid handles for the library).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     h = C.CDLL(LIB_PATH)
     for name, (res, args) in _SIGS.items():
         fn = getattr(h, name)
@@ -116,4 +124,5 @@ def tuning(t) -> "Tuning | None":
         return None
     if isinstance(t, Tuning):
         return t
-    return Tuning(int(t.get("lanes_v", 0)), int(t.get("targets_per_wave", 0)), int(t.get("waves_per_block", 0)))
+    return Tuning(int(t.get("lanes_v", 0)), int(t.get("targets_per_wave", 0)), int(t.get("waves_per_block", 0)),
+                  int(t.get("xcd_order", 0)))

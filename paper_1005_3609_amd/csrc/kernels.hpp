@@ -53,6 +53,18 @@ __device__ __forceinline__ void store_v(uint32_t* ptr, const uint32_t (&x)[V]) {
   }
 }
 
+// Workgroups are handed to the 8 XCDs round-robin in dispatch order.  This
+// bijection on [0, nb) gives each XCD one contiguous range of ids instead, so
+// neighbouring target rows -- which share many source rows -- run under the
+// same L2.
+__device__ __forceinline__ int xcd_contiguous(int b, int nb) {
+  constexpr int X = 8;
+  const int per = (nb + X - 1) / X;
+  const int tall = nb - (per - 1) * X;  // XCDs that receive `per` workgroups
+  const int xcd = b % X, local = b / X;
+  return xcd < tall ? xcd * per + local : tall * per + (xcd - tall) * (per - 1) + local;
+}
+
 __device__ __forceinline__ int wave_id() {
   return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
 }
@@ -115,11 +127,17 @@ struct FillArgs {
   int rows_per_wave;
 };
 
+// Two-level read-out reduction.  Level 1: workgroup g of a chunk sums the
+// partials [g*per, (g+1)*per) into part2[chunk][g][W]; level 2 sums the
+// n_groups level-1 results into out[inst].
 struct ReduceArgs {
   const uint32_t* partial;
   long p_cstride;
   int n_parts;
   InstConsts ic;
+  uint32_t* part2;         // [chunk][n_groups][W]
+  long p2_cstride;
+  int n_groups;
   uint32_t* out;           // out[inst] for inst < n_valid (this row)
   int n_valid;
 };
@@ -144,6 +162,35 @@ __device__ __forceinline__ void block_reduce_store(uint32_t (&red)[V], const uin
   __syncthreads();
 }
 
+// Accumulates coef(code) * x into acc (all lanes take the same branch).
+template <int V>
+__device__ __forceinline__ void accumulate(uint32_t (&acc)[V], const uint32_t (&x)[V], uint32_t code,
+                                           const uint32_t (&p)[V], const InstConsts& ic, int inst0) {
+  if (code == 0) {
+#pragma unroll
+    for (int j = 0; j < V; ++j) acc[j] = add_mod(acc[j], x[j], p[j]);
+  } else if (code == 1) {
+#pragma unroll
+    for (int j = 0; j < V; ++j) acc[j] = sub_mod(acc[j], x[j], p[j]);
+  } else {
+    uint32_t cv[V], cs[V];
+    load_v<V>(ic.cval + code * ic.ipad + inst0, cv);
+    load_v<V>(ic.cshp + code * ic.ipad + inst0, cs);
+#pragma unroll
+    for (int j = 0; j < V; ++j) acc[j] = add_mod(acc[j], mul_shoup(x[j], cv[j], cs[j], p[j]), p[j]);
+  }
+}
+
+// One wavefront computes target rows [r0, r1) of one chunk.  Its row
+// pointers (lane j holds row_ptr[r0 + j]) and up to 64 entry words at a time
+// (lane l holds one word) arrive with coalesced vector loads and are
+// broadcast with readlane; the source rows of kUnroll consecutive entries are
+// loaded before any is consumed, so several W*4-byte gathers are in flight
+// per wavefront.  Row boundaries are uniform, so each finished row is stored
+// (and, when fused, folded into the read-out) without divergence; rows with
+// no entries are stored as zero.
+constexpr int kUnroll = 4;
+
 template <int V>
 __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* lds) {
   constexpr int W = 64 * V;
@@ -153,76 +200,63 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
   load_v<V>(a.ic.p + inst0, p);
   const uint32_t* in = a.in + chunk * a.in_cstride + lane * V;
   uint32_t* out = a.out + chunk * a.out_cstride + lane * V;
-  const int32_t* row_ptr = a.csr.row_ptr;
-  const uint32_t* ent = a.csr.ent;
-  const int nw = blockDim.x >> 6;
-  int r0 = (tile * nw + wave) * a.rows_per_wave;
-  int r1 = min(r0 + a.rows_per_wave, a.csr.n_rows);
-  uint32_t red[V];
-#pragma unroll
-  for (int j = 0; j < V; ++j) red[j] = 0;
   const bool fused = a.w != nullptr;
   const uint32_t* wv = fused ? a.w + chunk * a.w_cstride + lane * V : nullptr;
   uint32_t pinv[V];
   if (fused) load_v<V>(a.ic.pinv + inst0, pinv);
-  for (int r = r0; r < r1; ++r) {
-    const int beg = row_ptr[r], end = row_ptr[r + 1];
-    uint32_t acc[V];
+  uint32_t red[V], acc[V];
 #pragma unroll
-    for (int j = 0; j < V; ++j) acc[j] = 0;
-    int e = beg;
-    // Two entries per pass so that two row loads are in flight.
-    for (; e + 1 < end; e += 2) {
-      const uint32_t w0 = ent[e], w1 = ent[e + 1];
-      uint32_t x0[V], x1[V];
-      load_v<V>(in + static_cast<size_t>(w0 & kEntSrcMask) * W, x0);
-      load_v<V>(in + static_cast<size_t>(w1 & kEntSrcMask) * W, x1);
-      const uint32_t c0 = w0 >> 28, c1 = w1 >> 28;
+  for (int j = 0; j < V; ++j) red[j] = acc[j] = 0;
+  const int nw = blockDim.x >> 6;
+  const int r0 = (tile * nw + wave) * a.rows_per_wave;
+  const int r1 = min(r0 + a.rows_per_wave, a.csr.n_rows);
+  if (r0 < r1) {
+    const int nrows = r1 - r0;
+    const int rp = (lane <= nrows) ? a.csr.row_ptr[r0 + lane] : 0;
+    const int beg = __builtin_amdgcn_readlane(rp, 0);
+    const int end = __builtin_amdgcn_readlane(rp, nrows);
+    int row = r0;
+    int row_end = __builtin_amdgcn_readlane(rp, 1);
+    auto flush = [&]() {
+      store_v<V>(out + static_cast<size_t>(row) * W, acc);
+      if (fused) {
+        uint32_t wr[V];
+        load_v<V>(wv + static_cast<size_t>(row) * W, wr);
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const uint32_t c = h ? c1 : c0;
-        uint32_t* x = h ? x1 : x0;
-        if (c == 0) {
+        for (int j = 0; j < V; ++j) red[j] = add_mod(red[j], mul_redc(acc[j], wr[j], p[j], pinv[j]), p[j]);
+      }
 #pragma unroll
-          for (int j = 0; j < V; ++j) acc[j] = add_mod(acc[j], x[j], p[j]);
-        } else if (c == 1) {
+      for (int j = 0; j < V; ++j) acc[j] = 0;
+      ++row;
+      if (row < r1) row_end = __builtin_amdgcn_readlane(rp, row - r0 + 1);
+    };
+    for (int base = beg; base < end; base += 64) {
+      const int n = min(64, end - base);
+      const uint32_t ev = (lane < n) ? a.csr.ent[base + lane] : 0u;
+      int k = 0;
+      for (; k + kUnroll <= n; k += kUnroll) {
+        uint32_t word[kUnroll];
+        uint32_t x[kUnroll][V];
 #pragma unroll
-          for (int j = 0; j < V; ++j) acc[j] = sub_mod(acc[j], x[j], p[j]);
-        } else {
-          uint32_t cv[V], cs[V];
-          load_v<V>(a.ic.cval + c * a.ic.ipad + inst0, cv);
-          load_v<V>(a.ic.cshp + c * a.ic.ipad + inst0, cs);
+        for (int u = 0; u < kUnroll; ++u) {
+          word[u] = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ev), k + u));
+          load_v<V>(in + static_cast<size_t>(word[u] & kEntSrcMask) * W, x[u]);
+        }
 #pragma unroll
-          for (int j = 0; j < V; ++j) acc[j] = add_mod(acc[j], mul_shoup(x[j], cv[j], cs[j], p[j]), p[j]);
+        for (int u = 0; u < kUnroll; ++u) {
+          while (base + k + u >= row_end) flush();
+          accumulate<V>(acc, x[u], word[u] >> 28, p, a.ic, inst0);
         }
       }
-    }
-    if (e < end) {
-      const uint32_t w0 = ent[e];
-      uint32_t x0[V];
-      load_v<V>(in + static_cast<size_t>(w0 & kEntSrcMask) * W, x0);
-      const uint32_t c = w0 >> 28;
-      if (c == 0) {
-#pragma unroll
-        for (int j = 0; j < V; ++j) acc[j] = add_mod(acc[j], x0[j], p[j]);
-      } else if (c == 1) {
-#pragma unroll
-        for (int j = 0; j < V; ++j) acc[j] = sub_mod(acc[j], x0[j], p[j]);
-      } else {
-        uint32_t cv[V], cs[V];
-        load_v<V>(a.ic.cval + c * a.ic.ipad + inst0, cv);
-        load_v<V>(a.ic.cshp + c * a.ic.ipad + inst0, cs);
-#pragma unroll
-        for (int j = 0; j < V; ++j) acc[j] = add_mod(acc[j], mul_shoup(x0[j], cv[j], cs[j], p[j]), p[j]);
+      for (; k < n; ++k) {
+        const uint32_t word = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ev), k));
+        uint32_t x[V];
+        load_v<V>(in + static_cast<size_t>(word & kEntSrcMask) * W, x);
+        while (base + k >= row_end) flush();
+        accumulate<V>(acc, x, word >> 28, p, a.ic, inst0);
       }
     }
-    store_v<V>(out + static_cast<size_t>(r) * W, acc);
-    if (fused) {
-      uint32_t wr[V];
-      load_v<V>(wv + static_cast<size_t>(r) * W, wr);
-#pragma unroll
-      for (int j = 0; j < V; ++j) red[j] = add_mod(red[j], mul_redc(acc[j], wr[j], p[j], pinv[j]), p[j]);
-    }
+    while (row < r1) flush();
   }
   if (fused) block_reduce_store<V>(red, p, a.partial + chunk * a.p_cstride + static_cast<long>(tile) * W, lds);
 }
@@ -276,33 +310,78 @@ __device__ void fill_tile(const FillArgs& a, int chunk, int tile) {
   }
 }
 
-// One workgroup per chunk; thread j < W sums instance j over the parts.
 template <int V>
-__device__ void reduce_tile(const ReduceArgs& a, int chunk) {
+__device__ void reduce1_tile(const ReduceArgs& a, int chunk, int g, uint32_t* lds) {
+  constexpr int W = 64 * V;
+  const int nt = blockDim.x, tid = threadIdx.x;
+  const int per = (a.n_parts + a.n_groups - 1) / a.n_groups;
+  const int k0 = g * per, k1 = min(k0 + per, a.n_parts);
+  const int span = nt >= W ? W : nt;      // threads sharing one pass over the instances
+  const int G = nt >= W ? nt / W : 1;     // groups splitting the parts
+  const int grp = tid / span;
+  const uint32_t* src = a.partial + chunk * a.p_cstride;
+  for (int j = tid % span; j < W; j += span) {
+    const uint32_t p = a.ic.p[chunk * W + j];
+    uint32_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    int k = k0 + grp;
+    for (; k + 3 * G < k1; k += 4 * G) {
+      s0 = add_mod(s0, src[static_cast<long>(k) * W + j], p);
+      s1 = add_mod(s1, src[static_cast<long>(k + G) * W + j], p);
+      s2 = add_mod(s2, src[static_cast<long>(k + 2 * G) * W + j], p);
+      s3 = add_mod(s3, src[static_cast<long>(k + 3 * G) * W + j], p);
+    }
+    for (; k < k1; k += G) s0 = add_mod(s0, src[static_cast<long>(k) * W + j], p);
+    lds[grp * W + j] = add_mod(add_mod(s0, s1, p), add_mod(s2, s3, p), p);
+  }
+  __syncthreads();
+  for (int j = tid; j < W; j += nt) {
+    const uint32_t p = a.ic.p[chunk * W + j];
+    uint32_t s = 0;
+    for (int q = 0; q < G; ++q) s = add_mod(s, lds[q * W + j], p);
+    a.part2[chunk * a.p2_cstride + static_cast<long>(g) * W + j] = s;
+  }
+  __syncthreads();
+}
+
+template <int V>
+__device__ void reduce2_tile(const ReduceArgs& a, int chunk, uint32_t* out) {
   constexpr int W = 64 * V;
   for (int j = threadIdx.x; j < W; j += blockDim.x) {
     const int inst = chunk * W + j;
     const uint32_t p = a.ic.p[inst];
-    const uint32_t* src = a.partial + chunk * a.p_cstride + j;
+    const uint32_t* src = a.part2 + chunk * a.p2_cstride + j;
     uint32_t s = 0;
-    for (int k = 0; k < a.n_parts; ++k) s = add_mod(s, src[static_cast<long>(k) * W], p);
-    if (inst < a.n_valid) a.out[inst] = s;
+    for (int k = 0; k < a.n_groups; ++k) s = add_mod(s, src[static_cast<long>(k) * W], p);
+    if (inst < a.n_valid) out[inst] = s;
   }
 }
 
 // ---------------------------------------------------------------------------
 // Eager kernels: grid.x = tiles, grid.y = chunks
 // ---------------------------------------------------------------------------
-template <int V>
-__global__ void __launch_bounds__(512) k_gather(GatherArgs a) {
-  __shared__ uint32_t lds[8 * 64 * V];
-  gather_tile<V>(a, blockIdx.y, blockIdx.x, lds);
+// Block (x, y) = (tile, chunk); with xcd != 0 the linear block id is first
+// remapped so each XCD sweeps a contiguous range.
+__device__ __forceinline__ void tile_chunk(int xcd, int& tile, int& chunk) {
+  int b = blockIdx.y * gridDim.x + blockIdx.x;
+  if (xcd) b = xcd_contiguous(b, gridDim.x * gridDim.y);
+  tile = b % gridDim.x;
+  chunk = b / gridDim.x;
 }
 
 template <int V>
-__global__ void __launch_bounds__(512) k_dot(DotArgs a) {
+__global__ void __launch_bounds__(512) k_gather(GatherArgs a, int xcd) {
   __shared__ uint32_t lds[8 * 64 * V];
-  dot_tile<V>(a, blockIdx.y, blockIdx.x, lds);
+  int tile, chunk;
+  tile_chunk(xcd, tile, chunk);
+  gather_tile<V>(a, chunk, tile, lds);
+}
+
+template <int V>
+__global__ void __launch_bounds__(512) k_dot(DotArgs a, int xcd) {
+  __shared__ uint32_t lds[8 * 64 * V];
+  int tile, chunk;
+  tile_chunk(xcd, tile, chunk);
+  dot_tile<V>(a, chunk, tile, lds);
 }
 
 template <int V>
@@ -310,19 +389,24 @@ __global__ void __launch_bounds__(512) k_fill(FillArgs a) {
   fill_tile<V>(a, blockIdx.y, blockIdx.x);
 }
 
+// grid (n_groups, chunks)
 template <int V>
-__global__ void __launch_bounds__(512) k_reduce(ReduceArgs a) {
-  reduce_tile<V>(a, blockIdx.x);
+__global__ void __launch_bounds__(512) k_reduce1(ReduceArgs a) {
+  __shared__ uint32_t lds[8 * 64 * V];
+  reduce1_tile<V>(a, blockIdx.y, blockIdx.x, lds);
 }
 
-// Reduce whose output row is taken from a device counter (hipGraph replays
-// write successive rows); thread 0 of block 0 does not bump the counter --
-// k_bump does, after every block has read it.
+// grid (chunks)
 template <int V>
-__global__ void __launch_bounds__(512) k_reduce_counted(ReduceArgs a, const int* row, long row_stride) {
-  ReduceArgs b = a;
-  b.out = a.out + static_cast<long>(*row) * row_stride;
-  reduce_tile<V>(b, blockIdx.x);
+__global__ void __launch_bounds__(512) k_reduce2(ReduceArgs a) {
+  reduce2_tile<V>(a, blockIdx.x, a.out);
+}
+
+// Level 2 whose output row is taken from a device counter (hipGraph replays
+// write successive rows); k_bump advances the counter afterwards.
+template <int V>
+__global__ void __launch_bounds__(512) k_reduce2_counted(ReduceArgs a, const int* row, long row_stride) {
+  reduce2_tile<V>(a, blockIdx.x, a.out + static_cast<long>(*row) * row_stride);
 }
 
 __global__ void k_bump(int* row) {
@@ -396,7 +480,7 @@ __global__ void __launch_bounds__(256) k_dot_plain(const uint32_t* __restrict__ 
 // ---------------------------------------------------------------------------
 // Grouped launches: one launch runs one step of many (job, chunk) items
 // ---------------------------------------------------------------------------
-enum StepOp : int { kOpFill = 0, kOpGather = 1, kOpDot = 2, kOpReduce = 3 };
+enum StepOp : int { kOpFill = 0, kOpGather = 1, kOpDot = 2, kOpReduce1 = 3, kOpReduce2 = 4 };
 
 struct Step {
   int op;
@@ -418,12 +502,13 @@ struct GroupArgs {
   const Step* steps;
   const int* tile_start;   // nsteps + 1 prefix sums of ntiles
   int nsteps;
+  int xcd;                 // remap block ids to contiguous per-XCD ranges
 };
 
 template <int V>
 __global__ void __launch_bounds__(512) k_grouped(GroupArgs g) {
   __shared__ uint32_t lds[8 * 64 * V];
-  const int b = blockIdx.x;
+  const int b = g.xcd ? xcd_contiguous(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
   int lo = 0, hi = g.nsteps - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -436,7 +521,8 @@ __global__ void __launch_bounds__(512) k_grouped(GroupArgs g) {
     case kOpGather: gather_tile<V>(st.u.g, st.chunk, tile, lds); break;
     case kOpDot: dot_tile<V>(st.u.d, st.chunk, tile, lds); break;
     case kOpFill: fill_tile<V>(st.u.f, st.chunk, tile); break;
-    case kOpReduce: reduce_tile<V>(st.u.r, st.chunk); break;
+    case kOpReduce1: reduce1_tile<V>(st.u.r, st.chunk, tile, lds); break;
+    case kOpReduce2: reduce2_tile<V>(st.u.r, st.chunk, st.u.r.out); break;
   }
 }
 

@@ -225,7 +225,7 @@ uint32_t shoup_of(uint32_t c, uint32_t p) {
 // Tuning and workspace layout
 // ---------------------------------------------------------------------------
 struct Tune {
-  int V = 2, rpw = 8, wpb = 4;
+  int V = 2, rpw = 8, wpb = 4, xcd = 0;
 };
 
 Tune resolve(const chrom_tuning* t) {
@@ -234,8 +234,10 @@ Tune resolve(const chrom_tuning* t) {
   if (t->lanes_v) r.V = t->lanes_v;
   if (t->targets_per_wave) r.rpw = t->targets_per_wave;
   if (t->waves_per_block) r.wpb = t->waves_per_block;
+  if (t->xcd_order < 0 || t->xcd_order > 2) throw ArgError("xcd_order must be 0, 1 or 2");
+  if (t->xcd_order) r.xcd = t->xcd_order - 1;
   if (r.V != 1 && r.V != 2 && r.V != 4) throw ArgError("lanes_v must be 1, 2 or 4");
-  if (r.rpw < 1 || r.rpw > 64) throw ArgError("targets_per_wave must be in 1..64");
+  if (r.rpw < 1 || r.rpw > 63) throw ArgError("targets_per_wave must be in 1..63");
   if (r.wpb != 1 && r.wpb != 2 && r.wpb != 4 && r.wpb != 8) throw ArgError("waves_per_block must be 1, 2, 4 or 8");
   return r;
 }
@@ -246,8 +248,12 @@ struct JobLayout {
   int rows_tile = 32;    // rows per workgroup tile
   int64_t s_nc = 0, s_max = 0;
   int nparts = 0;        // read-out partial tiles per chunk
-  size_t x0 = 0, x1 = 0, w = 0, part = 0, p = 0, pinv = 0, r1 = 0, cval = 0, cshp = 0, bytes = 0;
+  int ngroups = 0;       // level-1 reduction groups per chunk
+  size_t x0 = 0, x1 = 0, w = 0, part = 0, part2 = 0, p = 0, pinv = 0, r1 = 0, cval = 0, cshp = 0, bytes = 0;
 };
+
+// Level-1 groups: about 32 partials each, at most 64 groups.
+int reduce_groups(int nparts) { return std::max(1, std::min(64, (nparts + 31) / 32)); }
 
 JobLayout job_layout(int lattice, int m, int I, const Tune& t, int ncodes, int rows_tile) {
   JobLayout L;
@@ -264,6 +270,7 @@ JobLayout job_layout(int lattice, int m, int I, const Tune& t, int ncodes, int r
   L.s_nc = s.s_nc;
   L.s_max = s.s_max;
   L.nparts = static_cast<int>((L.s_nc + rows_tile - 1) / rows_tile);
+  L.ngroups = reduce_groups(L.nparts);
   size_t off = 0;
   auto take = [&](size_t b) {
     size_t o = off;
@@ -275,6 +282,7 @@ JobLayout job_layout(int lattice, int m, int I, const Tune& t, int ncodes, int r
   L.x1 = take(vec);
   L.w = take(static_cast<size_t>(L.nchunk) * L.s_nc * L.W * 4);
   L.part = take(static_cast<size_t>(L.nchunk) * L.nparts * L.W * 4);
+  L.part2 = take(static_cast<size_t>(L.nchunk) * L.ngroups * L.W * 4);
   L.p = take(L.ipad * 4);
   L.pinv = take(L.ipad * 4);
   L.r1 = take(L.ipad * 4);
@@ -311,7 +319,7 @@ std::vector<uint32_t> const_image(const JobLayout& L, const std::vector<Inst>& i
 
 // Pointers of one job's device state.
 struct JobPtrs {
-  uint32_t *x0, *x1, *w, *part, *p, *pinv, *r1, *cval, *cshp;
+  uint32_t *x0, *x1, *w, *part, *part2, *p, *pinv, *r1, *cval, *cshp;
   InstConsts ic() const { return InstConsts{p, pinv, cval, cshp, 0}; }
 };
 
@@ -322,6 +330,7 @@ JobPtrs job_ptrs(const JobLayout& L, void* base) {
   j.x1 = reinterpret_cast<uint32_t*>(b + L.x1);
   j.w = reinterpret_cast<uint32_t*>(b + L.w);
   j.part = reinterpret_cast<uint32_t*>(b + L.part);
+  j.part2 = reinterpret_cast<uint32_t*>(b + L.part2);
   j.p = reinterpret_cast<uint32_t*>(b + L.p);
   j.pinv = reinterpret_cast<uint32_t*>(b + L.pinv);
   j.r1 = reinterpret_cast<uint32_t*>(b + L.r1);
@@ -405,13 +414,22 @@ Step gather_step(const JobCtx& j, const DevCsr& c, const uint32_t* in, uint32_t*
   return s;
 }
 
-Step reduce_step(const JobCtx& j, int out_row) {
+ReduceArgs reduce_args(const JobCtx& j, int out_row) {
+  return ReduceArgs{j.P.part, static_cast<long>(j.L.nparts) * j.L.W, j.L.nparts, inst_consts(j.L, j.P),
+                    j.P.part2, static_cast<long>(j.L.ngroups) * j.L.W, j.L.ngroups,
+                    j.d_out ? j.d_out + static_cast<long>(out_row) * j.L.I : nullptr, j.L.I};
+}
+
+// The read-out of one row: level-1 then level-2 reduction of the partials.
+int push_reduce(Program& pg, const JobCtx& j, int out_row, int dep) {
   Step s{};
-  s.op = kOpReduce;
+  s.op = kOpReduce1;
+  s.ntiles = j.L.ngroups;
+  s.u.r = reduce_args(j, out_row);
+  const int r1 = push(pg, s, dep, -1);
+  s.op = kOpReduce2;
   s.ntiles = 1;
-  s.u.r = ReduceArgs{j.P.part, static_cast<long>(j.L.nparts) * j.L.W, j.L.nparts, inst_consts(j.L, j.P),
-                     j.d_out + static_cast<long>(out_row) * j.L.I, j.L.I};
-  return s;
+  return push(pg, s, r1, -1);
 }
 
 // Set-up: w = (T_1^last)^T ... (T_m^last)^T (R e_0) built in x0/x1 and
@@ -444,7 +462,7 @@ int add_setup(Program& pg, const JobCtx& j) {
   s.u.d = DotArgs{j.P.x0, j.P.w, cs_x, cs_w, static_cast<int>(L.s_nc), inst_consts(L, j.P), j.P.part,
                   static_cast<long>(L.nparts) * L.W, j.t.rpw};
   last = push(pg, s, last, -1);
-  return push(pg, reduce_step(j, 0), last, -1);
+  return push_reduce(pg, j, 0, last);
 }
 
 // Rows: out rows r = r_first..r_last (0-based; row r holds P of m x (r+1)),
@@ -466,7 +484,7 @@ void add_rows(Program& pg, const JobCtx& j, int r_first, int r_last, int after, 
       after = tm;
       std::swap(cur, oth);
     }
-    prev_reduce = push(pg, reduce_step(j, r), tm, -1);
+    prev_reduce = push_reduce(pg, j, r, tm);
   }
 }
 
@@ -483,33 +501,37 @@ Program strip_program(const JobCtx& j, int n_max) {
 // Eager execution of a program: one launch per step, grid (ntiles, nchunk)
 // ---------------------------------------------------------------------------
 template <int V>
-void launch_step_v(const Step& s, int nchunk, int wpb, hipStream_t st, const int* row_ctr, long row_stride) {
+void launch_step_v(const Step& s, int nchunk, int wpb, int xcd, hipStream_t st, const int* row_ctr,
+                   long row_stride) {
   dim3 grid(s.ntiles, nchunk), block(64 * wpb);
   switch (s.op) {
-    case kOpGather: hipLaunchKernelGGL(k_gather<V>, grid, block, 0, st, s.u.g); break;
-    case kOpDot: hipLaunchKernelGGL(k_dot<V>, grid, block, 0, st, s.u.d); break;
+    case kOpGather: hipLaunchKernelGGL(k_gather<V>, grid, block, 0, st, s.u.g, xcd); break;
+    case kOpDot: hipLaunchKernelGGL(k_dot<V>, grid, block, 0, st, s.u.d, xcd); break;
     case kOpFill: hipLaunchKernelGGL(k_fill<V>, grid, block, 0, st, s.u.f); break;
-    case kOpReduce:
+    case kOpReduce1:
+      hipLaunchKernelGGL(k_reduce1<V>, dim3(s.ntiles, nchunk), dim3(256), 0, st, s.u.r);
+      break;
+    case kOpReduce2:
       if (row_ctr)
-        hipLaunchKernelGGL(k_reduce_counted<V>, dim3(nchunk), dim3(256), 0, st, s.u.r, row_ctr, row_stride);
+        hipLaunchKernelGGL(k_reduce2_counted<V>, dim3(nchunk), dim3(256), 0, st, s.u.r, row_ctr, row_stride);
       else
-        hipLaunchKernelGGL(k_reduce<V>, dim3(nchunk), dim3(256), 0, st, s.u.r);
+        hipLaunchKernelGGL(k_reduce2<V>, dim3(nchunk), dim3(256), 0, st, s.u.r);
       break;
   }
   HIPX(hipGetLastError());
 }
 
-void launch_step(const Step& s, int V, int nchunk, int wpb, hipStream_t st, const int* row_ctr = nullptr,
+void launch_step(const Step& s, const Tune& t, int nchunk, hipStream_t st, const int* row_ctr = nullptr,
                  long row_stride = 0) {
-  switch (V) {
-    case 1: launch_step_v<1>(s, nchunk, wpb, st, row_ctr, row_stride); break;
-    case 2: launch_step_v<2>(s, nchunk, wpb, st, row_ctr, row_stride); break;
-    default: launch_step_v<4>(s, nchunk, wpb, st, row_ctr, row_stride); break;
+  switch (t.V) {
+    case 1: launch_step_v<1>(s, nchunk, t.wpb, t.xcd, st, row_ctr, row_stride); break;
+    case 2: launch_step_v<2>(s, nchunk, t.wpb, t.xcd, st, row_ctr, row_stride); break;
+    default: launch_step_v<4>(s, nchunk, t.wpb, t.xcd, st, row_ctr, row_stride); break;
   }
 }
 
 void run_eager(const Program& pg, const Tune& t, hipStream_t st) {
-  for (const PStep& ps : pg.steps) launch_step(ps.s, t.V, pg.nchunk, t.wpb, st);
+  for (const PStep& ps : pg.steps) launch_step(ps.s, t, pg.nchunk, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -519,10 +541,10 @@ void run_eager(const Program& pg, const Tune& t, hipStream_t st) {
 struct GraphKey {
   void* ws;
   uint32_t* out;
-  int lattice, m, I, V, rpw, wpb, rows_per_graph;
+  int lattice, m, I, V, rpw, wpb, xcd, rows_per_graph;
   bool operator<(const GraphKey& o) const {
-    return std::tie(ws, out, lattice, m, I, V, rpw, wpb, rows_per_graph) <
-           std::tie(o.ws, o.out, o.lattice, o.m, o.I, o.V, o.rpw, o.wpb, o.rows_per_graph);
+    return std::tie(ws, out, lattice, m, I, V, rpw, wpb, xcd, rows_per_graph) <
+           std::tie(o.ws, o.out, o.lattice, o.m, o.I, o.V, o.rpw, o.wpb, o.xcd, o.rows_per_graph);
   }
 };
 struct GraphEntry {
@@ -554,7 +576,7 @@ void run_graph(const JobCtx& j, int n_max, int* row_ctr, void* ws, hipStream_t s
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, row_ctr, 1);
   HIPX(hipGetLastError());
   if (replays > 0) {
-    GraphKey key{ws, j.d_out, j.L.lattice, j.L.m, j.L.I, j.t.V, j.t.rpw, j.t.wpb, per};
+    GraphKey key{ws, j.d_out, j.L.lattice, j.L.m, j.L.I, j.t.V, j.t.rpw, j.t.wpb, j.t.xcd, per};
     hipGraphExec_t exec = nullptr;
     {
       std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -569,13 +591,13 @@ void run_graph(const JobCtx& j, int n_max, int* row_ctr, void* ws, hipStream_t s
       hipStream_t cs = capture_stream();
       HIPX(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       for (const PStep& ps : rows_pg.steps) {
-        if (ps.s.op == kOpReduce) {
+        if (ps.s.op == kOpReduce2) {
           Step counted = ps.s;
           counted.u.r.out = j.d_out;  // row offset comes from the device counter
-          launch_step(counted, j.t.V, rows_pg.nchunk, j.t.wpb, cs, row_ctr, j.L.I);
+          launch_step(counted, j.t, rows_pg.nchunk, cs, row_ctr, j.L.I);
           hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, cs, row_ctr);
         } else {
-          launch_step(ps.s, j.t.V, rows_pg.nchunk, j.t.wpb, cs);
+          launch_step(ps.s, j.t, rows_pg.nchunk, cs);
         }
       }
       hipGraph_t graph = nullptr;
@@ -643,12 +665,12 @@ uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull) 
   return h;
 }
 
-void launch_stages(const StageImage& im, const Step* d_steps, const int* d_tiles, int V, int wpb, hipStream_t st) {
+void launch_stages(const StageImage& im, const Step* d_steps, const int* d_tiles, const Tune& t, hipStream_t st) {
   for (size_t k = 0; k < im.nsteps.size(); ++k) {
     if (im.nsteps[k] == 0) continue;
-    GroupArgs g{d_steps + im.step_off[k], d_tiles + im.tile_off[k], im.nsteps[k]};
-    dim3 grid(im.ntiles[k]), block(64 * wpb);
-    switch (V) {
+    GroupArgs g{d_steps + im.step_off[k], d_tiles + im.tile_off[k], im.nsteps[k], t.xcd};
+    dim3 grid(im.ntiles[k]), block(64 * t.wpb);
+    switch (t.V) {
       case 1: hipLaunchKernelGGL(k_grouped<1>, grid, block, 0, st, g); break;
       case 2: hipLaunchKernelGGL(k_grouped<2>, grid, block, 0, st, g); break;
       default: hipLaunchKernelGGL(k_grouped<4>, grid, block, 0, st, g); break;
@@ -695,7 +717,7 @@ void run_grouped(const std::vector<const Program*>& progs, const Tune& t, void* 
   if (!as_graph) {
     upload(d_steps, im.steps.data(), im.steps.size() * sizeof(Step), st);
     upload(d_tiles, im.tile_start.data(), im.tile_start.size() * sizeof(int), st);
-    launch_stages(im, d_steps, d_tiles, t.V, t.wpb, st);
+    launch_stages(im, d_steps, d_tiles, t, st);
     return;
   }
   hipGraphExec_t exec = nullptr;
@@ -718,7 +740,7 @@ void run_grouped(const std::vector<const Program*>& progs, const Tune& t, void* 
     upload(d_tiles, im.tile_start.data(), im.tile_start.size() * sizeof(int), st);
     hipStream_t cs = capture_stream();
     HIPX(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    launch_stages(im, d_steps, d_tiles, t.V, t.wpb, cs);
+    launch_stages(im, d_steps, d_tiles, t, cs);
     hipGraph_t graph = nullptr;
     HIPX(hipStreamEndCapture(cs, &graph));
     HIPX(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
@@ -729,7 +751,7 @@ void run_grouped(const std::vector<const Program*>& progs, const Tune& t, void* 
   HIPX(hipGraphLaunch(exec, st));
 }
 
-int strip_program_len(int m, int n_max) { return n_max < 1 ? 0 : (m + 4) + (n_max - 1) * (m + 1); }
+int strip_program_len(int m, int n_max) { return n_max < 1 ? 0 : (m + 5) + (n_max - 1) * (m + 2); }
 
 // ---------------------------------------------------------------------------
 // Plain per-instance path
@@ -919,7 +941,7 @@ int factor_launches_impl(int lattice, int m, const uint32_t* q, int nq, const ui
   pg.nchunk = j.L.nchunk;
   add_rows(pg, j, 1, rows, -1, -1);
   for (const PStep& ps : pg.steps)
-    if (ps.s.op == kOpGather) launch_step(ps.s, t.V, pg.nchunk, t.wpb, st);
+    if (ps.s.op == kOpGather) launch_step(ps.s, t, pg.nchunk, st);
   return CHROM_OK;
 }
 

@@ -20,16 +20,17 @@ from . import api
 
 DEFAULT_CACHE = os.environ.get("CHROMSTRIP_TUNE_CACHE",
                                os.path.join(os.path.expanduser("~"), ".cache", "chromstrip", "tune.json"))
-SPACE = dict(lanes_v=[1, 2, 4], targets_per_wave=[2, 4, 8, 16], waves_per_block=[2, 4, 8],
-             mode=["graph", "grouped"])
+SPACE = dict(lanes_v=[1, 2, 4], targets_per_wave=[4, 8, 16, 32], waves_per_block=[2, 4, 8],
+             xcd_order=[1, 2], mode=["graph", "grouped"])
 
 
 def candidates(space=None) -> list[dict]:
     space = space or SPACE
     out = []
-    for v, t, w, mode in itertools.product(space["lanes_v"], space["targets_per_wave"], space["waves_per_block"],
-                                           space["mode"]):
-        out.append(dict(lanes_v=v, targets_per_wave=t, waves_per_block=w, mode=mode))
+    for v, t, w, x, mode in itertools.product(space["lanes_v"], space["targets_per_wave"],
+                                              space["waves_per_block"], space.get("xcd_order", [0]),
+                                              space["mode"]):
+        out.append(dict(lanes_v=v, targets_per_wave=t, waves_per_block=w, xcd_order=x, mode=mode))
     return out
 
 
@@ -100,3 +101,31 @@ def tune(lattice, m, n_max, q_points, primes, space=None, steps=3, path=DEFAULT_
     with open(path, "w") as f:
         json.dump(cache, f, indent=1)
     return dict(best=best, table=table)
+
+
+def main():
+    """python -m paper_1005_3609_amd.tune --workload square_14x15 [--cache PATH]"""
+    import argparse
+    import sys
+
+    from . import workloads as W
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="square_14x15")
+    ap.add_argument("--cache", default=DEFAULT_CACHE)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--quick", action="store_true", help="a reduced search space")
+    args = ap.parse_args()
+    w = W.workload(args.workload)
+    space = None
+    if args.quick:
+        space = dict(lanes_v=[1, 2], targets_per_wave=[8, 16, 32], waves_per_block=[4, 8], xcd_order=[1, 2],
+                     mode=["graph"])
+    for lat, m, n in w["strips"]:
+        api.prepare(lat, m)
+        res = tune(lat, m, n, w["q_points"], w["primes"], space=space, steps=args.steps, path=args.cache,
+                   log=lambda s: print(s, file=sys.stderr, flush=True))
+        print(json.dumps(dict(workload=args.workload, lattice=lat, m=m, n_max=n, best=res["best"])), flush=True)
+
+
+if __name__ == "__main__":
+    main()
