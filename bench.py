@@ -206,10 +206,16 @@ def main():
         nel = args.copy_mib * (1 << 20) // 4
         src = torch.randint(0, 1 << 30, (nel,), dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        ev0.record(stream)
         for _ in range(3):
             dst.copy_(src)
+        ev1.record(stream)
         torch.cuda.synchronize()
-        log(f"copied {args.copy_mib} MiB three times (counter calibration)")
+        c_ms = ev0.elapsed_time(ev1) / 3
+        log(f"copied {args.copy_mib} MiB x4 (counter calibration); device copy "
+            f"{2 * args.copy_mib * (1 << 20) / (c_ms / 1e3) / 1e9:.0f} GB/s read+write")
 
     line = {
         "metric": "state-updates/s, square lattice m=14 (14x15 strip), batched",

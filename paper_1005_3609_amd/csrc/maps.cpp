@@ -17,6 +17,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <climits>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 #include <map>
@@ -289,6 +291,67 @@ void build_factor(const FactorDef& d, bool gather_form, int threads, Csr& csr,
   }
 }
 
+// Renumbers the rows of `c` by new_row[old] and its columns by new_col[old]
+// (either may be empty = identity); entries of a row end up sorted by column.
+void renumber(Csr& c, const std::vector<int32_t>& new_row, const std::vector<int32_t>& new_col) {
+  const int64_t nr = c.n_rows;
+  std::vector<int32_t> old_of(nr);
+  for (int64_t r = 0; r < nr; ++r) old_of[new_row.empty() ? r : new_row[r]] = static_cast<int32_t>(r);
+  Csr out;
+  out.n_rows = c.n_rows;
+  out.n_cols = c.n_cols;
+  out.row_ptr.assign(nr + 1, 0);
+  out.ent.resize(c.ent.size());
+  int64_t w = 0;
+  for (int64_t r = 0; r < nr; ++r) {
+    const int32_t o = old_of[r];
+    const int64_t lo = w;
+    for (int64_t e = c.row_ptr[o]; e < c.row_ptr[o + 1]; ++e) {
+      const uint32_t col = c.ent[e] & kSrcMask, code = c.ent[e] >> kSrcBits;
+      const uint32_t nc = new_col.empty() ? col : static_cast<uint32_t>(new_col[col]);
+      out.ent[w++] = nc | (code << kSrcBits);
+    }
+    std::sort(out.ent.begin() + lo, out.ent.begin() + w,
+              [](uint32_t a, uint32_t b) { return (a & kSrcMask) < (b & kSrcMask); });
+    out.row_ptr[r + 1] = static_cast<int32_t>(w);
+  }
+  c = std::move(out);
+}
+
+// Reader order for the spaces between the factors of one transfer row.  The
+// NCNNN space S_0 = S_m (input of T_1, output of T_m, space of the read-out
+// vector) keeps the paper's order.  Going backwards, S_{k} (k = m-1..1) is
+// ordered by the first target row of T_{k+1} -- in S_{k+1}'s order, already
+// fixed -- that reads it (ties by old rank; unread states last).  The rows of
+// T_{k+1} are then visited in an order that touches most sources for the
+// first time in increasing address order, and re-reads of a source follow
+// its first read closely, so they are served by the L2.  The numbering is
+// internal to the maps: every factor is renumbered consistently.
+void reader_order(MapSet& ms) {
+  const int m = ms.m;
+  if (m < 2) return;
+  std::vector<std::vector<int32_t>> perm(m + 1);  // perm[k][old] = new, for S_k
+  for (int k = m - 1; k >= 1; --k) {
+    const Csr& t = ms.fwd[k];  // T_{k+1}: rows in S_{k+1}, columns in S_k
+    const int64_t ns = t.n_cols;
+    std::vector<int64_t> first(ns, INT64_MAX);
+    for (int64_t r = 0; r < t.n_rows; ++r) {
+      const int64_t nr = perm[k + 1].empty() ? r : perm[k + 1][r];
+      for (int64_t e = t.row_ptr[r]; e < t.row_ptr[r + 1]; ++e) {
+        const uint32_t col = t.ent[e] & kSrcMask;
+        first[col] = std::min(first[col], nr);
+      }
+    }
+    std::vector<int32_t> order(ns);
+    for (int64_t s = 0; s < ns; ++s) order[s] = static_cast<int32_t>(s);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return first[a] < first[b]; });
+    perm[k].assign(ns, 0);
+    for (int64_t pos = 0; pos < ns; ++pos) perm[k][order[pos]] = static_cast<int32_t>(pos);
+  }
+  // fwd[k] = T_{k+1}: rows in S_{k+1}, columns in S_k
+  for (int k = 0; k < m; ++k) renumber(ms.fwd[k], perm[k + 1], perm[k]);
+}
+
 }  // namespace
 
 int64_t MapSet::total_nnz() const {
@@ -353,6 +416,8 @@ std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads) {
     finish(ms->fwd[i], fkeys[i]);
     finish(ms->last[i], lkeys[i]);
   }
+  const char* order = std::getenv("CHROMSTRIP_STATE_ORDER");
+  if (!(order && std::string(order) == "paper")) reader_order(*ms);
   return ms;
 }
 
