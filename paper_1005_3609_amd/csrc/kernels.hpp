@@ -184,14 +184,12 @@ __device__ __forceinline__ void accumulate(uint32_t (&acc)[V], const uint32_t (&
 // One wavefront computes target rows [r0, r1) of one chunk.  Its row
 // pointers (lane j holds row_ptr[r0 + j]) and up to 64 entry words at a time
 // (lane l holds one word) arrive with coalesced vector loads and are
-// broadcast with readlane; the source rows of kUnroll consecutive entries are
+// broadcast with readlane; the source rows of U consecutive entries are
 // loaded before any is consumed, so several W*4-byte gathers are in flight
 // per wavefront.  Row boundaries are uniform, so each finished row is stored
 // (and, when fused, folded into the read-out) without divergence; rows with
 // no entries are stored as zero.
-constexpr int kUnroll = 4;
-
-template <int V>
+template <int V, int U>
 __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* lds) {
   constexpr int W = 64 * V;
   const int lane = lane_id(), wave = wave_id();
@@ -234,16 +232,16 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
       const int n = min(64, end - base);
       const uint32_t ev = (lane < n) ? a.csr.ent[base + lane] : 0u;
       int k = 0;
-      for (; k + kUnroll <= n; k += kUnroll) {
-        uint32_t word[kUnroll];
-        uint32_t x[kUnroll][V];
+      for (; k + U <= n; k += U) {
+        uint32_t word[U];
+        uint32_t x[U][V];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < U; ++u) {
           word[u] = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ev), k + u));
           load_v<V>(in + static_cast<size_t>(word[u] & kEntSrcMask) * W, x[u]);
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < U; ++u) {
           while (base + k + u >= row_end) flush();
           accumulate<V>(acc, x[u], word[u] >> 28, p, a.ic, inst0);
         }
@@ -359,54 +357,54 @@ __device__ void reduce2_tile(const ReduceArgs& a, int chunk, uint32_t* out) {
 // ---------------------------------------------------------------------------
 // Eager kernels: grid.x = tiles, grid.y = chunks
 // ---------------------------------------------------------------------------
-// Block (x, y) = (tile, chunk); with xcd != 0 the linear block id is first
-// remapped so each XCD sweeps a contiguous range.
-__device__ __forceinline__ void tile_chunk(int xcd, int& tile, int& chunk) {
+// Block (x, y) = (tile, chunk0 + y); with xcd != 0 the linear block id is
+// first remapped so each XCD sweeps a contiguous range.
+__device__ __forceinline__ void tile_chunk(int xcd, int chunk0, int& tile, int& chunk) {
   int b = blockIdx.y * gridDim.x + blockIdx.x;
   if (xcd) b = xcd_contiguous(b, gridDim.x * gridDim.y);
   tile = b % gridDim.x;
-  chunk = b / gridDim.x;
+  chunk = chunk0 + b / gridDim.x;
+}
+
+template <int V, int U>
+__global__ void __launch_bounds__(512) k_gather(GatherArgs a, int xcd, int chunk0) {
+  __shared__ uint32_t lds[8 * 64 * V];
+  int tile, chunk;
+  tile_chunk(xcd, chunk0, tile, chunk);
+  gather_tile<V, U>(a, chunk, tile, lds);
 }
 
 template <int V>
-__global__ void __launch_bounds__(512) k_gather(GatherArgs a, int xcd) {
+__global__ void __launch_bounds__(512) k_dot(DotArgs a, int xcd, int chunk0) {
   __shared__ uint32_t lds[8 * 64 * V];
   int tile, chunk;
-  tile_chunk(xcd, tile, chunk);
-  gather_tile<V>(a, chunk, tile, lds);
-}
-
-template <int V>
-__global__ void __launch_bounds__(512) k_dot(DotArgs a, int xcd) {
-  __shared__ uint32_t lds[8 * 64 * V];
-  int tile, chunk;
-  tile_chunk(xcd, tile, chunk);
+  tile_chunk(xcd, chunk0, tile, chunk);
   dot_tile<V>(a, chunk, tile, lds);
 }
 
 template <int V>
-__global__ void __launch_bounds__(512) k_fill(FillArgs a) {
-  fill_tile<V>(a, blockIdx.y, blockIdx.x);
+__global__ void __launch_bounds__(512) k_fill(FillArgs a, int chunk0) {
+  fill_tile<V>(a, chunk0 + blockIdx.y, blockIdx.x);
 }
 
 // grid (n_groups, chunks)
 template <int V>
-__global__ void __launch_bounds__(512) k_reduce1(ReduceArgs a) {
+__global__ void __launch_bounds__(512) k_reduce1(ReduceArgs a, int chunk0) {
   __shared__ uint32_t lds[8 * 64 * V];
-  reduce1_tile<V>(a, blockIdx.y, blockIdx.x, lds);
+  reduce1_tile<V>(a, chunk0 + blockIdx.y, blockIdx.x, lds);
 }
 
 // grid (chunks)
 template <int V>
-__global__ void __launch_bounds__(512) k_reduce2(ReduceArgs a) {
-  reduce2_tile<V>(a, blockIdx.x, a.out);
+__global__ void __launch_bounds__(512) k_reduce2(ReduceArgs a, int chunk0) {
+  reduce2_tile<V>(a, chunk0 + blockIdx.x, a.out);
 }
 
 // Level 2 whose output row is taken from a device counter (hipGraph replays
 // write successive rows); k_bump advances the counter afterwards.
 template <int V>
-__global__ void __launch_bounds__(512) k_reduce2_counted(ReduceArgs a, const int* row, long row_stride) {
-  reduce2_tile<V>(a, blockIdx.x, a.out + static_cast<long>(*row) * row_stride);
+__global__ void __launch_bounds__(512) k_reduce2_counted(ReduceArgs a, int chunk0, const int* row, long row_stride) {
+  reduce2_tile<V>(a, chunk0 + blockIdx.x, a.out + static_cast<long>(*row) * row_stride);
 }
 
 __global__ void k_bump(int* row) {
@@ -505,7 +503,7 @@ struct GroupArgs {
   int xcd;                 // remap block ids to contiguous per-XCD ranges
 };
 
-template <int V>
+template <int V, int U>
 __global__ void __launch_bounds__(512) k_grouped(GroupArgs g) {
   __shared__ uint32_t lds[8 * 64 * V];
   const int b = g.xcd ? xcd_contiguous(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
@@ -518,7 +516,7 @@ __global__ void __launch_bounds__(512) k_grouped(GroupArgs g) {
   const int tile = __builtin_amdgcn_readfirstlane(b - g.tile_start[k]);
   const Step& st = g.steps[k];
   switch (st.op) {
-    case kOpGather: gather_tile<V>(st.u.g, st.chunk, tile, lds); break;
+    case kOpGather: gather_tile<V, U>(st.u.g, st.chunk, tile, lds); break;
     case kOpDot: dot_tile<V>(st.u.d, st.chunk, tile, lds); break;
     case kOpFill: fill_tile<V>(st.u.f, st.chunk, tile); break;
     case kOpReduce1: reduce1_tile<V>(st.u.r, st.chunk, tile, lds); break;

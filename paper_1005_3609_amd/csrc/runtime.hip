@@ -225,7 +225,7 @@ uint32_t shoup_of(uint32_t c, uint32_t p) {
 // Tuning and workspace layout
 // ---------------------------------------------------------------------------
 struct Tune {
-  int V = 2, rpw = 8, wpb = 4, xcd = 0;
+  int V = 2, rpw = 8, wpb = 4, xcd = 0, U = 4, streams = 1;
 };
 
 Tune resolve(const chrom_tuning* t) {
@@ -236,6 +236,10 @@ Tune resolve(const chrom_tuning* t) {
   if (t->waves_per_block) r.wpb = t->waves_per_block;
   if (t->xcd_order < 0 || t->xcd_order > 2) throw ArgError("xcd_order must be 0, 1 or 2");
   if (t->xcd_order) r.xcd = t->xcd_order - 1;
+  if (t->unroll) r.U = t->unroll;
+  if (t->streams) r.streams = t->streams;
+  if (r.U != 4 && r.U != 8) throw ArgError("unroll must be 4 or 8");
+  if (r.streams < 1 || r.streams > 4) throw ArgError("streams must be in 1..4");
   if (r.V != 1 && r.V != 2 && r.V != 4) throw ArgError("lanes_v must be 1, 2 or 4");
   if (r.rpw < 1 || r.rpw > 63) throw ArgError("targets_per_wave must be in 1..63");
   if (r.wpb != 1 && r.wpb != 2 && r.wpb != 4 && r.wpb != 8) throw ArgError("waves_per_block must be 1, 2, 4 or 8");
@@ -500,38 +504,106 @@ Program strip_program(const JobCtx& j, int n_max) {
 // ---------------------------------------------------------------------------
 // Eager execution of a program: one launch per step, grid (ntiles, nchunk)
 // ---------------------------------------------------------------------------
-template <int V>
-void launch_step_v(const Step& s, int nchunk, int wpb, int xcd, hipStream_t st, const int* row_ctr,
-                   long row_stride) {
-  dim3 grid(s.ntiles, nchunk), block(64 * wpb);
+// Launches one step over chunks [c0, c0 + nch).
+template <int V, int U>
+void launch_step_vu(const Step& s, int c0, int nch, int wpb, int xcd, hipStream_t st, const int* row_ctr,
+                    long row_stride) {
+  dim3 grid(s.ntiles, nch), block(64 * wpb);
   switch (s.op) {
-    case kOpGather: hipLaunchKernelGGL(k_gather<V>, grid, block, 0, st, s.u.g, xcd); break;
-    case kOpDot: hipLaunchKernelGGL(k_dot<V>, grid, block, 0, st, s.u.d, xcd); break;
-    case kOpFill: hipLaunchKernelGGL(k_fill<V>, grid, block, 0, st, s.u.f); break;
+    case kOpGather: hipLaunchKernelGGL((k_gather<V, U>), grid, block, 0, st, s.u.g, xcd, c0); break;
+    case kOpDot: hipLaunchKernelGGL(k_dot<V>, grid, block, 0, st, s.u.d, xcd, c0); break;
+    case kOpFill: hipLaunchKernelGGL(k_fill<V>, grid, block, 0, st, s.u.f, c0); break;
     case kOpReduce1:
-      hipLaunchKernelGGL(k_reduce1<V>, dim3(s.ntiles, nchunk), dim3(256), 0, st, s.u.r);
+      hipLaunchKernelGGL(k_reduce1<V>, dim3(s.ntiles, nch), dim3(256), 0, st, s.u.r, c0);
       break;
     case kOpReduce2:
       if (row_ctr)
-        hipLaunchKernelGGL(k_reduce2_counted<V>, dim3(nchunk), dim3(256), 0, st, s.u.r, row_ctr, row_stride);
+        hipLaunchKernelGGL(k_reduce2_counted<V>, dim3(nch), dim3(256), 0, st, s.u.r, c0, row_ctr, row_stride);
       else
-        hipLaunchKernelGGL(k_reduce2<V>, dim3(nchunk), dim3(256), 0, st, s.u.r);
+        hipLaunchKernelGGL(k_reduce2<V>, dim3(nch), dim3(256), 0, st, s.u.r, c0);
       break;
   }
   HIPX(hipGetLastError());
 }
 
-void launch_step(const Step& s, const Tune& t, int nchunk, hipStream_t st, const int* row_ctr = nullptr,
+void launch_step(const Step& s, const Tune& t, int c0, int nch, hipStream_t st, const int* row_ctr = nullptr,
                  long row_stride = 0) {
-  switch (t.V) {
-    case 1: launch_step_v<1>(s, nchunk, t.wpb, t.xcd, st, row_ctr, row_stride); break;
-    case 2: launch_step_v<2>(s, nchunk, t.wpb, t.xcd, st, row_ctr, row_stride); break;
-    default: launch_step_v<4>(s, nchunk, t.wpb, t.xcd, st, row_ctr, row_stride); break;
+  const int key = t.V * 10 + t.U;
+  switch (key) {
+    case 14: launch_step_vu<1, 4>(s, c0, nch, t.wpb, t.xcd, st, row_ctr, row_stride); break;
+    case 18: launch_step_vu<1, 8>(s, c0, nch, t.wpb, t.xcd, st, row_ctr, row_stride); break;
+    case 24: launch_step_vu<2, 4>(s, c0, nch, t.wpb, t.xcd, st, row_ctr, row_stride); break;
+    case 28: launch_step_vu<2, 8>(s, c0, nch, t.wpb, t.xcd, st, row_ctr, row_stride); break;
+    case 44: launch_step_vu<4, 4>(s, c0, nch, t.wpb, t.xcd, st, row_ctr, row_stride); break;
+    default: launch_step_vu<4, 8>(s, c0, nch, t.wpb, t.xcd, st, row_ctr, row_stride); break;
   }
 }
 
-void run_eager(const Program& pg, const Tune& t, hipStream_t st) {
-  for (const PStep& ps : pg.steps) launch_step(ps.s, t, pg.nchunk, st);
+// Instance chunks split into up to `streams` groups that run their step
+// sequences on parallel streams (fork/join through events), so one group's
+// kernel tail overlaps another group's kernels.  Groups never share data.
+struct ChunkGroups {
+  int n = 1;
+  int c0[4], nch[4];
+};
+
+ChunkGroups chunk_groups(int nchunk, int streams) {
+  ChunkGroups g;
+  g.n = std::max(1, std::min(streams, nchunk));
+  for (int k = 0; k < g.n; ++k) {
+    g.c0[k] = nchunk * k / g.n;
+    g.nch[k] = nchunk * (k + 1) / g.n - g.c0[k];
+  }
+  return g;
+}
+
+struct AuxStreams {
+  hipStream_t s[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
+};
+std::mutex g_aux_mu;
+AuxStreams g_aux[64], g_aux_capture[64];
+
+AuxStreams& aux_streams(bool capture) {
+  int dev = 0;
+  HIPX(hipGetDevice(&dev));
+  AuxStreams& a = capture ? g_aux_capture[dev] : g_aux[dev];
+  if (!a.fork) {
+    for (int k = 0; k < 3; ++k) {
+      HIPX(hipStreamCreateWithFlags(&a.s[k], hipStreamNonBlocking));
+      HIPX(hipEventCreateWithFlags(&a.join[k], hipEventDisableTiming));
+    }
+    HIPX(hipEventCreateWithFlags(&a.fork, hipEventDisableTiming));
+  }
+  return a;
+}
+
+// Runs `body(group, stream)` for every chunk group, group 0 on `st` and the
+// others on auxiliary streams forked from and joined back into `st`.
+template <class F>
+void for_groups(const ChunkGroups& g, hipStream_t st, bool capture, F&& body) {
+  if (g.n == 1) {
+    body(0, st);
+    return;
+  }
+  std::lock_guard<std::mutex> lk(g_aux_mu);
+  AuxStreams& a = aux_streams(capture);
+  HIPX(hipEventRecord(a.fork, st));
+  for (int k = 1; k < g.n; ++k) HIPX(hipStreamWaitEvent(a.s[k - 1], a.fork, 0));
+  body(0, st);
+  for (int k = 1; k < g.n; ++k) body(k, a.s[k - 1]);
+  for (int k = 1; k < g.n; ++k) {
+    HIPX(hipEventRecord(a.join[k - 1], a.s[k - 1]));
+    HIPX(hipStreamWaitEvent(st, a.join[k - 1], 0));
+  }
+}
+
+void run_eager(const Program& pg, const Tune& t, hipStream_t st, bool capture = false,
+               const int* row_ctr = nullptr, long row_stride = 0) {
+  ChunkGroups g = chunk_groups(pg.nchunk, t.streams);
+  for_groups(g, st, capture, [&](int k, hipStream_t s) {
+    for (const PStep& ps : pg.steps) launch_step(ps.s, t, g.c0[k], g.nch[k], s, row_ctr, row_stride);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -576,7 +648,7 @@ void run_graph(const JobCtx& j, int n_max, int* row_ctr, void* ws, hipStream_t s
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, row_ctr, 1);
   HIPX(hipGetLastError());
   if (replays > 0) {
-    GraphKey key{ws, j.d_out, j.L.lattice, j.L.m, j.L.I, j.t.V, j.t.rpw, j.t.wpb, j.t.xcd, per};
+    GraphKey key{ws, j.d_out, j.L.lattice, j.L.m, j.L.I, j.t.V, j.t.rpw, j.t.wpb, j.t.xcd * 100 + j.t.U * 10 + j.t.streams, per};
     hipGraphExec_t exec = nullptr;
     {
       std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -588,17 +660,19 @@ void run_graph(const JobCtx& j, int n_max, int* row_ctr, void* ws, hipStream_t s
       rows_pg.nchunk = j.L.nchunk;
       // rows 1..per starting from the parity of row 1 (x in x0)
       add_rows(rows_pg, j, 1, per, -1, -1);
+      // reduce2 writes the row given by the device counter; k_bump advances
+      // it once every chunk group has written
+      for (PStep& ps : rows_pg.steps)
+        if (ps.s.op == kOpReduce2) ps.s.u.r.out = j.d_out;
       hipStream_t cs = capture_stream();
       HIPX(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-      for (const PStep& ps : rows_pg.steps) {
-        if (ps.s.op == kOpReduce2) {
-          Step counted = ps.s;
-          counted.u.r.out = j.d_out;  // row offset comes from the device counter
-          launch_step(counted, j.t, rows_pg.nchunk, cs, row_ctr, j.L.I);
-          hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, cs, row_ctr);
-        } else {
-          launch_step(ps.s, j.t, rows_pg.nchunk, cs);
-        }
+      for (int r = 0; r < per; ++r) {
+        Program one;
+        one.nchunk = rows_pg.nchunk;
+        const size_t len = rows_pg.steps.size() / per;
+        one.steps.assign(rows_pg.steps.begin() + r * len, rows_pg.steps.begin() + (r + 1) * len);
+        run_eager(one, j.t, cs, true, row_ctr, j.L.I);
+        hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, cs, row_ctr);
       }
       hipGraph_t graph = nullptr;
       HIPX(hipStreamEndCapture(cs, &graph));
@@ -670,10 +744,13 @@ void launch_stages(const StageImage& im, const Step* d_steps, const int* d_tiles
     if (im.nsteps[k] == 0) continue;
     GroupArgs g{d_steps + im.step_off[k], d_tiles + im.tile_off[k], im.nsteps[k], t.xcd};
     dim3 grid(im.ntiles[k]), block(64 * t.wpb);
-    switch (t.V) {
-      case 1: hipLaunchKernelGGL(k_grouped<1>, grid, block, 0, st, g); break;
-      case 2: hipLaunchKernelGGL(k_grouped<2>, grid, block, 0, st, g); break;
-      default: hipLaunchKernelGGL(k_grouped<4>, grid, block, 0, st, g); break;
+    switch (t.V * 10 + t.U) {
+      case 14: hipLaunchKernelGGL((k_grouped<1, 4>), grid, block, 0, st, g); break;
+      case 18: hipLaunchKernelGGL((k_grouped<1, 8>), grid, block, 0, st, g); break;
+      case 24: hipLaunchKernelGGL((k_grouped<2, 4>), grid, block, 0, st, g); break;
+      case 28: hipLaunchKernelGGL((k_grouped<2, 8>), grid, block, 0, st, g); break;
+      case 44: hipLaunchKernelGGL((k_grouped<4, 4>), grid, block, 0, st, g); break;
+      default: hipLaunchKernelGGL((k_grouped<4, 8>), grid, block, 0, st, g); break;
     }
     HIPX(hipGetLastError());
   }
@@ -940,8 +1017,11 @@ int factor_launches_impl(int lattice, int m, const uint32_t* q, int nq, const ui
   Program pg;
   pg.nchunk = j.L.nchunk;
   add_rows(pg, j, 1, rows, -1, -1);
+  Program gathers;
+  gathers.nchunk = pg.nchunk;
   for (const PStep& ps : pg.steps)
-    if (ps.s.op == kOpGather) launch_step(ps.s, t, pg.nchunk, st);
+    if (ps.s.op == kOpGather) gathers.steps.push_back(ps);
+  run_eager(gathers, t, st);
   return CHROM_OK;
 }
 
