@@ -89,6 +89,7 @@ def main():
     ap.add_argument("--xcd-order", type=int, default=0)
     ap.add_argument("--unroll", type=int, default=0)
     ap.add_argument("--streams", type=int, default=0)
+    ap.add_argument("--fuse", type=int, default=0)
     ap.add_argument("--roofline-rows", type=int, default=10)
     ap.add_argument("--plain-instances", type=int, default=16)
     ap.add_argument("--no-plain", action="store_true")
@@ -117,7 +118,7 @@ def main():
     I = len(q) * len(p)
     tune = {"lanes_v": args.lanes_v, "targets_per_wave": args.targets_per_wave,
             "waves_per_block": args.waves_per_block, "xcd_order": args.xcd_order,
-            "unroll": args.unroll, "streams": args.streams}
+            "unroll": args.unroll, "streams": args.streams, "fuse": args.fuse}
     V = args.lanes_v or 2
     ipad = -(-I // (64 * V)) * 64 * V
 

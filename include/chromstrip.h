@@ -74,6 +74,8 @@ typedef struct chrom_tuning {
   int unroll;           /* source rows loaded ahead per wavefront: 4 or 8 (0 = 4) */
   int streams;          /* instance-chunk groups run on parallel streams, 1..4 (0 = 1);
                            graph and batched modes */
+  int fuse;             /* consecutive factors applied per launch as one precomputed
+                           product map, 1..3 (0 = 1) */
 } chrom_tuning;
 
 /* ------------------------------------------------------------------------
@@ -222,25 +224,37 @@ int64_t chromatic_rank(int m, int space, int i, const uint8_t* lab);
  * state of rank r into lab[m]. */
 int chromatic_unrank(int m, int space, int i, int64_t r, uint8_t* lab);
 
-/* Summary of the factor maps of (lattice, m), building them if needed. */
+/* Summary of the single-factor maps of (lattice, m), building them if
+ * needed. */
 typedef struct chrom_maps_info {
   int n_factors;            /* m forward factors T_1..T_m */
   int n_last;               /* m read-out factors (T_1^last..T_m^last, transposed) */
-  int n_codes;              /* coefficient codes in use */
-  int code_a[16], code_b[16]; /* code k means the coefficient a + b q */
+  int n_codes;              /* coefficient codes of the single factors */
   int64_t total_nnz;
   int64_t max_states;
 } chrom_maps_info;
 
 int chromatic_maps_info(int lattice, int m, chrom_maps_info* info);
 
+/* Factor family `fuse` (1 = the single factors T_1..T_m; k = 2, 3 = the
+ * products T_hi ... T_lo of k consecutive factors, lo = idx*k + 1,
+ * hi = min(m, lo + k - 1), used by tuning.fuse = k): number of factors and
+ * the coefficient table.  coef (may be NULL) receives n_codes x 4 int64
+ * values: code c means coef[4c] + coef[4c+1] q + coef[4c+2] q^2 + coef[4c+3] q^3.
+ * The table extends the single factors' table, code numbers unchanged. */
+int chromatic_family_info(int lattice, int m, int fuse, int* n_factors, int* n_codes, int64_t* coef);
+
 /* Copies one factor's map to caller buffers.  which = 0: forward factor
  * T_{idx+1} as target-major CSR (rows = states after the factor, entries =
  * source states before it).  which = 1: read-out factor T_{idx+1}^last,
  * transposed (rows = states before it, entries = states after it).
- * Entry word: bits 0..27 = column state rank, bits 28..31 = coefficient
+ * which = 2 or 3: factor idx of the fused family of that size.
+ * Entry word: bits 0..25 = column state rank, bits 26..31 = coefficient
  * code.  Sizes are returned through n_rows, n_cols, nnz; pass NULL buffers
- * to query sizes only.  row_ptr has n_rows+1 entries. */
+ * to query sizes only.  row_ptr has n_rows+1 entries.  The state numbering
+ * of the spaces between factors is internal (chosen for memory locality);
+ * the NCNNN space before the first and after the last factor of a row, and
+ * the read-out spaces, use the paper's order. */
 int chromatic_map_export(int lattice, int m, int which, int idx,
                          int64_t* n_rows, int64_t* n_cols, int64_t* nnz,
                          int32_t* row_ptr, uint32_t* entries);

@@ -25,7 +25,7 @@ class ChromError(RuntimeError):
 
 class Tuning(C.Structure):
     _fields_ = [("lanes_v", C.c_int), ("targets_per_wave", C.c_int), ("waves_per_block", C.c_int),
-                ("xcd_order", C.c_int), ("unroll", C.c_int), ("streams", C.c_int)]
+                ("xcd_order", C.c_int), ("unroll", C.c_int), ("streams", C.c_int), ("fuse", C.c_int)]
 
 
 class Job(C.Structure):
@@ -44,7 +44,6 @@ class Slot(C.Structure):
 
 class MapsInfo(C.Structure):
     _fields_ = [("n_factors", C.c_int), ("n_last", C.c_int), ("n_codes", C.c_int),
-                ("code_a", C.c_int * 16), ("code_b", C.c_int * 16),
                 ("total_nnz", C.c_int64), ("max_states", C.c_int64)]
 
 
@@ -72,6 +71,8 @@ _SIGS = {
     "chromatic_rank": (C.c_int64, [C.c_int, C.c_int, C.c_int, C.c_void_p]),
     "chromatic_unrank": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int64, C.c_void_p]),
     "chromatic_maps_info": (C.c_int, [C.c_int, C.c_int, C.POINTER(MapsInfo)]),
+    "chromatic_family_info": (C.c_int, [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                        C.c_void_p]),
     "chromatic_map_export": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int64),
                                        C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_void_p, C.c_void_p]),
     "chromatic_last_error": (C.c_char_p, []),
@@ -125,4 +126,5 @@ def tuning(t) -> "Tuning | None":
     if isinstance(t, Tuning):
         return t
     return Tuning(int(t.get("lanes_v", 0)), int(t.get("targets_per_wave", 0)), int(t.get("waves_per_block", 0)),
-                  int(t.get("xcd_order", 0)), int(t.get("unroll", 0)), int(t.get("streams", 0)))
+                  int(t.get("xcd_order", 0)), int(t.get("unroll", 0)), int(t.get("streams", 0)),
+                  int(t.get("fuse", 0)))

@@ -209,16 +209,26 @@ def unrank(m: int, r: int, space: int = _lib.SPACE_NCNNN, i: int = 0) -> tuple:
     return tuple(int(x) for x in lab)
 
 
+def family_info(lattice, m: int, fuse: int = 1) -> dict:
+    """Factor count and coefficient table of a factor family; codes are
+    polynomials (c0, c1, c2, c3) in q."""
+    nf, nc = C.c_int(), C.c_int()
+    coef = np.zeros(64 * 4, dtype=np.int64)
+    check(lib().chromatic_family_info(lattice_id(lattice), m, fuse, C.byref(nf), C.byref(nc), _ptr(coef)))
+    return dict(n_factors=nf.value, codes=[tuple(int(x) for x in coef[4 * c:4 * c + 4]) for c in range(nc.value)])
+
+
 def maps_info(lattice, m: int) -> dict:
     info = _lib.MapsInfo()
     check(lib().chromatic_maps_info(lattice_id(lattice), m, C.byref(info)))
     return dict(n_factors=info.n_factors, n_last=info.n_last, n_codes=info.n_codes,
-                codes=[(info.code_a[k], info.code_b[k]) for k in range(info.n_codes)],
+                codes=family_info(lattice, m, 1)["codes"],
                 total_nnz=int(info.total_nnz), max_states=int(info.max_states))
 
 
 def map_export(lattice, m: int, which: int, idx: int):
-    """(row_ptr int32[n_rows+1], cols int32[nnz], codes uint8[nnz], n_cols)."""
+    """(row_ptr int32[n_rows+1], cols int64[nnz], codes int64[nnz], n_cols);
+    which: 0 forward factor, 1 read-out factor (transposed), 2/3 fused family."""
     L = lib()
     nr, nc, nz = C.c_int64(), C.c_int64(), C.c_int64()
     check(L.chromatic_map_export(lattice_id(lattice), m, which, idx, C.byref(nr), C.byref(nc), C.byref(nz),
@@ -227,4 +237,4 @@ def map_export(lattice, m: int, which: int, idx: int):
     ent = np.zeros(max(nz.value, 1), dtype=np.uint32)
     check(L.chromatic_map_export(lattice_id(lattice), m, which, idx, None, None, None, _ptr(rp), _ptr(ent)))
     ent = ent[: nz.value]
-    return rp, (ent & ((1 << 28) - 1)).astype(np.int64), (ent >> 28).astype(np.int64), int(nc.value)
+    return rp, (ent & ((1 << 26) - 1)).astype(np.int64), (ent >> 26).astype(np.int64), int(nc.value)

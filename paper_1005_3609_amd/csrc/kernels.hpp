@@ -19,8 +19,9 @@
 
 namespace cs {
 
-constexpr uint32_t kEntSrcMask = (1u << 28) - 1;
-constexpr int kCodes = 16;
+constexpr uint32_t kEntSrcBits = 26;
+constexpr uint32_t kEntSrcMask = (1u << kEntSrcBits) - 1;
+constexpr int kCodes = 64;
 
 // ---------------------------------------------------------------------------
 // Vector helpers
@@ -243,7 +244,7 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           while (base + k + u >= row_end) flush();
-          accumulate<V>(acc, x[u], word[u] >> 28, p, a.ic, inst0);
+          accumulate<V>(acc, x[u], word[u] >> kEntSrcBits, p, a.ic, inst0);
         }
       }
       for (; k < n; ++k) {
@@ -251,7 +252,7 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
         uint32_t x[V];
         load_v<V>(in + static_cast<size_t>(word & kEntSrcMask) * W, x);
         while (base + k >= row_end) flush();
-        accumulate<V>(acc, x, word >> 28, p, a.ic, inst0);
+        accumulate<V>(acc, x, word >> kEntSrcBits, p, a.ic, inst0);
       }
     }
     while (row < r1) flush();
@@ -433,7 +434,7 @@ __global__ void __launch_bounds__(256) k_gather_plain(DevCsr csr, const uint32_t
   for (int e = beg; e < end; ++e) {
     const uint32_t w = csr.ent[e];
     const uint32_t x = in[w & kEntSrcMask];
-    const uint32_t code = w >> 28;
+    const uint32_t code = w >> kEntSrcBits;
     if (code == 0)
       acc = add_mod(acc, x, c.p);
     else if (code == 1)

@@ -12,7 +12,9 @@
 //   triangular  T_i = P_all V_i H_{i-1,i} H_{i,i+1}  (H's omitted at the ends)
 //   read-out    T_i^last = P_{j > i} D_i H_{i,i+1}   (H omitted for i = m)
 // Every coefficient is a + b q with small integers a, b; it is stored as a
-// code into a per-map-set table.
+// code into a per-map-set table.  Products of consecutive factors (fused
+// families) carry polynomial coefficients of degree up to the number of
+// factors multiplied.
 #include "maps.hpp"
 
 #include <algorithm>
@@ -318,21 +320,22 @@ void renumber(Csr& c, const std::vector<int32_t>& new_row, const std::vector<int
   c = std::move(out);
 }
 
-// Reader order for the spaces between the factors of one transfer row.  The
-// NCNNN space S_0 = S_m (input of T_1, output of T_m, space of the read-out
-// vector) keeps the paper's order.  Going backwards, S_{k} (k = m-1..1) is
-// ordered by the first target row of T_{k+1} -- in S_{k+1}'s order, already
-// fixed -- that reads it (ties by old rank; unread states last).  The rows of
-// T_{k+1} are then visited in an order that touches most sources for the
-// first time in increasing address order, and re-reads of a source follow
-// its first read closely, so they are served by the L2.  The numbering is
-// internal to the maps: every factor is renumbered consistently.
-void reader_order(MapSet& ms) {
-  const int m = ms.m;
-  if (m < 2) return;
-  std::vector<std::vector<int32_t>> perm(m + 1);  // perm[k][old] = new, for S_k
-  for (int k = m - 1; k >= 1; --k) {
-    const Csr& t = ms.fwd[k];  // T_{k+1}: rows in S_{k+1}, columns in S_k
+// Reader order for the spaces between consecutive factors F_1..F_n of one
+// transfer row.  The NCNNN space before F_1 and after F_n (the read-out
+// vector's space) keeps the paper's order.  Going backwards, the space
+// between F_k and F_{k+1} is ordered by the first target row of F_{k+1} --
+// in its own output order, already fixed -- that reads it (ties by old rank;
+// unread states last).  The rows of F_{k+1} are then visited in an order
+// that touches most sources for the first time in increasing address order,
+// and re-reads of a source follow its first read closely, so they are served
+// by the L2.  The numbering is internal to the maps: every factor is
+// renumbered consistently.
+void reader_order(std::vector<Csr>& facs) {
+  const int n = static_cast<int>(facs.size());
+  if (n < 2) return;
+  std::vector<std::vector<int32_t>> perm(n + 1);  // perm[k][old] = new, space after F_k
+  for (int k = n - 1; k >= 1; --k) {
+    const Csr& t = facs[k];  // F_{k+1}: rows in space k+1, columns in space k
     const int64_t ns = t.n_cols;
     std::vector<int64_t> first(ns, INT64_MAX);
     for (int64_t r = 0; r < t.n_rows; ++r) {
@@ -348,8 +351,136 @@ void reader_order(MapSet& ms) {
     perm[k].assign(ns, 0);
     for (int64_t pos = 0; pos < ns; ++pos) perm[k][order[pos]] = static_cast<int32_t>(pos);
   }
-  // fwd[k] = T_{k+1}: rows in S_{k+1}, columns in S_k
-  for (int k = 0; k < m; ++k) renumber(ms.fwd[k], perm[k + 1], perm[k]);
+  for (int k = 0; k < n; ++k) renumber(facs[k], perm[k + 1], perm[k]);
+}
+
+// Adds two polynomials / multiplies them (degrees stay <= kMaxDeg).
+Poly padd(const Poly& a, const Poly& b) {
+  Poly r;
+  for (int k = 0; k <= kMaxDeg; ++k) r.c[k] = a.c[k] + b.c[k];
+  return r;
+}
+Poly pmul(const Poly& a, const Poly& b) {
+  int64_t full[2 * kMaxDeg + 1] = {0};
+  for (int i = 0; i <= kMaxDeg; ++i)
+    for (int j = 0; j <= kMaxDeg; ++j) full[i + j] += a.c[i] * b.c[j];
+  for (int k = kMaxDeg + 1; k <= 2 * kMaxDeg; ++k)
+    if (full[k] != 0) throw std::runtime_error("coefficient degree above 3");
+  Poly r;
+  for (int k = 0; k <= kMaxDeg; ++k) r.c[k] = full[k];
+  return r;
+}
+
+// F = T_hi ... T_lo from the single factors (any consistent numbering).
+// Entries carry polynomials; entries that cancel exactly are dropped.
+struct PolyCsr {
+  int64_t n_rows = 0, n_cols = 0;
+  std::vector<int64_t> row_ptr;
+  std::vector<int32_t> col;
+  std::vector<Poly> coef;
+};
+
+PolyCsr to_poly(const Csr& c, const std::vector<Poly>& codes) {
+  PolyCsr p;
+  p.n_rows = c.n_rows;
+  p.n_cols = c.n_cols;
+  p.row_ptr.assign(c.row_ptr.begin(), c.row_ptr.end());
+  p.col.resize(c.ent.size());
+  p.coef.resize(c.ent.size());
+  for (size_t e = 0; e < c.ent.size(); ++e) {
+    p.col[e] = static_cast<int32_t>(c.ent[e] & kSrcMask);
+    p.coef[e] = codes[c.ent[e] >> kSrcBits];
+  }
+  return p;
+}
+
+// (T · P): row r of T combines rows of P.
+PolyCsr compose(const PolyCsr& t, const PolyCsr& p, int threads) {
+  PolyCsr out;
+  out.n_rows = t.n_rows;
+  out.n_cols = p.n_cols;
+  std::vector<std::vector<std::pair<int32_t, Poly>>> rows(t.n_rows);
+  parallel_for(t.n_rows, threads, [&](int, int64_t lo, int64_t hi) {
+    std::vector<std::pair<int32_t, Poly>> acc;
+    for (int64_t r = lo; r < hi; ++r) {
+      acc.clear();
+      for (int64_t e = t.row_ptr[r]; e < t.row_ptr[r + 1]; ++e) {
+        const int32_t mid = t.col[e];
+        for (int64_t f = p.row_ptr[mid]; f < p.row_ptr[mid + 1]; ++f) {
+          const Poly term = pmul(t.coef[e], p.coef[f]);
+          bool found = false;
+          for (auto& kv : acc)
+            if (kv.first == p.col[f]) {
+              kv.second = padd(kv.second, term);
+              found = true;
+              break;
+            }
+          if (!found) acc.emplace_back(p.col[f], term);
+        }
+      }
+      auto& dst = rows[r];
+      for (auto& kv : acc)
+        if (!kv.second.zero()) dst.push_back(kv);
+      std::sort(dst.begin(), dst.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+    }
+  });
+  out.row_ptr.assign(t.n_rows + 1, 0);
+  for (int64_t r = 0; r < t.n_rows; ++r) out.row_ptr[r + 1] = out.row_ptr[r] + static_cast<int64_t>(rows[r].size());
+  out.col.resize(out.row_ptr.back());
+  out.coef.resize(out.row_ptr.back());
+  for (int64_t r = 0; r < t.n_rows; ++r) {
+    int64_t w = out.row_ptr[r];
+    for (auto& kv : rows[r]) {
+      out.col[w] = kv.first;
+      out.coef[w] = kv.second;
+      ++w;
+    }
+  }
+  return out;
+}
+
+std::unique_ptr<Family> build_family(const MapSet& ms, int k) {
+  const int m = ms.m;
+  const int threads = std::max(1u, std::thread::hardware_concurrency());
+  auto fam = std::make_unique<Family>();
+  fam->k = k;
+  fam->codes = ms.codes;
+  std::map<Poly, int> code_of;
+  for (size_t c = 0; c < ms.codes.size(); ++c) code_of[ms.codes[c]] = static_cast<int>(c);
+  std::vector<PolyCsr> prods;
+  for (int lo = 1; lo <= m; lo += k) {
+    const int hi = std::min(m, lo + k - 1);
+    PolyCsr p = to_poly(ms.fwd[lo - 1], ms.codes);
+    for (int j = lo + 1; j <= hi; ++j) p = compose(to_poly(ms.fwd[j - 1], ms.codes), p, threads);
+    fam->lo.push_back(lo);
+    fam->hi.push_back(hi);
+    prods.push_back(std::move(p));
+  }
+  // new coefficient polynomials get codes after the base table, in order
+  std::map<Poly, int> fresh;
+  for (const PolyCsr& p : prods)
+    for (const Poly& c : p.coef)
+      if (!code_of.count(c)) fresh[c] = 0;
+  for (auto& kv : fresh) {
+    if (static_cast<int>(fam->codes.size()) >= kMaxCodes)
+      throw std::runtime_error("more than 64 distinct coefficients in a fused family");
+    code_of[kv.first] = static_cast<int>(fam->codes.size());
+    fam->codes.push_back(kv.first);
+  }
+  for (const PolyCsr& p : prods) {
+    Csr c;
+    c.n_rows = p.n_rows;
+    c.n_cols = p.n_cols;
+    if (p.row_ptr.back() > INT32_MAX) throw std::runtime_error("too many entries in a fused factor");
+    c.row_ptr.assign(p.row_ptr.begin(), p.row_ptr.end());
+    c.ent.resize(p.col.size());
+    for (size_t e = 0; e < p.col.size(); ++e)
+      c.ent[e] = static_cast<uint32_t>(p.col[e]) | (static_cast<uint32_t>(code_of[p.coef[e]]) << kSrcBits);
+    fam->fac.push_back(std::move(c));
+  }
+  const char* order = std::getenv("CHROMSTRIP_STATE_ORDER");
+  if (!(order && std::string(order) == "paper")) reader_order(fam->fac);
+  return fam;
 }
 
 }  // namespace
@@ -366,6 +497,16 @@ int64_t MapSet::max_states() const {
   for (auto& c : fwd) s = std::max({s, c.n_rows, c.n_cols});
   for (auto& c : last) s = std::max({s, c.n_rows, c.n_cols});
   return s;
+}
+
+const Family& MapSet::family(int k) const {
+  std::lock_guard<std::mutex> lk(fam_mu_);
+  auto it = fam_.find(k);
+  if (it != fam_.end()) return *it->second;
+  auto f = build_family(*this, k);
+  const Family& ref = *f;
+  fam_.emplace(k, std::move(f));
+  return ref;
 }
 
 size_t MapSet::host_bytes() const {
@@ -394,20 +535,19 @@ std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads) {
   // Codes: +1 -> 0, -1 -> 1, then every other coefficient in key order.
   int key_to_code[kKeys];
   std::fill(key_to_code, key_to_code + kKeys, -1);
-  int n = 0;
   auto add = [&](int key) {
     if (key_to_code[key] >= 0) return;
-    if (n >= kMaxCodes) throw std::runtime_error("more than 16 distinct coefficients");
-    key_to_code[key] = n;
-    ms->code_a[n] = key % 33 - kKeyA;
-    ms->code_b[n] = key / 33 - kKeyB;
-    ++n;
+    if (static_cast<int>(ms->codes.size()) >= kMaxCodes) throw std::runtime_error("too many distinct coefficients");
+    key_to_code[key] = static_cast<int>(ms->codes.size());
+    Poly p;
+    p.c[0] = key % 33 - kKeyA;
+    p.c[1] = key / 33 - kKeyB;
+    ms->codes.push_back(p);
   };
   add(coef_key(1, 0));
   add(coef_key(-1, 0));
   for (int k = 0; k < kKeys; ++k)
     if ((seen[k / 64].load() >> (k % 64)) & 1ull) add(k);
-  ms->n_codes = n;
   auto finish = [&](Csr& c, const std::vector<uint16_t>& keys) {
     for (size_t e = 0; e < c.ent.size(); ++e)
       c.ent[e] |= static_cast<uint32_t>(key_to_code[keys[e]]) << kSrcBits;
@@ -417,7 +557,7 @@ std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads) {
     finish(ms->last[i], lkeys[i]);
   }
   const char* order = std::getenv("CHROMSTRIP_STATE_ORDER");
-  if (!(order && std::string(order) == "paper")) reader_order(*ms);
+  if (!(order && std::string(order) == "paper")) reader_order(ms->fwd);
   return ms;
 }
 

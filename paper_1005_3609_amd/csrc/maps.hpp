@@ -1,9 +1,13 @@
 // Factor maps: each per-site factor of the sparse transfer matrix as a
-// sparse integer matrix over ranked states.
+// sparse integer matrix over ranked states, and products of consecutive
+// factors ("fused" families) for kernels that skip writing the states in
+// between.
 #pragma once
 
 #include <cstdint>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "states.hpp"
@@ -12,17 +16,44 @@ namespace cs {
 
 enum Lattice { kSquare = 0, kTriangular = 1 };
 
-constexpr int kMaxCodes = 16;
-constexpr uint32_t kSrcBits = 28;
+constexpr int kMaxCodes = 64;
+constexpr uint32_t kSrcBits = 26;
 constexpr uint32_t kSrcMask = (1u << kSrcBits) - 1;
+constexpr int kMaxDeg = 3;  // coefficient polynomials in q up to q^3 (three fused factors)
+constexpr int kMaxFuse = 3;
 
-// Compressed sparse rows.  Entry word: column state rank in the low 28 bits,
-// coefficient code in the high 4 bits.
+// Compressed sparse rows.  Entry word: column state rank in the low 26 bits,
+// coefficient code in the high 6 bits.
 struct Csr {
   int64_t n_rows = 0, n_cols = 0;
   std::vector<int32_t> row_ptr;   // n_rows + 1
   std::vector<uint32_t> ent;      // nnz
   int64_t nnz() const { return static_cast<int64_t>(ent.size()); }
+};
+
+// Coefficient polynomial c[0] + c[1] q + c[2] q^2 + c[3] q^3.
+struct Poly {
+  int64_t c[kMaxDeg + 1] = {0, 0, 0, 0};
+  bool operator<(const Poly& o) const {
+    for (int k = kMaxDeg; k >= 0; --k)
+      if (c[k] != o.c[k]) return c[k] < o.c[k];
+    return false;
+  }
+  bool operator==(const Poly& o) const {
+    for (int k = 0; k <= kMaxDeg; ++k)
+      if (c[k] != o.c[k]) return false;
+    return true;
+  }
+  bool zero() const { return c[0] == 0 && c[1] == 0 && c[2] == 0 && c[3] == 0; }
+};
+
+// Products T_hi ... T_lo of consecutive forward factors, covering 1..m.
+// Family k = 1 is the single factors themselves.
+struct Family {
+  int k = 1;
+  std::vector<Csr> fac;           // rows: states after T_hi; columns: states before T_lo
+  std::vector<int> lo, hi;        // 1-based site ranges
+  std::vector<Poly> codes;        // extends the base table (same numbers for shared codes)
 };
 
 struct MapSet {
@@ -34,15 +65,20 @@ struct MapSet {
   // columns = states after it (L_i).  Applied for i = m..1 to e_0 it gives
   // the read-out vector w = T_last^T e_0 over the NCNNN states.
   std::vector<Csr> last;
-  int n_codes = 0;
-  int code_a[kMaxCodes] = {0}, code_b[kMaxCodes] = {0};  // code k: a + b q
+  std::vector<Poly> codes;        // base table: codes of fwd and last (degree <= 1)
   int64_t total_nnz() const;
   int64_t max_states() const;
   size_t host_bytes() const;
+  // Fused families, built on first request (thread safe).
+  const Family& family(int k) const;
+
+ private:
+  mutable std::mutex fam_mu_;
+  mutable std::map<int, std::unique_ptr<Family>> fam_;
 };
 
-// Builds every map of (lattice, m); threads = 0 uses the hardware count.
-// Throws std::runtime_error on failure.
+// Builds every single-factor map of (lattice, m); threads = 0 uses the
+// hardware count.  Throws std::runtime_error on failure.
 std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads = 0);
 
 // Host-side map cache (thread safe): built on first request.

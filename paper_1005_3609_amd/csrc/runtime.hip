@@ -75,16 +75,41 @@ size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 // ---------------------------------------------------------------------------
 // Device copies of the factor maps, one per (device, lattice, m)
 // ---------------------------------------------------------------------------
+struct DevFamily {
+  void* base = nullptr;
+  std::vector<DevCsr> fac;
+  std::vector<Poly> codes;   // extends the base table
+};
+
 struct DevMaps {
   void* base = nullptr;
   size_t bytes = 0;
   DevCsr fwd[kMaxM];
   DevCsr last[kMaxM];
-  int n_codes = 0;
-  int code_a[kMaxCodes], code_b[kMaxCodes];
+  std::vector<Poly> codes;   // base table of fwd and last
   int64_t s_nc = 0;    // NCNNN states
   int64_t s_max = 0;   // largest space
+  int lattice = 0, m = 0;
+  // fused families (k >= 2), uploaded on first use
+  mutable std::mutex fam_mu;
+  mutable std::map<int, std::unique_ptr<DevFamily>> fam;
 };
+
+size_t csr_bytes(const Csr& c) { return align_up(c.row_ptr.size() * 4) + align_up(std::max<size_t>(c.ent.size(), 1) * 4); }
+
+// Copies one CSR into device memory at `cur` (advanced).
+void upload_csr(const Csr& c, DevCsr& d, char*& cur) {
+  int32_t* rp = reinterpret_cast<int32_t*>(cur);
+  HIPX(hipMemcpy(rp, c.row_ptr.data(), c.row_ptr.size() * 4, hipMemcpyHostToDevice));
+  cur += align_up(c.row_ptr.size() * 4);
+  uint32_t* en = reinterpret_cast<uint32_t*>(cur);
+  if (!c.ent.empty()) HIPX(hipMemcpy(en, c.ent.data(), c.ent.size() * 4, hipMemcpyHostToDevice));
+  cur += align_up(std::max<size_t>(c.ent.size(), 1) * 4);
+  d.row_ptr = rp;
+  d.ent = en;
+  d.n_rows = static_cast<int>(c.n_rows);
+  d.n_cols = static_cast<int>(c.n_cols);
+}
 
 std::mutex g_dev_mu;
 std::map<std::tuple<int, int, int>, std::unique_ptr<DevMaps>> g_dev;
@@ -99,36 +124,47 @@ const DevMaps& dev_maps(int lattice, int m) {
   const MapSet& ms = get_maps(lattice, m);
   auto dm = std::make_unique<DevMaps>();
   size_t bytes = 0;
-  auto sz = [&](const Csr& c) { return align_up(c.row_ptr.size() * 4) + align_up(std::max<size_t>(c.ent.size(), 1) * 4); };
-  for (int i = 0; i < m; ++i) bytes += sz(ms.fwd[i]) + sz(ms.last[i]);
+  for (int i = 0; i < m; ++i) bytes += csr_bytes(ms.fwd[i]) + csr_bytes(ms.last[i]);
   void* base = nullptr;
   if (hipMalloc(&base, bytes) != hipSuccess) throw MemError("device allocation of factor maps failed");
   char* cur = static_cast<char*>(base);
-  auto up = [&](const Csr& c, DevCsr& d) {
-    int32_t* rp = reinterpret_cast<int32_t*>(cur);
-    HIPX(hipMemcpy(rp, c.row_ptr.data(), c.row_ptr.size() * 4, hipMemcpyHostToDevice));
-    cur += align_up(c.row_ptr.size() * 4);
-    uint32_t* en = reinterpret_cast<uint32_t*>(cur);
-    if (!c.ent.empty()) HIPX(hipMemcpy(en, c.ent.data(), c.ent.size() * 4, hipMemcpyHostToDevice));
-    cur += align_up(std::max<size_t>(c.ent.size(), 1) * 4);
-    d.row_ptr = rp;
-    d.ent = en;
-    d.n_rows = static_cast<int>(c.n_rows);
-    d.n_cols = static_cast<int>(c.n_cols);
-  };
   for (int i = 0; i < m; ++i) {
-    up(ms.fwd[i], dm->fwd[i]);
-    up(ms.last[i], dm->last[i]);
+    upload_csr(ms.fwd[i], dm->fwd[i], cur);
+    upload_csr(ms.last[i], dm->last[i], cur);
   }
   dm->base = base;
   dm->bytes = bytes;
-  dm->n_codes = ms.n_codes;
-  std::copy(ms.code_a, ms.code_a + kMaxCodes, dm->code_a);
-  std::copy(ms.code_b, ms.code_b + kMaxCodes, dm->code_b);
+  dm->codes = ms.codes;
+  dm->lattice = lattice;
+  dm->m = m;
   dm->s_nc = ncnnn_count(m);
   dm->s_max = ms.max_states();
   const DevMaps& ref = *dm;
   g_dev.emplace(key, std::move(dm));
+  return ref;
+}
+
+// Device copy of fused family k (k = 1: the single factors).
+const DevFamily& dev_family(const DevMaps& dm, int k) {
+  std::lock_guard<std::mutex> lk(dm.fam_mu);
+  auto it = dm.fam.find(k);
+  if (it != dm.fam.end()) return *it->second;
+  auto df = std::make_unique<DevFamily>();
+  if (k == 1) {
+    df->fac.assign(dm.fwd, dm.fwd + dm.m);
+    df->codes = dm.codes;
+  } else {
+    const Family& f = get_maps(dm.lattice, dm.m).family(k);
+    size_t bytes = 0;
+    for (const Csr& c : f.fac) bytes += csr_bytes(c);
+    if (hipMalloc(&df->base, bytes) != hipSuccess) throw MemError("device allocation of fused maps failed");
+    char* cur = static_cast<char*>(df->base);
+    df->fac.resize(f.fac.size());
+    for (size_t i = 0; i < f.fac.size(); ++i) upload_csr(f.fac[i], df->fac[i], cur);
+    df->codes = f.codes;
+  }
+  const DevFamily& ref = *df;
+  dm.fam.emplace(k, std::move(df));
   return ref;
 }
 
@@ -209,12 +245,15 @@ std::vector<Inst> make_instances(const uint32_t* q, int nq, const uint32_t* p, i
   return v;
 }
 
-uint32_t coef_mod(int a, int b, uint32_t q, uint32_t p) {
-  int64_t am = a % static_cast<int64_t>(p);
-  if (am < 0) am += p;
-  int64_t bm = b % static_cast<int64_t>(p);
-  if (bm < 0) bm += p;
-  return static_cast<uint32_t>((static_cast<uint64_t>(am) + static_cast<uint64_t>(bm) * q) % p);
+// c0 + c1 q + c2 q^2 + c3 q^3 mod p (Horner, every step reduced).
+uint32_t coef_mod(const Poly& c, uint32_t q, uint32_t p) {
+  uint64_t acc = 0;
+  for (int k = kMaxDeg; k >= 0; --k) {
+    int64_t ck = c.c[k] % static_cast<int64_t>(p);
+    if (ck < 0) ck += p;
+    acc = (acc * q + static_cast<uint64_t>(ck)) % p;
+  }
+  return static_cast<uint32_t>(acc);
 }
 
 uint32_t shoup_of(uint32_t c, uint32_t p) {
@@ -225,7 +264,7 @@ uint32_t shoup_of(uint32_t c, uint32_t p) {
 // Tuning and workspace layout
 // ---------------------------------------------------------------------------
 struct Tune {
-  int V = 2, rpw = 8, wpb = 4, xcd = 0, U = 4, streams = 1;
+  int V = 2, rpw = 8, wpb = 4, xcd = 0, U = 4, streams = 1, fuse = 1;
 };
 
 Tune resolve(const chrom_tuning* t) {
@@ -240,6 +279,8 @@ Tune resolve(const chrom_tuning* t) {
   if (t->streams) r.streams = t->streams;
   if (r.U != 4 && r.U != 8) throw ArgError("unroll must be 4 or 8");
   if (r.streams < 1 || r.streams > 4) throw ArgError("streams must be in 1..4");
+  if (t->fuse) r.fuse = t->fuse;
+  if (r.fuse < 1 || r.fuse > kMaxFuse) throw ArgError("fuse must be in 1..3");
   if (r.V != 1 && r.V != 2 && r.V != 4) throw ArgError("lanes_v must be 1, 2 or 4");
   if (r.rpw < 1 || r.rpw > 63) throw ArgError("targets_per_wave must be in 1..63");
   if (r.wpb != 1 && r.wpb != 2 && r.wpb != 4 && r.wpb != 8) throw ArgError("waves_per_block must be 1, 2, 4 or 8");
@@ -298,7 +339,8 @@ JobLayout job_layout(int lattice, int m, int I, const Tune& t, int ncodes, int r
 
 // Constants of a job: p, pinv, r1, cval[ncodes][ipad], cshp[...] as one
 // host image laid out like the workspace region [p .. cshp].
-std::vector<uint32_t> const_image(const JobLayout& L, const std::vector<Inst>& inst, const DevMaps& dm) {
+std::vector<uint32_t> const_image(const JobLayout& L, const std::vector<Inst>& inst,
+                                  const std::vector<Poly>& codes) {
   const size_t base = L.p;
   std::vector<uint32_t> img((L.cshp + static_cast<size_t>(kMaxCodes) * L.ipad * 4 - base) / 4, 0);
   auto at = [&](size_t off) { return img.data() + (off - base) / 4; };
@@ -312,8 +354,8 @@ std::vector<uint32_t> const_image(const JobLayout& L, const std::vector<Inst>& i
     p[k] = in.p;
     pinv[k] = neg_inv_2_32(in.p);
     r1[k] = static_cast<uint32_t>((uint64_t(1) << 32) % in.p);
-    for (int c = 0; c < dm.n_codes; ++c) {
-      uint32_t v = coef_mod(dm.code_a[c], dm.code_b[c], in.q, in.p);
+    for (size_t c = 0; c < codes.size(); ++c) {
+      uint32_t v = coef_mod(codes[c], in.q, in.p);
       cv[static_cast<size_t>(c) * L.ipad + k] = v;
       cs[static_cast<size_t>(c) * L.ipad + k] = shoup_of(v, in.p);
     }
@@ -378,6 +420,7 @@ struct Program {
 
 struct JobCtx {
   const DevMaps* dm;
+  const DevFamily* fam;   // forward factors (single or fused) and their code table
   JobLayout L;
   JobPtrs P;
   Tune t;
@@ -470,20 +513,22 @@ int add_setup(Program& pg, const JobCtx& j) {
 }
 
 // Rows: out rows r = r_first..r_last (0-based; row r holds P of m x (r+1)),
-// each x <- T_m ... T_1 x with the read-out fused into T_m, then a reduce.
+// each x <- F_n ... F_1 x over the family's factors (F = one factor T_i, or
+// a product of consecutive ones), the read-out fused into F_n, then a reduce.
 // `after` is the step the first factor waits for; `prev_reduce` the last
 // reduce issued before (its partials are overwritten by the next T_m).
 void add_rows(Program& pg, const JobCtx& j, int r_first, int r_last, int after, int prev_reduce) {
   const JobLayout& L = j.L;
   const long cs_x = static_cast<long>(L.s_max) * L.W;
+  const int nf = static_cast<int>(j.fam->fac.size());
   for (int r = r_first; r <= r_last; ++r) {
-    const long done_gathers = static_cast<long>(r - 1) * L.m;
+    const long done_gathers = static_cast<long>(r - 1) * nf;
     uint32_t* cur = (done_gathers % 2 == 0) ? j.P.x0 : j.P.x1;
     uint32_t* oth = (cur == j.P.x0) ? j.P.x1 : j.P.x0;
     int tm = -1;
-    for (int i = 1; i <= L.m; ++i) {
-      const bool fused = (i == L.m);
-      Step g = gather_step(j, j.dm->fwd[i - 1], cur, oth, cs_x, fused);
+    for (int i = 1; i <= nf; ++i) {
+      const bool fused = (i == nf);
+      Step g = gather_step(j, j.fam->fac[i - 1], cur, oth, cs_x, fused);
       tm = push(pg, g, after, fused ? prev_reduce : -1);
       after = tm;
       std::swap(cur, oth);
@@ -641,14 +686,15 @@ void run_graph(const JobCtx& j, int n_max, int* row_ctr, void* ws, hipStream_t s
   (void)red;
   run_eager(setup, j.t, st);
   if (n_max <= 1) return;
-  const int per = (j.L.m % 2 == 1) ? 2 : 1;
+  const int per = (static_cast<int>(j.fam->fac.size()) % 2 == 1) ? 2 : 1;
   const int rows = n_max - 1;
   const int replays = rows / per;
   const int tail = rows - replays * per;
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, row_ctr, 1);
   HIPX(hipGetLastError());
   if (replays > 0) {
-    GraphKey key{ws, j.d_out, j.L.lattice, j.L.m, j.L.I, j.t.V, j.t.rpw, j.t.wpb, j.t.xcd * 100 + j.t.U * 10 + j.t.streams, per};
+    GraphKey key{ws, j.d_out, j.L.lattice, j.L.m, j.L.I, j.t.V, j.t.rpw, j.t.wpb,
+                 j.t.fuse * 1000 + j.t.xcd * 100 + j.t.U * 10 + j.t.streams, per};
     hipGraphExec_t exec = nullptr;
     {
       std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -828,7 +874,11 @@ void run_grouped(const std::vector<const Program*>& progs, const Tune& t, void* 
   HIPX(hipGraphLaunch(exec, st));
 }
 
-int strip_program_len(int m, int n_max) { return n_max < 1 ? 0 : (m + 5) + (n_max - 1) * (m + 2); }
+int n_factors(int m, int fuse) { return (m + fuse - 1) / fuse; }
+
+int strip_program_len(int m, int fuse, int n_max) {
+  return n_max < 1 ? 0 : (m + 5) + (n_max - 1) * (n_factors(m, fuse) + 2);
+}
 
 // ---------------------------------------------------------------------------
 // Plain per-instance path
@@ -863,8 +913,8 @@ void run_plain(const DevMaps& dm, int lattice, int m, int n_max, const std::vect
     PlainConsts c{};
     c.p = inst[k].p;
     c.pinv = neg_inv_2_32(c.p);
-    for (int code = 0; code < dm.n_codes; ++code) {
-      c.cval[code] = coef_mod(dm.code_a[code], dm.code_b[code], inst[k].q, c.p);
+    for (size_t code = 0; code < dm.codes.size(); ++code) {
+      c.cval[code] = coef_mod(dm.codes[code], inst[k].q, c.p);
       c.cshp[code] = shoup_of(c.cval[code], c.p);
     }
     const uint32_t r1 = static_cast<uint32_t>((uint64_t(1) << 32) % c.p);
@@ -905,7 +955,7 @@ size_t workspace_bytes(int lattice, int m, int I, int n_max_hint, int mode, cons
   JobLayout L = job_layout(lattice, m, I, t, kMaxCodes, rows_tile_of(t));
   size_t b = L.bytes + 256;  // + graph row counter
   if (mode == CHROM_MODE_GROUPED) {
-    const long len = strip_program_len(m, n_max_hint);
+    const long len = strip_program_len(m, t.fuse, n_max_hint);
     b += stage_bytes(L.nchunk * len, len);
   }
   return b;
@@ -931,11 +981,12 @@ int strip_async_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, c
   }
   JobCtx j;
   j.dm = &dm;
+  j.fam = &dev_family(dm, t.fuse);
   j.t = t;
   j.L = job_layout(lattice, m, I, t, kMaxCodes, rows_tile_of(t));
   j.P = job_ptrs(j.L, ws);
   j.d_out = d_out;
-  std::vector<uint32_t> img = const_image(j.L, inst, dm);
+  std::vector<uint32_t> img = const_image(j.L, inst, j.fam->codes);
   upload(static_cast<char*>(ws) + j.L.p, img.data(), img.size() * 4, st);
   int* row_ctr = reinterpret_cast<int*>(static_cast<char*>(ws) + j.L.bytes);
   if (mode == CHROM_MODE_BATCHED) {
@@ -1010,6 +1061,7 @@ int factor_launches_impl(int lattice, int m, const uint32_t* q, int nq, const ui
   const DevMaps& dm = dev_maps(lattice, m);
   JobCtx j;
   j.dm = &dm;
+  j.fam = &dev_family(dm, t.fuse);
   j.t = t;
   j.L = job_layout(lattice, m, I, t, kMaxCodes, rows_tile_of(t));
   j.P = job_ptrs(j.L, ws);
@@ -1047,8 +1099,8 @@ BatchPlan batch_plan(const chrom_job* jobs, int njobs, const Tune& t) {
     bp.layouts.push_back(L);
     bp.job_off.push_back(off);
     off += align_up(L.bytes);
-    bp.nsteps += static_cast<long>(L.nchunk) * strip_program_len(jb.m, jb.n_max);
-    bp.nstages = std::max<long>(bp.nstages, strip_program_len(jb.m, jb.n_max));
+    bp.nsteps += static_cast<long>(L.nchunk) * strip_program_len(jb.m, t.fuse, jb.n_max);
+    bp.nstages = std::max<long>(bp.nstages, strip_program_len(jb.m, t.fuse, jb.n_max));
   }
   bp.queue_off = off;
   bp.bytes = off + stage_bytes(bp.nsteps, bp.nstages);
@@ -1071,13 +1123,14 @@ int batch_impl(const chrom_job* jobs, int njobs, const chrom_tuning* tune, void*
     const DevMaps& dm = dev_maps(jb.lattice, jb.m);
     JobCtx j;
     j.dm = &dm;
+    j.fam = &dev_family(dm, t.fuse);
     j.t = t;
     j.L = bp.layouts[k];
     void* base = static_cast<char*>(ws) + bp.job_off[k];
     j.P = job_ptrs(j.L, base);
     j.d_out = jb.d_out;
     if (jb.n_max > 0) {
-      std::vector<uint32_t> img = const_image(j.L, inst, dm);
+      std::vector<uint32_t> img = const_image(j.L, inst, j.fam->codes);
       upload(static_cast<char*>(base) + j.L.p, img.data(), img.size() * 4, st);
     }
     progs[k] = strip_program(j, jb.n_max);
@@ -1132,6 +1185,7 @@ int server_step_impl(chrom_slot* slots, int nslots, int rows, const chrom_tuning
     const DevMaps& dm = dev_maps(sl.lattice, sl.m);
     JobCtx j;
     j.dm = &dm;
+    j.fam = &dev_family(dm, t.fuse);
     j.t = t;
     j.L = L;
     j.P = job_ptrs(L, sl.d_state);
@@ -1141,7 +1195,7 @@ int server_step_impl(chrom_slot* slots, int nslots, int rows, const chrom_tuning
     int last_row = std::min(sl.n_max - 1, first + rows - 1);  // 0-based out rows to produce
     if (first == 0) {
       std::vector<Inst> inst = make_instances(sl.q_points, sl.nq, sl.primes, sl.np);
-      std::vector<uint32_t> img = const_image(L, inst, dm);
+      std::vector<uint32_t> img = const_image(L, inst, j.fam->codes);
       upload(static_cast<char*>(sl.d_state) + L.p, img.data(), img.size() * 4, st);
       int red = add_setup(progs[k], j);
       if (last_row >= 1) add_rows(progs[k], j, 1, last_row, red, red);
@@ -1349,13 +1403,24 @@ int chromatic_maps_info(int lattice, int m, chrom_maps_info* info) {
     const MapSet& ms = get_maps(lattice, m);
     info->n_factors = m;
     info->n_last = m;
-    info->n_codes = ms.n_codes;
-    for (int k = 0; k < 16; ++k) {
-      info->code_a[k] = ms.code_a[k];
-      info->code_b[k] = ms.code_b[k];
-    }
+    info->n_codes = static_cast<int>(ms.codes.size());
     info->total_nnz = ms.total_nnz();
     info->max_states = ms.max_states();
+    return CHROM_OK;
+  });
+}
+
+int chromatic_family_info(int lattice, int m, int fuse, int* n_factors, int* n_codes, int64_t* coef) {
+  return guarded([&] {
+    check_args(lattice, m, 0);
+    if (fuse < 1 || fuse > kMaxFuse) throw ArgError("fuse must be in 1..3");
+    const MapSet& ms = get_maps(lattice, m);
+    const std::vector<Poly>& codes = fuse == 1 ? ms.codes : ms.family(fuse).codes;
+    if (n_factors) *n_factors = fuse == 1 ? m : static_cast<int>(ms.family(fuse).fac.size());
+    if (n_codes) *n_codes = static_cast<int>(codes.size());
+    if (coef)
+      for (size_t c = 0; c < codes.size(); ++c)
+        for (int k = 0; k <= kMaxDeg; ++k) coef[c * (kMaxDeg + 1) + k] = codes[c].c[k];
     return CHROM_OK;
   });
 }
@@ -1364,15 +1429,22 @@ int chromatic_map_export(int lattice, int m, int which, int idx, int64_t* n_rows
                          int32_t* row_ptr, uint32_t* entries) {
   return guarded([&] {
     check_args(lattice, m, 0);
-    if (which != 0 && which != 1) throw ArgError("which must be 0 or 1");
-    if (idx < 0 || idx >= m) throw ArgError("idx out of range");
+    if (which < 0 || which > 3) throw ArgError("which must be 0, 1, 2 or 3");
     const MapSet& ms = get_maps(lattice, m);
-    const Csr& c = which == 0 ? ms.fwd[idx] : ms.last[idx];
-    if (n_rows) *n_rows = c.n_rows;
-    if (n_cols) *n_cols = c.n_cols;
-    if (nnz) *nnz = c.nnz();
-    if (row_ptr) std::memcpy(row_ptr, c.row_ptr.data(), c.row_ptr.size() * 4);
-    if (entries && !c.ent.empty()) std::memcpy(entries, c.ent.data(), c.ent.size() * 4);
+    const Csr* c = nullptr;
+    if (which <= 1) {
+      if (idx < 0 || idx >= m) throw ArgError("idx out of range");
+      c = which == 0 ? &ms.fwd[idx] : &ms.last[idx];
+    } else {
+      const Family& f = ms.family(which);
+      if (idx < 0 || idx >= static_cast<int>(f.fac.size())) throw ArgError("idx out of range");
+      c = &f.fac[idx];
+    }
+    if (n_rows) *n_rows = c->n_rows;
+    if (n_cols) *n_cols = c->n_cols;
+    if (nnz) *nnz = c->nnz();
+    if (row_ptr) std::memcpy(row_ptr, c->row_ptr.data(), c->row_ptr.size() * 4);
+    if (entries && !c->ent.empty()) std::memcpy(entries, c->ent.data(), c->ent.size() * 4);
     return CHROM_OK;
   });
 }

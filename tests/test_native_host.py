@@ -93,12 +93,24 @@ def _apply(csr, cvals, x, p):
     return out % p
 
 
-def _run_maps(lat, m, n_max, qs, ps):
-    info = api.maps_info(lat, m)
+def _eval_codes(codes, qs, ps):
+    """coefficient polynomial of every code at every instance, mod p (Horner)"""
+    out = []
+    for c in codes:
+        acc = np.zeros_like(qs)
+        for k in range(len(c) - 1, -1, -1):
+            acc = (acc * (qs % ps) + (c[k] % ps)) % ps
+        out.append(acc)
+    return np.stack(out)
+
+
+def _run_maps(lat, m, n_max, qs, ps, fuse=1):
     qs = np.asarray(qs, dtype=np.int64)
     ps = np.asarray(ps, dtype=np.int64)
-    cvals = np.stack([(a % ps + (b % ps) * (qs % ps)) % ps for a, b in info["codes"]])
-    fwd = [api.map_export(lat, m, 0, i) for i in range(m)]
+    fam = api.family_info(lat, m, fuse)
+    cvals = _eval_codes(fam["codes"], qs, ps)
+    which = 0 if fuse == 1 else fuse
+    fwd = [api.map_export(lat, m, which, i) for i in range(fam["n_factors"])]
     last = [api.map_export(lat, m, 1, i) for i in range(m)]
     u = np.ones((1, qs.size), dtype=np.int64)
     for i in range(m, 0, -1):
@@ -108,8 +120,8 @@ def _run_maps(lat, m, n_max, qs, ps):
     x[0] = 1
     rows = [(w * x % ps).sum(axis=0) % ps]
     for _ in range(1, n_max):
-        for i in range(m):
-            x = _apply(fwd[i], cvals, x, ps)
+        for f in fwd:
+            x = _apply(f, cvals, x, ps)
         rows.append((w * x % ps).sum(axis=0) % ps)
     return np.stack(rows)
 
@@ -129,7 +141,7 @@ def test_maps_reproduce_oracle(lat, m):
 def test_map_structure(lat):
     for m in range(1, 11):
         info = api.maps_info(lat, m)
-        assert info["codes"][:2] == [(1, 0), (-1, 0)]
+        assert info["codes"][:2] == [(1, 0, 0, 0), (-1, 0, 0, 0)]
         for i in range(m):
             rp, cols, codes, ncols = api.map_export(lat, m, 0, i)
             assert rp[0] == 0 and np.all(np.diff(rp) >= 0) and rp[-1] == cols.size
@@ -157,9 +169,27 @@ def test_map_structure(lat):
 
 def test_coefficient_tables():
     sq = api.maps_info(SQ, 6)["codes"]
-    assert set(sq) == {(1, 0), (-1, 0), (-2, 1), (-1, 1), (0, 1)}   # +-1, q-2, q-1, q
+    # +-1, q-2, q-1, q
+    assert set(sq) == {(1, 0, 0, 0), (-1, 0, 0, 0), (-2, 1, 0, 0), (-1, 1, 0, 0), (0, 1, 0, 0)}
     tri = api.maps_info(TRI, 6)["codes"]
-    assert (-3, 1) in tri and (0, 1) in tri
+    assert (-3, 1, 0, 0) in tri and (0, 1, 0, 0) in tri
+    for lat in (SQ, TRI):
+        base = api.family_info(lat, 9, 1)["codes"]
+        for k in (2, 3):
+            fam = api.family_info(lat, 9, k)
+            assert fam["codes"][:len(base)] == base           # extends the single-factor table
+            assert fam["n_factors"] == -(-9 // k)
+            assert max(max(i for i in range(4) if c[i] or i == 0) for c in fam["codes"]) <= k
+
+
+@pytest.mark.parametrize("lat", [SQ, TRI])
+@pytest.mark.parametrize("fuse", [2, 3])
+@pytest.mark.parametrize("m", [1, 2, 3, 5, 7])
+def test_fused_families_reproduce_oracle(lat, fuse, m):
+    qs = [0, 1, 2, 3, 7, 100, P31 - 1, 5]
+    ps = [P31, P31, P31, P31, P31, 1000000007, P31, 998244353]
+    got = _run_maps(lat, m, 5, qs, ps, fuse=fuse)
+    np.testing.assert_array_equal(got, OT.chromatic_residues(lat, m, 5, qs, ps))
 
 
 def test_bad_arguments_are_errors_without_touching_a_gpu():
