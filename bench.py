@@ -1,18 +1,24 @@
 """Benchmark: state-updates/s of the batched sparse transfer-matrix sweep.
 
-Workload (one GPU): the square-lattice 14 x 15 rectangle, P read out after
-every row, at 80 q points x 8 seeded 31-bit primes = 640 instances, inputs
-and maps resident in HBM.  One step = one whole sweep: read-out vector build
-(T_last), x = e_0, 14 rows of T_14 ... T_1 with the read-out of every row.
+Headline workload (one GPU): the square-lattice 14 x 15 rectangle, P read out
+after every row, at 80 q points x 8 seeded 31-bit primes = 640 instances,
+inputs and maps resident in HBM.  One step = one whole sweep: read-out vector
+build (T_last), x = e_0, 14 rows of T_14 ... T_1 with the read-out of every
+row, launched as a hipGraph row replay with the autotuned launch shape.
 
 A state-update is one target residue written by one forward per-site factor
 T_i for one instance; a step performs 14 rows x 787 333 targets x 640
-instances = 7.05e9 of them.
+instances = 7.05e9 of them (a launch that applies a precomputed product of
+two factors counts the updates of both).
 
 Printed: one JSON line with the headline value, the roofline of the factor
 kernel (timed alone with HIP events on its launch stream), the plain
-per-instance path on the same workload, and the CPU oracle on a bounded
-sample.  Usage: python bench.py [--steps K] [--warmup W] [--mode graph]
+per-instance path on the same workload, the CPU oracle on a bounded sample,
+and secondary workloads (the m = 2..14 square sweep as one graph, the
+triangular m = 12 strip, and the continuous-batching server against the
+plain path on a Poisson job stream).
+
+Usage: python bench.py [--steps K] [--warmup W] [--quick]
 """
 from __future__ import annotations
 
@@ -33,21 +39,21 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def factor_sizes(lat, m):
-    """Per forward factor T_i: (|S_in|, |S_out|, nnz) from the maps."""
+def factor_sizes(lat, m, which=0, count=None):
+    """Per factor of a family: (|S_in|, |S_out|, nnz) from the maps."""
     from paper_1005_3609_amd import api
     out = []
-    for i in range(m):
-        rp, cols, _, ncols = api.map_export(lat, m, 0, i)
+    for i in range(count if count is not None else m):
+        rp, cols, _, ncols = api.map_export(lat, m, which, i)
         out.append((ncols, rp.size - 1, cols.size))
     return out
 
 
-def algorithmic_bytes_per_row(sizes, ipad, s_nc):
-    """Bytes one row of factor launches must move at minimum: every source
-    row read once and every target row written once (4 B per residue per
-    instance), the CSR row pointers and entry words, and the read-out vector
-    w read once by the fused read-out in T_m."""
+def row_bytes(sizes, ipad, s_nc):
+    """Bytes of one row of factor applications: for every factor each source
+    row read once and each target row written once (4 B per residue per
+    instance), its CSR row pointers and entry words, and the read-out vector w
+    read once by the read-out fused into the last launch."""
     total = 0
     for k, (s_in, s_out, nnz) in enumerate(sizes):
         total += 4 * ipad * (s_in + s_out) + 4 * (s_out + 1) + 4 * nnz
@@ -77,21 +83,103 @@ def cpu_baseline(lat, m, q_points, primes, n_inst=64):
     return dt, n_inst
 
 
+def timed(torch, stream, fn, reps=1):
+    """Milliseconds per call of fn, HIP events on `stream`."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def updates_of(lat, m, n, n_inst):
+    return (n - 1) * sum(s for _, s, _ in factor_sizes(lat, m)) * n_inst
+
+
+def bench_sweep(torch, stream, tune, steps):
+    """The square m = 2..14 sweep (n = m+1, 640 instances), all widths in one
+    hipGraph of grouped launches."""
+    from paper_1005_3609_amd import api
+    from paper_1005_3609_amd import workloads as W
+    w = W.workload("square_sweep_2_14")
+    jobs = [dict(lattice=lat, m=m, n_max=n, q_points=w["q_points"], primes=w["primes"])
+            for lat, m, n in w["strips"]]
+    for jb in jobs:
+        api.prepare(jb["lattice"], jb["m"])
+    t = {k: v for k, v in tune.items() if k != "streams"}
+    outs, ws = api.batch(jobs, tuning=t, stream=stream)
+    ms = timed(torch, stream, lambda: api.batch(jobs, tuning=t, workspace=ws, outs=outs, stream=stream), steps)
+    I = len(w["q_points"]) * len(w["primes"])
+    upd = sum(updates_of(lat, m, n, I) for lat, m, n in w["strips"])
+    return {"workload": "square m=2..14, n=m+1, 640 instances, one graph of grouped launches",
+            "ms_per_step": ms, "value": upd / (ms / 1e3), "unit": "state-updates/s"}
+
+
+def bench_triangular(torch, stream, steps):
+    from paper_1005_3609_amd import api
+    from paper_1005_3609_amd import workloads as W
+    w = W.workload("triangular_m12")
+    lat, m, n = w["strips"][0]
+    api.prepare(lat, m)
+    tune = {"streams": 3, "unroll": 8}
+    out, ws = api.strip_async(lat, m, n, w["q_points"], w["primes"], mode="graph", tuning=tune, stream=stream)
+    ms = timed(torch, stream, lambda: api.strip_async(lat, m, n, w["q_points"], w["primes"], mode="graph",
+                                                      tuning=tune, workspace=ws, out=out, stream=stream), steps)
+    I = len(w["q_points"]) * len(w["primes"])
+    return {"workload": "triangular 12x13, 48 q x 6 primes, graph row replay", "ms_per_step": ms,
+            "value": updates_of(lat, m, n, I) / (ms / 1e3), "unit": "state-updates/s"}
+
+
+def bench_serving(torch, n_jobs, n_plain):
+    """Continuous batching on a seeded Poisson stream (mean 20 jobs/s) against
+    the plain per-instance path serving the same arrivals one job at a time."""
+    from paper_1005_3609_amd import api
+    from paper_1005_3609_amd import workloads as W
+    from paper_1005_3609_amd.server import GpuBackend, Job, Server, fifo_baseline
+    stream_jobs = W.serving_stream(n_jobs)
+
+    def jobs(k):
+        return [Job(id=j["id"], lattice=j["lattice"], m=j["m"], n_max=j["n_max"], q_points=j["q_points"],
+                    primes=j["primes"], arrival=j["arrival"]) for j in stream_jobs[:k]]
+    be = GpuBackend(tuning={"unroll": 8})
+    for j in stream_jobs:
+        be.prepare(j["lattice"], j["m"])          # maps built before the clock starts
+    free, _ = torch.cuda.mem_get_info()
+    rep = Server(be, budget_bytes=int(0.8 * free), rows_per_tick=1).run(jobs(n_jobs))
+    served = rep.summary()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    pstream = torch.cuda.Stream(device=dev)
+
+    def run_plain(j):
+        out, ws = api.strip_async(j.lattice, j.m, j.n_max, j.q_points, j.primes, mode="plain", stream=pstream)
+        pstream.synchronize()
+        j.result = api.to_u32(out)
+    rep_p = fifo_baseline(run_plain, jobs(n_plain))
+    plain = rep_p.summary()
+    return {"stream": f"seeded Poisson, mean 20 jobs/s; lattice U{{sq,tri}}, m U{{6..16}}, n=m+1, "
+                      f"q=1..U{{16..80}}, 1-4 primes; {n_jobs} jobs served, the first {n_plain} also through "
+                      f"the plain path one job at a time",
+            "served": {k: served[k] for k in ("done", "failed", "p50_s", "p99_s", "jobs_per_s", "ticks")},
+            "plain_fifo": {k: plain[k] for k in ("done", "p50_s", "p99_s", "jobs_per_s")}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="graph", choices=["batched", "graph", "grouped"])
-    ap.add_argument("--lanes-v", type=int, default=0)
-    ap.add_argument("--targets-per-wave", type=int, default=0)
-    ap.add_argument("--waves-per-block", type=int, default=0)
-    ap.add_argument("--xcd-order", type=int, default=0)
-    ap.add_argument("--unroll", type=int, default=0)
-    ap.add_argument("--streams", type=int, default=0)
-    ap.add_argument("--fuse", type=int, default=0)
+    ap.add_argument("--mode", default=None, choices=["batched", "graph", "grouped"])
+    for k in ("lanes-v", "targets-per-wave", "waves-per-block", "xcd-order", "unroll", "streams", "fuse"):
+        ap.add_argument("--" + k, type=int, default=None)
+    ap.add_argument("--untuned", action="store_true", help="library defaults instead of the tuned table")
     ap.add_argument("--roofline-rows", type=int, default=10)
     ap.add_argument("--plain-instances", type=int, default=16)
+    ap.add_argument("--serve-jobs", type=int, default=120)
+    ap.add_argument("--serve-plain-jobs", type=int, default=20)
+    ap.add_argument("--quick", action="store_true", help="headline and roofline only")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -107,6 +195,7 @@ def main():
     import torch
 
     from paper_1005_3609_amd import api
+    from paper_1005_3609_amd import tune as tuner
     from paper_1005_3609_amd import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -116,88 +205,97 @@ def main():
     lat, m, n = w["strips"][0]
     q, p = w["q_points"], w["primes"]
     I = len(q) * len(p)
-    tune = {"lanes_v": args.lanes_v, "targets_per_wave": args.targets_per_wave,
-            "waves_per_block": args.waves_per_block, "xcd_order": args.xcd_order,
-            "unroll": args.unroll, "streams": args.streams, "fuse": args.fuse}
-    V = args.lanes_v or 2
+
+    tuned = None if args.untuned else tuner.lookup_tuned(lat, m, I, n)
+    tune = dict(tuned or {})
+    mode = args.mode or tune.pop("mode", "graph")
+    tune.pop("mode", None)
+    tune.pop("ms", None)
+    for k in ("lanes_v", "targets_per_wave", "waves_per_block", "xcd_order", "unroll", "streams", "fuse"):
+        v = getattr(args, k)
+        if v is not None:
+            tune[k] = v
+    V = tune.get("lanes_v") or 2
+    fuse = tune.get("fuse") or 1
     ipad = -(-I // (64 * V)) * 64 * V
 
     t0 = time.time()
     api.prepare(lat, m)
     sizes = factor_sizes(lat, m)
     s_nc = api.space_size(m)
-    updates_per_row = sum(s_out for _, s_out, _ in sizes) * I
-    updates_per_step = (n - 1) * updates_per_row
-    log(f"maps ready in {time.time() - t0:.1f} s; {updates_per_step:.3e} state-updates per step")
+    updates_per_step = updates_of(lat, m, n, I)
+    log(f"maps ready in {time.time() - t0:.1f} s; {updates_per_step:.3e} state-updates per step; "
+        f"mode {mode}, tuning {tune} ({'autotuned table' if tuned else 'given or defaults'})")
 
     stream = torch.cuda.current_stream(dev)
     out = torch.zeros((n, len(q), len(p)), dtype=torch.int32, device=dev)
-    ws = api.alloc_workspace(api.workspace_bytes(lat, m, n, len(q), len(p), args.mode, tune), dev)
+    ws = api.alloc_workspace(api.workspace_bytes(lat, m, n, len(q), len(p), mode, tune), dev)
+
+    def step():
+        api.strip_async(lat, m, n, q, p, mode=mode, tuning=tune, workspace=ws, out=out, stream=stream)
     for _ in range(args.warmup):
-        api.strip_async(lat, m, n, q, p, mode=args.mode, tuning=tune, workspace=ws, out=out, stream=stream)
+        step()
     torch.cuda.synchronize()
     log("warmup done")
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t_wall = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        api.strip_async(lat, m, n, q, p, mode=args.mode, tuning=tune, workspace=ws, out=out, stream=stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
+    ms_per_step = timed(torch, stream, step, args.steps)
     wall = time.perf_counter() - t_wall
-    ms = ev0.elapsed_time(ev1)
-    ms_per_step = ms / args.steps
     value = updates_per_step / (ms_per_step / 1e3)
     res = api.to_u32(out).astype("int64").reshape(n, len(q), len(p))
     assert (res[:, 0, :] == 0).all() and (res[:, 1, :] == 2).all(), "invariants P(1)=0, P(2)=2 failed"
-    log(f"{args.mode}: {ms_per_step:.3f} ms/step, {value:.3e} state-updates/s (wall {wall:.2f} s)")
+    log(f"{mode}: {ms_per_step:.3f} ms/step, {value:.3e} state-updates/s (wall {wall:.2f} s)")
 
     # ---- roofline of the factor kernel, timed alone -----------------------
     del ws
     ws_b = api.alloc_workspace(api.workspace_bytes(lat, m, n, len(q), len(p), "batched", tune), dev)
     api.strip_async(lat, m, n, q, p, mode="batched", tuning=tune, workspace=ws_b, out=out, stream=stream)
     api.factor_launches(lat, m, q, p, 2, ws_b, tune, stream)
-    torch.cuda.synchronize()
     R = args.roofline_rows
-    ev0.record(stream)
-    api.factor_launches(lat, m, q, p, R, ws_b, tune, stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    k_ms = ev0.elapsed_time(ev1)
-    launches = R * m
+    k_ms = timed(torch, stream, lambda: api.factor_launches(lat, m, q, p, R, ws_b, tune, stream))
+    nf = -(-m // fuse)
+    launches = R * nf
     avg_us = k_ms * 1e3 / launches
-    bytes_row = algorithmic_bytes_per_row(sizes, ipad, s_nc)
+    bytes_row = row_bytes(sizes, ipad, s_nc)
+    own_row = bytes_row if fuse == 1 else row_bytes(factor_sizes(lat, m, fuse, nf), ipad, s_nc)
     achieved = R * bytes_row / (k_ms / 1e3) / 1e9
-    log(f"factor kernel: {launches} launches, avg {avg_us:.1f} us, {achieved:.0f} GB/s algorithmic")
+    achieved_own = R * own_row / (k_ms / 1e3) / 1e9
+    kname = f"k_gather<{V},{tune.get('unroll') or 4}>"
+    log(f"factor kernel {kname}: {launches} launches, avg {avg_us:.1f} us, {achieved:.0f} GB/s algorithmic "
+        f"({achieved_own:.0f} GB/s of the launches' own minimum traffic)")
     del ws_b
 
     # ---- plain per-instance path on a subset of the instances -------------
     plain = None
-    if not args.no_plain:
+    if not args.no_plain and not args.quick:
         k = args.plain_instances
         qs_sub, ps_sub = q[: max(1, k // len(p))], p
         Ik = len(qs_sub) * len(ps_sub)
         ws_p = api.alloc_workspace(api.workspace_bytes(lat, m, n, len(qs_sub), len(ps_sub), "plain"), dev)
         out_p = torch.zeros((n, len(qs_sub), len(ps_sub)), dtype=torch.int32, device=dev)
-        api.strip_async(lat, m, n, qs_sub, ps_sub, mode="plain", workspace=ws_p, out=out_p, stream=stream)
-        torch.cuda.synchronize()
-        ev0.record(stream)
-        api.strip_async(lat, m, n, qs_sub, ps_sub, mode="plain", workspace=ws_p, out=out_p, stream=stream)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        p_ms = ev0.elapsed_time(ev1)
+
+        def plain_step():
+            api.strip_async(lat, m, n, qs_sub, ps_sub, mode="plain", workspace=ws_p, out=out_p, stream=stream)
+        plain_step()
+        p_ms = timed(torch, stream, plain_step)
         ref = res[:, : len(qs_sub), :]
         assert (api.to_u32(out_p).astype("int64") == ref).all(), "plain path differs from batched"
-        plain = {"value": (n - 1) * sum(s for _, s, _ in sizes) * Ik / (p_ms / 1e3),
-                 "unit": "state-updates/s", "instances_timed": Ik,
-                 "ms_per_instance": p_ms / Ik, "batched_speedup": None}
+        plain = {"value": updates_of(lat, m, n, Ik) / (p_ms / 1e3), "unit": "state-updates/s",
+                 "instances_timed": Ik, "ms_per_instance": p_ms / Ik}
         plain["batched_speedup"] = value / plain["value"]
         log(f"plain: {plain['value']:.3e} state-updates/s over {Ik} instances")
 
+    extra = {}
+    if not args.quick:
+        extra["sweep_square_2_14"] = bench_sweep(torch, stream, tune, max(2, args.steps // 4))
+        log(f"sweep m=2..14: {extra['sweep_square_2_14']['value']:.3e} state-updates/s")
+        extra["triangular_12x13"] = bench_triangular(torch, stream, max(2, args.steps // 2))
+        log(f"triangular m=12: {extra['triangular_12x13']['value']:.3e} state-updates/s")
+        extra["serving"] = bench_serving(torch, args.serve_jobs, args.serve_plain_jobs)
+        log(f"serving: {extra['serving']}")
+
     # ---- CPU oracle on a bounded sample -----------------------------------
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and not args.quick:
         dt, ninst = cpu_baseline(lat, m, q, p)
         upd = sum(s for _, s, _ in sizes) * ninst
         cpu = {"value": upd / dt, "unit": "state-updates/s", "cores": 1, "kind": "oracle",
@@ -210,15 +308,8 @@ def main():
         nel = args.copy_mib * (1 << 20) // 4
         src = torch.randint(0, 1 << 30, (nel,), dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        ev0.record(stream)
-        for _ in range(3):
-            dst.copy_(src)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        c_ms = ev0.elapsed_time(ev1) / 3
-        log(f"copied {args.copy_mib} MiB x4 (counter calibration); device copy "
+        c_ms = timed(torch, stream, lambda: dst.copy_(src), 3)
+        log(f"copied {args.copy_mib} MiB x3 (counter calibration); device copy "
             f"{2 * args.copy_mib * (1 << 20) / (c_ms / 1e3) / 1e9:.0f} GB/s read+write")
 
     line = {
@@ -236,13 +327,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": "square 14x15 strip, 80 q x 8 seeded primes (640 instances), "
                                "row-by-row read-out", "lattice": lat, "m": m, "n_max": n,
-                   "instances": I, "mode": args.mode, "tuning": tune},
+                   "instances": I, "mode": mode, "tuning": tune, "autotuned": bool(tuned)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"k_gather<{V}>", "avg_launch_us": avg_us,
-                     "algorithmic_bytes_per_row": bytes_row, "launches_timed": launches},
+                     "kernel": kname, "avg_launch_us": avg_us, "launches_timed": launches,
+                     "algorithmic_bytes_per_row": bytes_row, "own_min_bytes_per_row": own_row,
+                     "achieved_own_min": achieved_own},
         "plain": plain,
         "cpu_baseline": cpu,
+        "secondary": extra or None,
     }
     print(json.dumps(line), flush=True)
 

@@ -59,6 +59,19 @@ def lookup(lattice, m, n_inst, n_max, path=DEFAULT_CACHE):
     return load(path).get(_key(lattice, m, n_inst, n_max))
 
 
+PACKAGE_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
+
+
+def lookup_tuned(lattice, m, n_inst, n_max):
+    """Best known configuration: the user's tuning cache first, then the
+    table shipped with the package.  None if neither has the workload."""
+    for path in (DEFAULT_CACHE, PACKAGE_TABLE):
+        hit = load(path).get(_key(lattice, m, n_inst, n_max))
+        if hit:
+            return dict(hit["best"])
+    return None
+
+
 def time_candidate(lattice, m, n_max, q_points, primes, cand, steps=3, stream=None):
     """(ms per sweep, residues) for one candidate."""
     import torch
