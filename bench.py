@@ -95,6 +95,33 @@ def timed(torch, stream, fn, reps=1):
     return e0.elapsed_time(e1) / reps
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "modarith.hpp"):
+        with open(os.path.join(ROOT, "paper_1005_3609_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kname, rtune):
+    """HBM bytes per factor launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a copy-kernel calibration), or None
+    when the kernel source or launch shape differs from what was profiled."""
+    path = os.path.join(ROOT, "profiles", "k_gather_square_14x15.md")
+    try:
+        with open(path) as f:
+            for line in f:
+                if line.startswith("bench-traffic:"):
+                    rec = json.loads(line.split(":", 1)[1])
+                    if rec["kernel"] == kname and rec["kernel_src"] == kernel_source_hash() and \
+                            rec["tuning"] == {k: rtune.get(k) for k in rec["tuning"]}:
+                        return rec["bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
+
+
 def updates_of(lat, m, n, n_inst):
     return (n - 1) * sum(s for _, s, _ in factor_sizes(lat, m)) * n_inst
 
@@ -246,12 +273,16 @@ def main():
     log(f"{mode}: {ms_per_step:.3f} ms/step, {value:.3e} state-updates/s (wall {wall:.2f} s)")
 
     # ---- roofline of the factor kernel, timed alone -----------------------
+    # One launch per factor step over all instance chunks (streams = 1), so
+    # that a launch's duration is the kernel's own and matches what a
+    # kernel trace reports for this launch shape.
     del ws
-    ws_b = api.alloc_workspace(api.workspace_bytes(lat, m, n, len(q), len(p), "batched", tune), dev)
-    api.strip_async(lat, m, n, q, p, mode="batched", tuning=tune, workspace=ws_b, out=out, stream=stream)
-    api.factor_launches(lat, m, q, p, 2, ws_b, tune, stream)
+    rtune = dict(tune, streams=1)
+    ws_b = api.alloc_workspace(api.workspace_bytes(lat, m, n, len(q), len(p), "batched", rtune), dev)
+    api.strip_async(lat, m, n, q, p, mode="batched", tuning=rtune, workspace=ws_b, out=out, stream=stream)
+    api.factor_launches(lat, m, q, p, 2, ws_b, rtune, stream)
     R = args.roofline_rows
-    k_ms = timed(torch, stream, lambda: api.factor_launches(lat, m, q, p, R, ws_b, tune, stream))
+    k_ms = timed(torch, stream, lambda: api.factor_launches(lat, m, q, p, R, ws_b, rtune, stream))
     nf = -(-m // fuse)
     launches = R * nf
     avg_us = k_ms * 1e3 / launches
@@ -329,7 +360,7 @@ def main():
                                "row-by-row read-out", "lattice": lat, "m": m, "n_max": n,
                    "instances": I, "mode": mode, "tuning": tune, "autotuned": bool(tuned)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname, rtune),
                      "kernel": kname, "avg_launch_us": avg_us, "launches_timed": launches,
                      "algorithmic_bytes_per_row": bytes_row, "own_min_bytes_per_row": own_row,
                      "achieved_own_min": achieved_own},
