@@ -185,9 +185,9 @@ __device__ __forceinline__ void accumulate(uint32_t (&acc)[V], const uint32_t (&
 // One wavefront computes target rows [r0, r1) of one chunk.  Its row
 // pointers (lane j holds row_ptr[r0 + j]) and up to 64 entry words at a time
 // (lane l holds one word) arrive with coalesced vector loads and are
-// broadcast with readlane; the source rows of U consecutive entries are
-// loaded before any is consumed, so several W*4-byte gathers are in flight
-// per wavefront.  Row boundaries are uniform, so each finished row is stored
+// broadcast with readlane; source rows are loaded U entries at a time, one
+// group ahead of the group being consumed, so up to 2U W*4-byte gathers are
+// in flight per wavefront.  Row boundaries are uniform, so each finished row is stored
 // (and, when fused, folded into the read-out) without divergence; rows with
 // no entries are stored as zero.
 template <int V, int U>
@@ -229,30 +229,40 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
       ++row;
       if (row < r1) row_end = __builtin_amdgcn_readlane(rp, row - r0 + 1);
     };
+    // Entries stream through in batches of 64 words; inside a batch, groups of
+    // U source rows are software-pipelined: group g+1 is issued before group
+    // g is consumed, so up to 2U row loads are in flight per wavefront.
     for (int base = beg; base < end; base += 64) {
       const int n = min(64, end - base);
       const uint32_t ev = (lane < n) ? a.csr.ent[base + lane] : 0u;
-      int k = 0;
-      for (; k + U <= n; k += U) {
-        uint32_t word[U];
-        uint32_t x[U][V];
+      uint32_t wa[U], wb[U];
+      uint32_t xa[U][V], xb[U][V];
+      auto issue = [&](int k0, uint32_t (&w)[U], uint32_t (&x)[U][V]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          word[u] = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ev), k + u));
-          load_v<V>(in + static_cast<size_t>(word[u] & kEntSrcMask) * W, x[u]);
+          if (k0 + u < n) {
+            w[u] = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ev), k0 + u));
+            load_v<V>(in + static_cast<size_t>(w[u] & kEntSrcMask) * W, x[u]);
+          }
         }
+      };
+      auto consume = [&](int k0, const uint32_t (&w)[U], const uint32_t (&x)[U][V]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          while (base + k + u >= row_end) flush();
-          accumulate<V>(acc, x[u], word[u] >> kEntSrcBits, p, a.ic, inst0);
+          if (k0 + u < n) {
+            while (base + k0 + u >= row_end) flush();
+            accumulate<V>(acc, x[u], w[u] >> kEntSrcBits, p, a.ic, inst0);
+          }
         }
-      }
-      for (; k < n; ++k) {
-        const uint32_t word = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ev), k));
-        uint32_t x[V];
-        load_v<V>(in + static_cast<size_t>(word & kEntSrcMask) * W, x);
-        while (base + k >= row_end) flush();
-        accumulate<V>(acc, x, word >> kEntSrcBits, p, a.ic, inst0);
+      };
+      issue(0, wa, xa);
+      for (int k = 0; k < n; k += 2 * U) {
+        if (k + U < n) issue(k + U, wb, xb);
+        consume(k, wa, xa);
+        if (k + U < n) {
+          if (k + 2 * U < n) issue(k + 2 * U, wa, xa);
+          consume(k + U, wb, xb);
+        }
       }
     }
     while (row < r1) flush();
