@@ -54,6 +54,19 @@ __device__ __forceinline__ void store_v(uint32_t* ptr, const uint32_t (&x)[V]) {
   }
 }
 
+// Row access as a wave-uniform base plus a 32-bit byte offset (the row's
+// offset plus the lane's): the form the scalar-base global load/store
+// instructions take.  A chunk's vector stays below 4 GiB (checked on the host).
+template <int V>
+__device__ __forceinline__ void load_row(const uint32_t* base, uint32_t off, uint32_t (&x)[V]) {
+  load_v<V>(reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(base) + off), x);
+}
+
+template <int V>
+__device__ __forceinline__ void store_row(uint32_t* base, uint32_t off, const uint32_t (&x)[V]) {
+  store_v<V>(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(base) + off), x);
+}
+
 // Workgroups are handed to the 8 XCDs round-robin in dispatch order.  This
 // bijection on [0, nb) gives each XCD one contiguous range of ids instead, so
 // neighbouring target rows -- which share many source rows -- run under the
@@ -82,14 +95,17 @@ struct DevCsr {
 };
 
 // Per-instance constants of a batch, instance index inst = chunk W + lane V + j.
-//   p[inst], pinv[inst] = -p^{-1} mod 2^32, cval[k*ipad + inst] = code k's
-//   coefficient mod p, cshp[...] = floor(cval 2^32 / p).
+//   p[inst], pinv[inst] = -p^{-1} mod 2^32, qv[inst] = q mod p,
+//   qs[inst] = floor(qv 2^32 / p).
+// Coefficient codes: poly[code] holds the integer coefficients c0..c3 of the
+// code's polynomial c0 + c1 q + c2 q^2 + c3 q^3 as four signed bytes (c_k in
+// byte k); 64 words, unused codes zero.  Code 0 is +1 and code 1 is -1.
 struct InstConsts {
   const uint32_t* p;
   const uint32_t* pinv;
-  const uint32_t* cval;
-  const uint32_t* cshp;
-  int ipad;
+  const uint32_t* qv;
+  const uint32_t* qs;
+  const int32_t* poly;
 };
 
 struct GatherArgs {
@@ -163,22 +179,77 @@ __device__ __forceinline__ void block_reduce_store(uint32_t (&red)[V], const uin
   __syncthreads();
 }
 
-// Accumulates coef(code) * x into acc (all lanes take the same branch).
+// A += c x mod p for a small wave-uniform integer c != 0: |c| x by
+// left-to-right binary doubling, then one modular add or subtract.
 template <int V>
-__device__ __forceinline__ void accumulate(uint32_t (&acc)[V], const uint32_t (&x)[V], uint32_t code,
-                                           const uint32_t (&p)[V], const InstConsts& ic, int inst0) {
+__device__ __forceinline__ void add_multiple(uint32_t (&A)[V], const uint32_t (&x)[V], int c,
+                                             const uint32_t (&p)[V]) {
+  const int n = c < 0 ? -c : c;
+  uint32_t y[V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) y[j] = x[j];
+  for (int b = 30 - __builtin_clz(static_cast<unsigned>(n)); b >= 0; --b) {
+#pragma unroll
+    for (int j = 0; j < V; ++j) y[j] = add_mod(y[j], y[j], p[j]);
+    if ((n >> b) & 1) {
+#pragma unroll
+      for (int j = 0; j < V; ++j) y[j] = add_mod(y[j], x[j], p[j]);
+    }
+  }
+  if (c > 0) {
+#pragma unroll
+    for (int j = 0; j < V; ++j) A[j] = add_mod(A[j], y[j], p[j]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < V; ++j) A[j] = sub_mod(A[j], y[j], p[j]);
+  }
+}
+
+// Coefficient accumulation without multiplications.  A factor entry's
+// coefficient is an integer polynomial in q, c(q) = sum_k c_k q^k, so a
+// target row's value sum_e c_e(q) x_e equals sum_k q^k A_k with
+// A_k = sum_e c_{e,k} x_e.  Each entry adds small multiples of its source
+// row to the A_k (modular adds only); the row is finished by Horner's rule in
+// q (at most three Shoup products).  `pw` is the wavefront's copy of the code
+// table (lane c holds code c); `deg` tracks the row's highest power of q.
+template <int V>
+__device__ __forceinline__ void accumulate(uint32_t (&A)[4][V], const uint32_t (&x)[V], uint32_t code,
+                                           const uint32_t (&p)[V], int pw, int& deg) {
   if (code == 0) {
 #pragma unroll
-    for (int j = 0; j < V; ++j) acc[j] = add_mod(acc[j], x[j], p[j]);
+    for (int j = 0; j < V; ++j) A[0][j] = add_mod(A[0][j], x[j], p[j]);
   } else if (code == 1) {
 #pragma unroll
-    for (int j = 0; j < V; ++j) acc[j] = sub_mod(acc[j], x[j], p[j]);
+    for (int j = 0; j < V; ++j) A[0][j] = sub_mod(A[0][j], x[j], p[j]);
   } else {
-    uint32_t cv[V], cs[V];
-    load_v<V>(ic.cval + code * ic.ipad + inst0, cv);
-    load_v<V>(ic.cshp + code * ic.ipad + inst0, cs);
+    const int cw = __builtin_amdgcn_readlane(pw, static_cast<int>(code));
 #pragma unroll
-    for (int j = 0; j < V; ++j) acc[j] = add_mod(acc[j], mul_shoup(x[j], cv[j], cs[j], p[j]), p[j]);
+    for (int k = 0; k < 4; ++k) {
+      const int c = static_cast<int>(static_cast<int8_t>(static_cast<uint32_t>(cw) >> (8 * k)));
+      if (c != 0) {
+        add_multiple<V>(A[k], x, c, p);
+        deg = deg > k ? deg : k;
+      }
+    }
+  }
+}
+
+// sum_k q^k A_k mod p by Horner's rule; A_k = 0 for k > deg.
+template <int V>
+__device__ __forceinline__ void horner(uint32_t (&v)[V], const uint32_t (&A)[4][V], int deg,
+                                       const uint32_t (&qv)[V], const uint32_t (&qs)[V],
+                                       const uint32_t (&p)[V]) {
+#pragma unroll
+  for (int j = 0; j < V; ++j) v[j] = A[3][j];
+#pragma unroll
+  for (int k = 2; k >= 0; --k) {
+    if (deg > k) {
+#pragma unroll
+      for (int j = 0; j < V; ++j) v[j] = add_mod(mul_shoup(v[j], qv[j], qs[j], p[j]), A[k][j], p[j]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < V; ++j) v[j] = A[k][j];
+    }
   }
 }
 
@@ -187,25 +258,36 @@ __device__ __forceinline__ void accumulate(uint32_t (&acc)[V], const uint32_t (&
 // (lane l holds one word) arrive with coalesced vector loads and are
 // broadcast with readlane; source rows are loaded U entries at a time, one
 // group ahead of the group being consumed, so up to 2U W*4-byte gathers are
-// in flight per wavefront.  Row boundaries are uniform, so each finished row is stored
-// (and, when fused, folded into the read-out) without divergence; rows with
-// no entries are stored as zero.
+// in flight per wavefront.  The inner loop loads nothing else: coefficients
+// come from registers (see accumulate), so the only waits are for the source
+// rows themselves, oldest first.  Row boundaries are uniform, so each
+// finished row is stored without divergence; rows with no entries are stored
+// as zero.
 template <int V, int U>
 __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* lds) {
   constexpr int W = 64 * V;
   const int lane = lane_id(), wave = wave_id();
   const int inst0 = chunk * W + lane * V;
-  uint32_t p[V];
+  const uint32_t boff = static_cast<uint32_t>(lane) * (4u * V);
+  uint32_t p[V], qv[V], qs[V];
   load_v<V>(a.ic.p + inst0, p);
-  const uint32_t* in = a.in + chunk * a.in_cstride + lane * V;
-  uint32_t* out = a.out + chunk * a.out_cstride + lane * V;
+  load_v<V>(a.ic.qv + inst0, qv);
+  load_v<V>(a.ic.qs + inst0, qs);
+  const int pw = a.ic.poly[lane];
+  const uint32_t* in = a.in + chunk * a.in_cstride;     // uniform bases
+  uint32_t* out = a.out + chunk * a.out_cstride;
   const bool fused = a.w != nullptr;
-  const uint32_t* wv = fused ? a.w + chunk * a.w_cstride + lane * V : nullptr;
+  const uint32_t* wv = fused ? a.w + chunk * a.w_cstride : nullptr;
   uint32_t pinv[V];
   if (fused) load_v<V>(a.ic.pinv + inst0, pinv);
-  uint32_t red[V], acc[V];
+  uint32_t red[V], A[4][V];
 #pragma unroll
-  for (int j = 0; j < V; ++j) red[j] = acc[j] = 0;
+  for (int j = 0; j < V; ++j) red[j] = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int j = 0; j < V; ++j) A[k][j] = 0;
+  int deg = 0;
   const int nw = blockDim.x >> 6;
   const int r0 = (tile * nw + wave) * a.rows_per_wave;
   const int r1 = min(r0 + a.rows_per_wave, a.csr.n_rows);
@@ -217,33 +299,37 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
     int row = r0;
     int row_end = __builtin_amdgcn_readlane(rp, 1);
     auto flush = [&]() {
-      store_v<V>(out + static_cast<size_t>(row) * W, acc);
-      if (fused) {
-        uint32_t wr[V];
-        load_v<V>(wv + static_cast<size_t>(row) * W, wr);
+      uint32_t v[V];
+      horner<V>(v, A, deg, qv, qs, p);
+      store_row<V>(out, static_cast<uint32_t>(row) * (4u * W) + boff, v);
 #pragma unroll
-        for (int j = 0; j < V; ++j) red[j] = add_mod(red[j], mul_redc(acc[j], wr[j], p[j], pinv[j]), p[j]);
-      }
+      for (int k = 0; k < 4; ++k)
+        if (k <= deg) {
 #pragma unroll
-      for (int j = 0; j < V; ++j) acc[j] = 0;
+          for (int j = 0; j < V; ++j) A[k][j] = 0;
+        }
+      deg = 0;
       ++row;
       if (row < r1) row_end = __builtin_amdgcn_readlane(rp, row - r0 + 1);
     };
     // Entries stream through in batches of 64 words; inside a batch, groups of
     // U source rows are software-pipelined: group g+1 is issued before group
-    // g is consumed, so up to 2U row loads are in flight per wavefront.
+    // g is consumed.
     for (int base = beg; base < end; base += 64) {
       const int n = min(64, end - base);
       const uint32_t ev = (lane < n) ? a.csr.ent[base + lane] : 0u;
       uint32_t wa[U], wb[U];
       uint32_t xa[U][V], xb[U][V];
+      // Every group issues U loads; slots past the batch repeat its last
+      // entry (a cache hit), so the number of loads in flight is fixed.
       auto issue = [&](int k0, uint32_t (&w)[U], uint32_t (&x)[U][V]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          if (k0 + u < n) {
-            w[u] = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ev), k0 + u));
-            load_v<V>(in + static_cast<size_t>(w[u] & kEntSrcMask) * W, x[u]);
-          }
+          w[u] = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ev), min(k0 + u, n - 1)));
+          load_row<V>(in, (w[u] & kEntSrcMask) * (4u * W) + boff, x[u]);
+          // Keep the loads in entry order: completions are counted in issue
+          // order, so entry u must not be issued after entry u + 1.
+          __builtin_amdgcn_sched_barrier(0);
         }
       };
       auto consume = [&](int k0, const uint32_t (&w)[U], const uint32_t (&x)[U][V]) {
@@ -251,21 +337,46 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
         for (int u = 0; u < U; ++u) {
           if (k0 + u < n) {
             while (base + k0 + u >= row_end) flush();
-            accumulate<V>(acc, x[u], w[u] >> kEntSrcBits, p, a.ic, inst0);
+            accumulate<V>(A, x[u], w[u] >> kEntSrcBits, p, pw, deg);
           }
         }
       };
+      // Each consume is preceded by exactly one unconditional issue of the
+      // next group, so every wait is for a fixed count of newer loads; the
+      // group issued past the batch end only repeats its last entry.
       issue(0, wa, xa);
-      for (int k = 0; k < n; k += 2 * U) {
-        if (k + U < n) issue(k + U, wb, xb);
+      for (int k = 0;;) {
+        issue(k + U, wb, xb);
         consume(k, wa, xa);
-        if (k + U < n) {
-          if (k + 2 * U < n) issue(k + 2 * U, wa, xa);
-          consume(k + U, wb, xb);
-        }
+        k += U;
+        if (k >= n) break;
+        issue(k + U, wa, xa);
+        consume(k, wb, xb);
+        k += U;
+        if (k >= n) break;
       }
     }
     while (row < r1) flush();
+    // Fused read-out, after the entry stream so that its loads never sit
+    // behind in-flight gathers: each lane reads back its own just-stored
+    // rows (cache-resident) with their weights, four rows per wait.
+    if (fused) {
+      for (int r = r0; r < r1; r += 4) {
+        uint32_t xo[4][V], wr[4][V];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t off = static_cast<uint32_t>(min(r + i, r1 - 1)) * (4u * W) + boff;
+          load_row<V>(out, off, xo[i]);
+          load_row<V>(wv, off, wr[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (r + i < r1) {
+#pragma unroll
+            for (int j = 0; j < V; ++j) red[j] = add_mod(red[j], mul_redc(xo[i][j], wr[i][j], p[j], pinv[j]), p[j]);
+          }
+      }
+    }
   }
   if (fused) block_reduce_store<V>(red, p, a.partial + chunk * a.p_cstride + static_cast<long>(tile) * W, lds);
 }

@@ -294,7 +294,7 @@ struct JobLayout {
   int64_t s_nc = 0, s_max = 0;
   int nparts = 0;        // read-out partial tiles per chunk
   int ngroups = 0;       // level-1 reduction groups per chunk
-  size_t x0 = 0, x1 = 0, w = 0, part = 0, part2 = 0, p = 0, pinv = 0, r1 = 0, cval = 0, cshp = 0, bytes = 0;
+  size_t x0 = 0, x1 = 0, w = 0, part = 0, part2 = 0, p = 0, pinv = 0, r1 = 0, qv = 0, qs = 0, poly = 0, bytes = 0;
 };
 
 // Level-1 groups: about 32 partials each, at most 64 groups.
@@ -322,6 +322,9 @@ JobLayout job_layout(int lattice, int m, int I, const Tune& t, int ncodes, int r
     off += align_up(b);
     return o;
   };
+  // Kernels address a chunk's rows with 32-bit byte offsets.
+  if (static_cast<uint64_t>(L.s_max) * L.W * 4 >= (uint64_t(1) << 32))
+    throw ArgError("one chunk's state vector would exceed 4 GiB; use fewer lanes_v");
   const size_t vec = static_cast<size_t>(L.nchunk) * L.s_max * L.W * 4;
   L.x0 = take(vec);
   L.x1 = take(vec);
@@ -331,42 +334,55 @@ JobLayout job_layout(int lattice, int m, int I, const Tune& t, int ncodes, int r
   L.p = take(L.ipad * 4);
   L.pinv = take(L.ipad * 4);
   L.r1 = take(L.ipad * 4);
-  L.cval = take(static_cast<size_t>(kMaxCodes) * L.ipad * 4);
-  L.cshp = take(static_cast<size_t>(kMaxCodes) * L.ipad * 4);
+  L.qv = take(L.ipad * 4);
+  L.qs = take(L.ipad * 4);
+  L.poly = take(static_cast<size_t>(kMaxCodes) * 4);
   L.bytes = off;
   return L;
 }
 
-// Constants of a job: p, pinv, r1, cval[ncodes][ipad], cshp[...] as one
-// host image laid out like the workspace region [p .. cshp].
+// Code table word: the coefficients c0..c3 as signed bytes, c_k in byte k.
+uint32_t pack_poly(const Poly& c) {
+  uint32_t w = 0;
+  for (int k = 0; k <= kMaxDeg; ++k) {
+    if (c.c[k] < -127 || c.c[k] > 127) throw std::runtime_error("coefficient polynomial out of the packed range");
+    w |= (static_cast<uint32_t>(c.c[k]) & 0xffu) << (8 * k);
+  }
+  return w;
+}
+
+// Constants of a job: p, pinv, r1, qv, qs over the padded instances and the
+// packed code table, as one host image laid out like the workspace region
+// [p .. poly].
 std::vector<uint32_t> const_image(const JobLayout& L, const std::vector<Inst>& inst,
                                   const std::vector<Poly>& codes) {
   const size_t base = L.p;
-  std::vector<uint32_t> img((L.cshp + static_cast<size_t>(kMaxCodes) * L.ipad * 4 - base) / 4, 0);
+  if (codes.size() < 2 || !(codes[0].c[0] == 1 && codes[1].c[0] == -1))
+    throw std::runtime_error("code table must start with +1 and -1");
+  std::vector<uint32_t> img((L.poly + static_cast<size_t>(kMaxCodes) * 4 - base) / 4, 0);
   auto at = [&](size_t off) { return img.data() + (off - base) / 4; };
   uint32_t* p = at(L.p);
   uint32_t* pinv = at(L.pinv);
   uint32_t* r1 = at(L.r1);
-  uint32_t* cv = at(L.cval);
-  uint32_t* cs = at(L.cshp);
+  uint32_t* qv = at(L.qv);
+  uint32_t* qs = at(L.qs);
+  uint32_t* poly = at(L.poly);
+  for (size_t c = 0; c < codes.size(); ++c) poly[c] = pack_poly(codes[c]);
   for (int k = 0; k < L.ipad; ++k) {
     const Inst& in = inst[k < L.I ? k : 0];
     p[k] = in.p;
     pinv[k] = neg_inv_2_32(in.p);
     r1[k] = static_cast<uint32_t>((uint64_t(1) << 32) % in.p);
-    for (size_t c = 0; c < codes.size(); ++c) {
-      uint32_t v = coef_mod(codes[c], in.q, in.p);
-      cv[static_cast<size_t>(c) * L.ipad + k] = v;
-      cs[static_cast<size_t>(c) * L.ipad + k] = shoup_of(v, in.p);
-    }
+    qv[k] = in.q % in.p;
+    qs[k] = shoup_of(qv[k], in.p);
   }
   return img;
 }
 
 // Pointers of one job's device state.
 struct JobPtrs {
-  uint32_t *x0, *x1, *w, *part, *part2, *p, *pinv, *r1, *cval, *cshp;
-  InstConsts ic() const { return InstConsts{p, pinv, cval, cshp, 0}; }
+  uint32_t *x0, *x1, *w, *part, *part2, *p, *pinv, *r1, *qv, *qs, *poly;
+  InstConsts ic() const { return InstConsts{p, pinv, qv, qs, reinterpret_cast<const int32_t*>(poly)}; }
 };
 
 JobPtrs job_ptrs(const JobLayout& L, void* base) {
@@ -380,14 +396,12 @@ JobPtrs job_ptrs(const JobLayout& L, void* base) {
   j.p = reinterpret_cast<uint32_t*>(b + L.p);
   j.pinv = reinterpret_cast<uint32_t*>(b + L.pinv);
   j.r1 = reinterpret_cast<uint32_t*>(b + L.r1);
-  j.cval = reinterpret_cast<uint32_t*>(b + L.cval);
-  j.cshp = reinterpret_cast<uint32_t*>(b + L.cshp);
+  j.qv = reinterpret_cast<uint32_t*>(b + L.qv);
+  j.qs = reinterpret_cast<uint32_t*>(b + L.qs);
+  j.poly = reinterpret_cast<uint32_t*>(b + L.poly);
   return j;
 }
 
-InstConsts inst_consts(const JobLayout& L, const JobPtrs& j) {
-  return InstConsts{j.p, j.pinv, j.cval, j.cshp, L.ipad};
-}
 
 // The persistent work-queue mode (workgroups waiting on completion counters
 // of other workgroups) is switched off: it stalled on the device.  Grouped
@@ -450,7 +464,7 @@ Step gather_step(const JobCtx& j, const DevCsr& c, const uint32_t* in, uint32_t*
   a.out = out;
   a.in_cstride = static_cast<long>(j.L.s_max) * j.L.W;
   a.out_cstride = out_cstride;
-  a.ic = inst_consts(j.L, j.P);
+  a.ic = j.P.ic();
   a.rows_per_wave = j.t.rpw;
   if (fused) {
     a.w = j.P.w;
@@ -462,7 +476,7 @@ Step gather_step(const JobCtx& j, const DevCsr& c, const uint32_t* in, uint32_t*
 }
 
 ReduceArgs reduce_args(const JobCtx& j, int out_row) {
-  return ReduceArgs{j.P.part, static_cast<long>(j.L.nparts) * j.L.W, j.L.nparts, inst_consts(j.L, j.P),
+  return ReduceArgs{j.P.part, static_cast<long>(j.L.nparts) * j.L.W, j.L.nparts, j.P.ic(),
                     j.P.part2, static_cast<long>(j.L.ngroups) * j.L.W, j.L.ngroups,
                     j.d_out ? j.d_out + static_cast<long>(out_row) * j.L.I : nullptr, j.L.I};
 }
@@ -506,7 +520,7 @@ int add_setup(Program& pg, const JobCtx& j) {
   s = Step{};
   s.op = kOpDot;
   s.ntiles = L.nparts;
-  s.u.d = DotArgs{j.P.x0, j.P.w, cs_x, cs_w, static_cast<int>(L.s_nc), inst_consts(L, j.P), j.P.part,
+  s.u.d = DotArgs{j.P.x0, j.P.w, cs_x, cs_w, static_cast<int>(L.s_nc), j.P.ic(), j.P.part,
                   static_cast<long>(L.nparts) * L.W, j.t.rpw};
   last = push(pg, s, last, -1);
   return push_reduce(pg, j, 0, last);
