@@ -95,16 +95,17 @@ struct DevCsr {
 };
 
 // Per-instance constants of a batch, instance index inst = chunk W + lane V + j.
-//   p[inst], pinv[inst] = -p^{-1} mod 2^32, qv[inst] = q mod p,
-//   qs[inst] = floor(qv 2^32 / p).
-// Coefficient codes: poly[code] holds the integer coefficients c0..c3 of the
-// code's polynomial c0 + c1 q + c2 q^2 + c3 q^3 as four signed bytes (c_k in
-// byte k); 64 words, unused codes zero.  Code 0 is +1 and code 1 is -1.
+//   p[inst], pinv[inst] = -p^{-1} mod 2^32, tv[inst] = t mod p with
+//   t = q - s for the job's basis shift s, ts[inst] = floor(tv 2^32 / p).
+// Coefficient codes: poly[code] holds the integer coefficients d0..d3 of the
+// code's polynomial written in powers of t, d0 + d1 t + d2 t^2 + d3 t^3, as
+// four signed bytes (d_k in byte k); 64 words, unused codes zero.  Code 0 is
+// +1 and code 1 is -1 (constants, so the same in every basis).
 struct InstConsts {
   const uint32_t* p;
   const uint32_t* pinv;
-  const uint32_t* qv;
-  const uint32_t* qs;
+  const uint32_t* tv;
+  const uint32_t* ts;
   const int32_t* poly;
 };
 
@@ -180,7 +181,8 @@ __device__ __forceinline__ void block_reduce_store(uint32_t (&red)[V], const uin
 }
 
 // A += c x mod p for a small wave-uniform integer c != 0: |c| x by
-// left-to-right binary doubling, then one modular add or subtract.
+// left-to-right binary doubling (no steps for |c| = 1), then one modular add
+// or subtract.
 template <int V>
 __device__ __forceinline__ void add_multiple(uint32_t (&A)[V], const uint32_t (&x)[V], int c,
                                              const uint32_t (&p)[V]) {
@@ -206,11 +208,12 @@ __device__ __forceinline__ void add_multiple(uint32_t (&A)[V], const uint32_t (&
 }
 
 // Coefficient accumulation without multiplications.  A factor entry's
-// coefficient is an integer polynomial in q, c(q) = sum_k c_k q^k, so a
-// target row's value sum_e c_e(q) x_e equals sum_k q^k A_k with
-// A_k = sum_e c_{e,k} x_e.  Each entry adds small multiples of its source
-// row to the A_k (modular adds only); the row is finished by Horner's rule in
-// q (at most three Shoup products).  `pw` is the wavefront's copy of the code
+// coefficient is an integer polynomial in q, written in powers of t = q - s
+// (the host picks the shift s that makes the coefficients smallest, e.g.
+// q - 2 = t), c = sum_k d_k t^k, so a target row's value sum_e c_e x_e equals
+// sum_k t^k A_k with A_k = sum_e d_{e,k} x_e.  Each entry adds small
+// multiples of its source row to the A_k (modular adds only); the row is
+// finished by Horner's rule in t (at most three Shoup products).  `pw` is the wavefront's copy of the code
 // table (lane c holds code c); `deg` tracks the row's highest power of q.
 template <int V>
 __device__ __forceinline__ void accumulate(uint32_t (&A)[4][V], const uint32_t (&x)[V], uint32_t code,
@@ -234,10 +237,10 @@ __device__ __forceinline__ void accumulate(uint32_t (&A)[4][V], const uint32_t (
   }
 }
 
-// sum_k q^k A_k mod p by Horner's rule; A_k = 0 for k > deg.
+// sum_k t^k A_k mod p by Horner's rule; A_k = 0 for k > deg.
 template <int V>
 __device__ __forceinline__ void horner(uint32_t (&v)[V], const uint32_t (&A)[4][V], int deg,
-                                       const uint32_t (&qv)[V], const uint32_t (&qs)[V],
+                                       const uint32_t (&tv)[V], const uint32_t (&ts)[V],
                                        const uint32_t (&p)[V]) {
 #pragma unroll
   for (int j = 0; j < V; ++j) v[j] = A[3][j];
@@ -245,7 +248,7 @@ __device__ __forceinline__ void horner(uint32_t (&v)[V], const uint32_t (&A)[4][
   for (int k = 2; k >= 0; --k) {
     if (deg > k) {
 #pragma unroll
-      for (int j = 0; j < V; ++j) v[j] = add_mod(mul_shoup(v[j], qv[j], qs[j], p[j]), A[k][j], p[j]);
+      for (int j = 0; j < V; ++j) v[j] = add_mod(mul_shoup(v[j], tv[j], ts[j], p[j]), A[k][j], p[j]);
     } else {
 #pragma unroll
       for (int j = 0; j < V; ++j) v[j] = A[k][j];
@@ -269,10 +272,10 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
   const int lane = lane_id(), wave = wave_id();
   const int inst0 = chunk * W + lane * V;
   const uint32_t boff = static_cast<uint32_t>(lane) * (4u * V);
-  uint32_t p[V], qv[V], qs[V];
+  uint32_t p[V], tv[V], ts[V];
   load_v<V>(a.ic.p + inst0, p);
-  load_v<V>(a.ic.qv + inst0, qv);
-  load_v<V>(a.ic.qs + inst0, qs);
+  load_v<V>(a.ic.tv + inst0, tv);
+  load_v<V>(a.ic.ts + inst0, ts);
   const int pw = a.ic.poly[lane];
   const uint32_t* in = a.in + chunk * a.in_cstride;     // uniform bases
   uint32_t* out = a.out + chunk * a.out_cstride;
@@ -300,7 +303,7 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
     int row_end = __builtin_amdgcn_readlane(rp, 1);
     auto flush = [&]() {
       uint32_t v[V];
-      horner<V>(v, A, deg, qv, qs, p);
+      horner<V>(v, A, deg, tv, ts, p);
       store_row<V>(out, static_cast<uint32_t>(row) * (4u * W) + boff, v);
 #pragma unroll
       for (int k = 0; k < 4; ++k)

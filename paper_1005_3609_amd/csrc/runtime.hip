@@ -79,6 +79,7 @@ struct DevFamily {
   void* base = nullptr;
   std::vector<DevCsr> fac;
   std::vector<Poly> codes;   // extends the base table
+  int shift = 0;             // kernels expand the codes in powers of t = q - shift
 };
 
 struct DevMaps {
@@ -144,6 +145,60 @@ const DevMaps& dev_maps(int lattice, int m) {
   return ref;
 }
 
+// Coefficients of c(q) in powers of t = q - s: d_j = sum_{k >= j} c_k C(k, j) s^(k-j).
+Poly shift_basis(const Poly& c, int s) {
+  static const int64_t binom[kMaxDeg + 1][kMaxDeg + 1] = {{1, 0, 0, 0}, {1, 1, 0, 0}, {1, 2, 1, 0}, {1, 3, 3, 1}};
+  Poly d;
+  for (int j = 0; j <= kMaxDeg; ++j) {
+    int64_t acc = 0, sp = 1;
+    for (int k = j; k <= kMaxDeg; ++k) {
+      acc += c.c[k] * binom[k][j] * sp;
+      sp *= s;
+    }
+    d.c[j] = acc;
+  }
+  return d;
+}
+
+// Modular additions the factor kernel spends on one entry with code
+// polynomial d: a coefficient of magnitude n costs floor(log2 n) doublings,
+// popcount(n) - 1 further additions and the final one.
+int64_t entry_cost(const Poly& d) {
+  int64_t ops = 0;
+  for (int k = 0; k <= kMaxDeg; ++k) {
+    const int64_t n = d.c[k] < 0 ? -d.c[k] : d.c[k];
+    if (n == 0) continue;
+    if (n > 127) return -1;   // outside the packed table
+    ops += (63 - __builtin_clzll(static_cast<uint64_t>(n))) + __builtin_popcountll(static_cast<uint64_t>(n));
+  }
+  return ops;
+}
+
+// Basis shift with the fewest modular additions over the family's entries
+// (ties to the smallest |s|).
+int choose_shift(const std::vector<Poly>& codes, const std::vector<Csr>& fac) {
+  std::vector<int64_t> count(codes.size(), 0);
+  for (const Csr& c : fac)
+    for (uint32_t e : c.ent) ++count[e >> kSrcBits];
+  int best = 0;
+  int64_t best_cost = -1;
+  for (int s : {0, 1, -1, 2, -2, 3, -3, 4, -4}) {
+    int64_t cost = 0;
+    bool ok = true;
+    for (size_t c = 0; c < codes.size() && ok; ++c) {
+      const int64_t e = entry_cost(shift_basis(codes[c], s));
+      if (e < 0) ok = false;
+      cost += e * count[c];
+    }
+    if (ok && (best_cost < 0 || cost < best_cost)) {
+      best = s;
+      best_cost = cost;
+    }
+  }
+  if (best_cost < 0) throw std::runtime_error("no basis shift keeps the coefficient polynomials in the packed range");
+  return best;
+}
+
 // Device copy of fused family k (k = 1: the single factors).
 const DevFamily& dev_family(const DevMaps& dm, int k) {
   std::lock_guard<std::mutex> lk(dm.fam_mu);
@@ -153,6 +208,7 @@ const DevFamily& dev_family(const DevMaps& dm, int k) {
   if (k == 1) {
     df->fac.assign(dm.fwd, dm.fwd + dm.m);
     df->codes = dm.codes;
+    df->shift = choose_shift(dm.codes, get_maps(dm.lattice, dm.m).fwd);
   } else {
     const Family& f = get_maps(dm.lattice, dm.m).family(k);
     size_t bytes = 0;
@@ -162,6 +218,7 @@ const DevFamily& dev_family(const DevMaps& dm, int k) {
     df->fac.resize(f.fac.size());
     for (size_t i = 0; i < f.fac.size(); ++i) upload_csr(f.fac[i], df->fac[i], cur);
     df->codes = f.codes;
+    df->shift = choose_shift(f.codes, f.fac);
   }
   const DevFamily& ref = *df;
   dm.fam.emplace(k, std::move(df));
@@ -294,7 +351,7 @@ struct JobLayout {
   int64_t s_nc = 0, s_max = 0;
   int nparts = 0;        // read-out partial tiles per chunk
   int ngroups = 0;       // level-1 reduction groups per chunk
-  size_t x0 = 0, x1 = 0, w = 0, part = 0, part2 = 0, p = 0, pinv = 0, r1 = 0, qv = 0, qs = 0, poly = 0, bytes = 0;
+  size_t x0 = 0, x1 = 0, w = 0, part = 0, part2 = 0, p = 0, pinv = 0, r1 = 0, tv = 0, ts = 0, poly = 0, bytes = 0;
 };
 
 // Level-1 groups: about 32 partials each, at most 64 groups.
@@ -334,14 +391,14 @@ JobLayout job_layout(int lattice, int m, int I, const Tune& t, int ncodes, int r
   L.p = take(L.ipad * 4);
   L.pinv = take(L.ipad * 4);
   L.r1 = take(L.ipad * 4);
-  L.qv = take(L.ipad * 4);
-  L.qs = take(L.ipad * 4);
+  L.tv = take(L.ipad * 4);
+  L.ts = take(L.ipad * 4);
   L.poly = take(static_cast<size_t>(kMaxCodes) * 4);
   L.bytes = off;
   return L;
 }
 
-// Code table word: the coefficients c0..c3 as signed bytes, c_k in byte k.
+// Code table word: the coefficients d0..d3 as signed bytes, d_k in byte k.
 uint32_t pack_poly(const Poly& c) {
   uint32_t w = 0;
   for (int k = 0; k <= kMaxDeg; ++k) {
@@ -351,11 +408,12 @@ uint32_t pack_poly(const Poly& c) {
   return w;
 }
 
-// Constants of a job: p, pinv, r1, qv, qs over the padded instances and the
-// packed code table, as one host image laid out like the workspace region
+// Constants of a job: p, pinv, r1, tv = (q - shift) mod p and its Shoup
+// constant over the padded instances, and the code table in powers of
+// t = q - shift, as one host image laid out like the workspace region
 // [p .. poly].
 std::vector<uint32_t> const_image(const JobLayout& L, const std::vector<Inst>& inst,
-                                  const std::vector<Poly>& codes) {
+                                  const std::vector<Poly>& codes, int shift) {
   const size_t base = L.p;
   if (codes.size() < 2 || !(codes[0].c[0] == 1 && codes[1].c[0] == -1))
     throw std::runtime_error("code table must start with +1 and -1");
@@ -364,25 +422,26 @@ std::vector<uint32_t> const_image(const JobLayout& L, const std::vector<Inst>& i
   uint32_t* p = at(L.p);
   uint32_t* pinv = at(L.pinv);
   uint32_t* r1 = at(L.r1);
-  uint32_t* qv = at(L.qv);
-  uint32_t* qs = at(L.qs);
+  uint32_t* tv = at(L.tv);
+  uint32_t* ts = at(L.ts);
   uint32_t* poly = at(L.poly);
-  for (size_t c = 0; c < codes.size(); ++c) poly[c] = pack_poly(codes[c]);
+  for (size_t c = 0; c < codes.size(); ++c) poly[c] = pack_poly(shift_basis(codes[c], shift));
   for (int k = 0; k < L.ipad; ++k) {
     const Inst& in = inst[k < L.I ? k : 0];
     p[k] = in.p;
     pinv[k] = neg_inv_2_32(in.p);
     r1[k] = static_cast<uint32_t>((uint64_t(1) << 32) % in.p);
-    qv[k] = in.q % in.p;
-    qs[k] = shoup_of(qv[k], in.p);
+    const int64_t sm = ((static_cast<int64_t>(shift) % in.p) + in.p) % in.p;
+    tv[k] = static_cast<uint32_t>((static_cast<int64_t>(in.q % in.p) + in.p - sm) % in.p);
+    ts[k] = shoup_of(tv[k], in.p);
   }
   return img;
 }
 
 // Pointers of one job's device state.
 struct JobPtrs {
-  uint32_t *x0, *x1, *w, *part, *part2, *p, *pinv, *r1, *qv, *qs, *poly;
-  InstConsts ic() const { return InstConsts{p, pinv, qv, qs, reinterpret_cast<const int32_t*>(poly)}; }
+  uint32_t *x0, *x1, *w, *part, *part2, *p, *pinv, *r1, *tv, *ts, *poly;
+  InstConsts ic() const { return InstConsts{p, pinv, tv, ts, reinterpret_cast<const int32_t*>(poly)}; }
 };
 
 JobPtrs job_ptrs(const JobLayout& L, void* base) {
@@ -396,8 +455,8 @@ JobPtrs job_ptrs(const JobLayout& L, void* base) {
   j.p = reinterpret_cast<uint32_t*>(b + L.p);
   j.pinv = reinterpret_cast<uint32_t*>(b + L.pinv);
   j.r1 = reinterpret_cast<uint32_t*>(b + L.r1);
-  j.qv = reinterpret_cast<uint32_t*>(b + L.qv);
-  j.qs = reinterpret_cast<uint32_t*>(b + L.qs);
+  j.tv = reinterpret_cast<uint32_t*>(b + L.tv);
+  j.ts = reinterpret_cast<uint32_t*>(b + L.ts);
   j.poly = reinterpret_cast<uint32_t*>(b + L.poly);
   return j;
 }
@@ -1000,7 +1059,7 @@ int strip_async_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, c
   j.L = job_layout(lattice, m, I, t, kMaxCodes, rows_tile_of(t));
   j.P = job_ptrs(j.L, ws);
   j.d_out = d_out;
-  std::vector<uint32_t> img = const_image(j.L, inst, j.fam->codes);
+  std::vector<uint32_t> img = const_image(j.L, inst, j.fam->codes, j.fam->shift);
   upload(static_cast<char*>(ws) + j.L.p, img.data(), img.size() * 4, st);
   int* row_ctr = reinterpret_cast<int*>(static_cast<char*>(ws) + j.L.bytes);
   if (mode == CHROM_MODE_BATCHED) {
@@ -1144,7 +1203,7 @@ int batch_impl(const chrom_job* jobs, int njobs, const chrom_tuning* tune, void*
     j.P = job_ptrs(j.L, base);
     j.d_out = jb.d_out;
     if (jb.n_max > 0) {
-      std::vector<uint32_t> img = const_image(j.L, inst, j.fam->codes);
+      std::vector<uint32_t> img = const_image(j.L, inst, j.fam->codes, j.fam->shift);
       upload(static_cast<char*>(base) + j.L.p, img.data(), img.size() * 4, st);
     }
     progs[k] = strip_program(j, jb.n_max);
@@ -1209,7 +1268,7 @@ int server_step_impl(chrom_slot* slots, int nslots, int rows, const chrom_tuning
     int last_row = std::min(sl.n_max - 1, first + rows - 1);  // 0-based out rows to produce
     if (first == 0) {
       std::vector<Inst> inst = make_instances(sl.q_points, sl.nq, sl.primes, sl.np);
-      std::vector<uint32_t> img = const_image(L, inst, j.fam->codes);
+      std::vector<uint32_t> img = const_image(L, inst, j.fam->codes, j.fam->shift);
       upload(static_cast<char*>(sl.d_state) + L.p, img.data(), img.size() * 4, st);
       int red = add_setup(progs[k], j);
       if (last_row >= 1) add_rows(progs[k], j, 1, last_row, red, red);

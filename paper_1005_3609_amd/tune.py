@@ -135,8 +135,8 @@ def main():
     w = W.workload(args.workload)
     space = None
     if args.quick:
-        space = dict(lanes_v=[2], targets_per_wave=[4, 8, 16], waves_per_block=[4], xcd_order=[1],
-                     unroll=[4, 8], streams=[1, 3], fuse=[1, 2, 3], mode=["graph"])
+        space = dict(lanes_v=[2], targets_per_wave=[4, 8], waves_per_block=[4], xcd_order=[1],
+                     unroll=[4, 8], streams=[1, 3], fuse=[1, 2], mode=["graph"])
     for lat, m, n in w["strips"]:
         api.prepare(lat, m)
         res = tune(lat, m, n, w["q_points"], w["primes"], space=space, steps=args.steps, path=args.cache,
