@@ -99,8 +99,9 @@ struct DevCsr {
 //   t = q - s for the job's basis shift s, ts[inst] = floor(tv 2^32 / p).
 // Coefficient codes: poly[code] holds the integer coefficients d0..d3 of the
 // code's polynomial written in powers of t, d0 + d1 t + d2 t^2 + d3 t^3, as
-// four signed bytes (d_k in byte k); 64 words, unused codes zero.  Code 0 is
-// +1 and code 1 is -1 (constants, so the same in every basis).
+// four signed bytes (d_k in byte k); poly[64 + code] holds the same as masks
+// (see accumulate); 2 x 64 words, unused codes zero.  Code 0 is +1 and code
+// 1 is -1 (constants, so the same in every basis).
 struct InstConsts {
   const uint32_t* p;
   const uint32_t* pinv;
@@ -213,28 +214,51 @@ __device__ __forceinline__ void add_multiple(uint32_t (&A)[V], const uint32_t (&
 // q - 2 = t), c = sum_k d_k t^k, so a target row's value sum_e c_e x_e equals
 // sum_k t^k A_k with A_k = sum_e d_{e,k} x_e.  Each entry adds small
 // multiples of its source row to the A_k (modular adds only); the row is
-// finished by Horner's rule in t (at most three Shoup products).  `pw` is the wavefront's copy of the code
-// table (lane c holds code c); `deg` tracks the row's highest power of q.
-template <int V>
+// finished by Horner's rule in t (at most three Shoup products).
+//
+// The wavefront keeps two copies of the code table, one word per lane:
+// `pm` (lane c: code c's unit coefficients as masks -- bit k for d_k = +1,
+// bit 4+k for d_k = -1 -- bit 8 when some |d_k| > 1, degree in bits 12-13)
+// and `pw` (lane c: d_0..d_3 as signed bytes, for the rare codes with bit 8).
+// Every branch below updates one A_k in place, so the common paths compile
+// to the modular additions alone.  Launches whose codes all have unit
+// coefficients use the G = false instance, which has no general path at all
+// (its merges would cost register copies on every entry).
+constexpr uint32_t kMaskGeneral = 0x100u;
+
+template <int V, bool G>
 __device__ __forceinline__ void accumulate(uint32_t (&A)[4][V], const uint32_t (&x)[V], uint32_t code,
-                                           const uint32_t (&p)[V], int pw, int& deg) {
-  if (code == 0) {
-#pragma unroll
-    for (int j = 0; j < V; ++j) A[0][j] = add_mod(A[0][j], x[j], p[j]);
-  } else if (code == 1) {
-#pragma unroll
-    for (int j = 0; j < V; ++j) A[0][j] = sub_mod(A[0][j], x[j], p[j]);
-  } else {
+                                           const uint32_t (&p)[V], int pw, int pm, int& deg) {
+  const uint32_t m = static_cast<uint32_t>(__builtin_amdgcn_readlane(pm, static_cast<int>(code)));
+  if (G && (m & kMaskGeneral)) {
     const int cw = __builtin_amdgcn_readlane(pw, static_cast<int>(code));
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int c = static_cast<int>(static_cast<int8_t>(static_cast<uint32_t>(cw) >> (8 * k)));
-      if (c != 0) {
-        add_multiple<V>(A[k], x, c, p);
-        deg = deg > k ? deg : k;
+      if (c != 0) add_multiple<V>(A[k], x, c, p);
+    }
+  } else {
+    // Real (uniform) branches, up to the code's own degree: the empty
+    // volatile statements keep the compiler from computing every arm and
+    // selecting.
+    const int dc = static_cast<int>((m >> 12) & 3u);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (k > dc) break;
+      if (m & (1u << k)) {
+        asm volatile("");
+#pragma unroll
+        for (int j = 0; j < V; ++j) A[k][j] = add_mod(A[k][j], x[j], p[j]);
+      }
+      if (m & (16u << k)) {
+        asm volatile("");
+#pragma unroll
+        for (int j = 0; j < V; ++j) A[k][j] = sub_mod(A[k][j], x[j], p[j]);
       }
     }
   }
+  const int dk = static_cast<int>((m >> 12) & 3u);
+  deg = deg > dk ? deg : dk;
 }
 
 // sum_k t^k A_k mod p by Horner's rule; A_k = 0 for k > deg.
@@ -266,7 +290,7 @@ __device__ __forceinline__ void horner(uint32_t (&v)[V], const uint32_t (&A)[4][
 // rows themselves, oldest first.  Row boundaries are uniform, so each
 // finished row is stored without divergence; rows with no entries are stored
 // as zero.
-template <int V, int U>
+template <int V, int U, bool G>
 __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* lds) {
   constexpr int W = 64 * V;
   const int lane = lane_id(), wave = wave_id();
@@ -277,6 +301,7 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
   load_v<V>(a.ic.tv + inst0, tv);
   load_v<V>(a.ic.ts + inst0, ts);
   const int pw = a.ic.poly[lane];
+  const int pm = a.ic.poly[kCodes + lane];
   const uint32_t* in = a.in + chunk * a.in_cstride;     // uniform bases
   uint32_t* out = a.out + chunk * a.out_cstride;
   const bool fused = a.w != nullptr;
@@ -340,7 +365,7 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
         for (int u = 0; u < U; ++u) {
           if (k0 + u < n) {
             while (base + k0 + u >= row_end) flush();
-            accumulate<V>(A, x[u], w[u] >> kEntSrcBits, p, pw, deg);
+            accumulate<V, G>(A, x[u], w[u] >> kEntSrcBits, p, pw, pm, deg);
           }
         }
       };
@@ -491,12 +516,12 @@ __device__ __forceinline__ void tile_chunk(int xcd, int chunk0, int& tile, int& 
   chunk = chunk0 + b / gridDim.x;
 }
 
-template <int V, int U>
+template <int V, int U, bool G>
 __global__ void __launch_bounds__(512) k_gather(GatherArgs a, int xcd, int chunk0) {
   __shared__ uint32_t lds[8 * 64 * V];
   int tile, chunk;
   tile_chunk(xcd, chunk0, tile, chunk);
-  gather_tile<V, U>(a, chunk, tile, lds);
+  gather_tile<V, U, G>(a, chunk, tile, lds);
 }
 
 template <int V>
@@ -609,7 +634,7 @@ struct Step {
   int op;
   int ntiles;
   int chunk;               // chunk index handed to the tile body
-  int pad_;
+  int general;             // gather: needs the general coefficient path (host-side kernel choice)
   union {
     GatherArgs g;
     DotArgs d;
@@ -628,7 +653,7 @@ struct GroupArgs {
   int xcd;                 // remap block ids to contiguous per-XCD ranges
 };
 
-template <int V, int U>
+template <int V, int U, bool G>
 __global__ void __launch_bounds__(512) k_grouped(GroupArgs g) {
   __shared__ uint32_t lds[8 * 64 * V];
   const int b = g.xcd ? xcd_contiguous(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
@@ -641,7 +666,7 @@ __global__ void __launch_bounds__(512) k_grouped(GroupArgs g) {
   const int tile = __builtin_amdgcn_readfirstlane(b - g.tile_start[k]);
   const Step& st = g.steps[k];
   switch (st.op) {
-    case kOpGather: gather_tile<V, U>(st.u.g, st.chunk, tile, lds); break;
+    case kOpGather: gather_tile<V, U, G>(st.u.g, st.chunk, tile, lds); break;
     case kOpDot: dot_tile<V>(st.u.d, st.chunk, tile, lds); break;
     case kOpFill: fill_tile<V>(st.u.f, st.chunk, tile); break;
     case kOpReduce1: reduce1_tile<V>(st.u.r, st.chunk, tile, lds); break;

@@ -80,6 +80,7 @@ struct DevFamily {
   std::vector<DevCsr> fac;
   std::vector<Poly> codes;   // extends the base table
   int shift = 0;             // kernels expand the codes in powers of t = q - shift
+  bool general = false;      // some coefficient its factors use has magnitude above 1
 };
 
 struct DevMaps {
@@ -174,28 +175,40 @@ int64_t entry_cost(const Poly& d) {
   return ops;
 }
 
-// Basis shift with the fewest modular additions over the family's entries
-// (ties to the smallest |s|).
-int choose_shift(const std::vector<Poly>& codes, const std::vector<Csr>& fac) {
+// Basis shift for a family: one under which every coefficient its factors
+// use is 0 or +-1 if there is one (their launches then run the factor kernel
+// without its general path), else any; among those, the fewest modular
+// additions over the family's entries, ties to the smallest |s|.  Every code
+// of the table (also those only the read-out factors use) must fit the
+// packed range.
+int choose_shift(const std::vector<Poly>& codes, const std::vector<Csr>& fac, bool& general) {
   std::vector<int64_t> count(codes.size(), 0);
   for (const Csr& c : fac)
     for (uint32_t e : c.ent) ++count[e >> kSrcBits];
   int best = 0;
   int64_t best_cost = -1;
+  bool best_general = true;
   for (int s : {0, 1, -1, 2, -2, 3, -3, 4, -4}) {
     int64_t cost = 0;
-    bool ok = true;
+    bool ok = true, gen = false;
     for (size_t c = 0; c < codes.size() && ok; ++c) {
-      const int64_t e = entry_cost(shift_basis(codes[c], s));
+      const Poly d = shift_basis(codes[c], s);
+      const int64_t e = entry_cost(d);
       if (e < 0) ok = false;
       cost += e * count[c];
+      if (count[c] > 0)
+        for (int k = 0; k <= kMaxDeg; ++k) gen = gen || d.c[k] > 1 || d.c[k] < -1;
     }
-    if (ok && (best_cost < 0 || cost < best_cost)) {
+    if (!ok) continue;
+    const bool better = best_cost < 0 || (best_general && !gen) || (best_general == gen && cost < best_cost);
+    if (better) {
       best = s;
       best_cost = cost;
+      best_general = gen;
     }
   }
   if (best_cost < 0) throw std::runtime_error("no basis shift keeps the coefficient polynomials in the packed range");
+  general = best_general;
   return best;
 }
 
@@ -208,7 +221,7 @@ const DevFamily& dev_family(const DevMaps& dm, int k) {
   if (k == 1) {
     df->fac.assign(dm.fwd, dm.fwd + dm.m);
     df->codes = dm.codes;
-    df->shift = choose_shift(dm.codes, get_maps(dm.lattice, dm.m).fwd);
+    df->shift = choose_shift(dm.codes, get_maps(dm.lattice, dm.m).fwd, df->general);
   } else {
     const Family& f = get_maps(dm.lattice, dm.m).family(k);
     size_t bytes = 0;
@@ -218,7 +231,7 @@ const DevFamily& dev_family(const DevMaps& dm, int k) {
     df->fac.resize(f.fac.size());
     for (size_t i = 0; i < f.fac.size(); ++i) upload_csr(f.fac[i], df->fac[i], cur);
     df->codes = f.codes;
-    df->shift = choose_shift(f.codes, f.fac);
+    df->shift = choose_shift(f.codes, f.fac, df->general);
   }
   const DevFamily& ref = *df;
   dm.fam.emplace(k, std::move(df));
@@ -393,7 +406,7 @@ JobLayout job_layout(int lattice, int m, int I, const Tune& t, int ncodes, int r
   L.r1 = take(L.ipad * 4);
   L.tv = take(L.ipad * 4);
   L.ts = take(L.ipad * 4);
-  L.poly = take(static_cast<size_t>(kMaxCodes) * 4);
+  L.poly = take(static_cast<size_t>(kMaxCodes) * 8);
   L.bytes = off;
   return L;
 }
@@ -408,6 +421,20 @@ uint32_t pack_poly(const Poly& c) {
   return w;
 }
 
+// Mask word of a code (kernel side: accumulate): bit k for d_k = +1, bit
+// 4 + k for d_k = -1, bit 8 when some |d_k| > 1, the degree in bits 12-13.
+uint32_t pack_mask(const Poly& d) {
+  uint32_t m = 0;
+  int deg = 0;
+  for (int k = 0; k <= kMaxDeg; ++k) {
+    if (d.c[k] == 1) m |= 1u << k;
+    else if (d.c[k] == -1) m |= 16u << k;
+    else if (d.c[k] != 0) m |= 0x100u;
+    if (d.c[k] != 0) deg = k;
+  }
+  return m | (static_cast<uint32_t>(deg) << 12);
+}
+
 // Constants of a job: p, pinv, r1, tv = (q - shift) mod p and its Shoup
 // constant over the padded instances, and the code table in powers of
 // t = q - shift, as one host image laid out like the workspace region
@@ -417,7 +444,7 @@ std::vector<uint32_t> const_image(const JobLayout& L, const std::vector<Inst>& i
   const size_t base = L.p;
   if (codes.size() < 2 || !(codes[0].c[0] == 1 && codes[1].c[0] == -1))
     throw std::runtime_error("code table must start with +1 and -1");
-  std::vector<uint32_t> img((L.poly + static_cast<size_t>(kMaxCodes) * 4 - base) / 4, 0);
+  std::vector<uint32_t> img((L.poly + static_cast<size_t>(kMaxCodes) * 8 - base) / 4, 0);
   auto at = [&](size_t off) { return img.data() + (off - base) / 4; };
   uint32_t* p = at(L.p);
   uint32_t* pinv = at(L.pinv);
@@ -425,7 +452,11 @@ std::vector<uint32_t> const_image(const JobLayout& L, const std::vector<Inst>& i
   uint32_t* tv = at(L.tv);
   uint32_t* ts = at(L.ts);
   uint32_t* poly = at(L.poly);
-  for (size_t c = 0; c < codes.size(); ++c) poly[c] = pack_poly(shift_basis(codes[c], shift));
+  for (size_t c = 0; c < codes.size(); ++c) {
+    const Poly d = shift_basis(codes[c], shift);
+    poly[c] = pack_poly(d);
+    poly[kMaxCodes + c] = pack_mask(d);
+  }
   for (int k = 0; k < L.ipad; ++k) {
     const Inst& in = inst[k < L.I ? k : 0];
     p[k] = in.p;
@@ -513,9 +544,11 @@ int push(Program& pg, const Step& s, int d0, int d1) {
   return static_cast<int>(pg.steps.size()) - 1;
 }
 
-Step gather_step(const JobCtx& j, const DevCsr& c, const uint32_t* in, uint32_t* out, long out_cstride, bool fused) {
+Step gather_step(const JobCtx& j, const DevCsr& c, const uint32_t* in, uint32_t* out, long out_cstride, bool fused,
+                 bool general) {
   Step s{};
   s.op = kOpGather;
+  s.general = general ? 1 : 0;
   s.ntiles = tiles_for(c.n_rows, j.L.rows_tile);
   GatherArgs& a = s.u.g;
   a.csr = c;
@@ -567,7 +600,7 @@ int add_setup(Program& pg, const JobCtx& j) {
   uint32_t* oth = j.P.x1;
   for (int i = L.m; i >= 1; --i) {
     const bool to_w = (i == 1);
-    Step g = gather_step(j, j.dm->last[i - 1], cur, to_w ? j.P.w : oth, to_w ? cs_w : cs_x, false);
+    Step g = gather_step(j, j.dm->last[i - 1], cur, to_w ? j.P.w : oth, to_w ? cs_w : cs_x, false, true);
     last = push(pg, g, last, -1);
     std::swap(cur, oth);
   }
@@ -601,7 +634,7 @@ void add_rows(Program& pg, const JobCtx& j, int r_first, int r_last, int after, 
     int tm = -1;
     for (int i = 1; i <= nf; ++i) {
       const bool fused = (i == nf);
-      Step g = gather_step(j, j.fam->fac[i - 1], cur, oth, cs_x, fused);
+      Step g = gather_step(j, j.fam->fac[i - 1], cur, oth, cs_x, fused, j.fam->general);
       tm = push(pg, g, after, fused ? prev_reduce : -1);
       after = tm;
       std::swap(cur, oth);
@@ -628,7 +661,12 @@ void launch_step_vu(const Step& s, int c0, int nch, int wpb, int xcd, hipStream_
                     long row_stride) {
   dim3 grid(s.ntiles, nch), block(64 * wpb);
   switch (s.op) {
-    case kOpGather: hipLaunchKernelGGL((k_gather<V, U>), grid, block, 0, st, s.u.g, xcd, c0); break;
+    case kOpGather:
+      if (s.general)
+        hipLaunchKernelGGL((k_gather<V, U, true>), grid, block, 0, st, s.u.g, xcd, c0);
+      else
+        hipLaunchKernelGGL((k_gather<V, U, false>), grid, block, 0, st, s.u.g, xcd, c0);
+      break;
     case kOpDot: hipLaunchKernelGGL(k_dot<V>, grid, block, 0, st, s.u.d, xcd, c0); break;
     case kOpFill: hipLaunchKernelGGL(k_fill<V>, grid, block, 0, st, s.u.f, c0); break;
     case kOpReduce1:
@@ -863,13 +901,21 @@ void launch_stages(const StageImage& im, const Step* d_steps, const int* d_tiles
     if (im.nsteps[k] == 0) continue;
     GroupArgs g{d_steps + im.step_off[k], d_tiles + im.tile_off[k], im.nsteps[k], t.xcd};
     dim3 grid(im.ntiles[k]), block(64 * t.wpb);
-    switch (t.V * 10 + t.U) {
-      case 14: hipLaunchKernelGGL((k_grouped<1, 4>), grid, block, 0, st, g); break;
-      case 18: hipLaunchKernelGGL((k_grouped<1, 8>), grid, block, 0, st, g); break;
-      case 24: hipLaunchKernelGGL((k_grouped<2, 4>), grid, block, 0, st, g); break;
-      case 28: hipLaunchKernelGGL((k_grouped<2, 8>), grid, block, 0, st, g); break;
-      case 44: hipLaunchKernelGGL((k_grouped<4, 4>), grid, block, 0, st, g); break;
-      default: hipLaunchKernelGGL((k_grouped<4, 8>), grid, block, 0, st, g); break;
+    bool general = false;
+    for (int i = 0; i < im.nsteps[k]; ++i) general = general || im.steps[im.step_off[k] + i].general;
+    switch (t.V * 100 + t.U * 10 + (general ? 1 : 0)) {
+      case 140: hipLaunchKernelGGL((k_grouped<1, 4, false>), grid, block, 0, st, g); break;
+      case 141: hipLaunchKernelGGL((k_grouped<1, 4, true>), grid, block, 0, st, g); break;
+      case 180: hipLaunchKernelGGL((k_grouped<1, 8, false>), grid, block, 0, st, g); break;
+      case 181: hipLaunchKernelGGL((k_grouped<1, 8, true>), grid, block, 0, st, g); break;
+      case 240: hipLaunchKernelGGL((k_grouped<2, 4, false>), grid, block, 0, st, g); break;
+      case 241: hipLaunchKernelGGL((k_grouped<2, 4, true>), grid, block, 0, st, g); break;
+      case 280: hipLaunchKernelGGL((k_grouped<2, 8, false>), grid, block, 0, st, g); break;
+      case 281: hipLaunchKernelGGL((k_grouped<2, 8, true>), grid, block, 0, st, g); break;
+      case 440: hipLaunchKernelGGL((k_grouped<4, 4, false>), grid, block, 0, st, g); break;
+      case 441: hipLaunchKernelGGL((k_grouped<4, 4, true>), grid, block, 0, st, g); break;
+      case 480: hipLaunchKernelGGL((k_grouped<4, 8, false>), grid, block, 0, st, g); break;
+      default: hipLaunchKernelGGL((k_grouped<4, 8, true>), grid, block, 0, st, g); break;
     }
     HIPX(hipGetLastError());
   }
@@ -1197,7 +1243,7 @@ int batch_impl(const chrom_job* jobs, int njobs, const chrom_tuning* tune, void*
     JobCtx j;
     j.dm = &dm;
     j.fam = &dev_family(dm, t.fuse);
-    j.t = t;
+      j.t = t;
     j.L = bp.layouts[k];
     void* base = static_cast<char*>(ws) + bp.job_off[k];
     j.P = job_ptrs(j.L, base);
@@ -1259,7 +1305,7 @@ int server_step_impl(chrom_slot* slots, int nslots, int rows, const chrom_tuning
     JobCtx j;
     j.dm = &dm;
     j.fam = &dev_family(dm, t.fuse);
-    j.t = t;
+      j.t = t;
     j.L = L;
     j.P = job_ptrs(L, sl.d_state);
     j.d_out = sl.d_out;
