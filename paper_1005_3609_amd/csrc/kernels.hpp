@@ -79,6 +79,20 @@ __device__ __forceinline__ int xcd_contiguous(int b, int nb) {
   return xcd < tall ? xcd * per + local : tall * per + (xcd - tall) * (per - 1) + local;
 }
 
+// Block-id remaps (all bijections on [0, nb)): mode 1 gives each XCD one
+// contiguous range; modes 2 and 3 give each XCD runs of 4 or 16 consecutive
+// ids, the runs dealt round-robin (neighbouring tiles share an L2 while every
+// XCD still samples the whole launch); ids past the last whole round stay.
+__device__ __forceinline__ int xcd_remap(int b, int nb, int mode) {
+  if (mode == 1) return xcd_contiguous(b, nb);
+  constexpr int X = 8;
+  const int G = mode == 2 ? 4 : 16;
+  const int nfull = nb / (X * G) * (X * G);
+  if (b >= nfull) return b;
+  const int x = b % X, k = b / X;
+  return ((k / G) * X + x) * G + k % G;
+}
+
 __device__ __forceinline__ int wave_id() {
   return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
 }
@@ -281,11 +295,11 @@ __device__ __forceinline__ void horner(uint32_t (&v)[V], const uint32_t (&A)[4][
 }
 
 // One wavefront computes target rows [r0, r1) of one chunk.  Its row
-// pointers (lane j holds row_ptr[r0 + j]) and up to 64 entry words at a time
-// (lane l holds one word) arrive with coalesced vector loads and are
-// broadcast with readlane; source rows are loaded U entries at a time, one
-// group ahead of the group being consumed, so up to 2U W*4-byte gathers are
-// in flight per wavefront.  The inner loop loads nothing else: coefficients
+// pointers (lane j holds row_ptr[r0 + j]) and its entry words (64 per
+// register, lane l holding one) arrive with coalesced vector loads and are
+// broadcast with readlane; source rows are loaded U entries at a time, P
+// groups ahead of the group being consumed, so up to P U W*4-byte gathers
+// are in flight per wavefront.  The inner loop loads nothing else: coefficients
 // come from registers (see accumulate), so the only waits are for the source
 // rows themselves, oldest first.  Row boundaries are uniform, so each
 // finished row is stored without divergence; rows with no entries are stored
@@ -340,48 +354,61 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
       ++row;
       if (row < r1) row_end = __builtin_amdgcn_readlane(rp, row - r0 + 1);
     };
-    // Entries stream through in batches of 64 words; inside a batch, groups of
-    // U source rows are software-pipelined: group g+1 is issued before group
-    // g is consumed.
-    for (int base = beg; base < end; base += 64) {
-      const int n = min(64, end - base);
-      const uint32_t ev = (lane < n) ? a.csr.ent[base + lane] : 0u;
-      uint32_t wa[U], wb[U];
-      uint32_t xa[U][V], xb[U][V];
-      // Every group issues U loads; slots past the batch repeat its last
-      // entry (a cache hit), so the number of loads in flight is fixed.
-      auto issue = [&](int k0, uint32_t (&w)[U], uint32_t (&x)[U][V]) {
+    // One continuous entry stream [beg, end) in groups of U.  P groups are in
+    // flight: group g + P - 1 is issued before group g is consumed, and every
+    // issue is unconditional (slots past `end` repeat the last entry, a cache
+    // hit), so each wait is for a fixed count of newer loads.  Entry words
+    // come through a window of 128 (ev0: [base, base + 64), ev1: the next
+    // 64); the window moves when the issue point leaves ev0, and the next
+    // words are requested then, a full window ahead of their use.  U divides
+    // 64, so no group straddles the two halves.
+    constexpr int P = (U == 4) ? 3 : 2;
+    int base = beg;
+    uint32_t ev0 = (base + lane < end) ? a.csr.ent[base + lane] : 0u;
+    uint32_t ev1 = (base + 64 + lane < end) ? a.csr.ent[base + 64 + lane] : 0u;
+    uint32_t wq[P][U];
+    uint32_t xq[P][U][V];
+    auto issue = [&](int g, uint32_t (&w)[U], uint32_t (&x)[U][V]) {
+      const int e0 = beg + g * U;
+      if (e0 - base >= 64 && base + 64 < end) {
+        base += 64;
+        ev0 = ev1;
+        ev1 = (base + 64 + lane < end) ? a.csr.ent[base + 64 + lane] : 0u;
+      }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          w[u] = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ev), min(k0 + u, n - 1)));
-          load_row<V>(in, (w[u] & kEntSrcMask) * (4u * W) + boff, x[u]);
-          // Keep the loads in entry order: completions are counted in issue
-          // order, so entry u must not be issued after entry u + 1.
-          __builtin_amdgcn_sched_barrier(0);
+      for (int u = 0; u < U; ++u) {
+        w[u] = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ev0), min(e0 + u, end - 1) - base));
+        load_row<V>(in, (w[u] & kEntSrcMask) * (4u * W) + boff, x[u]);
+        // Keep the loads in entry order: completions are counted in issue
+        // order, so entry u must not be issued after entry u + 1.
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    };
+    auto consume = [&](int g, const uint32_t (&w)[U], const uint32_t (&x)[U][V]) {
+      const int e0 = beg + g * U;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (e0 + u < end) {
+          while (e0 + u >= row_end) flush();
+          accumulate<V, G>(A, x[u], w[u] >> kEntSrcBits, p, pw, pm, deg);
         }
-      };
-      auto consume = [&](int k0, const uint32_t (&w)[U], const uint32_t (&x)[U][V]) {
+      }
+    };
+    if (beg < end) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          if (k0 + u < n) {
-            while (base + k0 + u >= row_end) flush();
-            accumulate<V, G>(A, x[u], w[u] >> kEntSrcBits, p, pw, pm, deg);
+      for (int s = 0; s < P - 1; ++s) issue(s, wq[s], xq[s]);
+      for (int g = 0;;) {
+        bool done = false;
+#pragma unroll
+        for (int s = 0; s < P; ++s) {
+          if (!done) {
+            issue(g + P - 1, wq[(s + P - 1) % P], xq[(s + P - 1) % P]);
+            consume(g, wq[s], xq[s]);
+            ++g;
+            done = beg + g * U >= end;
           }
         }
-      };
-      // Each consume is preceded by exactly one unconditional issue of the
-      // next group, so every wait is for a fixed count of newer loads; the
-      // group issued past the batch end only repeats its last entry.
-      issue(0, wa, xa);
-      for (int k = 0;;) {
-        issue(k + U, wb, xb);
-        consume(k, wa, xa);
-        k += U;
-        if (k >= n) break;
-        issue(k + U, wa, xa);
-        consume(k, wb, xb);
-        k += U;
-        if (k >= n) break;
+        if (done) break;
       }
     }
     while (row < r1) flush();
@@ -511,7 +538,7 @@ __device__ void reduce2_tile(const ReduceArgs& a, int chunk, uint32_t* out) {
 // first remapped so each XCD sweeps a contiguous range.
 __device__ __forceinline__ void tile_chunk(int xcd, int chunk0, int& tile, int& chunk) {
   int b = blockIdx.y * gridDim.x + blockIdx.x;
-  if (xcd) b = xcd_contiguous(b, gridDim.x * gridDim.y);
+  if (xcd) b = xcd_remap(b, gridDim.x * gridDim.y, xcd);
   tile = b % gridDim.x;
   chunk = chunk0 + b / gridDim.x;
 }
@@ -650,13 +677,13 @@ struct GroupArgs {
   const Step* steps;
   const int* tile_start;   // nsteps + 1 prefix sums of ntiles
   int nsteps;
-  int xcd;                 // remap block ids to contiguous per-XCD ranges
+  int xcd;                 // block-id remap mode (xcd_remap)
 };
 
 template <int V, int U, bool G>
 __global__ void __launch_bounds__(512) k_grouped(GroupArgs g) {
   __shared__ uint32_t lds[8 * 64 * V];
-  const int b = g.xcd ? xcd_contiguous(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
+  const int b = g.xcd ? xcd_remap(blockIdx.x, gridDim.x, g.xcd) : static_cast<int>(blockIdx.x);
   int lo = 0, hi = g.nsteps - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;

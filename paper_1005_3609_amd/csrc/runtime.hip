@@ -343,7 +343,7 @@ Tune resolve(const chrom_tuning* t) {
   if (t->lanes_v) r.V = t->lanes_v;
   if (t->targets_per_wave) r.rpw = t->targets_per_wave;
   if (t->waves_per_block) r.wpb = t->waves_per_block;
-  if (t->xcd_order < 0 || t->xcd_order > 2) throw ArgError("xcd_order must be 0, 1 or 2");
+  if (t->xcd_order < 0 || t->xcd_order > 4) throw ArgError("xcd_order must be in 0..4");
   if (t->xcd_order) r.xcd = t->xcd_order - 1;
   if (t->unroll) r.U = t->unroll;
   if (t->streams) r.streams = t->streams;
