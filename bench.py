@@ -199,7 +199,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", default=None, choices=["batched", "graph", "grouped"])
-    for k in ("lanes-v", "targets-per-wave", "waves-per-block", "xcd-order", "unroll", "streams", "fuse"):
+    for k in ("lanes-v", "targets-per-wave", "waves-per-block", "xcd-order", "unroll", "streams", "fuse", "stage"):
         ap.add_argument("--" + k, type=int, default=None)
     ap.add_argument("--untuned", action="store_true", help="library defaults instead of the tuned table")
     ap.add_argument("--roofline-rows", type=int, default=10)
@@ -238,7 +238,7 @@ def main():
     mode = args.mode or tune.pop("mode", "graph")
     tune.pop("mode", None)
     tune.pop("ms", None)
-    for k in ("lanes_v", "targets_per_wave", "waves_per_block", "xcd_order", "unroll", "streams", "fuse"):
+    for k in ("lanes_v", "targets_per_wave", "waves_per_block", "xcd_order", "unroll", "streams", "fuse", "stage"):
         v = getattr(args, k)
         if v is not None:
             tune[k] = v

@@ -77,6 +77,9 @@ typedef struct chrom_tuning {
                            graph and batched modes */
   int fuse;             /* consecutive factors applied per launch as one precomputed
                            product map, 1..3 (0 = 1) */
+  int stage;            /* 1: each workgroup first copies the distinct source rows of its
+                           tile of target states into LDS (batched and graph modes, lanes_v
+                           1 or 2; the read-out factor is not staged); 0: direct gathers */
 } chrom_tuning;
 
 /* ------------------------------------------------------------------------

@@ -25,7 +25,8 @@ class ChromError(RuntimeError):
 
 class Tuning(C.Structure):
     _fields_ = [("lanes_v", C.c_int), ("targets_per_wave", C.c_int), ("waves_per_block", C.c_int),
-                ("xcd_order", C.c_int), ("unroll", C.c_int), ("streams", C.c_int), ("fuse", C.c_int)]
+                ("xcd_order", C.c_int), ("unroll", C.c_int), ("streams", C.c_int), ("fuse", C.c_int),
+                ("stage", C.c_int)]
 
 
 class Job(C.Structure):
@@ -127,4 +128,4 @@ def tuning(t) -> "Tuning | None":
         return t
     return Tuning(int(t.get("lanes_v", 0)), int(t.get("targets_per_wave", 0)), int(t.get("waves_per_block", 0)),
                   int(t.get("xcd_order", 0)), int(t.get("unroll", 0)), int(t.get("streams", 0)),
-                  int(t.get("fuse", 0)))
+                  int(t.get("fuse", 0)), int(t.get("stage", 0)))

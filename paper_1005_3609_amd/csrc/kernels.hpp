@@ -138,6 +138,11 @@ struct GatherArgs {
   uint32_t* partial;
   long p_cstride;
   int rows_per_wave;
+  // Staged tiles (tile_row0 == nullptr: direct gathers).  Entry words then
+  // hold a slot of the tile's source list instead of a source state.
+  const int32_t* tile_row0;
+  const int32_t* tile_src0;
+  const int32_t* tile_src;
 };
 
 struct DotArgs {
@@ -436,6 +441,108 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
   if (fused) block_reduce_store<V>(red, p, a.partial + chunk * a.p_cstride + static_cast<long>(tile) * W, lds);
 }
 
+// Staged variant of gather_tile: the workgroup first copies the distinct
+// source rows of its tile (one W*4-byte row per slot, listed ascending) into
+// LDS with independent loads spread over its wavefronts, then each
+// wavefront computes a contiguous share of the tile's rows reading its
+// sources from LDS.  Sources shared by several rows of the tile are read
+// from memory once; the coefficient handling and row finishing are those of
+// gather_tile.  `slots` is the LDS area (max_slots rows of W words).
+template <int V, int U, bool G>
+__device__ void stage_tile(const GatherArgs& a, int chunk, int tile, uint32_t* slots) {
+  constexpr int W = 64 * V;
+  const int lane = lane_id(), wave = wave_id();
+  const int nw = blockDim.x >> 6;
+  const int inst0 = chunk * W + lane * V;
+  const uint32_t boff = static_cast<uint32_t>(lane) * (4u * V);
+  const uint32_t* in = a.in + chunk * a.in_cstride;
+  uint32_t* out = a.out + chunk * a.out_cstride;
+  // tile bounds (lanes 0/1 read the two ends, broadcast)
+  const int tr = a.tile_row0[tile + (lane & 1)];
+  const int ts = a.tile_src0[tile + (lane & 1)];
+  const int row0 = __builtin_amdgcn_readlane(tr, 0), row1 = __builtin_amdgcn_readlane(tr, 1);
+  const int s0 = __builtin_amdgcn_readlane(ts, 0), ns = __builtin_amdgcn_readlane(ts, 1) - s0;
+  // this wavefront's rows, and its row pointers and first entry words,
+  // requested before the staging loads so their latency overlaps them
+  const int per = (row1 - row0 + nw - 1) / nw;
+  const int r0 = min(row0 + wave * per, row1), r1 = min(r0 + per, row1);
+  const int nrows = r1 - r0;
+  const int rp = (lane <= nrows) ? a.csr.row_ptr[r0 + lane] : 0;
+  uint32_t p[V], tv[V], ts_[V];
+  load_v<V>(a.ic.p + inst0, p);
+  load_v<V>(a.ic.tv + inst0, tv);
+  load_v<V>(a.ic.ts + inst0, ts_);
+  const int pw = a.ic.poly[lane];
+  const int pm = a.ic.poly[kCodes + lane];
+  // phase 1: slot k of the tile goes to wavefront k % nw, U slots per batch;
+  // batch slots past the end repeat the last one (same data, same place)
+  for (int k0 = wave; k0 < ns; k0 += nw * U) {
+    const int sid = (lane < U) ? a.tile_src[s0 + min(k0 + lane * nw, ns - 1)] : 0;
+    uint32_t x[U][V];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t src = static_cast<uint32_t>(__builtin_amdgcn_readlane(sid, u));
+      load_row<V>(in, src * (4u * W) + boff, x[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = min(k0 + u * nw, ns - 1);
+#pragma unroll
+      for (int j = 0; j < V; ++j) slots[k * W + lane * V + j] = x[u][j];
+    }
+  }
+  __syncthreads();
+  // phase 2
+  if (nrows > 0) {
+    uint32_t A[4][V];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int j = 0; j < V; ++j) A[k][j] = 0;
+    int deg = 0;
+    const int beg = __builtin_amdgcn_readlane(rp, 0);
+    const int end = __builtin_amdgcn_readlane(rp, nrows);
+    int row = r0;
+    int row_end = __builtin_amdgcn_readlane(rp, 1);
+    auto flush = [&]() {
+      uint32_t v[V];
+      horner<V>(v, A, deg, tv, ts_, p);
+      store_row<V>(out, static_cast<uint32_t>(row) * (4u * W) + boff, v);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (k <= deg) {
+#pragma unroll
+          for (int j = 0; j < V; ++j) A[k][j] = 0;
+        }
+      deg = 0;
+      ++row;
+      if (row < r1) row_end = __builtin_amdgcn_readlane(rp, row - r0 + 1);
+    };
+    for (int base = beg; base < end; base += 64) {
+      const int n = min(64, end - base);
+      const uint32_t ev = (lane < n) ? a.csr.ent[base + lane] : 0u;
+      for (int k = 0; k < n; k += U) {
+        uint32_t w[U], x[U][V];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          w[u] = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ev), min(k + u, n - 1)));
+          const uint32_t* sl = slots + (w[u] & kEntSrcMask) * W + lane * V;
+#pragma unroll
+          for (int j = 0; j < V; ++j) x[u][j] = sl[j];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (k + u < n) {
+            while (base + k + u >= row_end) flush();
+            accumulate<V, G>(A, x[u], w[u] >> kEntSrcBits, p, pw, pm, deg);
+          }
+        }
+      }
+    }
+    while (row < r1) flush();
+  }
+}
+
 template <int V>
 __device__ void dot_tile(const DotArgs& a, int chunk, int tile, uint32_t* lds) {
   constexpr int W = 64 * V;
@@ -551,6 +658,15 @@ __global__ void __launch_bounds__(512) k_gather(GatherArgs a, int xcd, int chunk
   gather_tile<V, U, G>(a, chunk, tile, lds);
 }
 
+// grid (tiles, chunks); dynamic LDS: max_slots * 64 V words
+template <int V, int U, bool G>
+__global__ void __launch_bounds__(512) k_stage(GatherArgs a, int xcd, int chunk0) {
+  extern __shared__ uint32_t stage_lds[];
+  int tile, chunk;
+  tile_chunk(xcd, chunk0, tile, chunk);
+  stage_tile<V, U, G>(a, chunk, tile, stage_lds);
+}
+
 template <int V>
 __global__ void __launch_bounds__(512) k_dot(DotArgs a, int xcd, int chunk0) {
   __shared__ uint32_t lds[8 * 64 * V];
@@ -662,6 +778,8 @@ struct Step {
   int ntiles;
   int chunk;               // chunk index handed to the tile body
   int general;             // gather: needs the general coefficient path (host-side kernel choice)
+  int lds_bytes;           // staged gather: dynamic LDS of the launch
+  int pad_;
   union {
     GatherArgs g;
     DotArgs d;

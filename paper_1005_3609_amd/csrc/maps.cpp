@@ -561,6 +561,59 @@ std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads) {
   return ms;
 }
 
+StagedCsr build_staged(const Csr& c, int slots, int rows) {
+  if (slots < 1 || rows < 1) throw std::runtime_error("bad staging limits");
+  StagedCsr st;
+  st.ent.resize(c.ent.size());
+  st.tile_row0.push_back(0);
+  st.tile_src0.push_back(0);
+  std::vector<int32_t> slot_of(static_cast<size_t>(std::max<int64_t>(c.n_cols, 1)), -1);
+  std::vector<int32_t> cur;
+  const int64_t n = c.n_rows;
+  int64_t r = 0;
+  while (r < n) {
+    const int64_t r0 = r;
+    cur.clear();
+    while (r < n && r - r0 < rows) {
+      // distinct sources this row would add
+      int add = 0;
+      for (int32_t e = c.row_ptr[r]; e < c.row_ptr[r + 1]; ++e) {
+        const int32_t s = static_cast<int32_t>(c.ent[e] & kSrcMask);
+        if (slot_of[s] == -1) {
+          slot_of[s] = -2;
+          ++add;
+        }
+      }
+      const bool fits = static_cast<int>(cur.size()) + add <= slots || r == r0;
+      for (int32_t e = c.row_ptr[r]; e < c.row_ptr[r + 1]; ++e) {
+        const int32_t s = static_cast<int32_t>(c.ent[e] & kSrcMask);
+        if (slot_of[s] == -2) {
+          if (fits) {
+            slot_of[s] = static_cast<int32_t>(cur.size());
+            cur.push_back(s);
+          } else {
+            slot_of[s] = -1;
+          }
+        }
+      }
+      if (!fits) break;
+      ++r;
+    }
+    std::sort(cur.begin(), cur.end());
+    for (size_t i = 0; i < cur.size(); ++i) slot_of[cur[i]] = static_cast<int32_t>(i);
+    for (int32_t e = c.row_ptr[r0]; e < c.row_ptr[r]; ++e) {
+      const uint32_t w = c.ent[e];
+      st.ent[e] = (w & ~kSrcMask) | static_cast<uint32_t>(slot_of[w & kSrcMask]);
+    }
+    st.src.insert(st.src.end(), cur.begin(), cur.end());
+    for (int32_t s : cur) slot_of[s] = -1;
+    st.max_slots = std::max(st.max_slots, static_cast<int>(cur.size()));
+    st.tile_row0.push_back(static_cast<int32_t>(r));
+    st.tile_src0.push_back(static_cast<int32_t>(st.src.size()));
+  }
+  return st;
+}
+
 namespace {
 std::mutex g_cache_mu;
 std::map<std::pair<int, int>, std::unique_ptr<MapSet>> g_cache;

@@ -77,6 +77,23 @@ struct MapSet {
   mutable std::map<int, std::unique_ptr<Family>> fam_;
 };
 
+// A factor cut into tiles of consecutive target rows for kernels that stage
+// each tile's source rows in on-chip memory: tile t covers rows
+// [tile_row0[t], tile_row0[t+1]) and reads the distinct source states
+// src[tile_src0[t] .. tile_src0[t+1]) (ascending); the entries keep their
+// codes, with the source replaced by its position (slot) in that list.
+struct StagedCsr {
+  std::vector<int32_t> tile_row0, tile_src0, src;
+  std::vector<uint32_t> ent;      // code << kSrcBits | slot, same order as the CSR
+  int max_slots = 0;              // largest source list of a tile
+  int n_tiles() const { return static_cast<int>(tile_row0.size()) - 1; }
+};
+
+// Greedy tiling: a tile grows row by row while it has at most `rows` rows and
+// `slots` distinct sources (a single row with more sources forms a tile of
+// its own).
+StagedCsr build_staged(const Csr& c, int slots, int rows);
+
 // Builds every single-factor map of (lattice, m); threads = 0 uses the
 // hardware count.  Throws std::runtime_error on failure.
 std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads = 0);

@@ -75,12 +75,29 @@ size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 // ---------------------------------------------------------------------------
 // Device copies of the factor maps, one per (device, lattice, m)
 // ---------------------------------------------------------------------------
+// A factor's staged tiles on the device (see StagedCsr).
+struct DevStaged {
+  DevCsr csr;                 // row pointers shared with the plain map; entries hold slots
+  const int32_t* tile_row0 = nullptr;
+  const int32_t* tile_src0 = nullptr;
+  const int32_t* src = nullptr;
+  int n_tiles = 0, max_slots = 0;
+};
+struct DevStagedSet {
+  void* base = nullptr;
+  std::vector<DevStaged> fac;
+};
+
 struct DevFamily {
+  int k = 1;
   void* base = nullptr;
   std::vector<DevCsr> fac;
   std::vector<Poly> codes;   // extends the base table
   int shift = 0;             // kernels expand the codes in powers of t = q - shift
   bool general = false;      // some coefficient its factors use has magnitude above 1
+  // staged copies, one set per (slot limit, rows per tile), built on first use
+  mutable std::mutex st_mu;
+  mutable std::map<std::pair<int, int>, std::unique_ptr<DevStagedSet>> staged;
 };
 
 struct DevMaps {
@@ -218,6 +235,7 @@ const DevFamily& dev_family(const DevMaps& dm, int k) {
   auto it = dm.fam.find(k);
   if (it != dm.fam.end()) return *it->second;
   auto df = std::make_unique<DevFamily>();
+  df->k = k;
   if (k == 1) {
     df->fac.assign(dm.fwd, dm.fwd + dm.m);
     df->codes = dm.codes;
@@ -235,6 +253,50 @@ const DevFamily& dev_family(const DevMaps& dm, int k) {
   }
   const DevFamily& ref = *df;
   dm.fam.emplace(k, std::move(df));
+  return ref;
+}
+
+// Slot limit of a staged tile: 48 KiB of LDS (rows of 64 V words).
+int stage_slots(int V) { return 48 * 1024 / (256 * V); }
+constexpr int kStageMaxLds = 64 * 1024;
+
+// Device copies of family fam's factors cut into staged tiles.
+const DevStagedSet& dev_staged(const DevMaps& dm, const DevFamily& fam, int slots, int rows) {
+  std::lock_guard<std::mutex> lk(fam.st_mu);
+  auto key = std::make_pair(slots, rows);
+  auto it = fam.staged.find(key);
+  if (it != fam.staged.end()) return *it->second;
+  const MapSet& ms = get_maps(dm.lattice, dm.m);
+  const std::vector<Csr>& host = (fam.k == 1) ? ms.fwd : ms.family(fam.k).fac;
+  std::vector<StagedCsr> st(host.size());
+  size_t bytes = 0;
+  for (size_t i = 0; i < host.size(); ++i) {
+    st[i] = build_staged(host[i], slots, rows);
+    bytes += align_up(st[i].ent.size() * 4 + 4) + align_up(st[i].tile_row0.size() * 4 + 4) +
+             align_up(st[i].tile_src0.size() * 4 + 4) + align_up(st[i].src.size() * 4 + 4);
+  }
+  auto set = std::make_unique<DevStagedSet>();
+  if (hipMalloc(&set->base, bytes) != hipSuccess) throw MemError("device allocation of staged maps failed");
+  char* cur = static_cast<char*>(set->base);
+  auto put = [&](const void* src, size_t n) {
+    void* dst = cur;
+    if (n) HIPX(hipMemcpy(dst, src, n, hipMemcpyHostToDevice));
+    cur += align_up(n + 4);
+    return dst;
+  };
+  set->fac.resize(host.size());
+  for (size_t i = 0; i < host.size(); ++i) {
+    DevStaged& d = set->fac[i];
+    d.csr = fam.fac[i];
+    d.csr.ent = static_cast<const uint32_t*>(put(st[i].ent.data(), st[i].ent.size() * 4));
+    d.tile_row0 = static_cast<const int32_t*>(put(st[i].tile_row0.data(), st[i].tile_row0.size() * 4));
+    d.tile_src0 = static_cast<const int32_t*>(put(st[i].tile_src0.data(), st[i].tile_src0.size() * 4));
+    d.src = static_cast<const int32_t*>(put(st[i].src.data(), st[i].src.size() * 4));
+    d.n_tiles = st[i].n_tiles();
+    d.max_slots = st[i].max_slots;
+  }
+  const DevStagedSet& ref = *set;
+  fam.staged.emplace(key, std::move(set));
   return ref;
 }
 
@@ -334,7 +396,7 @@ uint32_t shoup_of(uint32_t c, uint32_t p) {
 // Tuning and workspace layout
 // ---------------------------------------------------------------------------
 struct Tune {
-  int V = 2, rpw = 8, wpb = 4, xcd = 0, U = 4, streams = 1, fuse = 1;
+  int V = 2, rpw = 8, wpb = 4, xcd = 0, U = 4, streams = 1, fuse = 1, stage = 0;
 };
 
 Tune resolve(const chrom_tuning* t) {
@@ -351,6 +413,8 @@ Tune resolve(const chrom_tuning* t) {
   if (r.streams < 1 || r.streams > 4) throw ArgError("streams must be in 1..4");
   if (t->fuse) r.fuse = t->fuse;
   if (r.fuse < 1 || r.fuse > kMaxFuse) throw ArgError("fuse must be in 1..3");
+  if (t->stage < 0 || t->stage > 1) throw ArgError("stage must be 0 or 1");
+  r.stage = t->stage;
   if (r.V != 1 && r.V != 2 && r.V != 4) throw ArgError("lanes_v must be 1, 2 or 4");
   if (r.rpw < 1 || r.rpw > 63) throw ArgError("targets_per_wave must be in 1..63");
   if (r.wpb != 1 && r.wpb != 2 && r.wpb != 4 && r.wpb != 8) throw ArgError("waves_per_block must be 1, 2, 4 or 8");
@@ -525,6 +589,7 @@ struct Program {
 struct JobCtx {
   const DevMaps* dm;
   const DevFamily* fam;   // forward factors (single or fused) and their code table
+  const DevStagedSet* stg = nullptr;   // staged tiles of fam's factors (batched / graph modes)
   JobLayout L;
   JobPtrs P;
   Tune t;
@@ -634,7 +699,17 @@ void add_rows(Program& pg, const JobCtx& j, int r_first, int r_last, int after, 
     int tm = -1;
     for (int i = 1; i <= nf; ++i) {
       const bool fused = (i == nf);
+      const DevStaged* sd = (j.stg && !fused) ? &j.stg->fac[i - 1] : nullptr;
+      const int lds = sd ? sd->max_slots * j.L.W * 4 : 0;
       Step g = gather_step(j, j.fam->fac[i - 1], cur, oth, cs_x, fused, j.fam->general);
+      if (sd && sd->max_slots > 0 && lds <= kStageMaxLds) {
+        g.ntiles = std::max(1, sd->n_tiles);
+        g.lds_bytes = lds;
+        g.u.g.csr = sd->csr;
+        g.u.g.tile_row0 = sd->tile_row0;
+        g.u.g.tile_src0 = sd->tile_src0;
+        g.u.g.tile_src = sd->src;
+      }
       tm = push(pg, g, after, fused ? prev_reduce : -1);
       after = tm;
       std::swap(cur, oth);
@@ -662,10 +737,20 @@ void launch_step_vu(const Step& s, int c0, int nch, int wpb, int xcd, hipStream_
   dim3 grid(s.ntiles, nch), block(64 * wpb);
   switch (s.op) {
     case kOpGather:
-      if (s.general)
+      if (s.u.g.tile_row0) {
+        if constexpr (V <= 2) {
+          if (s.general)
+            hipLaunchKernelGGL((k_stage<V, U, true>), grid, block, s.lds_bytes, st, s.u.g, xcd, c0);
+          else
+            hipLaunchKernelGGL((k_stage<V, U, false>), grid, block, s.lds_bytes, st, s.u.g, xcd, c0);
+        } else {
+          throw std::runtime_error("staged tiles need lanes_v 1 or 2");
+        }
+      } else if (s.general) {
         hipLaunchKernelGGL((k_gather<V, U, true>), grid, block, 0, st, s.u.g, xcd, c0);
-      else
+      } else {
         hipLaunchKernelGGL((k_gather<V, U, false>), grid, block, 0, st, s.u.g, xcd, c0);
+      }
       break;
     case kOpDot: hipLaunchKernelGGL(k_dot<V>, grid, block, 0, st, s.u.d, xcd, c0); break;
     case kOpFill: hipLaunchKernelGGL(k_fill<V>, grid, block, 0, st, s.u.f, c0); break;
@@ -805,7 +890,7 @@ void run_graph(const JobCtx& j, int n_max, int* row_ctr, void* ws, hipStream_t s
   HIPX(hipGetLastError());
   if (replays > 0) {
     GraphKey key{ws, j.d_out, j.L.lattice, j.L.m, j.L.I, j.t.V, j.t.rpw, j.t.wpb,
-                 j.t.fuse * 1000 + j.t.xcd * 100 + j.t.U * 10 + j.t.streams, per};
+                 j.t.stage * 10000 + j.t.fuse * 1000 + j.t.xcd * 100 + j.t.U * 10 + j.t.streams, per};
     hipGraphExec_t exec = nullptr;
     {
       std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -1069,6 +1154,12 @@ void run_plain(const DevMaps& dm, int lattice, int m, int n_max, const std::vect
 // ---------------------------------------------------------------------------
 int rows_tile_of(const Tune& t) { return t.rpw * t.wpb; }
 
+// Staged tiles for the forward factors of a batched or graph-mode job.
+void bind_staging(JobCtx& j, int mode) {
+  if (j.t.stage && j.t.V <= 2 && (mode == CHROM_MODE_BATCHED || mode == CHROM_MODE_GRAPH))
+    j.stg = &dev_staged(*j.dm, *j.fam, stage_slots(j.t.V), rows_tile_of(j.t));
+}
+
 size_t workspace_bytes(int lattice, int m, int I, int n_max_hint, int mode, const Tune& t) {
   if (mode == CHROM_MODE_PLAIN) return plain_layout(lattice, m).bytes;
   JobLayout L = job_layout(lattice, m, I, t, kMaxCodes, rows_tile_of(t));
@@ -1105,6 +1196,7 @@ int strip_async_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, c
   j.L = job_layout(lattice, m, I, t, kMaxCodes, rows_tile_of(t));
   j.P = job_ptrs(j.L, ws);
   j.d_out = d_out;
+  bind_staging(j, mode);
   std::vector<uint32_t> img = const_image(j.L, inst, j.fam->codes, j.fam->shift);
   upload(static_cast<char*>(ws) + j.L.p, img.data(), img.size() * 4, st);
   int* row_ctr = reinterpret_cast<int*>(static_cast<char*>(ws) + j.L.bytes);
@@ -1185,6 +1277,7 @@ int factor_launches_impl(int lattice, int m, const uint32_t* q, int nq, const ui
   j.L = job_layout(lattice, m, I, t, kMaxCodes, rows_tile_of(t));
   j.P = job_ptrs(j.L, ws);
   j.d_out = nullptr;
+  bind_staging(j, CHROM_MODE_BATCHED);
   Program pg;
   pg.nchunk = j.L.nchunk;
   add_rows(pg, j, 1, rows, -1, -1);

@@ -21,20 +21,24 @@ from . import api
 DEFAULT_CACHE = os.environ.get("CHROMSTRIP_TUNE_CACHE",
                                os.path.join(os.path.expanduser("~"), ".cache", "chromstrip", "tune.json"))
 SPACE = dict(lanes_v=[1, 2, 4], targets_per_wave=[4, 8, 16], waves_per_block=[2, 4, 8],
-             xcd_order=[1, 2], unroll=[4, 8], streams=[1, 2], fuse=[1, 2, 3], mode=["graph", "grouped"])
+             xcd_order=[1, 2], unroll=[4, 8], streams=[1, 2], fuse=[1, 2, 3], stage=[0, 1],
+             mode=["graph", "grouped"])
 
 
 def candidates(space=None) -> list[dict]:
     space = space or SPACE
     out = []
-    for v, t, w, x, u, s, f, mode in itertools.product(space["lanes_v"], space["targets_per_wave"],
-                                                       space["waves_per_block"], space.get("xcd_order", [0]),
-                                                       space.get("unroll", [4]), space.get("streams", [1]),
-                                                       space.get("fuse", [1]), space["mode"]):
+    for v, t, w, x, u, s, f, g, mode in itertools.product(space["lanes_v"], space["targets_per_wave"],
+                                                          space["waves_per_block"], space.get("xcd_order", [0]),
+                                                          space.get("unroll", [4]), space.get("streams", [1]),
+                                                          space.get("fuse", [1]), space.get("stage", [0]),
+                                                          space["mode"]):
         if mode == "grouped" and s != 1:
             continue            # grouped launches already cover every chunk at once
+        if g and (mode == "grouped" or v > 2):
+            continue            # staging applies to graph / batched launches with lanes_v <= 2
         out.append(dict(lanes_v=v, targets_per_wave=t, waves_per_block=w, xcd_order=x, unroll=u, streams=s,
-                        fuse=f, mode=mode))
+                        fuse=f, stage=g, mode=mode))
     return out
 
 
@@ -135,8 +139,8 @@ def main():
     w = W.workload(args.workload)
     space = None
     if args.quick:
-        space = dict(lanes_v=[2], targets_per_wave=[4, 8], waves_per_block=[4], xcd_order=[1],
-                     unroll=[4, 8], streams=[1, 3], fuse=[1, 2], mode=["graph"])
+        space = dict(lanes_v=[2], targets_per_wave=[4, 8], waves_per_block=[4, 8], xcd_order=[1],
+                     unroll=[4], streams=[3], fuse=[2], stage=[0, 1], mode=["graph"])
     for lat, m, n in w["strips"]:
         api.prepare(lat, m)
         res = tune(lat, m, n, w["q_points"], w["primes"], space=space, steps=args.steps, path=args.cache,
