@@ -263,6 +263,22 @@ int chromatic_map_export(int lattice, int m, int which, int idx,
                          int64_t* n_rows, int64_t* n_cols, int64_t* nnz,
                          int32_t* row_ptr, uint32_t* entries);
 
+/* The staged-tile form (tuning field `stage`) of forward factor idx of the
+ * fuse-sized family, for a given slot limit and rows-per-tile limit: tiles of
+ * consecutive target rows (tile t = rows tile_row0[t] .. tile_row0[t+1]-1,
+ * n_tiles + 1 entries), each with its distinct source states
+ * src[tile_src0[t] .. tile_src0[t+1]) in ascending order (n_src in all), and
+ * the entry words of the factor's CSR (same order, same row pointers as
+ * chromatic_map_export) with the source replaced by its slot in the tile's
+ * list.  A tile grows row by row while it has at most `rows` rows and
+ * `slots` sources; a single row with more sources forms a tile of its own;
+ * max_slots is the largest list.  Host-only (no device work).  Pass NULL
+ * buffers to query sizes; entries has the factor's nnz words. */
+int chromatic_stage_export(int lattice, int m, int fuse, int idx, int slots, int rows,
+                           int32_t* n_tiles, int64_t* n_src, int32_t* max_slots,
+                           int32_t* tile_row0, int32_t* tile_src0, int32_t* src,
+                           uint32_t* entries);
+
 /* Thread-local description of the last error. */
 const char* chromatic_last_error(void);
 

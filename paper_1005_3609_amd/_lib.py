@@ -76,6 +76,9 @@ _SIGS = {
                                         C.c_void_p]),
     "chromatic_map_export": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int64),
                                        C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_void_p, C.c_void_p]),
+    "chromatic_stage_export": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                         C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "chromatic_last_error": (C.c_char_p, []),
     "chromatic_version": (C.c_char_p, []),
 }

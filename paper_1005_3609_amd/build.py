@@ -18,6 +18,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libchromstrip.so")
+# Memory-pattern ceiling probe (an executable, not part of the library).
+CEILING = os.path.join(PKG, "gather_ceiling")
 ARCH = "gfx950"
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
@@ -45,7 +47,9 @@ def build(verbose: bool = False) -> str:
         ([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "runtime.hip"), "-o",
           os.path.join(OUT_DIR, "runtime.o")]),
     ]
-    with ThreadPoolExecutor(3) as ex:
+    jobs.append([HIPCC, *[f for f in HIP_FLAGS if f != "-fPIC"], os.path.join(CSRC, "gather_ceiling.hip"),
+                 "-o", CEILING])
+    with ThreadPoolExecutor(4) as ex:
         logs = list(ex.map(_run, jobs))
     tmp = LIB + ".tmp"
     logs.append(_run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp,

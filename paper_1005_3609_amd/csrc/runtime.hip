@@ -1661,4 +1661,26 @@ int chromatic_map_export(int lattice, int m, int which, int idx, int64_t* n_rows
   });
 }
 
+int chromatic_stage_export(int lattice, int m, int fuse, int idx, int slots, int rows, int32_t* n_tiles,
+                           int64_t* n_src, int32_t* max_slots, int32_t* tile_row0, int32_t* tile_src0,
+                           int32_t* src, uint32_t* entries) {
+  return guarded([&] {
+    check_args(lattice, m, 0);
+    if (fuse < 1 || fuse > kMaxFuse) throw ArgError("fuse must be in 1..3");
+    if (slots < 1 || rows < 1) throw ArgError("slots and rows must be >= 1");
+    const MapSet& ms = get_maps(lattice, m);
+    const std::vector<Csr>& fac = (fuse == 1) ? ms.fwd : ms.family(fuse).fac;
+    if (idx < 0 || idx >= static_cast<int>(fac.size())) throw ArgError("idx out of range");
+    const StagedCsr st = build_staged(fac[idx], slots, rows);
+    if (n_tiles) *n_tiles = st.n_tiles();
+    if (n_src) *n_src = static_cast<int64_t>(st.src.size());
+    if (max_slots) *max_slots = st.max_slots;
+    if (tile_row0) std::memcpy(tile_row0, st.tile_row0.data(), st.tile_row0.size() * 4);
+    if (tile_src0) std::memcpy(tile_src0, st.tile_src0.data(), st.tile_src0.size() * 4);
+    if (src && !st.src.empty()) std::memcpy(src, st.src.data(), st.src.size() * 4);
+    if (entries && !st.ent.empty()) std::memcpy(entries, st.ent.data(), st.ent.size() * 4);
+    return CHROM_OK;
+  });
+}
+
 }  // extern "C"

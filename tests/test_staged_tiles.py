@@ -1,0 +1,55 @@
+"""Host logic of the staged-tile form of the factor maps (the `stage`
+tuning): every tile respects its limits, its source list is exactly the set
+of sources its rows read, and each re-encoded entry points back at the
+source and code of the plain map."""
+import numpy as np
+import pytest
+
+from paper_1005_3609_amd import api
+
+
+@pytest.mark.parametrize("lattice,m,fuse", [("square", 6, 1), ("square", 7, 2), ("triangular", 6, 1),
+                                            ("triangular", 5, 3), ("square", 9, 2)])
+@pytest.mark.parametrize("slots,rows", [(1, 1), (8, 4), (24, 16), (96, 32)])
+def test_staged_tiles_reproduce_the_map(lattice, m, fuse, slots, rows):
+    nfac = -(-m // fuse)
+    for idx in range(nfac):
+        rp, cols, codes, _ = api.map_export(lattice, m, 0 if fuse == 1 else fuse, idx)
+        st = api.stage_export(lattice, m, fuse, idx, slots, rows)
+        tr, ts, src = st["tile_row0"], st["tile_src0"], st["src"]
+        n_rows = len(rp) - 1
+        assert tr[0] == 0 and tr[-1] == n_rows and ts[0] == 0 and ts[-1] == len(src)
+        assert np.all(np.diff(tr) >= 1) and np.all(np.diff(tr) <= rows)
+        np.testing.assert_array_equal(st["codes"], codes)
+        widest = 0
+        for t in range(len(tr) - 1):
+            e0, e1 = rp[tr[t]], rp[tr[t + 1]]
+            lst = src[ts[t]:ts[t + 1]]
+            assert np.all(np.diff(lst) > 0)                       # ascending, distinct
+            np.testing.assert_array_equal(lst, np.unique(cols[e0:e1]))
+            np.testing.assert_array_equal(lst[st["slots"][e0:e1]], cols[e0:e1])
+            if tr[t + 1] - tr[t] > 1:                               # several rows: within the slot limit
+                assert len(lst) <= slots
+            widest = max(widest, len(lst))
+        assert st["max_slots"] == widest
+
+
+def test_staged_tiles_are_greedy():
+    # a tile stops only when the next row would break a limit
+    rp, cols, _, _ = api.map_export("square", 8, 2, 1)
+    st = api.stage_export("square", 8, 2, 1, 24, 8)
+    tr = st["tile_row0"]
+    for t in range(len(tr) - 2):
+        nxt = tr[t + 1]
+        rows_ok = nxt - tr[t] < 8
+        union = np.unique(cols[rp[tr[t]]:rp[nxt + 1]])
+        assert not (rows_ok and len(union) <= 24), f"tile {t} could have taken row {nxt}"
+
+
+def test_stage_export_rejects_bad_arguments():
+    with pytest.raises(api.ChromError):
+        api.stage_export("square", 6, 4, 0, 8, 4)
+    with pytest.raises(api.ChromError):
+        api.stage_export("square", 6, 1, 6, 8, 4)
+    with pytest.raises(api.ChromError):
+        api.stage_export("square", 6, 1, 0, 0, 4)
