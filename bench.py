@@ -104,11 +104,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kname, rtune):
+def measured_traffic(kname, rtune, workload=WORKLOAD):
     """HBM bytes per factor launch from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by a copy-kernel calibration), or None
     when the kernel source or launch shape differs from what was profiled."""
-    path = os.path.join(ROOT, "profiles", "k_gather_square_14x15.md")
+    path = os.path.join(ROOT, "profiles", f"k_gather_{workload}.md")
     try:
         with open(path) as f:
             for line in f:
@@ -160,6 +160,71 @@ def bench_triangular(torch, stream, steps):
             "value": updates_of(lat, m, n, I) / (ms / 1e3), "unit": "state-updates/s"}
 
 
+def bench_m18(torch, stream, tune, rows):
+    """The square 18x19 strip with the workload's 640 instances: one vector is
+    8.2 GB, far beyond the 256 MB Infinity Cache, so the factor kernel's
+    bandwidth here is HBM bandwidth.  Reports the whole strip (graph mode,
+    the m = 14 tuned shape), the factor kernel timed alone over `rows` rows
+    (one launch per factor step, as in the m = 14 roofline leg), and one
+    (q, p) instance through the plain path (12.8 MB per vector)."""
+    from paper_1005_3609_amd import api
+    from paper_1005_3609_amd import workloads as W
+    w = W.workload("square_18x19")
+    lat, m, n = w["strips"][0]
+    q, p = w["q_points"], w["primes"]
+    I = len(q) * len(p)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    t0 = time.time()
+    api.prepare(lat, m)
+    sizes = factor_sizes(lat, m)
+    s_nc = api.space_size(m)
+    maps_s = time.time() - t0
+    V = tune.get("lanes_v") or 2
+    fuse = tune.get("fuse") or 1
+    ipad = -(-I // (64 * V)) * 64 * V
+    out = torch.zeros((n, len(q), len(p)), dtype=torch.int32, device=dev)
+    ws = api.alloc_workspace(api.workspace_bytes(lat, m, n, len(q), len(p), "graph", tune), dev)
+
+    def strip():
+        api.strip_async(lat, m, n, q, p, mode="graph", tuning=tune, workspace=ws, out=out, stream=stream)
+    strip()                                   # fused maps, graph capture
+    ms = timed(torch, stream, strip)
+    res = api.to_u32(out).astype("int64").reshape(n, len(q), len(p))
+    assert (res[:, 0, :] == 0).all() and (res[:, 1, :] == 2).all(), "invariants P(1)=0, P(2)=2 failed at m=18"
+    del ws
+    rtune = dict(tune, streams=1)
+    ws_b = api.alloc_workspace(api.workspace_bytes(lat, m, n, len(q), len(p), "batched", rtune), dev)
+    api.strip_async(lat, m, 1, q, p, mode="batched", tuning=rtune, workspace=ws_b, out=out, stream=stream)
+    api.factor_launches(lat, m, q, p, 1, ws_b, rtune, stream)
+    k_ms = timed(torch, stream, lambda: api.factor_launches(lat, m, q, p, rows, ws_b, rtune, stream))
+    del ws_b
+    nf = -(-m // fuse)
+    bytes_row = row_bytes(sizes, ipad, s_nc)
+    achieved = rows * bytes_row / (k_ms / 1e3) / 1e9
+    # one (q, p) instance through the plain path, two rows
+    q1, p1 = q[:1], p[:1]
+    ws_p = api.alloc_workspace(api.workspace_bytes(lat, m, 3, 1, 1, "plain"), dev)
+    out_p = torch.zeros((3, 1, 1), dtype=torch.int32, device=dev)
+
+    def plain():
+        api.strip_async(lat, m, 3, q1, p1, mode="plain", workspace=ws_p, out=out_p, stream=stream)
+    plain()
+    p_ms = timed(torch, stream, plain)
+    assert (api.to_u32(out_p).astype("int64").reshape(3) == res[:3, 0, 0]).all(), "plain path differs at m=18"
+    p_bytes = 2 * row_bytes(sizes, 1, s_nc)
+    return {"workload": "square 18x19, 80 q x 8 seeded primes (640 instances), graph row replay, "
+                        f"tuning {tune}",
+            "maps_build_s": maps_s, "ms_per_strip": ms,
+            "value": updates_of(lat, m, n, I) / (ms / 1e3), "unit": "state-updates/s",
+            "factor_kernel": {"rows_timed": rows, "launches": rows * nf, "avg_launch_us": k_ms * 1e3 / (rows * nf),
+                              "achieved_GBs": achieved, "frac_of_hbm_peak": achieved / HBM_PEAK_GBS,
+                              "algorithmic_bytes_per_row": bytes_row},
+            "plain_single_instance": {"rows": 2, "ms": p_ms,
+                                      "value": updates_of(lat, m, 3, 1) / (p_ms / 1e3),
+                                      "algorithmic_GBs": p_bytes / (p_ms / 1e3) / 1e9,
+                                      "note": "12.8 MB per vector: cache-resident, not an HBM figure"}}
+
+
 def bench_serving(torch, n_jobs, n_plain):
     """Continuous batching on a seeded Poisson stream (mean 20 jobs/s) against
     the plain per-instance path serving the same arrivals one job at a time."""
@@ -209,6 +274,10 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline and roofline only")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default=WORKLOAD, choices=["square_14x15", "square_18x19"],
+                    help="strip of the headline and roofline legs (the metric is quoted on square_14x15)")
+    ap.add_argument("--no-m18", action="store_true", help="skip the square 18x19 leg (about 2 minutes)")
+    ap.add_argument("--m18-rows", type=int, default=1, help="rows of factor launches timed at m=18")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
@@ -228,7 +297,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    w = W.workload(WORKLOAD)
+    wname = args.workload
+    w = W.workload(wname)
     lat, m, n = w["strips"][0]
     q, p = w["q_points"], w["primes"]
     I = len(q) * len(p)
@@ -323,14 +393,20 @@ def main():
         log(f"triangular m=12: {extra['triangular_12x13']['value']:.3e} state-updates/s")
         extra["serving"] = bench_serving(torch, args.serve_jobs, args.serve_plain_jobs)
         log(f"serving: {extra['serving']}")
+    if not args.quick and not args.no_m18 and wname != "square_18x19":
+        extra["square_18x19"] = bench_m18(torch, stream, tune, args.m18_rows)
+        k = extra["square_18x19"]["factor_kernel"]
+        log(f"square 18x19: {extra['square_18x19']['value']:.3e} state-updates/s, factor kernel "
+            f"{k['avg_launch_us']:.0f} us/launch, {k['achieved_GBs']:.0f} GB/s algorithmic "
+            f"({100 * k['frac_of_hbm_peak']:.0f} % of HBM peak)")
 
     # ---- CPU oracle on a bounded sample -----------------------------------
     cpu = None
-    if not args.no_cpu and not args.quick:
+    if not args.no_cpu and not args.quick and wname == "square_14x15":
         dt, ninst = cpu_baseline(lat, m, q, p)
         upd = sum(s for _, s, _ in sizes) * ninst
         cpu = {"value": upd / dt, "unit": "state-updates/s", "cores": 1, "kind": "oracle",
-               "sample": f"one transfer row (T_14..T_1) of the square m=14 sweep applied to a dense seeded "
+               "sample": f"one transfer row (T_{m}..T_1) of the square m={m} strip applied to a dense seeded "
                          f"vector over all {s_nc} NCNNN states, first {ninst} of the 640 instances, "
                          f"{dt:.1f} s single-threaded Python"}
         log(f"cpu oracle: {cpu['value']:.3e} state-updates/s")
@@ -344,7 +420,7 @@ def main():
             f"{2 * args.copy_mib * (1 << 20) / (c_ms / 1e3) / 1e9:.0f} GB/s read+write")
 
     line = {
-        "metric": "state-updates/s, square lattice m=14 (14x15 strip), batched",
+        "metric": f"state-updates/s, square lattice m={m} ({m}x{n} strip), batched",
         "value": value,
         "unit": "state-updates/s",
         "n_gpus": 1,
@@ -356,11 +432,11 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": "square 14x15 strip, 80 q x 8 seeded primes (640 instances), "
+        "config": {"workload": f"square {m}x{n} strip, 80 q x 8 seeded primes (640 instances), "
                                "row-by-row read-out", "lattice": lat, "m": m, "n_max": n,
                    "instances": I, "mode": mode, "tuning": tune, "autotuned": bool(tuned)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname, rtune),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname, rtune, wname),
                      "kernel": kname, "avg_launch_us": avg_us, "launches_timed": launches,
                      "algorithmic_bytes_per_row": bytes_row, "own_min_bytes_per_row": own_row,
                      "achieved_own_min": achieved_own},
