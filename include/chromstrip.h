@@ -109,6 +109,40 @@ int chromatic_strip_batched(int lattice, int m, int n_max,
 size_t chromatic_workspace_bytes(int lattice, int m, int n_max, int nq, int np,
                                  int mode, const chrom_tuning* tune);
 
+/* ------------------------------------------------------------------------
+ * Coefficient form: the normalised chromatic polynomial of eq. Z_modified,
+ * P~ = q^{-|V|} P_G(q), a polynomial in x = 1/q with constant term 1, kept
+ * as truncated coefficient arrays mod p (Sec. 3.5: the transfer uses only
+ * additions and subtractions; results for several primes combine by CRT).
+ * Every state carries, per prime, the coefficients of x^0 .. x^{64 V - 1}
+ * (V = tuning lanes_v); the read-out applies T_last to every row's state.
+ * ------------------------------------------------------------------------ */
+
+/* Workspace bytes for chromatic_series_async (mode BATCHED or GRAPH).
+ * d_max must be below 64 * lanes_v.  Returns 0 on bad arguments. */
+size_t chromatic_series_workspace_bytes(int lattice, int m, int n_max, int np, int d_max,
+                                        int mode, const chrom_tuning* tune);
+
+/* Asynchronous coefficient-form strip.  d_out (device, [n_max][np][d_max+1]
+ * uint32): row r, prime b holds the coefficients of x^0 .. x^d_max of
+ * P~ for the m x (r+1) rectangle, mod primes[b] (the exact polynomial has
+ * degree |V| - 1 = m (r+1) - 1; higher coefficients are 0).  primes: host
+ * memory, odd, 2 < p < 2^31.  mode: CHROM_MODE_BATCHED or CHROM_MODE_GRAPH;
+ * tune: fuse and stage must be 0 or 1 / 0 (single factors, no staging);
+ * lanes_v sets the coefficients kept (64 lanes_v > d_max).  Workspace rules
+ * as for chromatic_strip_async. */
+int chromatic_series_async(int lattice, int m, int n_max, int d_max,
+                           const uint32_t* primes, int np, int mode,
+                           const chrom_tuning* tune, void* d_workspace, size_t ws_bytes,
+                           void* stream, uint32_t* d_out);
+
+/* Same, synchronous, host output [n_max][np][d_max+1], internal
+ * allocation; lanes_v defaults to the smallest of 1, 2, 4 that holds
+ * d_max + 1 coefficients. */
+int chromatic_series(int lattice, int m, int n_max, int d_max,
+                     const uint32_t* primes, int np, int mode,
+                     const chrom_tuning* tune, uint32_t* out);
+
 /* Asynchronous strip on `stream` (a hipStream_t; NULL = null stream).
  * q_points/primes: host memory, read before return.  d_workspace: device
  * memory of at least chromatic_workspace_bytes(...) bytes, 256-byte
@@ -253,6 +287,10 @@ int chromatic_family_info(int lattice, int m, int fuse, int* n_factors, int* n_c
  * source states before it).  which = 1: read-out factor T_{idx+1}^last,
  * transposed (rows = states before it, entries = states after it).
  * which = 2 or 3: factor idx of the fused family of that size.
+ * which = 4: forward factor T_{idx+1} of the normalised (coefficient-form)
+ * set; which = 5: its read-out factor T_{idx+1}^last in gather form (rows =
+ * states after it, entries = states before it).  Codes index
+ * chromatic_code_table of the same form.
  * Entry word: bits 0..25 = column state rank, bits 26..31 = coefficient
  * code.  Sizes are returned through n_rows, n_cols, nnz; pass NULL buffers
  * to query sizes only.  row_ptr has n_rows+1 entries.  The state numbering
@@ -262,6 +300,12 @@ int chromatic_family_info(int lattice, int m, int fuse, int* n_factors, int* n_c
 int chromatic_map_export(int lattice, int m, int which, int idx,
                          int64_t* n_rows, int64_t* n_cols, int64_t* nnz,
                          int32_t* row_ptr, uint32_t* entries);
+
+/* Coefficient table of the maps of (lattice, m): code c is the polynomial
+ * coef[4c] + coef[4c+1] z + coef[4c+2] z^2 + coef[4c+3] z^3 with z = q
+ * (normalised = 0, the evaluation form) or z = x = 1/q (normalised = 1, the
+ * coefficient form).  Pass coef = NULL to query n_codes. */
+int chromatic_code_table(int lattice, int m, int normalised, int* n_codes, int64_t* coef);
 
 /* The staged-tile form (tuning field `stage`) of forward factor idx of the
  * fuse-sized family, for a given slot limit and rows-per-tile limit: tiles of

@@ -51,6 +51,59 @@ def strip(lattice, m: int, n_max: int, q_points, primes, mode: str = "plain", tu
     return out
 
 
+# ---------------------------------------------------------------------------
+# Coefficient form: the normalised polynomial P~ = q^-|V| P in x = 1/q
+# ---------------------------------------------------------------------------
+def series(lattice, m: int, n_max: int, d_max: int, primes, mode: str = "graph", tuning=None) -> np.ndarray:
+    """Coefficients of x^0..x^d_max of P~ for the m x r rectangles, r =
+    1..n_max, mod every prime: uint32 [n_max, np, d_max + 1]."""
+    p = _u32(primes)
+    out = np.zeros((max(n_max, 0), p.size, d_max + 1), dtype=np.uint32)
+    t = _lib.tuning(tuning)
+    check(lib().chromatic_series(lattice_id(lattice), m, n_max, d_max, _ptr(p), p.size, _lib.MODES[mode],
+                                 C.byref(t) if t else None, _ptr(out)))
+    return out
+
+
+def series_workspace_bytes(lattice, m: int, n_max: int, np_: int, d_max: int, mode: str = "graph",
+                           tuning=None) -> int:
+    t = _lib.tuning(tuning)
+    n = lib().chromatic_series_workspace_bytes(lattice_id(lattice), m, n_max, np_, d_max, _lib.MODES[mode],
+                                               C.byref(t) if t else None)
+    if n == 0:
+        check(-1)
+    return int(n)
+
+
+def series_async(lattice, m: int, n_max: int, d_max: int, primes, mode: str = "graph", tuning=None,
+                 workspace=None, out=None, stream=None, device=None):
+    """Queues a coefficient-form strip on `stream`; returns (out, workspace),
+    out = int32 storage of uint32 [n_max, np, d_max + 1]."""
+    torch = _torch()
+    p = _u32(primes)
+    t = _lib.tuning(tuning)
+    need = series_workspace_bytes(lattice, m, n_max, p.size, d_max, mode, tuning)
+    if workspace is None:
+        workspace = alloc_workspace(need, device)
+    if out is None:
+        out = torch.zeros((max(n_max, 1), p.size, d_max + 1), dtype=torch.int32, device=workspace.device)
+    check(lib().chromatic_series_async(lattice_id(lattice), m, n_max, d_max, _ptr(p), p.size, _lib.MODES[mode],
+                                       C.byref(t) if t else None, C.c_void_p(workspace.data_ptr()),
+                                       workspace.numel(), _stream_handle(stream), C.c_void_p(out.data_ptr())))
+    return out, workspace
+
+
+def code_table(lattice, m: int, normalised: bool = False) -> np.ndarray:
+    """int64 [n_codes, 4]: coefficients of z^0..z^3 of every code (z = q, or
+    x = 1/q for the normalised maps)."""
+    L = lib()
+    n = C.c_int()
+    check(L.chromatic_code_table(lattice_id(lattice), m, int(normalised), C.byref(n), None))
+    out = np.zeros((n.value, 4), dtype=np.int64)
+    check(L.chromatic_code_table(lattice_id(lattice), m, int(normalised), None, _ptr(out)))
+    return out
+
+
 def prepare(lattice, m: int) -> None:
     check(lib().chromatic_prepare(lattice_id(lattice), m))
 
@@ -248,7 +301,8 @@ def stage_export(lattice, m: int, fuse: int, idx: int, slots: int, rows: int) ->
 
 def map_export(lattice, m: int, which: int, idx: int):
     """(row_ptr int32[n_rows+1], cols int64[nnz], codes int64[nnz], n_cols);
-    which: 0 forward factor, 1 read-out factor (transposed), 2/3 fused family."""
+    which: 0 forward factor, 1 read-out factor (transposed), 2/3 fused family,
+    4 normalised forward factor, 5 normalised read-out factor (gather form)."""
     L = lib()
     nr, nc, nz = C.c_int64(), C.c_int64(), C.c_int64()
     check(L.chromatic_map_export(lattice_id(lattice), m, which, idx, C.byref(nr), C.byref(nc), C.byref(nz),

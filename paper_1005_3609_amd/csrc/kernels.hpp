@@ -165,6 +165,15 @@ struct FillArgs {
   int rows_per_wave;
 };
 
+// Coefficient-form read-out: copies coefficients 0 .. dlen-1 of state 0 of
+// every chunk (one prime each) to dst[chunk][dlen] of the output row.
+struct EmitArgs {
+  const uint32_t* src;     // chunk 0, state 0
+  long src_cstride;
+  uint32_t* dst;           // output row
+  int dlen;
+};
+
 // Two-level read-out reduction.  Level 1: workgroup g of a chunk sums the
 // partials [g*per, (g+1)*per) into part2[chunk][g][W]; level 2 sums the
 // n_groups level-1 results into out[inst].
@@ -299,6 +308,37 @@ __device__ __forceinline__ void horner(uint32_t (&v)[V], const uint32_t (&A)[4][
   }
 }
 
+// Coefficient form: a chunk holds one prime's truncated coefficient array
+// of a polynomial in x = 1/q, coefficient k = lane V + j.  Multiplying by x
+// moves every coefficient up one place (the top one drops out of the
+// truncation); across lanes by one shuffle per wavefront.
+template <int V>
+__device__ __forceinline__ void shift_up(uint32_t (&v)[V]) {
+  const uint32_t carry = static_cast<uint32_t>(__shfl_up(static_cast<int>(v[V - 1]), 1, 64));
+#pragma unroll
+  for (int j = V - 1; j > 0; --j) v[j] = v[j - 1];
+  v[0] = (lane_id() == 0) ? 0u : carry;
+}
+
+// sum_k x^k A_k by Horner's rule on coefficient arrays; A_k = 0 for k > deg.
+template <int V>
+__device__ __forceinline__ void horner_cf(uint32_t (&v)[V], const uint32_t (&A)[4][V], int deg,
+                                          const uint32_t (&p)[V]) {
+#pragma unroll
+  for (int j = 0; j < V; ++j) v[j] = A[3][j];
+#pragma unroll
+  for (int k = 2; k >= 0; --k) {
+    if (deg > k) {
+      shift_up<V>(v);
+#pragma unroll
+      for (int j = 0; j < V; ++j) v[j] = add_mod(v[j], A[k][j], p[j]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < V; ++j) v[j] = A[k][j];
+    }
+  }
+}
+
 // One wavefront computes target rows [r0, r1) of one chunk.  Its row
 // pointers (lane j holds row_ptr[r0 + j]) and its entry words (64 per
 // register, lane l holding one) arrive with coalesced vector loads and are
@@ -309,7 +349,7 @@ __device__ __forceinline__ void horner(uint32_t (&v)[V], const uint32_t (&A)[4][
 // rows themselves, oldest first.  Row boundaries are uniform, so each
 // finished row is stored without divergence; rows with no entries are stored
 // as zero.
-template <int V, int U, bool G>
+template <int V, int U, bool G, bool CF>
 __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* lds) {
   constexpr int W = 64 * V;
   const int lane = lane_id(), wave = wave_id();
@@ -347,7 +387,10 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
     int row_end = __builtin_amdgcn_readlane(rp, 1);
     auto flush = [&]() {
       uint32_t v[V];
-      horner<V>(v, A, deg, tv, ts, p);
+      if constexpr (CF)
+        horner_cf<V>(v, A, deg, p);
+      else
+        horner<V>(v, A, deg, tv, ts, p);
       store_row<V>(out, static_cast<uint32_t>(row) * (4u * W) + boff, v);
 #pragma unroll
       for (int k = 0; k < 4; ++k)
@@ -650,12 +693,12 @@ __device__ __forceinline__ void tile_chunk(int xcd, int chunk0, int& tile, int& 
   chunk = chunk0 + b / gridDim.x;
 }
 
-template <int V, int U, bool G>
+template <int V, int U, bool G, bool CF>
 __global__ void __launch_bounds__(512) k_gather(GatherArgs a, int xcd, int chunk0) {
   __shared__ uint32_t lds[8 * 64 * V];
   int tile, chunk;
   tile_chunk(xcd, chunk0, tile, chunk);
-  gather_tile<V, U, G>(a, chunk, tile, lds);
+  gather_tile<V, U, G, CF>(a, chunk, tile, lds);
 }
 
 // grid (tiles, chunks); dynamic LDS: max_slots * 64 V words
@@ -698,6 +741,21 @@ __global__ void __launch_bounds__(512) k_reduce2(ReduceArgs a, int chunk0) {
 template <int V>
 __global__ void __launch_bounds__(512) k_reduce2_counted(ReduceArgs a, int chunk0, const int* row, long row_stride) {
   reduce2_tile<V>(a, chunk0 + blockIdx.x, a.out + static_cast<long>(*row) * row_stride);
+}
+
+// grid (chunks)
+__global__ void __launch_bounds__(256) k_emit(EmitArgs a, int chunk0) {
+  const int chunk = chunk0 + blockIdx.x;
+  for (int k = threadIdx.x; k < a.dlen; k += blockDim.x)
+    a.dst[static_cast<long>(chunk) * a.dlen + k] = a.src[chunk * a.src_cstride + k];
+}
+
+// Output row taken from a device counter (hipGraph replays), as k_reduce2_counted.
+__global__ void __launch_bounds__(256) k_emit_counted(EmitArgs a, int chunk0, const int* row, long row_stride) {
+  const int chunk = chunk0 + blockIdx.x;
+  uint32_t* dst = a.dst + static_cast<long>(*row) * row_stride;
+  for (int k = threadIdx.x; k < a.dlen; k += blockDim.x)
+    dst[static_cast<long>(chunk) * a.dlen + k] = a.src[chunk * a.src_cstride + k];
 }
 
 __global__ void k_bump(int* row) {
@@ -771,7 +829,7 @@ __global__ void __launch_bounds__(256) k_dot_plain(const uint32_t* __restrict__ 
 // ---------------------------------------------------------------------------
 // Grouped launches: one launch runs one step of many (job, chunk) items
 // ---------------------------------------------------------------------------
-enum StepOp : int { kOpFill = 0, kOpGather = 1, kOpDot = 2, kOpReduce1 = 3, kOpReduce2 = 4 };
+enum StepOp : int { kOpFill = 0, kOpGather = 1, kOpDot = 2, kOpReduce1 = 3, kOpReduce2 = 4, kOpEmit = 5 };
 
 struct Step {
   int op;
@@ -779,11 +837,12 @@ struct Step {
   int chunk;               // chunk index handed to the tile body
   int general;             // gather: needs the general coefficient path (host-side kernel choice)
   int lds_bytes;           // staged gather: dynamic LDS of the launch
-  int pad_;
+  int cf;                  // gather: coefficient form (polynomials in x = 1/q)
   union {
     GatherArgs g;
     DotArgs d;
     FillArgs f;
+    EmitArgs e;
     ReduceArgs r;
   } u;
 };
@@ -811,7 +870,7 @@ __global__ void __launch_bounds__(512) k_grouped(GroupArgs g) {
   const int tile = __builtin_amdgcn_readfirstlane(b - g.tile_start[k]);
   const Step& st = g.steps[k];
   switch (st.op) {
-    case kOpGather: gather_tile<V, U, G>(st.u.g, st.chunk, tile, lds); break;
+    case kOpGather: gather_tile<V, U, G, false>(st.u.g, st.chunk, tile, lds); break;
     case kOpDot: dot_tile<V>(st.u.d, st.chunk, tile, lds); break;
     case kOpFill: fill_tile<V>(st.u.f, st.chunk, tile); break;
     case kOpReduce1: reduce1_tile<V>(st.u.r, st.chunk, tile, lds); break;

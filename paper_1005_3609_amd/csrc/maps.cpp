@@ -1,18 +1,23 @@
 // Factor-map builder.
 //
 // Every per-site factor of arXiv 1005.3609 is expanded on each source state
-// with the single-edge operators of Sec. 3.1 at v = -1, evaluated at integer
-// q in un-normalised form (a component pays q when it leaves the layer):
+// with the single-edge operators of Sec. 3.1 at v = -1, either in
+// un-normalised form with coefficients in q (a component pays q when it
+// leaves the layer):
 //   H_{a,b} s = s - J_{a,b} s          (0 if a, b already share a block)
 //   V_i s     = -s + D_i s             ((q-1) s if i is alone in s)
 //   D_i s     = i made a singleton     (q s if i is alone in s)
+// or in the normalised form of eq. Z_modified with coefficients in x = 1/q
+// (a join pays x, nothing pays on leaving):
+//   H_{a,b} s = s - x J_{a,b} s,  V_i s = -x s + D_i s,  D_i s as above without q
 //   P         = drop states whose listed neighbour pairs share a block
 // Factors (1-based site i, Sec. 3.2 - 3.3):
 //   square      T_i = P_{j != i} V_i H_{i,i+1} (i < m),  T_m = P_all V_m
 //   triangular  T_i = P_all V_i H_{i-1,i} H_{i,i+1}  (H's omitted at the ends)
 //   read-out    T_i^last = P_{j > i} D_i H_{i,i+1}   (H omitted for i = m)
-// Every coefficient is a + b q with small integers a, b; it is stored as a
-// code into a per-map-set table.  Products of consecutive factors (fused
+// Every coefficient is a small-integer polynomial (degree <= 1 in q for a
+// single un-normalised factor, <= 3 in x for a normalised one); it is stored
+// as a code into a per-map-set table.  Products of consecutive factors (fused
 // families) carry polynomial coefficients of degree up to the number of
 // factors multiplied.
 #include "maps.hpp"
@@ -28,33 +33,63 @@
 #include <stdexcept>
 #include <string>
 #include <thread>
+#include <tuple>
 
 namespace cs {
 
 namespace {
 
-// Coefficient key for a in [-16,16], b in [-2,2].
-constexpr int kKeyA = 16, kKeyB = 2, kKeys = 33 * 5;
-inline int coef_key(int a, int b) {
-  if (a < -kKeyA || a > kKeyA || b < -kKeyB || b > kKeyB)
-    throw std::runtime_error("coefficient out of the supported range");
-  return (a + kKeyA) + 33 * (b + kKeyB);
+// Coefficient key of a polynomial c0 + c1 z + c2 z^2 + c3 z^3 (z = q in the
+// un-normalised form, z = x = 1/q in the normalised one), each c_k in
+// [-8, 8].
+constexpr int kKeyOff = 8, kKeyBase = 17, kKeys = kKeyBase * kKeyBase * kKeyBase * kKeyBase;
+inline int coef_key(const int (&c)[kMaxDeg + 1]) {
+  int key = 0;
+  for (int k = kMaxDeg; k >= 0; --k) {
+    if (c[k] < -kKeyOff || c[k] > kKeyOff) throw std::runtime_error("coefficient out of the supported range");
+    key = key * kKeyBase + (c[k] + kKeyOff);
+  }
+  return key;
+}
+inline Poly key_poly(int key) {
+  Poly p;
+  for (int k = 0; k <= kMaxDeg; ++k) {
+    p.c[k] = key % kKeyBase - kKeyOff;
+    key /= kKeyBase;
+  }
+  return p;
 }
 
 struct Term {
   Part p;
-  int a, b;  // coefficient a + b q
+  int c[kMaxDeg + 1];  // coefficient polynomial
 };
 
-// Applies single-edge operators to a short list of terms.
+inline bool coef_zero(const Term& t) { return t.c[0] == 0 && t.c[1] == 0 && t.c[2] == 0 && t.c[3] == 0; }
+
+// c -> sign * z * c
+inline void times_z(Term& t, int sign) {
+  if (t.c[kMaxDeg] != 0) throw std::runtime_error("coefficient degree above 3");
+  for (int k = kMaxDeg; k > 0; --k) t.c[k] = sign * t.c[k - 1];
+  t.c[0] = 0;
+}
+
+// Applies single-edge operators to a short list of terms.  Un-normalised
+// (z = q): H = 1 - J, V = -1 + D, D pays q when its point is alone.
+// Normalised (z = x = 1/q, eq. Z_modified): J pays x, so H = 1 - x J,
+// V = -x + D, and D never pays.
 class Expander {
  public:
-  explicit Expander(int m) : m_(m) {}
+  Expander(int m, bool normalised) : m_(m), norm_(normalised) {}
   void reset(const Part& p) {
     terms_.clear();
-    terms_.push_back({p, 1, 0});
+    Term t;
+    t.p = p;
+    t.c[0] = 1;
+    t.c[1] = t.c[2] = t.c[3] = 0;
+    terms_.push_back(t);
   }
-  // H_{x,y} = 1 - J_{x,y}
+  // H_{x,y} = 1 - J_{x,y}  (J pays x in the normalised form)
   void H(int x, int y) {
     tmp_.clear();
     for (const Term& t : terms_) {
@@ -62,25 +97,33 @@ class Expander {
       tmp_.push_back(t);
       Term j = t;
       join(j.p, m_, x, y);
-      j.a = -t.a;
-      j.b = -t.b;
+      if (norm_) {
+        times_z(j, -1);
+      } else {
+        for (int k = 0; k <= kMaxDeg; ++k) j.c[k] = -t.c[k];
+      }
       tmp_.push_back(j);
     }
     terms_.swap(tmp_);
   }
-  // V_i = -1 + D_i
+  // V_i = -1 + D_i (un-normalised) or -x + D_i (normalised)
   void V(int i) {
     tmp_.clear();
     for (const Term& t : terms_) {
-      if (is_alone(t.p, m_, i)) {
-        if (t.b != 0) throw std::runtime_error("q^2 coefficient");
-        tmp_.push_back({t.p, -t.a, t.a});  // (q - 1) a
+      Term present = t;
+      if (norm_) {
+        times_z(present, -1);
       } else {
-        tmp_.push_back({t.p, -t.a, -t.b});
-        Term d = t;
-        detach(d.p, m_, i);
-        tmp_.push_back(d);
+        for (int k = 0; k <= kMaxDeg; ++k) present.c[k] = -t.c[k];
       }
+      tmp_.push_back(present);
+      Term d = t;
+      if (is_alone(t.p, m_, i)) {
+        if (!norm_) times_z(d, 1);  // the component leaves the layer: q
+      } else {
+        detach(d.p, m_, i);
+      }
+      tmp_.push_back(d);
     }
     terms_.swap(tmp_);
   }
@@ -88,9 +131,7 @@ class Expander {
   void D(int i) {
     for (Term& t : terms_) {
       if (is_alone(t.p, m_, i)) {
-        if (t.b != 0) throw std::runtime_error("q^2 coefficient");
-        t.b = t.a;
-        t.a = 0;
+        if (!norm_) times_z(t, 1);
       } else {
         detach(t.p, m_, i);
       }
@@ -117,8 +158,7 @@ class Expander {
       bool found = false;
       for (Term& u : tmp_)
         if (std::memcmp(u.p.lab, t.p.lab, m_) == 0) {
-          u.a += t.a;
-          u.b += t.b;
+          for (int k = 0; k <= kMaxDeg; ++k) u.c[k] += t.c[k];
           found = true;
           break;
         }
@@ -126,12 +166,13 @@ class Expander {
     }
     terms_.clear();
     for (const Term& t : tmp_)
-      if (t.a != 0 || t.b != 0) terms_.push_back(t);
+      if (!coef_zero(t)) terms_.push_back(t);
   }
   const std::vector<Term>& terms() const { return terms_; }
 
  private:
   int m_;
+  bool norm_;
   std::vector<Term> terms_, tmp_;
 };
 
@@ -224,21 +265,21 @@ void parallel_for(int64_t n, int threads, F&& f) {
 
 struct Triple {
   int32_t row, col;
-  int16_t key;
+  int32_t key;
 };
 
 // Builds one factor with coefficient keys in place of codes (resolved later).
-void build_factor(const FactorDef& d, bool gather_form, int threads, Csr& csr,
-                  std::vector<uint16_t>& keys, std::atomic<uint64_t>* seen) {
+void build_factor(const FactorDef& d, bool gather_form, bool normalised, int threads, Csr& csr,
+                  std::vector<int32_t>& keys, std::atomic<uint64_t>* seen) {
   const int64_t nin = d.in.size(), nout = d.out.size();
   if (nin > int64_t(kSrcMask) || nout > int64_t(kSrcMask))
     throw std::runtime_error("state space too large for 28-bit ranks");
   std::vector<std::vector<Triple>> buf(std::max(threads, 1));
   parallel_for(nin, threads, [&](int t, int64_t lo, int64_t hi) {
-    Expander e(d.m);
+    Expander e(d.m, normalised);
     auto& out = buf[t];
     out.reserve(static_cast<size_t>((hi - lo) * 4));
-    uint64_t local_seen[(kKeys + 63) / 64] = {0};
+    std::vector<uint64_t> local_seen((kKeys + 63) / 64, 0);
     for (int64_t r = lo; r < hi; ++r) {
       Part p;
       d.in.unrank(r, p);
@@ -247,15 +288,16 @@ void build_factor(const FactorDef& d, bool gather_form, int threads, Csr& csr,
       for (const Term& term : e.terms()) {
         int64_t tr = d.out.rank(term.p);
         if (tr < 0) throw std::runtime_error("target outside its space: " + to_string(term.p, d.m));
-        int key = coef_key(term.a, term.b);
+        const int key = coef_key(term.c);
         local_seen[key / 64] |= 1ull << (key % 64);
         if (gather_form)
-          out.push_back({static_cast<int32_t>(tr), static_cast<int32_t>(r), static_cast<int16_t>(key)});
+          out.push_back({static_cast<int32_t>(tr), static_cast<int32_t>(r), key});
         else
-          out.push_back({static_cast<int32_t>(r), static_cast<int32_t>(tr), static_cast<int16_t>(key)});
+          out.push_back({static_cast<int32_t>(r), static_cast<int32_t>(tr), key});
       }
     }
-    for (int w = 0; w < (kKeys + 63) / 64; ++w) seen[w].fetch_or(local_seen[w]);
+    for (int w = 0; w < (kKeys + 63) / 64; ++w)
+      if (local_seen[w]) seen[w].fetch_or(local_seen[w]);
   });
   const int64_t nrows = gather_form ? nout : nin;
   csr.n_rows = nrows;
@@ -278,7 +320,7 @@ void build_factor(const FactorDef& d, bool gather_form, int threads, Csr& csr,
     for (const Triple& x : b) {
       int64_t at = cur[x.row]++;
       csr.ent[at] = static_cast<uint32_t>(x.col);
-      keys[at] = static_cast<uint16_t>(x.key);
+      keys[at] = x.key;
     }
   if (!gather_form) {
     for (int64_t r = 0; r < nrows; ++r) {
@@ -500,6 +542,7 @@ int64_t MapSet::max_states() const {
 }
 
 const Family& MapSet::family(int k) const {
+  if (normalised && k > 1) throw std::runtime_error("fused families are built for the un-normalised form only");
   std::lock_guard<std::mutex> lk(fam_mu_);
   auto it = fam_.find(k);
   if (it != fam_.end()) return *it->second;
@@ -516,45 +559,48 @@ size_t MapSet::host_bytes() const {
   return s;
 }
 
-std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads) {
+std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads, bool normalised) {
   if (lattice != kSquare && lattice != kTriangular) throw std::runtime_error("bad lattice");
   if (m < 1 || m > kMaxM) throw std::runtime_error("m out of range");
   if (threads <= 0) threads = std::max(1u, std::thread::hardware_concurrency());
   auto ms = std::make_unique<MapSet>();
   ms->lattice = lattice;
   ms->m = m;
+  ms->normalised = normalised;
   ms->fwd.resize(m);
   ms->last.resize(m);
-  std::vector<std::vector<uint16_t>> fkeys(m), lkeys(m);
-  std::atomic<uint64_t> seen[(kKeys + 63) / 64];
-  for (auto& s : seen) s = 0;
+  if (normalised) ms->last_fwd.resize(m);
+  std::vector<std::vector<int32_t>> fkeys(m), lkeys(m), gkeys(m);
+  std::vector<std::atomic<uint64_t>> seen((kKeys + 63) / 64);
+  for (auto& w : seen) w = 0;
   for (int i = 1; i <= m; ++i) {
-    build_factor(forward_def(lattice, m, i), true, threads, ms->fwd[i - 1], fkeys[i - 1], seen);
-    build_factor(last_def(lattice, m, i), false, threads, ms->last[i - 1], lkeys[i - 1], seen);
+    build_factor(forward_def(lattice, m, i), true, normalised, threads, ms->fwd[i - 1], fkeys[i - 1], seen.data());
+    build_factor(last_def(lattice, m, i), false, normalised, threads, ms->last[i - 1], lkeys[i - 1], seen.data());
+    if (normalised)
+      build_factor(last_def(lattice, m, i), true, normalised, threads, ms->last_fwd[i - 1], gkeys[i - 1],
+                   seen.data());
   }
   // Codes: +1 -> 0, -1 -> 1, then every other coefficient in key order.
-  int key_to_code[kKeys];
-  std::fill(key_to_code, key_to_code + kKeys, -1);
+  std::vector<int> key_to_code(kKeys, -1);
   auto add = [&](int key) {
     if (key_to_code[key] >= 0) return;
     if (static_cast<int>(ms->codes.size()) >= kMaxCodes) throw std::runtime_error("too many distinct coefficients");
     key_to_code[key] = static_cast<int>(ms->codes.size());
-    Poly p;
-    p.c[0] = key % 33 - kKeyA;
-    p.c[1] = key / 33 - kKeyB;
-    ms->codes.push_back(p);
+    ms->codes.push_back(key_poly(key));
   };
-  add(coef_key(1, 0));
-  add(coef_key(-1, 0));
+  const int one[kMaxDeg + 1] = {1, 0, 0, 0}, minus_one[kMaxDeg + 1] = {-1, 0, 0, 0};
+  add(coef_key(one));
+  add(coef_key(minus_one));
   for (int k = 0; k < kKeys; ++k)
     if ((seen[k / 64].load() >> (k % 64)) & 1ull) add(k);
-  auto finish = [&](Csr& c, const std::vector<uint16_t>& keys) {
+  auto finish = [&](Csr& c, const std::vector<int32_t>& keys) {
     for (size_t e = 0; e < c.ent.size(); ++e)
       c.ent[e] |= static_cast<uint32_t>(key_to_code[keys[e]]) << kSrcBits;
   };
   for (int i = 0; i < m; ++i) {
     finish(ms->fwd[i], fkeys[i]);
     finish(ms->last[i], lkeys[i]);
+    if (normalised) finish(ms->last_fwd[i], gkeys[i]);
   }
   const char* order = std::getenv("CHROMSTRIP_STATE_ORDER");
   if (!(order && std::string(order) == "paper")) reader_order(ms->fwd);
@@ -616,15 +662,15 @@ StagedCsr build_staged(const Csr& c, int slots, int rows) {
 
 namespace {
 std::mutex g_cache_mu;
-std::map<std::pair<int, int>, std::unique_ptr<MapSet>> g_cache;
+std::map<std::tuple<int, int, bool>, std::unique_ptr<MapSet>> g_cache;
 }  // namespace
 
-const MapSet& get_maps(int lattice, int m) {
+const MapSet& get_maps(int lattice, int m, bool normalised) {
   std::lock_guard<std::mutex> lk(g_cache_mu);
-  auto key = std::make_pair(lattice, m);
+  auto key = std::make_tuple(lattice, m, normalised);
   auto it = g_cache.find(key);
   if (it != g_cache.end()) return *it->second;
-  auto ms = build_maps(lattice, m);
+  auto ms = build_maps(lattice, m, 0, normalised);
   const MapSet& ref = *ms;
   g_cache.emplace(key, std::move(ms));
   return ref;

@@ -58,6 +58,9 @@ struct Family {
 
 struct MapSet {
   int lattice = 0, m = 0;
+  // Coefficients in z = q (false) or in z = x = 1/q, the normalised weights
+  // of eq. Z_modified (true).
+  bool normalised = false;
   // fwd[i-1]: factor T_i, rows = states after it, columns = states before it
   // (gather form: out[row] = sum over entries coef * in[col]).
   std::vector<Csr> fwd;
@@ -65,7 +68,11 @@ struct MapSet {
   // columns = states after it (L_i).  Applied for i = m..1 to e_0 it gives
   // the read-out vector w = T_last^T e_0 over the NCNNN states.
   std::vector<Csr> last;
-  std::vector<Poly> codes;        // base table: codes of fwd and last (degree <= 1)
+  // Normalised sets only: last_fwd[i-1] = T_i^last in gather form (rows =
+  // states after it, L_i; columns = states before it, L_{i-1}), for a
+  // read-out that applies T_last to the state of every row.
+  std::vector<Csr> last_fwd;
+  std::vector<Poly> codes;        // base table: codes of fwd, last and last_fwd
   int64_t total_nnz() const;
   int64_t max_states() const;
   size_t host_bytes() const;
@@ -96,10 +103,10 @@ StagedCsr build_staged(const Csr& c, int slots, int rows);
 
 // Builds every single-factor map of (lattice, m); threads = 0 uses the
 // hardware count.  Throws std::runtime_error on failure.
-std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads = 0);
+std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads = 0, bool normalised = false);
 
 // Host-side map cache (thread safe): built on first request.
-const MapSet& get_maps(int lattice, int m);
+const MapSet& get_maps(int lattice, int m, bool normalised = false);
 void release_host_maps();
 
 }  // namespace cs

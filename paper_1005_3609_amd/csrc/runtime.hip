@@ -105,6 +105,9 @@ struct DevMaps {
   size_t bytes = 0;
   DevCsr fwd[kMaxM];
   DevCsr last[kMaxM];
+  DevCsr last_fwd[kMaxM];    // normalised sets: T_i^last in gather form
+  bool normalised = false;
+  int64_t l_max = 0;         // normalised sets: largest read-out space L_1 .. L_m
   std::vector<Poly> codes;   // base table of fwd and last
   int64_t s_nc = 0;    // NCNNN states
   int64_t s_max = 0;   // largest space
@@ -131,19 +134,22 @@ void upload_csr(const Csr& c, DevCsr& d, char*& cur) {
 }
 
 std::mutex g_dev_mu;
-std::map<std::tuple<int, int, int>, std::unique_ptr<DevMaps>> g_dev;
+std::map<std::tuple<int, int, int, int>, std::unique_ptr<DevMaps>> g_dev;
 
-const DevMaps& dev_maps(int lattice, int m) {
+// Device copy of the maps of (lattice, m) in the un-normalised (evaluation)
+// or normalised (coefficient) form.
+const DevMaps& dev_maps(int lattice, int m, bool normalised = false) {
   int dev = 0;
   HIPX(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_dev_mu);
-  auto key = std::make_tuple(dev, lattice, m);
+  auto key = std::make_tuple(dev, lattice, m, normalised ? 1 : 0);
   auto it = g_dev.find(key);
   if (it != g_dev.end()) return *it->second;
-  const MapSet& ms = get_maps(lattice, m);
+  const MapSet& ms = get_maps(lattice, m, normalised);
   auto dm = std::make_unique<DevMaps>();
   size_t bytes = 0;
   for (int i = 0; i < m; ++i) bytes += csr_bytes(ms.fwd[i]) + csr_bytes(ms.last[i]);
+  for (const Csr& c : ms.last_fwd) bytes += csr_bytes(c);
   void* base = nullptr;
   if (hipMalloc(&base, bytes) != hipSuccess) throw MemError("device allocation of factor maps failed");
   char* cur = static_cast<char*>(base);
@@ -151,6 +157,11 @@ const DevMaps& dev_maps(int lattice, int m) {
     upload_csr(ms.fwd[i], dm->fwd[i], cur);
     upload_csr(ms.last[i], dm->last[i], cur);
   }
+  for (size_t i = 0; i < ms.last_fwd.size(); ++i) {
+    upload_csr(ms.last_fwd[i], dm->last_fwd[i], cur);
+    dm->l_max = std::max<int64_t>(dm->l_max, ms.last_fwd[i].n_rows);
+  }
+  dm->normalised = normalised;
   dm->base = base;
   dm->bytes = bytes;
   dm->codes = ms.codes;
@@ -236,7 +247,22 @@ const DevFamily& dev_family(const DevMaps& dm, int k) {
   if (it != dm.fam.end()) return *it->second;
   auto df = std::make_unique<DevFamily>();
   df->k = k;
-  if (k == 1) {
+  if (dm.normalised) {
+    // coefficient form: the kernels' Horner variable is x itself (no shift)
+    if (k != 1) throw ArgError("the coefficient form runs single factors only (fuse 1)");
+    df->fac.assign(dm.fwd, dm.fwd + dm.m);
+    df->codes = dm.codes;
+    df->shift = 0;
+    const MapSet& ms = get_maps(dm.lattice, dm.m, true);
+    std::vector<bool> used(dm.codes.size(), false);
+    for (const Csr& c : ms.fwd)
+      for (uint32_t e : c.ent) used[e >> kSrcBits] = true;
+    for (const Csr& c : ms.last_fwd)
+      for (uint32_t e : c.ent) used[e >> kSrcBits] = true;
+    for (size_t c = 0; c < dm.codes.size(); ++c)
+      for (int d = 0; d <= kMaxDeg && used[c]; ++d)
+        df->general = df->general || dm.codes[c].c[d] > 1 || dm.codes[c].c[d] < -1;
+  } else if (k == 1) {
     df->fac.assign(dm.fwd, dm.fwd + dm.m);
     df->codes = dm.codes;
     df->shift = choose_shift(dm.codes, get_maps(dm.lattice, dm.m).fwd, df->general);
@@ -429,6 +455,11 @@ struct JobLayout {
   int nparts = 0;        // read-out partial tiles per chunk
   int ngroups = 0;       // level-1 reduction groups per chunk
   size_t x0 = 0, x1 = 0, w = 0, part = 0, part2 = 0, p = 0, pinv = 0, r1 = 0, tv = 0, ts = 0, poly = 0, bytes = 0;
+  // coefficient form: one chunk per prime, lane V + j = coefficient of x^k
+  bool cf = false;
+  int dlen = 0;          // coefficients emitted per row and prime (d_max + 1)
+  int64_t l_max = 0;     // largest read-out space
+  size_t ra = 0, rb = 0, e0 = 0;
 };
 
 // Level-1 groups: about 32 partials each, at most 64 groups.
@@ -471,6 +502,52 @@ JobLayout job_layout(int lattice, int m, int I, const Tune& t, int ncodes, int r
   L.tv = take(L.ipad * 4);
   L.ts = take(L.ipad * 4);
   L.poly = take(static_cast<size_t>(kMaxCodes) * 8);
+  L.bytes = off;
+  return L;
+}
+
+// Layout of a coefficient-form strip: np chunks (one per prime) of W = 64 V
+// coefficients, the two state vectors, the read-out ping-pong pair and the
+// constants.  No read-out vector, partials or reductions.
+JobLayout job_layout_series(int lattice, int m, int np, int d_max, const Tune& t, int64_t l_max) {
+  JobLayout L;
+  L.lattice = lattice;
+  L.m = m;
+  L.V = t.V;
+  L.W = 64 * t.V;
+  if (d_max < 0 || d_max >= L.W) throw ArgError("d_max must be in 0 .. 64 * lanes_v - 1");
+  L.cf = true;
+  L.dlen = d_max + 1;
+  L.nchunk = np;
+  L.I = np * L.W;
+  L.ipad = L.I;
+  L.ncodes = kMaxCodes;
+  L.rows_tile = t.rpw * t.wpb;
+  Sizes s = space_sizes(lattice, m);
+  L.s_nc = s.s_nc;
+  L.s_max = s.s_max;
+  L.l_max = std::max<int64_t>(l_max, 1);
+  if (static_cast<uint64_t>(std::max(L.s_max, L.l_max)) * L.W * 4 >= (uint64_t(1) << 32))
+    throw ArgError("one chunk's state vector would exceed 4 GiB; use fewer lanes_v");
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    size_t o = off;
+    off += align_up(b);
+    return o;
+  };
+  const size_t vec = static_cast<size_t>(L.nchunk) * L.s_max * L.W * 4;
+  L.x0 = take(vec);
+  L.x1 = take(vec);
+  L.ra = take(static_cast<size_t>(L.nchunk) * L.l_max * L.W * 4);
+  L.rb = take(static_cast<size_t>(L.nchunk) * L.l_max * L.W * 4);
+  L.w = L.part = L.part2 = off;
+  L.p = take(L.ipad * 4);
+  L.pinv = take(L.ipad * 4);
+  L.r1 = take(L.ipad * 4);
+  L.tv = take(L.ipad * 4);
+  L.ts = take(L.ipad * 4);
+  L.poly = take(static_cast<size_t>(kMaxCodes) * 8);
+  L.e0 = take(L.ipad * 4);
   L.bytes = off;
   return L;
 }
@@ -536,6 +613,7 @@ std::vector<uint32_t> const_image(const JobLayout& L, const std::vector<Inst>& i
 // Pointers of one job's device state.
 struct JobPtrs {
   uint32_t *x0, *x1, *w, *part, *part2, *p, *pinv, *r1, *tv, *ts, *poly;
+  uint32_t *ra = nullptr, *rb = nullptr, *e0 = nullptr;   // coefficient form
   InstConsts ic() const { return InstConsts{p, pinv, tv, ts, reinterpret_cast<const int32_t*>(poly)}; }
 };
 
@@ -553,6 +631,11 @@ JobPtrs job_ptrs(const JobLayout& L, void* base) {
   j.tv = reinterpret_cast<uint32_t*>(b + L.tv);
   j.ts = reinterpret_cast<uint32_t*>(b + L.ts);
   j.poly = reinterpret_cast<uint32_t*>(b + L.poly);
+  if (L.cf) {
+    j.ra = reinterpret_cast<uint32_t*>(b + L.ra);
+    j.rb = reinterpret_cast<uint32_t*>(b + L.rb);
+    j.e0 = reinterpret_cast<uint32_t*>(b + L.e0);
+  }
   return j;
 }
 
@@ -593,7 +676,8 @@ struct JobCtx {
   JobLayout L;
   JobPtrs P;
   Tune t;
-  uint32_t* d_out;   // [n_max][I]
+  uint32_t* d_out;   // [n_max][I], or [n_max][np][dlen] in the coefficient form
+  long out_row_stride = 0;   // elements per output row
 };
 
 int tiles_for(int64_t rows, int rows_tile) {
@@ -652,7 +736,47 @@ int push_reduce(Program& pg, const JobCtx& j, int out_row, int dep) {
 
 // Set-up: w = (T_1^last)^T ... (T_m^last)^T (R e_0) built in x0/x1 and
 // written to w, then x = e_0 in x0 and Z_1 = <w, e_0>.  Linear chain.
+// Coefficient form: read-out of the state in x by the read-out factors in
+// gather form, T_1^last first (x -> L_1 -> ... -> L_m, ping-pong through
+// ra / rb), then the single state left (all singletons) emitted as output
+// row out_row.  Returns the emit step.
+int push_readout_cf(Program& pg, const JobCtx& j, const uint32_t* x, int after, int out_row) {
+  const JobLayout& L = j.L;
+  const uint32_t* in = x;
+  long in_cs = static_cast<long>(L.s_max) * L.W;
+  const long r_cs = static_cast<long>(L.l_max) * L.W;
+  uint32_t* buf[2] = {j.P.ra, j.P.rb};
+  for (int i = 1; i <= L.m; ++i) {
+    uint32_t* out = buf[(i - 1) % 2];
+    Step g = gather_step(j, j.dm->last_fwd[i - 1], in, out, r_cs, false, j.fam->general);
+    g.u.g.in_cstride = in_cs;
+    g.cf = 1;
+    after = push(pg, g, after, -1);
+    in = out;
+    in_cs = r_cs;
+  }
+  Step e{};
+  e.op = kOpEmit;
+  e.ntiles = 1;
+  e.u.e = EmitArgs{in, r_cs, j.d_out ? j.d_out + static_cast<long>(out_row) * j.out_row_stride : nullptr, L.dlen};
+  return push(pg, e, after, -1);
+}
+
+// Coefficient form, row 0: x0 = e_0 (coefficient array 1 in every chunk),
+// then its read-out.
+int add_setup_cf(Program& pg, const JobCtx& j) {
+  const JobLayout& L = j.L;
+  const long cs_x = static_cast<long>(L.s_max) * L.W;
+  Step s{};
+  s.op = kOpFill;
+  s.ntiles = tiles_for(L.s_nc, L.rows_tile);
+  s.u.f = FillArgs{j.P.x0, cs_x, static_cast<int>(L.s_nc), j.P.e0, j.t.rpw};
+  const int last = push(pg, s, -1, -1);
+  return push_readout_cf(pg, j, j.P.x0, last, 0);
+}
+
 int add_setup(Program& pg, const JobCtx& j) {
+  if (j.L.cf) return add_setup_cf(pg, j);
   const JobLayout& L = j.L;
   const long cs_x = static_cast<long>(L.s_max) * L.W;
   const long cs_w = static_cast<long>(L.s_nc) * L.W;
@@ -697,6 +821,17 @@ void add_rows(Program& pg, const JobCtx& j, int r_first, int r_last, int after, 
     uint32_t* cur = (done_gathers % 2 == 0) ? j.P.x0 : j.P.x1;
     uint32_t* oth = (cur == j.P.x0) ? j.P.x1 : j.P.x0;
     int tm = -1;
+    if (L.cf) {
+      // coefficient form: the factors, then the read-out chain on a copy
+      for (int i = 1; i <= nf; ++i) {
+        Step g = gather_step(j, j.fam->fac[i - 1], cur, oth, cs_x, false, j.fam->general);
+        g.cf = 1;
+        after = push(pg, g, after, -1);
+        std::swap(cur, oth);
+      }
+      after = push_readout_cf(pg, j, cur, after, r);
+      continue;
+    }
     for (int i = 1; i <= nf; ++i) {
       const bool fused = (i == nf);
       const DevStaged* sd = (j.stg && !fused) ? &j.stg->fac[i - 1] : nullptr;
@@ -737,7 +872,12 @@ void launch_step_vu(const Step& s, int c0, int nch, int wpb, int xcd, hipStream_
   dim3 grid(s.ntiles, nch), block(64 * wpb);
   switch (s.op) {
     case kOpGather:
-      if (s.u.g.tile_row0) {
+      if (s.cf) {
+        if (s.general)
+          hipLaunchKernelGGL((k_gather<V, U, true, true>), grid, block, 0, st, s.u.g, xcd, c0);
+        else
+          hipLaunchKernelGGL((k_gather<V, U, false, true>), grid, block, 0, st, s.u.g, xcd, c0);
+      } else if (s.u.g.tile_row0) {
         if constexpr (V <= 2) {
           if (s.general)
             hipLaunchKernelGGL((k_stage<V, U, true>), grid, block, s.lds_bytes, st, s.u.g, xcd, c0);
@@ -747,10 +887,16 @@ void launch_step_vu(const Step& s, int c0, int nch, int wpb, int xcd, hipStream_
           throw std::runtime_error("staged tiles need lanes_v 1 or 2");
         }
       } else if (s.general) {
-        hipLaunchKernelGGL((k_gather<V, U, true>), grid, block, 0, st, s.u.g, xcd, c0);
+        hipLaunchKernelGGL((k_gather<V, U, true, false>), grid, block, 0, st, s.u.g, xcd, c0);
       } else {
-        hipLaunchKernelGGL((k_gather<V, U, false>), grid, block, 0, st, s.u.g, xcd, c0);
+        hipLaunchKernelGGL((k_gather<V, U, false, false>), grid, block, 0, st, s.u.g, xcd, c0);
       }
+      break;
+    case kOpEmit:
+      if (row_ctr)
+        hipLaunchKernelGGL(k_emit_counted, dim3(nch), dim3(256), 0, st, s.u.e, c0, row_ctr, row_stride);
+      else
+        hipLaunchKernelGGL(k_emit, dim3(nch), dim3(256), 0, st, s.u.e, c0);
       break;
     case kOpDot: hipLaunchKernelGGL(k_dot<V>, grid, block, 0, st, s.u.d, xcd, c0); break;
     case kOpFill: hipLaunchKernelGGL(k_fill<V>, grid, block, 0, st, s.u.f, c0); break;
@@ -855,9 +1001,10 @@ struct GraphKey {
   void* ws;
   uint32_t* out;
   int lattice, m, I, V, rpw, wpb, xcd, rows_per_graph;
+  int cf_len;   // coefficient form: coefficients per row and prime (0: evaluation form)
   bool operator<(const GraphKey& o) const {
-    return std::tie(ws, out, lattice, m, I, V, rpw, wpb, xcd, rows_per_graph) <
-           std::tie(o.ws, o.out, o.lattice, o.m, o.I, o.V, o.rpw, o.wpb, o.xcd, o.rows_per_graph);
+    return std::tie(ws, out, lattice, m, I, V, rpw, wpb, xcd, rows_per_graph, cf_len) <
+           std::tie(o.ws, o.out, o.lattice, o.m, o.I, o.V, o.rpw, o.wpb, o.xcd, o.rows_per_graph, o.cf_len);
   }
 };
 struct GraphEntry {
@@ -890,7 +1037,8 @@ void run_graph(const JobCtx& j, int n_max, int* row_ctr, void* ws, hipStream_t s
   HIPX(hipGetLastError());
   if (replays > 0) {
     GraphKey key{ws, j.d_out, j.L.lattice, j.L.m, j.L.I, j.t.V, j.t.rpw, j.t.wpb,
-                 j.t.stage * 10000 + j.t.fuse * 1000 + j.t.xcd * 100 + j.t.U * 10 + j.t.streams, per};
+                 j.t.stage * 10000 + j.t.fuse * 1000 + j.t.xcd * 100 + j.t.U * 10 + j.t.streams, per,
+                 j.L.cf ? j.L.dlen : 0};
     hipGraphExec_t exec = nullptr;
     {
       std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -904,8 +1052,10 @@ void run_graph(const JobCtx& j, int n_max, int* row_ctr, void* ws, hipStream_t s
       add_rows(rows_pg, j, 1, per, -1, -1);
       // reduce2 writes the row given by the device counter; k_bump advances
       // it once every chunk group has written
-      for (PStep& ps : rows_pg.steps)
+      for (PStep& ps : rows_pg.steps) {
         if (ps.s.op == kOpReduce2) ps.s.u.r.out = j.d_out;
+        if (ps.s.op == kOpEmit) ps.s.u.e.dst = j.d_out;
+      }
       hipStream_t cs = capture_stream();
       HIPX(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       for (int r = 0; r < per; ++r) {
@@ -913,7 +1063,7 @@ void run_graph(const JobCtx& j, int n_max, int* row_ctr, void* ws, hipStream_t s
         one.nchunk = rows_pg.nchunk;
         const size_t len = rows_pg.steps.size() / per;
         one.steps.assign(rows_pg.steps.begin() + r * len, rows_pg.steps.begin() + (r + 1) * len);
-        run_eager(one, j.t, cs, true, row_ctr, j.L.I);
+        run_eager(one, j.t, cs, true, row_ctr, j.out_row_stride);
         hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, cs, row_ctr);
       }
       hipGraph_t graph = nullptr;
@@ -1196,6 +1346,7 @@ int strip_async_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, c
   j.L = job_layout(lattice, m, I, t, kMaxCodes, rows_tile_of(t));
   j.P = job_ptrs(j.L, ws);
   j.d_out = d_out;
+  j.out_row_stride = j.L.I;
   bind_staging(j, mode);
   std::vector<uint32_t> img = const_image(j.L, inst, j.fam->codes, j.fam->shift);
   upload(static_cast<char*>(ws) + j.L.p, img.data(), img.size() * 4, st);
@@ -1254,6 +1405,107 @@ int strip_sync_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, co
       }
     }
   }
+  return CHROM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Coefficient form (normalised weights as truncated polynomials in x = 1/q)
+// ---------------------------------------------------------------------------
+int64_t readout_l_max(int lattice, int m) {
+  const MapSet& ms = get_maps(lattice, m, true);
+  int64_t l = 1;
+  for (const Csr& c : ms.last_fwd) l = std::max<int64_t>(l, c.n_rows);
+  return l;
+}
+
+Tune resolve_series(const chrom_tuning* tune) {
+  Tune t = resolve(tune);
+  if (t.fuse != 1) throw ArgError("the coefficient form runs single factors only (fuse 1)");
+  if (t.stage) throw ArgError("the coefficient form does not stage tiles");
+  return t;
+}
+
+size_t series_workspace_bytes(int lattice, int m, int np, int d_max, const Tune& t) {
+  return job_layout_series(lattice, m, np, d_max, t, readout_l_max(lattice, m)).bytes + 256;  // + row counter
+}
+
+void check_primes(const uint32_t* p, int np) {
+  if (np < 1 || !p) throw ArgError("need at least one prime");
+  for (int b = 0; b < np; ++b)
+    if (p[b] <= 2u || p[b] >= (1u << 31) || (p[b] & 1u) == 0u)
+      throw ArgError("each prime must be odd with 2 < p < 2^31");
+}
+
+int series_async_impl(int lattice, int m, int n_max, int d_max, const uint32_t* p, int np, int mode,
+                      const chrom_tuning* tune, void* ws, size_t ws_bytes, hipStream_t st, uint32_t* d_out) {
+  check_args(lattice, m, n_max);
+  if (mode != CHROM_MODE_BATCHED && mode != CHROM_MODE_GRAPH)
+    throw ArgError("the coefficient form runs in batched or graph mode");
+  check_primes(p, np);
+  Tune t = resolve_series(tune);
+  if (n_max == 0) return CHROM_OK;
+  if (!ws || !d_out) throw ArgError("null workspace or output");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) throw ArgError("workspace must be 256-byte aligned");
+  const DevMaps& dm = dev_maps(lattice, m, true);
+  JobCtx j;
+  j.dm = &dm;
+  j.fam = &dev_family(dm, 1);
+  j.t = t;
+  j.L = job_layout_series(lattice, m, np, d_max, t, dm.l_max);
+  if (ws_bytes < j.L.bytes + 256) throw MemError("workspace too small: need " + std::to_string(j.L.bytes + 256) + " bytes");
+  j.P = job_ptrs(j.L, ws);
+  j.d_out = d_out;
+  j.out_row_stride = static_cast<long>(np) * j.L.dlen;
+  std::vector<Inst> inst(j.L.ipad);
+  for (int k = 0; k < j.L.ipad; ++k) inst[k] = Inst{0u, p[k / j.L.W]};
+  std::vector<uint32_t> img = const_image(j.L, inst, j.fam->codes, 0);
+  upload(static_cast<char*>(ws) + j.L.p, img.data(), img.size() * 4, st);
+  std::vector<uint32_t> e0(j.L.ipad, 0u);
+  for (int c = 0; c < np; ++c) e0[static_cast<size_t>(c) * j.L.W] = 1u;
+  upload(static_cast<char*>(ws) + j.L.e0, e0.data(), e0.size() * 4, st);
+  int* row_ctr = reinterpret_cast<int*>(static_cast<char*>(ws) + j.L.bytes);
+  if (mode == CHROM_MODE_BATCHED) {
+    Program pg = strip_program(j, n_max);
+    run_eager(pg, t, st);
+  } else {
+    run_graph(j, n_max, row_ctr, ws, st);
+  }
+  return CHROM_OK;
+}
+
+void drop_graphs_on(void* ws) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+    if (it->first.ws == ws) {
+      (void)hipGraphExecDestroy(it->second.exec);
+      it = g_graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+int series_sync_impl(int lattice, int m, int n_max, int d_max, const uint32_t* p, int np, int mode,
+                     const chrom_tuning* tune, uint32_t* out) {
+  check_args(lattice, m, n_max);
+  check_primes(p, np);
+  if (n_max == 0) return CHROM_OK;
+  if (!out) throw ArgError("null output");
+  chrom_tuning tt{};
+  if (tune) tt = *tune;
+  if (!tt.lanes_v) tt.lanes_v = d_max < 64 ? 1 : (d_max < 128 ? 2 : 4);
+  const Tune t = resolve_series(&tt);
+  const size_t wsb = series_workspace_bytes(lattice, m, np, d_max, t);
+  DevBuf ws(wsb);
+  const size_t outb = static_cast<size_t>(n_max) * np * (d_max + 1) * 4;
+  DevBuf dout(outb);
+  HIPX(hipMemset(dout.p, 0, outb));
+  int rc = series_async_impl(lattice, m, n_max, d_max, p, np, mode, &tt, ws.p, wsb, nullptr,
+                             static_cast<uint32_t*>(dout.p));
+  if (rc != CHROM_OK) return rc;
+  HIPX(hipDeviceSynchronize());
+  HIPX(hipMemcpy(out, dout.p, outb, hipMemcpyDeviceToHost));
+  if (mode == CHROM_MODE_GRAPH) drop_graphs_on(ws.p);
   return CHROM_OK;
 }
 
@@ -1341,6 +1593,7 @@ int batch_impl(const chrom_job* jobs, int njobs, const chrom_tuning* tune, void*
     void* base = static_cast<char*>(ws) + bp.job_off[k];
     j.P = job_ptrs(j.L, base);
     j.d_out = jb.d_out;
+    j.out_row_stride = j.L.I;
     if (jb.n_max > 0) {
       std::vector<uint32_t> img = const_image(j.L, inst, j.fam->codes, j.fam->shift);
       upload(static_cast<char*>(base) + j.L.p, img.data(), img.size() * 4, st);
@@ -1402,6 +1655,7 @@ int server_step_impl(chrom_slot* slots, int nslots, int rows, const chrom_tuning
     j.L = L;
     j.P = job_ptrs(L, sl.d_state);
     j.d_out = sl.d_out;
+    j.out_row_stride = j.L.I;
     progs[k].nchunk = L.nchunk;
     int first = sl.rows_done;
     int last_row = std::min(sl.n_max - 1, first + rows - 1);  // 0-based out rows to produce
@@ -1479,6 +1733,34 @@ int chromatic_strip_async(int lattice, int m, int n_max, const uint32_t* q_point
   });
 }
 
+size_t chromatic_series_workspace_bytes(int lattice, int m, int n_max, int np, int d_max, int mode,
+                                        const chrom_tuning* tune) {
+  size_t r = 0;
+  int rc = guarded([&] {
+    check_args(lattice, m, n_max);
+    if (np < 1) throw ArgError("need np >= 1");
+    if (mode != CHROM_MODE_BATCHED && mode != CHROM_MODE_GRAPH)
+      throw ArgError("the coefficient form runs in batched or graph mode");
+    r = series_workspace_bytes(lattice, m, np, d_max, resolve_series(tune));
+    return CHROM_OK;
+  });
+  return rc == CHROM_OK ? r : 0;
+}
+
+int chromatic_series_async(int lattice, int m, int n_max, int d_max, const uint32_t* primes, int np, int mode,
+                           const chrom_tuning* tune, void* d_workspace, size_t ws_bytes, void* stream,
+                           uint32_t* d_out) {
+  return guarded([&] {
+    return series_async_impl(lattice, m, n_max, d_max, primes, np, mode, tune, d_workspace, ws_bytes,
+                             static_cast<hipStream_t>(stream), d_out);
+  });
+}
+
+int chromatic_series(int lattice, int m, int n_max, int d_max, const uint32_t* primes, int np, int mode,
+                     const chrom_tuning* tune, uint32_t* out) {
+  return guarded([&] { return series_sync_impl(lattice, m, n_max, d_max, primes, np, mode, tune, out); });
+}
+
 int chromatic_factor_launches(int lattice, int m, const uint32_t* q_points, int nq, const uint32_t* primes, int np,
                               int rows, const chrom_tuning* tune, void* d_workspace, size_t ws_bytes, void* stream) {
   return guarded([&] {
@@ -1507,6 +1789,11 @@ void chromatic_release_maps(void) {
       int cur = 0;
       (void)hipGetDevice(&cur);
       (void)hipSetDevice(std::get<0>(kv.first));
+      (void)hipDeviceSynchronize();
+      for (auto& fam : kv.second->fam) {
+        for (auto& st : fam.second->staged) (void)hipFree(st.second->base);
+        if (fam.second->base) (void)hipFree(fam.second->base);
+      }
       (void)hipFree(kv.second->base);
       (void)hipSetDevice(cur);
     }
@@ -1641,12 +1928,12 @@ int chromatic_map_export(int lattice, int m, int which, int idx, int64_t* n_rows
                          int32_t* row_ptr, uint32_t* entries) {
   return guarded([&] {
     check_args(lattice, m, 0);
-    if (which < 0 || which > 3) throw ArgError("which must be 0, 1, 2 or 3");
-    const MapSet& ms = get_maps(lattice, m);
+    if (which < 0 || which > 5) throw ArgError("which must be in 0..5");
+    const MapSet& ms = get_maps(lattice, m, which >= 4);
     const Csr* c = nullptr;
-    if (which <= 1) {
+    if (which <= 1 || which >= 4) {
       if (idx < 0 || idx >= m) throw ArgError("idx out of range");
-      c = which == 0 ? &ms.fwd[idx] : &ms.last[idx];
+      c = (which == 0 || which == 4) ? &ms.fwd[idx] : (which == 1 ? &ms.last[idx] : &ms.last_fwd[idx]);
     } else {
       const Family& f = ms.family(which);
       if (idx < 0 || idx >= static_cast<int>(f.fac.size())) throw ArgError("idx out of range");
@@ -1657,6 +1944,18 @@ int chromatic_map_export(int lattice, int m, int which, int idx, int64_t* n_rows
     if (nnz) *nnz = c->nnz();
     if (row_ptr) std::memcpy(row_ptr, c->row_ptr.data(), c->row_ptr.size() * 4);
     if (entries && !c->ent.empty()) std::memcpy(entries, c->ent.data(), c->ent.size() * 4);
+    return CHROM_OK;
+  });
+}
+
+int chromatic_code_table(int lattice, int m, int normalised, int* n_codes, int64_t* coef) {
+  return guarded([&] {
+    check_args(lattice, m, 0);
+    const MapSet& ms = get_maps(lattice, m, normalised != 0);
+    if (n_codes) *n_codes = static_cast<int>(ms.codes.size());
+    if (coef)
+      for (size_t c = 0; c < ms.codes.size(); ++c)
+        for (int k = 0; k <= kMaxDeg; ++k) coef[c * (kMaxDeg + 1) + k] = ms.codes[c].c[k];
     return CHROM_OK;
   });
 }

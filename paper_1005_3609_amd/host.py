@@ -81,3 +81,29 @@ def stabilised(q_points, residues, primes) -> tuple[list[int], int]:
             return cur, k
         prev = cur
     return prev, len(primes)
+
+
+def series_exact(residues, primes) -> tuple[list[int], int]:
+    """Integer coefficients of the normalised polynomial P~ (powers of x =
+    1/q) from the coefficient form: residues[b][k] = coefficient k mod
+    primes[b].  Returns (coefficients, modulus); exact while every
+    |coefficient| < modulus / 2 (Sec. 3.5: CRT over the primes)."""
+    M = prod(int(p) for p in primes)
+    out = []
+    for k in range(len(residues[0])):
+        x, _ = crt([residues[b][k] for b in range(len(primes))], primes)
+        out.append(symmetric(x, M))
+    return out, M
+
+
+def series_stabilised(residues, primes) -> tuple[list[int], int]:
+    """Adds primes one at a time until the lifted coefficients of P~ stop
+    changing (the stopping rule of Sec. 3.5); returns (coefficients, primes
+    used)."""
+    prev = None
+    for k in range(1, len(primes) + 1):
+        cur, _ = series_exact([row for row in residues[:k]], primes[:k])
+        if cur == prev:
+            return cur, k
+        prev = cur
+    return prev, len(primes)

@@ -1,0 +1,101 @@
+"""Host side of the coefficient form (normalised weights, polynomials in
+x = 1/q, Sec. 3.5): the normalised factor maps and read-out maps, run by a
+small numpy interpreter on truncated coefficient arrays mod p (test code,
+not a product path), reproduce the oracle's truncated P~ exactly; the maps
+have the same sparsity as the evaluation-form maps; the CRT helpers lift
+residues back to the integers."""
+import numpy as np
+import pytest
+
+from oracle import transfer as OT
+from paper_1005_3609_amd import api, host
+
+SQ, TRI = "square", "triangular"
+P31 = 2 ** 31 - 1
+
+
+def _apply_poly(csr, polys, X, p):
+    """out[t] = sum over entries (t, s, c) of polys[c](x) * X[s], truncated
+    to X's number of coefficients, mod p."""
+    rp, cols, codes, _ = csr
+    nrows = rp.size - 1
+    D1 = X.shape[1]
+    out = np.zeros((nrows, D1), dtype=np.int64)
+    if cols.size:
+        rows = np.repeat(np.arange(nrows), np.diff(rp))
+        src = X[cols]
+        for k in range(polys.shape[1]):
+            ck = polys[codes, k] % p
+            if not ck.any() or k >= D1:
+                continue
+            contrib = np.zeros_like(src)
+            contrib[:, k:] = (ck[:, None] * src[:, : D1 - k]) % p
+            np.add.at(out, rows, contrib)
+    return out % p
+
+
+def _run_series(lat, m, n_max, d, p):
+    polys = api.code_table(lat, m, normalised=True)
+    fwd = [api.map_export(lat, m, 4, i) for i in range(m)]
+    last = [api.map_export(lat, m, 5, i) for i in range(m)]
+    x = np.zeros((fwd[0][3], d + 1), dtype=np.int64)
+    x[0, 0] = 1                                          # e_0: all singletons, weight 1
+    rows = []
+    for r in range(n_max):
+        y = x
+        for i in range(m):
+            y = _apply_poly(last[i], polys, y, p)
+        assert y.shape[0] == 1
+        rows.append(y[0])
+        if r + 1 < n_max:
+            for i in range(m):
+                x = _apply_poly(fwd[i], polys, x, p)
+    return np.stack(rows)
+
+
+def _oracle_series(lat, m, n_max, d, p):
+    res = OT.projected_strip(lat, m, n_max, OT.ExactX(dmax=d))
+    out = np.zeros((n_max, d + 1), dtype=np.int64)
+    for r, z in enumerate(res):
+        z = list(z)[: d + 1]
+        out[r, : len(z)] = [c % p for c in z]
+    return out
+
+
+@pytest.mark.parametrize("lat", [SQ, TRI])
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("d,p", [(5, P31), (30, 998244353)])
+def test_normalised_maps_reproduce_oracle(lat, m, d, p):
+    np.testing.assert_array_equal(_run_series(lat, m, 4, d, p), _oracle_series(lat, m, 4, d, p))
+
+
+@pytest.mark.parametrize("lat", [SQ, TRI])
+def test_normalised_maps_share_the_sparsity(lat):
+    m = 6
+    for i in range(m):
+        a = api.map_export(lat, m, 0, i)
+        b = api.map_export(lat, m, 4, i)
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
+        # entry by entry the two coefficients agree up to a power of q:
+        # c_norm(1/q) q^k = c(q) for some k in 0..3
+        un = api.code_table(lat, m, normalised=False)[a[2]]
+        no = api.code_table(lat, m, normalised=True)[b[2]]
+        for u, n in zip(un, no):
+            ok = any(all(n[i] == (u[k - i] if 0 <= k - i < 4 else 0) for i in range(4)) and
+                     all(u[j] == (n[k - j] if 0 <= k - j < 4 else 0) for j in range(4)) for k in range(4))
+            assert ok, (u, n)
+
+
+def test_series_crt_lifts_to_the_exact_polynomial():
+    # 3 x 4 square: P~ has degree 11, coefficients well below the product of 3 primes
+    ps = [P31, 998244353, 1000000007]
+    d = 14
+    res = np.stack([_run_series(SQ, 3, 4, d, p)[3] for p in ps])
+    coef, _ = host.series_exact(res, ps)
+    exact = OT.chromatic_exact(SQ, 3, 4)[3]                 # P(q), ascending powers of q
+    V = 12
+    want = [exact[V - k] if 0 <= V - k < len(exact) else 0 for k in range(d + 1)]
+    assert coef == want
+    stab, used = host.series_stabilised(res, ps)
+    assert stab == want and used <= 3
