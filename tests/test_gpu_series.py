@@ -1,0 +1,99 @@
+"""GPU parity of the coefficient form (normalised chromatic polynomial
+P~ = q^-|V| P as truncated polynomials in x = 1/q, Sec. 3.5): bit-exact
+against the oracle's truncated P~, and at full width against the
+evaluation form's polynomial recovered by interpolation."""
+import numpy as np
+import pytest
+
+from oracle import transfer as OT
+from paper_1005_3609_amd import api, host
+from paper_1005_3609_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+SQ, TRI = "square", "triangular"
+P31 = 2 ** 31 - 1
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    yield
+
+
+def _oracle(lat, m, n_max, d, primes):
+    res = OT.projected_strip(lat, m, n_max, OT.ExactX(dmax=d))
+    out = np.zeros((n_max, len(primes), d + 1), dtype=np.int64)
+    for r, z in enumerate(res):
+        z = list(z)[: d + 1]
+        for b, p in enumerate(primes):
+            out[r, b, : len(z)] = [c % p for c in z]
+    return out
+
+
+@pytest.mark.parametrize("lat", [SQ, TRI])
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6])
+def test_series_matches_oracle(lat, m):
+    primes = [P31, 998244353]
+    for d, tune in ((20, dict(lanes_v=1)), (63, dict(lanes_v=1, targets_per_wave=3, waves_per_block=2)),
+                    (100, dict(lanes_v=2, unroll=8, streams=2))):
+        want = _oracle(lat, m, 5, d, primes)
+        for mode in ("batched", "graph"):
+            got = api.series(lat, m, 5, d, primes, mode=mode, tuning=tune).astype(np.int64)
+            np.testing.assert_array_equal(got, want, err_msg=f"{lat} m={m} d={d} {mode} {tune}")
+
+
+def test_series_tunings_identical():
+    primes = W.seeded_primes(3, 11)
+    ref = api.series(SQ, 7, 6, 120, primes, mode="graph", tuning=dict(lanes_v=2))
+    for tune in (dict(lanes_v=4, targets_per_wave=16, waves_per_block=8, xcd_order=3),
+                 dict(lanes_v=2, targets_per_wave=1, waves_per_block=1, unroll=8),
+                 dict(lanes_v=2, targets_per_wave=33, waves_per_block=4, streams=3, xcd_order=2)):
+        for mode in ("batched", "graph"):
+            got = api.series(SQ, 7, 6, 120, primes, mode=mode, tuning=tune)
+            np.testing.assert_array_equal(got, ref, err_msg=f"{mode} {tune}")
+
+
+def test_series_lifts_to_exact_polynomial():
+    primes = W.seeded_primes(4, 12)
+    d = 25
+    res = api.series(SQ, 4, 6, d, primes, mode="graph", tuning=dict(lanes_v=1))
+    exact = OT.chromatic_exact(SQ, 4, 6)
+    for r in range(6):
+        V = 4 * (r + 1)
+        want = [exact[r][V - k] if 0 <= V - k < len(exact[r]) else 0 for k in range(d + 1)]
+        coef, used = host.series_stabilised(res[r].astype(np.int64), primes)
+        assert coef == want, r
+
+
+@pytest.mark.parametrize("lat,m", [(SQ, 14), (TRI, 12)])
+def test_series_full_width_matches_evaluation_form(lat, m):
+    # m x 1 .. m x 5 rectangles: |V| = m (r+1) <= 70 < 80 coefficients kept, so
+    # the coefficient form holds P~ exactly; the evaluation form at q = 0..70
+    # gives P itself by interpolation (mod p): P~_k = P_{|V|-k}.
+    primes = W.seeded_primes(2, 13)
+    n = 5
+    d = 79
+    ser = api.series(lat, m, n, d, primes, mode="graph", tuning=dict(lanes_v=2))
+    qs = list(range(0, 71))
+    ev = api.strip(lat, m, n, qs, primes, mode="graph")
+    for r in range(n):
+        V = m * (r + 1)
+        if V > 70:
+            continue
+        for b, p in enumerate(primes):
+            poly = host.interp_mod_p(qs, [int(ev[r, a, b]) for a in range(len(qs))], p)
+            want = [poly[V - k] if V - k >= 0 else 0 for k in range(d + 1)]
+            np.testing.assert_array_equal(ser[r, b].astype(np.int64), want, err_msg=f"{lat} m={m} r={r} p={p}")
+
+
+def test_series_bad_arguments():
+    with pytest.raises(api.ChromError):
+        api.series(SQ, 4, 3, 64, [P31], tuning=dict(lanes_v=1))          # d_max >= 64 lanes_v
+    with pytest.raises(api.ChromError):
+        api.series(SQ, 4, 3, 10, [P31], tuning=dict(fuse=2))
+    with pytest.raises(api.ChromError):
+        api.series(SQ, 4, 3, 10, [P31], mode="grouped")
+    with pytest.raises(api.ChromError):
+        api.series(SQ, 4, 3, 10, [4])
