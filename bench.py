@@ -160,6 +160,56 @@ def bench_triangular(torch, stream, steps):
             "value": updates_of(lat, m, n, I) / (ms / 1e3), "unit": "state-updates/s"}
 
 
+def bench_series(torch, stream, tune, steps):
+    """The coefficient form (normalised P~ as truncated polynomials in 1/q,
+    x^0..x^79, the paper's series order) on the square 14x15 strip for the
+    workload's 8 primes: 8 x 80 = 640 useful coefficient lanes, one launch
+    chain per row with the T_last read-out applied to every row's state."""
+    from paper_1005_3609_amd import api
+    from paper_1005_3609_amd import workloads as W
+    w = W.workload("square_14x15")
+    lat, m, n = w["strips"][0]
+    primes = w["primes"]
+    d = 79
+    t = {k: v for k, v in tune.items() if k not in ("fuse", "stage")}
+    t["lanes_v"] = 2
+    dev = torch.device("cuda", torch.cuda.current_device())
+    out, ws = api.series_async(lat, m, n, d, primes, mode="graph", tuning=t, stream=stream, device=dev)
+    ms = timed(torch, stream, lambda: api.series_async(lat, m, n, d, primes, mode="graph", tuning=t,
+                                                       workspace=ws, out=out, stream=stream), steps)
+    res = api.to_u32(out).astype("int64").reshape(n, len(primes), d + 1)
+    assert (res[:, :, 0] == 1).all(), "constant term of P~ must be 1"
+    lanes = len(primes) * (d + 1)
+    return {"workload": f"square 14x15, coefficient form x^0..x^{d} (normalised P~), {len(primes)} seeded primes "
+                        f"({lanes} coefficient lanes), graph row replay, tuning {t}",
+            "ms_per_step": ms, "value": updates_of(lat, m, n, lanes) / (ms / 1e3), "unit": "state-updates/s"}
+
+
+def bench_finite_lattice(k):
+    """The square-lattice free-energy series of Table 1 to z^{2k-4} by the
+    finite-lattice method: coefficient-form strips of widths 1..k/2 on the
+    GPU, per-prime combination and CRT on the host; checked against the
+    paper's Table 1."""
+    from paper_1005_3609_amd import finite_lattice as FL
+    from paper_1005_3609_amd import workloads as W
+    t0 = time.perf_counter()
+    res = FL.square_series(k, W.seeded_primes(5, 2024), mode="graph")
+    dt = time.perf_counter() - t0
+    N = 2 * k - 4
+    tab = {}
+    with open(os.path.join(ROOT, "tests", "golden", "table1_square.txt")) as f:
+        for ln in f:
+            if not ln.startswith("#") and ln.strip():
+                kk, a, b, c = ln.split()
+                tab[int(kk)] = (int(a), int(b), None if c == "-" else int(c))
+    match = all(res[name][i] == tab[i][j] for j, name in enumerate(("alpha", "beta", "gamma"))
+                for i in range(N + 1))
+    assert match, "finite-lattice series differ from Table 1"
+    return {"workload": f"square-lattice bulk, surface and corner series to z^{N} (finite-lattice k = {k}: "
+                        f"widths 1..{k // 2}, coefficient form x^0..x^{N}, 5 seeded primes)",
+            "seconds": dt, "primes_used": res["primes_used"], "matches_table1": match}
+
+
 def bench_m18(torch, stream, tune, rows):
     """The square 18x19 strip with the workload's 640 instances: one vector is
     8.2 GB, far beyond the 256 MB Infinity Cache, so the factor kernel's
@@ -393,6 +443,11 @@ def main():
         log(f"triangular m=12: {extra['triangular_12x13']['value']:.3e} state-updates/s")
         extra["serving"] = bench_serving(torch, args.serve_jobs, args.serve_plain_jobs)
         log(f"serving: {extra['serving']}")
+        extra["finite_lattice_square"] = bench_finite_lattice(33)
+        log(f"finite-lattice series: {extra['finite_lattice_square']}")
+        extra["series_square_14x15"] = bench_series(torch, stream, tune, max(2, args.steps // 2))
+        log(f"coefficient form m=14: {extra['series_square_14x15']['value']:.3e} state-updates/s, "
+            f"{extra['series_square_14x15']['ms_per_step']:.2f} ms/strip")
     if not args.quick and not args.no_m18 and wname != "square_18x19":
         extra["square_18x19"] = bench_m18(torch, stream, tune, args.m18_rows)
         k = extra["square_18x19"]["factor_kernel"]

@@ -1,0 +1,164 @@
+"""Finite-lattice series of the square-lattice chromatic polynomial (Sec. 4.1),
+from the coefficient form computed on the GPU.
+
+The free energies are combinations, with integer finite-lattice weights, of
+log P~_{G(r,s)}(z) over the rectangles of B(k) = {r <= s, r + s <= k}, in
+z = 1/(q-1), correct to O(z^{2k-3}).  Exponentiated they are products of
+powers of power series with constant term 1:
+    A(z) = (1+z)^2 prod P~^{alpha_k(r,s)}   (Table 1: exp f_b = (q-1)^2/q A)
+    B(z) = prod P~^{beta_k(r,s)}             (exp f_s)
+    C(z) = prod P~^{gamma_k(r,s)}            (exp f_c)
+Only ring operations occur (products, inverses of series with constant term
+1), so every prime is combined on its own, straight from the GPU residues
+of P~ (no lift of P~ itself, whose coefficients are far larger), and only
+the final coefficients are lifted by CRT; primes are added until they stop
+changing (Sec. 3.5).
+
+Surface weights: the last term of the printed beta_k(r,s) reads
+(r+s-2)/2; the one weight of that shape that extracts the (r+s) part of
+rs f_b + (r+s) f_s + f_c has (r+s+2)/2, which is used here.
+"""
+from __future__ import annotations
+
+from . import api, host
+
+SQUARE = "square"
+
+
+def rectangles(k: int):
+    """B(k) as (r, s) pairs, r <= s, r + s <= k."""
+    out = []
+    for r in range(1, k // 2 + 1):
+        for s in range(r, k - r + 1):
+            out.append((r, s))
+    return out
+
+
+def weights(k: int, r: int, s: int) -> tuple[int, int, int]:
+    """(alpha_k, beta_k, gamma_k)(r, s): finite-lattice weights for the bulk,
+    surface and corner free energies (integers; zero unless k-3 <= r+s <= k)."""
+    j = k - (r + s)
+    if j < 0 or j > 3:
+        return 0, 0, 0
+    n, rs = r + s, r * s
+    mult = 1 if r == s else 2
+    a = (1, -3, 3, -1)[j]
+    twice_b = (2 - n, 3 * n - 2, -(3 * n + 2), n + 2)[j]
+    c = ((r - 1) * (s - 1), 1 + n - 3 * rs, 3 * rs + n - 1, -(r + 1) * (s + 1))[j]
+    b = mult * twice_b
+    assert b % 2 == 0
+    return mult * a, b // 2, mult * c
+
+
+# ---------------------------------------------------------------------------
+# Power series mod p, truncated after z^N (lists of N + 1 residues)
+# ---------------------------------------------------------------------------
+def _mul(a, b, N, p):
+    """a b mod p by one big-integer product (Kronecker substitution: the
+    coefficients become digits of 2^bits-ary numbers wide enough for the
+    exact convolution sums)."""
+    bits = 2 * p.bit_length() + (N + 1).bit_length() + 1
+    A = int.from_bytes(b"".join(int(x).to_bytes((bits + 7) // 8, "little") for x in a[: N + 1]), "little")
+    B = int.from_bytes(b"".join(int(x).to_bytes((bits + 7) // 8, "little") for x in b[: N + 1]), "little")
+    step = 8 * ((bits + 7) // 8)
+    prod = A * B
+    mask = (1 << step) - 1
+    out = []
+    for _ in range(N + 1):
+        out.append((prod & mask) % p)
+        prod >>= step
+    return out
+
+
+def _inv(a, N, p):
+    """1 / a mod p for a[0] = 1 (coefficient recurrence)."""
+    out = [1] + [0] * N
+    for n in range(1, N + 1):
+        acc = 0
+        for i in range(1, min(n, len(a) - 1) + 1):
+            acc += a[i] * out[n - i]
+        out[n] = (-acc) % p
+    return out
+
+
+def _pow(a, e: int, N, p):
+    base = _inv(a, N, p) if e < 0 else [x % p for x in a[: N + 1]]
+    e = abs(e)
+    out = [1] + [0] * N
+    while e:
+        if e & 1:
+            out = _mul(out, base, N, p)
+        e >>= 1
+        if e:
+            base = _mul(base, base, N, p)
+    return out
+
+
+def _in_z(px, N, p):
+    """P~(x) with x = z/(1+z), by Horner's rule on series mod p."""
+    X = [0] + [(1 if i % 2 else p - 1) for i in range(1, N + 1)]   # z - z^2 + z^3 - ...
+    acc = [0] * (N + 1)
+    for j in range(min(len(px), N + 1) - 1, -1, -1):
+        acc = _mul(acc, X, N, p)
+        acc[0] = (acc[0] + int(px[j])) % p
+    return acc
+
+
+def combine_mod(ptilde, k: int, p: int):
+    """(A, B, C) mod p from P~_{r,s}(x) mod p, ptilde[(r, s)] = coefficient
+    list of x^0 .. (at least) x^{2k-4}."""
+    N = 2 * k - 4
+    A = [1, 2, 1][: N + 1] + [0] * max(0, N - 2)
+    B = [1] + [0] * N
+    C = [1] + [0] * N
+    for (r, s) in rectangles(k):
+        wa, wb, wc = weights(k, r, s)
+        if not (wa or wb or wc):
+            continue
+        pz = _in_z(ptilde[(r, s)], N, p)
+        if wa:
+            A = _mul(A, _pow(pz, wa, N, p), N, p)
+        if wb:
+            B = _mul(B, _pow(pz, wb, N, p), N, p)
+        if wc:
+            C = _mul(C, _pow(pz, wc, N, p), N, p)
+    return A, B, C
+
+
+def square_series(k: int, primes, mode: str = "graph", tuning=None, lanes_v: int | None = None):
+    """Table 1's series A, B, C to z^{2k-4} from the GPU coefficient form.
+
+    Runs one coefficient-form strip per width r = 1..k/2 (rows up to k - r,
+    d_max = 2k - 4) for all primes at once, combines every prime, and lifts
+    the final coefficients by CRT, adding primes until two successive lifts
+    agree.  Returns dict(alpha, beta, gamma, primes_used, stable)."""
+    N = 2 * k - 4
+    if lanes_v is None:
+        lanes_v = 1 if N < 64 else (2 if N < 128 else 4)
+    t = dict(tuning or {})
+    t["lanes_v"] = lanes_v
+    per_prime = [dict() for _ in primes]
+    for r in range(1, k // 2 + 1):
+        n = k - r
+        res = api.series(SQUARE, r, n, N, primes, mode=mode, tuning=t)   # [n][np][N+1]
+        for s in range(r, n + 1):
+            for b in range(len(primes)):
+                per_prime[b][(r, s)] = [int(v) for v in res[s - 1, b]]
+    mods = [combine_mod(per_prime[b], k, int(p)) for b, p in enumerate(primes)]
+    out, prev, used = None, None, len(primes)
+    for u in range(1, len(primes) + 1):
+        cur = []
+        for which in range(3):
+            col = []
+            for i in range(N + 1):
+                x, M = host.crt([mods[b][which][i] for b in range(u)], primes[:u])
+                col.append(host.symmetric(x, M))
+            cur.append(col)
+        if cur == prev:
+            out, used = cur, u
+            break
+        prev = cur
+    stable = out is not None
+    if out is None:
+        out = prev
+    return {"alpha": out[0], "beta": out[1], "gamma": out[2], "primes_used": used, "stable": stable}

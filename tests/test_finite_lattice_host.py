@@ -1,0 +1,50 @@
+"""Host finish of the finite-lattice series (paper_1005_3609_amd.finite_lattice):
+its weights equal the oracle's, and combining P~ residues computed without
+the GPU (the normalised maps run by a test interpreter) reproduces the
+paper's Table 1 after the CRT lift."""
+import pytest
+
+from mapinterp import run_series, table1
+from oracle import series as S
+from paper_1005_3609_amd import finite_lattice as FL
+from paper_1005_3609_amd import host
+
+
+@pytest.mark.parametrize("k", range(3, 30))
+def test_weights_match_oracle(k):
+    assert sorted(FL.rectangles(k)) == sorted(S.rectangles(k))
+    for r, s in FL.rectangles(k):
+        assert FL.weights(k, r, s) == (S.alpha_weight(k, r, s), S.beta_weight(k, r, s), S.gamma_weight(k, r, s))
+
+
+def test_series_helpers_mod_p():
+    p = 998244353
+    N = 9
+    a = [1, 4, p - 3, 7, 0, 2, 0, 0, 0, 0]
+    inv = FL._inv(a, N, p)
+    assert FL._mul(a, inv, N, p) == [1] + [0] * N
+    assert FL._mul(FL._pow(a, -3, N, p), FL._pow(a, 3, N, p), N, p) == [1] + [0] * N
+    # x -> z agrees with the oracle's integer substitution, reduced mod p
+    px = [1, -5, 9, -2, 4]
+    assert FL._in_z([c % p for c in px], N, p) == [c % p for c in S.x_to_z(px, N)]
+
+
+def test_combination_reproduces_table1():
+    k = 10
+    N = 2 * k - 4
+    primes = [2147483647, 998244353, 1000000007]
+    mods = []
+    for p in primes:
+        pt = {}
+        for r in range(1, k // 2 + 1):
+            res = run_series("square", r, k - r, N, p)
+            for s in range(r, k - r + 1):
+                pt[(r, s)] = [int(v) for v in res[s - 1]]
+        mods.append(FL.combine_mod(pt, k, p))
+    t = table1()
+    for which in range(3):
+        got = []
+        for i in range(N + 1):
+            x, M = host.crt([mods[b][which][i] for b in range(len(primes))], primes)
+            got.append(host.symmetric(x, M))
+        assert got == [t[i][which] for i in range(N + 1)], which

@@ -1,0 +1,102 @@
+"""Pins of the oracle's finite-lattice series (Sec. 4.1) against what the
+paper fixes: the coefficients Table 1 prints for the square lattice, and
+the identities the finite-lattice weights must satisfy (each weight set
+extracts exactly its own term of rs f_b + (r+s) f_s + f_c)."""
+import os
+
+import pytest
+
+from oracle import series as S
+from oracle import transfer as T
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def table1():
+    """tests/golden/table1_square.txt: the paper's Table 1 (k, alpha, beta, gamma)."""
+    rows = {}
+    with open(os.path.join(GOLDEN, "table1_square.txt")) as f:
+        for ln in f:
+            if ln.startswith("#") or not ln.strip():
+                continue
+            k, a, b, c = ln.split()
+            rows[int(k)] = (int(a), int(b), None if c == "-" else int(c))
+    return rows
+
+
+def test_table1_fixture_is_whole():
+    t = table1()
+    assert sorted(t) == list(range(80))
+    assert t[0] == (1, 1, 1) and t[8] == (3, -8, 12) and t[79][2] is None
+
+
+@pytest.mark.parametrize("k", [5, 8, 11])
+def test_series_reproduce_table1(k):
+    t = table1()
+    N = 2 * k - 4
+    al, be, ga = S.square_series(k)
+    assert al == [t[i][0] for i in range(N + 1)]
+    assert be == [t[i][1] for i in range(N + 1)]
+    assert ga == [t[i][2] for i in range(N + 1)]
+
+
+@pytest.mark.parametrize("k", range(4, 26))
+def test_weights_extract_their_term(k):
+    # sum over B(k) of w * F for F = 1, r+s, rs: (0, 0, 1) for alpha (bulk),
+    # (0, 1, 0) for beta (surface), (1, 0, 0) for gamma (corner)
+    for wfun, want in ((S.alpha_weight, (0, 0, 1)), (S.beta_weight, (0, 1, 0)), (S.gamma_weight, (1, 0, 0))):
+        got = [0, 0, 0]
+        for r, s in S.rectangles(k):
+            w = wfun(k, r, s)
+            got[0] += w
+            got[1] += w * (r + s)
+            got[2] += w * r * s
+        assert tuple(got) == want, (wfun.__name__, k)
+
+
+def test_printed_surface_weight_fails_the_pins():
+    # planted mistake: the printed last term (r+s-2)/2 of beta_k
+    from fractions import Fraction
+
+    def printed(k, r, s):
+        n = r + s
+        d = lambda a, b: 1 if a == b else 0  # noqa: E731
+        w = (Fraction(2 - n, 2) * d(n, k) + Fraction(3 * n - 2, 2) * d(n, k - 1)
+             - Fraction(3 * n + 2, 2) * d(n, k - 2) + Fraction(n - 2, 2) * d(n, k - 3)) * (2 - d(r, s))
+        return int(w)
+    k = 8
+    assert sum(printed(k, r, s) * (r + s) for r, s in S.rectangles(k)) != 1
+    orig = S.beta_weight
+    try:
+        S.beta_weight = printed
+        _, be, _ = S.square_series(k)
+    finally:
+        S.beta_weight = orig
+    assert be != [table1()[i][1] for i in range(2 * k - 3)]
+
+
+def test_x_to_z_substitution():
+    N = 10
+    # x = z/(1+z) = z - z^2 + z^3 - ...
+    assert S.x_to_z([0, 1], N) == [0] + [(-1) ** (i + 1) for i in range(1, N + 1)]
+    # 1/(1-x) = 1 + z in z: (1 - x) (1 + z) = 1
+    one_minus_x = S.x_to_z([1, -1], N)
+    assert S.ps_mul(one_minus_x, [1, 1] + [0] * (N - 1), N) == [1] + [0] * N
+
+
+def test_power_series_inverse_and_powers():
+    N = 12
+    a = [1, 3, -2, 5] + [0] * (N - 3)
+    assert S.ps_mul(a, S.ps_inv(a, N), N) == [1] + [0] * N
+    assert S.ps_pow(a, 3, N) == S.ps_mul(S.ps_mul(a, a, N), a, N)
+    assert S.ps_mul(S.ps_pow(a, -2, N), S.ps_pow(a, 2, N), N) == [1] + [0] * N
+
+
+def test_ptilde_of_a_path_in_z():
+    # 1 x s rectangle = path of s vertices: P = q (q-1)^(s-1), so
+    # P~ = q^-s P = (1 - x)^(s-1) and, in z, (1+z)^-(s-1)
+    N = 8
+    rows = S.ptilde_x(T.SQUARE, 1, 4, N)
+    for s in range(1, 5):
+        pz = S.x_to_z(rows[s - 1], N)
+        assert S.ps_mul(pz, S.ps_pow([1, 1] + [0] * (N - 1), s - 1, N), N) == [1] + [0] * N

@@ -8,49 +8,11 @@ import numpy as np
 import pytest
 
 from oracle import transfer as OT
+from mapinterp import run_series as _run_series
 from paper_1005_3609_amd import api, host
 
 SQ, TRI = "square", "triangular"
 P31 = 2 ** 31 - 1
-
-
-def _apply_poly(csr, polys, X, p):
-    """out[t] = sum over entries (t, s, c) of polys[c](x) * X[s], truncated
-    to X's number of coefficients, mod p."""
-    rp, cols, codes, _ = csr
-    nrows = rp.size - 1
-    D1 = X.shape[1]
-    out = np.zeros((nrows, D1), dtype=np.int64)
-    if cols.size:
-        rows = np.repeat(np.arange(nrows), np.diff(rp))
-        src = X[cols]
-        for k in range(polys.shape[1]):
-            ck = polys[codes, k] % p
-            if not ck.any() or k >= D1:
-                continue
-            contrib = np.zeros_like(src)
-            contrib[:, k:] = (ck[:, None] * src[:, : D1 - k]) % p
-            np.add.at(out, rows, contrib)
-    return out % p
-
-
-def _run_series(lat, m, n_max, d, p):
-    polys = api.code_table(lat, m, normalised=True)
-    fwd = [api.map_export(lat, m, 4, i) for i in range(m)]
-    last = [api.map_export(lat, m, 5, i) for i in range(m)]
-    x = np.zeros((fwd[0][3], d + 1), dtype=np.int64)
-    x[0, 0] = 1                                          # e_0: all singletons, weight 1
-    rows = []
-    for r in range(n_max):
-        y = x
-        for i in range(m):
-            y = _apply_poly(last[i], polys, y, p)
-        assert y.shape[0] == 1
-        rows.append(y[0])
-        if r + 1 < n_max:
-            for i in range(m):
-                x = _apply_poly(fwd[i], polys, x, p)
-    return np.stack(rows)
 
 
 def _oracle_series(lat, m, n_max, d, p):
