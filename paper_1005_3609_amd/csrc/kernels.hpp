@@ -67,6 +67,18 @@ __device__ __forceinline__ void store_row(uint32_t* base, uint32_t off, const ui
   store_v<V>(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(base) + off), x);
 }
 
+// Row base for vectors whose chunk exceeds 4 GiB: the 64-bit address of row
+// `row` formed in scalar registers (readfirstlane keeps the compiler from
+// folding it into per-lane 64-bit addresses), so every access is that base
+// plus the lane's 32-bit offset.
+template <int W>
+__device__ __forceinline__ uint32_t* wide_row(const uint32_t* base, uint32_t row) {
+  const uint64_t a = reinterpret_cast<uint64_t>(base) + static_cast<uint64_t>(row) * (4u * W);
+  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(static_cast<uint32_t>(a))));
+  const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(static_cast<uint32_t>(a >> 32))));
+  return reinterpret_cast<uint32_t*>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
 // Workgroups are handed to the 8 XCDs round-robin in dispatch order.  This
 // bijection on [0, nb) gives each XCD one contiguous range of ids instead, so
 // neighbouring target rows -- which share many source rows -- run under the
@@ -349,7 +361,7 @@ __device__ __forceinline__ void horner_cf(uint32_t (&v)[V], const uint32_t (&A)[
 // rows themselves, oldest first.  Row boundaries are uniform, so each
 // finished row is stored without divergence; rows with no entries are stored
 // as zero.
-template <int V, int U, bool G, bool CF>
+template <int V, int U, bool G, bool CF, bool WIDE = false>
 __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* lds) {
   constexpr int W = 64 * V;
   const int lane = lane_id(), wave = wave_id();
@@ -391,7 +403,10 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
         horner_cf<V>(v, A, deg, p);
       else
         horner<V>(v, A, deg, tv, ts, p);
-      store_row<V>(out, static_cast<uint32_t>(row) * (4u * W) + boff, v);
+      if constexpr (WIDE)
+        store_row<V>(wide_row<W>(out, static_cast<uint32_t>(row)), boff, v);
+      else
+        store_row<V>(out, static_cast<uint32_t>(row) * (4u * W) + boff, v);
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         if (k <= deg) {
@@ -426,7 +441,10 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         w[u] = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ev0), min(e0 + u, end - 1) - base));
-        load_row<V>(in, (w[u] & kEntSrcMask) * (4u * W) + boff, x[u]);
+        if constexpr (WIDE)
+          load_row<V>(wide_row<W>(in, w[u] & kEntSrcMask), boff, x[u]);
+        else
+          load_row<V>(in, (w[u] & kEntSrcMask) * (4u * W) + boff, x[u]);
         // Keep the loads in entry order: completions are counted in issue
         // order, so entry u must not be issued after entry u + 1.
         __builtin_amdgcn_sched_barrier(0);
@@ -693,12 +711,12 @@ __device__ __forceinline__ void tile_chunk(int xcd, int chunk0, int& tile, int& 
   chunk = chunk0 + b / gridDim.x;
 }
 
-template <int V, int U, bool G, bool CF>
+template <int V, int U, bool G, bool CF, bool WIDE = false>
 __global__ void __launch_bounds__(512) k_gather(GatherArgs a, int xcd, int chunk0) {
   __shared__ uint32_t lds[8 * 64 * V];
   int tile, chunk;
   tile_chunk(xcd, chunk0, tile, chunk);
-  gather_tile<V, U, G, CF>(a, chunk, tile, lds);
+  gather_tile<V, U, G, CF, WIDE>(a, chunk, tile, lds);
 }
 
 // grid (tiles, chunks); dynamic LDS: max_slots * 64 V words
@@ -837,7 +855,7 @@ struct Step {
   int chunk;               // chunk index handed to the tile body
   int general;             // gather: needs the general coefficient path (host-side kernel choice)
   int lds_bytes;           // staged gather: dynamic LDS of the launch
-  int cf;                  // gather: coefficient form (polynomials in x = 1/q)
+  int cf;                  // gather: coefficient form (polynomials in x = 1/q); 2: also wide rows
   union {
     GatherArgs g;
     DotArgs d;

@@ -24,7 +24,9 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <climits>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <exception>
@@ -559,6 +561,24 @@ size_t MapSet::host_bytes() const {
   return s;
 }
 
+// One stderr line per built site when CHROMSTRIP_VERBOSE=1 (large widths take
+// minutes on the host).
+struct BuildLog {
+  bool on;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  BuildLog() {
+    const char* v = std::getenv("CHROMSTRIP_VERBOSE");
+    on = v && std::string(v) == "1";
+  }
+  void line(int lattice, int m, bool normalised, const char* what, int i) const {
+    if (!on) return;
+    const double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    std::fprintf(stderr, "[maps %s m=%d%s] %s %d  %.1f s\n", lattice == kSquare ? "square" : "triangular", m,
+                 normalised ? " normalised" : "", what, i, s);
+    std::fflush(stderr);
+  }
+};
+
 std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads, bool normalised) {
   if (lattice != kSquare && lattice != kTriangular) throw std::runtime_error("bad lattice");
   if (m < 1 || m > kMaxM) throw std::runtime_error("m out of range");
@@ -573,12 +593,17 @@ std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads, bool normali
   std::vector<std::vector<int32_t>> fkeys(m), lkeys(m), gkeys(m);
   std::vector<std::atomic<uint64_t>> seen((kKeys + 63) / 64);
   for (auto& w : seen) w = 0;
+  // The coefficient form reads its read-out maps in gather form only, so a
+  // normalised set leaves the scatter-form `last` empty.
+  const BuildLog log;
   for (int i = 1; i <= m; ++i) {
     build_factor(forward_def(lattice, m, i), true, normalised, threads, ms->fwd[i - 1], fkeys[i - 1], seen.data());
-    build_factor(last_def(lattice, m, i), false, normalised, threads, ms->last[i - 1], lkeys[i - 1], seen.data());
     if (normalised)
       build_factor(last_def(lattice, m, i), true, normalised, threads, ms->last_fwd[i - 1], gkeys[i - 1],
                    seen.data());
+    else
+      build_factor(last_def(lattice, m, i), false, normalised, threads, ms->last[i - 1], lkeys[i - 1], seen.data());
+    log.line(lattice, m, normalised, "site", i);
   }
   // Codes: +1 -> 0, -1 -> 1, then every other coefficient in key order.
   std::vector<int> key_to_code(kKeys, -1);
@@ -599,11 +624,14 @@ std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads, bool normali
   };
   for (int i = 0; i < m; ++i) {
     finish(ms->fwd[i], fkeys[i]);
-    finish(ms->last[i], lkeys[i]);
-    if (normalised) finish(ms->last_fwd[i], gkeys[i]);
+    if (normalised)
+      finish(ms->last_fwd[i], gkeys[i]);
+    else
+      finish(ms->last[i], lkeys[i]);
   }
   const char* order = std::getenv("CHROMSTRIP_STATE_ORDER");
   if (!(order && std::string(order) == "paper")) reader_order(ms->fwd);
+  log.line(lattice, m, normalised, "reader order, sites", m);
   return ms;
 }
 

@@ -148,14 +148,14 @@ const DevMaps& dev_maps(int lattice, int m, bool normalised = false) {
   const MapSet& ms = get_maps(lattice, m, normalised);
   auto dm = std::make_unique<DevMaps>();
   size_t bytes = 0;
-  for (int i = 0; i < m; ++i) bytes += csr_bytes(ms.fwd[i]) + csr_bytes(ms.last[i]);
+  for (int i = 0; i < m; ++i) bytes += csr_bytes(ms.fwd[i]) + (normalised ? 0 : csr_bytes(ms.last[i]));
   for (const Csr& c : ms.last_fwd) bytes += csr_bytes(c);
   void* base = nullptr;
   if (hipMalloc(&base, bytes) != hipSuccess) throw MemError("device allocation of factor maps failed");
   char* cur = static_cast<char*>(base);
   for (int i = 0; i < m; ++i) {
     upload_csr(ms.fwd[i], dm->fwd[i], cur);
-    upload_csr(ms.last[i], dm->last[i], cur);
+    if (!normalised) upload_csr(ms.last[i], dm->last[i], cur);
   }
   for (size_t i = 0; i < ms.last_fwd.size(); ++i) {
     upload_csr(ms.last_fwd[i], dm->last_fwd[i], cur);
@@ -457,6 +457,7 @@ struct JobLayout {
   size_t x0 = 0, x1 = 0, w = 0, part = 0, part2 = 0, p = 0, pinv = 0, r1 = 0, tv = 0, ts = 0, poly = 0, bytes = 0;
   // coefficient form: one chunk per prime, lane V + j = coefficient of x^k
   bool cf = false;
+  bool wide = false;     // a chunk's vector reaches 4 GiB: kernels form 64-bit row bases
   int dlen = 0;          // coefficients emitted per row and prime (d_max + 1)
   int64_t l_max = 0;     // largest read-out space
   size_t ra = 0, rb = 0, e0 = 0;
@@ -527,8 +528,11 @@ JobLayout job_layout_series(int lattice, int m, int np, int d_max, const Tune& t
   L.s_nc = s.s_nc;
   L.s_max = s.s_max;
   L.l_max = std::max<int64_t>(l_max, 1);
-  if (static_cast<uint64_t>(std::max(L.s_max, L.l_max)) * L.W * 4 >= (uint64_t(1) << 32))
-    throw ArgError("one chunk's state vector would exceed 4 GiB; use fewer lanes_v");
+  L.wide = static_cast<uint64_t>(std::max(L.s_max, L.l_max)) * L.W * 4 >= (uint64_t(1) << 32);
+  // CHROMSTRIP_WIDE_ROWS=1 takes the 64-bit row-base path for any size
+  // (same results; lets small cases exercise it).
+  const char* wide_env = std::getenv("CHROMSTRIP_WIDE_ROWS");
+  if (wide_env && std::string(wide_env) == "1") L.wide = true;
   size_t off = 0;
   auto take = [&](size_t b) {
     size_t o = off;
@@ -750,7 +754,7 @@ int push_readout_cf(Program& pg, const JobCtx& j, const uint32_t* x, int after, 
     uint32_t* out = buf[(i - 1) % 2];
     Step g = gather_step(j, j.dm->last_fwd[i - 1], in, out, r_cs, false, j.fam->general);
     g.u.g.in_cstride = in_cs;
-    g.cf = 1;
+    g.cf = L.wide ? 2 : 1;
     after = push(pg, g, after, -1);
     in = out;
     in_cs = r_cs;
@@ -825,7 +829,7 @@ void add_rows(Program& pg, const JobCtx& j, int r_first, int r_last, int after, 
       // coefficient form: the factors, then the read-out chain on a copy
       for (int i = 1; i <= nf; ++i) {
         Step g = gather_step(j, j.fam->fac[i - 1], cur, oth, cs_x, false, j.fam->general);
-        g.cf = 1;
+        g.cf = L.wide ? 2 : 1;
         after = push(pg, g, after, -1);
         std::swap(cur, oth);
       }
@@ -872,7 +876,12 @@ void launch_step_vu(const Step& s, int c0, int nch, int wpb, int xcd, hipStream_
   dim3 grid(s.ntiles, nch), block(64 * wpb);
   switch (s.op) {
     case kOpGather:
-      if (s.cf) {
+      if (s.cf == 2) {
+        if (s.general)
+          hipLaunchKernelGGL((k_gather<V, U, true, true, true>), grid, block, 0, st, s.u.g, xcd, c0);
+        else
+          hipLaunchKernelGGL((k_gather<V, U, false, true, true>), grid, block, 0, st, s.u.g, xcd, c0);
+      } else if (s.cf) {
         if (s.general)
           hipLaunchKernelGGL((k_gather<V, U, true, true>), grid, block, 0, st, s.u.g, xcd, c0);
         else

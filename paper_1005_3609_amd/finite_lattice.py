@@ -125,13 +125,25 @@ def combine_mod(ptilde, k: int, p: int):
     return A, B, C
 
 
-def square_series(k: int, primes, mode: str = "graph", tuning=None, lanes_v: int | None = None):
+def prime_groups(r: int, n: int, N: int, primes, mode: str, tuning, limit: int):
+    """Splits the primes into consecutive groups whose strip workspace
+    (series_workspace_bytes, which grows linearly with the group size)
+    stays within `limit` bytes; one prime per group at the least."""
+    one = api.series_workspace_bytes(SQUARE, r, n, 1, N, mode, tuning)
+    per = max(1, min(len(primes), limit // max(one, 1)))
+    return [list(primes[i:i + per]) for i in range(0, len(primes), per)]
+
+
+def square_series(k: int, primes, mode: str = "graph", tuning=None, lanes_v: int | None = None,
+                  workspace_limit: int = 96 << 30, log=None):
     """Table 1's series A, B, C to z^{2k-4} from the GPU coefficient form.
 
     Runs one coefficient-form strip per width r = 1..k/2 (rows up to k - r,
-    d_max = 2k - 4) for all primes at once, combines every prime, and lifts
-    the final coefficients by CRT, adding primes until two successive lifts
-    agree.  Returns dict(alpha, beta, gamma, primes_used, stable)."""
+    d_max = 2k - 4), all primes at once or, where the workspace would pass
+    `workspace_limit` bytes, in groups of primes; combines every prime, and
+    lifts the final coefficients by CRT, adding primes until two successive
+    lifts agree.  `log(msg)`, if given, is called once per strip.  Returns
+    dict(alpha, beta, gamma, primes_used, stable)."""
     N = 2 * k - 4
     if lanes_v is None:
         lanes_v = 1 if N < 64 else (2 if N < 128 else 4)
@@ -140,10 +152,15 @@ def square_series(k: int, primes, mode: str = "graph", tuning=None, lanes_v: int
     per_prime = [dict() for _ in primes]
     for r in range(1, k // 2 + 1):
         n = k - r
-        res = api.series(SQUARE, r, n, N, primes, mode=mode, tuning=t)   # [n][np][N+1]
-        for s in range(r, n + 1):
-            for b in range(len(primes)):
-                per_prime[b][(r, s)] = [int(v) for v in res[s - 1, b]]
+        b0 = 0
+        for group in prime_groups(r, n, N, primes, mode, t, workspace_limit):
+            res = api.series(SQUARE, r, n, N, group, mode=mode, tuning=t)   # [n][len(group)][N+1]
+            for s in range(r, n + 1):
+                for b in range(len(group)):
+                    per_prime[b0 + b][(r, s)] = [int(v) for v in res[s - 1, b]]
+            b0 += len(group)
+            if log is not None:
+                log(f"width {r}: rows 1..{n}, {len(group)} prime(s) done")
     mods = [combine_mod(per_prime[b], k, int(p)) for b, p in enumerate(primes)]
     out, prev, used = None, None, len(primes)
     for u in range(1, len(primes) + 1):
@@ -162,3 +179,62 @@ def square_series(k: int, primes, mode: str = "graph", tuning=None, lanes_v: int
     if out is None:
         out = prev
     return {"alpha": out[0], "beta": out[1], "gamma": out[2], "primes_used": used, "stable": stable}
+
+
+def _read_table(path):
+    """k -> (alpha_k, beta_k, gamma_k) from a whitespace table with columns
+    k alpha beta gamma ('-' for an entry not given, '#' comment lines)."""
+    tab = {}
+    with open(path) as f:
+        for ln in f:
+            if ln.strip() and not ln.startswith("#"):
+                k, a, b, c = ln.split()
+                tab[int(k)] = tuple(None if x == "-" else int(x) for x in (a, b, c))
+    return tab
+
+
+def main(argv=None) -> int:
+    import argparse
+    import sys
+    import time
+
+    import numpy as np
+
+    from . import workloads as W
+
+    ap = argparse.ArgumentParser(description="Square-lattice bulk, surface and corner series to z^(2k-4) by the "
+                                             "finite-lattice method on the GPU")
+    ap.add_argument("k", type=int)
+    ap.add_argument("--primes", type=int, default=5, help="number of seeded 31-bit primes")
+    ap.add_argument("--seed", type=int, default=2024)
+    ap.add_argument("--mode", default="graph", choices=["graph", "batched"])
+    ap.add_argument("--workspace-gib", type=int, default=96, help="largest strip workspace per call")
+    ap.add_argument("--check", default=None, help="table (k alpha beta gamma) to compare with")
+    a = ap.parse_args(argv)
+    import torch
+    if not torch.cuda.is_available():
+        print("a GPU is required", file=sys.stderr)
+        return 2
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    res = square_series(a.k, W.seeded_primes(a.primes, a.seed), mode=a.mode, workspace_limit=a.workspace_gib << 30,
+                        log=lambda msg: print(f"[{time.perf_counter() - t0:7.1f} s] {msg}", flush=True))
+    dt = time.perf_counter() - t0
+    N = 2 * a.k - 4
+    for i in range(N + 1):
+        print(i, res["alpha"][i], res["beta"][i], res["gamma"][i])
+    ok = True
+    if a.check:
+        tab = _read_table(a.check)
+        bad = [(i, j) for i in range(N + 1) for j, name in enumerate(("alpha", "beta", "gamma"))
+               if i in tab and tab[i][j] is not None and res[name][i] != tab[i][j]]
+        ok = not bad and all(i in tab for i in range(N + 1))
+        print(f"check against {a.check}: {'all ' + str(3 * (N + 1)) + ' coefficients equal' if ok else bad[:10]}")
+    print(f"k = {a.k}: z^0..z^{N}, widths 1..{a.k // 2}, {res['primes_used']} of {a.primes} primes to stabilise "
+          f"({'stable' if res['stable'] else 'NOT stable'}), {dt:.1f} s; torch {torch.__version__}, "
+          f"numpy {np.__version__}", flush=True)
+    return 0 if (ok and res["stable"]) else 1
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

@@ -8,6 +8,7 @@ from mapinterp import run_series, table1
 from oracle import series as S
 from paper_1005_3609_amd import finite_lattice as FL
 from paper_1005_3609_amd import host
+from paper_1005_3609_amd import workloads as W
 
 
 @pytest.mark.parametrize("k", range(3, 30))
@@ -48,3 +49,14 @@ def test_combination_reproduces_table1():
             x, M = host.crt([mods[b][which][i] for b in range(len(primes))], primes)
             got.append(host.symmetric(x, M))
         assert got == [t[i][which] for i in range(N + 1)], which
+
+
+def test_prime_groups_bound_the_workspace():
+    from paper_1005_3609_amd import api
+    primes = W.seeded_primes(5, 2024)
+    one = api.series_workspace_bytes("square", 6, 8, 1, 30, "graph", dict(lanes_v=1))
+    assert api.series_workspace_bytes("square", 6, 8, 3, 30, "graph", dict(lanes_v=1)) <= 3 * one
+    for limit, sizes in ((10 * one, [5]), (2 * one + 1, [2, 2, 1]), (one, [1] * 5), (1, [1] * 5)):
+        g = FL.prime_groups(6, 8, 30, primes, "graph", dict(lanes_v=1), limit)
+        assert [len(x) for x in g] == sizes
+        assert sum(g, []) == primes

@@ -18,7 +18,7 @@ def _gpu():
     yield
 
 
-@pytest.mark.parametrize("k,mode", [(14, "batched"), (24, "graph")])
+@pytest.mark.parametrize("k,mode", [(14, "batched"), (24, "graph"), (37, "graph")])
 def test_square_series_match_table1(k, mode):
     res = FL.square_series(k, W.seeded_primes(5, 2024), mode=mode)
     assert res["stable"]

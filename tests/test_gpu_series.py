@@ -97,3 +97,18 @@ def test_series_bad_arguments():
         api.series(SQ, 4, 3, 10, [P31], mode="grouped")
     with pytest.raises(api.ChromError):
         api.series(SQ, 4, 3, 10, [4])
+
+
+def test_series_wide_row_addressing_identical(monkeypatch):
+    # 64-bit row bases (used when one chunk's vector reaches 4 GiB, m >= 19
+    # with 80+ coefficients) give the same residues as 32-bit offsets
+    primes = W.seeded_primes(2, 14)
+    ref = api.series(SQ, 8, 6, 90, primes, mode="graph", tuning=dict(lanes_v=2))
+    monkeypatch.setenv("CHROMSTRIP_WIDE_ROWS", "1")
+    for mode, tune in (("graph", dict(lanes_v=2)), ("batched", dict(lanes_v=2, unroll=8, streams=2)),
+                       ("graph", dict(lanes_v=4, targets_per_wave=3, waves_per_block=2))):
+        got = api.series(SQ, 8, 6, 90, primes, mode=mode, tuning=tune)
+        np.testing.assert_array_equal(got, ref, err_msg=f"{mode} {tune}")
+    got = api.series(TRI, 7, 5, 40, primes, mode="graph", tuning=dict(lanes_v=1))
+    monkeypatch.delenv("CHROMSTRIP_WIDE_ROWS")
+    np.testing.assert_array_equal(got, api.series(TRI, 7, 5, 40, primes, mode="graph", tuning=dict(lanes_v=1)))
