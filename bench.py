@@ -186,27 +186,24 @@ def bench_series(torch, stream, tune, steps):
 
 
 def bench_finite_lattice(k):
-    """The square-lattice free-energy series of Table 1 to z^{2k-4} by the
-    finite-lattice method: coefficient-form strips of widths 1..k/2 on the
-    GPU, per-prime combination and CRT on the host; checked against the
-    paper's Table 1."""
+    """The square-lattice free-energy series of Table 1 by the finite-lattice
+    method: coefficient-form strips of widths 1..k/2 on the GPU, per-prime
+    combination and CRT on the host; for odd k alpha and beta reach z^{2k-3}
+    with the polygon term; checked against the paper's Table 1."""
     from paper_1005_3609_amd import finite_lattice as FL
     from paper_1005_3609_amd import workloads as W
+    extra = k % 2 == 1
     t0 = time.perf_counter()
-    res = FL.square_series(k, W.seeded_primes(5, 2024), mode="graph")
+    res = FL.square_series(k, W.seeded_primes(5, 2024), mode="graph", extra=extra)
     dt = time.perf_counter() - t0
-    N = 2 * k - 4
-    tab = {}
-    with open(os.path.join(ROOT, "tests", "golden", "table1_square.txt")) as f:
-        for ln in f:
-            if not ln.startswith("#") and ln.strip():
-                kk, a, b, c = ln.split()
-                tab[int(kk)] = (int(a), int(b), None if c == "-" else int(c))
-    match = all(res[name][i] == tab[i][j] for j, name in enumerate(("alpha", "beta", "gamma"))
-                for i in range(N + 1))
+    tab = FL._read_table(os.path.join(ROOT, "tests", "golden", "table1_square.txt"))
+    names = ("alpha", "beta", "gamma")
+    match = all(res[name][i] == tab[i][j] for j, name in enumerate(names) for i in range(len(res[name])))
     assert match, "finite-lattice series differ from Table 1"
-    return {"workload": f"square-lattice bulk, surface and corner series to z^{N} (finite-lattice k = {k}: "
-                        f"widths 1..{k // 2}, coefficient form x^0..x^{N}, 5 seeded primes)",
+    N = len(res["alpha"]) - 1
+    return {"workload": f"square-lattice bulk and surface series to z^{N}, corner to z^{len(res['gamma']) - 1} "
+                        f"(finite-lattice k = {k}: widths 1..{k // 2}, coefficient form x^0..x^{N}, "
+                        f"5 seeded primes{', polygon term' if extra else ''})",
             "seconds": dt, "primes_used": res["primes_used"], "matches_table1": match}
 
 

@@ -119,11 +119,64 @@ def ptilde_x(lattice: str, r: int, s_max: int, dmax: int) -> list[list[int]]:
     return out
 
 
-def square_series(k: int):
+def mu_coefficients(n: int) -> list[Fraction]:
+    """mu_0 .. mu_n of the polygon generating function quoted in Sec. 4.2
+    (sum over p >= 4 of mu_p x^{2p}), as exact series in y = x^2:
+        y^4 (2 - 2y - y S) / ((1 - 4y)(2 + y)) + y^6 (3 - 4y - 4S) / (1 - 4y)^2,
+    S = sqrt(1 - 4y) = 1 - 2 sum_{j>=1} Cat(j-1) y^j (Catalan numbers)."""
+    def mul(a, b):
+        out = [Fraction(0)] * (n + 1)
+        for i, x in enumerate(a[: n + 1]):
+            if x:
+                for j, y in enumerate(b[: n + 1 - i]):
+                    out[i + j] += x * y
+        return out
+
+    def inv(a):
+        out = [Fraction(0)] * (n + 1)
+        out[0] = 1 / Fraction(a[0])
+        for t in range(1, n + 1):
+            out[t] = -sum(a[i] * out[t - i] for i in range(1, min(t, len(a) - 1) + 1)) / a[0]
+        return out
+
+    def catalan(j):
+        c = 1
+        for i in range(j):
+            c = c * 2 * (2 * i + 1) // (i + 2)
+        return c
+
+    def shifted(a, e):
+        return [Fraction(0)] * e + a[: n + 1 - e]
+
+    pad = [Fraction(0)] * (n + 1)
+    S = [Fraction(1)] + [Fraction(-2 * catalan(j - 1)) for j in range(1, n + 1)]
+    one_m4y = ([Fraction(1), Fraction(-4)] + pad)[: n + 1]
+    num1 = ([Fraction(2), Fraction(-2)] + pad)[: n + 1]
+    num1 = [a - b for a, b in zip(num1, shifted(S, 1))]
+    den1 = mul(one_m4y, ([Fraction(2), Fraction(1)] + pad)[: n + 1])
+    num2 = ([Fraction(3), Fraction(-4)] + pad)[: n + 1]
+    num2 = [a - 4 * b for a, b in zip(num2, S)]
+    den2 = mul(one_m4y, one_m4y)
+    t1 = shifted(mul(num1, inv(den1)), 4)
+    t2 = shifted(mul(num2, inv(den2)), 6)
+    return [a + b for a, b in zip(t1, t2)]
+
+
+def square_series(k: int, extra: bool = False):
     """(alpha, beta, gamma) coefficient lists of Table 1's three series,
     from the rectangles of B(k), each to order z^{2k-4} (the orders the
-    finite-lattice formulas fix)."""
-    N = 2 * k - 4
+    finite-lattice formulas fix).
+
+    extra (odd k only): alpha and beta one order further, to z^{2k-3}: the
+    finite-lattice products are taken to that order and the missing polygon
+    term of Sec. 4.2 is added to the logarithms, mu_{2 m_max} z^{4 m_max - 1}
+    to f_b and -m_max mu_{2 m_max} z^{4 m_max - 1} to f_s, with m_max =
+    (k - 1)/2 the widest strip (so 4 m_max - 1 = 2k - 3).  As the series start
+    with 1, adding c z^N to the logarithm adds c z^N to the series mod
+    z^{N+1}.  gamma stays at z^{2k-4}."""
+    if extra and k % 2 == 0:
+        raise ValueError("the extra order needs odd k (4 m_max - 1 = 2k - 3)")
+    N = 2 * k - 4 + (1 if extra else 0)
     rects = rectangles(k)
     pz = {}
     for r in sorted({r for r, _ in rects}):
@@ -139,4 +192,11 @@ def square_series(k: int):
             if e:
                 acc = ps_mul(acc, ps_pow(pz[(r, s)], e, N), N)
         series.append(acc)
+    if extra:
+        m_max = (k - 1) // 2
+        mu = mu_coefficients(2 * m_max)[2 * m_max]
+        assert mu.denominator == 1
+        series[0][N] += int(mu)
+        series[1][N] -= m_max * int(mu)
+        series[2] = series[2][:N]
     return tuple(series)

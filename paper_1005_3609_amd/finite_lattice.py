@@ -104,10 +104,49 @@ def _in_z(px, N, p):
     return acc
 
 
-def combine_mod(ptilde, k: int, p: int):
+def polygon_mu(p_max: int) -> list[int]:
+    """mu_0 .. mu_{p_max} of the generating function sum_{p>=4} mu_p x^{2p}
+    quoted in Sec. 4.2, by coefficient recurrences in y = x^2: the two terms
+    y^4 (2 - 2y - y S) / ((1 - 4y)(2 + y)) and y^6 (3 - 4y - 4S) / (1 - 4y)^2
+    with S = sqrt(1 - 4y), whose coefficients are -2 C(2j-2, j-1)/j for
+    j >= 1.  Division by (1 - 4y) is u_j = a_j + 4 u_{j-1}, by (2 + y) is
+    v_j = (u_j - v_{j-1}) / 2."""
+    from fractions import Fraction
+    from math import comb
+
+    n = max(p_max, 0)
+    S = [1] + [-2 * comb(2 * j - 2, j - 1) // j for j in range(1, n + 1)]
+
+    def over_1m4y(a):
+        out, prev = [], 0
+        for x in a:
+            prev = x + 4 * prev
+            out.append(prev)
+        return out
+
+    num1 = [(2 if j == 0 else 0) - (2 if j == 1 else 0) - (S[j - 1] if j >= 1 else 0) for j in range(n + 1)]
+    u = over_1m4y(num1)
+    v, prev = [], Fraction(0)
+    for x in u:
+        prev = (x - prev) / 2
+        v.append(prev)
+    num2 = [(3 if j == 0 else 0) - (4 if j == 1 else 0) - 4 * S[j] for j in range(n + 1)]
+    w = over_1m4y(over_1m4y(num2))
+    mu = []
+    for q in range(n + 1):
+        c = (v[q - 4] if q >= 4 else 0) + (w[q - 6] if q >= 6 else 0)
+        if Fraction(c).denominator != 1:
+            raise ArithmeticError("non-integer polygon coefficient")
+        mu.append(int(c))
+    return mu[: p_max + 1]
+
+
+def combine_mod(ptilde, k: int, p: int, N: int | None = None):
     """(A, B, C) mod p from P~_{r,s}(x) mod p, ptilde[(r, s)] = coefficient
-    list of x^0 .. (at least) x^{2k-4}."""
-    N = 2 * k - 4
+    list of x^0 .. (at least) x^N; N defaults to 2k-4, the finite-lattice
+    order."""
+    if N is None:
+        N = 2 * k - 4
     A = [1, 2, 1][: N + 1] + [0] * max(0, N - 2)
     B = [1] + [0] * N
     C = [1] + [0] * N
@@ -135,16 +174,25 @@ def prime_groups(r: int, n: int, N: int, primes, mode: str, tuning, limit: int):
 
 
 def square_series(k: int, primes, mode: str = "graph", tuning=None, lanes_v: int | None = None,
-                  workspace_limit: int = 96 << 30, log=None):
+                  workspace_limit: int = 96 << 30, log=None, extra: bool = False):
     """Table 1's series A, B, C to z^{2k-4} from the GPU coefficient form.
 
     Runs one coefficient-form strip per width r = 1..k/2 (rows up to k - r,
     d_max = 2k - 4), all primes at once or, where the workspace would pass
     `workspace_limit` bytes, in groups of primes; combines every prime, and
     lifts the final coefficients by CRT, adding primes until two successive
-    lifts agree.  `log(msg)`, if given, is called once per strip.  Returns
-    dict(alpha, beta, gamma, primes_used, stable)."""
-    N = 2 * k - 4
+    lifts agree.  `log(msg)`, if given, is called once per strip.
+
+    extra (odd k): A and B one order further, to z^{2k-3} = z^{4 m_max - 1}
+    (m_max = (k-1)/2, the widest strip): the strips and products run to that
+    order and the missing polygon term of Sec. 4.2 is added, mu_{2 m_max} to
+    A's and -m_max mu_{2 m_max} to B's last coefficient (their logarithms
+    gain those terms and both series start with 1); C stays at z^{2k-4}.
+
+    Returns dict(alpha, beta, gamma, primes_used, stable)."""
+    if extra and k % 2 == 0:
+        raise ValueError("the extra order needs odd k (4 m_max - 1 = 2k - 3)")
+    N = 2 * k - 4 + (1 if extra else 0)
     if lanes_v is None:
         lanes_v = 1 if N < 64 else (2 if N < 128 else 4)
     t = dict(tuning or {})
@@ -161,7 +209,14 @@ def square_series(k: int, primes, mode: str = "graph", tuning=None, lanes_v: int
             b0 += len(group)
             if log is not None:
                 log(f"width {r}: rows 1..{n}, {len(group)} prime(s) done")
-    mods = [combine_mod(per_prime[b], k, int(p)) for b, p in enumerate(primes)]
+    mods = [list(combine_mod(per_prime[b], k, int(p), N)) for b, p in enumerate(primes)]
+    if extra:
+        m_max = (k - 1) // 2
+        mu = polygon_mu(2 * m_max)[2 * m_max]
+        for b, p in enumerate(primes):
+            p = int(p)
+            mods[b][0][N] = (mods[b][0][N] + mu) % p
+            mods[b][1][N] = (mods[b][1][N] - m_max * mu) % p
     out, prev, used = None, None, len(primes)
     for u in range(1, len(primes) + 1):
         cur = []
@@ -178,7 +233,8 @@ def square_series(k: int, primes, mode: str = "graph", tuning=None, lanes_v: int
     stable = out is not None
     if out is None:
         out = prev
-    return {"alpha": out[0], "beta": out[1], "gamma": out[2], "primes_used": used, "stable": stable}
+    gamma = out[2][: 2 * k - 3]
+    return {"alpha": out[0], "beta": out[1], "gamma": gamma, "primes_used": used, "stable": stable}
 
 
 def _read_table(path):
@@ -210,6 +266,7 @@ def main(argv=None) -> int:
     ap.add_argument("--mode", default="graph", choices=["graph", "batched"])
     ap.add_argument("--workspace-gib", type=int, default=96, help="largest strip workspace per call")
     ap.add_argument("--check", default=None, help="table (k alpha beta gamma) to compare with")
+    ap.add_argument("--extra", action="store_true", help="odd k: alpha and beta to z^(2k-3) (polygon term)")
     a = ap.parse_args(argv)
     import torch
     if not torch.cuda.is_available():
@@ -218,18 +275,20 @@ def main(argv=None) -> int:
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
     res = square_series(a.k, W.seeded_primes(a.primes, a.seed), mode=a.mode, workspace_limit=a.workspace_gib << 30,
-                        log=lambda msg: print(f"[{time.perf_counter() - t0:7.1f} s] {msg}", flush=True))
+                        log=lambda msg: print(f"[{time.perf_counter() - t0:7.1f} s] {msg}", flush=True),
+                        extra=a.extra)
     dt = time.perf_counter() - t0
-    N = 2 * a.k - 4
+    N = len(res["alpha"]) - 1
+    names = ("alpha", "beta", "gamma")
     for i in range(N + 1):
-        print(i, res["alpha"][i], res["beta"][i], res["gamma"][i])
+        print(i, *(res[n][i] if i < len(res[n]) else "-" for n in names))
     ok = True
     if a.check:
         tab = _read_table(a.check)
-        bad = [(i, j) for i in range(N + 1) for j, name in enumerate(("alpha", "beta", "gamma"))
-               if i in tab and tab[i][j] is not None and res[name][i] != tab[i][j]]
-        ok = not bad and all(i in tab for i in range(N + 1))
-        print(f"check against {a.check}: {'all ' + str(3 * (N + 1)) + ' coefficients equal' if ok else bad[:10]}")
+        cells = [(i, j) for i in range(N + 1) for j in range(3) if i < len(res[names[j]])]
+        bad = [(i, j) for i, j in cells if i not in tab or tab[i][j] is None or res[names[j]][i] != tab[i][j]]
+        ok = not bad
+        print(f"check against {a.check}: {f'all {len(cells)} coefficients equal' if ok else bad[:10]}")
     print(f"k = {a.k}: z^0..z^{N}, widths 1..{a.k // 2}, {res['primes_used']} of {a.primes} primes to stabilise "
           f"({'stable' if res['stable'] else 'NOT stable'}), {dt:.1f} s; torch {torch.__version__}, "
           f"numpy {np.__version__}", flush=True)

@@ -60,3 +60,33 @@ def test_prime_groups_bound_the_workspace():
         g = FL.prime_groups(6, 8, 30, primes, "graph", dict(lanes_v=1), limit)
         assert [len(x) for x in g] == sizes
         assert sum(g, []) == primes
+
+
+def test_polygon_mu_matches_oracle():
+    assert FL.polygon_mu(44) == [int(x) for x in S.mu_coefficients(44)]
+
+
+@pytest.mark.parametrize("k,extra", [(9, True), (10, False), (11, True)])
+def test_square_series_host_pipeline(monkeypatch, k, extra):
+    # the whole host side of square_series (prime groups, per-prime
+    # combination, polygon term, CRT stabilisation) with the strips run by
+    # the map interpreter instead of the GPU
+    import numpy as np
+
+    def cpu_series(lat, m, n, d, primes, mode="graph", tuning=None):
+        return np.stack([run_series(lat, m, n, d, int(p)) for p in primes], axis=1)
+    monkeypatch.setattr(FL.api, "series", cpu_series)
+    res = FL.square_series(k, W.seeded_primes(4, 7), workspace_limit=1, extra=extra)
+    t = table1()
+    N = 2 * k - 4 + extra
+    assert res["stable"]
+    assert res["alpha"] == [t[i][0] for i in range(N + 1)]
+    assert res["beta"] == [t[i][1] for i in range(N + 1)]
+    assert res["gamma"] == [t[i][2] for i in range(2 * k - 3)]
+    if extra:
+        monkeypatch.setattr(FL, "polygon_mu", lambda n: [0] * (n + 1))   # planted: the polygon term dropped
+        bad = FL.square_series(k, W.seeded_primes(4, 7), extra=True)
+        assert bad["alpha"][N] != t[N][0] and bad["beta"][N] != t[N][1]
+    else:
+        with pytest.raises(ValueError):
+            FL.square_series(k, W.seeded_primes(4, 7), extra=True)

@@ -1,6 +1,7 @@
 """The finite-lattice series end to end (Sec. 4.1 with the coefficient form
 on the GPU, Sec. 3.5): the square-lattice bulk, surface and corner series
-equal the paper's Table 1."""
+equal the paper's Table 1, at odd k one order further with the polygon
+term of Sec. 4.2."""
 import pytest
 
 from mapinterp import table1
@@ -18,12 +19,14 @@ def _gpu():
     yield
 
 
-@pytest.mark.parametrize("k,mode", [(14, "batched"), (24, "graph"), (37, "graph")])
-def test_square_series_match_table1(k, mode):
-    res = FL.square_series(k, W.seeded_primes(5, 2024), mode=mode)
+@pytest.mark.parametrize("k,mode,extra", [(14, "batched", False), (24, "graph", False), (13, "graph", True),
+                                          (37, "graph", True)])
+def test_square_series_match_table1(k, mode, extra):
+    # extra: alpha and beta one order further (z^{2k-3}) with the polygon term
+    res = FL.square_series(k, W.seeded_primes(5, 2024), mode=mode, extra=extra)
     assert res["stable"]
-    N = 2 * k - 4
+    N = 2 * k - 4 + extra
     t = table1()
     assert res["alpha"] == [t[i][0] for i in range(N + 1)]
     assert res["beta"] == [t[i][1] for i in range(N + 1)]
-    assert res["gamma"] == [t[i][2] for i in range(N + 1)]
+    assert res["gamma"] == [t[i][2] for i in range(2 * k - 3)]

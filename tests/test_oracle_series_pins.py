@@ -40,6 +40,32 @@ def test_series_reproduce_table1(k):
     assert ga == [t[i][2] for i in range(N + 1)]
 
 
+@pytest.mark.parametrize("k", [5, 7, 9, 11])
+def test_extra_order_reproduces_table1(k):
+    # one order past the finite-lattice truncation, alpha and beta only
+    t = table1()
+    N = 2 * k - 3
+    al, be, ga = S.square_series(k, extra=True)
+    assert len(al) == len(be) == N + 1 and len(ga) == N
+    assert al == [t[i][0] for i in range(N + 1)]
+    assert be == [t[i][1] for i in range(N + 1)]
+    assert ga == [t[i][2] for i in range(N)]
+
+
+def test_extra_order_needs_the_polygon_term():
+    # without the mu term the z^{2k-3} coefficients are those of the plain
+    # products (planted mistake: the correction dropped)
+    k = 9
+    mu = S.mu_coefficients(k - 1)
+    assert all(x.denominator == 1 for x in mu) and mu[:4] == [0, 0, 0, 0] and mu[4] == 1
+    al, be, _ = S.square_series(k, extra=True)
+    t = table1()
+    assert al[-1] - int(mu[k - 1]) != t[2 * k - 3][0]
+    assert be[-1] + (k - 1) // 2 * int(mu[k - 1]) != t[2 * k - 3][1]
+    with pytest.raises(ValueError):
+        S.square_series(8, extra=True)
+
+
 @pytest.mark.parametrize("k", range(4, 26))
 def test_weights_extract_their_term(k):
     # sum over B(k) of w * F for F = 1, r+s, rs: (0, 0, 1) for alpha (bulk),
