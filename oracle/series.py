@@ -16,6 +16,9 @@ and Table 1 lists the coefficients alpha_k of exp(f_b) = (q-1)^2/q *
 sum alpha_k z^k, and those of exp(f_s) and exp(f_c).  With q = (1+z)/z,
 q^2/(q-1)^2 = (1+z)^2, so sum alpha_k z^k = (1+z)^2 prod P~^{alpha}.
 
+The triangular lattice takes the same weights (Sec. 4.4) with the series
+written in Baxter's variable x, q = 2 - x - 1/x, to x^{k-1}.
+
 P~_{G(r,s)} (eq. Z_modified, a polynomial in x = 1/q with constant term 1)
 comes from the oracle's transfer matrix in the normalised form
 (transfer.projected_strip with transfer.ExactX); x = z/(1+z).
@@ -23,6 +26,7 @@ comes from the oracle's transfer matrix in the normalised form
 from __future__ import annotations
 
 from fractions import Fraction
+from math import comb
 
 from . import transfer as T
 
@@ -105,6 +109,20 @@ def x_to_z(px, N):
             if i > 0:
                 binom = binom * (j + i - 1) // i
             out[j + i] += c * (-1) ** i * (binom if j > 0 else (1 if i == 0 else 0))
+    return out
+
+
+def inverse_q_to_baxter_x(pu, N):
+    """A polynomial in u = 1/q rewritten in the variable x of Sec. 4.4,
+    q = 2 - x - 1/x = -(1-x)^2/x, so u = -x (1-x)^{-2} and
+    u^j = (-1)^j x^j (1-x)^{-2j} = (-1)^j sum_i C(2j+i-1, i) x^{j+i}."""
+    out = [0] * (N + 1)
+    for j, c in enumerate(pu):
+        if j > N or not c:
+            continue
+        for i in range(0, N - j + 1):
+            binom = comb(2 * j + i - 1, i) if j > 0 else (1 if i == 0 else 0)
+            out[j + i] += c * (-1) ** j * binom
     return out
 
 
@@ -199,4 +217,30 @@ def square_series(k: int, extra: bool = False):
         series[0][N] += int(mu)
         series[1][N] -= m_max * int(mu)
         series[2] = series[2][:N]
+    return tuple(series)
+
+
+def triangular_series(k: int):
+    """(bulk, surface, corner) series of the triangular lattice in Baxter's
+    variable x (q = 2 - x - 1/x, Sec. 4.4), to x^{k-1}: the same
+    finite-lattice weights over B(k), error O(z^k) = O(x^k) there.
+        bulk    = (1-x)^2 prod P~^alpha   (exp f_b = q prod P~^alpha = -(1/x) bulk)
+        surface = prod P~^beta            (exp f_s)
+        corner  = prod P~^gamma           (exp f_c)"""
+    N = k - 1
+    rects = rectangles(k)
+    px = {}
+    for r in sorted({r for r, _ in rects}):
+        s_max = max(s for rr, s in rects if rr == r)
+        rows = ptilde_x(T.TRIANGULAR, r, s_max, N)
+        for s in range(r, s_max + 1):
+            px[(r, s)] = inverse_q_to_baxter_x(rows[s - 1], N)
+    series = []
+    for wfun, lead in ((alpha_weight, [1, -2, 1]), (beta_weight, [1]), (gamma_weight, [1])):
+        acc = (lead + [0] * (N + 1))[: N + 1]
+        for (r, s) in rects:
+            e = wfun(k, r, s)
+            if e:
+                acc = ps_mul(acc, ps_pow(px[(r, s)], e, N), N)
+        series.append(acc)
     return tuple(series)

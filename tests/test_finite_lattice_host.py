@@ -90,3 +90,46 @@ def test_square_series_host_pipeline(monkeypatch, k, extra):
     else:
         with pytest.raises(ValueError):
             FL.square_series(k, W.seeded_primes(4, 7), extra=True)
+
+
+def _triangular_golden():
+    import os
+    fs, fc = [], []
+    with open(os.path.join(os.path.dirname(__file__), "golden", "triangular_series.txt")) as f:
+        for ln in f:
+            if ln.strip() and not ln.startswith("#"):
+                _, a, b = ln.split()
+                fs.append(int(a))
+                fc.append(int(b))
+    return fs, fc
+
+
+def test_baxter_bulk_matches_the_oracle_pin():
+    from test_oracle_series_pins import baxter_bulk
+    assert FL.baxter_bulk(40) == baxter_bulk(40)
+
+
+@pytest.mark.parametrize("k", [9, 12])
+def test_triangular_series_host_pipeline(monkeypatch, k):
+    # host side of triangular_series with the strips run by the map interpreter
+    import numpy as np
+
+    def cpu_series(lat, m, n, d, primes, mode="graph", tuning=None):
+        assert lat == "triangular"
+        return np.stack([run_series(lat, m, n, d, int(p)) for p in primes], axis=1)
+    monkeypatch.setattr(FL.api, "series", cpu_series)
+    res = FL.triangular_series(k, W.seeded_primes(3, 11), workspace_limit=1)
+    fs, fc = _triangular_golden()
+    N = k - 1
+    assert res["stable"] and res["primes_used"] == 2
+    assert res["bulk"] == FL.baxter_bulk(N)
+    assert res["surface"] == fs[: N + 1]
+    assert res["corner"] == fc[: N + 1]
+    assert res == dict(zip(("bulk", "surface", "corner"), S.triangular_series(k)), primes_used=2, stable=True)
+
+
+def test_triangular_substitution_mod_p():
+    p = 998244353
+    pu = [1, -7, 3, 0, 12, -1]
+    N = 11
+    assert FL._in_baxter_x([c % p for c in pu], N, p) == [c % p for c in S.inverse_q_to_baxter_x(pu, N)]

@@ -30,3 +30,27 @@ def test_square_series_match_table1(k, mode, extra):
     assert res["alpha"] == [t[i][0] for i in range(N + 1)]
     assert res["beta"] == [t[i][1] for i in range(N + 1)]
     assert res["gamma"] == [t[i][2] for i in range(2 * k - 3)]
+
+
+def _triangular_golden():
+    import os
+    fs, fc = [], []
+    with open(os.path.join(os.path.dirname(__file__), "golden", "triangular_series.txt")) as f:
+        for ln in f:
+            if ln.strip() and not ln.startswith("#"):
+                _, a, b = ln.split()
+                fs.append(int(a))
+                fc.append(int(b))
+    return fs, fc
+
+
+@pytest.mark.parametrize("k,mode", [(12, "batched"), (30, "graph")])
+def test_triangular_series_match_paper(k, mode):
+    # Sec. 4.4: surface and corner series as printed, bulk = Baxter's product
+    res = FL.triangular_series(k, W.seeded_primes(3, 2024), mode=mode)
+    assert res["stable"]
+    fs, fc = _triangular_golden()
+    N = k - 1
+    assert res["bulk"] == FL.baxter_bulk(N)
+    assert res["surface"] == fs[: N + 1]
+    assert res["corner"] == fc[: N + 1]

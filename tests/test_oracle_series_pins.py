@@ -126,3 +126,93 @@ def test_ptilde_of_a_path_in_z():
     for s in range(1, 5):
         pz = S.x_to_z(rows[s - 1], N)
         assert S.ps_mul(pz, S.ps_pow([1, 1] + [0] * (N - 1), s - 1, N), N) == [1] + [0] * N
+
+
+# ---------------------------------------------------------------------------
+# Triangular lattice (Sec. 4.4): Baxter's variable x, q = 2 - x - 1/x
+# ---------------------------------------------------------------------------
+def triangular_golden():
+    """tests/golden/triangular_series.txt: the printed exp(f_s), exp(f_c)."""
+    fs, fc = [], []
+    with open(os.path.join(GOLDEN, "triangular_series.txt")) as f:
+        for ln in f:
+            if ln.startswith("#") or not ln.strip():
+                continue
+            k, a, b = ln.split()
+            assert int(k) == len(fs)
+            fs.append(int(a))
+            fc.append(int(b))
+    return fs, fc
+
+
+def _one_minus_power(e, power, N):
+    """(1 - x^e)^power as a series to x^N (power may be negative)."""
+    f = [1] + [0] * N
+    if e <= N:
+        f[e] = -1
+    base = f if power > 0 else S.ps_inv(f, N)
+    out = [1] + [0] * N
+    for _ in range(abs(power)):
+        out = S.ps_mul(out, base, N)
+    return out
+
+
+def _periodic_product(period, exps, N):
+    """prod_{j>=1} prod_k (1 - x^{period j - k})^{exps[k]} to x^N."""
+    out = [1] + [0] * N
+    for j in range(1, N // period + 2):
+        for k, pw in exps.items():
+            e = period * j - k
+            if 1 <= e <= N:
+                out = S.ps_mul(out, _one_minus_power(e, pw, N), N)
+    return out
+
+
+def baxter_bulk(N):
+    """-x exp(f_b) from Baxter's product (eq. efb): the product over j of
+    (1-x^{6j-3})(1-x^{6j-2})^2(1-x^{6j-1}) / ((1-x^{6j-5})(1-x^{6j-4})(1-x^{6j})(1-x^{6j+1}))."""
+    return _periodic_product(6, {3: 1, 2: 2, 1: 1, 5: -1, 4: -1, 0: -1, -1: -1}, N)
+
+
+def test_triangular_golden_matches_the_printed_products():
+    # the transcribed series against the paper's own product forms of
+    # exp(f_s) and exp(f_c) (eqs. efs, efc), which it reports agree to x^40
+    fs, fc = triangular_golden()
+    assert len(fs) == len(fc) == 41
+    assert fs == _periodic_product(12, {11: 2, 6: 2, 5: 2, 4: 2, 9: -2, 8: -2, 7: -2, 2: -2}, 40)
+    assert fc == _periodic_product(12, {11: -1, 10: 1, 9: 3, 8: 2, 7: 4, 6: -3, 5: 1, 4: -3, 3: 5, 2: 2, 1: 2, 0: 1},
+                                   40)
+
+
+def test_baxter_to_x_substitution():
+    # u = 1/q with q = 2 - x - 1/x: u = -x/(1-x)^2 = -x - 2x^2 - 3x^3 - ...;
+    # a polynomial in u and its series in x agree at a rational point inside
+    # the disc of convergence (exact rationals, truncation far below 1e-40)
+    N = 12
+    assert S.inverse_q_to_baxter_x([0, 1], N) == [0] + [-i for i in range(1, N + 1)]
+    from fractions import Fraction
+    x = Fraction(1, 9)
+    u = -x / (1 - x) ** 2
+    poly = [3, -1, 4, 1, -5]
+    lhs = sum(c * u ** j for j, c in enumerate(poly))
+    ser = S.inverse_q_to_baxter_x(poly, 60)
+    rhs = sum(c * x ** i for i, c in enumerate(ser))
+    assert abs(float(lhs - rhs)) < 1e-40
+
+
+@pytest.mark.parametrize("k", [5, 8, 11, 12])
+def test_triangular_series_match_paper(k):
+    fs, fc = triangular_golden()
+    N = k - 1
+    bulk, surf, corner = S.triangular_series(k)
+    assert bulk == baxter_bulk(N)
+    assert surf == fs[: N + 1]
+    assert corner == fc[: N + 1]
+
+
+def test_triangular_bulk_needs_its_prefactor():
+    # planted mistake: exp(f_b) without q = -(1-x)^2/x (the bulk product alone)
+    k = 9
+    bulk, _, _ = S.triangular_series(k)
+    alone = S.ps_mul(bulk, S.ps_inv([1, -2, 1] + [0] * (k - 1), k - 1), k - 1)
+    assert alone != baxter_bulk(k - 1)
