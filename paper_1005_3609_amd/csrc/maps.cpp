@@ -265,17 +265,81 @@ void parallel_for(int64_t n, int threads, F&& f) {
   if (err) std::rethrow_exception(err);
 }
 
+// Host threads for map builds: CHROMSTRIP_THREADS if set (> 0), else the
+// hardware's count.  Results do not depend on it.
+int build_threads() {
+  const char* v = std::getenv("CHROMSTRIP_THREADS");
+  if (v) {
+    const int n = std::atoi(v);
+    if (n > 0) return n;
+  }
+  return static_cast<int>(std::max(1u, std::thread::hardware_concurrency()));
+}
+
 struct Triple {
   int32_t row, col;
   int32_t key;
 };
+
+// Runs f(i) for i = 0..n-1, one thread each (n small: one per buffer).
+template <class F>
+void each_thread(int n, F&& f) {
+  if (n <= 1) {
+    if (n == 1) f(0);
+    return;
+  }
+  std::vector<std::thread> pool;
+  std::exception_ptr err;
+  std::mutex err_mu;
+  for (int i = 0; i < n; ++i)
+    pool.emplace_back([&, i] {
+      try {
+        f(i);
+      } catch (...) {
+        std::lock_guard<std::mutex> lk(err_mu);
+        if (!err) err = std::current_exception();
+      }
+    });
+  for (auto& th : pool) th.join();
+  if (err) std::rethrow_exception(err);
+}
+
+// Exclusive prefix sum of counts into row pointers (n + 1 entries).
+void row_pointers(const std::vector<int32_t>& cnt, std::vector<int32_t>& row_ptr) {
+  const int64_t n = static_cast<int64_t>(cnt.size());
+  row_ptr.assign(n + 1, 0);
+  int64_t acc = 0;
+  for (int64_t r = 0; r < n; ++r) {
+    acc += cnt[r];
+    if (acc > INT32_MAX) throw std::runtime_error("too many map entries for 32-bit row pointers");
+    row_ptr[r + 1] = static_cast<int32_t>(acc);
+  }
+}
+
+// Sorts the entries of rows [lo, hi) by column, then by the parallel `keys`
+// value (rows hold a handful of entries: insertion sort), so that the CSR
+// does not depend on the order its entries were scattered in.
+void sort_rows(const std::vector<int32_t>& row_ptr, std::vector<uint32_t>& ent, int32_t* keys, int64_t lo,
+               int64_t hi) {
+  for (int64_t r = lo; r < hi; ++r) {
+    const int64_t a0 = row_ptr[r], a1 = row_ptr[r + 1];
+    for (int64_t a = a0 + 1; a < a1; ++a)
+      for (int64_t b = a; b > a0; --b) {
+        const uint32_t cp = ent[b - 1] & kSrcMask, cb = ent[b] & kSrcMask;
+        const bool swap = cp > cb || (cp == cb && (keys ? keys[b - 1] > keys[b] : ent[b - 1] > ent[b]));
+        if (!swap) break;
+        std::swap(ent[b - 1], ent[b]);
+        if (keys) std::swap(keys[b - 1], keys[b]);
+      }
+  }
+}
 
 // Builds one factor with coefficient keys in place of codes (resolved later).
 void build_factor(const FactorDef& d, bool gather_form, bool normalised, int threads, Csr& csr,
                   std::vector<int32_t>& keys, std::atomic<uint64_t>* seen) {
   const int64_t nin = d.in.size(), nout = d.out.size();
   if (nin > int64_t(kSrcMask) || nout > int64_t(kSrcMask))
-    throw std::runtime_error("state space too large for 28-bit ranks");
+    throw std::runtime_error("state space too large for 26-bit ranks");
   std::vector<std::vector<Triple>> buf(std::max(threads, 1));
   parallel_for(nin, threads, [&](int t, int64_t lo, int64_t hi) {
     Expander e(d.m, normalised);
@@ -304,63 +368,59 @@ void build_factor(const FactorDef& d, bool gather_form, bool normalised, int thr
   const int64_t nrows = gather_form ? nout : nin;
   csr.n_rows = nrows;
   csr.n_cols = gather_form ? nin : nout;
-  std::vector<int64_t> count(nrows + 1, 0);
+  // Parallel assembly: row counts by atomic increments, row pointers, then
+  // every buffer scatters its triples through atomic row cursors; the rows
+  // are sorted afterwards, so the result is the same for any schedule.
   int64_t nnz = 0;
-  for (auto& b : buf)
-    for (const Triple& x : b) ++count[x.row + 1], ++nnz;
+  for (auto& b : buf) nnz += static_cast<int64_t>(b.size());
   if (nnz > INT32_MAX) throw std::runtime_error("too many map entries for 32-bit row pointers");
-  csr.row_ptr.assign(nrows + 1, 0);
-  for (int64_t r = 0; r < nrows; ++r) count[r + 1] += count[r];
-  for (int64_t r = 0; r <= nrows; ++r) csr.row_ptr[r] = static_cast<int32_t>(count[r]);
+  const int nb = static_cast<int>(buf.size());
+  std::vector<int32_t> cnt(nrows, 0);
+  each_thread(nb, [&](int t) {
+    for (const Triple& x : buf[t]) __atomic_fetch_add(&cnt[x.row], 1, __ATOMIC_RELAXED);
+  });
+  row_pointers(cnt, csr.row_ptr);
   csr.ent.assign(nnz, 0);
   keys.assign(nnz, 0);
-  // Sources are visited in increasing order (thread ranges ascend), so each
-  // row's entries come out sorted by column in the gather form; the
-  // scatter form is sorted per row below.
-  std::vector<int64_t> cur(count.begin(), count.end() - 1);
-  for (auto& b : buf)
-    for (const Triple& x : b) {
-      int64_t at = cur[x.row]++;
+  std::vector<int32_t>& cur = cnt;  // reused as row cursors
+  for (int64_t r = 0; r < nrows; ++r) cur[r] = csr.row_ptr[r];
+  each_thread(nb, [&](int t) {
+    for (const Triple& x : buf[t]) {
+      const int32_t at = __atomic_fetch_add(&cur[x.row], 1, __ATOMIC_RELAXED);
       csr.ent[at] = static_cast<uint32_t>(x.col);
       keys[at] = x.key;
     }
-  if (!gather_form) {
-    for (int64_t r = 0; r < nrows; ++r) {
-      int64_t lo = csr.row_ptr[r], hi = csr.row_ptr[r + 1];
-      // tiny rows: insertion sort of (col, key) pairs
-      for (int64_t a = lo + 1; a < hi; ++a)
-        for (int64_t b = a; b > lo && csr.ent[b - 1] > csr.ent[b]; --b) {
-          std::swap(csr.ent[b - 1], csr.ent[b]);
-          std::swap(keys[b - 1], keys[b]);
-        }
-    }
-  }
+    std::vector<Triple>().swap(buf[t]);
+  });
+  parallel_for(nrows, threads,
+               [&](int, int64_t lo, int64_t hi) { sort_rows(csr.row_ptr, csr.ent, keys.data(), lo, hi); });
 }
 
 // Renumbers the rows of `c` by new_row[old] and its columns by new_col[old]
 // (either may be empty = identity); entries of a row end up sorted by column.
-void renumber(Csr& c, const std::vector<int32_t>& new_row, const std::vector<int32_t>& new_col) {
+void renumber(Csr& c, const std::vector<int32_t>& new_row, const std::vector<int32_t>& new_col, int threads) {
   const int64_t nr = c.n_rows;
   std::vector<int32_t> old_of(nr);
   for (int64_t r = 0; r < nr; ++r) old_of[new_row.empty() ? r : new_row[r]] = static_cast<int32_t>(r);
   Csr out;
   out.n_rows = c.n_rows;
   out.n_cols = c.n_cols;
-  out.row_ptr.assign(nr + 1, 0);
+  std::vector<int32_t> len(nr);
+  for (int64_t r = 0; r < nr; ++r) len[r] = c.row_ptr[old_of[r] + 1] - c.row_ptr[old_of[r]];
+  row_pointers(len, out.row_ptr);
   out.ent.resize(c.ent.size());
-  int64_t w = 0;
-  for (int64_t r = 0; r < nr; ++r) {
-    const int32_t o = old_of[r];
-    const int64_t lo = w;
-    for (int64_t e = c.row_ptr[o]; e < c.row_ptr[o + 1]; ++e) {
-      const uint32_t col = c.ent[e] & kSrcMask, code = c.ent[e] >> kSrcBits;
-      const uint32_t nc = new_col.empty() ? col : static_cast<uint32_t>(new_col[col]);
-      out.ent[w++] = nc | (code << kSrcBits);
+  parallel_for(nr, threads, [&](int, int64_t lo, int64_t hi) {
+    for (int64_t r = lo; r < hi; ++r) {
+      const int32_t o = old_of[r];
+      int64_t w = out.row_ptr[r];
+      for (int64_t e = c.row_ptr[o]; e < c.row_ptr[o + 1]; ++e) {
+        const uint32_t col = c.ent[e] & kSrcMask, code = c.ent[e] >> kSrcBits;
+        const uint32_t nc = new_col.empty() ? col : static_cast<uint32_t>(new_col[col]);
+        out.ent[w++] = nc | (code << kSrcBits);
+      }
     }
-    std::sort(out.ent.begin() + lo, out.ent.begin() + w,
-              [](uint32_t a, uint32_t b) { return (a & kSrcMask) < (b & kSrcMask); });
-    out.row_ptr[r + 1] = static_cast<int32_t>(w);
-  }
+    sort_rows(out.row_ptr, out.ent, nullptr, lo, hi);
+  });
   c = std::move(out);
 }
 
@@ -374,28 +434,34 @@ void renumber(Csr& c, const std::vector<int32_t>& new_row, const std::vector<int
 // and re-reads of a source follow its first read closely, so they are served
 // by the L2.  The numbering is internal to the maps: every factor is
 // renumbered consistently.
-void reader_order(std::vector<Csr>& facs) {
+void reader_order(std::vector<Csr>& facs, int threads) {
   const int n = static_cast<int>(facs.size());
   if (n < 2) return;
   std::vector<std::vector<int32_t>> perm(n + 1);  // perm[k][old] = new, space after F_k
   for (int k = n - 1; k >= 1; --k) {
     const Csr& t = facs[k];  // F_{k+1}: rows in space k+1, columns in space k
-    const int64_t ns = t.n_cols;
-    std::vector<int64_t> first(ns, INT64_MAX);
-    for (int64_t r = 0; r < t.n_rows; ++r) {
-      const int64_t nr = perm[k + 1].empty() ? r : perm[k + 1][r];
-      for (int64_t e = t.row_ptr[r]; e < t.row_ptr[r + 1]; ++e) {
-        const uint32_t col = t.ent[e] & kSrcMask;
-        first[col] = std::min(first[col], nr);
+    const int64_t ns = t.n_cols, nrows = t.n_rows;
+    // first[s]: the lowest (new) row of F_{k+1} reading s; nrows if none
+    std::vector<int32_t> first(ns, static_cast<int32_t>(nrows));
+    parallel_for(nrows, threads, [&](int, int64_t lo, int64_t hi) {
+      for (int64_t r = lo; r < hi; ++r) {
+        const int32_t nr = perm[k + 1].empty() ? static_cast<int32_t>(r) : perm[k + 1][r];
+        for (int64_t e = t.row_ptr[r]; e < t.row_ptr[r + 1]; ++e) {
+          int32_t* f = &first[t.ent[e] & kSrcMask];
+          int32_t seen = __atomic_load_n(f, __ATOMIC_RELAXED);
+          while (nr < seen && !__atomic_compare_exchange_n(f, &seen, nr, true, __ATOMIC_RELAXED, __ATOMIC_RELAXED)) {
+          }
+        }
       }
-    }
-    std::vector<int32_t> order(ns);
-    for (int64_t s = 0; s < ns; ++s) order[s] = static_cast<int32_t>(s);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return first[a] < first[b]; });
+    });
+    // stable counting sort of the states by first reader (ties by old rank)
+    std::vector<int32_t> start(nrows + 2, 0);
+    for (int64_t s = 0; s < ns; ++s) ++start[first[s] + 1];
+    for (int64_t b = 0; b <= nrows; ++b) start[b + 1] += start[b];
     perm[k].assign(ns, 0);
-    for (int64_t pos = 0; pos < ns; ++pos) perm[k][order[pos]] = static_cast<int32_t>(pos);
+    for (int64_t s = 0; s < ns; ++s) perm[k][s] = start[first[s]]++;
   }
-  for (int k = 0; k < n; ++k) renumber(facs[k], perm[k + 1], perm[k]);
+  for (int k = 0; k < n; ++k) renumber(facs[k], perm[k + 1], perm[k], threads);
 }
 
 // Adds two polynomials / multiplies them (degrees stay <= kMaxDeg).
@@ -485,7 +551,7 @@ PolyCsr compose(const PolyCsr& t, const PolyCsr& p, int threads) {
 
 std::unique_ptr<Family> build_family(const MapSet& ms, int k) {
   const int m = ms.m;
-  const int threads = std::max(1u, std::thread::hardware_concurrency());
+  const int threads = build_threads();
   auto fam = std::make_unique<Family>();
   fam->k = k;
   fam->codes = ms.codes;
@@ -523,7 +589,7 @@ std::unique_ptr<Family> build_family(const MapSet& ms, int k) {
     fam->fac.push_back(std::move(c));
   }
   const char* order = std::getenv("CHROMSTRIP_STATE_ORDER");
-  if (!(order && std::string(order) == "paper")) reader_order(fam->fac);
+  if (!(order && std::string(order) == "paper")) reader_order(fam->fac, threads);
   return fam;
 }
 
@@ -582,7 +648,7 @@ struct BuildLog {
 std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads, bool normalised) {
   if (lattice != kSquare && lattice != kTriangular) throw std::runtime_error("bad lattice");
   if (m < 1 || m > kMaxM) throw std::runtime_error("m out of range");
-  if (threads <= 0) threads = std::max(1u, std::thread::hardware_concurrency());
+  if (threads <= 0) threads = build_threads();
   auto ms = std::make_unique<MapSet>();
   ms->lattice = lattice;
   ms->m = m;
@@ -619,8 +685,9 @@ std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads, bool normali
   for (int k = 0; k < kKeys; ++k)
     if ((seen[k / 64].load() >> (k % 64)) & 1ull) add(k);
   auto finish = [&](Csr& c, const std::vector<int32_t>& keys) {
-    for (size_t e = 0; e < c.ent.size(); ++e)
-      c.ent[e] |= static_cast<uint32_t>(key_to_code[keys[e]]) << kSrcBits;
+    parallel_for(static_cast<int64_t>(c.ent.size()), threads, [&](int, int64_t lo, int64_t hi) {
+      for (int64_t e = lo; e < hi; ++e) c.ent[e] |= static_cast<uint32_t>(key_to_code[keys[e]]) << kSrcBits;
+    });
   };
   for (int i = 0; i < m; ++i) {
     finish(ms->fwd[i], fkeys[i]);
@@ -630,7 +697,7 @@ std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads, bool normali
       finish(ms->last[i], lkeys[i]);
   }
   const char* order = std::getenv("CHROMSTRIP_STATE_ORDER");
-  if (!(order && std::string(order) == "paper")) reader_order(ms->fwd);
+  if (!(order && std::string(order) == "paper")) reader_order(ms->fwd, threads);
   log.line(lattice, m, normalised, "reader order, sites", m);
   return ms;
 }
