@@ -171,7 +171,11 @@ def bench_series(torch, stream, tune, steps):
     lat, m, n = w["strips"][0]
     primes = w["primes"]
     d = 79
-    t = {k: v for k, v in tune.items() if k not in ("fuse", "stage")}
+    from paper_1005_3609_amd import tune as tuner
+    t = tuner.lookup_tuned_series(lat, m, len(primes), d, n)
+    if t is None:
+        t = {k: v for k, v in tune.items() if k not in ("fuse", "stage")}
+    t = {k: v for k, v in t.items() if k not in ("mode", "ms")}
     t["lanes_v"] = 2
     dev = torch.device("cuda", torch.cuda.current_device())
     out, ws = api.series_async(lat, m, n, d, primes, mode="graph", tuning=t, stream=stream, device=dev)

@@ -257,20 +257,26 @@ __device__ __forceinline__ void add_multiple(uint32_t (&A)[V], const uint32_t (&
 // finished by Horner's rule in t (at most three Shoup products).
 //
 // The wavefront keeps two copies of the code table, one word per lane:
-// `pm` (lane c: code c's unit coefficients as masks -- bit k for d_k = +1,
+// `pm` (lane c: code c's small coefficients as masks -- bit k for d_k = +1,
 // bit 4+k for d_k = -1 -- bit 8 when some |d_k| > 1, degree in bits 12-13)
 // and `pw` (lane c: d_0..d_3 as signed bytes, for the rare codes with bit 8).
 // Every branch below updates one A_k in place, so the common paths compile
 // to the modular additions alone.  Launches whose codes all have unit
 // coefficients use the G = false instance, which has no general path at all
 // (its merges would cost register copies on every entry).
+//
+// The coefficient-form instances (CF) also take |d_k| = 2, 3 on the fast
+// path: such a d_k is written as +-2 (bit 16+k for +2, 20+k for -2) plus
+// the +-1 bits, and only |d_k| > 3 (bit 9) needs the general path.  The
+// normalised single factors never have one, so their launches run G = false.
 constexpr uint32_t kMaskGeneral = 0x100u;
+constexpr uint32_t kMaskGeneralCF = 0x200u;
 
-template <int V, bool G>
+template <int V, bool G, bool CF = false>
 __device__ __forceinline__ void accumulate(uint32_t (&A)[4][V], const uint32_t (&x)[V], uint32_t code,
                                            const uint32_t (&p)[V], int pw, int pm, int& deg) {
   const uint32_t m = static_cast<uint32_t>(__builtin_amdgcn_readlane(pm, static_cast<int>(code)));
-  if (G && (m & kMaskGeneral)) {
+  if (G && (m & (CF ? kMaskGeneralCF : kMaskGeneral))) {
     const int cw = __builtin_amdgcn_readlane(pw, static_cast<int>(code));
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -294,6 +300,18 @@ __device__ __forceinline__ void accumulate(uint32_t (&A)[4][V], const uint32_t (
         asm volatile("");
 #pragma unroll
         for (int j = 0; j < V; ++j) A[k][j] = sub_mod(A[k][j], x[j], p[j]);
+      }
+      if constexpr (CF) {
+        if (m & (0x10000u << k)) {
+          asm volatile("");
+#pragma unroll
+          for (int j = 0; j < V; ++j) A[k][j] = add_mod(A[k][j], add_mod(x[j], x[j], p[j]), p[j]);
+        }
+        if (m & (0x100000u << k)) {
+          asm volatile("");
+#pragma unroll
+          for (int j = 0; j < V; ++j) A[k][j] = sub_mod(A[k][j], add_mod(x[j], x[j], p[j]), p[j]);
+        }
       }
     }
   }
@@ -456,7 +474,7 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
       for (int u = 0; u < U; ++u) {
         if (e0 + u < end) {
           while (e0 + u >= row_end) flush();
-          accumulate<V, G>(A, x[u], w[u] >> kEntSrcBits, p, pw, pm, deg);
+          accumulate<V, G, CF>(A, x[u], w[u] >> kEntSrcBits, p, pw, pm, deg);
         }
       }
     };

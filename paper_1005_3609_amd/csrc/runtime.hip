@@ -94,7 +94,7 @@ struct DevFamily {
   std::vector<DevCsr> fac;
   std::vector<Poly> codes;   // extends the base table
   int shift = 0;             // kernels expand the codes in powers of t = q - shift
-  bool general = false;      // some coefficient its factors use has magnitude above 1
+  bool general = false;      // some coefficient its factors use exceeds the fast path (|d| > 1; > 3 in the coefficient form)
   // staged copies, one set per (slot limit, rows per tile), built on first use
   mutable std::mutex st_mu;
   mutable std::map<std::pair<int, int>, std::unique_ptr<DevStagedSet>> staged;
@@ -259,9 +259,10 @@ const DevFamily& dev_family(const DevMaps& dm, int k) {
       for (uint32_t e : c.ent) used[e >> kSrcBits] = true;
     for (const Csr& c : ms.last_fwd)
       for (uint32_t e : c.ent) used[e >> kSrcBits] = true;
+    // the coefficient-form kernels take |d| <= 3 on their fast path
     for (size_t c = 0; c < dm.codes.size(); ++c)
       for (int d = 0; d <= kMaxDeg && used[c]; ++d)
-        df->general = df->general || dm.codes[c].c[d] > 1 || dm.codes[c].c[d] < -1;
+        df->general = df->general || dm.codes[c].c[d] > 3 || dm.codes[c].c[d] < -3;
   } else if (k == 1) {
     df->fac.assign(dm.fwd, dm.fwd + dm.m);
     df->codes = dm.codes;
@@ -566,16 +567,27 @@ uint32_t pack_poly(const Poly& c) {
   return w;
 }
 
-// Mask word of a code (kernel side: accumulate): bit k for d_k = +1, bit
-// 4 + k for d_k = -1, bit 8 when some |d_k| > 1, the degree in bits 12-13.
+// Mask word of a code (kernel side: accumulate): bit 8 when some |d_k| > 1,
+// bit 9 when some |d_k| > 3, the degree in bits 12-13; every d_k with
+// |d_k| <= 3 as +-2 (bit 16+k for +2, 20+k for -2) plus +-1 (bit k for +1,
+// 4+k for -1).  The evaluation-form kernels read the +-1 bits only when bit
+// 8 is clear (all |d_k| <= 1), the coefficient-form kernels all of them
+// unless bit 9 is set.
 uint32_t pack_mask(const Poly& d) {
   uint32_t m = 0;
   int deg = 0;
   for (int k = 0; k <= kMaxDeg; ++k) {
-    if (d.c[k] == 1) m |= 1u << k;
-    else if (d.c[k] == -1) m |= 16u << k;
-    else if (d.c[k] != 0) m |= 0x100u;
-    if (d.c[k] != 0) deg = k;
+    const int64_t c = d.c[k];
+    if (c == 0) continue;
+    deg = k;
+    const int64_t a = c < 0 ? -c : c;
+    if (a > 1) m |= 0x100u;
+    if (a > 3) {
+      m |= 0x200u;
+    } else {
+      if (a & 1) m |= (c > 0 ? 1u : 16u) << k;
+      if (a & 2) m |= (c > 0 ? 0x10000u : 0x100000u) << k;
+    }
   }
   return m | (static_cast<uint32_t>(deg) << 12);
 }

@@ -25,6 +25,7 @@ x^{k-1}; its bulk series is (1-x)^2 prod P~^alpha = -x exp(f_b).
 from __future__ import annotations
 
 from . import api, host
+from . import tune as tuner
 
 SQUARE = "square"
 TRIANGULAR = "triangular"
@@ -205,7 +206,7 @@ def _strips(lattice, k: int, N: int, primes, mode, tuning, lanes_v, workspace_li
     dict {(r, s): coefficients} per prime."""
     if lanes_v is None:
         lanes_v = 1 if N < 64 else (2 if N < 128 else 4)
-    t = dict(tuning or {})
+    t = dict(tuning) if tuning else dict(tuner.SERIES_DEFAULT)
     t["lanes_v"] = lanes_v
     per_prime = [dict() for _ in primes]
     for r in range(1, k // 2 + 1):

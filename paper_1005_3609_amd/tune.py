@@ -7,6 +7,11 @@ stream.  Every candidate must return residues bit-identical to the first
 one; a candidate that differs is rejected and reported (the arithmetic is
 exact, so a difference is a bug, never rounding).  Results are cached as
 JSON keyed by (gfx arch, lattice, m, instances, n_max).
+
+The coefficient form (normalised P~ as truncated polynomials, one chunk per
+prime) is tuned the same way over its own space (single factors, no
+staging, graph row replay), keyed by (gfx arch, "series", lattice, m,
+primes x coefficients, n_max).
 """
 from __future__ import annotations
 
@@ -124,8 +129,80 @@ def tune(lattice, m, n_max, q_points, primes, space=None, steps=3, path=DEFAULT_
     return dict(best=best, table=table)
 
 
+# Coefficient-form launch shape used where no tuned entry exists: the best of
+# SERIES_SPACE for square m = 14, 8 primes x 80 coefficients on the MI355X
+# (wider wavefront tiles than the evaluation form's).
+SERIES_DEFAULT = dict(targets_per_wave=16, waves_per_block=4, xcd_order=1, unroll=4, streams=3)
+
+SERIES_SPACE = dict(targets_per_wave=[4, 8, 16], waves_per_block=[4, 8], xcd_order=[1], unroll=[4, 8],
+                    streams=[1, 3])
+
+
+def _series_key(lattice, m, n_primes, d_max, n_max):
+    return f"{_arch()}|series|{lattice}|{m}|{n_primes}x{d_max + 1}|{n_max}"
+
+
+def series_lanes_v(d_max: int) -> int:
+    """Smallest chunk width (64 lanes_v coefficients) that holds x^0..x^d_max."""
+    return 1 if d_max < 64 else (2 if d_max < 128 else 4)
+
+
+def lookup_tuned_series(lattice, m, n_primes, d_max, n_max):
+    """Best known coefficient-form launch shape (user cache, then the shipped
+    table), or None."""
+    for path in (DEFAULT_CACHE, PACKAGE_TABLE):
+        hit = load(path).get(_series_key(lattice, m, n_primes, d_max, n_max))
+        if hit:
+            return dict(hit["best"])
+    return None
+
+
+def tune_series(lattice, m, n_max, d_max, primes, space=None, steps=3, path=DEFAULT_CACHE, log=None) -> dict:
+    """Times coefficient-form strips over the launch-shape space; every
+    candidate's coefficients must equal the first one's."""
+    import torch
+    space = space or SERIES_SPACE
+    dev = torch.device("cuda", torch.cuda.current_device())
+    stream = torch.cuda.current_stream(dev)
+    table, ref, best = [], None, None
+    for t, w, x, u, s in itertools.product(space["targets_per_wave"], space["waves_per_block"],
+                                           space["xcd_order"], space["unroll"], space["streams"]):
+        cand = dict(lanes_v=series_lanes_v(d_max), targets_per_wave=t, waves_per_block=w, xcd_order=x, unroll=u,
+                    streams=s)
+        out, ws = api.series_async(lattice, m, n_max, d_max, primes, mode="graph", tuning=cand, stream=stream,
+                                   device=dev)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            api.series_async(lattice, m, n_max, d_max, primes, mode="graph", tuning=cand, workspace=ws, out=out,
+                             stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res = api.to_u32(out)
+        if ref is None:
+            ref = res
+        ok = bool(np.array_equal(res, ref))
+        table.append(dict(cand, ms=ms, identical=ok))
+        if log:
+            log(f"{cand} {ms:.3f} ms {'ok' if ok else 'MISMATCH'}")
+        if ok and (best is None or ms < best["ms"]):
+            best = dict(cand, mode="graph", ms=ms)
+        del out, ws
+    bad = [t for t in table if not t["identical"]]
+    if bad:
+        raise RuntimeError(f"tuning candidates disagree with the reference result: {bad}")
+    cache = load(path)
+    cache[_series_key(lattice, m, len(primes), d_max, n_max)] = dict(best=best, table=table)
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1)
+    return dict(best=best, table=table)
+
+
 def main():
-    """python -m paper_1005_3609_amd.tune --workload square_14x15 [--cache PATH]"""
+    """python -m paper_1005_3609_amd.tune --workload square_14x15 [--cache PATH] [--series D]"""
     import argparse
     import sys
 
@@ -135,8 +212,17 @@ def main():
     ap.add_argument("--cache", default=DEFAULT_CACHE)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--quick", action="store_true", help="a reduced search space")
+    ap.add_argument("--series", type=int, default=None, metavar="D",
+                    help="tune the coefficient form to x^D for the workload's strips and primes instead")
     args = ap.parse_args()
     w = W.workload(args.workload)
+    if args.series is not None:
+        for lat, m, n in w["strips"]:
+            res = tune_series(lat, m, n, args.series, w["primes"], steps=args.steps, path=args.cache,
+                              log=lambda s: print(s, file=sys.stderr, flush=True))
+            print(json.dumps(dict(workload=args.workload, series_d_max=args.series, lattice=lat, m=m, n_max=n,
+                                  best=res["best"])), flush=True)
+        return
     space = None
     if args.quick:
         space = dict(lanes_v=[2], targets_per_wave=[4, 8], waves_per_block=[4, 8], xcd_order=[1],
