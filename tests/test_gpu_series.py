@@ -88,6 +88,24 @@ def test_series_full_width_matches_evaluation_form(lat, m):
             np.testing.assert_array_equal(ser[r, b].astype(np.int64), want, err_msg=f"{lat} m={m} r={r} p={p}")
 
 
+def test_series_edge_cases():
+    # d_max = 0: only the constant term, 1 for every rectangle
+    got = api.series(SQ, 5, 4, 0, [P31, 3], mode="graph")
+    assert got.shape == (4, 2, 1) and (got == 1).all()
+    # n_max = 0: nothing to compute
+    assert api.series(TRI, 4, 0, 10, [P31]).shape == (0, 1, 11)
+    # the largest truncation of each chunk width, extreme primes (3, 5 and
+    # 2^31 - 19), one row, one prime
+    for d, lanes_v in ((63, 1), (127, 2), (255, 4)):
+        primes = [3, 5, 2147483629]
+        want = _oracle(TRI, 3, 6, d, primes)
+        for mode in ("batched", "graph"):
+            got = api.series(TRI, 3, 6, d, primes, mode=mode, tuning=dict(lanes_v=lanes_v)).astype(np.int64)
+            np.testing.assert_array_equal(got, want, err_msg=f"d={d} {mode}")
+    want = _oracle(SQ, 6, 1, 40, [2147483629])
+    np.testing.assert_array_equal(api.series(SQ, 6, 1, 40, [2147483629]).astype(np.int64), want)
+
+
 def test_series_bad_arguments():
     with pytest.raises(api.ChromError):
         api.series(SQ, 4, 3, 64, [P31], tuning=dict(lanes_v=1))          # d_max >= 64 lanes_v
