@@ -173,7 +173,16 @@ int chromatic_factor_launches(int lattice, int m,
  * (lattice, m) ahead of time, so that later calls do no host work. */
 int chromatic_prepare(int lattice, int m);
 
-/* Frees every cached map on host and devices. */
+/* Builds the host copy of the factor maps of (lattice, m) only, in the
+ * evaluation form (normalised = 0) or the coefficient form (normalised = 1,
+ * eq. Z_modified); touches no device.  Builds of different map sets run
+ * concurrently, so a second host thread may prepare the next width while
+ * device work for another is queued; a call for a set already being built
+ * waits for it.  Returns 0 or CHROM_EINVAL. */
+int chromatic_prepare_host(int lattice, int m, int normalised);
+
+/* Frees every cached map on host and devices.  Must not run concurrently
+ * with any other call of the library. */
 void chromatic_release_maps(void);
 
 /* ------------------------------------------------------------------------

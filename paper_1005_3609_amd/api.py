@@ -108,6 +108,13 @@ def prepare(lattice, m: int) -> None:
     check(lib().chromatic_prepare(lattice_id(lattice), m))
 
 
+def prepare_host(lattice, m: int, normalised: bool = False) -> None:
+    """Host maps of (lattice, m) only (no device); safe to call from a second
+    thread while device work for other widths runs (the GIL is released
+    during the call)."""
+    check(lib().chromatic_prepare_host(lattice_id(lattice), m, 1 if normalised else 0))
+
+
 def release_maps() -> None:
     lib().chromatic_release_maps()
 

@@ -756,19 +756,29 @@ StagedCsr build_staged(const Csr& c, int slots, int rows) {
 }
 
 namespace {
+// One slot per (lattice, m, normalised), each with its own lock: a build
+// holds only its slot, so different map sets build concurrently (a caller
+// can prepare the next width while the device runs the current one) and a
+// second request for a set under construction waits for it.
+struct CacheSlot {
+  std::mutex mu;
+  std::unique_ptr<MapSet> ms;
+};
 std::mutex g_cache_mu;
-std::map<std::tuple<int, int, bool>, std::unique_ptr<MapSet>> g_cache;
+std::map<std::tuple<int, int, bool>, std::shared_ptr<CacheSlot>> g_cache;
 }  // namespace
 
 const MapSet& get_maps(int lattice, int m, bool normalised) {
-  std::lock_guard<std::mutex> lk(g_cache_mu);
-  auto key = std::make_tuple(lattice, m, normalised);
-  auto it = g_cache.find(key);
-  if (it != g_cache.end()) return *it->second;
-  auto ms = build_maps(lattice, m, 0, normalised);
-  const MapSet& ref = *ms;
-  g_cache.emplace(key, std::move(ms));
-  return ref;
+  std::shared_ptr<CacheSlot> slot;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto& s = g_cache[std::make_tuple(lattice, m, normalised)];
+    if (!s) s = std::make_shared<CacheSlot>();
+    slot = s;
+  }
+  std::lock_guard<std::mutex> lk(slot->mu);
+  if (!slot->ms) slot->ms = build_maps(lattice, m, 0, normalised);  // a failed build leaves the slot empty
+  return *slot->ms;
 }
 
 void release_host_maps() {

@@ -105,7 +105,9 @@ StagedCsr build_staged(const Csr& c, int slots, int rows);
 // hardware count.  Throws std::runtime_error on failure.
 std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads = 0, bool normalised = false);
 
-// Host-side map cache (thread safe): built on first request.
+// Host-side map cache (thread safe): built on first request; different
+// map sets may build concurrently.  release_host_maps invalidates every
+// reference handed out and must not run concurrently with other calls.
 const MapSet& get_maps(int lattice, int m, bool normalised = false);
 void release_host_maps();
 

@@ -1798,6 +1798,15 @@ int chromatic_prepare(int lattice, int m) {
   });
 }
 
+int chromatic_prepare_host(int lattice, int m, int normalised) {
+  return guarded([&] {
+    check_args(lattice, m, 0);
+    if (normalised != 0 && normalised != 1) throw ArgError("normalised must be 0 or 1");
+    (void)get_maps(lattice, m, normalised == 1);
+    return CHROM_OK;
+  });
+}
+
 void chromatic_release_maps(void) {
   (void)guarded([&] {
     {

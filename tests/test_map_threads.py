@@ -35,3 +35,39 @@ def _digest(threads):
 
 def test_maps_identical_for_any_thread_count():
     assert _digest(1) == _digest(3) == _digest(8)
+
+
+CONCURRENT = r"""
+import hashlib, threading
+from paper_1005_3609_amd import api
+jobs = [("square", 12, True), ("square", 11, True), ("square", 12, True), ("triangular", 11, True),
+        ("square", 12, False), ("triangular", 11, False)]
+ths = [threading.Thread(target=api.prepare_host, args=j[:2], kwargs=dict(normalised=j[2])) for j in jobs]
+for t in ths:
+    t.start()
+for t in ths:
+    t.join()
+h = hashlib.sha256()
+for lat, m, norm in sorted(set(jobs)):
+    for which in ((4, 5) if norm else (0, 1)):
+        for i in range(m):
+            rp, cols, codes, nc = api.map_export(lat, m, which, i)
+            for a in (rp, cols, codes):
+                h.update(a.tobytes())
+print(h.hexdigest())
+"""
+
+SERIAL = CONCURRENT.replace("for t in ths:\n    t.start()\nfor t in ths:\n    t.join()\n", "")
+
+
+def test_concurrent_host_builds_match_serial_ones():
+    # map sets built at the same time from several threads (two of them the
+    # same set) equal the ones built on demand one at a time
+    env = dict(os.environ, PYTHONPATH=ROOT)
+    outs = []
+    for script in (CONCURRENT, SERIAL):
+        r = subprocess.run([sys.executable, "-c", script], env=env, capture_output=True, text=True, timeout=600)
+        assert r.returncode == 0, r.stderr
+        outs.append(r.stdout.strip())
+    assert outs[0] == outs[1]
+    assert SERIAL != CONCURRENT
