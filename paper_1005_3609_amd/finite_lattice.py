@@ -209,21 +209,7 @@ def _strips(lattice, k: int, N: int, primes, mode, tuning, lanes_v, workspace_li
     t = dict(tuning) if tuning else dict(tuner.SERIES_DEFAULT)
     t["lanes_v"] = lanes_v
     per_prime = [dict() for _ in primes]
-    # The host maps of the widths are built ahead on a second thread, in the
-    # order the strips need them, while the device runs the earlier widths.
-    import threading
-    widths = list(range(1, k // 2 + 1))
-    errors = []
-
-    def build_ahead():
-        try:
-            for r in widths:
-                api.prepare_host(lattice, r, normalised=True)
-        except Exception as e:          # the strip that needs the width reports it again
-            errors.append(e)
-    ahead = threading.Thread(target=build_ahead, daemon=True)
-    ahead.start()
-    for r in widths:
+    for r in range(1, k // 2 + 1):
         n = k - r
         b0 = 0
         for group in prime_groups(r, n, N, primes, mode, t, workspace_limit, lattice):
@@ -234,7 +220,6 @@ def _strips(lattice, k: int, N: int, primes, mode, tuning, lanes_v, workspace_li
             b0 += len(group)
             if log is not None:
                 log(f"width {r}: rows 1..{n}, {len(group)} prime(s) done")
-    ahead.join()
     return per_prime
 
 
