@@ -181,6 +181,15 @@ int chromatic_prepare(int lattice, int m);
  * waits for it.  Returns 0 or CHROM_EINVAL. */
 int chromatic_prepare_host(int lattice, int m, int normalised);
 
+/* Host-side check of the per-state expansion that builds the coefficient
+ * form's maps on the device (Sec. 3.1-3.4): the same expansion and CSR
+ * assembly run on the host and are compared, factor by factor, with the
+ * host builder's maps of (lattice, m) in the paper's state order (every
+ * forward factor; with normalised = 1 also every read-out factor).  Touches
+ * no device.  Returns 0 when identical, CHROM_EUNSUPPORTED with the first
+ * difference as the error message otherwise. */
+int chromatic_check_expansion(int lattice, int m, int normalised);
+
 /* Frees every cached map on host and devices.  Must not run concurrently
  * with any other call of the library. */
 void chromatic_release_maps(void);

@@ -115,6 +115,12 @@ def prepare_host(lattice, m: int, normalised: bool = False) -> None:
     check(lib().chromatic_prepare_host(lattice_id(lattice), m, 1 if normalised else 0))
 
 
+def check_expansion(lattice, m: int, normalised: bool = True) -> None:
+    """Raises ChromError unless the device map builder's expansion, run on the
+    host, reproduces the host builder's maps of (lattice, m) (paper order)."""
+    check(lib().chromatic_check_expansion(lattice_id(lattice), m, 1 if normalised else 0))
+
+
 def release_maps() -> None:
     lib().chromatic_release_maps()
 

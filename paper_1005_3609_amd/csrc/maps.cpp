@@ -645,7 +645,7 @@ struct BuildLog {
   }
 };
 
-std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads, bool normalised) {
+std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads, bool normalised, bool paper_order) {
   if (lattice != kSquare && lattice != kTriangular) throw std::runtime_error("bad lattice");
   if (m < 1 || m > kMaxM) throw std::runtime_error("m out of range");
   if (threads <= 0) threads = build_threads();
@@ -697,7 +697,7 @@ std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads, bool normali
       finish(ms->last[i], lkeys[i]);
   }
   const char* order = std::getenv("CHROMSTRIP_STATE_ORDER");
-  if (!(order && std::string(order) == "paper")) reader_order(ms->fwd, threads);
+  if (!paper_order && !(order && std::string(order) == "paper")) reader_order(ms->fwd, threads);
   log.line(lattice, m, normalised, "reader order, sites", m);
   return ms;
 }

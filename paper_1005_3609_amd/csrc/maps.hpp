@@ -102,8 +102,11 @@ struct StagedCsr {
 StagedCsr build_staged(const Csr& c, int slots, int rows);
 
 // Builds every single-factor map of (lattice, m); threads = 0 uses the
-// hardware count.  Throws std::runtime_error on failure.
-std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads = 0, bool normalised = false);
+// hardware count; paper_order keeps the paper's state order between the
+// forward factors (no reader-order relabelling).  Throws std::runtime_error
+// on failure.
+std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads = 0, bool normalised = false,
+                                   bool paper_order = false);
 
 // Host-side map cache (thread safe): built on first request; different
 // map sets may build concurrently.  release_host_maps invalidates every

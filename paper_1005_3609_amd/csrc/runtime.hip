@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../include/chromstrip.h"
+#include "devexpand.hpp"
 #include "kernels.hpp"
 #include "maps.hpp"
 #include "states.hpp"
@@ -112,6 +113,11 @@ struct DevMaps {
   int64_t s_nc = 0;    // NCNNN states
   int64_t s_max = 0;   // largest space
   int lattice = 0, m = 0;
+  // built on the device (coefficient form): the per-factor allocations, and
+  // whether some coefficient needs the general kernel path (|d| > 3)
+  bool on_device = false;
+  bool general_cf = false;
+  std::vector<void*> allocs;
   // fused families (k >= 2), uploaded on first use
   mutable std::mutex fam_mu;
   mutable std::map<int, std::unique_ptr<DevFamily>> fam;
@@ -133,8 +139,336 @@ void upload_csr(const Csr& c, DevCsr& d, char*& cur) {
   d.n_cols = static_cast<int>(c.n_cols);
 }
 
+
+// ---------------------------------------------------------------------------
+// Coefficient-form maps built on the device.  Every source state of a
+// factor is expanded by one thread (devexpand.hpp: unrank, the factor's
+// single-edge operators, rank of each target); the gather-form CSR then
+// follows from atomic row counts, a prefix sum, atomic row cursors and a
+// per-row sort, so it does not depend on the schedule.  Two passes: the
+// first only collects the coefficient keys of every factor (they fix the
+// code table, numbered as the host builder numbers it), the second writes
+// each factor's CSR with final codes.  States keep the paper's order.
+// ---------------------------------------------------------------------------
+constexpr int kKeyWords = (dx::kKeys + 31) / 32;
+
+__global__ void __launch_bounds__(256, 8) k_dx_keys(dx::Factor f, const dx::Tables* tab, int64_t nin, uint32_t* keybits,
+                                                 int* err) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= nin) return;
+  int32_t tg[dx::kTerms], ky[dx::kTerms];
+  const int n = dx::expand_source(*tab, f, r, tg, ky);
+  if (n < 0) {
+    atomicOr(err, 1);
+    return;
+  }
+  for (int j = 0; j < n; ++j) atomicOr(&keybits[ky[j] >> 5], 1u << (ky[j] & 31));
+}
+
+// Per source: up to kTerms (target, code) pairs, target -1 for unused slots.
+__global__ void __launch_bounds__(256, 8) k_dx_expand(dx::Factor f, const dx::Tables* tab, int64_t nin,
+                                                   const int8_t* code_of_key, int32_t* tgt, uint8_t* code,
+                                                   int32_t* cnt, int* err) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= nin) return;
+  int32_t tg[dx::kTerms], ky[dx::kTerms];
+  int n = dx::expand_source(*tab, f, r, tg, ky);
+  if (n < 0) {
+    atomicOr(err, 1);
+    n = 0;
+  }
+  for (int j = 0; j < dx::kTerms; ++j) {
+    const int c = j < n ? code_of_key[ky[j]] : 0;
+    if (j < n && c < 0) atomicOr(err, 2);
+    const bool use = j < n && c >= 0;
+    tgt[r * dx::kTerms + j] = use ? tg[j] : -1;
+    code[r * dx::kTerms + j] = static_cast<uint8_t>(use ? c : 0);
+    if (use) atomicAdd(&cnt[tg[j]], 1);
+  }
+}
+
+// Exclusive prefix sum, first level: blocks of 1024 counts scanned in LDS;
+// block totals to sums[block].
+__global__ void __launch_bounds__(1024) k_dx_scan_blocks(const int32_t* cnt, int64_t n, int32_t* out, int32_t* sums) {
+  __shared__ int32_t s[1024];
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 1024 + threadIdx.x;
+  const int32_t v = i < n ? cnt[i] : 0;
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int32_t add = threadIdx.x >= static_cast<unsigned>(off) ? s[threadIdx.x - off] : 0;
+    __syncthreads();
+    s[threadIdx.x] += add;
+    __syncthreads();
+  }
+  if (i < n) out[i] = s[threadIdx.x] - v;
+  if (threadIdx.x == 1023) sums[blockIdx.x] = s[1023];
+}
+
+__global__ void __launch_bounds__(1024) k_dx_scan_add(int32_t* out, int64_t n, const int32_t* offs) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 1024 + threadIdx.x;
+  if (i < n) out[i] += offs[blockIdx.x];
+}
+
+__global__ void __launch_bounds__(256) k_dx_fill(const int32_t* tgt, const uint8_t* code, int64_t nslots,
+                                                 const int32_t* row_ptr, int32_t* cur, uint32_t* ent) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= nslots) return;
+  const int32_t t = tgt[e];
+  if (t < 0) return;
+  const int32_t pos = row_ptr[t] + atomicAdd(&cur[t], 1);
+  ent[pos] = static_cast<uint32_t>(e / dx::kTerms) | (static_cast<uint32_t>(code[e]) << kSrcBits);
+}
+
+// Each row's entries by source, then code (insertion sort: rows are short).
+__global__ void __launch_bounds__(256) k_dx_sort_rows(const int32_t* row_ptr, int64_t nrows, uint32_t* ent) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  const int32_t a0 = row_ptr[r], a1 = row_ptr[r + 1];
+  for (int32_t a = a0 + 1; a < a1; ++a) {
+    const uint32_t v = ent[a];
+    int32_t b = a;
+    while (b > a0) {
+      const uint32_t u = ent[b - 1];
+      const bool after = (u & kSrcMask) > (v & kSrcMask) || ((u & kSrcMask) == (v & kSrcMask) && u > v);
+      if (!after) break;
+      ent[b] = u;
+      --b;
+    }
+    ent[b] = v;
+  }
+}
+
+// Codes in the host builder's numbering: +1, -1, then every other key seen,
+// ascending.  code_of_key: kKeys entries, -1 for keys not seen.
+std::vector<Poly> codes_from_keys(const std::vector<uint32_t>& keybits, std::vector<int8_t>& code_of_key) {
+  auto poly_of = [](int key) {
+    Poly p;
+    for (int k = 0; k <= kMaxDeg; ++k) {
+      p.c[k] = key % dx::kKeyBase - dx::kKeyOff;
+      key /= dx::kKeyBase;
+    }
+    return p;
+  };
+  auto key_of = [](int c0) {
+    int8_t c[4] = {static_cast<int8_t>(c0), 0, 0, 0};
+    return dx::coef_key(c);
+  };
+  code_of_key.assign(dx::kKeys, -1);
+  std::vector<Poly> codes;
+  auto add = [&](int key) {
+    if (code_of_key[key] >= 0) return;
+    if (static_cast<int>(codes.size()) >= kMaxCodes) throw std::runtime_error("too many distinct coefficients");
+    code_of_key[key] = static_cast<int8_t>(codes.size());
+    codes.push_back(poly_of(key));
+  };
+  add(key_of(1));
+  add(key_of(-1));
+  for (int k = 0; k < dx::kKeys; ++k)
+    if ((keybits[k >> 5] >> (k & 31)) & 1u) add(k);
+  return codes;
+}
+
+// Temporary device buffer of the builder.
+struct DxBuf {
+  void* p = nullptr;
+  explicit DxBuf(size_t n) {
+    if (n && hipMalloc(&p, n) != hipSuccess) throw MemError("device allocation of " + std::to_string(n) + " bytes failed");
+  }
+  ~DxBuf() {
+    if (p) (void)hipFree(p);
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+unsigned dx_blocks(int64_t n, int per) { return static_cast<unsigned>((n + per - 1) / per); }
+
+// Builds the forward and read-out maps of the coefficient form of
+// (lattice, m) on the current device.
+std::unique_ptr<DevMaps> build_dev_maps_cf(int lattice, int m) {
+  dx::Tables th;
+  dx::make_tables(th);
+  std::vector<dx::Factor> fac;
+  for (int i = 1; i <= m; ++i) fac.push_back(dx::forward_factor(lattice, m, i, true));
+  for (int i = 1; i <= m; ++i) fac.push_back(dx::last_factor(lattice, m, i, true));
+  int64_t in_max = 1, out_max = 1;
+  for (const dx::Factor& f : fac) {
+    in_max = std::max(in_max, dx::space_size(th, f.in));
+    out_max = std::max(out_max, dx::space_size(th, f.out));
+  }
+  if (in_max > static_cast<int64_t>(kSrcMask) || out_max > static_cast<int64_t>(kSrcMask))
+    throw std::runtime_error("state space too large for 26-bit ranks");
+  DxBuf tab(sizeof(dx::Tables)), keybits(kKeyWords * 4), err(4), code_map(dx::kKeys);
+  HIPX(hipMemcpy(tab.p, &th, sizeof th, hipMemcpyHostToDevice));
+  HIPX(hipMemset(keybits.p, 0, kKeyWords * 4));
+  HIPX(hipMemset(err.p, 0, 4));
+  // pass 1: coefficient keys of every factor
+  for (const dx::Factor& f : fac) {
+    const int64_t nin = dx::space_size(th, f.in);
+    hipLaunchKernelGGL(k_dx_keys, dim3(dx_blocks(nin, 256)), dim3(256), 0, nullptr, f, tab.as<dx::Tables>(), nin,
+                       keybits.as<uint32_t>(), err.as<int>());
+  }
+  HIPX(hipGetLastError());
+  std::vector<uint32_t> kb(kKeyWords);
+  int herr = 0;
+  HIPX(hipMemcpy(kb.data(), keybits.p, kKeyWords * 4, hipMemcpyDeviceToHost));
+  HIPX(hipMemcpy(&herr, err.p, 4, hipMemcpyDeviceToHost));
+  if (herr) throw std::runtime_error("device map build: an expansion left the supported coefficient range");
+  std::vector<int8_t> cok;
+  auto dm = std::make_unique<DevMaps>();
+  dm->codes = codes_from_keys(kb, cok);
+  HIPX(hipMemcpy(code_map.p, cok.data(), cok.size(), hipMemcpyHostToDevice));
+  for (const Poly& c : dm->codes)
+    for (int k = 0; k <= kMaxDeg; ++k) dm->general_cf = dm->general_cf || c.c[k] > 3 || c.c[k] < -3;
+  // pass 2: one factor at a time
+  const int64_t nslots_max = in_max * dx::kTerms;
+  DxBuf tgt(nslots_max * 4), code(nslots_max), cnt(out_max * 4), cur(out_max * 4),
+      sums(dx_blocks(out_max, 1024) * 4);
+  std::vector<int32_t> hs;
+  try {
+    for (size_t fi = 0; fi < fac.size(); ++fi) {
+      const dx::Factor& f = fac[fi];
+      const int64_t nin = dx::space_size(th, f.in), nout = dx::space_size(th, f.out);
+      HIPX(hipMemset(cnt.p, 0, nout * 4));
+      hipLaunchKernelGGL(k_dx_expand, dim3(dx_blocks(nin, 256)), dim3(256), 0, nullptr, f, tab.as<dx::Tables>(), nin,
+                         code_map.as<int8_t>(), tgt.as<int32_t>(), code.as<uint8_t>(), cnt.as<int32_t>(), err.as<int>());
+      void* rp = nullptr;
+      if (hipMalloc(&rp, (nout + 1) * 4) != hipSuccess) throw MemError("device allocation of factor maps failed");
+      dm->allocs.push_back(rp);
+      int32_t* row_ptr = static_cast<int32_t*>(rp);
+      const unsigned nb = dx_blocks(nout, 1024);
+      hipLaunchKernelGGL(k_dx_scan_blocks, dim3(nb), dim3(1024), 0, nullptr, cnt.as<int32_t>(), nout, row_ptr,
+                         sums.as<int32_t>());
+      HIPX(hipGetLastError());
+      hs.resize(nb);
+      HIPX(hipMemcpy(hs.data(), sums.p, nb * 4, hipMemcpyDeviceToHost));
+      HIPX(hipMemcpy(&herr, err.p, 4, hipMemcpyDeviceToHost));
+      if (herr) throw std::runtime_error("device map build: an expansion failed");
+      int64_t total = 0;
+      for (unsigned b = 0; b < nb; ++b) {
+        const int64_t v = hs[b];
+        hs[b] = static_cast<int32_t>(total);
+        total += v;
+        if (total > INT32_MAX) throw std::runtime_error("too many map entries for 32-bit row pointers");
+      }
+      const int32_t nnz = static_cast<int32_t>(total);
+      HIPX(hipMemcpy(sums.p, hs.data(), nb * 4, hipMemcpyHostToDevice));
+      HIPX(hipMemcpy(row_ptr + nout, &nnz, 4, hipMemcpyHostToDevice));
+      hipLaunchKernelGGL(k_dx_scan_add, dim3(nb), dim3(1024), 0, nullptr, row_ptr, nout, sums.as<int32_t>());
+      void* ep = nullptr;
+      if (hipMalloc(&ep, std::max<int64_t>(nnz, 1) * 4) != hipSuccess)
+        throw MemError("device allocation of factor maps failed");
+      dm->allocs.push_back(ep);
+      uint32_t* ent = static_cast<uint32_t*>(ep);
+      HIPX(hipMemset(cur.p, 0, nout * 4));
+      hipLaunchKernelGGL(k_dx_fill, dim3(dx_blocks(nin * dx::kTerms, 256)), dim3(256), 0, nullptr, tgt.as<int32_t>(),
+                         code.as<uint8_t>(), nin * dx::kTerms, row_ptr, cur.as<int32_t>(), ent);
+      hipLaunchKernelGGL(k_dx_sort_rows, dim3(dx_blocks(nout, 256)), dim3(256), 0, nullptr, row_ptr, nout, ent);
+      HIPX(hipGetLastError());
+      HIPX(hipDeviceSynchronize());
+      DevCsr d{row_ptr, ent, static_cast<int>(nout), static_cast<int>(nin)};
+      if (fi < static_cast<size_t>(m)) {
+        dm->fwd[fi] = d;
+      } else {
+        dm->last_fwd[fi - m] = d;
+        dm->l_max = std::max<int64_t>(dm->l_max, nout);
+      }
+    }
+  } catch (...) {
+    (void)hipDeviceSynchronize();
+    for (void* a : dm->allocs) (void)hipFree(a);
+    throw;
+  }
+  dm->normalised = true;
+  dm->on_device = true;
+  dm->lattice = lattice;
+  dm->m = m;
+  dm->s_nc = ncnnn_count(m);
+  dm->s_max = (lattice == kSquare && m >= 2) ? ncnnn_count(m) + ncnnn_count(m - 1) : ncnnn_count(m);
+  return dm;
+}
+
+// The builder's expansion and CSR assembly run on the host (same functions,
+// same order of operations) and compared with the host builder's maps in
+// the paper's state order: every forward factor, and for the coefficient
+// form every read-out factor in gather form.  Returns "" or the first
+// difference.
+std::string check_expansion(int lattice, int m, bool normalised) {
+  dx::Tables th;
+  dx::make_tables(th);
+  std::unique_ptr<MapSet> ms = build_maps(lattice, m, 0, normalised, true);
+  std::vector<dx::Factor> fac;
+  for (int i = 1; i <= m; ++i) fac.push_back(dx::forward_factor(lattice, m, i, normalised));
+  if (normalised)
+    for (int i = 1; i <= m; ++i) fac.push_back(dx::last_factor(lattice, m, i, normalised));
+  std::vector<uint32_t> kb(kKeyWords, 0u);
+  int32_t tg[dx::kTerms], ky[dx::kTerms];
+  for (const dx::Factor& f : fac) {
+    const int64_t nin = dx::space_size(th, f.in);
+    for (int64_t r = 0; r < nin; ++r) {
+      const int n = dx::expand_source(th, f, r, tg, ky);
+      if (n < 0) return "expansion failed for a source state";
+      for (int j = 0; j < n; ++j) kb[ky[j] >> 5] |= 1u << (ky[j] & 31);
+    }
+  }
+  std::vector<int8_t> cok;
+  std::vector<Poly> codes = codes_from_keys(kb, cok);
+  if (!normalised) {
+    // the host's evaluation-form table also holds the read-out factors' codes
+    if (codes.size() > ms->codes.size()) return "code table larger than the host's";
+  } else if (codes.size() != ms->codes.size()) {
+    return "code table size differs";
+  }
+  for (size_t c = 0; c < codes.size(); ++c)
+    for (int k = 0; k <= kMaxDeg; ++k)
+      if (codes[c].c[k] != ms->codes[c].c[k] && normalised) return "code table differs";
+  for (size_t fi = 0; fi < fac.size(); ++fi) {
+    const dx::Factor& f = fac[fi];
+    const Csr& h = fi < static_cast<size_t>(m) ? ms->fwd[fi] : ms->last_fwd[fi - m];
+    const int64_t nin = dx::space_size(th, f.in), nout = dx::space_size(th, f.out);
+    if (h.n_rows != nout || h.n_cols != nin) return "space sizes differ at factor " + std::to_string(fi);
+    std::vector<std::vector<uint32_t>> rows(nout);
+    for (int64_t r = 0; r < nin; ++r) {
+      const int n = dx::expand_source(th, f, r, tg, ky);
+      for (int j = 0; j < n; ++j) {
+        // codes by the host table's numbering (same keys, same order)
+        const Poly want = codes[cok[ky[j]]];
+        int hc = -1;
+        for (size_t c = 0; c < ms->codes.size() && hc < 0; ++c) {
+          bool eq = true;
+          for (int k = 0; k <= kMaxDeg; ++k) eq = eq && ms->codes[c].c[k] == want.c[k];
+          if (eq) hc = static_cast<int>(c);
+        }
+        if (hc < 0) return "coefficient missing from the host table";
+        rows[tg[j]].push_back(static_cast<uint32_t>(r) | (static_cast<uint32_t>(hc) << kSrcBits));
+      }
+    }
+    for (int64_t t = 0; t < nout; ++t) {
+      std::vector<uint32_t>& v = rows[t];
+      std::sort(v.begin(), v.end(), [](uint32_t a, uint32_t b) {
+        return (a & kSrcMask) != (b & kSrcMask) ? (a & kSrcMask) < (b & kSrcMask) : a < b;
+      });
+      const int64_t a0 = h.row_ptr[t], a1 = h.row_ptr[t + 1];
+      if (a1 - a0 != static_cast<int64_t>(v.size())) return "row length differs at factor " + std::to_string(fi);
+      for (int64_t a = a0; a < a1; ++a)
+        if (h.ent[a] != v[a - a0]) return "entry differs at factor " + std::to_string(fi);
+    }
+  }
+  return "";
+}
+
 std::mutex g_dev_mu;
 std::map<std::tuple<int, int, int, int>, std::unique_ptr<DevMaps>> g_dev;
+
+// Where the coefficient form's maps are built: on the device unless
+// CHROMSTRIP_HOST_MAPS=1 (host build and upload, reader order).
+bool cf_maps_on_device() {
+  const char* v = std::getenv("CHROMSTRIP_HOST_MAPS");
+  return !(v && std::string(v) == "1");
+}
 
 // Device copy of the maps of (lattice, m) in the un-normalised (evaluation)
 // or normalised (coefficient) form.
@@ -145,6 +479,12 @@ const DevMaps& dev_maps(int lattice, int m, bool normalised = false) {
   auto key = std::make_tuple(dev, lattice, m, normalised ? 1 : 0);
   auto it = g_dev.find(key);
   if (it != g_dev.end()) return *it->second;
+  if (normalised && cf_maps_on_device()) {
+    auto dm = build_dev_maps_cf(lattice, m);
+    const DevMaps& ref = *dm;
+    g_dev.emplace(key, std::move(dm));
+    return ref;
+  }
   const MapSet& ms = get_maps(lattice, m, normalised);
   auto dm = std::make_unique<DevMaps>();
   size_t bytes = 0;
@@ -253,6 +593,12 @@ const DevFamily& dev_family(const DevMaps& dm, int k) {
     df->fac.assign(dm.fwd, dm.fwd + dm.m);
     df->codes = dm.codes;
     df->shift = 0;
+    if (dm.on_device) {
+      df->general = dm.general_cf;
+      const DevFamily& r = *df;
+      dm.fam.emplace(k, std::move(df));
+      return r;
+    }
     const MapSet& ms = get_maps(dm.lattice, dm.m, true);
     std::vector<bool> used(dm.codes.size(), false);
     for (const Csr& c : ms.fwd)
@@ -1432,11 +1778,11 @@ int strip_sync_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, co
 // ---------------------------------------------------------------------------
 // Coefficient form (normalised weights as truncated polynomials in x = 1/q)
 // ---------------------------------------------------------------------------
+// Largest read-out space of the coefficient form: T_i^last leaves the
+// points 1..i singletons, N(m - i) states, largest for i = 1.
 int64_t readout_l_max(int lattice, int m) {
-  const MapSet& ms = get_maps(lattice, m, true);
-  int64_t l = 1;
-  for (const Csr& c : ms.last_fwd) l = std::max<int64_t>(l, c.n_rows);
-  return l;
+  (void)lattice;
+  return std::max<int64_t>(1, ncnnn_count(m - 1));
 }
 
 Tune resolve_series(const chrom_tuning* tune) {
@@ -1798,6 +2144,16 @@ int chromatic_prepare(int lattice, int m) {
   });
 }
 
+int chromatic_check_expansion(int lattice, int m, int normalised) {
+  return guarded([&] {
+    check_args(lattice, m, 0);
+    if (normalised != 0 && normalised != 1) throw ArgError("normalised must be 0 or 1");
+    const std::string diff = check_expansion(lattice, m, normalised == 1);
+    if (!diff.empty()) throw std::runtime_error("expansion check: " + diff);
+    return CHROM_OK;
+  });
+}
+
 int chromatic_prepare_host(int lattice, int m, int normalised) {
   return guarded([&] {
     check_args(lattice, m, 0);
@@ -1825,6 +2181,7 @@ void chromatic_release_maps(void) {
         if (fam.second->base) (void)hipFree(fam.second->base);
       }
       (void)hipFree(kv.second->base);
+      for (void* a : kv.second->allocs) (void)hipFree(a);
       (void)hipSetDevice(cur);
     }
     g_dev.clear();

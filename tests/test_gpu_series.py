@@ -130,3 +130,19 @@ def test_series_wide_row_addressing_identical(monkeypatch):
     got = api.series(TRI, 7, 5, 40, primes, mode="graph", tuning=dict(lanes_v=1))
     monkeypatch.delenv("CHROMSTRIP_WIDE_ROWS")
     np.testing.assert_array_equal(got, api.series(TRI, 7, 5, 40, primes, mode="graph", tuning=dict(lanes_v=1)))
+
+
+@pytest.mark.parametrize("lat,m,d", [(SQ, 1, 10), (SQ, 7, 40), (SQ, 12, 79), (TRI, 3, 20), (TRI, 11, 60)])
+def test_device_built_maps_match_host_built(monkeypatch, lat, m, d):
+    # the coefficient form's maps built on the device (paper order) and on the
+    # host (reader order, uploaded) give the same coefficients
+    primes = W.seeded_primes(3, 21)
+    api.release_maps()
+    dev = api.series(lat, m, m + 2, d, primes, mode="graph")
+    api.release_maps()
+    monkeypatch.setenv("CHROMSTRIP_HOST_MAPS", "1")
+    host_built = api.series(lat, m, m + 2, d, primes, mode="graph")
+    api.release_maps()
+    monkeypatch.delenv("CHROMSTRIP_HOST_MAPS")
+    np.testing.assert_array_equal(dev, host_built)
+    np.testing.assert_array_equal(dev[:, :, 0], 1)

@@ -61,3 +61,14 @@ def test_series_crt_lifts_to_the_exact_polynomial():
     assert coef == want
     stab, used = host.series_stabilised(res, ps)
     assert stab == want and used <= 3
+
+
+@pytest.mark.parametrize("lat", [SQ, TRI])
+@pytest.mark.parametrize("m", [1, 2, 3, 5, 8, 11, 13])
+def test_device_expansion_reproduces_host_maps(lat, m):
+    # the per-state expansion that builds the coefficient form's maps on the
+    # device, run on the host: every forward and read-out factor equal to
+    # the host builder's (paper order), and the evaluation form's forward
+    # factors too
+    api.check_expansion(lat, m, normalised=True)
+    api.check_expansion(lat, m, normalised=False)
