@@ -162,7 +162,12 @@ __global__ void __launch_bounds__(256, 8) k_dx_keys(dx::Factor f, const dx::Tabl
     atomicOr(err, 1);
     return;
   }
-  for (int j = 0; j < n; ++j) atomicOr(&keybits[ky[j] >> 5], 1u << (ky[j] & 31));
+  // Few distinct keys exist, so almost every bit is already set: a plain
+  // read first keeps the atomics (all on a handful of words) rare.
+  for (int j = 0; j < n; ++j) {
+    const uint32_t bit = 1u << (ky[j] & 31);
+    if (!(keybits[ky[j] >> 5] & bit)) atomicOr(&keybits[ky[j] >> 5], bit);  // a stale read only costs an atomic
+  }
 }
 
 // Per source: up to kTerms (target, code) pairs, target -1 for unused slots.
