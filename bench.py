@@ -15,8 +15,11 @@ Printed: one JSON line with the headline value, the roofline of the factor
 kernel (timed alone with HIP events on its launch stream), the plain
 per-instance path on the same workload, the CPU oracle on a bounded sample,
 and secondary workloads (the m = 2..14 square sweep as one graph, the
-triangular m = 12 strip, and the continuous-batching server against the
-plain path on a Poisson job stream).
+triangular m = 12 strip, the continuous-batching server against the plain
+path on a Poisson job stream, the coefficient form on the 14 x 15 strip, the
+square 18 x 19 strip, and the finite-lattice series at k = 41 on both
+lattices, checked against the paper's Table 1, printed series and Baxter's
+product).
 
 Usage: python bench.py [--steps K] [--warmup W] [--quick]
 """
@@ -209,6 +212,25 @@ def bench_finite_lattice(k):
                         f"(finite-lattice k = {k}: widths 1..{k // 2}, coefficient form x^0..x^{N}, "
                         f"5 seeded primes{', polygon term' if extra else ''})",
             "seconds": dt, "primes_used": res["primes_used"], "matches_table1": match}
+
+
+def bench_triangular_series(k):
+    """The triangular-lattice series of Sec. 4.4 to x^{k-1} by the
+    finite-lattice method on the GPU; surface and corner checked against the
+    printed series, bulk against Baxter's product."""
+    from paper_1005_3609_amd import finite_lattice as FL
+    from paper_1005_3609_amd import workloads as W
+    t0 = time.perf_counter()
+    res = FL.triangular_series(k, W.seeded_primes(3, 2024), mode="graph")
+    dt = time.perf_counter() - t0
+    tab = FL._read_table(os.path.join(ROOT, "tests", "golden", "triangular_series.txt"))
+    N = k - 1
+    match = (all(res["surface"][i] == tab[i][0] and res["corner"][i] == tab[i][1] for i in range(N + 1))
+             and res["bulk"] == FL.baxter_bulk(N))
+    assert match, "triangular series differ from the paper's"
+    return {"workload": f"triangular-lattice bulk, surface and corner series to x^{N} (finite-lattice k = {k}: "
+                        f"widths 1..{k // 2}, coefficient form, 3 seeded primes)",
+            "seconds": dt, "primes_used": res["primes_used"], "matches_paper": match}
 
 
 def bench_m18(torch, stream, tune, rows):
@@ -444,8 +466,10 @@ def main():
         log(f"triangular m=12: {extra['triangular_12x13']['value']:.3e} state-updates/s")
         extra["serving"] = bench_serving(torch, args.serve_jobs, args.serve_plain_jobs)
         log(f"serving: {extra['serving']}")
-        extra["finite_lattice_square"] = bench_finite_lattice(33)
+        extra["finite_lattice_square"] = bench_finite_lattice(41)
         log(f"finite-lattice series: {extra['finite_lattice_square']}")
+        extra["finite_lattice_triangular"] = bench_triangular_series(41)
+        log(f"triangular series: {extra['finite_lattice_triangular']}")
         extra["series_square_14x15"] = bench_series(torch, stream, tune, max(2, args.steps // 2))
         log(f"coefficient form m=14: {extra['series_square_14x15']['value']:.3e} state-updates/s, "
             f"{extra['series_square_14x15']['ms_per_step']:.2f} ms/strip")
