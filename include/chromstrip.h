@@ -32,6 +32,19 @@
  *     device), kept until chromatic_release_maps() or process exit.
  *   - Host-pointer arguments are read before the call returns.  Device
  *     pointers must stay valid until the work queued on `stream` finishes.
+ *
+ * Environment (read when the maps of a (lattice, m) are first built or a
+ * job is laid out; none changes any result):
+ *   CHROMSTRIP_THREADS=n       host threads for host map builds (default:
+ *                              the hardware's count)
+ *   CHROMSTRIP_HOST_MAPS=1     build the coefficient form's maps on the host
+ *                              and upload them, instead of on the device
+ *   CHROMSTRIP_STATE_ORDER=paper  keep the paper's state order between the
+ *                              forward factors of host-built maps (default:
+ *                              reader order, for locality)
+ *   CHROMSTRIP_WIDE_ROWS=1     64-bit row bases in the coefficient form at
+ *                              any size (they are used past 4 GiB anyway)
+ *   CHROMSTRIP_VERBOSE=1       one stderr line per site of a host map build
  */
 #ifndef CHROMSTRIP_H
 #define CHROMSTRIP_H
