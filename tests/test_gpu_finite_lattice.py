@@ -59,3 +59,16 @@ def test_triangular_series_match_paper(k, mode):
     assert res["bulk"] == FL.baxter_bulk(N)
     assert res["surface"] == fs[: N + 1]
     assert res["corner"] == fc[: N + 1]
+
+
+def test_series_cli(capsys):
+    # the command-line driver, both lattices, checked against the paper's tables
+    import os
+    golden = os.path.join(os.path.dirname(__file__), "golden")
+    rc = FL.main(["13", "--extra", "--check", os.path.join(golden, "table1_square.txt")])
+    out = capsys.readouterr().out
+    assert rc == 0 and "all 71 coefficients equal" in out
+    rc = FL.main(["16", "--lattice", "triangular", "--primes", "3", "--baxter", "--check",
+                  os.path.join(golden, "triangular_series.txt")])
+    out = capsys.readouterr().out
+    assert rc == 0 and "all 32 coefficients equal" in out and "Baxter's product to x^15: equal" in out
