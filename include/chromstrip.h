@@ -194,6 +194,13 @@ int chromatic_prepare(int lattice, int m);
  * waits for it.  Returns 0 or CHROM_EINVAL. */
 int chromatic_prepare_host(int lattice, int m, int normalised);
 
+/* Builds the coefficient form's factor maps of (lattice, m) on the current
+ * device (or on the host and uploads them, with CHROMSTRIP_HOST_MAPS=1)
+ * ahead of time.  The first coefficient-form call for (lattice, m) does this
+ * itself, with allocations and synchronous copies, so call this first when
+ * that call is to be captured in a hipGraph.  Returns 0 or a CHROM_E* code. */
+int chromatic_prepare_series(int lattice, int m);
+
 /* Host-side check of the per-state expansion that builds the coefficient
  * form's maps on the device (Sec. 3.1-3.4): the same expansion and CSR
  * assembly run on the host and are compared, factor by factor, with the

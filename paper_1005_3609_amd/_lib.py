@@ -62,6 +62,7 @@ _SIGS = {
     "chromatic_prepare": (C.c_int, [C.c_int, C.c_int]),
     "chromatic_prepare_host": (C.c_int, [C.c_int, C.c_int, C.c_int]),
     "chromatic_check_expansion": (C.c_int, [C.c_int, C.c_int, C.c_int]),
+    "chromatic_prepare_series": (C.c_int, [C.c_int, C.c_int]),
     "chromatic_release_maps": (None, []),
     "chromatic_batch_workspace_bytes": (C.c_size_t, [C.POINTER(Job), C.c_int, C.POINTER(Tuning)]),
     "chromatic_batch": (C.c_int, [C.POINTER(Job), C.c_int, C.POINTER(Tuning), C.c_void_p, C.c_size_t,

@@ -108,6 +108,12 @@ def prepare(lattice, m: int) -> None:
     check(lib().chromatic_prepare(lattice_id(lattice), m))
 
 
+def prepare_series(lattice, m: int) -> None:
+    """Coefficient-form maps of (lattice, m) on the current device ahead of
+    time (the first series call would build them itself)."""
+    check(lib().chromatic_prepare_series(lattice_id(lattice), m))
+
+
 def prepare_host(lattice, m: int, normalised: bool = False) -> None:
     """Host maps of (lattice, m) only (no device); safe to call from a second
     thread while device work for other widths runs (the GIL is released

@@ -2149,6 +2149,15 @@ int chromatic_prepare(int lattice, int m) {
   });
 }
 
+int chromatic_prepare_series(int lattice, int m) {
+  return guarded([&] {
+    check_args(lattice, m, 0);
+    const DevMaps& dm = dev_maps(lattice, m, true);
+    (void)dev_family(dm, 1);
+    return CHROM_OK;
+  });
+}
+
 int chromatic_check_expansion(int lattice, int m, int normalised) {
   return guarded([&] {
     check_args(lattice, m, 0);

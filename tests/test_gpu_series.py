@@ -106,6 +106,16 @@ def test_series_edge_cases():
     np.testing.assert_array_equal(api.series(SQ, 6, 1, 40, [2147483629]).astype(np.int64), want)
 
 
+def test_prepare_series_then_capture_free_call():
+    # maps prepared ahead; the series call itself then only queues work
+    api.prepare_series(TRI, 9)
+    primes = W.seeded_primes(2, 5)
+    got = api.series(TRI, 9, 4, 30, primes, mode="graph").astype(np.int64)
+    np.testing.assert_array_equal(got, _oracle(TRI, 9, 4, 30, primes))
+    with pytest.raises(api.ChromError):
+        api.prepare_series(SQ, 0)
+
+
 def test_series_bad_arguments():
     with pytest.raises(api.ChromError):
         api.series(SQ, 4, 3, 64, [P31], tuning=dict(lanes_v=1))          # d_max >= 64 lanes_v
