@@ -148,6 +148,40 @@ def bench_sweep(torch, stream, tune, steps):
             "ms_per_step": ms, "value": upd / (ms / 1e3), "unit": "state-updates/s"}
 
 
+def bench_small_configs(torch, stream, steps):
+    """The two plain-method workloads: the square 4x5 rectangle at q = 0..20
+    mod 2^31-1 (per-instance launches, checked against P(1) = 0, P(2) = 2),
+    and the square m = 10 strip (rows 1..11) at 80 q x 4 primes, one launch
+    sequence per instance, beside the same 320 instances batched."""
+    from paper_1005_3609_amd import api
+    from paper_1005_3609_amd import workloads as W
+    out = {}
+    for name in ("square_4x5", "square_m10"):
+        w = W.workload(name)
+        lat, m, n = w["strips"][0]
+        q, p = w["q_points"], w["primes"]
+        api.prepare(lat, m)
+        I = len(q) * len(p)
+        rows = {}
+        for mode in ("plain", "graph"):
+            ws = api.alloc_workspace(api.workspace_bytes(lat, m, n, len(q), len(p), mode), None)
+            res = torch.zeros((n, len(q), len(p)), dtype=torch.int32, device=ws.device)
+
+            def run():
+                api.strip_async(lat, m, n, q, p, mode=mode, workspace=ws, out=res, stream=stream)
+            run()
+            ms = timed(torch, stream, run, steps)
+            r = api.to_u32(res).astype("int64").reshape(n, len(q), len(p))
+            q1, q2 = q.index(1), q.index(2)
+            assert (r[:, q1, :] == 0).all() and (r[:, q2, :] == 2).all(), f"{name} {mode}: P(1) = 0, P(2) = 2 failed"
+            rows[mode] = {"ms_per_step": ms, "value": updates_of(lat, m, n, I) / (ms / 1e3),
+                          "unit": "state-updates/s"}
+        rows["workload"] = f"square {m}x{n}, {len(q)} q x {len(p)} primes ({I} instances); plain = one launch " \
+                           f"sequence per instance, graph = all instances batched"
+        out[name] = rows
+    return out
+
+
 def bench_triangular(torch, stream, steps):
     from paper_1005_3609_amd import api
     from paper_1005_3609_amd import workloads as W
@@ -460,6 +494,9 @@ def main():
 
     extra = {}
     if not args.quick:
+        extra["plain_configs"] = bench_small_configs(torch, stream, max(2, args.steps // 4))
+        log("plain configs: " + ", ".join(f"{k} plain {v['plain']['value']:.3e} / graph {v['graph']['value']:.3e}"
+                                          for k, v in extra["plain_configs"].items()))
         extra["sweep_square_2_14"] = bench_sweep(torch, stream, tune, max(2, args.steps // 4))
         log(f"sweep m=2..14: {extra['sweep_square_2_14']['value']:.3e} state-updates/s")
         extra["triangular_12x13"] = bench_triangular(torch, stream, max(2, args.steps // 2))
