@@ -77,8 +77,9 @@ enum {
   CHROM_MODE_GROUPED = 4,    /* every step one grouped launch; the whole sweep one hipGraph */
 };
 
-/* Launch shape of the batched and persistent kernels.  Zero fields take
- * the library's defaults.  Every choice gives bit-identical results. */
+/* Launch shape of the batched, graph and grouped kernels (and of the
+ * coefficient form).  Zero fields take the library's defaults.  Every
+ * choice gives bit-identical results. */
 typedef struct chrom_tuning {
   int lanes_v;          /* instances per lane: 1, 2 or 4 (chunk width W = 64 * lanes_v) */
   int targets_per_wave; /* consecutive target states handled by one wavefront, 1..63 */
@@ -215,7 +216,7 @@ int chromatic_check_expansion(int lattice, int m, int normalised);
 void chromatic_release_maps(void);
 
 /* ------------------------------------------------------------------------
- * Many strips of uneven size in one persistent launch
+ * Many strips of uneven size in shared grouped launches
  * ---------------------------------------------------------------------- */
 typedef struct chrom_job {
   int lattice;
