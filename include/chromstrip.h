@@ -202,6 +202,17 @@ int chromatic_prepare_host(int lattice, int m, int normalised);
  * that call is to be captured in a hipGraph.  Returns 0 or a CHROM_E* code. */
 int chromatic_prepare_series(int lattice, int m);
 
+/* Copies one coefficient-form factor map of (lattice, m) as the current
+ * device holds it (built there, or uploaded with CHROMSTRIP_HOST_MAPS=1) to
+ * the host: which = 4 forward factor T_{idx+1}, 5 read-out factor
+ * T_{idx+1}^last, both in gather form.  Call once with null row_ptr and
+ * entries for the sizes, then with host buffers of n_rows + 1 and nnz
+ * words.  Entry layout as the kernels read it: source rank in bits 0-25,
+ * coefficient code in bits 26-31 (codes as chromatic_code_table with
+ * normalised = 1).  Returns 0 or a CHROM_E* code. */
+int chromatic_series_map_export(int lattice, int m, int which, int idx, int64_t* n_rows, int64_t* n_cols,
+                                int64_t* nnz, int32_t* row_ptr, uint32_t* entries);
+
 /* Host-side check of the per-state expansion that builds the coefficient
  * form's maps on the device (Sec. 3.1-3.4): the same expansion and CSR
  * assembly run on the host and are compared, factor by factor, with the

@@ -63,6 +63,9 @@ _SIGS = {
     "chromatic_prepare_host": (C.c_int, [C.c_int, C.c_int, C.c_int]),
     "chromatic_check_expansion": (C.c_int, [C.c_int, C.c_int, C.c_int]),
     "chromatic_prepare_series": (C.c_int, [C.c_int, C.c_int]),
+    "chromatic_series_map_export": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int64),
+                                              C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_void_p,
+                                              C.c_void_p]),
     "chromatic_release_maps": (None, []),
     "chromatic_batch_workspace_bytes": (C.c_size_t, [C.POINTER(Job), C.c_int, C.POINTER(Tuning)]),
     "chromatic_batch": (C.c_int, [C.POINTER(Job), C.c_int, C.POINTER(Tuning), C.c_void_p, C.c_size_t,

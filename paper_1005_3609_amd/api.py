@@ -114,6 +114,19 @@ def prepare_series(lattice, m: int) -> None:
     check(lib().chromatic_prepare_series(lattice_id(lattice), m))
 
 
+def series_map_export(lattice, m: int, which: int, idx: int):
+    """The coefficient-form map the current device holds: (row_ptr int32,
+    entries uint32, n_cols); which 4 = forward, 5 = read-out factor."""
+    L = lib()
+    nr, nc, nz = C.c_int64(), C.c_int64(), C.c_int64()
+    check(L.chromatic_series_map_export(lattice_id(lattice), m, which, idx, C.byref(nr), C.byref(nc), C.byref(nz),
+                                        None, None))
+    rp = np.zeros(nr.value + 1, dtype=np.int32)
+    ent = np.zeros(max(nz.value, 1), dtype=np.uint32)
+    check(L.chromatic_series_map_export(lattice_id(lattice), m, which, idx, None, None, None, _ptr(rp), _ptr(ent)))
+    return rp, ent[: nz.value], int(nc.value)
+
+
 def prepare_host(lattice, m: int, normalised: bool = False) -> None:
     """Host maps of (lattice, m) only (no device); safe to call from a second
     thread while device work for other widths runs (the GIL is released

@@ -192,6 +192,11 @@ __global__ void __launch_bounds__(256, 8) k_dx_expand(dx::Factor f, const dx::Ta
   }
 }
 
+__global__ void __launch_bounds__(256) k_set_fill(int32_t* a, int64_t n, int32_t v) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
 // Exclusive prefix sum, first level: blocks of 1024 counts scanned in LDS;
 // block totals to sums[block].
 __global__ void __launch_bounds__(1024) k_dx_scan_blocks(const int32_t* cnt, int64_t n, int32_t* out, int32_t* sums) {
@@ -291,6 +296,162 @@ struct DxBuf {
 
 unsigned dx_blocks(int64_t n, int per) { return static_cast<unsigned>((n + per - 1) / per); }
 
+// out[0..n] = exclusive prefix sums of in[0..n-1] (out[n] = total), on the
+// device; block totals are combined on the host.  `sums` holds at least
+// dx_blocks(n, 1024) words.  Returns the total.
+int64_t dx_exclusive_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* sums) {
+  const unsigned nb = dx_blocks(std::max<int64_t>(n, 1), 1024);
+  hipLaunchKernelGGL(k_dx_scan_blocks, dim3(nb), dim3(1024), 0, nullptr, in, n, out, sums);
+  HIPX(hipGetLastError());
+  std::vector<int32_t> hs(nb);
+  HIPX(hipMemcpy(hs.data(), sums, nb * 4, hipMemcpyDeviceToHost));
+  int64_t total = 0;
+  for (unsigned b = 0; b < nb; ++b) {
+    const int64_t v = hs[b];
+    hs[b] = static_cast<int32_t>(total);
+    total += v;
+    if (total > INT32_MAX) throw std::runtime_error("prefix sum beyond 32 bits");
+  }
+  const int32_t t32 = static_cast<int32_t>(total);
+  HIPX(hipMemcpy(sums, hs.data(), nb * 4, hipMemcpyHostToDevice));
+  HIPX(hipMemcpy(out + n, &t32, 4, hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(k_dx_scan_add, dim3(nb), dim3(1024), 0, nullptr, out, n, sums);
+  HIPX(hipGetLastError());
+  return total;
+}
+
+// Reader order on the device (the host builder's rule): going backwards
+// over the forward factors, the states between F_k and F_{k+1} are ordered
+// by the first row of F_{k+1}, in its own new order, that reads them (ties
+// by old rank), unread states last.  first[s] = that row (nrows if none).
+__global__ void __launch_bounds__(256) k_ro_first(const int32_t* row_ptr, const uint32_t* ent, int64_t nrows,
+                                                  const int32_t* perm_rows, int32_t* first) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  const int32_t nr = perm_rows ? perm_rows[r] : static_cast<int32_t>(r);
+  for (int32_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) atomicMin(&first[ent[e] & kSrcMask], nr);
+}
+
+// cnt[row] = states first read by that (new) row; unread[s] = 1 for states no row reads.
+__global__ void __launch_bounds__(256) k_ro_count(const int32_t* first, int64_t ns, int64_t nrows, int32_t* cnt,
+                                                  int32_t* unread) {
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= ns) return;
+  const int32_t f = first[s];
+  unread[s] = f >= nrows ? 1 : 0;
+  if (f < nrows) atomicAdd(&cnt[f], 1);
+}
+
+// A row's first-read states, in column (old rank) order, take consecutive
+// positions from its bucket's start.
+__global__ void __launch_bounds__(256) k_ro_assign(const int32_t* row_ptr, const uint32_t* ent, int64_t nrows,
+                                                   const int32_t* perm_rows, const int32_t* first,
+                                                   const int32_t* start, int32_t* perm) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  const int32_t nr = perm_rows ? perm_rows[r] : static_cast<int32_t>(r);
+  int32_t j = start[nr];
+  for (int32_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
+    const uint32_t s = ent[e] & kSrcMask;
+    if (first[s] == nr) perm[s] = j++;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_ro_unread(const int32_t* first, int64_t ns, int64_t nrows,
+                                                   const int32_t* upos, int32_t base, int32_t* perm) {
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= ns) return;
+  if (first[s] >= nrows) perm[s] = base + upos[s];
+}
+
+// Renumbering of one factor: new row lengths, then entries copied with new
+// columns (rows sorted afterwards by k_dx_sort_rows).
+__global__ void __launch_bounds__(256) k_rn_len(const int32_t* row_ptr, int64_t nrows, const int32_t* perm_rows,
+                                                int32_t* len) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  len[perm_rows ? perm_rows[r] : r] = row_ptr[r + 1] - row_ptr[r];
+}
+
+__global__ void __launch_bounds__(256) k_rn_fill(const int32_t* row_ptr, const uint32_t* ent, int64_t nrows,
+                                                 const int32_t* perm_rows, const int32_t* perm_cols,
+                                                 const int32_t* new_row_ptr, uint32_t* new_ent) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  int32_t w = new_row_ptr[perm_rows ? perm_rows[r] : r];
+  for (int32_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
+    const uint32_t c = ent[e] & kSrcMask, code = ent[e] & ~kSrcMask;
+    new_ent[w++] = (perm_cols ? static_cast<uint32_t>(perm_cols[c]) : c) | code;
+  }
+}
+
+// Applies the reader order to the forward factors of a device-built set:
+// fwd[k] (F_{k+1}) has rows in space k+1 and columns in space k; spaces 0
+// and m (NCNNN, before and after the row) keep the paper's order.
+void device_reader_order(DevMaps& dm, int m) {
+  if (m < 2) return;
+  std::vector<DxBuf*> perm(m + 1, nullptr);   // perm[k][old] = new, space after F_k
+  std::vector<std::unique_ptr<DxBuf>> own;
+  int64_t big = 1;
+  for (int k = 0; k < m; ++k) big = std::max<int64_t>(big, std::max(dm.fwd[k].n_rows, dm.fwd[k].n_cols));
+  DxBuf first((big + 1) * 4), cnt((big + 1) * 4), start((big + 2) * 4), unread((big + 1) * 4),
+      upos((big + 2) * 4), sums(dx_blocks(big + 1, 1024) * 4 + 64);
+  for (int k = m - 1; k >= 1; --k) {
+    const DevCsr& t = dm.fwd[k];   // F_{k+1}
+    const int64_t ns = t.n_cols, nrows = t.n_rows;
+    const int32_t* prow = perm[k + 1] ? perm[k + 1]->as<int32_t>() : nullptr;
+    hipLaunchKernelGGL(k_set_fill, dim3(dx_blocks(ns, 256)), dim3(256), 0, nullptr, first.as<int32_t>(), ns,
+                       static_cast<int32_t>(nrows));
+    hipLaunchKernelGGL(k_ro_first, dim3(dx_blocks(nrows, 256)), dim3(256), 0, nullptr, t.row_ptr, t.ent, nrows, prow,
+                       first.as<int32_t>());
+    HIPX(hipMemset(cnt.p, 0, nrows * 4));
+    hipLaunchKernelGGL(k_ro_count, dim3(dx_blocks(ns, 256)), dim3(256), 0, nullptr, first.as<int32_t>(), ns, nrows,
+                       cnt.as<int32_t>(), unread.as<int32_t>());
+    const int64_t nread = dx_exclusive_scan(cnt.as<int32_t>(), nrows, start.as<int32_t>(), sums.as<int32_t>());
+    (void)dx_exclusive_scan(unread.as<int32_t>(), ns, upos.as<int32_t>(), sums.as<int32_t>());
+    own.push_back(std::make_unique<DxBuf>(ns * 4));
+    perm[k] = own.back().get();
+    hipLaunchKernelGGL(k_ro_assign, dim3(dx_blocks(nrows, 256)), dim3(256), 0, nullptr, t.row_ptr, t.ent, nrows,
+                       prow, first.as<int32_t>(), start.as<int32_t>(), perm[k]->as<int32_t>());
+    hipLaunchKernelGGL(k_ro_unread, dim3(dx_blocks(ns, 256)), dim3(256), 0, nullptr, first.as<int32_t>(), ns, nrows,
+                       upos.as<int32_t>(), static_cast<int32_t>(nread), perm[k]->as<int32_t>());
+    HIPX(hipGetLastError());
+  }
+  for (int k = 0; k < m; ++k) {
+    DevCsr& c = dm.fwd[k];
+    const int64_t nrows = c.n_rows;
+    const int32_t* prow = perm[k + 1] ? perm[k + 1]->as<int32_t>() : nullptr;
+    const int32_t* pcol = perm[k] ? perm[k]->as<int32_t>() : nullptr;
+    hipLaunchKernelGGL(k_rn_len, dim3(dx_blocks(nrows, 256)), dim3(256), 0, nullptr, c.row_ptr, nrows, prow,
+                       cnt.as<int32_t>());
+    void* rp = nullptr;
+    void* ep = nullptr;
+    if (hipMalloc(&rp, (nrows + 1) * 4) != hipSuccess) throw MemError("device allocation of factor maps failed");
+    dm.allocs.push_back(rp);
+    const int64_t nnz = dx_exclusive_scan(cnt.as<int32_t>(), nrows, static_cast<int32_t*>(rp), sums.as<int32_t>());
+    if (hipMalloc(&ep, std::max<int64_t>(nnz, 1) * 4) != hipSuccess)
+      throw MemError("device allocation of factor maps failed");
+    dm.allocs.push_back(ep);
+    hipLaunchKernelGGL(k_rn_fill, dim3(dx_blocks(nrows, 256)), dim3(256), 0, nullptr, c.row_ptr, c.ent, nrows, prow,
+                       pcol, static_cast<int32_t*>(rp), static_cast<uint32_t*>(ep));
+    hipLaunchKernelGGL(k_dx_sort_rows, dim3(dx_blocks(nrows, 256)), dim3(256), 0, nullptr,
+                       static_cast<const int32_t*>(rp), nrows, static_cast<uint32_t*>(ep));
+    HIPX(hipGetLastError());
+    HIPX(hipDeviceSynchronize());
+    // the old arrays go
+    for (auto it = dm.allocs.begin(); it != dm.allocs.end();) {
+      if (*it == static_cast<const void*>(c.row_ptr) || *it == static_cast<const void*>(c.ent)) {
+        (void)hipFree(*it);
+        it = dm.allocs.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    c.row_ptr = static_cast<const int32_t*>(rp);
+    c.ent = static_cast<const uint32_t*>(ep);
+  }
+}
+
 // Builds the forward and read-out maps of the coefficient form of
 // (lattice, m) on the current device.
 std::unique_ptr<DevMaps> build_dev_maps_cf(int lattice, int m) {
@@ -382,6 +543,8 @@ std::unique_ptr<DevMaps> build_dev_maps_cf(int lattice, int m) {
         dm->l_max = std::max<int64_t>(dm->l_max, nout);
       }
     }
+    const char* order = std::getenv("CHROMSTRIP_STATE_ORDER");
+    if (!(order && std::string(order) == "paper")) device_reader_order(*dm, m);
   } catch (...) {
     (void)hipDeviceSynchronize();
     for (void* a : dm->allocs) (void)hipFree(a);
@@ -2154,6 +2317,25 @@ int chromatic_prepare_series(int lattice, int m) {
     check_args(lattice, m, 0);
     const DevMaps& dm = dev_maps(lattice, m, true);
     (void)dev_family(dm, 1);
+    return CHROM_OK;
+  });
+}
+
+int chromatic_series_map_export(int lattice, int m, int which, int idx, int64_t* n_rows, int64_t* n_cols,
+                                int64_t* nnz, int32_t* row_ptr, uint32_t* entries) {
+  return guarded([&] {
+    check_args(lattice, m, 0);
+    if (which != 4 && which != 5) throw ArgError("which must be 4 (forward) or 5 (read-out)");
+    if (idx < 0 || idx >= m) throw ArgError("idx out of range");
+    const DevMaps& dm = dev_maps(lattice, m, true);
+    const DevCsr& c = which == 4 ? dm.fwd[idx] : dm.last_fwd[idx];
+    int32_t total = 0;
+    HIPX(hipMemcpy(&total, c.row_ptr + c.n_rows, 4, hipMemcpyDeviceToHost));
+    if (n_rows) *n_rows = c.n_rows;
+    if (n_cols) *n_cols = c.n_cols;
+    if (nnz) *nnz = total;
+    if (row_ptr) HIPX(hipMemcpy(row_ptr, c.row_ptr, (static_cast<size_t>(c.n_rows) + 1) * 4, hipMemcpyDeviceToHost));
+    if (entries && total > 0) HIPX(hipMemcpy(entries, c.ent, static_cast<size_t>(total) * 4, hipMemcpyDeviceToHost));
     return CHROM_OK;
   });
 }

@@ -116,6 +116,21 @@ def test_prepare_series_then_capture_free_call():
         api.prepare_series(SQ, 0)
 
 
+@pytest.mark.parametrize("lat,m", [(SQ, 1), (SQ, 2), (SQ, 9), (SQ, 13), (TRI, 3), (TRI, 12)])
+def test_device_built_maps_equal_host_maps(lat, m):
+    # with the reader order applied on the device, the maps built there are
+    # word for word the host builder's (same spaces, numbering and codes)
+    api.release_maps()
+    for which in (4, 5):
+        for i in range(m):
+            rp_d, ent_d, nc_d = api.series_map_export(lat, m, which, i)
+            rp_h, cols, codes, nc_h = api.map_export(lat, m, which, i)
+            ent_h = (cols | (codes << 26)).astype(np.uint32)
+            assert nc_d == nc_h, (which, i)
+            np.testing.assert_array_equal(rp_d, rp_h, err_msg=f"row pointers {which} {i}")
+            np.testing.assert_array_equal(ent_d, ent_h, err_msg=f"entries {which} {i}")
+
+
 def test_series_bad_arguments():
     with pytest.raises(api.ChromError):
         api.series(SQ, 4, 3, 64, [P31], tuning=dict(lanes_v=1))          # d_max >= 64 lanes_v
