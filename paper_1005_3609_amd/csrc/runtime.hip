@@ -493,7 +493,6 @@ std::unique_ptr<DevMaps> build_dev_maps_cf(int lattice, int m) {
   const int64_t nslots_max = in_max * dx::kTerms;
   DxBuf tgt(nslots_max * 4), code(nslots_max), cnt(out_max * 4), cur(out_max * 4),
       sums(dx_blocks(out_max, 1024) * 4);
-  std::vector<int32_t> hs;
   try {
     for (size_t fi = 0; fi < fac.size(); ++fi) {
       const dx::Factor& f = fac[fi];
@@ -505,25 +504,9 @@ std::unique_ptr<DevMaps> build_dev_maps_cf(int lattice, int m) {
       if (hipMalloc(&rp, (nout + 1) * 4) != hipSuccess) throw MemError("device allocation of factor maps failed");
       dm->allocs.push_back(rp);
       int32_t* row_ptr = static_cast<int32_t*>(rp);
-      const unsigned nb = dx_blocks(nout, 1024);
-      hipLaunchKernelGGL(k_dx_scan_blocks, dim3(nb), dim3(1024), 0, nullptr, cnt.as<int32_t>(), nout, row_ptr,
-                         sums.as<int32_t>());
-      HIPX(hipGetLastError());
-      hs.resize(nb);
-      HIPX(hipMemcpy(hs.data(), sums.p, nb * 4, hipMemcpyDeviceToHost));
+      const int32_t nnz = static_cast<int32_t>(dx_exclusive_scan(cnt.as<int32_t>(), nout, row_ptr, sums.as<int32_t>()));
       HIPX(hipMemcpy(&herr, err.p, 4, hipMemcpyDeviceToHost));
       if (herr) throw std::runtime_error("device map build: an expansion failed");
-      int64_t total = 0;
-      for (unsigned b = 0; b < nb; ++b) {
-        const int64_t v = hs[b];
-        hs[b] = static_cast<int32_t>(total);
-        total += v;
-        if (total > INT32_MAX) throw std::runtime_error("too many map entries for 32-bit row pointers");
-      }
-      const int32_t nnz = static_cast<int32_t>(total);
-      HIPX(hipMemcpy(sums.p, hs.data(), nb * 4, hipMemcpyHostToDevice));
-      HIPX(hipMemcpy(row_ptr + nout, &nnz, 4, hipMemcpyHostToDevice));
-      hipLaunchKernelGGL(k_dx_scan_add, dim3(nb), dim3(1024), 0, nullptr, row_ptr, nout, sums.as<int32_t>());
       void* ep = nullptr;
       if (hipMalloc(&ep, std::max<int64_t>(nnz, 1) * 4) != hipSuccess)
         throw MemError("device allocation of factor maps failed");
