@@ -188,12 +188,14 @@ def bench_triangular(torch, stream, steps):
     w = W.workload("triangular_m12")
     lat, m, n = w["strips"][0]
     api.prepare(lat, m)
-    tune = {"streams": 3, "unroll": 8}
+    from paper_1005_3609_amd import tune as tuner
+    I = len(w["q_points"]) * len(w["primes"])
+    tune = tuner.lookup_tuned(lat, m, I, n) or {"streams": 3, "unroll": 8}
+    tune = {k: v for k, v in tune.items() if k not in ("mode", "ms")}
     out, ws = api.strip_async(lat, m, n, w["q_points"], w["primes"], mode="graph", tuning=tune, stream=stream)
     ms = timed(torch, stream, lambda: api.strip_async(lat, m, n, w["q_points"], w["primes"], mode="graph",
                                                       tuning=tune, workspace=ws, out=out, stream=stream), steps)
-    I = len(w["q_points"]) * len(w["primes"])
-    return {"workload": "triangular 12x13, 48 q x 6 primes, graph row replay", "ms_per_step": ms,
+    return {"workload": f"triangular 12x13, 48 q x 6 primes, graph row replay, tuning {tune}", "ms_per_step": ms,
             "value": updates_of(lat, m, n, I) / (ms / 1e3), "unit": "state-updates/s"}
 
 

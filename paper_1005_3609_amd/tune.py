@@ -212,6 +212,8 @@ def main():
     ap.add_argument("--cache", default=DEFAULT_CACHE)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--quick", action="store_true", help="a reduced search space")
+    ap.add_argument("--medium", action="store_true",
+                    help="lanes_v 1-2, fused families 1-3, one or three chunk groups, graph mode (96 candidates)")
     ap.add_argument("--series", type=int, default=None, metavar="D",
                     help="tune the coefficient form to x^D for the workload's strips and primes instead")
     args = ap.parse_args()
@@ -224,6 +226,9 @@ def main():
                                   best=res["best"])), flush=True)
         return
     space = None
+    if args.medium:
+        space = dict(lanes_v=[1, 2], targets_per_wave=[4, 8], waves_per_block=[4, 8], xcd_order=[1],
+                     unroll=[4, 8], streams=[1, 3], fuse=[1, 2, 3], stage=[0], mode=["graph"])
     if args.quick:
         space = dict(lanes_v=[2], targets_per_wave=[4, 8], waves_per_block=[4, 8], xcd_order=[1],
                      unroll=[4], streams=[3], fuse=[2], stage=[0, 1], mode=["graph"])
