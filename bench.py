@@ -163,12 +163,16 @@ def bench_small_configs(torch, stream, steps):
         api.prepare(lat, m)
         I = len(q) * len(p)
         rows = {}
+        from paper_1005_3609_amd import tune as tuner
+        tuned = tuner.lookup_tuned(lat, m, I, n) or {}
+        tuned = {k: v for k, v in tuned.items() if k not in ("mode", "ms")}
         for mode in ("plain", "graph"):
-            ws = api.alloc_workspace(api.workspace_bytes(lat, m, n, len(q), len(p), mode), None)
+            t = tuned if mode == "graph" else None
+            ws = api.alloc_workspace(api.workspace_bytes(lat, m, n, len(q), len(p), mode, t), None)
             res = torch.zeros((n, len(q), len(p)), dtype=torch.int32, device=ws.device)
 
             def run():
-                api.strip_async(lat, m, n, q, p, mode=mode, workspace=ws, out=res, stream=stream)
+                api.strip_async(lat, m, n, q, p, mode=mode, tuning=t, workspace=ws, out=res, stream=stream)
             run()
             ms = timed(torch, stream, run, steps)
             r = api.to_u32(res).astype("int64").reshape(n, len(q), len(p))
