@@ -139,12 +139,14 @@ def bench_sweep(torch, stream, tune, steps):
             for lat, m, n in w["strips"]]
     for jb in jobs:
         api.prepare(jb["lattice"], jb["m"])
-    t = {k: v for k, v in tune.items() if k != "streams"}
+    from paper_1005_3609_amd import tune as tuner
+    t = tuner.lookup_tuned_batch("square_sweep_2_14") or {k: v for k, v in tune.items() if k != "streams"}
+    t = {k: v for k, v in t.items() if k not in ("mode", "ms", "streams")}
     outs, ws = api.batch(jobs, tuning=t, stream=stream)
     ms = timed(torch, stream, lambda: api.batch(jobs, tuning=t, workspace=ws, outs=outs, stream=stream), steps)
     I = len(w["q_points"]) * len(w["primes"])
     upd = sum(updates_of(lat, m, n, I) for lat, m, n in w["strips"])
-    return {"workload": "square m=2..14, n=m+1, 640 instances, one graph of grouped launches",
+    return {"workload": f"square m=2..14, n=m+1, 640 instances, one graph of grouped launches, tuning {t}",
             "ms_per_step": ms, "value": upd / (ms / 1e3), "unit": "state-updates/s"}
 
 

@@ -201,6 +201,65 @@ def tune_series(lattice, m, n_max, d_max, primes, space=None, steps=3, path=DEFA
     return dict(best=best, table=table)
 
 
+BATCH_SPACE = dict(lanes_v=[1, 2], targets_per_wave=[4, 8], waves_per_block=[4, 8], xcd_order=[1], unroll=[4, 8],
+                   fuse=[1, 2])
+
+
+def _batch_key(name: str):
+    return f"{_arch()}|batch|{name}"
+
+
+def lookup_tuned_batch(name: str):
+    """Best known grouped-launch shape for a named job list, or None."""
+    for path in (DEFAULT_CACHE, PACKAGE_TABLE):
+        hit = load(path).get(_batch_key(name))
+        if hit:
+            return dict(hit["best"])
+    return None
+
+
+def tune_batch(name: str, jobs, space=None, steps=3, path=DEFAULT_CACHE, log=None) -> dict:
+    """Times one hipGraph of grouped launches over `jobs` (chromatic_batch)
+    for every launch shape of the space; every candidate's residues must
+    equal the first one's.  Cached under `name`."""
+    import torch
+    space = space or BATCH_SPACE
+    dev = torch.device("cuda", torch.cuda.current_device())
+    stream = torch.cuda.current_stream(dev)
+    table, ref, best = [], None, None
+    for v, t, w, x, u, f in itertools.product(space["lanes_v"], space["targets_per_wave"], space["waves_per_block"],
+                                              space["xcd_order"], space["unroll"], space["fuse"]):
+        cand = dict(lanes_v=v, targets_per_wave=t, waves_per_block=w, xcd_order=x, unroll=u, fuse=f)
+        outs, ws = api.batch(jobs, tuning=cand, stream=stream, device=dev)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            api.batch(jobs, tuning=cand, workspace=ws, outs=outs, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res = [api.to_u32(o) for o in outs]
+        if ref is None:
+            ref = res
+        ok = all(np.array_equal(a, b) for a, b in zip(res, ref))
+        table.append(dict(cand, ms=ms, identical=ok))
+        if log:
+            log(f"{cand} {ms:.3f} ms {'ok' if ok else 'MISMATCH'}")
+        if ok and (best is None or ms < best["ms"]):
+            best = dict(cand, mode="grouped", ms=ms)
+        del outs, ws
+    bad = [t for t in table if not t["identical"]]
+    if bad:
+        raise RuntimeError(f"tuning candidates disagree with the reference result: {bad}")
+    cache = load(path)
+    cache[_batch_key(name)] = dict(best=best, table=table)
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1)
+    return dict(best=best, table=table)
+
+
 def main():
     """python -m paper_1005_3609_amd.tune --workload square_14x15 [--cache PATH] [--series D]"""
     import argparse
@@ -212,12 +271,23 @@ def main():
     ap.add_argument("--cache", default=DEFAULT_CACHE)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--quick", action="store_true", help="a reduced search space")
+    ap.add_argument("--batch", action="store_true",
+                    help="tune the workload's strips as one batch of grouped launches (chromatic_batch)")
     ap.add_argument("--medium", action="store_true",
                     help="lanes_v 1-2, fused families 1-3, one or three chunk groups, graph mode (96 candidates)")
     ap.add_argument("--series", type=int, default=None, metavar="D",
                     help="tune the coefficient form to x^D for the workload's strips and primes instead")
     args = ap.parse_args()
     w = W.workload(args.workload)
+    if args.batch:
+        jobs = [dict(lattice=lat, m=m, n_max=n, q_points=w["q_points"], primes=w["primes"])
+                for lat, m, n in w["strips"]]
+        for jb in jobs:
+            api.prepare(jb["lattice"], jb["m"])
+        res = tune_batch(args.workload, jobs, steps=args.steps, path=args.cache,
+                         log=lambda s: print(s, file=sys.stderr, flush=True))
+        print(json.dumps(dict(workload=args.workload, batch=True, best=res["best"])), flush=True)
+        return
     if args.series is not None:
         for lat, m, n in w["strips"]:
             res = tune_series(lat, m, n, args.series, w["primes"], steps=args.steps, path=args.cache,
