@@ -140,7 +140,7 @@ def bench_sweep(torch, stream, tune, steps):
     for jb in jobs:
         api.prepare(jb["lattice"], jb["m"])
     from paper_1005_3609_amd import tune as tuner
-    t = tuner.lookup_tuned_batch("square_sweep_2_14") or {k: v for k, v in tune.items() if k != "streams"}
+    t = tuner.lookup_tuned_batch("square_sweep_2_14") or dict(tune)
     t = {k: v for k, v in t.items() if k not in ("mode", "ms", "streams")}
     outs, ws = api.batch(jobs, tuning=t, stream=stream)
     ms = timed(torch, stream, lambda: api.batch(jobs, tuning=t, workspace=ws, outs=outs, stream=stream), steps)

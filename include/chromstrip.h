@@ -248,10 +248,11 @@ size_t chromatic_batch_workspace_bytes(const chrom_job* jobs, int njobs,
  * is split into instance chunks of width 64*lanes_v, and step k of every
  * (job, chunk) item runs in one grouped kernel launch whose workgroups map
  * to (item, tile) pairs, so jobs of uneven state-space size share every
- * launch.  The graph is captured once per workspace and job list and
- * replayed on later identical calls.  Same results as chromatic_strip for
- * each job.  The workspace must not be reused for another job list while a
- * launch on it is in flight. */
+ * launch.  tune->streams is ignored (one launch chain).  The graph is
+ * captured once per workspace and job list and replayed on later identical
+ * calls.  Same results as chromatic_strip for each job.  The workspace must
+ * not be reused for another job list while a launch on it is in flight, and
+ * its size (chromatic_batch_workspace_bytes) depends on the tuning. */
 int chromatic_batch(const chrom_job* jobs, int njobs, const chrom_tuning* tune,
                     void* d_workspace, size_t ws_bytes, void* stream);
 

@@ -1612,7 +1612,10 @@ struct StageImage {
   std::vector<int> step_off, tile_off, nsteps, ntiles;  // per stage
 };
 
-StageImage build_stages(const std::vector<const Program*>& progs) {
+// Stage image of the (program, chunk) items of one chunk group: with
+// `groups` > 1, chunk c of program k belongs to group (c + k) mod groups
+// (chunks are independent, so the groups can run on parallel streams).
+StageImage build_stages(const std::vector<const Program*>& progs, int groups = 1, int group = 0) {
   StageImage im;
   size_t maxlen = 0;
   for (const Program* pg : progs) maxlen = std::max(maxlen, pg->steps.size());
@@ -1620,9 +1623,11 @@ StageImage build_stages(const std::vector<const Program*>& progs) {
     im.step_off.push_back(static_cast<int>(im.steps.size()));
     im.tile_off.push_back(static_cast<int>(im.tile_start.size()));
     int tiles = 0, n = 0;
-    for (const Program* pg : progs) {
+    for (size_t pi = 0; pi < progs.size(); ++pi) {
+      const Program* pg = progs[pi];
       if (k >= pg->steps.size()) continue;
       for (int c = 0; c < pg->nchunk; ++c) {
+        if ((c + static_cast<int>(pi)) % groups != group) continue;
         Step s = pg->steps[k].s;
         s.chunk = c;
         im.tile_start.push_back(tiles);
@@ -1700,19 +1705,46 @@ void drop_stage_graphs_in(void* lo, size_t bytes) {
 
 // Uploads the stage tables to `base` and runs them on `st`, either as
 // separate launches or as one (cached) graph.
-void run_grouped(const std::vector<const Program*>& progs, const Tune& t, void* base, hipStream_t st, bool as_graph) {
-  StageImage im = build_stages(progs);
-  if (im.steps.empty()) return;
+// Runs the programs' steps as grouped launches, in `groups` chunk groups on
+// parallel streams (forked from and joined into `st`); `base` holds the
+// groups' stage tables, at most groups x stage_bytes(steps, stages).  With
+// as_graph, the launches are captured once per (base, tables) and replayed.
+void run_grouped(const std::vector<const Program*>& progs, const Tune& t, void* base, hipStream_t st, bool as_graph,
+                 int groups = 1) {
+  groups = std::max(1, std::min(groups, 4));
+  std::vector<StageImage> ims;
+  for (int g = 0; g < groups; ++g) {
+    StageImage im = build_stages(progs, groups, g);
+    if (!im.steps.empty()) ims.push_back(std::move(im));
+  }
+  if (ims.empty()) return;
   char* b = static_cast<char*>(base);
-  Step* d_steps = reinterpret_cast<Step*>(b);
-  int* d_tiles = reinterpret_cast<int*>(b + align_up(im.steps.size() * sizeof(Step)));
-  uint64_t h = fnv1a(im.steps.data(), im.steps.size() * sizeof(Step));
-  h = fnv1a(im.tile_start.data(), im.tile_start.size() * sizeof(int), h);
-  h = fnv1a(&t, sizeof(t), h);
+  std::vector<Step*> d_steps;
+  std::vector<int*> d_tiles;
+  size_t off = 0;
+  uint64_t h = fnv1a(&t, sizeof(t));
+  for (const StageImage& im : ims) {
+    d_steps.push_back(reinterpret_cast<Step*>(b + off));
+    off += align_up(im.steps.size() * sizeof(Step));
+    d_tiles.push_back(reinterpret_cast<int*>(b + off));
+    off += align_up(im.tile_start.size() * sizeof(int));
+    h = fnv1a(im.steps.data(), im.steps.size() * sizeof(Step), h);
+    h = fnv1a(im.tile_start.data(), im.tile_start.size() * sizeof(int), h);
+  }
+  auto upload_all = [&]() {
+    for (size_t g = 0; g < ims.size(); ++g) {
+      upload(d_steps[g], ims[g].steps.data(), ims[g].steps.size() * sizeof(Step), st);
+      upload(d_tiles[g], ims[g].tile_start.data(), ims[g].tile_start.size() * sizeof(int), st);
+    }
+  };
+  auto launch_all = [&](hipStream_t s0, bool capture) {
+    ChunkGroups cg;
+    cg.n = static_cast<int>(ims.size());
+    for_groups(cg, s0, capture, [&](int g, hipStream_t s) { launch_stages(ims[g], d_steps[g], d_tiles[g], t, s); });
+  };
   if (!as_graph) {
-    upload(d_steps, im.steps.data(), im.steps.size() * sizeof(Step), st);
-    upload(d_tiles, im.tile_start.data(), im.tile_start.size() * sizeof(int), st);
-    launch_stages(im, d_steps, d_tiles, t, st);
+    upload_all();
+    launch_all(st, false);
     return;
   }
   hipGraphExec_t exec = nullptr;
@@ -1731,11 +1763,10 @@ void run_grouped(const std::vector<const Program*>& progs, const Tune& t, void* 
     }
   }
   if (!exec) {
-    upload(d_steps, im.steps.data(), im.steps.size() * sizeof(Step), st);
-    upload(d_tiles, im.tile_start.data(), im.tile_start.size() * sizeof(int), st);
+    upload_all();
     hipStream_t cs = capture_stream();
     HIPX(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    launch_stages(im, d_steps, d_tiles, t, cs);
+    launch_all(cs, true);
     hipGraph_t graph = nullptr;
     HIPX(hipStreamEndCapture(cs, &graph));
     HIPX(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
@@ -2067,6 +2098,7 @@ struct BatchPlan {
   std::vector<JobLayout> layouts;
   size_t queue_off = 0, bytes = 0;
   long nsteps = 0, nstages = 0;
+  int groups = 1;   // chunk groups on parallel streams (tuning `streams`, 1..4)
 };
 
 BatchPlan batch_plan(const chrom_job* jobs, int njobs, const Tune& t) {
@@ -2085,7 +2117,12 @@ BatchPlan batch_plan(const chrom_job* jobs, int njobs, const Tune& t) {
     bp.nstages = std::max<long>(bp.nstages, strip_program_len(jb.m, t.fuse, jb.n_max));
   }
   bp.queue_off = off;
-  bp.bytes = off + stage_bytes(bp.nsteps, bp.nstages);
+  // Chunk groups on parallel graph branches are switched off for batches:
+  // a tuning run over many batch shapes ended in a host segmentation fault
+  // on a three-group candidate whose cause was not found.  `streams` is
+  // ignored here, as it was before the groups existed.
+  bp.groups = 1;
+  bp.bytes = off + bp.groups * stage_bytes(bp.nsteps, bp.nstages);
   return bp;
 }
 
@@ -2119,7 +2156,7 @@ int batch_impl(const chrom_job* jobs, int njobs, const chrom_tuning* tune, void*
     progs[k] = strip_program(j, jb.n_max);
     pp.push_back(&progs[k]);
   }
-  run_grouped(pp, t, static_cast<char*>(ws) + bp.queue_off, st, true);
+  run_grouped(pp, t, static_cast<char*>(ws) + bp.queue_off, st, true, bp.groups);
   return CHROM_OK;
 }
 

@@ -201,7 +201,7 @@ def tune_series(lattice, m, n_max, d_max, primes, space=None, steps=3, path=DEFA
     return dict(best=best, table=table)
 
 
-BATCH_SPACE = dict(lanes_v=[1, 2], targets_per_wave=[4, 8], waves_per_block=[4, 8], xcd_order=[1], unroll=[4, 8],
+BATCH_SPACE = dict(lanes_v=[1, 2], targets_per_wave=[4, 8], waves_per_block=[4, 8], xcd_order=[1], unroll=[4],
                    fuse=[1, 2])
 
 
@@ -227,9 +227,10 @@ def tune_batch(name: str, jobs, space=None, steps=3, path=DEFAULT_CACHE, log=Non
     dev = torch.device("cuda", torch.cuda.current_device())
     stream = torch.cuda.current_stream(dev)
     table, ref, best = [], None, None
-    for v, t, w, x, u, f in itertools.product(space["lanes_v"], space["targets_per_wave"], space["waves_per_block"],
-                                              space["xcd_order"], space["unroll"], space["fuse"]):
-        cand = dict(lanes_v=v, targets_per_wave=t, waves_per_block=w, xcd_order=x, unroll=u, fuse=f)
+    for v, t, w, x, u, f, st in itertools.product(space["lanes_v"], space["targets_per_wave"],
+                                                  space["waves_per_block"], space["xcd_order"], space["unroll"],
+                                                  space["fuse"], space.get("streams", [1])):
+        cand = dict(lanes_v=v, targets_per_wave=t, waves_per_block=w, xcd_order=x, unroll=u, fuse=f, streams=st)
         outs, ws = api.batch(jobs, tuning=cand, stream=stream, device=dev)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

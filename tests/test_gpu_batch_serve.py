@@ -21,7 +21,15 @@ def _gpu():
     yield
 
 
-def test_mixed_batch_one_launch():
+GROUPS_OFF = ("chunk groups on parallel graph branches are switched off for chromatic_batch: a tuning run ended in "
+              "a host segmentation fault on a three-group batch candidate, cause not found")
+
+
+@pytest.mark.parametrize("tuning", [None, dict(lanes_v=1, fuse=2), dict(targets_per_wave=3),
+                                    pytest.param(dict(streams=2), marks=pytest.mark.skip(reason=GROUPS_OFF)),
+                                    pytest.param(dict(streams=3, lanes_v=1, fuse=2),
+                                                 marks=pytest.mark.skip(reason=GROUPS_OFF))])
+def test_mixed_batch_one_launch(tuning):
     import torch
     pool = W.seeded_primes(4, 321)
     jobs = [
@@ -31,8 +39,14 @@ def test_mixed_batch_one_launch():
         dict(lattice="triangular", m=2, n_max=6, q_points=list(range(0, 70)), primes=pool[:2]),
         dict(lattice="square", m=10, n_max=3, q_points=[2, 3, 4], primes=pool),
     ]
-    outs, ws = api.batch(jobs)
+    outs, ws = api.batch(jobs, tuning=tuning)
     torch.cuda.synchronize()
+    # a replay of the cached graph gives the same residues
+    first = [api.to_u32(o).copy() for o in outs]
+    api.batch(jobs, tuning=tuning, workspace=ws, outs=outs)
+    torch.cuda.synchronize()
+    for a, o in zip(first, outs):
+        np.testing.assert_array_equal(api.to_u32(o), a)
     for jb, o in zip(jobs, outs):
         want = OT.chromatic_grid(jb["lattice"], jb["m"], jb["n_max"], jb["q_points"], jb["primes"])
         np.testing.assert_array_equal(api.to_u32(o).astype(np.int64), want, err_msg=str(jb)[:80])
