@@ -1623,6 +1623,10 @@ StageImage build_stages(const std::vector<const Program*>& progs, int groups = 1
     im.step_off.push_back(static_cast<int>(im.steps.size()));
     im.tile_off.push_back(static_cast<int>(im.tile_start.size()));
     int tiles = 0, n = 0;
+    // Items with the most tiles first: workgroups are dispatched in index
+    // order, so the largest items start first and the small ones fill the
+    // launch's tail instead of forming it.
+    std::vector<Step> items;
     for (size_t pi = 0; pi < progs.size(); ++pi) {
       const Program* pg = progs[pi];
       if (k >= pg->steps.size()) continue;
@@ -1630,11 +1634,15 @@ StageImage build_stages(const std::vector<const Program*>& progs, int groups = 1
         if ((c + static_cast<int>(pi)) % groups != group) continue;
         Step s = pg->steps[k].s;
         s.chunk = c;
-        im.tile_start.push_back(tiles);
-        tiles += s.ntiles;
-        im.steps.push_back(s);
-        ++n;
+        items.push_back(s);
       }
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Step& a, const Step& b) { return a.ntiles > b.ntiles; });
+    for (const Step& s : items) {
+      im.tile_start.push_back(tiles);
+      tiles += s.ntiles;
+      im.steps.push_back(s);
+      ++n;
     }
     im.tile_start.push_back(tiles);
     im.nsteps.push_back(n);
