@@ -171,3 +171,18 @@ def test_device_built_maps_match_host_built(monkeypatch, lat, m, d):
     monkeypatch.delenv("CHROMSTRIP_HOST_MAPS")
     np.testing.assert_array_equal(dev, host_built)
     np.testing.assert_array_equal(dev[:, :, 0], 1)
+
+
+@pytest.mark.parametrize("lat,m,n", [(SQ, 1, 4), (SQ, 4, 6), (TRI, 3, 5), (SQ, 6, 7)])
+def test_exact_chromatic_polynomials(lat, m, n):
+    # the whole integer polynomial from the coefficient form and CRT, no
+    # interpolation, against the oracle's exact polynomials
+    from paper_1005_3609_amd import polynomial as PL
+    polys, used = PL.chromatic_polynomials(lat, m, n)
+    want = OT.chromatic_exact(lat, m, n)
+    for r in range(n):
+        got = list(polys[r])
+        while len(got) > 1 and got[-1] == 0:
+            got.pop()
+        assert got == want[r], (lat, m, r + 1)
+    assert used >= 2

@@ -72,3 +72,19 @@ def test_device_expansion_reproduces_host_maps(lat, m):
     # factors too
     api.check_expansion(lat, m, normalised=True)
     api.check_expansion(lat, m, normalised=False)
+
+
+def test_exact_polynomials_host_side(monkeypatch):
+    # polynomial.chromatic_polynomials with the strips run by the map
+    # interpreter: the prime loop, the CRT and the x^k -> q^{|V|-k} reversal
+    from paper_1005_3609_amd import polynomial as PL
+
+    def cpu_series(lat, m, n, d, primes, mode="graph", tuning=None):
+        return np.stack([_run_series(lat, m, n, d, int(p)) for p in primes], axis=1)
+    monkeypatch.setattr(PL.api, "series", cpu_series)
+    polys, used = PL.chromatic_polynomials(SQ, 3, 4, batch=1)
+    want = OT.chromatic_exact(SQ, 3, 4)
+    assert [p[: len(w)] for p, w in zip(polys, want)] == want and all(not any(p[len(w):]) for p, w in zip(polys, want))
+    assert used >= 2
+    with pytest.raises(ValueError):
+        PL.chromatic_polynomials(SQ, 16, 17)
