@@ -1,10 +1,20 @@
 // Runtime and C ABI of the chromatic-strip library.
 //
-// The sweep computes P of the m x r rectangles, r = 1..n_max, as
-// Z_r = <w, x_r>, x_1 = e_0, x_{r+1} = T_m ... T_1 x_r, and
+// Evaluation form: the sweep computes P of the m x r rectangles, r =
+// 1..n_max, as Z_r = <w, x_r>, x_1 = e_0, x_{r+1} = T_m ... T_1 x_r, and
 // w = (T_1^last)^T ... (T_m^last)^T e_0 (arXiv 1005.3609, eqs. Z_from_T,
 // T_sq_decomp, T_last).  w is built once per instance set on the device and
 // kept in Montgomery form so the read-out is a plain dot product.
+//
+// Coefficient form (eq. Z_modified, Sec. 3.5): the states carry truncated
+// polynomials in x = 1/q mod p, and T_last is applied to every row's state
+// (a polynomial read-out vector would need a convolution per state).  Its
+// factor maps are built on the device (devexpand.hpp, the k_dx_* kernels).
+//
+// Sections: device copies of the maps and the device map build; constants
+// and job layouts; step programs (setup, rows, read-out); launches, chunk
+// groups on parallel streams and hipGraph row replay; grouped launches for
+// batches and the server; the plain per-instance path; the C ABI.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
