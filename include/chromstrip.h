@@ -81,7 +81,8 @@ enum {
  * coefficient form).  Zero fields take the library's defaults.  Every
  * choice gives bit-identical results. */
 typedef struct chrom_tuning {
-  int lanes_v;          /* instances per lane: 1, 2 or 4 (chunk width W = 64 * lanes_v) */
+  int lanes_v;          /* instances per lane: 1, 2 or 4 (chunk width W = 64 * lanes_v);
+                           the coefficient form also takes 8, with unroll 4 */
   int targets_per_wave; /* consecutive target states handled by one wavefront, 1..63 */
   int waves_per_block;  /* wavefronts per workgroup: 1, 2, 4 or 8 */
   int xcd_order;        /* 0 = default, 1 = hardware round-robin, 2 = contiguous tile range per XCD,
@@ -133,7 +134,10 @@ size_t chromatic_workspace_bytes(int lattice, int m, int n_max, int nq, int np,
  * ------------------------------------------------------------------------ */
 
 /* Workspace bytes for chromatic_series_async (mode BATCHED or GRAPH).
- * d_max must be below 64 * lanes_v.  Returns 0 on bad arguments. */
+ * d_max must be below 64 * lanes_v; lanes_v 0 (or tune NULL) takes the
+ * smallest of 1, 2, 4, 8 that holds d_max + 1 coefficients, as do
+ * chromatic_series_async and chromatic_series.  d_max is at most 511.
+ * Returns 0 on bad arguments. */
 size_t chromatic_series_workspace_bytes(int lattice, int m, int n_max, int np, int d_max,
                                         int mode, const chrom_tuning* tune);
 
@@ -151,8 +155,7 @@ int chromatic_series_async(int lattice, int m, int n_max, int d_max,
                            void* stream, uint32_t* d_out);
 
 /* Same, synchronous, host output [n_max][np][d_max+1], internal
- * allocation; lanes_v defaults to the smallest of 1, 2, 4 that holds
- * d_max + 1 coefficients. */
+ * allocation. */
 int chromatic_series(int lattice, int m, int n_max, int d_max,
                      const uint32_t* primes, int np, int mode,
                      const chrom_tuning* tune, uint32_t* out);

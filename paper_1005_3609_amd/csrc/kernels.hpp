@@ -26,8 +26,11 @@ constexpr int kCodes = 64;
 // ---------------------------------------------------------------------------
 // Vector helpers
 // ---------------------------------------------------------------------------
+// V = 1, 2, 4 or 8 consecutive words per lane (8: the coefficient form's
+// widest rows, two 16-byte accesses).
 template <int V>
 __device__ __forceinline__ void load_v(const uint32_t* ptr, uint32_t (&x)[V]) {
+  static_assert(V == 1 || V == 2 || V == 4 || V == 8, "V must be 1, 2, 4 or 8");
   if constexpr (V == 1) {
     x[0] = *ptr;
   } else if constexpr (V == 2) {
@@ -35,22 +38,28 @@ __device__ __forceinline__ void load_v(const uint32_t* ptr, uint32_t (&x)[V]) {
     x[0] = t.x;
     x[1] = t.y;
   } else {
-    uint4 t = *reinterpret_cast<const uint4*>(ptr);
-    x[0] = t.x;
-    x[1] = t.y;
-    x[2] = t.z;
-    x[3] = t.w;
+#pragma unroll
+    for (int h = 0; h < V / 4; ++h) {
+      uint4 t = *reinterpret_cast<const uint4*>(ptr + 4 * h);
+      x[4 * h] = t.x;
+      x[4 * h + 1] = t.y;
+      x[4 * h + 2] = t.z;
+      x[4 * h + 3] = t.w;
+    }
   }
 }
 
 template <int V>
 __device__ __forceinline__ void store_v(uint32_t* ptr, const uint32_t (&x)[V]) {
+  static_assert(V == 1 || V == 2 || V == 4 || V == 8, "V must be 1, 2, 4 or 8");
   if constexpr (V == 1) {
     *ptr = x[0];
   } else if constexpr (V == 2) {
     *reinterpret_cast<uint2*>(ptr) = make_uint2(x[0], x[1]);
   } else {
-    *reinterpret_cast<uint4*>(ptr) = make_uint4(x[0], x[1], x[2], x[3]);
+#pragma unroll
+    for (int h = 0; h < V / 4; ++h)
+      *reinterpret_cast<uint4*>(ptr + 4 * h) = make_uint4(x[4 * h], x[4 * h + 1], x[4 * h + 2], x[4 * h + 3]);
   }
 }
 

@@ -933,7 +933,9 @@ struct Tune {
   int V = 2, rpw = 8, wpb = 4, xcd = 0, U = 4, streams = 1, fuse = 1, stage = 0;
 };
 
-Tune resolve(const chrom_tuning* t) {
+// lanes_v 8 (512 coefficient slots per row) exists for the coefficient form
+// only: `series` admits it.
+Tune resolve(const chrom_tuning* t, bool series = false) {
   Tune r;
   if (!t) return r;
   if (t->lanes_v) r.V = t->lanes_v;
@@ -949,7 +951,11 @@ Tune resolve(const chrom_tuning* t) {
   if (r.fuse < 1 || r.fuse > kMaxFuse) throw ArgError("fuse must be in 1..3");
   if (t->stage < 0 || t->stage > 1) throw ArgError("stage must be 0 or 1");
   r.stage = t->stage;
-  if (r.V != 1 && r.V != 2 && r.V != 4) throw ArgError("lanes_v must be 1, 2 or 4");
+  if (series && r.V == 8) {
+    if (r.U != 4) throw ArgError("lanes_v 8 runs with unroll 4");
+  } else if (r.V != 1 && r.V != 2 && r.V != 4) {
+    throw ArgError(series ? "lanes_v must be 1, 2, 4 or 8" : "lanes_v must be 1, 2 or 4");
+  }
   if (r.rpw < 1 || r.rpw > 63) throw ArgError("targets_per_wave must be in 1..63");
   if (r.wpb != 1 && r.wpb != 2 && r.wpb != 4 && r.wpb != 8) throw ArgError("waves_per_block must be 1, 2, 4 or 8");
   return r;
@@ -1441,10 +1447,40 @@ void launch_step_vu(const Step& s, int c0, int nch, int wpb, int xcd, hipStream_
   HIPX(hipGetLastError());
 }
 
+// lanes_v 8: the coefficient form's steps only (gathers, fills, emits).
+void launch_step_cf8(const Step& s, int c0, int nch, int wpb, int xcd, hipStream_t st, const int* row_ctr,
+                     long row_stride) {
+  dim3 grid(s.ntiles, nch), block(64 * wpb);
+  switch (s.op) {
+    case kOpGather:
+      if (s.cf == 2 && s.general)
+        hipLaunchKernelGGL((k_gather<8, 4, true, true, true>), grid, block, 0, st, s.u.g, xcd, c0);
+      else if (s.cf == 2)
+        hipLaunchKernelGGL((k_gather<8, 4, false, true, true>), grid, block, 0, st, s.u.g, xcd, c0);
+      else if (s.cf && s.general)
+        hipLaunchKernelGGL((k_gather<8, 4, true, true>), grid, block, 0, st, s.u.g, xcd, c0);
+      else if (s.cf)
+        hipLaunchKernelGGL((k_gather<8, 4, false, true>), grid, block, 0, st, s.u.g, xcd, c0);
+      else
+        throw std::runtime_error("lanes_v 8 is for the coefficient form only");
+      break;
+    case kOpEmit:
+      if (row_ctr)
+        hipLaunchKernelGGL(k_emit_counted, dim3(nch), dim3(256), 0, st, s.u.e, c0, row_ctr, row_stride);
+      else
+        hipLaunchKernelGGL(k_emit, dim3(nch), dim3(256), 0, st, s.u.e, c0);
+      break;
+    case kOpFill: hipLaunchKernelGGL(k_fill<8>, grid, block, 0, st, s.u.f, c0); break;
+    default: throw std::runtime_error("lanes_v 8 is for the coefficient form only");
+  }
+  HIPX(hipGetLastError());
+}
+
 void launch_step(const Step& s, const Tune& t, int c0, int nch, hipStream_t st, const int* row_ctr = nullptr,
                  long row_stride = 0) {
   const int key = t.V * 10 + t.U;
   switch (key) {
+    case 84: launch_step_cf8(s, c0, nch, t.wpb, t.xcd, st, row_ctr, row_stride); break;
     case 14: launch_step_vu<1, 4>(s, c0, nch, t.wpb, t.xcd, st, row_ctr, row_stride); break;
     case 18: launch_step_vu<1, 8>(s, c0, nch, t.wpb, t.xcd, st, row_ctr, row_stride); break;
     case 24: launch_step_vu<2, 4>(s, c0, nch, t.wpb, t.xcd, st, row_ctr, row_stride); break;
@@ -1985,8 +2021,13 @@ int64_t readout_l_max(int lattice, int m) {
   return std::max<int64_t>(1, ncnnn_count(m - 1));
 }
 
-Tune resolve_series(const chrom_tuning* tune) {
-  Tune t = resolve(tune);
+// lanes_v 0 (or no tuning): the smallest of 1, 2, 4, 8 whose 64 lanes_v
+// slots hold x^0 .. x^d_max.
+Tune resolve_series(const chrom_tuning* tune, int d_max) {
+  chrom_tuning tt{};
+  if (tune) tt = *tune;
+  if (!tt.lanes_v) tt.lanes_v = d_max < 64 ? 1 : (d_max < 128 ? 2 : (d_max < 256 ? 4 : 8));
+  Tune t = resolve(&tt, true);
   if (t.fuse != 1) throw ArgError("the coefficient form runs single factors only (fuse 1)");
   if (t.stage) throw ArgError("the coefficient form does not stage tiles");
   return t;
@@ -2009,7 +2050,7 @@ int series_async_impl(int lattice, int m, int n_max, int d_max, const uint32_t* 
   if (mode != CHROM_MODE_BATCHED && mode != CHROM_MODE_GRAPH)
     throw ArgError("the coefficient form runs in batched or graph mode");
   check_primes(p, np);
-  Tune t = resolve_series(tune);
+  Tune t = resolve_series(tune, d_max);
   if (n_max == 0) return CHROM_OK;
   if (!ws || !d_out) throw ArgError("null workspace or output");
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) throw ArgError("workspace must be 256-byte aligned");
@@ -2058,16 +2099,13 @@ int series_sync_impl(int lattice, int m, int n_max, int d_max, const uint32_t* p
   check_primes(p, np);
   if (n_max == 0) return CHROM_OK;
   if (!out) throw ArgError("null output");
-  chrom_tuning tt{};
-  if (tune) tt = *tune;
-  if (!tt.lanes_v) tt.lanes_v = d_max < 64 ? 1 : (d_max < 128 ? 2 : 4);
-  const Tune t = resolve_series(&tt);
+  const Tune t = resolve_series(tune, d_max);
   const size_t wsb = series_workspace_bytes(lattice, m, np, d_max, t);
   DevBuf ws(wsb);
   const size_t outb = static_cast<size_t>(n_max) * np * (d_max + 1) * 4;
   DevBuf dout(outb);
   HIPX(hipMemset(dout.p, 0, outb));
-  int rc = series_async_impl(lattice, m, n_max, d_max, p, np, mode, &tt, ws.p, wsb, nullptr,
+  int rc = series_async_impl(lattice, m, n_max, d_max, p, np, mode, tune, ws.p, wsb, nullptr,
                              static_cast<uint32_t*>(dout.p));
   if (rc != CHROM_OK) return rc;
   HIPX(hipDeviceSynchronize());
@@ -2314,7 +2352,7 @@ size_t chromatic_series_workspace_bytes(int lattice, int m, int n_max, int np, i
     if (np < 1) throw ArgError("need np >= 1");
     if (mode != CHROM_MODE_BATCHED && mode != CHROM_MODE_GRAPH)
       throw ArgError("the coefficient form runs in batched or graph mode");
-    r = series_workspace_bytes(lattice, m, np, d_max, resolve_series(tune));
+    r = series_workspace_bytes(lattice, m, np, d_max, resolve_series(tune, d_max));
     return CHROM_OK;
   });
   return rc == CHROM_OK ? r : 0;

@@ -11,19 +11,78 @@ x^k in P~.  Primes are added until the CRT lift stops changing (Sec. 3.5).
 """
 from __future__ import annotations
 
+from math import comb
+
 from . import api, host
 from . import workloads as W
 
 
-def chromatic_polynomials(lattice, m: int, n: int, primes=None, batch: int = 4, max_primes: int = 64):
+def graph_counts(lattice, m: int, n: int):
+    """(|V|, |E|, triangles, 4-cycles) of the m x n rectangle: the square
+    lattice's edges plus, on the triangular lattice, one diagonal per face
+    (Sec. 3.3).  Every 4-cycle of the square lattice is a face; the
+    triangular lattice's are not counted (None)."""
+    faces = max(m - 1, 0) * max(n - 1, 0)
+    e = m * (n - 1) + n * (m - 1)
+    if lattice == "square":
+        return m * n, e, 0, faces
+    return m * n, e + faces, 2 * faces, None
+
+
+def check(lattice, m: int, n: int, c) -> list:
+    """Properties every chromatic polynomial P = sum c_j q^j of the m x n
+    rectangle has; returns the ones that fail (empty: all hold).
+
+    * degree |V|, monic; c_{|V|-1} = -|E|; c_{|V|-2} = C(|E|, 2) - (triangles);
+      on the square lattice (no triangles, every 4-cycle a face, no two faces
+      sharing two edges) c_{|V|-3} = -(C(|E|, 3) - faces) and c_{|V|-4} =
+      C(|E|, 4) - (faces)(|E| - 3) -- Whitney's broken-circuit expansion;
+    * P(0) = P(1) = 0 (at least one edge), and for a connected graph the
+      coefficients of q^1..q^|V| are non-zero with alternating signs;
+    * the absolute values |c_1|..|c_|V|| are log-concave (Huh);
+    * square: P(2) = 2 (connected, bipartite); triangular with m, n >= 2:
+      P(2) = 0 and P(3) = 6 (the faces' triangles force a 3-colouring)."""
+    V, E, T, F = graph_counts(lattice, m, n)
+    bad = []
+    c = list(c) + [0] * max(0, V + 1 - len(c))
+    if any(c[V + 1:]) or c[V] != 1:
+        bad.append("not monic of degree |V|")
+    if V >= 2 and c[V - 1] != -E:
+        bad.append("c_{|V|-1} != -|E|")
+    if V >= 3 and c[V - 2] != comb(E, 2) - T:
+        bad.append("c_{|V|-2} != C(|E|,2) - triangles")
+    if lattice == "square" and V >= 4 and c[V - 3] != -(comb(E, 3) - F):
+        bad.append("c_{|V|-3} != -(C(|E|,3) - faces)")
+    if lattice == "square" and V >= 5 and c[V - 4] != comb(E, 4) - F * (E - 3):
+        bad.append("c_{|V|-4} != C(|E|,4) - faces (|E| - 3)")
+    ev = lambda q: sum(cj * q ** j for j, cj in enumerate(c))
+    if c[0] != 0:
+        bad.append("P(0) != 0")
+    if E and ev(1) != 0:
+        bad.append("P(1) != 0")
+    if any(c[j] == 0 or (c[j] > 0) != ((V - j) % 2 == 0) for j in range(1, V + 1)):
+        bad.append("coefficients of q^1..q^|V| not alternating and non-zero")
+    a = [abs(x) for x in c[1:V + 1]]
+    if any(a[j] * a[j] < a[j - 1] * a[j + 1] for j in range(1, len(a) - 1)):
+        bad.append("|c_j| not log-concave")
+    if lattice == "square" and V >= 2 and ev(2) != 2:
+        bad.append("P(2) != 2")
+    if lattice == "triangular" and m >= 2 and n >= 2 and (ev(2) != 0 or ev(3) != 6):
+        bad.append("P(2) != 0 or P(3) != 6")
+    return bad
+
+
+def chromatic_polynomials(lattice, m: int, n: int, primes=None, batch: int = 4, max_primes: int = 64,
+                          log=None):
     """[P_{m x r}(q) for r = 1..n], each a list of integers c_0..c_{|V|}
-    with P = sum c_j q^j.  Needs m n <= 256 (coefficients x^0..x^{mn-1} in
-    at most 4 lanes per wavefront lane).  Primes are drawn in groups of
+    with P = sum c_j q^j.  Needs m n <= 512 (coefficients x^0..x^{mn-1} in
+    at most 8 slots per wavefront lane).  Primes are drawn in groups of
     `batch` from `primes` (default: seeded 31-bit primes) until every row's
-    lift is stable; returns (polynomials, primes used)."""
+    lift is stable; returns (polynomials, primes used).  `log(text)`, if
+    given, hears of every finished prime group."""
     V = m * n
-    if V > 256:
-        raise ValueError("m * n must be at most 256 (coefficient slots per state row)")
+    if V > 512:
+        raise ValueError("m * n must be at most 512 (coefficient slots per state row)")
     d = V - 1
     pool = list(primes) if primes is not None else W.seeded_primes(max_primes, 1005)
     residues = []            # [prime][row][coefficient]
@@ -36,6 +95,8 @@ def chromatic_polynomials(lattice, m: int, n: int, primes=None, batch: int = 4, 
         for b in range(len(group)):
             residues.append([[int(v) for v in res[r, b]] for r in range(n)])
         used += group
+        if log:
+            log(f"{lattice} {m}x{n}: {len(used)} primes done")
         # stable: the lift over every prime so far equals the lift without
         # the last one, for every row
         out, stable = [], len(used) > 1
@@ -61,18 +122,45 @@ def main(argv=None) -> int:
     ap.add_argument("lattice", choices=["square", "triangular"])
     ap.add_argument("m", type=int)
     ap.add_argument("n", type=int)
+    ap.add_argument("--batch", type=int, default=4, help="primes per coefficient-form call")
+    ap.add_argument("--max-primes", type=int, default=64)
+    ap.add_argument("--transposed", type=int, default=0, metavar="K",
+                    help="also compute P of the r x m rectangles, r = 1..K, by strips of width r, and compare "
+                         "(P is symmetric under transposition)")
+    ap.add_argument("--out", help="write the polynomials here instead of standard output")
     a = ap.parse_args(argv)
+    import time
     import torch
     if not torch.cuda.is_available():
         print("a GPU is required", file=sys.stderr)
         return 2
     torch.cuda.set_device(0)
-    polys, used = chromatic_polynomials(a.lattice, a.m, a.n)
+    t0 = time.time()
+    say = lambda text: print(f"[{time.time() - t0:7.1f} s] {text}", file=sys.stderr, flush=True)
+    polys, used = chromatic_polynomials(a.lattice, a.m, a.n, batch=a.batch, max_primes=a.max_primes, log=say)
+    say(f"{a.lattice} {a.m}x1..{a.n}: {used} primes")
+    rc = 0
+    for r, p in enumerate(polys, start=1):
+        bad = check(a.lattice, a.m, r, p)
+        if bad:
+            rc = 1
+            say(f"{a.m}x{r}: FAILED " + "; ".join(bad))
+    say(f"properties of all {a.n} polynomials: " + ("FAILED" if rc else "hold"))
+    for r in range(1, min(a.transposed, a.n) + 1):
+        tp, _ = chromatic_polynomials(a.lattice, r, a.m, batch=max(a.batch, 4), max_primes=a.max_primes)
+        same = tp[-1] == polys[r - 1]
+        rc = rc or (0 if same else 1)
+        say(f"{a.m}x{r} against {r}x{a.m} by width-{r} strips: " + ("equal" if same else "DIFFERENT"))
+    lines = []
     for r, p in enumerate(polys, start=1):
         terms = " + ".join(f"({c})*q^{j}" for j, c in enumerate(p) if c)
-        print(f"{a.lattice} {a.m}x{r}: {terms}")
-    print(f"{used} primes", file=sys.stderr)
-    return 0
+        lines.append(f"{a.lattice} {a.m}x{r}: {terms}")
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write("\n".join(lines) + "\n")
+    else:
+        print("\n".join(lines))
+    return rc
 
 
 if __name__ == "__main__":

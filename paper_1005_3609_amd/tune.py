@@ -144,7 +144,7 @@ def _series_key(lattice, m, n_primes, d_max, n_max):
 
 def series_lanes_v(d_max: int) -> int:
     """Smallest chunk width (64 lanes_v coefficients) that holds x^0..x^d_max."""
-    return 1 if d_max < 64 else (2 if d_max < 128 else 4)
+    return 1 if d_max < 64 else (2 if d_max < 128 else (4 if d_max < 256 else 8))
 
 
 def lookup_tuned_series(lattice, m, n_primes, d_max, n_max):

@@ -56,7 +56,7 @@ def test_tuner_candidates_respect_the_rules():
 
 
 def test_series_lanes_v():
-    assert [tune.series_lanes_v(d) for d in (0, 63, 64, 127, 128, 255)] == [1, 1, 2, 2, 4, 4]
+    assert [tune.series_lanes_v(d) for d in (0, 63, 64, 127, 128, 255, 256, 511)] == [1, 1, 2, 2, 4, 4, 8, 8]
 
 
 def test_tuned_table_lookups(monkeypatch, tmp_path):

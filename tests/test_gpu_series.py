@@ -96,7 +96,7 @@ def test_series_edge_cases():
     assert api.series(TRI, 4, 0, 10, [P31]).shape == (0, 1, 11)
     # the largest truncation of each chunk width, extreme primes (3, 5 and
     # 2^31 - 19), one row, one prime
-    for d, lanes_v in ((63, 1), (127, 2), (255, 4)):
+    for d, lanes_v in ((63, 1), (127, 2), (255, 4), (511, 8)):
         primes = [3, 5, 2147483629]
         want = _oracle(TRI, 3, 6, d, primes)
         for mode in ("batched", "graph"):
@@ -104,6 +104,35 @@ def test_series_edge_cases():
             np.testing.assert_array_equal(got, want, err_msg=f"d={d} {mode}")
     want = _oracle(SQ, 6, 1, 40, [2147483629])
     np.testing.assert_array_equal(api.series(SQ, 6, 1, 40, [2147483629]).astype(np.int64), want)
+
+
+@pytest.mark.parametrize("lat,m,n", [(SQ, 5, 6), (TRI, 4, 7), (SQ, 4, 66)])
+def test_series_lanes_v8_matches_oracle(lat, m, n):
+    # 512 coefficient slots per row (two 16-byte accesses per lane); 4 x 66
+    # has 264 vertices, so coefficients past x^255 are non-zero
+    primes = [P31, 998244353, 3]
+    for d in (255, 300, 511):
+        want = _oracle(lat, m, n, d, primes)
+        for mode, tune in (("graph", None), ("batched", dict(lanes_v=8)),
+                           ("graph", dict(lanes_v=8, targets_per_wave=3, waves_per_block=2, xcd_order=2)),
+                           ("batched", dict(lanes_v=8, targets_per_wave=33, waves_per_block=8, streams=2))):
+            if tune is None and d < 256:
+                continue
+            got = api.series(lat, m, n, d, primes, mode=mode, tuning=tune).astype(np.int64)
+            np.testing.assert_array_equal(got, want, err_msg=f"{lat} m={m} d={d} {mode} {tune}")
+
+
+def test_series_lanes_v8_identical_to_narrower(monkeypatch):
+    # the same truncation through every chunk width, 32-bit and 64-bit row
+    # addressing
+    primes = W.seeded_primes(2, 15)
+    ref = api.series(SQ, 9, 7, 60, primes, mode="graph", tuning=dict(lanes_v=1))
+    for tune in (dict(lanes_v=2), dict(lanes_v=4), dict(lanes_v=8)):
+        np.testing.assert_array_equal(api.series(SQ, 9, 7, 60, primes, mode="graph", tuning=tune), ref)
+    monkeypatch.setenv("CHROMSTRIP_WIDE_ROWS", "1")
+    for mode in ("graph", "batched"):
+        got = api.series(SQ, 9, 7, 60, primes, mode=mode, tuning=dict(lanes_v=8))
+        np.testing.assert_array_equal(got, ref, err_msg=f"wide rows {mode}")
 
 
 def test_prepare_series_then_capture_free_call():
@@ -140,6 +169,14 @@ def test_series_bad_arguments():
         api.series(SQ, 4, 3, 10, [P31], mode="grouped")
     with pytest.raises(api.ChromError):
         api.series(SQ, 4, 3, 10, [4])
+    with pytest.raises(api.ChromError):
+        api.series(SQ, 4, 3, 512, [P31])                                 # past 64 * 8 slots
+    with pytest.raises(api.ChromError):
+        api.series(SQ, 4, 3, 300, [P31], tuning=dict(lanes_v=8, unroll=8))
+    with pytest.raises(api.ChromError):
+        api.series(SQ, 4, 3, 300, [P31], tuning=dict(lanes_v=16))
+    with pytest.raises(api.ChromError):                                   # evaluation form: at most 4
+        api.strip(SQ, 4, 3, [3, 4], [P31], mode="batched", tuning=dict(lanes_v=8))
 
 
 def test_series_wide_row_addressing_identical(monkeypatch):
@@ -173,7 +210,7 @@ def test_device_built_maps_match_host_built(monkeypatch, lat, m, d):
     np.testing.assert_array_equal(dev[:, :, 0], 1)
 
 
-@pytest.mark.parametrize("lat,m,n", [(SQ, 1, 4), (SQ, 4, 6), (TRI, 3, 5), (SQ, 6, 7)])
+@pytest.mark.parametrize("lat,m,n", [(SQ, 1, 4), (SQ, 4, 6), (TRI, 3, 5), (SQ, 6, 7), (SQ, 6, 43), (TRI, 7, 73)])
 def test_exact_chromatic_polynomials(lat, m, n):
     # the whole integer polynomial from the coefficient form and CRT, no
     # interpolation, against the oracle's exact polynomials
