@@ -87,4 +87,4 @@ def test_exact_polynomials_host_side(monkeypatch):
     assert [p[: len(w)] for p, w in zip(polys, want)] == want and all(not any(p[len(w):]) for p, w in zip(polys, want))
     assert used >= 2
     with pytest.raises(ValueError):
-        PL.chromatic_polynomials(SQ, 16, 17)
+        PL.chromatic_polynomials(SQ, 23, 23)                      # |V| = 529 > 512 slots
