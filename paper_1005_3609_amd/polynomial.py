@@ -13,7 +13,7 @@ from __future__ import annotations
 
 from math import comb
 
-from . import api, host
+from . import api, host, tune
 from . import workloads as W
 
 
@@ -84,6 +84,8 @@ def chromatic_polynomials(lattice, m: int, n: int, primes=None, batch: int = 4, 
     if V > 512:
         raise ValueError("m * n must be at most 512 (coefficient slots per state row)")
     d = V - 1
+    lanes_v = tune.series_lanes_v(d)
+    shape = dict(tune.SERIES_WIDE_DEFAULT if lanes_v == 8 else tune.SERIES_DEFAULT, lanes_v=lanes_v)
     pool = list(primes) if primes is not None else W.seeded_primes(max_primes, 1005)
     residues = []            # [prime][row][coefficient]
     used = []
@@ -91,7 +93,7 @@ def chromatic_polynomials(lattice, m: int, n: int, primes=None, batch: int = 4, 
         group = pool[len(used):len(used) + batch]
         if not group:
             raise RuntimeError("the lift did not stabilise with the primes given")
-        res = api.series(lattice, m, n, d, group, mode="graph")          # [n][len(group)][d + 1]
+        res = api.series(lattice, m, n, d, group, mode="graph", tuning=shape)   # [n][len(group)][d + 1]
         for b in range(len(group)):
             residues.append([[int(v) for v in res[r, b]] for r in range(n)])
         used += group
