@@ -192,6 +192,37 @@ def test_square_sweep_one_launch():
 
 
 # ---------------------------------------------------------------------------
+# Square 14 x 15, 640 instances, in the configurations the benchmark times:
+# graph row replay with the tuned launch shape (its step) and batched launches
+# on one stream (its roofline leg), then the roofline's bare factor launches
+# ---------------------------------------------------------------------------
+def test_square_14x15_benchmark_configurations():
+    import torch
+    from paper_1005_3609_amd import tune as tuner
+    w = W.workload("square_14x15")
+    q, p = w["q_points"], w["primes"]
+    g = _golden("oracle_square_14x15.json")
+    tune = dict(tuner.lookup_tuned("square", 14, 640, 15) or {})
+    tune.pop("mode", None)
+    tune.pop("ms", None)
+    want = np.array(g["z"], dtype=np.int64)
+    for mode, t in (("graph", tune), ("batched", dict(tune, streams=1))):
+        out, ws = api.strip_async("square", 14, 15, q, p, mode=mode, tuning=t)
+        torch.cuda.synchronize()
+        res = api.to_u32(out).astype(np.int64)
+        np.testing.assert_array_equal(_sampled(res, g), want, err_msg=f"{mode} {t}")
+        z = res.reshape(15, 80, 8)
+        assert (z[:, 0, :] == 0).all() and (z[:, 1, :] == 2).all()
+        if mode == "batched":
+            # the bare factor launches leave the strip's output untouched
+            stream = torch.cuda.current_stream()
+            api.factor_launches("square", 14, q, p, 2, ws, t, stream)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(api.to_u32(out).astype(np.int64), res)
+        del ws
+
+
+# ---------------------------------------------------------------------------
 # Square 18 x 19 (the large-state run), 640 instances
 # ---------------------------------------------------------------------------
 def test_square_18x19_against_transposed_oracle():
