@@ -234,6 +234,52 @@ def bench_series(torch, stream, tune, steps):
             "ms_per_step": ms, "value": updates_of(lat, m, n, lanes) / (ms / 1e3), "unit": "state-updates/s"}
 
 
+def copy_calibration(torch, stream, dev, mib):
+    """A plain device copy of `mib` MiB, three times: the HBM counters of a
+    kernel of known traffic, to scale FETCH_SIZE and WRITE_SIZE by."""
+    nel = mib * (1 << 20) // 4
+    src = torch.randint(0, 1 << 30, (nel,), dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    c_ms = timed(torch, stream, lambda: dst.copy_(src), 3)
+    log(f"copied {mib} MiB x3 (counter calibration); device copy "
+        f"{2 * mib * (1 << 20) / (c_ms / 1e3) / 1e9:.0f} GB/s read+write")
+
+
+def cf_strip_probe(torch, spec, steps, warmup, log):
+    """One coefficient-form strip (`lattice,m,n,d`: P~ of the m x r
+    rectangles to x^d, r = 1..n) for one seeded prime with the library's
+    launch shape for that chunk width, timed on its own.  Prints one JSON
+    line: time per strip and the forward factors' own minimum row traffic
+    (each source row read once, each target row written once, the maps).
+    Used to take kernel traces and HBM counters of the coefficient form."""
+    from paper_1005_3609_amd import api
+    from paper_1005_3609_amd import tune as tuner
+    from paper_1005_3609_amd import workloads as W
+    lat, m, n, d = spec.split(",")
+    m, n, d = int(m), int(n), int(d)
+    primes = W.seeded_primes(1, 1005)
+    lanes_v = tuner.series_lanes_v(d)
+    t = dict(tuner.SERIES_WIDE_DEFAULT if lanes_v == 8 else tuner.SERIES_DEFAULT, lanes_v=lanes_v)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    stream = torch.cuda.current_stream(dev)
+    api.prepare_series(lat, m)
+    out, ws = api.series_async(lat, m, n, d, primes, mode="graph", tuning=t, stream=stream, device=dev)
+    for _ in range(warmup):
+        api.series_async(lat, m, n, d, primes, mode="graph", tuning=t, workspace=ws, out=out, stream=stream)
+    ms = timed(torch, stream, lambda: api.series_async(lat, m, n, d, primes, mode="graph", tuning=t, workspace=ws,
+                                                       out=out, stream=stream), steps)
+    res = api.to_u32(out).astype("int64").reshape(n, 1, d + 1)
+    assert (res[:, :, 0] == 1).all(), "constant term of P~ must be 1"
+    row = 4 * 64 * lanes_v
+    fwd = [api.series_map_info(lat, m, 4, i) for i in range(m)]
+    own = [row * (nc + nr) + 4 * (nr + 1) + 4 * nz for nr, nc, nz in fwd]
+    line = {"probe": "coefficient-form strip", "lattice": lat, "m": m, "n": n, "d_max": d, "primes": 1,
+            "tuning": t, "ms_per_strip": ms, "row_bytes": row,
+            "forward_factors": [dict(rows=nr, cols=nc, entries=nz, own_min_bytes=b) for (nr, nc, nz), b in zip(fwd, own)]}
+    log(f"coefficient form {lat} {m}x1..{n}, x^0..x^{d}: {ms:.2f} ms per strip")
+    print(json.dumps(line), flush=True)
+
+
 def bench_finite_lattice(k):
     """The square-lattice free-energy series of Table 1 by the finite-lattice
     method: coefficient-form strips of widths 1..k/2 on the GPU, per-prime
@@ -395,6 +441,8 @@ def main():
     ap.add_argument("--m18-rows", type=int, default=1, help="rows of factor launches timed at m=18")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (calibrates HBM counters)")
+    ap.add_argument("--cf-strip", metavar="LATTICE,M,N,D", default=None,
+                    help="only time one coefficient-form strip (one prime, x^0..x^D) and print its own JSON line")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -412,6 +460,11 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.cf_strip:
+        cf_strip_probe(torch, args.cf_strip, args.steps, args.warmup, log)
+        if args.copy_mib:
+            copy_calibration(torch, torch.cuda.current_stream(dev), dev, args.copy_mib)
+        return
     wname = args.workload
     w = W.workload(wname)
     lat, m, n = w["strips"][0]
@@ -537,12 +590,7 @@ def main():
         log(f"cpu oracle: {cpu['value']:.3e} state-updates/s")
 
     if args.copy_mib:
-        nel = args.copy_mib * (1 << 20) // 4
-        src = torch.randint(0, 1 << 30, (nel,), dtype=torch.int32, device=dev)
-        dst = torch.empty_like(src)
-        c_ms = timed(torch, stream, lambda: dst.copy_(src), 3)
-        log(f"copied {args.copy_mib} MiB x3 (counter calibration); device copy "
-            f"{2 * args.copy_mib * (1 << 20) / (c_ms / 1e3) / 1e9:.0f} GB/s read+write")
+        copy_calibration(torch, stream, dev, args.copy_mib)
 
     line = {
         "metric": f"state-updates/s, square lattice m={m} ({m}x{n} strip), batched",

@@ -114,6 +114,15 @@ def prepare_series(lattice, m: int) -> None:
     check(lib().chromatic_prepare_series(lattice_id(lattice), m))
 
 
+def series_map_info(lattice, m: int, which: int, idx: int):
+    """(rows, columns, entries) of a coefficient-form map on the current
+    device, without copying it; which 4 = forward, 5 = read-out factor."""
+    nr, nc, nz = C.c_int64(), C.c_int64(), C.c_int64()
+    check(lib().chromatic_series_map_export(lattice_id(lattice), m, which, idx, C.byref(nr), C.byref(nc), C.byref(nz),
+                                            None, None))
+    return int(nr.value), int(nc.value), int(nz.value)
+
+
 def series_map_export(lattice, m: int, which: int, idx: int):
     """The coefficient-form map the current device holds: (row_ptr int32,
     entries uint32, n_cols); which 4 = forward, 5 = read-out factor."""
