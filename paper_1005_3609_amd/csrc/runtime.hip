@@ -858,7 +858,10 @@ std::mutex g_stage_mu;
 std::vector<std::unique_ptr<StageBuf>> g_stage;
 
 // Copies `bytes` from `src` to device `dst` on `stream` through a pinned
-// buffer that is recycled once the copy has completed.
+// buffer that is recycled once the copy has completed.  The buffer is filled
+// and its copy and completion event queued under the lock: a buffer counts as
+// free when its last event has completed, so another thread must not see it
+// between the claim and the new event.
 void upload(void* dst, const void* src, size_t bytes, hipStream_t stream) {
   if (bytes == 0) return;
   StageBuf* sb = nullptr;
@@ -879,10 +882,10 @@ void upload(void* dst, const void* src, size_t bytes, hipStream_t stream) {
       g_stage.push_back(std::move(nb));
     }
     sb->in_use = true;
+    std::memcpy(sb->host, src, bytes);
+    HIPX(hipMemcpyAsync(dst, sb->host, bytes, hipMemcpyHostToDevice, stream));
+    HIPX(hipEventRecord(sb->done, stream));
   }
-  std::memcpy(sb->host, src, bytes);
-  HIPX(hipMemcpyAsync(dst, sb->host, bytes, hipMemcpyHostToDevice, stream));
-  HIPX(hipEventRecord(sb->done, stream));
 }
 
 // ---------------------------------------------------------------------------
