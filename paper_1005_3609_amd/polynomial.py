@@ -117,6 +117,28 @@ def chromatic_polynomials(lattice, m: int, n: int, primes=None, batch: int = 4, 
             return out, len(used)
 
 
+def evaluate(c, q: int) -> int:
+    """P(q) for P = sum c_j q^j."""
+    v = 0
+    for cj in reversed(c):
+        v = v * q + cj
+    return v
+
+
+def read_values(path, lattice, m: int, n: int):
+    """[(r, q, P(q))] from lines 'lattice m r q value' of `path` for the
+    given lattice and width and r <= n ('#' starts a comment line)."""
+    out = []
+    with open(path) as f:
+        for ln in f:
+            if ln.startswith("#") or not ln.strip():
+                continue
+            lat, mm, r, q, v = ln.split()
+            if lat == lattice and int(mm) == m and int(r) <= n:
+                out.append((int(r), int(q), int(v)))
+    return out
+
+
 def main(argv=None) -> int:
     import argparse
     import sys
@@ -129,6 +151,8 @@ def main(argv=None) -> int:
     ap.add_argument("--transposed", type=int, default=0, metavar="K",
                     help="also compute P of the r x m rectangles, r = 1..K, by strips of width r, and compare "
                          "(P is symmetric under transposition)")
+    ap.add_argument("--values", metavar="FILE",
+                    help="file of 'lattice m r q value' lines: P(q) of each listed m x r rectangle must equal value")
     ap.add_argument("--out", help="write the polynomials here instead of standard output")
     a = ap.parse_args(argv)
     import time
@@ -148,6 +172,12 @@ def main(argv=None) -> int:
             rc = 1
             say(f"{a.m}x{r}: FAILED " + "; ".join(bad))
     say(f"properties of all {a.n} polynomials: " + ("FAILED" if rc else "hold"))
+    if a.values:
+        want = read_values(a.values, a.lattice, a.m, a.n)
+        bad = [(r, q) for r, q, v in want if evaluate(polys[r - 1], q) != v]
+        rc = rc or (1 if bad or not want else 0)
+        say(f"values from {a.values}: {len(want) - len(bad)} of {len(want)} equal"
+            + (f"; DIFFERENT at (r, q) = {bad}" if bad else ""))
     for r in range(1, min(a.transposed, a.n) + 1):
         tp, _ = chromatic_polynomials(a.lattice, r, a.m, batch=max(a.batch, 4), max_primes=a.max_primes)
         same = tp[-1] == polys[r - 1]

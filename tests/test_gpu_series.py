@@ -223,3 +223,16 @@ def test_exact_chromatic_polynomials(lat, m, n):
             got.pop()
         assert got == want[r], (lat, m, r + 1)
     assert used >= 2
+
+
+def test_exact_polynomials_past_256_vertices_against_three_colourings():
+    # square 12 x r, r = 1..22 (|V| up to 264: 512-slot rows): P(3) of every
+    # rectangle equals the number of proper 3-colourings counted by the
+    # oracle's colour transfer matrix, which shares nothing with the
+    # partition transfer matrix; every polynomial has the properties of check
+    from oracle import colourings as OC
+    from paper_1005_3609_amd import polynomial as PL
+    polys, used = PL.chromatic_polynomials(SQ, 12, 22)
+    assert [PL.evaluate(p, 3) for p in polys] == OC.square_three_colourings(12, 22)
+    for r, p in enumerate(polys, start=1):
+        assert PL.check(SQ, 12, r, p) == [], r

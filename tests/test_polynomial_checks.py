@@ -62,3 +62,13 @@ def test_planted_mistakes_are_caught(lat):
     # the right polynomial for the wrong rectangle
     assert PL.check(lat, m, n + 1, good)
     assert PL.check(SQ if lat == TRI else TRI, m, n, good)
+
+
+def test_evaluate_and_read_values(tmp_path):
+    assert PL.evaluate([0, -1, 1], 3) == 6 and PL.evaluate([5], 7) == 5 and PL.evaluate([], 2) == 0
+    f = tmp_path / "v.txt"
+    f.write_text("# comment\nsquare 4 2 3 162\nsquare 4 9 3 1\ntriangular 4 2 3 6\nsquare 5 1 3 48\n")
+    assert PL.read_values(str(f), "square", 4, 5) == [(2, 3, 162)]
+    # the stored 3-colouring counts agree with the oracle's exact polynomials where both exist
+    p = OT.chromatic_exact(SQ, 4, 2)[-1]
+    assert PL.evaluate(p, 3) == 162
