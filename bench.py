@@ -447,7 +447,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the sweep shards over instances "
-                                   "with no communication, and multi-GPU runs are not part of this build",
+                                   "with no communication, and this program drives one GPU",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
