@@ -164,6 +164,13 @@ struct GatherArgs {
   const int32_t* tile_row0;
   const int32_t* tile_src0;
   const int32_t* tile_src;
+  // Coefficient form, degree bound (deg_step == 0: none).  The state being
+  // gathered belongs to output row r (r = *deg_row when deg_row is set, a
+  // device counter advanced by graph replays, else deg_row0) and has degree
+  // below deg_step (r + 2) in x, deg_step being the sites of one row.
+  int deg_step;
+  int deg_row0;
+  const int* deg_row;
 };
 
 struct DotArgs {
@@ -417,6 +424,19 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
   const int nw = blockDim.x >> 6;
   const int r0 = (tile * nw + wave) * a.rows_per_wave;
   const int r1 = min(r0 + a.rows_per_wave, a.csr.n_rows);
+  // Coefficient form: a state of a strip whose rows so far hold n sites has
+  // degree below n in x (each x pays for one merge of two components, and
+  // there are fewer merges than sites), so the lanes whose slots all lie
+  // above deg_step (r + 2) hold zeros.  They neither load nor store: the
+  // vectors start zeroed, and a lane becomes live before any of its slots can
+  // be non-zero.
+  bool live = true;
+  if constexpr (CF) {
+    if (a.deg_step) {
+      const int row = a.deg_row ? *a.deg_row : a.deg_row0;
+      live = lane <= a.deg_step * (row + 2) / V;
+    }
+  }
   if (r0 < r1) {
     const int nrows = r1 - r0;
     const int rp = (lane <= nrows) ? a.csr.row_ptr[r0 + lane] : 0;
@@ -430,10 +450,12 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
         horner_cf<V>(v, A, deg, p);
       else
         horner<V>(v, A, deg, tv, ts, p);
-      if constexpr (WIDE)
-        store_row<V>(wide_row<W>(out, static_cast<uint32_t>(row)), boff, v);
-      else
-        store_row<V>(out, static_cast<uint32_t>(row) * (4u * W) + boff, v);
+      if (live) {
+        if constexpr (WIDE)
+          store_row<V>(wide_row<W>(out, static_cast<uint32_t>(row)), boff, v);
+        else
+          store_row<V>(out, static_cast<uint32_t>(row) * (4u * W) + boff, v);
+      }
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         if (k <= deg) {
@@ -468,10 +490,15 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         w[u] = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ev0), min(e0 + u, end - 1) - base));
-        if constexpr (WIDE)
-          load_row<V>(wide_row<W>(in, w[u] & kEntSrcMask), boff, x[u]);
-        else
-          load_row<V>(in, (w[u] & kEntSrcMask) * (4u * W) + boff, x[u]);
+        if (!CF || live) {
+          if constexpr (WIDE)
+            load_row<V>(wide_row<W>(in, w[u] & kEntSrcMask), boff, x[u]);
+          else
+            load_row<V>(in, (w[u] & kEntSrcMask) * (4u * W) + boff, x[u]);
+        } else {
+#pragma unroll
+          for (int j = 0; j < V; ++j) x[u][j] = 0;
+        }
         // Keep the loads in entry order: completions are counted in issue
         // order, so entry u must not be issued after entry u + 1.
         __builtin_amdgcn_sched_barrier(0);

@@ -1068,7 +1068,7 @@ JobLayout job_layout_series(int lattice, int m, int np, int d_max, const Tune& t
   L.tv = take(L.ipad * 4);
   L.ts = take(L.ipad * 4);
   L.poly = take(static_cast<size_t>(kMaxCodes) * 8);
-  L.e0 = take(L.ipad * 4);
+  L.e0 = take(2 * static_cast<size_t>(L.ipad) * 4);   // e_0, then zeros
   L.bytes = off;
   return L;
 }
@@ -1283,6 +1283,8 @@ int push_readout_cf(Program& pg, const JobCtx& j, const uint32_t* x, int after, 
     Step g = gather_step(j, j.dm->last_fwd[i - 1], in, out, r_cs, false, j.fam->general);
     g.u.g.in_cstride = in_cs;
     g.cf = L.wide ? 2 : 1;
+    g.u.g.deg_step = L.m;
+    g.u.g.deg_row0 = out_row;
     after = push(pg, g, after, -1);
     in = out;
     in_cs = r_cs;
@@ -1295,15 +1297,29 @@ int push_readout_cf(Program& pg, const JobCtx& j, const uint32_t* x, int after, 
 }
 
 // Coefficient form, row 0: x0 = e_0 (coefficient array 1 in every chunk),
-// then its read-out.
+// then its read-out.  Every row of x0, x1, ra and rb is cleared first: the
+// gathers leave the slots above their degree bound untouched, so those
+// slots must start at zero (the second half of the e0 area is zeros).
 int add_setup_cf(Program& pg, const JobCtx& j) {
   const JobLayout& L = j.L;
   const long cs_x = static_cast<long>(L.s_max) * L.W;
-  Step s{};
-  s.op = kOpFill;
-  s.ntiles = tiles_for(L.s_nc, L.rows_tile);
-  s.u.f = FillArgs{j.P.x0, cs_x, static_cast<int>(L.s_nc), j.P.e0, j.t.rpw};
-  const int last = push(pg, s, -1, -1);
+  const long cs_r = static_cast<long>(L.l_max) * L.W;
+  const uint32_t* zeros = j.P.e0 + L.ipad;
+  struct {
+    uint32_t* x;
+    long cs;
+    int64_t rows;
+    const uint32_t* v0;
+  } fills[4] = {{j.P.x0, cs_x, L.s_max, j.P.e0}, {j.P.x1, cs_x, L.s_max, zeros},
+                {j.P.ra, cs_r, L.l_max, zeros}, {j.P.rb, cs_r, L.l_max, zeros}};
+  int last = -1;
+  for (const auto& f : fills) {
+    Step s{};
+    s.op = kOpFill;
+    s.ntiles = tiles_for(f.rows, L.rows_tile);
+    s.u.f = FillArgs{f.x, f.cs, static_cast<int>(f.rows), f.v0, j.t.rpw};
+    last = push(pg, s, last, -1);
+  }
   return push_readout_cf(pg, j, j.P.x0, last, 0);
 }
 
@@ -1358,6 +1374,8 @@ void add_rows(Program& pg, const JobCtx& j, int r_first, int r_last, int after, 
       for (int i = 1; i <= nf; ++i) {
         Step g = gather_step(j, j.fam->fac[i - 1], cur, oth, cs_x, false, j.fam->general);
         g.cf = L.wide ? 2 : 1;
+        g.u.g.deg_step = L.m;
+        g.u.g.deg_row0 = r;
         after = push(pg, g, after, -1);
         std::swap(cur, oth);
       }
@@ -1398,6 +1416,14 @@ Program strip_program(const JobCtx& j, int n_max) {
 // Eager execution of a program: one launch per step, grid (ntiles, nchunk)
 // ---------------------------------------------------------------------------
 // Launches one step over chunks [c0, c0 + nch).
+// Coefficient-form gather arguments of a step: under a graph replay the
+// degree bound follows the device row counter.
+GatherArgs cf_args(const Step& s, const int* row_ctr) {
+  GatherArgs g = s.u.g;
+  if (row_ctr && g.deg_step) g.deg_row = row_ctr;
+  return g;
+}
+
 template <int V, int U>
 void launch_step_vu(const Step& s, int c0, int nch, int wpb, int xcd, hipStream_t st, const int* row_ctr,
                     long row_stride) {
@@ -1406,14 +1432,14 @@ void launch_step_vu(const Step& s, int c0, int nch, int wpb, int xcd, hipStream_
     case kOpGather:
       if (s.cf == 2) {
         if (s.general)
-          hipLaunchKernelGGL((k_gather<V, U, true, true, true>), grid, block, 0, st, s.u.g, xcd, c0);
+          hipLaunchKernelGGL((k_gather<V, U, true, true, true>), grid, block, 0, st, cf_args(s, row_ctr), xcd, c0);
         else
-          hipLaunchKernelGGL((k_gather<V, U, false, true, true>), grid, block, 0, st, s.u.g, xcd, c0);
+          hipLaunchKernelGGL((k_gather<V, U, false, true, true>), grid, block, 0, st, cf_args(s, row_ctr), xcd, c0);
       } else if (s.cf) {
         if (s.general)
-          hipLaunchKernelGGL((k_gather<V, U, true, true>), grid, block, 0, st, s.u.g, xcd, c0);
+          hipLaunchKernelGGL((k_gather<V, U, true, true>), grid, block, 0, st, cf_args(s, row_ctr), xcd, c0);
         else
-          hipLaunchKernelGGL((k_gather<V, U, false, true>), grid, block, 0, st, s.u.g, xcd, c0);
+          hipLaunchKernelGGL((k_gather<V, U, false, true>), grid, block, 0, st, cf_args(s, row_ctr), xcd, c0);
       } else if (s.u.g.tile_row0) {
         if constexpr (V <= 2) {
           if (s.general)
@@ -1457,13 +1483,13 @@ void launch_step_cf8(const Step& s, int c0, int nch, int wpb, int xcd, hipStream
   switch (s.op) {
     case kOpGather:
       if (s.cf == 2 && s.general)
-        hipLaunchKernelGGL((k_gather<8, 4, true, true, true>), grid, block, 0, st, s.u.g, xcd, c0);
+        hipLaunchKernelGGL((k_gather<8, 4, true, true, true>), grid, block, 0, st, cf_args(s, row_ctr), xcd, c0);
       else if (s.cf == 2)
-        hipLaunchKernelGGL((k_gather<8, 4, false, true, true>), grid, block, 0, st, s.u.g, xcd, c0);
+        hipLaunchKernelGGL((k_gather<8, 4, false, true, true>), grid, block, 0, st, cf_args(s, row_ctr), xcd, c0);
       else if (s.cf && s.general)
-        hipLaunchKernelGGL((k_gather<8, 4, true, true>), grid, block, 0, st, s.u.g, xcd, c0);
+        hipLaunchKernelGGL((k_gather<8, 4, true, true>), grid, block, 0, st, cf_args(s, row_ctr), xcd, c0);
       else if (s.cf)
-        hipLaunchKernelGGL((k_gather<8, 4, false, true>), grid, block, 0, st, s.u.g, xcd, c0);
+        hipLaunchKernelGGL((k_gather<8, 4, false, true>), grid, block, 0, st, cf_args(s, row_ctr), xcd, c0);
       else
         throw std::runtime_error("lanes_v 8 is for the coefficient form only");
       break;
@@ -2071,7 +2097,7 @@ int series_async_impl(int lattice, int m, int n_max, int d_max, const uint32_t* 
   for (int k = 0; k < j.L.ipad; ++k) inst[k] = Inst{0u, p[k / j.L.W]};
   std::vector<uint32_t> img = const_image(j.L, inst, j.fam->codes, 0);
   upload(static_cast<char*>(ws) + j.L.p, img.data(), img.size() * 4, st);
-  std::vector<uint32_t> e0(j.L.ipad, 0u);
+  std::vector<uint32_t> e0(2 * static_cast<size_t>(j.L.ipad), 0u);   // e_0, then zeros
   for (int c = 0; c < np; ++c) e0[static_cast<size_t>(c) * j.L.W] = 1u;
   upload(static_cast<char*>(ws) + j.L.e0, e0.data(), e0.size() * 4, st);
   int* row_ctr = reinterpret_cast<int*>(static_cast<char*>(ws) + j.L.bytes);
