@@ -164,7 +164,8 @@ struct GatherArgs {
   const int32_t* tile_row0;
   const int32_t* tile_src0;
   const int32_t* tile_src;
-  // Coefficient form, degree bound (deg_step == 0: none).  The state being
+  // Coefficient form with 512-slot rows, degree bound (deg_step == 0: none;
+  // narrower rows ignore it).  The state being
   // gathered belongs to output row r (r = *deg_row when deg_row is set, a
   // device counter advanced by graph replays, else deg_row0) and has degree
   // below deg_step (r + 2) in x, deg_step being the sites of one row.
@@ -424,14 +425,16 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
   const int nw = blockDim.x >> 6;
   const int r0 = (tile * nw + wave) * a.rows_per_wave;
   const int r1 = min(r0 + a.rows_per_wave, a.csr.n_rows);
-  // Coefficient form: a state of a strip whose rows so far hold n sites has
-  // degree below n in x (each x pays for one merge of two components, and
-  // there are fewer merges than sites), so the lanes whose slots all lie
-  // above deg_step (r + 2) hold zeros.  They neither load nor store: the
-  // vectors start zeroed, and a lane becomes live before any of its slots can
-  // be non-zero.
+  // Coefficient form with 512-slot rows: a state of a strip whose rows so far
+  // hold n sites has degree below n in x (each x pays for one merge of two
+  // components, and there are fewer merges than sites), so the lanes whose
+  // slots all lie above deg_step (r + 2) hold zeros.  They neither load nor
+  // store: the vectors start zeroed, and a lane becomes live before any of
+  // its slots can be non-zero.  Narrower rows fill up within a few rows, and
+  // there the masking costs more than it saves.
+  constexpr bool kBound = CF && V == 8;
   bool live = true;
-  if constexpr (CF) {
+  if constexpr (kBound) {
     if (a.deg_step) {
       const int row = a.deg_row ? *a.deg_row : a.deg_row0;
       live = lane <= a.deg_step * (row + 2) / V;
@@ -450,7 +453,7 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
         horner_cf<V>(v, A, deg, p);
       else
         horner<V>(v, A, deg, tv, ts, p);
-      if (live) {
+      if (!kBound || live) {
         if constexpr (WIDE)
           store_row<V>(wide_row<W>(out, static_cast<uint32_t>(row)), boff, v);
         else
@@ -490,7 +493,7 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         w[u] = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ev0), min(e0 + u, end - 1) - base));
-        if (!CF || live) {
+        if (!kBound || live) {
           if constexpr (WIDE)
             load_row<V>(wide_row<W>(in, w[u] & kEntSrcMask), boff, x[u]);
           else

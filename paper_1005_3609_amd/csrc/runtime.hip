@@ -1283,7 +1283,7 @@ int push_readout_cf(Program& pg, const JobCtx& j, const uint32_t* x, int after, 
     Step g = gather_step(j, j.dm->last_fwd[i - 1], in, out, r_cs, false, j.fam->general);
     g.u.g.in_cstride = in_cs;
     g.cf = L.wide ? 2 : 1;
-    g.u.g.deg_step = L.m;
+    g.u.g.deg_step = L.V == 8 ? L.m : 0;
     g.u.g.deg_row0 = out_row;
     after = push(pg, g, after, -1);
     in = out;
@@ -1297,9 +1297,11 @@ int push_readout_cf(Program& pg, const JobCtx& j, const uint32_t* x, int after, 
 }
 
 // Coefficient form, row 0: x0 = e_0 (coefficient array 1 in every chunk),
-// then its read-out.  Every row of x0, x1, ra and rb is cleared first: the
-// gathers leave the slots above their degree bound untouched, so those
-// slots must start at zero (the second half of the e0 area is zeros).
+// then its read-out.  With 512-slot rows every row of x0, x1, ra and rb is
+// cleared first: the gathers leave the slots above their degree bound
+// untouched, so those slots must start at zero (the second half of the e0
+// area is zeros).  Narrower rows are written whole, and only x0's NCNNN rows
+// are filled.
 int add_setup_cf(Program& pg, const JobCtx& j) {
   const JobLayout& L = j.L;
   const long cs_x = static_cast<long>(L.s_max) * L.W;
@@ -1310,10 +1312,12 @@ int add_setup_cf(Program& pg, const JobCtx& j) {
     long cs;
     int64_t rows;
     const uint32_t* v0;
-  } fills[4] = {{j.P.x0, cs_x, L.s_max, j.P.e0}, {j.P.x1, cs_x, L.s_max, zeros},
+  } fills[4] = {{j.P.x0, cs_x, L.V == 8 ? L.s_max : L.s_nc, j.P.e0}, {j.P.x1, cs_x, L.s_max, zeros},
                 {j.P.ra, cs_r, L.l_max, zeros}, {j.P.rb, cs_r, L.l_max, zeros}};
+  const int nfills = L.V == 8 ? 4 : 1;
   int last = -1;
-  for (const auto& f : fills) {
+  for (int k = 0; k < nfills; ++k) {
+    const auto& f = fills[k];
     Step s{};
     s.op = kOpFill;
     s.ntiles = tiles_for(f.rows, L.rows_tile);
@@ -1374,7 +1378,7 @@ void add_rows(Program& pg, const JobCtx& j, int r_first, int r_last, int after, 
       for (int i = 1; i <= nf; ++i) {
         Step g = gather_step(j, j.fam->fac[i - 1], cur, oth, cs_x, false, j.fam->general);
         g.cf = L.wide ? 2 : 1;
-        g.u.g.deg_step = L.m;
+        g.u.g.deg_step = L.V == 8 ? L.m : 0;
         g.u.g.deg_row0 = r;
         after = push(pg, g, after, -1);
         std::swap(cur, oth);
