@@ -72,12 +72,19 @@ def check(lattice, m: int, n: int, c) -> list:
     return bad
 
 
-def chromatic_polynomials(lattice, m: int, n: int, primes=None, batch: int = 4, max_primes: int = 64,
+def primes_per_call(one_prime_bytes: int, free_bytes: int, most: int = 8) -> int:
+    """Primes per coefficient-form call: as many as fit in 80 % of the free
+    device memory (one prime's workspace each), between 1 and `most`."""
+    return max(1, min(most, int(0.8 * free_bytes) // max(one_prime_bytes, 1)))
+
+
+def chromatic_polynomials(lattice, m: int, n: int, primes=None, batch: int = 0, max_primes: int = 64,
                           log=None):
     """[P_{m x r}(q) for r = 1..n], each a list of integers c_0..c_{|V|}
     with P = sum c_j q^j.  Needs m n <= 512 (coefficients x^0..x^{mn-1} in
     at most 8 slots per wavefront lane).  Primes are drawn in groups of
-    `batch` from `primes` (default: seeded 31-bit primes) until every row's
+    `batch` (0: as many as the free device memory holds, at most 8) from
+    `primes` (default: seeded 31-bit primes) until every row's
     lift is stable; returns (polynomials, primes used).  `log(text)`, if
     given, hears of every finished prime group."""
     V = m * n
@@ -86,6 +93,10 @@ def chromatic_polynomials(lattice, m: int, n: int, primes=None, batch: int = 4, 
     d = V - 1
     lanes_v = tune.series_lanes_v(d)
     shape = dict(tune.SERIES_WIDE_DEFAULT if lanes_v == 8 else tune.SERIES_DEFAULT, lanes_v=lanes_v)
+    if batch <= 0:
+        import torch
+        free, _ = torch.cuda.mem_get_info()
+        batch = primes_per_call(api.series_workspace_bytes(lattice, m, n, 1, d, "graph", shape), free)
     pool = list(primes) if primes is not None else W.seeded_primes(max_primes, 1005)
     residues = []            # [prime][row][coefficient]
     used = []
@@ -146,7 +157,8 @@ def main(argv=None) -> int:
     ap.add_argument("lattice", choices=["square", "triangular"])
     ap.add_argument("m", type=int)
     ap.add_argument("n", type=int)
-    ap.add_argument("--batch", type=int, default=4, help="primes per coefficient-form call")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="primes per coefficient-form call (0: as many as fit in device memory, at most 8)")
     ap.add_argument("--max-primes", type=int, default=64)
     ap.add_argument("--transposed", type=int, default=0, metavar="K",
                     help="also compute P of the r x m rectangles, r = 1..K, by strips of width r, and compare "
@@ -179,7 +191,7 @@ def main(argv=None) -> int:
         say(f"values from {a.values}: {len(want) - len(bad)} of {len(want)} equal"
             + (f"; DIFFERENT at (r, q) = {bad}" if bad else ""))
     for r in range(1, min(a.transposed, a.n) + 1):
-        tp, _ = chromatic_polynomials(a.lattice, r, a.m, batch=max(a.batch, 4), max_primes=a.max_primes)
+        tp, _ = chromatic_polynomials(a.lattice, r, a.m, max_primes=a.max_primes)
         same = tp[-1] == polys[r - 1]
         rc = rc or (0 if same else 1)
         say(f"{a.m}x{r} against {r}x{a.m} by width-{r} strips: " + ("equal" if same else "DIFFERENT"))

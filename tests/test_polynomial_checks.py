@@ -72,3 +72,11 @@ def test_evaluate_and_read_values(tmp_path):
     # the stored 3-colouring counts agree with the oracle's exact polynomials where both exist
     p = OT.chromatic_exact(SQ, 4, 2)[-1]
     assert PL.evaluate(p, 3) == 162
+
+
+def test_primes_per_call():
+    GiB = 1 << 30
+    assert PL.primes_per_call(119 * GiB, 287 * GiB) == 1       # square 20 x 21 on one MI355X
+    assert PL.primes_per_call(6 * GiB, 287 * GiB) == 8         # capped
+    assert PL.primes_per_call(100 * GiB, 10 * GiB) == 1        # never below one
+    assert PL.primes_per_call(30 * GiB, 100 * GiB) == 2
