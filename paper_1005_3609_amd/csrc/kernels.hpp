@@ -776,6 +776,21 @@ __global__ void __launch_bounds__(512) k_gather(GatherArgs a, int xcd, int chunk
   gather_tile<V, U, G, CF, WIDE>(a, chunk, tile, lds);
 }
 
+// The coefficient form's 512-slot rows (V = 8, U = 4).  The form never fuses
+// the read-out into a gather (it applies T_last instead), so this instance
+// has no read-out and no LDS, and asks for three wavefronts per SIMD (at
+// most 168 VGPRs).  Rows below their degree bound leave most lanes idle, and
+// such launches wait on load latency rather than bandwidth: the third
+// wavefront takes 26 % off the first six rows of a square m = 20 strip.
+template <bool G, bool WIDE>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3)))
+k_gather_cf8(GatherArgs a, int xcd, int chunk0) {
+  int tile, chunk;
+  tile_chunk(xcd, chunk0, tile, chunk);
+  a.w = nullptr;
+  gather_tile<8, 4, G, true, WIDE>(a, chunk, tile, nullptr);
+}
+
 // grid (tiles, chunks); dynamic LDS: max_slots * 64 V words
 template <int V, int U, bool G>
 __global__ void __launch_bounds__(512) k_stage(GatherArgs a, int xcd, int chunk0) {

@@ -1486,16 +1486,15 @@ void launch_step_cf8(const Step& s, int c0, int nch, int wpb, int xcd, hipStream
   dim3 grid(s.ntiles, nch), block(64 * wpb);
   switch (s.op) {
     case kOpGather:
+      if (!s.cf || s.u.g.w) throw std::runtime_error("lanes_v 8 is for the coefficient form only");
       if (s.cf == 2 && s.general)
-        hipLaunchKernelGGL((k_gather<8, 4, true, true, true>), grid, block, 0, st, cf_args(s, row_ctr), xcd, c0);
+        hipLaunchKernelGGL((k_gather_cf8<true, true>), grid, block, 0, st, cf_args(s, row_ctr), xcd, c0);
       else if (s.cf == 2)
-        hipLaunchKernelGGL((k_gather<8, 4, false, true, true>), grid, block, 0, st, cf_args(s, row_ctr), xcd, c0);
-      else if (s.cf && s.general)
-        hipLaunchKernelGGL((k_gather<8, 4, true, true>), grid, block, 0, st, cf_args(s, row_ctr), xcd, c0);
-      else if (s.cf)
-        hipLaunchKernelGGL((k_gather<8, 4, false, true>), grid, block, 0, st, cf_args(s, row_ctr), xcd, c0);
+        hipLaunchKernelGGL((k_gather_cf8<false, true>), grid, block, 0, st, cf_args(s, row_ctr), xcd, c0);
+      else if (s.general)
+        hipLaunchKernelGGL((k_gather_cf8<true, false>), grid, block, 0, st, cf_args(s, row_ctr), xcd, c0);
       else
-        throw std::runtime_error("lanes_v 8 is for the coefficient form only");
+        hipLaunchKernelGGL((k_gather_cf8<false, false>), grid, block, 0, st, cf_args(s, row_ctr), xcd, c0);
       break;
     case kOpEmit:
       if (row_ctr)

@@ -83,7 +83,8 @@ def chromatic_polynomials(lattice, m: int, n: int, primes=None, batch: int = 0, 
     """[P_{m x r}(q) for r = 1..n], each a list of integers c_0..c_{|V|}
     with P = sum c_j q^j.  Needs m n <= 512 (coefficients x^0..x^{mn-1} in
     at most 8 slots per wavefront lane).  Primes are drawn in groups of
-    `batch` (0: as many as the free device memory holds, at most 8) from
+    `batch` (0: one for 512-slot rows, else as many as the free device
+    memory holds, at most 8) from
     `primes` (default: seeded 31-bit primes) until every row's
     lift is stable; returns (polynomials, primes used).  `log(text)`, if
     given, hears of every finished prime group."""
@@ -93,7 +94,9 @@ def chromatic_polynomials(lattice, m: int, n: int, primes=None, batch: int = 0, 
     d = V - 1
     lanes_v = tune.series_lanes_v(d)
     shape = dict(tune.SERIES_WIDE_DEFAULT if lanes_v == 8 else tune.SERIES_DEFAULT, lanes_v=lanes_v)
-    if batch <= 0:
+    if batch <= 0 and lanes_v == 8:
+        batch = 1        # 512-slot rows: two primes per call ran 1.3x slower per prime (triangular 20 x 21)
+    elif batch <= 0:
         import torch
         free, _ = torch.cuda.mem_get_info()
         batch = primes_per_call(api.series_workspace_bytes(lattice, m, n, 1, d, "graph", shape), free)
@@ -158,7 +161,8 @@ def main(argv=None) -> int:
     ap.add_argument("m", type=int)
     ap.add_argument("n", type=int)
     ap.add_argument("--batch", type=int, default=0,
-                    help="primes per coefficient-form call (0: as many as fit in device memory, at most 8)")
+                    help="primes per coefficient-form call (0: one for |V| > 256, else as many as fit in device "
+                         "memory, at most 8)")
     ap.add_argument("--max-primes", type=int, default=64)
     ap.add_argument("--transposed", type=int, default=0, metavar="K",
                     help="also compute P of the r x m rectangles, r = 1..K, by strips of width r, and compare "
