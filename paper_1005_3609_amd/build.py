@@ -18,8 +18,6 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libchromstrip.so")
-# Memory-pattern ceiling probe (an executable, not part of the library).
-CEILING = os.path.join(PKG, "gather_ceiling")
 ARCH = "gfx950"
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
@@ -47,8 +45,6 @@ def build(verbose: bool = False) -> str:
         ([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "runtime.hip"), "-o",
           os.path.join(OUT_DIR, "runtime.o")]),
     ]
-    jobs.append([HIPCC, *[f for f in HIP_FLAGS if f != "-fPIC"], os.path.join(CSRC, "gather_ceiling.hip"),
-                 "-o", CEILING])
     with ThreadPoolExecutor(4) as ex:
         logs = list(ex.map(_run, jobs))
     tmp = LIB + ".tmp"
