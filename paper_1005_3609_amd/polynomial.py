@@ -5,7 +5,10 @@ P_G(q) of the m x r rectangles, r = 1..n, as integer coefficient lists
 normalised P~ = q^{-|V|} P (eq. Z_modified) as coefficients of x^0..x^d mod
 each prime, and with d = |V| - 1 (the constant term of P is 0) the whole
 polynomial is known mod p: the coefficient of q^{|V| - k} in P is that of
-x^k in P~.  Primes are added until the CRT lift stops changing (Sec. 3.5).
+x^k in P~.  Primes are added until the CRT lift stops changing (Sec. 3.5) and
+their product exceeds twice the largest coefficient any of the polynomials
+can have (Whitney's broken-circuit theorem bounds |c_{|V|-k}| by C(|E|, k)),
+so the symmetric lift is exact, not only stable.
 
     python -m paper_1005_3609_amd.polynomial square 6 7
 """
@@ -72,6 +75,14 @@ def check(lattice, m: int, n: int, c) -> list:
     return bad
 
 
+def coefficient_bound(lattice, m: int, n: int) -> int:
+    """An upper bound on |c_j| for the chromatic polynomial of the m x n
+    rectangle: c_{|V|-k} counts the k-edge subsets with no broken circuit
+    (Whitney), at most C(|E|, k), and k runs over 0..|V|-1 (c_0 = 0)."""
+    V, E, _, _ = graph_counts(lattice, m, n)
+    return max(comb(E, k) for k in range(0, max(min(E, V - 1), 0) + 1))
+
+
 def primes_per_call(one_prime_bytes: int, free_bytes: int, most: int = 8) -> int:
     """Primes per coefficient-form call: as many as fit in 80 % of the free
     device memory (one prime's workspace each), between 1 and `most`."""
@@ -86,7 +97,10 @@ def chromatic_polynomials(lattice, m: int, n: int, primes=None, batch: int = 0, 
     `batch` (0: one for 512-slot rows, else as many as the free device
     memory holds, at most 8) from
     `primes` (default: seeded 31-bit primes) until every row's
-    lift is stable; returns (polynomials, primes used).  `log(text)`, if
+    lift is stable and the product of the primes exceeds twice
+    `coefficient_bound` of the largest rectangle; returns (polynomials,
+    primes used).  Raises if a coefficient past a row's degree lifts to a
+    non-zero value.  `log(text)`, if
     given, hears of every finished prime group."""
     V = m * n
     if V > 512:
@@ -103,6 +117,8 @@ def chromatic_polynomials(lattice, m: int, n: int, primes=None, batch: int = 0, 
     pool = list(primes) if primes is not None else W.seeded_primes(max_primes, 1005)
     residues = []            # [prime][row][coefficient]
     used = []
+    need = 2 * coefficient_bound(lattice, m, n)
+    modulus = 1
     while True:
         group = pool[len(used):len(used) + batch]
         if not group:
@@ -111,11 +127,13 @@ def chromatic_polynomials(lattice, m: int, n: int, primes=None, batch: int = 0, 
         for b in range(len(group)):
             residues.append([[int(v) for v in res[r, b]] for r in range(n)])
         used += group
+        for p_ in group:
+            modulus *= p_
         if log:
             log(f"{lattice} {m}x{n}: {len(used)} primes done")
         # stable: the lift over every prime so far equals the lift without
         # the last one, for every row
-        out, stable = [], len(used) > 1
+        out, stable = [], len(used) > 1 and modulus > need
         for r in range(n):
             rows = [residues[b][r] for b in range(len(used))]
             coef, _ = host.series_exact(rows, used)
@@ -123,6 +141,8 @@ def chromatic_polynomials(lattice, m: int, n: int, primes=None, batch: int = 0, 
                 prev, _ = host.series_exact(rows[:-1], used[:-1])
                 stable = prev == coef
             Vr = m * (r + 1)
+            if stable and any(coef[Vr:]):
+                raise RuntimeError(f"{lattice} {m}x{r + 1}: a coefficient past x^{Vr - 1} lifted to a non-zero value")
             p = [0] * (Vr + 1)
             for k2, c in enumerate(coef[:Vr]):
                 p[Vr - k2] = c
