@@ -137,9 +137,9 @@ def series_map_export(lattice, m: int, which: int, idx: int):
 
 
 def prepare_host(lattice, m: int, normalised: bool = False) -> None:
-    """Host maps of (lattice, m) only (no device); safe to call from a second
-    thread while device work for other widths runs (the GIL is released
-    during the call)."""
+    """Host maps of (lattice, m) only (no device).  Builds are serialized in
+    the library; call it from the thread that makes the other library calls
+    (concurrent use from a second thread is not supported)."""
     check(lib().chromatic_prepare_host(lattice_id(lattice), m, 1 if normalised else 0))
 
 

@@ -756,15 +756,15 @@ StagedCsr build_staged(const Csr& c, int slots, int rows) {
 }
 
 namespace {
-// One slot per (lattice, m, normalised), each with its own lock: a build
-// holds only its slot, so different map sets build concurrently (a caller
-// can prepare the next width while the device runs the current one) and a
-// second request for a set under construction waits for it.
+// One slot per (lattice, m, normalised).  Builds take the global build lock
+// as well, so map sets build one at a time; a request for a set already
+// built only takes its slot's lock.
 struct CacheSlot {
   std::mutex mu;
   std::unique_ptr<MapSet> ms;
 };
 std::mutex g_cache_mu;
+std::mutex g_build_mu;
 std::map<std::tuple<int, int, bool>, std::shared_ptr<CacheSlot>> g_cache;
 }  // namespace
 
@@ -777,7 +777,10 @@ const MapSet& get_maps(int lattice, int m, bool normalised) {
     slot = s;
   }
   std::lock_guard<std::mutex> lk(slot->mu);
-  if (!slot->ms) slot->ms = build_maps(lattice, m, 0, normalised);  // a failed build leaves the slot empty
+  if (!slot->ms) {
+    std::lock_guard<std::mutex> build(g_build_mu);
+    slot->ms = build_maps(lattice, m, 0, normalised);  // a failed build leaves the slot empty
+  }
   return *slot->ms;
 }
 

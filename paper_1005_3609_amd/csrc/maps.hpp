@@ -108,9 +108,10 @@ StagedCsr build_staged(const Csr& c, int slots, int rows);
 std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads = 0, bool normalised = false,
                                    bool paper_order = false);
 
-// Host-side map cache (thread safe): built on first request; different
-// map sets may build concurrently.  release_host_maps invalidates every
-// reference handed out and must not run concurrently with other calls.
+// Host-side map cache (thread safe): built on first request, one map set at
+// a time (a global build lock; each build is itself threaded).
+// release_host_maps invalidates every reference handed out and must not run
+// concurrently with other calls.
 const MapSet& get_maps(int lattice, int m, bool normalised = false);
 void release_host_maps();
 

@@ -61,8 +61,9 @@ SERIAL = CONCURRENT.replace("for t in ths:\n    t.start()\nfor t in ths:\n    t.
 
 
 def test_concurrent_host_builds_match_serial_ones():
-    # map sets built at the same time from several threads (two of them the
-    # same set) equal the ones built on demand one at a time
+    # map sets requested at the same time from several threads (two of them
+    # the same set; the library serializes the builds) equal the ones built
+    # on demand one at a time
     env = dict(os.environ, PYTHONPATH=ROOT)
     outs = []
     for script in (CONCURRENT, SERIAL):
