@@ -7,9 +7,12 @@ generator; nothing here touches the GPU path.  Run from the repository root:
 
 Each output file ``oracle_<lattice>_<m>x<n>.json`` holds P of the m x r
 rectangles, r = 1..n, modulo p, for a seeded sample of the workload's
-instances (q, p).  Tall rectangles that the oracle cannot sweep directly
-(width 18) are stored through transposition symmetry, P(m x r) = P(r x m):
-the oracle computes the narrow width r with m rows.
+instances (q, p), every width swept directly (the square 18 x 19 strip takes
+the oracle about an hour on one core).
+
+``oracle_serving_jobs.json`` holds the same for a sample of the jobs of the
+seeded serving stream: the first job of every (lattice, m) with m >= 11
+among the stream's first 36 jobs, on up to 16 of each job's instances.
 """
 from __future__ import annotations
 
@@ -48,40 +51,63 @@ def _direct(task):
     return path, out["oracle_seconds"]
 
 
-def _transposed(task):
-    """P(m x r) for r = 1..rmax via P(r x m): width r swept to m rows."""
-    name, lat, m, n, rmax, sample, seed = task
-    w = W.workload(name)
-    inst = W.instances(w["q_points"], w["primes"])
-    idx = W.sample_instances(len(inst), sample, seed)
+SERVING_JOBS = 36        # the serving test runs the stream's first 36 jobs
+SERVING_MIN_M = 11       # narrower jobs are checked against the live oracle
+
+
+def serving_sample():
+    """(job, instance indices) for the stored serving values."""
+    jobs = W.serving_stream(SERVING_JOBS)
+    seen, out = set(), []
+    for jb in jobs:
+        key = (jb["lattice"], jb["m"])
+        if jb["m"] < SERVING_MIN_M or key in seen:
+            continue
+        seen.add(key)
+        n_inst = len(jb["q_points"]) * len(jb["primes"])
+        out.append((jb, W.sample_instances(n_inst, 16, W.SEED_BASE + 99 + jb["id"])))
+    return out
+
+
+def _serving_job(task):
+    jb, idx = task
+    inst = W.instances(jb["q_points"], jb["primes"])
     qs = [inst[k][0] for k in idx]
     ps = [inst[k][1] for k in idx]
     t0 = time.time()
-    rows = []
-    for r in range(1, rmax + 1):
-        z = T.chromatic_residues(lat, r, m, qs, ps)[m - 1]
-        rows.append([int(x) for x in z])
-    out = dict(workload=name, lattice=lat, m=m, n_max=n, how="transposed",
-               rows_present=rmax, instance_index=idx, q=qs, p=ps, z=rows,
-               oracle_seconds=time.time() - t0)
-    path = os.path.join(HERE, f"oracle_{lat}_{m}x{n}.json")
-    with open(path, "w") as f:
-        json.dump(out, f, separators=(",", ":"))
-    return path, out["oracle_seconds"]
+    z = T.chromatic_residues(jb["lattice"], jb["m"], jb["n_max"], qs, ps)
+    return dict(id=jb["id"], lattice=jb["lattice"], m=jb["m"], n_max=jb["n_max"], instance_index=idx,
+                q=qs, p=ps, z=[[int(x) for x in row] for row in z], oracle_seconds=time.time() - t0)
 
 
 def _run(task):
-    return _transposed(task[1:]) if task[0] == "T" else _direct(task[1:])
+    return _direct(task[1:])
+
+
+def serving(jobs: int) -> None:
+    tasks = serving_sample()
+    with Pool(min(jobs, len(tasks))) as pool:
+        res = list(pool.imap(_serving_job, tasks))
+    for r in res:
+        print(f"serving job {r['id']} ({r['lattice']} {r['m']}x{r['n_max']}): oracle {r['oracle_seconds']:.1f} s",
+              flush=True)
+    path = os.path.join(HERE, "oracle_serving_jobs.json")
+    with open(path, "w") as f:
+        json.dump(dict(stream_jobs=SERVING_JOBS, jobs=res), f, separators=(",", ":"))
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=8)
     ap.add_argument("--only", default=None, help="comma list of output stems")
+    ap.add_argument("--serving", action="store_true", help="write oracle_serving_jobs.json only")
     args = ap.parse_args()
+    if args.serving:
+        serving(args.jobs)
+        return
     seed = W.SEED_BASE + 99
     tasks = [
-        ("T", "square_18x19", "square", 18, 19, 13, 16, seed),
+        ("D", "square_18x19", "square", 18, 19, 16, seed),
         ("D", "square_sweep_2_14", "square", 14, 15, 64, seed),
         ("D", "square_sweep_2_14", "square", 13, 14, 64, seed),
         ("D", "triangular_m12", "triangular", 12, 13, 288, seed),
