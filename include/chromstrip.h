@@ -73,16 +73,22 @@ enum {
   CHROM_MODE_PLAIN = 0,      /* per-instance vectors [S], one launch per factor per instance */
   CHROM_MODE_BATCHED = 1,    /* instance-minor vectors, one launch per factor for all instances */
   CHROM_MODE_GRAPH = 2,      /* as BATCHED, one row captured in a hipGraph and replayed */
-  CHROM_MODE_PERSISTENT = 3, /* disabled (returns CHROM_EUNSUPPORTED): device work queue */
+  CHROM_MODE_RESIDENT = 3,   /* the whole strip in ONE launch: each workgroup keeps the state
+                                vectors of lanes_v instances in LDS and runs every factor
+                                (Sec. 3.2-3.3) and row read-out (eq. Z_from_T) with workgroup
+                                barriers only; for widths whose two vectors fit 160 KiB (square
+                                m <= 12, triangular m <= 13 at lanes_v 1), else
+                                CHROM_EUNSUPPORTED.  waves_per_block may also be 16. */
   CHROM_MODE_GROUPED = 4,    /* every step one grouped launch; the whole sweep one hipGraph */
 };
 
-/* Launch shape of the batched, graph and grouped kernels (and of the
- * coefficient form).  Zero fields take the library's defaults.  Every
+/* Launch shape of the batched, graph, grouped and resident kernels (and of
+ * the coefficient form).  Zero fields take the library's defaults.  Every
  * choice gives bit-identical results. */
 typedef struct chrom_tuning {
   int lanes_v;          /* instances per lane: 1, 2 or 4 (chunk width W = 64 * lanes_v);
-                           the coefficient form also takes 8, with unroll 4 */
+                           the coefficient form also takes 8, with unroll 4; resident
+                           mode: instances per workgroup */
   int targets_per_wave; /* consecutive target states handled by one wavefront, 1..63 */
   int waves_per_block;  /* wavefronts per workgroup: 1, 2, 4 or 8 */
   int xcd_order;        /* 0 = default, 1 = hardware round-robin, 2 = contiguous tile range per XCD,
@@ -109,9 +115,9 @@ int chromatic_strip(int lattice, int m, int n_max,
                     const uint32_t* primes, int np,
                     uint32_t* out);
 
-/* Same result through the batched path (mode CHROM_MODE_BATCHED, GRAPH or
- * GROUPED), synchronous, host buffers, internal allocation.  tune may be
- * NULL. */
+/* Same result through the batched path (mode CHROM_MODE_BATCHED, GRAPH,
+ * RESIDENT or GROUPED), synchronous, host buffers, internal allocation.
+ * tune may be NULL. */
 int chromatic_strip_batched(int lattice, int m, int n_max,
                             const uint32_t* q_points, int nq,
                             const uint32_t* primes, int np,
@@ -192,10 +198,13 @@ int chromatic_prepare(int lattice, int m);
 
 /* Builds the host copy of the factor maps of (lattice, m) only, in the
  * evaluation form (normalised = 0) or the coefficient form (normalised = 1,
- * eq. Z_modified); touches no device.  Builds of different map sets run
- * concurrently, so a second host thread may prepare the next width while
- * device work for another is queued; a call for a set already being built
- * waits for it.  Returns 0 or CHROM_EINVAL. */
+ * eq. Z_modified); touches no device.  Host map builds are serialized: one
+ * map set builds at a time in the process (each build is itself threaded,
+ * CHROMSTRIP_THREADS), and a call for a set already built returns at once.
+ * Not supported concurrently with other calls of this library from another
+ * host thread: a run that did so once crashed in the caller's interpreter
+ * and the cause was not found, so call it from the thread that makes the
+ * library's other calls.  Returns 0 or CHROM_EINVAL. */
 int chromatic_prepare_host(int lattice, int m, int normalised);
 
 /* Builds the coefficient form's factor maps of (lattice, m) on the current

@@ -13,7 +13,7 @@ HEADER = os.path.join(os.path.dirname(PKG), "include", "chromstrip.h")
 CHROM_OK = 0
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED"}
 SQUARE, TRIANGULAR = 0, 1
-MODES = {"plain": 0, "batched": 1, "graph": 2, "persistent": 3, "grouped": 4}
+MODES = {"plain": 0, "batched": 1, "graph": 2, "resident": 3, "grouped": 4}
 SPACE_NCNNN, SPACE_SQ_INTER, SPACE_LAST = 0, 1, 2
 
 

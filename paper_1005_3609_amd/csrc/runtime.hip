@@ -14,7 +14,8 @@
 // Sections: device copies of the maps and the device map build; constants
 // and job layouts; step programs (setup, rows, read-out); launches, chunk
 // groups on parallel streams and hipGraph row replay; grouped launches for
-// batches and the server; the plain per-instance path; the C ABI.
+// batches and the server; the resident mode (a whole strip per launch, the
+// state vectors in LDS); the plain per-instance path; the C ABI.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,6 +33,7 @@
 #include "devexpand.hpp"
 #include "kernels.hpp"
 #include "maps.hpp"
+#include "resident.hpp"
 #include "states.hpp"
 
 namespace cs {
@@ -98,6 +100,11 @@ struct DevStagedSet {
   void* base = nullptr;
   std::vector<DevStaged> fac;
 };
+// A family's factors and the read-out maps in sliced-ELL form (resident.hpp).
+struct DevSellSet {
+  void* base = nullptr;
+  std::vector<DevSell> fac, last;
+};
 
 struct DevFamily {
   int k = 1;
@@ -109,6 +116,8 @@ struct DevFamily {
   // staged copies, one set per (slot limit, rows per tile), built on first use
   mutable std::mutex st_mu;
   mutable std::map<std::pair<int, int>, std::unique_ptr<DevStagedSet>> staged;
+  // sliced-ELL copies of the factors and read-out maps (resident mode), built on first use
+  mutable std::unique_ptr<struct DevSellSet> sell;
 };
 
 struct DevMaps {
@@ -834,7 +843,6 @@ const DevStagedSet& dev_staged(const DevMaps& dm, const DevFamily& fam, int slot
   return ref;
 }
 
-// Host-side sizes without building device copies.
 struct Sizes {
   int64_t s_nc, s_max;
 };
@@ -845,6 +853,101 @@ Sizes space_sizes(int lattice, int m) {
   return s;
 }
 
+// Sliced-ELL form of a gather-form map (resident.hpp): rows sorted by their
+// entries with coefficient other than +-1, then by their +-1 entries (most
+// first, ties in row order), slices of 64 rows; a slice stores its rows' +-1
+// entries column-major, padded to the slice's most, then the others likewise.
+// Padding entries read row `zero_row` with code 0.
+struct HostSell {
+  std::vector<int32_t> perm, slice;   // slice: (offset, unit columns, other columns, 0)
+  std::vector<uint32_t> ent;
+  int nslice = 0;
+};
+
+HostSell build_sell(const Csr& c, uint32_t zero_row) {
+  HostSell h;
+  const int64_t n = c.n_rows;
+  auto unit = [](uint32_t w) { return (w >> kEntSrcBits) <= 1u; };
+  std::vector<int32_t> nu(n, 0), ng(n, 0);
+  for (int64_t r = 0; r < n; ++r)
+    for (int32_t e = c.row_ptr[r]; e < c.row_ptr[r + 1]; ++e) (unit(c.ent[e]) ? nu[r] : ng[r]) += 1;
+  std::vector<int32_t> order(n);
+  for (int64_t r = 0; r < n; ++r) order[r] = static_cast<int32_t>(r);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return ng[a] != ng[b] ? ng[a] > ng[b] : nu[a] > nu[b]; });
+  h.nslice = static_cast<int>((n + 63) / 64);
+  h.perm.assign(static_cast<size_t>(h.nslice) * 64, -1);
+  const uint32_t pad = zero_row;   // code 0
+  for (int s = 0; s < h.nslice; ++s) {
+    const int64_t r0 = static_cast<int64_t>(s) * 64;
+    int U = 0, G = 0;
+    for (int l = 0; l < 64 && r0 + l < n; ++l) {
+      h.perm[r0 + l] = order[r0 + l];
+      U = std::max(U, nu[order[r0 + l]]);
+      G = std::max(G, ng[order[r0 + l]]);
+    }
+    h.slice.insert(h.slice.end(), {static_cast<int32_t>(h.ent.size()), U, G, 0});
+    for (int pass = 0; pass < 2; ++pass) {
+      const int cols = pass == 0 ? U : G;
+      const size_t base = h.ent.size();
+      h.ent.resize(base + static_cast<size_t>(cols) * 64, pad);
+      for (int l = 0; l < 64; ++l) {
+        const int32_t r = h.perm[r0 + l];
+        if (r < 0) continue;
+        int u = 0;
+        for (int32_t e = c.row_ptr[r]; e < c.row_ptr[r + 1]; ++e)
+          if (unit(c.ent[e]) == (pass == 0)) h.ent[base + static_cast<size_t>(u++) * 64 + l] = c.ent[e];
+      }
+    }
+  }
+  if (h.ent.size() >= (size_t(1) << 31)) throw std::runtime_error("sliced-ELL map too large");
+  return h;
+}
+
+// The family's forward factors and the read-out maps of (lattice, m) in
+// sliced-ELL form on the device, padding entries reading row s_max (kept at
+// zero by the resident kernel).
+const DevSellSet& dev_sell(const DevMaps& dm, const DevFamily& fam) {
+  std::lock_guard<std::mutex> lk(fam.st_mu);
+  if (fam.sell) return *fam.sell;
+  if (dm.normalised) throw std::runtime_error("resident mode runs the evaluation form only");
+  const MapSet& ms = get_maps(dm.lattice, dm.m);
+  const std::vector<Csr>& fwd = (fam.k == 1) ? ms.fwd : ms.family(fam.k).fac;
+  std::vector<HostSell> hs;
+  std::vector<const Csr*> src;
+  for (const Csr& c : fwd) src.push_back(&c);
+  for (int i = 0; i < dm.m; ++i) src.push_back(&ms.last[i]);
+  size_t bytes = 0;
+  for (const Csr* c : src) {
+    hs.push_back(build_sell(*c, static_cast<uint32_t>(space_sizes(dm.lattice, dm.m).s_max)));
+    const HostSell& h = hs.back();
+    bytes += align_up(h.perm.size() * 4 + 4) + align_up(h.slice.size() * 4 + 4) + align_up(h.ent.size() * 4 + 4);
+  }
+  auto set = std::make_unique<DevSellSet>();
+  if (hipMalloc(&set->base, bytes) != hipSuccess) throw MemError("device allocation of sliced-ELL maps failed");
+  char* cur = static_cast<char*>(set->base);
+  auto put = [&](const void* data, size_t n) {
+    void* dst = cur;
+    if (n) HIPX(hipMemcpy(dst, data, n, hipMemcpyHostToDevice));
+    cur += align_up(n + 4);
+    return dst;
+  };
+  for (size_t i = 0; i < src.size(); ++i) {
+    const HostSell& h = hs[i];
+    DevSell d{};
+    d.perm = static_cast<const int32_t*>(put(h.perm.data(), h.perm.size() * 4));
+    d.slice = static_cast<const int32_t*>(put(h.slice.data(), h.slice.size() * 4));
+    d.ent = static_cast<const uint32_t*>(put(h.ent.data(), h.ent.size() * 4));
+    d.n_rows = static_cast<int>(src[i]->n_rows);
+    d.n_cols = static_cast<int>(src[i]->n_cols);
+    d.nslice = h.nslice;
+    (i < fwd.size() ? set->fac : set->last).push_back(d);
+  }
+  fam.sell = std::move(set);
+  return *fam.sell;
+}
+
+// Host-side sizes without building device copies.
 // ---------------------------------------------------------------------------
 // Pinned staging buffers for host-to-device uploads on a stream
 // ---------------------------------------------------------------------------
@@ -938,7 +1041,9 @@ struct Tune {
 
 // lanes_v 8 (512 coefficient slots per row) exists for the coefficient form
 // only: `series` admits it.
-Tune resolve(const chrom_tuning* t, bool series = false) {
+// Resident mode (`resident`): lanes_v is the number of instances per
+// workgroup (1, 2 or 4) and waves_per_block may also be 16.
+Tune resolve(const chrom_tuning* t, bool series = false, bool resident = false) {
   Tune r;
   if (!t) return r;
   if (t->lanes_v) r.V = t->lanes_v;
@@ -960,7 +1065,8 @@ Tune resolve(const chrom_tuning* t, bool series = false) {
     throw ArgError(series ? "lanes_v must be 1, 2, 4 or 8" : "lanes_v must be 1, 2 or 4");
   }
   if (r.rpw < 1 || r.rpw > 63) throw ArgError("targets_per_wave must be in 1..63");
-  if (r.wpb != 1 && r.wpb != 2 && r.wpb != 4 && r.wpb != 8) throw ArgError("waves_per_block must be 1, 2, 4 or 8");
+  if (r.wpb != 1 && r.wpb != 2 && r.wpb != 4 && r.wpb != 8 && !(resident && r.wpb == 16))
+    throw ArgError(resident ? "waves_per_block must be 1, 2, 4, 8 or 16" : "waves_per_block must be 1, 2, 4 or 8");
   return r;
 }
 
@@ -1172,12 +1278,7 @@ JobPtrs job_ptrs(const JobLayout& L, void* base) {
 }
 
 
-// The persistent work-queue mode (workgroups waiting on completion counters
-// of other workgroups) is switched off: it stalled on the device.  Grouped
-// launches replace it.
 void check_mode(int mode) {
-  if (mode == CHROM_MODE_PERSISTENT)
-    throw std::runtime_error("the persistent work-queue mode is disabled; use CHROM_MODE_GROUPED");
   if (mode < CHROM_MODE_PLAIN || mode > CHROM_MODE_GROUPED) throw ArgError("unknown mode");
 }
 
@@ -1765,23 +1866,36 @@ void launch_stages(const StageImage& im, const Step* d_steps, const int* d_tiles
   }
 }
 
-// One cached graph per stage-table location; a different table at the same
-// location replaces it once the stream that last launched it has drained.
+// One cached graph per stage-table location.  The graph's kernels read the
+// stage tables from caller memory at `base`, so the tables are uploaded again
+// before every launch (the caller may have reused that memory since); the
+// cache only saves the capture and instantiation.  `done` is a library-owned
+// event recorded after every launch of the graph: a replaced graph is
+// destroyed once that event has completed, without touching the caller's
+// stream (which may no longer exist).
 struct StageGraph {
   uint64_t hash = 0;
   hipGraphExec_t exec = nullptr;
-  hipStream_t last = nullptr;
+  hipEvent_t done = nullptr;
 };
 std::mutex g_sgraph_mu;
 std::map<void*, StageGraph> g_sgraphs;
+
+void retire_stage_graph(StageGraph& g) {
+  if (g.done) {
+    (void)hipEventSynchronize(g.done);
+    (void)hipEventDestroy(g.done);
+  }
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  g = StageGraph{};
+}
 
 void drop_stage_graphs_in(void* lo, size_t bytes) {
   std::lock_guard<std::mutex> lk(g_sgraph_mu);
   for (auto it = g_sgraphs.begin(); it != g_sgraphs.end();) {
     char* k = static_cast<char*>(it->first);
     if (k >= static_cast<char*>(lo) && k < static_cast<char*>(lo) + bytes) {
-      (void)hipStreamSynchronize(it->second.last);
-      (void)hipGraphExecDestroy(it->second.exec);
+      retire_stage_graph(it->second);
       it = g_sgraphs.erase(it);
     } else {
       ++it;
@@ -1828,28 +1942,27 @@ void run_grouped(const std::vector<const Program*>& progs, const Tune& t, void* 
     cg.n = static_cast<int>(ims.size());
     for_groups(cg, s0, capture, [&](int g, hipStream_t s) { launch_stages(ims[g], d_steps[g], d_tiles[g], t, s); });
   };
+  upload_all();
   if (!as_graph) {
-    upload_all();
     launch_all(st, false);
     return;
   }
   hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_sgraph_mu);
     auto it = g_sgraphs.find(base);
     if (it != g_sgraphs.end()) {
       if (it->second.hash == h) {
         exec = it->second.exec;
-        it->second.last = st;
+        done = it->second.done;
       } else {
-        HIPX(hipStreamSynchronize(it->second.last));
-        HIPX(hipGraphExecDestroy(it->second.exec));
+        retire_stage_graph(it->second);
         g_sgraphs.erase(it);
       }
     }
   }
   if (!exec) {
-    upload_all();
     hipStream_t cs = capture_stream();
     HIPX(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     launch_all(cs, true);
@@ -1857,10 +1970,12 @@ void run_grouped(const std::vector<const Program*>& progs, const Tune& t, void* 
     HIPX(hipStreamEndCapture(cs, &graph));
     HIPX(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     HIPX(hipGraphDestroy(graph));
+    HIPX(hipEventCreateWithFlags(&done, hipEventDisableTiming));
     std::lock_guard<std::mutex> lk(g_sgraph_mu);
-    g_sgraphs[base] = StageGraph{h, exec, st};
+    g_sgraphs[base] = StageGraph{h, exec, done};
   }
   HIPX(hipGraphLaunch(exec, st));
+  HIPX(hipEventRecord(done, st));
 }
 
 int n_factors(int m, int fuse) { return (m + fuse - 1) / fuse; }
@@ -1935,6 +2050,177 @@ void run_plain(const DevMaps& dm, int lattice, int m, int n_max, const std::vect
 }
 
 // ---------------------------------------------------------------------------
+// Resident mode: one launch per strip (or per batch of strips); workgroup g
+// holds K instances' state vectors in LDS (resident.hpp)
+// ---------------------------------------------------------------------------
+constexpr size_t kResMaxLds = 160 * 1024;
+
+// Workspace of one resident job: per-instance code values and quotients,
+// p, -p^{-1}, 2^32 mod p, and the read-out vector [I][s_nc].
+struct ResLayout {
+  int I = 0, K = 1, ngroups = 0;
+  int64_t s_nc = 0, s_max = 0;
+  size_t coef = 0, coefs = 0, p = 0, pinv = 0, r1 = 0, w = 0, bytes = 0;
+};
+
+ResLayout res_layout(int lattice, int m, int I, const Tune& t) {
+  ResLayout L;
+  L.I = I;
+  L.K = t.V;
+  L.ngroups = (I + L.K - 1) / L.K;
+  Sizes s = space_sizes(lattice, m);
+  L.s_nc = s.s_nc;
+  L.s_max = s.s_max;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    size_t o = off;
+    off += align_up(b);
+    return o;
+  };
+  L.coef = take(static_cast<size_t>(I) * kMaxCodes * 4);
+  L.coefs = take(static_cast<size_t>(I) * kMaxCodes * 4);
+  L.p = take(static_cast<size_t>(I) * 4);
+  L.pinv = take(static_cast<size_t>(I) * 4);
+  L.r1 = take(static_cast<size_t>(I) * 4);
+  L.w = take(static_cast<size_t>(I) * L.s_nc * 4);
+  L.bytes = off;
+  return L;
+}
+
+// Host image of the constants region [coef .. w) of a resident job: every
+// code's value at each instance's q (the family's codes are polynomials in q
+// with the base table first, so the read-out maps' codes are included).
+std::vector<uint32_t> res_image(const ResLayout& L, const std::vector<Inst>& inst, const std::vector<Poly>& codes) {
+  const int nc = static_cast<int>(codes.size());
+  std::vector<uint32_t> img((L.w - L.coef) / 4, 0);
+  uint32_t* coef = img.data() + (L.coef - L.coef) / 4;
+  uint32_t* coefs = img.data() + (L.coefs - L.coef) / 4;
+  uint32_t* p = img.data() + (L.p - L.coef) / 4;
+  uint32_t* pinv = img.data() + (L.pinv - L.coef) / 4;
+  uint32_t* r1 = img.data() + (L.r1 - L.coef) / 4;
+  for (int i = 0; i < L.I; ++i) {
+    const Inst& in = inst[i];
+    for (int c = 0; c < nc; ++c) {
+      const uint32_t v = coef_mod(codes[c], in.q, in.p);
+      coef[static_cast<size_t>(i) * nc + c] = v;
+      coefs[static_cast<size_t>(i) * nc + c] = shoup_of(v, in.p);
+    }
+    p[i] = in.p;
+    pinv[i] = neg_inv_2_32(in.p);
+    r1[i] = static_cast<uint32_t>((uint64_t(1) << 32) % in.p);
+  }
+  return img;
+}
+
+// The job record of one strip whose resident workspace starts at `base`;
+// checks that the spaces fit the kernel's LDS and chain as the kernel
+// assumes: it reads only rows the step before it wrote (the factors map
+// NCNNN -> ... -> NCNNN, the read-out maps chain from their first space down
+// to the NCNNN space, all within the LDS vectors).
+ResidentJob resident_job(const DevMaps& dm, const DevFamily& fam, const ResLayout& L, void* base, int n_max,
+                         uint32_t* d_out, int g0, size_t& lds) {
+  if (dm.m > kResMaxM) throw std::runtime_error("resident mode: m above the kernel's limit");
+  const DevSellSet& sell = dev_sell(dm, fam);
+  const int nf = static_cast<int>(sell.fac.size());
+  const int nc = static_cast<int>(fam.codes.size());
+  if (nf < 1 || nf > kResMaxM || nc > kMaxCodes) throw std::runtime_error("resident mode: factor family out of range");
+  lds = resident_lds_bytes(static_cast<int>(L.s_max), nc, L.K);
+  if (lds > kResMaxLds)
+    throw std::runtime_error("resident mode: two state vectors of " + std::to_string(L.s_max) + " states x " +
+                             std::to_string(L.K) + " instances need " + std::to_string(lds) +
+                             " bytes of LDS, more than the 160 KiB a workgroup can hold");
+  ResidentJob J{};
+  for (int f = 0; f < nf; ++f) {
+    const DevSell& c = sell.fac[f];
+    const int64_t want_cols = f == 0 ? L.s_nc : sell.fac[f - 1].n_rows;
+    if (c.n_rows > L.s_max || c.n_cols != want_cols || (f == nf - 1 && c.n_rows != L.s_nc))
+      throw std::runtime_error("resident mode: factor spaces do not chain");
+    J.fac[f] = c;
+  }
+  for (int i = 0; i < dm.m; ++i) {
+    const DevSell& c = sell.last[i];
+    if (c.n_rows > L.s_max || c.n_cols > L.s_max || (i + 1 < dm.m && c.n_cols != sell.last[i + 1].n_rows))
+      throw std::runtime_error("resident mode: read-out spaces do not chain");
+    J.last[i] = c;
+  }
+  if (sell.last[0].n_rows != L.s_nc) throw std::runtime_error("resident mode: read-out vector size mismatch");
+  char* b = static_cast<char*>(base);
+  J.nf = nf;
+  J.m = dm.m;
+  J.s_nc = static_cast<int>(L.s_nc);
+  J.s_max = static_cast<int>(L.s_max);
+  J.n_max = n_max;
+  J.I = L.I;
+  J.ncodes = nc;
+  J.g0 = g0;
+  J.ngroups = L.ngroups;
+  J.coef = reinterpret_cast<const uint32_t*>(b + L.coef);
+  J.coefs = reinterpret_cast<const uint32_t*>(b + L.coefs);
+  J.p = reinterpret_cast<const uint32_t*>(b + L.p);
+  J.pinv = reinterpret_cast<const uint32_t*>(b + L.pinv);
+  J.r1 = reinterpret_cast<const uint32_t*>(b + L.r1);
+  J.w = reinterpret_cast<uint32_t*>(b + L.w);
+  J.out = d_out;
+  return J;
+}
+
+// Lifts the dynamic-LDS limit of k_resident<K> to 160 KiB once per device.
+template <int K>
+void allow_resident_lds() {
+  static bool done[64] = {false};
+  static std::mutex mu;
+  int dev = 0;
+  HIPX(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  if (done[dev]) return;
+  HIPX(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_resident<K>),
+                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kResMaxLds)));
+  done[dev] = true;
+}
+
+// Uploads the job table to `table` and launches every job's workgroups at
+// once (one launch: no workgroup waits on another).
+void run_resident(const std::vector<ResidentJob>& jobs, size_t lds, const Tune& t, void* table, hipStream_t st) {
+  if (jobs.empty()) return;
+  int total = 0;
+  for (const ResidentJob& J : jobs) total = std::max(total, J.g0 + J.ngroups);
+  if (total < 1) return;
+  upload(table, jobs.data(), jobs.size() * sizeof(ResidentJob), st);
+  const ResidentJob* d = static_cast<const ResidentJob*>(table);
+  const int nj = static_cast<int>(jobs.size());
+  dim3 grid(total), block(64 * t.wpb);
+  switch (t.V) {
+    case 1:
+      allow_resident_lds<1>();
+      hipLaunchKernelGGL(k_resident<1>, grid, block, lds, st, d, nj);
+      break;
+    case 2:
+      allow_resident_lds<2>();
+      hipLaunchKernelGGL(k_resident<2>, grid, block, lds, st, d, nj);
+      break;
+    default:
+      allow_resident_lds<4>();
+      hipLaunchKernelGGL(k_resident<4>, grid, block, lds, st, d, nj);
+      break;
+  }
+  HIPX(hipGetLastError());
+}
+
+// Refuses, before any device work, a width whose two state vectors alone
+// exceed the LDS a workgroup can hold.
+void check_resident_fits(int lattice, int m, const Tune& t) {
+  const Sizes s = space_sizes(lattice, m);
+  if (resident_lds_bytes(static_cast<int>(s.s_max), 0, t.V) > kResMaxLds)
+    throw std::runtime_error("resident mode: two state vectors of " + std::to_string(s.s_max) + " states x " +
+                             std::to_string(t.V) + " instances exceed the 160 KiB of LDS a workgroup can hold");
+}
+
+size_t resident_workspace_bytes(int lattice, int m, int I, const Tune& t) {
+  check_resident_fits(lattice, m, t);
+  return res_layout(lattice, m, I, t).bytes + align_up(sizeof(ResidentJob));
+}
+
+// ---------------------------------------------------------------------------
 // Strip front end shared by the sync and async calls
 // ---------------------------------------------------------------------------
 int rows_tile_of(const Tune& t) { return t.rpw * t.wpb; }
@@ -1947,6 +2233,7 @@ void bind_staging(JobCtx& j, int mode) {
 
 size_t workspace_bytes(int lattice, int m, int I, int n_max_hint, int mode, const Tune& t) {
   if (mode == CHROM_MODE_PLAIN) return plain_layout(lattice, m).bytes;
+  if (mode == CHROM_MODE_RESIDENT) return resident_workspace_bytes(lattice, m, I, t);
   JobLayout L = job_layout(lattice, m, I, t, kMaxCodes, rows_tile_of(t));
   size_t b = L.bytes + 256;  // + graph row counter
   if (mode == CHROM_MODE_GROUPED) {
@@ -1961,7 +2248,8 @@ int strip_async_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, c
   check_args(lattice, m, n_max);
   check_mode(mode);
   std::vector<Inst> inst = make_instances(q, nq, p, np);
-  Tune t = resolve(tune);
+  Tune t = resolve(tune, false, mode == CHROM_MODE_RESIDENT);
+  if (mode == CHROM_MODE_RESIDENT) check_resident_fits(lattice, m, t);
   if (n_max == 0) return CHROM_OK;
   if (!ws || !d_out) throw ArgError("null workspace or output");
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) throw ArgError("workspace must be 256-byte aligned");
@@ -1972,6 +2260,16 @@ int strip_async_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, c
   const DevMaps& dm = dev_maps(lattice, m);
   if (mode == CHROM_MODE_PLAIN) {
     run_plain(dm, lattice, m, n_max, inst, ws, st, d_out);
+    return CHROM_OK;
+  }
+  if (mode == CHROM_MODE_RESIDENT) {
+    const DevFamily& fam = dev_family(dm, t.fuse);
+    ResLayout R = res_layout(lattice, m, I, t);
+    size_t lds = 0;
+    std::vector<ResidentJob> jobs{resident_job(dm, fam, R, ws, n_max, d_out, 0, lds)};
+    std::vector<uint32_t> img = res_image(R, inst, fam.codes);
+    upload(static_cast<char*>(ws) + R.coef, img.data(), img.size() * 4, st);
+    run_resident(jobs, lds, t, static_cast<char*>(ws) + R.bytes, st);
     return CHROM_OK;
   }
   JobCtx j;
@@ -2015,7 +2313,8 @@ int strip_sync_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, co
   std::vector<Inst> inst = make_instances(q, nq, p, np);
   if (n_max == 0) return CHROM_OK;
   if (!out) throw ArgError("null output");
-  Tune t = resolve(tune);
+  Tune t = resolve(tune, false, mode == CHROM_MODE_RESIDENT);
+  if (mode == CHROM_MODE_RESIDENT) check_resident_fits(lattice, m, t);
   const int I = static_cast<int>(inst.size());
   const size_t wsb = workspace_bytes(lattice, m, I, n_max, mode, t);
   DevBuf ws(wsb);
@@ -2360,7 +2659,7 @@ size_t chromatic_workspace_bytes(int lattice, int m, int n_max, int nq, int np, 
     check_args(lattice, m, n_max);
     if (nq < 1 || np < 1) throw ArgError("need nq, np >= 1");
     check_mode(mode);
-    Tune t = resolve(tune);
+    Tune t = resolve(tune, false, mode == CHROM_MODE_RESIDENT);
     r = workspace_bytes(lattice, m, nq * np, n_max, mode, t);
     return CHROM_OK;
   });
@@ -2482,6 +2781,7 @@ void chromatic_release_maps(void) {
       (void)hipDeviceSynchronize();
       for (auto& fam : kv.second->fam) {
         for (auto& st : fam.second->staged) (void)hipFree(st.second->base);
+        if (fam.second->sell) (void)hipFree(fam.second->sell->base);
         if (fam.second->base) (void)hipFree(fam.second->base);
       }
       (void)hipFree(kv.second->base);

@@ -19,13 +19,7 @@ pytestmark = pytest.mark.gpu
 
 P31 = 2 ** 31 - 1
 HERE = os.path.dirname(os.path.abspath(__file__))
-MODES = ["plain", "batched", "graph", "grouped"]
-# The persistent work-queue path stalled on the GPU twice (the smoke check,
-# square 4x5, 21 instances) and its cause was not found; the path is
-# switched off (the library returns CHROM_EUNSUPPORTED) and its cases stay
-# here, skipped.
-PERSISTENT_OFF = pytest.mark.skip(reason="persistent work-queue path switched off after it stalled on the GPU "
-                                         "(square 4x5 smoke); cause not found")
+MODES = ["plain", "batched", "graph", "grouped", "resident"]
 
 
 def _golden(name):
@@ -142,7 +136,7 @@ def test_square_m10_plain_and_batched():
     w = W.workload("square_m10")
     lat, m, n = w["strips"][0]
     want = OT.chromatic_grid(lat, m, n, w["q_points"], w["primes"])
-    for mode in ("plain", "batched"):
+    for mode in ("plain", "batched", "resident"):
         got = api.strip(lat, m, n, w["q_points"], w["primes"], mode=mode).astype(np.int64)
         np.testing.assert_array_equal(got, want, err_msg=mode)
 
@@ -153,7 +147,7 @@ def test_square_m10_plain_and_batched():
 def test_triangular_m12_against_stored_oracle():
     w = W.workload("triangular_m12")
     g = _golden("oracle_triangular_12x13.json")
-    for mode in ("graph", "grouped"):
+    for mode in ("graph", "grouped", "resident"):
         got = api.strip("triangular", 12, 13, w["q_points"], w["primes"], mode=mode)
         np.testing.assert_array_equal(_sampled(got, g), np.array(g["z"], dtype=np.int64), err_msg=mode)
         # invariants at every length: P(1) = 0; P(2) = 0 and P(3) = 6 for r >= 2
@@ -240,18 +234,47 @@ def test_square_18x19_against_transposed_oracle():
 
 
 # ---------------------------------------------------------------------------
-# Persistent work-queue path: switched off, cases kept
+# Resident mode: the whole strip in one launch, state vectors in LDS (the
+# square 4 x 5 case and the m = 5 strips once ran a work-queue design that
+# stalled; this kernel has no inter-workgroup waits)
 # ---------------------------------------------------------------------------
-@PERSISTENT_OFF
-def test_persistent_square_4x5():
+def test_resident_square_4x5():
     q = list(range(21))
-    got = api.strip("square", 4, 5, q, [P31], mode="persistent").astype(np.int64)
+    got = api.strip("square", 4, 5, q, [P31], mode="resident").astype(np.int64)
     np.testing.assert_array_equal(got, OT.chromatic_grid("square", 4, 5, q, [P31]))
 
 
-@PERSISTENT_OFF
 @pytest.mark.parametrize("lat", ["square", "triangular"])
-def test_persistent_small_widths(lat):
+def test_resident_small_widths(lat):
     q, p = list(range(0, 35)), [P31, 1000000007]
-    got = api.strip(lat, 5, 6, q, p, mode="persistent").astype(np.int64)
+    got = api.strip(lat, 5, 6, q, p, mode="resident").astype(np.int64)
     np.testing.assert_array_equal(got, OT.chromatic_grid(lat, 5, 6, q, p))
+
+
+@pytest.mark.parametrize("tune", [
+    dict(lanes_v=1, waves_per_block=1),
+    dict(lanes_v=1, waves_per_block=16),
+    dict(lanes_v=2, waves_per_block=4),
+    dict(lanes_v=4, waves_per_block=8),
+    dict(lanes_v=4, waves_per_block=2, fuse=2),
+    dict(lanes_v=1, waves_per_block=8, fuse=2),
+    dict(lanes_v=2, waves_per_block=16, fuse=3),
+    dict(lanes_v=1, waves_per_block=4, fuse=3),
+])
+@pytest.mark.parametrize("lat", ["square", "triangular"])
+def test_resident_tuning_choices_are_bit_identical(lat, tune):
+    q = list(range(1, 44))                      # 43 q x 3 p = 129 instances: ragged groups at lanes_v 2, 4
+    p = [P31, 998244353, 1000000007]
+    want = OT.chromatic_grid(lat, 7, 5, q, p)
+    got = api.strip(lat, 7, 5, q, p, mode="resident", tuning=tune).astype(np.int64)
+    np.testing.assert_array_equal(got, want, err_msg=f"{lat} {tune}")
+
+
+def test_resident_largest_widths():
+    # the widest strips whose vectors fit: square m = 12 and triangular m = 13
+    # (one instance per workgroup), against the live oracle on a few instances
+    for lat, m in (("square", 12), ("triangular", 13)):
+        q, p = [1, 2, 3, 7, 40], [P31, 998244353]
+        want = OT.chromatic_grid(lat, m, 4, q, p)
+        got = api.strip(lat, m, 4, q, p, mode="resident", tuning=dict(lanes_v=1, waves_per_block=16))
+        np.testing.assert_array_equal(got.astype(np.int64), want, err_msg=f"{lat} {m}")

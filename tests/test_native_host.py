@@ -212,7 +212,13 @@ def test_bad_arguments_are_errors_without_touching_a_gpu():
     assert api.lib().chromatic_workspace_bytes(0, 0, 5, 3, 1, 1, None) == 0
     with pytest.raises(api.ChromError):
         api.strip("square", 4, 3, [1, 2], [P31], mode="batched", tuning={"lanes_v": 3})
-    # the persistent work-queue mode is switched off and says so before any device work
-    with pytest.raises(api.ChromError, match="disabled"):
-        api.strip("square", 4, 3, [1, 2], [P31], mode="persistent")
-    assert api.lib().chromatic_workspace_bytes(0, 4, 3, 2, 1, 3, None) == 0
+    # resident mode: widths whose two state vectors do not fit a workgroup's
+    # 160 KiB of LDS are refused before any device work
+    with pytest.raises(api.ChromError, match="LDS"):
+        api.strip("square", 13, 3, [1, 2], [P31], mode="resident")
+    with pytest.raises(api.ChromError, match="LDS"):
+        api.strip("triangular", 12, 3, [1, 2], [P31], mode="resident", tuning={"lanes_v": 4})
+    assert api.lib().chromatic_workspace_bytes(0, 4, 3, 2, 1, 3, None) > 0
+    assert api.lib().chromatic_workspace_bytes(0, 13, 3, 2, 1, 3, None) == 0
+    with pytest.raises(api.ChromError, match="waves_per_block"):
+        api.strip("square", 4, 3, [1, 2], [P31], mode="batched", tuning={"waves_per_block": 16})
