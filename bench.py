@@ -6,10 +6,13 @@ inputs and maps resident in HBM.  One step = one whole sweep: read-out vector
 build (T_last), x = e_0, 14 rows of T_14 ... T_1 with the read-out of every
 row, launched as a hipGraph row replay with the autotuned launch shape.
 
-A state-update is one target residue written by one forward per-site factor
-T_i for one instance; a step performs 14 rows x 787 333 targets x 640
-instances = 7.05e9 of them (a launch that applies a precomputed product of
-two factors counts the updates of both).
+A state-update is one target residue written by a factor launch for one
+instance.  `value` counts the residues the step's launches actually write:
+with single factors, 14 rows x 787 333 targets x 640 instances = 7.05e9;
+a launch that applies a precomputed product of two factors writes only the
+product's targets, so fused steps write about half as many.  The count of
+per-site factor updates the step performs (every T_i's targets, written or
+not) is reported beside it under its own key.
 
 Printed: one JSON line with the headline value, the roofline of the factor
 kernel (timed alone with HIP events on its launch stream), the plain
@@ -65,25 +68,62 @@ def row_bytes(sizes, ipad, s_nc):
     return total
 
 
-def cpu_baseline(lat, m, q_points, primes, n_inst=64):
-    """The oracle, unchanged, applying one transfer row T_m ... T_1 to a dense
-    seeded state vector over all NCNNN states, for the first n_inst of the
-    workload's instances (single process)."""
+def _oracle_row(args):
+    """One transfer row T_m ... T_1 of the unchanged oracle applied to a dense
+    seeded vector over all NCNNN states, for the given instances; returns
+    (seconds, per-site factor updates)."""
+    lat, m, inst, seed = args
     import numpy as np
 
     from oracle import partitions as OP
     from oracle import transfer as OT
-    from paper_1005_3609_amd import workloads as W
-    inst = W.instances(q_points, primes)[:n_inst]
     alg = OT.Residues([a for a, _ in inst], [b for _, b in inst])
-    rng = np.random.default_rng(W.SEED_BASE + 77)
+    rng = np.random.default_rng(seed)
     vec = {s: rng.integers(0, alg.p) for s in OP.ncnnn_in_paper_order(m)}
     factor = OT.factor_square if lat == "square" else OT.factor_triangular
     t0 = time.perf_counter()
+    upd = 0
     for i in range(1, m + 1):
         vec = factor(vec, i, m, alg)
-    dt = time.perf_counter() - t0
-    return dt, n_inst
+        upd += len(vec)
+    return time.perf_counter() - t0, upd * len(inst)
+
+
+def cpu_baseline(lat, m, q_points, primes):
+    """The oracle (unchanged) on the host cores: one transfer row of the
+    strip for all of the workload's instances, (a) one process per prime
+    (the instance groups of the survey's plan) in parallel, (b) all
+    instances in one process.  Returns the cpu_baseline record."""
+    import multiprocessing as mp
+    import platform
+    import subprocess
+
+    import numpy as np
+
+    from paper_1005_3609_amd import workloads as W
+    inst = W.instances(q_points, primes)
+    groups = [[x for x in inst if x[1] == p] for p in primes]
+    procs = min(len(groups), os.cpu_count() or 1, 16)
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(procs) as pool:
+        res = pool.map(_oracle_row, [(lat, m, g, W.SEED_BASE + 77) for g in groups])
+    wall = time.perf_counter() - t0
+    upd_all = sum(u for _, u in res)
+    t_one, upd_one = _oracle_row((lat, m, inst, W.SEED_BASE + 77))
+    model = ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        model = next((ln.split(":", 1)[1].strip() for ln in out.splitlines() if ln.startswith("Model name")), "")
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return {"value": upd_all / wall, "unit": "state-updates/s", "cores": procs, "kind": "oracle",
+            "sample": f"one transfer row (T_{m}..T_1) of the {lat} m={m} strip applied to a dense seeded vector over "
+                      f"all NCNNN states for all {len(inst)} instances, one process per prime ({procs} processes "
+                      f"of {len(inst) // len(primes)} instances, {wall:.1f} s wall, pool start-up included)",
+            "single_core": {"value": upd_one / t_one, "unit": "state-updates/s", "seconds": t_one,
+                            "sample": f"the same row, all {len(inst)} instances in one process"},
+            "host": {"cpu_count": os.cpu_count(), "model": model, "python": platform.python_version(),
+                     "numpy": np.__version__}}
 
 
 def timed(torch, stream, fn, reps=1):
@@ -126,7 +166,17 @@ def measured_traffic(kname, rtune, workload=WORKLOAD):
 
 
 def updates_of(lat, m, n, n_inst):
+    """Per-site factor updates of a strip: every T_i's targets, rows 2..n."""
     return (n - 1) * sum(s for _, s, _ in factor_sizes(lat, m)) * n_inst
+
+
+def written_of(lat, m, n, n_inst, fuse=1):
+    """Residues the strip's factor launches write: the targets of the
+    family's factors (single sites, or products of `fuse` of them)."""
+    if fuse <= 1:
+        return updates_of(lat, m, n, n_inst)
+    nf = -(-m // fuse)
+    return (n - 1) * sum(s for _, s, _ in factor_sizes(lat, m, fuse, nf)) * n_inst
 
 
 def bench_sweep(torch, stream, tune, steps):
@@ -146,15 +196,39 @@ def bench_sweep(torch, stream, tune, steps):
     ms = timed(torch, stream, lambda: api.batch(jobs, tuning=t, workspace=ws, outs=outs, stream=stream), steps)
     I = len(w["q_points"]) * len(w["primes"])
     upd = sum(updates_of(lat, m, n, I) for lat, m, n in w["strips"])
+    wr = sum(written_of(lat, m, n, I, t.get("fuse") or 1) for lat, m, n in w["strips"])
     return {"workload": f"square m=2..14, n=m+1, 640 instances, one graph of grouped launches, tuning {t}",
-            "ms_per_step": ms, "value": upd / (ms / 1e3), "unit": "state-updates/s"}
+            "ms_per_step": ms, "value": wr / (ms / 1e3), "unit": "state-updates/s (residues written)",
+            "per_site_factor_updates_per_s": upd / (ms / 1e3)}
+
+
+def _strip_leg(torch, stream, lat, m, n, q, p, mode, t, steps):
+    """(ms per strip, residues) of one strip in `mode` with tuning t."""
+    from paper_1005_3609_amd import api
+    ws = api.alloc_workspace(api.workspace_bytes(lat, m, n, len(q), len(p), mode, t), None)
+    res = torch.zeros((n, len(q), len(p)), dtype=torch.int32, device=ws.device)
+
+    def run():
+        api.strip_async(lat, m, n, q, p, mode=mode, tuning=t, workspace=ws, out=res, stream=stream)
+    run()
+    ms = timed(torch, stream, run, steps)
+    return ms, api.to_u32(res).astype("int64").reshape(n, len(q), len(p))
+
+
+def _tuned(lat, m, I, n, mode=None):
+    """The tuned table's entry (its mode, its tuning), or the best entry of
+    `mode` recorded in the table's search."""
+    from paper_1005_3609_amd import tune as tuner
+    t = dict(tuner.lookup_tuned(lat, m, I, n) or {})
+    return t.pop("mode", "graph"), {k: v for k, v in t.items() if k != "ms"}
 
 
 def bench_small_configs(torch, stream, steps):
     """The two plain-method workloads: the square 4x5 rectangle at q = 0..20
-    mod 2^31-1 (per-instance launches, checked against P(1) = 0, P(2) = 2),
-    and the square m = 10 strip (rows 1..11) at 80 q x 4 primes, one launch
-    sequence per instance, beside the same 320 instances batched."""
+    mod 2^31-1 and the square m = 10 strip (rows 1..11) at 80 q x 4 primes:
+    one launch sequence per instance (plain), all instances batched in a
+    graph row replay, and the resident mode (the whole strip in one launch,
+    vectors in LDS) with the tuned shape; residues equal across the three."""
     from paper_1005_3609_amd import api
     from paper_1005_3609_amd import workloads as W
     out = {}
@@ -164,45 +238,47 @@ def bench_small_configs(torch, stream, steps):
         q, p = w["q_points"], w["primes"]
         api.prepare(lat, m)
         I = len(q) * len(p)
-        rows = {}
-        from paper_1005_3609_amd import tune as tuner
-        tuned = tuner.lookup_tuned(lat, m, I, n) or {}
-        tuned = {k: v for k, v in tuned.items() if k not in ("mode", "ms")}
-        for mode in ("plain", "graph"):
-            t = tuned if mode == "graph" else None
-            ws = api.alloc_workspace(api.workspace_bytes(lat, m, n, len(q), len(p), mode, t), None)
-            res = torch.zeros((n, len(q), len(p)), dtype=torch.int32, device=ws.device)
-
-            def run():
-                api.strip_async(lat, m, n, q, p, mode=mode, tuning=t, workspace=ws, out=res, stream=stream)
-            run()
-            ms = timed(torch, stream, run, steps)
-            r = api.to_u32(res).astype("int64").reshape(n, len(q), len(p))
+        tmode, tt = _tuned(lat, m, I, n)
+        legs = {"plain": ("plain", None),
+                "graph": ("graph", tt if tmode == "graph" else {}),
+                "resident": ("resident", tt if tmode == "resident" else dict(lanes_v=1, waves_per_block=16))}
+        rows, ref = {}, None
+        for key, (mode, t) in legs.items():
+            ms, r = _strip_leg(torch, stream, lat, m, n, q, p, mode, t, steps)
             q1, q2 = q.index(1), q.index(2)
             assert (r[:, q1, :] == 0).all() and (r[:, q2, :] == 2).all(), f"{name} {mode}: P(1) = 0, P(2) = 2 failed"
-            rows[mode] = {"ms_per_step": ms, "value": updates_of(lat, m, n, I) / (ms / 1e3),
-                          "unit": "state-updates/s"}
+            if ref is None:
+                ref = r
+            assert (r == ref).all(), f"{name}: {mode} differs from the plain path"
+            rows[key] = {"ms_per_step": ms, "value": updates_of(lat, m, n, I) / (ms / 1e3),
+                         "unit": "state-updates/s", "tuning": t}
         rows["workload"] = f"square {m}x{n}, {len(q)} q x {len(p)} primes ({I} instances); plain = one launch " \
-                           f"sequence per instance, graph = all instances batched"
+                           f"sequence per instance, graph = all instances batched, resident = one launch per strip"
         out[name] = rows
     return out
 
 
 def bench_triangular(torch, stream, steps):
+    """The triangular 12x13 strip (48 q x 6 primes): the tuned shape (the
+    resident mode's single launch) beside the graph row replay."""
     from paper_1005_3609_amd import api
     from paper_1005_3609_amd import workloads as W
     w = W.workload("triangular_m12")
     lat, m, n = w["strips"][0]
+    q, p = w["q_points"], w["primes"]
     api.prepare(lat, m)
-    from paper_1005_3609_amd import tune as tuner
-    I = len(w["q_points"]) * len(w["primes"])
-    tune = tuner.lookup_tuned(lat, m, I, n) or {"streams": 3, "unroll": 8}
-    tune = {k: v for k, v in tune.items() if k not in ("mode", "ms")}
-    out, ws = api.strip_async(lat, m, n, w["q_points"], w["primes"], mode="graph", tuning=tune, stream=stream)
-    ms = timed(torch, stream, lambda: api.strip_async(lat, m, n, w["q_points"], w["primes"], mode="graph",
-                                                      tuning=tune, workspace=ws, out=out, stream=stream), steps)
-    return {"workload": f"triangular 12x13, 48 q x 6 primes, graph row replay, tuning {tune}", "ms_per_step": ms,
-            "value": updates_of(lat, m, n, I) / (ms / 1e3), "unit": "state-updates/s"}
+    I = len(q) * len(p)
+    mode, t = _tuned(lat, m, I, n)
+    ms, r = _strip_leg(torch, stream, lat, m, n, q, p, mode, t, steps)
+    assert (r[:, 0, :] == 0).all() and (r[1:, 1, :] == 0).all() and (r[1:, 2, :] == 6).all(), \
+        "triangular invariants P(1) = 0, P(2) = 0, P(3) = 6 failed"
+    g_ms, g = _strip_leg(torch, stream, lat, m, n, q, p, "graph", {"lanes_v": 1, "unroll": 8}, steps)
+    assert (g == r).all(), "graph and tuned paths differ"
+    return {"workload": f"triangular 12x13, 48 q x 6 primes, {mode}, tuning {t}", "ms_per_step": ms,
+            "value": written_of(lat, m, n, I, t.get("fuse") or 1) / (ms / 1e3),
+            "unit": "state-updates/s (residues written)",
+            "per_site_factor_updates_per_s": updates_of(lat, m, n, I) / (ms / 1e3),
+            "graph_row_replay_ms": g_ms}
 
 
 def bench_series(torch, stream, tune, steps):
@@ -325,15 +401,19 @@ def bench_m18(torch, stream, tune, rows):
     """The square 18x19 strip with the workload's 640 instances: one vector is
     8.2 GB, far beyond the 256 MB Infinity Cache, so the factor kernel's
     bandwidth here is HBM bandwidth.  Reports the whole strip (graph mode,
-    the m = 14 tuned shape), the factor kernel timed alone over `rows` rows
-    (one launch per factor step, as in the m = 14 roofline leg), and one
-    (q, p) instance through the plain path (12.8 MB per vector)."""
+    the tuned 18x19 shape), the factor kernel timed alone over `rows` rows
+    (one launch per factor step, all chunks), and one (q, p) instance through
+    the plain path (12.8 MB per vector)."""
     from paper_1005_3609_amd import api
+    from paper_1005_3609_amd import tune as tuner
     from paper_1005_3609_amd import workloads as W
     w = W.workload("square_18x19")
     lat, m, n = w["strips"][0]
     q, p = w["q_points"], w["primes"]
     I = len(q) * len(p)
+    tuned = tuner.lookup_tuned(lat, m, I, n)
+    if tuned:
+        tune = {k: v for k, v in tuned.items() if k not in ("mode", "ms")}
     dev = torch.device("cuda", torch.cuda.current_device())
     t0 = time.time()
     api.prepare(lat, m)
@@ -360,8 +440,9 @@ def bench_m18(torch, stream, tune, rows):
     k_ms = timed(torch, stream, lambda: api.factor_launches(lat, m, q, p, rows, ws_b, rtune, stream))
     del ws_b
     nf = -(-m // fuse)
-    bytes_row = row_bytes(sizes, ipad, s_nc)
-    achieved = rows * bytes_row / (k_ms / 1e3) / 1e9
+    per_site_row = row_bytes(sizes, ipad, s_nc)
+    own_row = per_site_row if fuse == 1 else row_bytes(factor_sizes(lat, m, fuse, nf), ipad, s_nc)
+    achieved = rows * own_row / (k_ms / 1e3) / 1e9
     # one (q, p) instance through the plain path, two rows
     q1, p1 = q[:1], p[:1]
     ws_p = api.alloc_workspace(api.workspace_bytes(lat, m, 3, 1, 1, "plain"), dev)
@@ -376,10 +457,12 @@ def bench_m18(torch, stream, tune, rows):
     return {"workload": "square 18x19, 80 q x 8 seeded primes (640 instances), graph row replay, "
                         f"tuning {tune}",
             "maps_build_s": maps_s, "ms_per_strip": ms,
-            "value": updates_of(lat, m, n, I) / (ms / 1e3), "unit": "state-updates/s",
+            "value": written_of(lat, m, n, I, fuse) / (ms / 1e3), "unit": "state-updates/s (residues written)",
+            "per_site_factor_updates_per_s": updates_of(lat, m, n, I) / (ms / 1e3),
             "factor_kernel": {"rows_timed": rows, "launches": rows * nf, "avg_launch_us": k_ms * 1e3 / (rows * nf),
                               "achieved_GBs": achieved, "frac_of_hbm_peak": achieved / HBM_PEAK_GBS,
-                              "algorithmic_bytes_per_row": bytes_row},
+                              "own_min_bytes_per_row": own_row, "per_site_bytes_per_row": per_site_row,
+                              "frac_per_site": rows * per_site_row / (k_ms / 1e3) / 1e9 / HBM_PEAK_GBS},
             "plain_single_instance": {"rows": 2, "ms": p_ms,
                                       "value": updates_of(lat, m, 3, 1) / (p_ms / 1e3),
                                       "algorithmic_GBs": p_bytes / (p_ms / 1e3) / 1e9,
@@ -403,6 +486,19 @@ def bench_serving(torch, n_jobs, n_plain):
     free, _ = torch.cuda.mem_get_info()
     rep = Server(be, budget_bytes=int(0.8 * free), rows_per_tick=1).run(jobs(n_jobs))
     served = rep.summary()
+    # every fifth served job, and the widest of each lattice, run again alone
+    done = [j for j in rep.jobs if j.state == "done"]
+    pick = {j.id for j in done[::5]}
+    for lat in ("square", "triangular"):
+        wide = [j for j in done if j.lattice == lat]
+        if wide:
+            pick.add(max(wide, key=lambda j: (j.m, j.instances)).id)
+    checked = 0
+    for j in done:
+        if j.id in pick:
+            alone = api.strip(j.lattice, j.m, j.n_max, j.q_points, j.primes, mode="batched")
+            assert (alone.reshape(j.result.shape) == j.result).all(), f"served job {j.id} differs from its run alone"
+            checked += 1
     dev = torch.device("cuda", torch.cuda.current_device())
     pstream = torch.cuda.Stream(device=dev)
 
@@ -416,6 +512,7 @@ def bench_serving(torch, n_jobs, n_plain):
                       f"q=1..U{{16..80}}, 1-4 primes; {n_jobs} jobs served, the first {n_plain} also through "
                       f"the plain path one job at a time",
             "served": {k: served[k] for k in ("done", "failed", "p50_s", "p99_s", "jobs_per_s", "ticks")},
+            "checked_against_alone": checked,
             "plain_fifo": {k: plain[k] for k in ("done", "p50_s", "p99_s", "jobs_per_s")}}
 
 
@@ -489,7 +586,9 @@ def main():
     sizes = factor_sizes(lat, m)
     s_nc = api.space_size(m)
     updates_per_step = updates_of(lat, m, n, I)
-    log(f"maps ready in {time.time() - t0:.1f} s; {updates_per_step:.3e} state-updates per step; "
+    written_per_step = written_of(lat, m, n, I, fuse)
+    log(f"maps ready in {time.time() - t0:.1f} s; {written_per_step:.3e} residues written per step "
+        f"({updates_per_step:.3e} per-site factor updates); "
         f"mode {mode}, tuning {tune} ({'autotuned table' if tuned else 'given or defaults'})")
 
     stream = torch.cuda.current_stream(dev)
@@ -505,10 +604,12 @@ def main():
     t_wall = time.perf_counter()
     ms_per_step = timed(torch, stream, step, args.steps)
     wall = time.perf_counter() - t_wall
-    value = updates_per_step / (ms_per_step / 1e3)
+    value = written_per_step / (ms_per_step / 1e3)
+    per_site = updates_per_step / (ms_per_step / 1e3)
     res = api.to_u32(out).astype("int64").reshape(n, len(q), len(p))
     assert (res[:, 0, :] == 0).all() and (res[:, 1, :] == 2).all(), "invariants P(1)=0, P(2)=2 failed"
-    log(f"{mode}: {ms_per_step:.3f} ms/step, {value:.3e} state-updates/s (wall {wall:.2f} s)")
+    log(f"{mode}: {ms_per_step:.3f} ms/step, {value:.3e} residues written/s, {per_site:.3e} per-site factor "
+        f"updates/s (wall {wall:.2f} s)")
 
     # ---- roofline of the factor kernel, timed alone -----------------------
     # One launch per factor step over all instance chunks (streams = 1), so
@@ -524,13 +625,13 @@ def main():
     nf = -(-m // fuse)
     launches = R * nf
     avg_us = k_ms * 1e3 / launches
-    bytes_row = row_bytes(sizes, ipad, s_nc)
-    own_row = bytes_row if fuse == 1 else row_bytes(factor_sizes(lat, m, fuse, nf), ipad, s_nc)
-    achieved = R * bytes_row / (k_ms / 1e3) / 1e9
-    achieved_own = R * own_row / (k_ms / 1e3) / 1e9
+    per_site_row = row_bytes(sizes, ipad, s_nc)
+    own_row = per_site_row if fuse == 1 else row_bytes(factor_sizes(lat, m, fuse, nf), ipad, s_nc)
+    achieved = R * own_row / (k_ms / 1e3) / 1e9
+    achieved_per_site = R * per_site_row / (k_ms / 1e3) / 1e9
     kname = f"k_gather<{V},{tune.get('unroll') or 4}>"
-    log(f"factor kernel {kname}: {launches} launches, avg {avg_us:.1f} us, {achieved:.0f} GB/s algorithmic "
-        f"({achieved_own:.0f} GB/s of the launches' own minimum traffic)")
+    log(f"factor kernel {kname}: {launches} launches, avg {avg_us:.1f} us, {achieved:.0f} GB/s of the launches' "
+        f"own minimum traffic ({achieved_per_site:.0f} GB/s counting every per-site factor's reads and writes)")
     del ws_b
 
     # ---- plain per-instance path on a subset of the instances -------------
@@ -549,19 +650,23 @@ def main():
         ref = res[:, : len(qs_sub), :]
         assert (api.to_u32(out_p).astype("int64") == ref).all(), "plain path differs from batched"
         plain = {"value": updates_of(lat, m, n, Ik) / (p_ms / 1e3), "unit": "state-updates/s",
-                 "instances_timed": Ik, "ms_per_instance": p_ms / Ik}
-        plain["batched_speedup"] = value / plain["value"]
+                 "instances_timed": Ik, "ms_per_instance": p_ms / Ik,
+                 "note": "single factors: every residue written is a per-site factor update"}
+        plain["batched_speedup_per_site_updates"] = per_site / plain["value"]
         log(f"plain: {plain['value']:.3e} state-updates/s over {Ik} instances")
 
     extra = {}
     if not args.quick:
         extra["plain_configs"] = bench_small_configs(torch, stream, max(2, args.steps // 4))
-        log("plain configs: " + ", ".join(f"{k} plain {v['plain']['value']:.3e} / graph {v['graph']['value']:.3e}"
+        log("plain configs: " + ", ".join(f"{k} plain {v['plain']['ms_per_step']:.3f} / graph "
+                                          f"{v['graph']['ms_per_step']:.3f} / resident "
+                                          f"{v['resident']['ms_per_step']:.3f} ms"
                                           for k, v in extra["plain_configs"].items()))
         extra["sweep_square_2_14"] = bench_sweep(torch, stream, tune, max(2, args.steps // 4))
         log(f"sweep m=2..14: {extra['sweep_square_2_14']['value']:.3e} state-updates/s")
         extra["triangular_12x13"] = bench_triangular(torch, stream, max(2, args.steps // 2))
-        log(f"triangular m=12: {extra['triangular_12x13']['value']:.3e} state-updates/s")
+        log(f"triangular m=12: {extra['triangular_12x13']['ms_per_step']:.3f} ms "
+            f"(graph row replay {extra['triangular_12x13']['graph_row_replay_ms']:.3f} ms)")
         extra["serving"] = bench_serving(torch, args.serve_jobs, args.serve_plain_jobs)
         log(f"serving: {extra['serving']}")
         extra["finite_lattice_square"] = bench_finite_lattice(41)
@@ -581,19 +686,16 @@ def main():
     # ---- CPU oracle on a bounded sample -----------------------------------
     cpu = None
     if not args.no_cpu and not args.quick and wname == "square_14x15":
-        dt, ninst = cpu_baseline(lat, m, q, p)
-        upd = sum(s for _, s, _ in sizes) * ninst
-        cpu = {"value": upd / dt, "unit": "state-updates/s", "cores": 1, "kind": "oracle",
-               "sample": f"one transfer row (T_{m}..T_1) of the square m={m} strip applied to a dense seeded "
-                         f"vector over all {s_nc} NCNNN states, first {ninst} of the 640 instances, "
-                         f"{dt:.1f} s single-threaded Python"}
-        log(f"cpu oracle: {cpu['value']:.3e} state-updates/s")
+        cpu = cpu_baseline(lat, m, q, p)
+        log(f"cpu oracle: {cpu['value']:.3e} state-updates/s on {cpu['cores']} processes, "
+            f"{cpu['single_core']['value']:.3e} on one")
 
     if args.copy_mib:
         copy_calibration(torch, stream, dev, args.copy_mib)
 
     line = {
-        "metric": f"state-updates/s, square lattice m={m} ({m}x{n} strip), batched",
+        "metric": f"state-updates/s (residues written by the factor launches), square lattice m={m} "
+                  f"({m}x{n} strip), batched",
         "value": value,
         "unit": "state-updates/s",
         "n_gpus": 1,
@@ -608,11 +710,16 @@ def main():
         "config": {"workload": f"square {m}x{n} strip, 80 q x 8 seeded primes (640 instances), "
                                "row-by-row read-out", "lattice": lat, "m": m, "n_max": n,
                    "instances": I, "mode": mode, "tuning": tune, "autotuned": bool(tuned)},
+        "per_site_factor_updates": {"value": per_site, "unit": "state-updates/s",
+                                    "note": "every per-site factor T_i's targets per step, including the "
+                                            "intermediate ones a fused launch never writes"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname, rtune, wname),
                      "kernel": kname, "avg_launch_us": avg_us, "launches_timed": launches,
-                     "algorithmic_bytes_per_row": bytes_row, "own_min_bytes_per_row": own_row,
-                     "achieved_own_min": achieved_own},
+                     "bytes": "each launch's own minimum: its input and output vectors once, its map, "
+                              "and the read-out vector with the last launch of a row",
+                     "own_min_bytes_per_row": own_row, "per_site_bytes_per_row": per_site_row,
+                     "achieved_per_site": achieved_per_site, "frac_per_site": achieved_per_site / HBM_PEAK_GBS},
         "plain": plain,
         "cpu_baseline": cpu,
         "secondary": extra or None,

@@ -1,9 +1,10 @@
 """Autotuner for the batched sweep: launch shape and execution mode.
 
 Searches instances per lane (chunk width W = 64 V), targets per wavefront,
-wavefronts per workgroup and the execution mode (hipGraph row replay, or the
-whole sweep as one graph of grouped launches), timing whole sweeps with HIP events on the launch
-stream.  Every candidate must return residues bit-identical to the first
+wavefronts per workgroup and the execution mode (hipGraph row replay, the
+whole sweep as one graph of grouped launches, or the resident mode's single
+launch with the vectors in LDS, where the width fits), timing whole sweeps
+with HIP events on the launch stream.  Every candidate must return residues bit-identical to the first
 one; a candidate that differs is rejected and reported (the arithmetic is
 exact, so a difference is a bug, never rounding).  Results are cached as
 JSON keyed by (gfx arch, lattice, m, instances, n_max).
@@ -38,12 +39,33 @@ def candidates(space=None) -> list[dict]:
                                                           space.get("unroll", [4]), space.get("streams", [1]),
                                                           space.get("fuse", [1]), space.get("stage", [0]),
                                                           space["mode"]):
+        if mode == "resident":
+            continue            # its own candidates: resident_candidates
         if mode == "grouped" and s != 1:
             continue            # grouped launches already cover every chunk at once
         if g and (mode == "grouped" or v > 2):
             continue            # staging applies to graph / batched launches with lanes_v <= 2
         out.append(dict(lanes_v=v, targets_per_wave=t, waves_per_block=w, xcd_order=x, unroll=u, streams=s,
                         fuse=f, stage=g, mode=mode))
+    return out
+
+
+# Resident mode (one launch per strip, vectors in LDS): instances per
+# workgroup, wavefronts per workgroup, fused family.
+RESIDENT_SPACE = dict(lanes_v=[1, 2, 4], waves_per_block=[8, 16], fuse=[1, 2, 3])
+
+
+def resident_candidates(lattice, m, n_inst, n_max, space=None) -> list[dict]:
+    """Resident-mode candidates whose two state vectors fit a workgroup's LDS."""
+    space = space or RESIDENT_SPACE
+    out = []
+    for v, w, f in itertools.product(space["lanes_v"], space["waves_per_block"], space["fuse"]):
+        t = dict(lanes_v=v, waves_per_block=w, fuse=f)
+        try:
+            api.workspace_bytes(lattice, m, n_max, n_inst, 1, "resident", t)
+        except api.ChromError:
+            continue
+        out.append(dict(t, mode="resident"))
     return out
 
 
@@ -103,12 +125,25 @@ def time_candidate(lattice, m, n_max, q_points, primes, cand, steps=3, stream=No
     return e0.elapsed_time(e1) / steps, api.to_u32(out)
 
 
-def tune(lattice, m, n_max, q_points, primes, space=None, steps=3, path=DEFAULT_CACHE, log=None) -> dict:
-    """Times every candidate, keeps the fastest bit-identical one, caches it."""
+def tune(lattice, m, n_max, q_points, primes, space=None, steps=3, path=DEFAULT_CACHE, log=None,
+         resident_only=False) -> dict:
+    """Times every candidate, keeps the fastest bit-identical one, caches it.
+    resident_only: the resident-mode candidates plus the best known entry."""
     table = []
     ref = None
     best = None
-    for cand in candidates(space):
+    n_inst = len(q_points) * len(primes)
+    if resident_only:
+        cands = resident_candidates(lattice, m, n_inst, n_max)
+        known = lookup_tuned(lattice, m, n_inst, n_max)
+        if known:
+            known.pop("ms", None)
+            cands = [known] + cands
+    else:
+        cands = candidates(space)
+        if "resident" in (space or SPACE)["mode"]:
+            cands += resident_candidates(lattice, m, n_inst, n_max)
+    for cand in cands:
         ms, res = time_candidate(lattice, m, n_max, q_points, primes, cand, steps)
         if ref is None:
             ref = res
@@ -280,6 +315,10 @@ def main():
     ap.add_argument("--quick", action="store_true", help="a reduced search space")
     ap.add_argument("--batch", action="store_true",
                     help="tune the workload's strips as one batch of grouped launches (chromatic_batch)")
+    ap.add_argument("--space", default=None, metavar="JSON",
+                    help="a search space as JSON (keys of SPACE, each a list)")
+    ap.add_argument("--resident", action="store_true",
+                    help="the resident mode's candidates against the best known entry")
     ap.add_argument("--medium", action="store_true",
                     help="lanes_v 1-2, fused families 1-3, one or three chunk groups, graph mode (96 candidates)")
     ap.add_argument("--series", type=int, default=None, metavar="D",
@@ -309,10 +348,12 @@ def main():
     if args.quick:
         space = dict(lanes_v=[2], targets_per_wave=[4, 8], waves_per_block=[4, 8], xcd_order=[1],
                      unroll=[4], streams=[3], fuse=[2], stage=[0, 1], mode=["graph"])
+    if args.space:
+        space = dict(SPACE, **json.loads(args.space))
     for lat, m, n in w["strips"]:
         api.prepare(lat, m)
         res = tune(lat, m, n, w["q_points"], w["primes"], space=space, steps=args.steps, path=args.cache,
-                   log=lambda s: print(s, file=sys.stderr, flush=True))
+                   log=lambda s: print(s, file=sys.stderr, flush=True), resident_only=args.resident)
         print(json.dumps(dict(workload=args.workload, lattice=lat, m=m, n_max=n, best=res["best"])), flush=True)
 
 

@@ -74,3 +74,21 @@ def test_tuned_table_lookups(monkeypatch, tmp_path):
     monkeypatch.setattr(tune, "_arch", lambda: "gfx942")
     monkeypatch.setattr(tune, "DEFAULT_CACHE", str(tmp_path / "none.json"))
     assert tune.lookup_tuned("square", 14, 640, 15) is None
+
+
+def test_resident_candidates_fit_lds():
+    # two state vectors of s_max + 1 rows per instance must fit 160 KiB:
+    # square m = 13 never fits, triangular m = 12 fits up to 2 instances
+    assert tune.resident_candidates("square", 13, 640, 14) == []
+    tri = tune.resident_candidates("triangular", 12, 288, 13)
+    assert tri and {c["lanes_v"] for c in tri} == {1, 2}
+    assert all(c["mode"] == "resident" for c in tri)
+    sq = tune.resident_candidates("square", 10, 320, 11)
+    assert {c["lanes_v"] for c in sq} == {1, 2, 4} and {c["fuse"] for c in sq} == {1, 2, 3}
+
+
+def test_written_residues_of_fused_steps():
+    # a fused pair writes only the product's targets: the square 14x15 step
+    # with pairs writes 14 rows x 385 911 targets x 640 instances
+    assert bench.written_of("square", 14, 15, 640, 1) == bench.updates_of("square", 14, 15, 640)
+    assert bench.written_of("square", 14, 15, 640, 2) == 14 * 385911 * 640
