@@ -99,8 +99,10 @@ typedef struct chrom_tuning {
   int fuse;             /* consecutive factors applied per launch as one precomputed
                            product map, 1..3 (0 = 1) */
   int stage;            /* 1: each workgroup first copies the distinct source rows of its
-                           tile of target states into LDS (batched and graph modes, lanes_v
-                           1 or 2; the read-out factor is not staged); 0: direct gathers */
+                           tile of consecutive target states into LDS; 2: the same for
+                           clustered tiles, targets grouped by the sources they share
+                           (chromatic_cluster_export); batched and graph modes, lanes_v 1
+                           or 2, the read-out factor is not staged; 0: direct gathers */
 } chrom_tuning;
 
 /* ------------------------------------------------------------------------
@@ -385,6 +387,24 @@ int chromatic_stage_export(int lattice, int m, int fuse, int idx, int slots, int
                            int32_t* n_tiles, int64_t* n_src, int32_t* max_slots,
                            int32_t* tile_row0, int32_t* tile_src0, int32_t* src,
                            uint32_t* entries);
+
+/* The clustered staged-tile form (tuning `stage` = 2) of forward factor idx
+ * of the fuse-sized family: tiles of target rows that read the same sources.
+ * A tile grows from the lowest unplaced target by adding every unplaced
+ * reader of the sources it already reads, while it keeps at most `rows`
+ * targets and `slots` distinct sources; when that closes, the next unplaced
+ * target seeds it again if it fits (a single row with more sources forms a
+ * tile of its own).  Tile t holds positions tile_row0[t] .. tile_row0[t+1]-1
+ * (n_tiles + 1 entries); position k writes target row tgt[k] and has the
+ * entries row_ptr[k] .. row_ptr[k+1]-1 of `entries` (the factor's entry
+ * words with the source replaced by its slot in the tile's list
+ * src[tile_src0[t] .. tile_src0[t+1]), ascending).  tgt and row_ptr have
+ * n_rows and n_rows + 1 entries, entries the factor's nnz.  Host-only (no
+ * device work).  Pass NULL buffers to query sizes. */
+int chromatic_cluster_export(int lattice, int m, int fuse, int idx, int slots, int rows,
+                             int32_t* n_tiles, int64_t* n_src, int32_t* max_slots,
+                             int32_t* tile_row0, int32_t* tile_src0, int32_t* src,
+                             int32_t* tgt, int32_t* row_ptr, uint32_t* entries);
 
 /* Thread-local description of the last error. */
 const char* chromatic_last_error(void);

@@ -340,6 +340,30 @@ def stage_export(lattice, m: int, fuse: int, idx: int, slots: int, rows: int) ->
                 codes=(ent >> 26).astype(np.int64), max_slots=int(mx.value))
 
 
+def cluster_export(lattice, m: int, fuse: int, idx: int, slots: int, rows: int) -> dict:
+    """Clustered staged-tile form of forward factor idx of the fuse-sized
+    family: dict(tile_row0, tile_src0, src, tgt, row_ptr, slots, codes,
+    max_slots)."""
+    L = lib()
+    nt, ns, mx = C.c_int32(), C.c_int64(), C.c_int32()
+    args = (lattice_id(lattice), m, fuse, idx, slots, rows)
+    check(L.chromatic_cluster_export(*args, C.byref(nt), C.byref(ns), C.byref(mx), *([None] * 6)))
+    rp, _, _, _ = map_export(lattice, m, 0 if fuse == 1 else fuse, idx)
+    n_rows, nnz = len(rp) - 1, int(rp[-1])
+    tr = np.zeros(nt.value + 1, dtype=np.int32)
+    ts = np.zeros(nt.value + 1, dtype=np.int32)
+    src = np.zeros(max(ns.value, 1), dtype=np.int32)
+    tgt = np.zeros(max(n_rows, 1), dtype=np.int32)
+    crp = np.zeros(n_rows + 1, dtype=np.int32)
+    ent = np.zeros(max(nnz, 1), dtype=np.uint32)
+    check(L.chromatic_cluster_export(*args, None, None, None, _ptr(tr), _ptr(ts), _ptr(src), _ptr(tgt), _ptr(crp),
+                                     _ptr(ent)))
+    ent = ent[:nnz]
+    return dict(tile_row0=tr, tile_src0=ts, src=src[: ns.value], tgt=tgt[:n_rows], row_ptr=crp,
+                slots=(ent & ((1 << 26) - 1)).astype(np.int64), codes=(ent >> 26).astype(np.int64),
+                max_slots=int(mx.value))
+
+
 def map_export(lattice, m: int, which: int, idx: int):
     """(row_ptr int32[n_rows+1], cols int64[nnz], codes int64[nnz], n_cols);
     which: 0 forward factor, 1 read-out factor (transposed), 2/3 fused family,

@@ -161,9 +161,12 @@ struct GatherArgs {
   int rows_per_wave;
   // Staged tiles (tile_row0 == nullptr: direct gathers).  Entry words then
   // hold a slot of the tile's source list instead of a source state.
+  // Clustered tiles (tile_tgt != nullptr): tile positions are not rows;
+  // position k writes row tile_tgt[k] (csr.row_ptr is then in tile order).
   const int32_t* tile_row0;
   const int32_t* tile_src0;
   const int32_t* tile_src;
+  const int32_t* tile_tgt;
   // Coefficient form with 512-slot rows, degree bound (deg_step == 0: none;
   // narrower rows ignore it).  The state being
   // gathered belongs to output row r (r = *deg_row when deg_row is set, a
@@ -565,7 +568,9 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
 // wavefront computes a contiguous share of the tile's rows reading its
 // sources from LDS.  Sources shared by several rows of the tile are read
 // from memory once; the coefficient handling and row finishing are those of
-// gather_tile.  `slots` is the LDS area (max_slots rows of W words).
+// gather_tile.  `slots` is the LDS area (max_slots rows of W words).  With
+// clustered tiles the tile's positions are written to the rows tile_tgt
+// lists (targets grouped by the sources they share).
 template <int V, int U, bool G>
 __device__ void stage_tile(const GatherArgs& a, int chunk, int tile, uint32_t* slots) {
   constexpr int W = 64 * V;
@@ -586,27 +591,34 @@ __device__ void stage_tile(const GatherArgs& a, int chunk, int tile, uint32_t* s
   const int r0 = min(row0 + wave * per, row1), r1 = min(r0 + per, row1);
   const int nrows = r1 - r0;
   const int rp = (lane <= nrows) ? a.csr.row_ptr[r0 + lane] : 0;
+  const int tg = (a.tile_tgt && lane < nrows) ? a.tile_tgt[r0 + lane] : 0;
   uint32_t p[V], tv[V], ts_[V];
   load_v<V>(a.ic.p + inst0, p);
   load_v<V>(a.ic.tv + inst0, tv);
   load_v<V>(a.ic.ts + inst0, ts_);
   const int pw = a.ic.poly[lane];
   const int pm = a.ic.poly[kCodes + lane];
-  // phase 1: slot k of the tile goes to wavefront k % nw, U slots per batch;
-  // batch slots past the end repeat the last one (same data, same place)
-  for (int k0 = wave; k0 < ns; k0 += nw * U) {
-    const int sid = (lane < U) ? a.tile_src[s0 + min(k0 + lane * nw, ns - 1)] : 0;
-    uint32_t x[U][V];
+  // phase 1: slot k of the tile goes to wavefront k % nw; a wavefront
+  // requests up to R of its slots at once (one round trip for a tile of up
+  // to R nw sources), then writes them to LDS in order
+  constexpr int R = 16;
+  for (int k0 = wave; k0 < ns; k0 += nw * R) {
+    const int sid = (lane < R) ? a.tile_src[s0 + min(k0 + lane * nw, ns - 1)] : 0;
+    uint32_t x[R][V];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t src = static_cast<uint32_t>(__builtin_amdgcn_readlane(sid, u));
-      load_row<V>(in, src * (4u * W) + boff, x[u]);
+    for (int u = 0; u < R; ++u) {
+      if (k0 + u * nw < ns) {
+        const uint32_t src = static_cast<uint32_t>(__builtin_amdgcn_readlane(sid, u));
+        load_row<V>(in, src * (4u * W) + boff, x[u]);
+      }
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int k = min(k0 + u * nw, ns - 1);
+    for (int u = 0; u < R; ++u) {
+      const int k = k0 + u * nw;
+      if (k < ns) {
 #pragma unroll
-      for (int j = 0; j < V; ++j) slots[k * W + lane * V + j] = x[u][j];
+        for (int j = 0; j < V; ++j) slots[k * W + lane * V + j] = x[u][j];
+      }
     }
   }
   __syncthreads();
@@ -625,7 +637,8 @@ __device__ void stage_tile(const GatherArgs& a, int chunk, int tile, uint32_t* s
     auto flush = [&]() {
       uint32_t v[V];
       horner<V>(v, A, deg, tv, ts_, p);
-      store_row<V>(out, static_cast<uint32_t>(row) * (4u * W) + boff, v);
+      const int dst = a.tile_tgt ? __builtin_amdgcn_readlane(tg, row - r0) : row;
+      store_row<V>(out, static_cast<uint32_t>(dst) * (4u * W) + boff, v);
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         if (k <= deg) {

@@ -755,6 +755,86 @@ StagedCsr build_staged(const Csr& c, int slots, int rows) {
   return st;
 }
 
+StagedCsr build_clustered(const Csr& c, int slots, int rows) {
+  if (slots < 1 || rows < 1) throw std::runtime_error("bad staging limits");
+  const int64_t n = c.n_rows, nc = std::max<int64_t>(c.n_cols, 1);
+  // readers of every source
+  std::vector<int64_t> cp(static_cast<size_t>(nc) + 1, 0);
+  for (uint32_t w : c.ent) ++cp[(w & kSrcMask) + 1];
+  for (int64_t i = 0; i < nc; ++i) cp[i + 1] += cp[i];
+  std::vector<int32_t> rd(c.ent.size());
+  {
+    std::vector<int64_t> cur(cp.begin(), cp.end() - 1);
+    for (int64_t r = 0; r < n; ++r)
+      for (int32_t e = c.row_ptr[r]; e < c.row_ptr[r + 1]; ++e) rd[cur[c.ent[e] & kSrcMask]++] = static_cast<int32_t>(r);
+  }
+  StagedCsr st;
+  st.tile_row0.push_back(0);
+  st.tile_src0.push_back(0);
+  st.row_ptr.push_back(0);
+  std::vector<char> placed(static_cast<size_t>(n), 0);
+  std::vector<int32_t> slot_of(static_cast<size_t>(nc), -1);
+  std::vector<int32_t> tsrc, ttgt;
+  int64_t next = 0, done = 0;
+  auto new_sources = [&](int64_t r) {
+    int k = 0;
+    for (int32_t e = c.row_ptr[r]; e < c.row_ptr[r + 1]; ++e) k += slot_of[c.ent[e] & kSrcMask] == -1;
+    return k;   // counts a source twice if the row reads it twice (an upper bound)
+  };
+  auto add = [&](int64_t r) {
+    placed[r] = 1;
+    ++done;
+    ttgt.push_back(static_cast<int32_t>(r));
+    for (int32_t e = c.row_ptr[r]; e < c.row_ptr[r + 1]; ++e) {
+      const uint32_t s = c.ent[e] & kSrcMask;
+      if (slot_of[s] == -1) {
+        slot_of[s] = static_cast<int32_t>(tsrc.size());
+        tsrc.push_back(static_cast<int32_t>(s));
+      }
+    }
+  };
+  while (done < n) {
+    while (placed[next]) ++next;
+    tsrc.clear();
+    ttgt.clear();
+    add(next);   // a row with more sources than `slots` forms a tile of its own
+    size_t qi = 0;
+    for (;;) {
+      if (static_cast<int>(ttgt.size()) >= rows) break;
+      if (qi >= tsrc.size()) {
+        while (next < n && placed[next]) ++next;
+        if (next >= n || static_cast<int>(tsrc.size()) + new_sources(next) > slots) break;
+        add(next);
+        continue;
+      }
+      const int32_t s = tsrc[qi++];
+      for (int64_t k = cp[s]; k < cp[s + 1] && static_cast<int>(ttgt.size()) < rows; ++k) {
+        const int32_t t = rd[k];
+        if (placed[t] || static_cast<int>(tsrc.size()) + new_sources(t) > slots) continue;
+        add(t);
+      }
+    }
+    // slots in ascending source order; entries renumbered
+    std::vector<int32_t> sorted(tsrc);
+    std::sort(sorted.begin(), sorted.end());
+    for (size_t i = 0; i < sorted.size(); ++i) slot_of[sorted[i]] = static_cast<int32_t>(i);
+    for (int32_t t : ttgt) {
+      for (int32_t e = c.row_ptr[t]; e < c.row_ptr[t + 1]; ++e) {
+        const uint32_t w = c.ent[e];
+        st.ent.push_back((w & ~kSrcMask) | static_cast<uint32_t>(slot_of[w & kSrcMask]));
+      }
+      st.row_ptr.push_back(static_cast<int32_t>(st.ent.size()));
+      st.tgt.push_back(t);
+    }
+    st.src.insert(st.src.end(), sorted.begin(), sorted.end());
+    for (int32_t sv : sorted) slot_of[sv] = -1;
+    st.max_slots = std::max(st.max_slots, static_cast<int>(sorted.size()));
+    st.tile_row0.push_back(static_cast<int32_t>(st.tgt.size()));
+    st.tile_src0.push_back(static_cast<int32_t>(st.src.size()));
+  }
+  return st;
+}
+
 namespace {
 // One slot per (lattice, m, normalised).  Builds take the global build lock
 // as well, so map sets build one at a time; a request for a set already

@@ -91,8 +91,13 @@ struct MapSet {
 // codes, with the source replaced by its position (slot) in that list.
 struct StagedCsr {
   std::vector<int32_t> tile_row0, tile_src0, src;
-  std::vector<uint32_t> ent;      // code << kSrcBits | slot, same order as the CSR
+  std::vector<uint32_t> ent;      // code << kSrcBits | slot, in the order of row_ptr
   int max_slots = 0;              // largest source list of a tile
+  // Clustered tiles only: the tiles' target rows in tile order (tile t holds
+  // positions tile_row0[t] .. tile_row0[t+1]-1, position k writing row
+  // tgt[k]) and the row pointers of that order.  Empty: tile t holds the
+  // consecutive rows tile_row0[t] .. and the map's own row pointers apply.
+  std::vector<int32_t> tgt, row_ptr;
   int n_tiles() const { return static_cast<int>(tile_row0.size()) - 1; }
 };
 
@@ -100,6 +105,16 @@ struct StagedCsr {
 // `slots` distinct sources (a single row with more sources forms a tile of
 // its own).
 StagedCsr build_staged(const Csr& c, int slots, int rows);
+
+// Clustered tiling: a tile grows from the lowest unplaced target through the
+// sources it reads -- every unplaced reader of a source already in the tile
+// joins while the tile keeps at most `rows` targets and `slots` distinct
+// sources -- and when that search closes, the next unplaced target seeds it
+// again if it fits.  Targets that read the same sources share a tile, so a
+// tile stages fewer source rows per target than a run of consecutive rows
+// (square m = 14 fused pairs: about 1.5 against 2.8 per target at 64 targets
+// and 96 slots).
+StagedCsr build_clustered(const Csr& c, int slots, int rows);
 
 // Builds every single-factor map of (lattice, m); threads = 0 uses the
 // hardware count; paper_order keeps the paper's state order between the

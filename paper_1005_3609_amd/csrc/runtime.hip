@@ -26,6 +26,7 @@
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -90,10 +91,11 @@ size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 // ---------------------------------------------------------------------------
 // A factor's staged tiles on the device (see StagedCsr).
 struct DevStaged {
-  DevCsr csr;                 // row pointers shared with the plain map; entries hold slots
+  DevCsr csr;                 // entries hold slots; row pointers the plain map's (clustered: tile order)
   const int32_t* tile_row0 = nullptr;
   const int32_t* tile_src0 = nullptr;
   const int32_t* src = nullptr;
+  const int32_t* tgt = nullptr;   // clustered tiles: row written by each tile position
   int n_tiles = 0, max_slots = 0;
 };
 struct DevStagedSet {
@@ -113,9 +115,10 @@ struct DevFamily {
   std::vector<Poly> codes;   // extends the base table
   int shift = 0;             // kernels expand the codes in powers of t = q - shift
   bool general = false;      // some coefficient its factors use exceeds the fast path (|d| > 1; > 3 in the coefficient form)
-  // staged copies, one set per (slot limit, rows per tile), built on first use
+  // staged copies, one set per (kind: 1 consecutive rows, 2 clustered;
+  // slot limit; rows per tile), built on first use
   mutable std::mutex st_mu;
-  mutable std::map<std::pair<int, int>, std::unique_ptr<DevStagedSet>> staged;
+  mutable std::map<std::tuple<int, int, int>, std::unique_ptr<DevStagedSet>> staged;
   // sliced-ELL copies of the factors and read-out maps (resident mode), built on first use
   mutable std::unique_ptr<struct DevSellSet> sell;
 };
@@ -803,21 +806,39 @@ const DevFamily& dev_family(const DevMaps& dm, int k) {
 int stage_slots(int V) { return 48 * 1024 / (256 * V); }
 constexpr int kStageMaxLds = 64 * 1024;
 
-// Device copies of family fam's factors cut into staged tiles.
-const DevStagedSet& dev_staged(const DevMaps& dm, const DevFamily& fam, int slots, int rows) {
+// Device copies of family fam's factors cut into staged tiles: kind 1 runs
+// of consecutive rows, kind 2 clustered tiles (build_clustered; the factors
+// are clustered on parallel host threads).
+const DevStagedSet& dev_staged(const DevMaps& dm, const DevFamily& fam, int slots, int rows, int kind = 1) {
   std::lock_guard<std::mutex> lk(fam.st_mu);
-  auto key = std::make_pair(slots, rows);
+  auto key = std::make_tuple(kind, slots, rows);
   auto it = fam.staged.find(key);
   if (it != fam.staged.end()) return *it->second;
   const MapSet& ms = get_maps(dm.lattice, dm.m);
   const std::vector<Csr>& host = (fam.k == 1) ? ms.fwd : ms.family(fam.k).fac;
   std::vector<StagedCsr> st(host.size());
-  size_t bytes = 0;
-  for (size_t i = 0; i < host.size(); ++i) {
-    st[i] = build_staged(host[i], slots, rows);
-    bytes += align_up(st[i].ent.size() * 4 + 4) + align_up(st[i].tile_row0.size() * 4 + 4) +
-             align_up(st[i].tile_src0.size() * 4 + 4) + align_up(st[i].src.size() * 4 + 4);
+  if (kind == 2) {
+    std::vector<std::thread> th;
+    std::vector<std::string> err(host.size());
+    for (size_t i = 0; i < host.size(); ++i)
+      th.emplace_back([&, i] {
+        try {
+          st[i] = build_clustered(host[i], slots, rows);
+        } catch (const std::exception& e) {
+          err[i] = e.what();
+        }
+      });
+    for (auto& t : th) t.join();
+    for (const std::string& e : err)
+      if (!e.empty()) throw std::runtime_error(e);
+  } else {
+    for (size_t i = 0; i < host.size(); ++i) st[i] = build_staged(host[i], slots, rows);
   }
+  size_t bytes = 0;
+  for (size_t i = 0; i < host.size(); ++i)
+    bytes += align_up(st[i].ent.size() * 4 + 4) + align_up(st[i].tile_row0.size() * 4 + 4) +
+             align_up(st[i].tile_src0.size() * 4 + 4) + align_up(st[i].src.size() * 4 + 4) +
+             align_up(st[i].tgt.size() * 4 + 4) + align_up(st[i].row_ptr.size() * 4 + 4);
   auto set = std::make_unique<DevStagedSet>();
   if (hipMalloc(&set->base, bytes) != hipSuccess) throw MemError("device allocation of staged maps failed");
   char* cur = static_cast<char*>(set->base);
@@ -835,6 +856,10 @@ const DevStagedSet& dev_staged(const DevMaps& dm, const DevFamily& fam, int slot
     d.tile_row0 = static_cast<const int32_t*>(put(st[i].tile_row0.data(), st[i].tile_row0.size() * 4));
     d.tile_src0 = static_cast<const int32_t*>(put(st[i].tile_src0.data(), st[i].tile_src0.size() * 4));
     d.src = static_cast<const int32_t*>(put(st[i].src.data(), st[i].src.size() * 4));
+    if (kind == 2) {
+      d.tgt = static_cast<const int32_t*>(put(st[i].tgt.data(), st[i].tgt.size() * 4));
+      d.csr.row_ptr = static_cast<const int32_t*>(put(st[i].row_ptr.data(), st[i].row_ptr.size() * 4));
+    }
     d.n_tiles = st[i].n_tiles();
     d.max_slots = st[i].max_slots;
   }
@@ -1057,7 +1082,7 @@ Tune resolve(const chrom_tuning* t, bool series = false, bool resident = false) 
   if (r.streams < 1 || r.streams > 4) throw ArgError("streams must be in 1..4");
   if (t->fuse) r.fuse = t->fuse;
   if (r.fuse < 1 || r.fuse > kMaxFuse) throw ArgError("fuse must be in 1..3");
-  if (t->stage < 0 || t->stage > 1) throw ArgError("stage must be 0 or 1");
+  if (t->stage < 0 || t->stage > 2) throw ArgError("stage must be 0, 1 or 2");
   r.stage = t->stage;
   if (series && r.V == 8) {
     if (r.U != 4) throw ArgError("lanes_v 8 runs with unroll 4");
@@ -1499,6 +1524,7 @@ void add_rows(Program& pg, const JobCtx& j, int r_first, int r_last, int after, 
         g.u.g.tile_row0 = sd->tile_row0;
         g.u.g.tile_src0 = sd->tile_src0;
         g.u.g.tile_src = sd->src;
+        g.u.g.tile_tgt = sd->tgt;
       }
       tm = push(pg, g, after, fused ? prev_reduce : -1);
       after = tm;
@@ -2228,7 +2254,7 @@ int rows_tile_of(const Tune& t) { return t.rpw * t.wpb; }
 // Staged tiles for the forward factors of a batched or graph-mode job.
 void bind_staging(JobCtx& j, int mode) {
   if (j.t.stage && j.t.V <= 2 && (mode == CHROM_MODE_BATCHED || mode == CHROM_MODE_GRAPH))
-    j.stg = &dev_staged(*j.dm, *j.fam, stage_slots(j.t.V), rows_tile_of(j.t));
+    j.stg = &dev_staged(*j.dm, *j.fam, stage_slots(j.t.V), rows_tile_of(j.t), j.t.stage);
 }
 
 size_t workspace_bytes(int lattice, int m, int I, int n_max_hint, int mode, const Tune& t) {
@@ -2968,6 +2994,30 @@ int chromatic_stage_export(int lattice, int m, int fuse, int idx, int slots, int
     if (tile_row0) std::memcpy(tile_row0, st.tile_row0.data(), st.tile_row0.size() * 4);
     if (tile_src0) std::memcpy(tile_src0, st.tile_src0.data(), st.tile_src0.size() * 4);
     if (src && !st.src.empty()) std::memcpy(src, st.src.data(), st.src.size() * 4);
+    if (entries && !st.ent.empty()) std::memcpy(entries, st.ent.data(), st.ent.size() * 4);
+    return CHROM_OK;
+  });
+}
+
+int chromatic_cluster_export(int lattice, int m, int fuse, int idx, int slots, int rows, int32_t* n_tiles,
+                             int64_t* n_src, int32_t* max_slots, int32_t* tile_row0, int32_t* tile_src0,
+                             int32_t* src, int32_t* tgt, int32_t* row_ptr, uint32_t* entries) {
+  return guarded([&] {
+    check_args(lattice, m, 0);
+    if (fuse < 1 || fuse > kMaxFuse) throw ArgError("fuse must be in 1..3");
+    if (slots < 1 || rows < 1) throw ArgError("slots and rows must be >= 1");
+    const MapSet& ms = get_maps(lattice, m);
+    const std::vector<Csr>& fac = (fuse == 1) ? ms.fwd : ms.family(fuse).fac;
+    if (idx < 0 || idx >= static_cast<int>(fac.size())) throw ArgError("idx out of range");
+    const StagedCsr st = build_clustered(fac[idx], slots, rows);
+    if (n_tiles) *n_tiles = st.n_tiles();
+    if (n_src) *n_src = static_cast<int64_t>(st.src.size());
+    if (max_slots) *max_slots = st.max_slots;
+    if (tile_row0) std::memcpy(tile_row0, st.tile_row0.data(), st.tile_row0.size() * 4);
+    if (tile_src0) std::memcpy(tile_src0, st.tile_src0.data(), st.tile_src0.size() * 4);
+    if (src && !st.src.empty()) std::memcpy(src, st.src.data(), st.src.size() * 4);
+    if (tgt && !st.tgt.empty()) std::memcpy(tgt, st.tgt.data(), st.tgt.size() * 4);
+    if (row_ptr) std::memcpy(row_ptr, st.row_ptr.data(), st.row_ptr.size() * 4);
     if (entries && !st.ent.empty()) std::memcpy(entries, st.ent.data(), st.ent.size() * 4);
     return CHROM_OK;
   });

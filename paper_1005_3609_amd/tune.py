@@ -27,7 +27,7 @@ from . import api
 DEFAULT_CACHE = os.environ.get("CHROMSTRIP_TUNE_CACHE",
                                os.path.join(os.path.expanduser("~"), ".cache", "chromstrip", "tune.json"))
 SPACE = dict(lanes_v=[1, 2, 4], targets_per_wave=[4, 8, 16], waves_per_block=[2, 4, 8],
-             xcd_order=[1, 2], unroll=[4, 8], streams=[1, 2], fuse=[1, 2, 3], stage=[0, 1],
+             xcd_order=[1, 2], unroll=[4, 8], streams=[1, 2], fuse=[1, 2, 3], stage=[0, 1, 2],
              mode=["graph", "grouped"])
 
 

@@ -53,3 +53,48 @@ def test_stage_export_rejects_bad_arguments():
         api.stage_export("square", 6, 1, 6, 8, 4)
     with pytest.raises(api.ChromError):
         api.stage_export("square", 6, 1, 0, 0, 4)
+
+
+@pytest.mark.parametrize("lattice,m,fuse", [("square", 6, 1), ("square", 9, 2), ("triangular", 6, 1),
+                                            ("triangular", 7, 2), ("square", 8, 3)])
+@pytest.mark.parametrize("slots,rows", [(1, 1), (12, 8), (48, 16), (96, 64)])
+def test_clustered_tiles_reproduce_the_map(lattice, m, fuse, slots, rows):
+    # every target row appears once; each tile's source list is exactly the
+    # set its targets read; each entry's slot points back at the plain
+    # map's source, with the plain map's code, in the row's order
+    nfac = -(-m // fuse)
+    for idx in range(nfac):
+        rp, cols, codes, _ = api.map_export(lattice, m, 0 if fuse == 1 else fuse, idx)
+        st = api.cluster_export(lattice, m, fuse, idx, slots, rows)
+        tr, ts, src, tgt, crp = st["tile_row0"], st["tile_src0"], st["src"], st["tgt"], st["row_ptr"]
+        n_rows = len(rp) - 1
+        assert tr[0] == 0 and tr[-1] == n_rows and ts[-1] == len(src)
+        assert np.all(np.diff(tr) >= 1) and np.all(np.diff(tr) <= rows)
+        np.testing.assert_array_equal(np.sort(tgt), np.arange(n_rows))
+        np.testing.assert_array_equal(np.diff(crp), np.diff(rp)[tgt])
+        widest = 0
+        for t in range(len(tr) - 1):
+            lst = src[ts[t]:ts[t + 1]]
+            assert np.all(np.diff(lst) > 0)
+            reads = []
+            for k in range(tr[t], tr[t + 1]):
+                r = tgt[k]
+                np.testing.assert_array_equal(lst[st["slots"][crp[k]:crp[k + 1]]], cols[rp[r]:rp[r + 1]])
+                np.testing.assert_array_equal(st["codes"][crp[k]:crp[k + 1]], codes[rp[r]:rp[r + 1]])
+                reads.append(cols[rp[r]:rp[r + 1]])
+            np.testing.assert_array_equal(lst, np.unique(np.concatenate(reads)))
+            if tr[t + 1] - tr[t] > 1:
+                assert len(lst) <= slots
+            widest = max(widest, len(lst))
+        assert st["max_slots"] == widest
+
+
+def test_clustered_tiles_share_sources():
+    # at 64 targets and 96 slots a fused pair's clustered tiles stage well
+    # under two source rows per target, against about 2.8 for consecutive rows
+    rp, cols, _, _ = api.map_export("square", 12, 2, 2)
+    n_rows = len(rp) - 1
+    cl = api.cluster_export("square", 12, 2, 2, 96, 64)
+    run = api.stage_export("square", 12, 2, 2, 10 ** 6, 64)
+    assert len(cl["src"]) / n_rows < 1.7
+    assert len(run["src"]) / n_rows > 2.3
