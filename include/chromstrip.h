@@ -182,6 +182,34 @@ int chromatic_strip_async(int lattice, int m, int n_max,
                           void* d_workspace, size_t ws_bytes,
                           void* stream, uint32_t* d_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * strip as chromatic_strip_async in CHROM_MODE_BATCHED, but with its
+ * workspace in a device array the library holds (128 MiB on every GPU it
+ * runs on, kept until the process ends).  The call allocates nothing: no
+ * hipMalloc, hipFree or pinned staging buffers; the per-instance constants
+ * are computed on the device from q_points and primes passed as kernel
+ * arguments, so the call only queues kernels on `stream`.
+ *   - Before the first call for (lattice, m) on a device, call
+ *     chromatic_prepare(lattice, m) (and, for tune->fuse > 1, run
+ *     chromatic_strip_async once with that fuse) so the factor maps are on
+ *     the device; otherwise CHROM_EINVAL.
+ *   - q_points[nq] (nq <= 512), primes[np] (np <= 64): host memory, read
+ *     before return.  d_out: device memory [n_max][nq][np], caller-owned.
+ *   - tune: streams and stage must be 0 or 1 / 0 (one stream, no staging).
+ *   - Returns CHROM_EINVAL if the strip's workspace (what
+ *     chromatic_workspace_bytes reports for CHROM_MODE_BATCHED, less its
+ *     256-byte graph counter) exceeds 128 MiB: e.g. square m <= 12 at 640
+ *     instances, m = 14 at 128.
+ *   - Every call on a GPU uses that GPU's one array: calls that overlap on
+ *     one GPU (different streams or threads) race and give wrong results.
+ *     Nothing carries over from one call to the next (every region the
+ *     kernels read is written first in the same call). */
+int chromatic_strip_noalloc(int lattice, int m, int n_max,
+                            const uint32_t* q_points, int nq,
+                            const uint32_t* primes, int np,
+                            const chrom_tuning* tune, void* stream, uint32_t* d_out);
+
 /* Measurement hook: queues `rows` rows of the per-site factor kernel
  * (T_1..T_m of eq. T_sq_decomp, read-out fused into T_m) on `stream`, on a
  * workspace that chromatic_strip_async has already run on in

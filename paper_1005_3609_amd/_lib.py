@@ -57,6 +57,8 @@ _SIGS = {
     "chromatic_strip_async": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_int,
                                         C.c_int, C.POINTER(Tuning), C.c_void_p, C.c_size_t, C.c_void_p,
                                         C.c_void_p]),
+    "chromatic_strip_noalloc": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_int,
+                                          C.POINTER(Tuning), C.c_void_p, C.c_void_p]),
     "chromatic_factor_launches": (C.c_int, [C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_int,
                                             C.POINTER(Tuning), C.c_void_p, C.c_size_t, C.c_void_p]),
     "chromatic_prepare": (C.c_int, [C.c_int, C.c_int]),

@@ -2651,6 +2651,138 @@ int server_step_impl(chrom_slot* slots, int nslots, int rows, const chrom_tuning
   return CHROM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// No-allocation strip: the workspace is a file-scope device array
+// ---------------------------------------------------------------------------
+// For callers that cannot allocate (graph capture, tight serving loops): the
+// batched strip with its workspace in `scratch`, a device array of
+// kScratchBytes that every GPU the library runs on holds until the process
+// ends.  Host code never passes `scratch` itself to a kernel or a copy: it
+// uses the address hipGetSymbolAddress returns for the current device
+// (scratch_ptr).  The per-instance constants are computed on the device from
+// q and p passed as kernel arguments, so the call queues kernels only.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+constexpr int kNoAllocMaxQ = 512, kNoAllocMaxP = 64;
+__device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {nullptr};
+
+// Device address of `scratch` on the current device, looked up once per device.
+void* scratch_ptr() {
+  int dev = 0;
+  HIPX(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) throw std::runtime_error("device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPX(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) throw HipError("hipGetSymbolAddress returned a null address for the scratch array");
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+// Kernel-argument image of a job's constants (the host-side const_image,
+// computed on the device).
+struct ConstSetupArgs {
+  int nq, np, I, ipad, shift;
+  uint32_t q[kNoAllocMaxQ];
+  uint32_t p[kNoAllocMaxP];
+  uint32_t poly[2 * kMaxCodes];
+  uint32_t *dp, *dpinv, *dr1, *dtv, *dts, *dpoly;
+};
+
+__global__ void k_setup_consts(const ConstSetupArgs a) {
+  const int i = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < 2 * kMaxCodes) a.dpoly[i] = a.poly[i];
+  if (i >= a.ipad) return;
+  const int inst = i < a.I ? i : 0;             // padding repeats instance 0
+  const uint32_t p = a.p[inst % a.np];
+  const uint32_t q = a.q[inst / a.np] % p;
+  uint32_t inv = p;                             // -p^{-1} mod 2^32 by Newton's iteration
+  for (int k = 0; k < 5; ++k) inv *= 2u - p * inv;
+  const uint32_t sm = static_cast<uint32_t>(((a.shift % static_cast<int64_t>(p)) + p) % p);
+  const uint32_t tv = static_cast<uint32_t>((static_cast<uint64_t>(q) + p - sm) % p);
+  a.dp[i] = p;
+  a.dpinv[i] = 0u - inv;
+  a.dr1[i] = static_cast<uint32_t>((uint64_t(1) << 32) % p);
+  a.dtv[i] = tv;
+  a.dts[i] = static_cast<uint32_t>((static_cast<uint64_t>(tv) << 32) / p);
+}
+
+int strip_noalloc_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, const uint32_t* p, int np,
+                       const chrom_tuning* tune, hipStream_t st, uint32_t* d_out) {
+  check_args(lattice, m, n_max);
+  std::vector<Inst> inst = make_instances(q, nq, p, np);
+  if (nq > kNoAllocMaxQ || np > kNoAllocMaxP)
+    throw ArgError("at most " + std::to_string(kNoAllocMaxQ) + " q points and " + std::to_string(kNoAllocMaxP) +
+                   " primes");
+  Tune t = resolve(tune);
+  if (t.streams != 1 || t.stage != 0) throw ArgError("the no-allocation strip runs one stream without staging");
+  if (n_max == 0) return CHROM_OK;
+  if (!d_out) throw ArgError("null output");
+  const int I = static_cast<int>(inst.size());
+  JobLayout L = job_layout(lattice, m, I, t, kMaxCodes, rows_tile_of(t));
+  if (L.bytes > kScratchBytes)
+    throw ArgError("this strip needs " + std::to_string(L.bytes) + " bytes of workspace, more than the " +
+                   std::to_string(kScratchBytes) + " the no-allocation strip holds");
+  // maps and family must already be on the device (chromatic_prepare; fused
+  // families after one call of another entry point with that fuse)
+  const DevMaps* dm = nullptr;
+  {
+    int dev = 0;
+    HIPX(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto it = g_dev.find(std::make_tuple(dev, lattice, m, 0));
+    if (it != g_dev.end()) dm = it->second.get();
+  }
+  if (!dm) throw ArgError("the factor maps of this (lattice, m) are not on the device: call chromatic_prepare first");
+  const DevFamily* fam = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(dm->fam_mu);
+    auto it = dm->fam.find(t.fuse);
+    if (it != dm->fam.end()) fam = it->second.get();
+  }
+  if (!fam) throw ArgError("the fused maps of this fuse are not on the device: run the strip once with it first");
+  void* ws = scratch_ptr();
+  JobCtx j;
+  j.dm = dm;
+  j.fam = fam;
+  j.t = t;
+  j.L = L;
+  j.P = job_ptrs(L, ws);
+  j.d_out = d_out;
+  j.out_row_stride = L.I;
+  ConstSetupArgs a{};
+  a.nq = nq;
+  a.np = np;
+  a.I = I;
+  a.ipad = L.ipad;
+  a.shift = fam->shift;
+  for (int k = 0; k < nq; ++k) a.q[k] = q[k];
+  for (int k = 0; k < np; ++k) a.p[k] = p[k];
+  if (fam->codes.size() < 2 || !(fam->codes[0].c[0] == 1 && fam->codes[1].c[0] == -1))
+    throw std::runtime_error("code table must start with +1 and -1");
+  for (size_t c = 0; c < fam->codes.size(); ++c) {
+    const Poly d = shift_basis(fam->codes[c], fam->shift);
+    a.poly[c] = pack_poly(d);
+    a.poly[kMaxCodes + c] = pack_mask(d);
+  }
+  a.dp = j.P.p;
+  a.dpinv = j.P.pinv;
+  a.dr1 = j.P.r1;
+  a.dtv = j.P.tv;
+  a.dts = j.P.ts;
+  a.dpoly = j.P.poly;
+  const int nthreads = std::max(L.ipad, 2 * kMaxCodes);
+  hipLaunchKernelGGL(k_setup_consts, dim3((nthreads + 255) / 256), dim3(256), 0, st, a);
+  HIPX(hipGetLastError());
+  Program pg = strip_program(j, n_max);
+  run_eager(pg, t, st);
+  return CHROM_OK;
+}
+
 }  // namespace
 }  // namespace cs
 
@@ -2690,6 +2822,14 @@ size_t chromatic_workspace_bytes(int lattice, int m, int n_max, int nq, int np, 
     return CHROM_OK;
   });
   return rc == CHROM_OK ? r : 0;
+}
+
+int chromatic_strip_noalloc(int lattice, int m, int n_max, const uint32_t* q_points, int nq, const uint32_t* primes,
+                            int np, const chrom_tuning* tune, void* stream, uint32_t* d_out) {
+  return guarded([&] {
+    return strip_noalloc_impl(lattice, m, n_max, q_points, nq, primes, np, tune, static_cast<hipStream_t>(stream),
+                              d_out);
+  });
 }
 
 int chromatic_strip_async(int lattice, int m, int n_max, const uint32_t* q_points, int nq, const uint32_t* primes,
@@ -2740,7 +2880,7 @@ int chromatic_factor_launches(int lattice, int m, const uint32_t* q_points, int 
 int chromatic_prepare(int lattice, int m) {
   return guarded([&] {
     check_args(lattice, m, 0);
-    (void)dev_maps(lattice, m);
+    (void)dev_family(dev_maps(lattice, m), 1);
     return CHROM_OK;
   });
 }
