@@ -98,3 +98,44 @@ def test_tuner_candidates_identical(tmp_path):
     assert all(row["identical"] for row in res["table"])
     assert res["best"]["ms"] == min(row["ms"] for row in res["table"])
     assert tune.lookup("square", 8, len(q) * len(p), 6, path=str(tmp_path / "t.json"))["best"] == res["best"]
+
+
+def test_server_at_workload_sizes_against_stored_oracle():
+    # the seeded stream's first 36 jobs as drawn (lattice, m 6..16, n = m+1,
+    # 16-80 q points, 1-4 primes) with their Poisson arrivals: every result
+    # equals the same job run alone; the first job of every (lattice, m) with
+    # m >= 11 equals the oracle's stored residues on 16 of its instances, and
+    # the narrower jobs the live oracle on 8 of theirs
+    import json
+    import os
+    import torch
+    with open(os.path.join(os.path.dirname(__file__), "golden", "oracle_serving_jobs.json")) as f:
+        gold = json.load(f)
+    stream = W.serving_stream(gold["stream_jobs"])
+    jobs = [Job(id=j["id"], lattice=j["lattice"], m=j["m"], n_max=j["n_max"], q_points=j["q_points"],
+                primes=j["primes"], arrival=j["arrival"]) for j in stream]
+    assert max(j.m for j in jobs) == 16 and max(len(j.q_points) for j in jobs) >= 75
+    be = GpuBackend()
+    for j in jobs:
+        be.prepare(j.lattice, j.m)
+    free, _ = torch.cuda.mem_get_info()
+    rep = Server(be, budget_bytes=int(0.8 * free), rows_per_tick=1).run(jobs)
+    s = rep.summary()
+    assert s["done"] == len(jobs) and s["failed"] == 0
+    by_id = {j.id: j for j in jobs}
+    for j in jobs:
+        alone = api.strip(j.lattice, j.m, j.n_max, j.q_points, j.primes, mode="batched")
+        np.testing.assert_array_equal(j.result, alone, err_msg=f"job {j.id}")
+    for g in gold["jobs"]:
+        j = by_id[g["id"]]
+        assert (j.lattice, j.m, j.n_max) == (g["lattice"], g["m"], g["n_max"])
+        flat = j.result.reshape(j.n_max, -1).astype(np.int64)[:, g["instance_index"]]
+        np.testing.assert_array_equal(flat, np.array(g["z"], dtype=np.int64), err_msg=f"job {j.id}")
+    for j in jobs:
+        if j.m > 10:
+            continue
+        inst = W.instances(j.q_points, j.primes)
+        idx = W.sample_instances(len(inst), 8, 1000 + j.id)
+        want = OT.chromatic_residues(j.lattice, j.m, j.n_max, [inst[k][0] for k in idx], [inst[k][1] for k in idx])
+        got = j.result.reshape(j.n_max, -1).astype(np.int64)[:, idx]
+        np.testing.assert_array_equal(got, want, err_msg=f"job {j.id}")
