@@ -101,8 +101,12 @@ typedef struct chrom_tuning {
   int stage;            /* 1: each workgroup first copies the distinct source rows of its
                            tile of consecutive target states into LDS; 2: the same for
                            clustered tiles, targets grouped by the sources they share
-                           (chromatic_cluster_export); batched and graph modes, lanes_v 1
-                           or 2, the read-out factor is not staged; 0: direct gathers */
+                           (chromatic_cluster_export); 3: clustered tiles, each workgroup
+                           running a range of them and requesting the next tile's rows
+                           while it computes the current one (1-3: batched and graph
+                           modes, lanes_v 1 or 2); 4: direct gathers over the clustered
+                           order of the targets (no LDS; lanes_v 1, 2 or 4); the read-out
+                           factor keeps its order; 0: direct gathers */
 } chrom_tuning;
 
 /* ------------------------------------------------------------------------

@@ -167,6 +167,13 @@ struct GatherArgs {
   const int32_t* tile_src0;
   const int32_t* tile_src;
   const int32_t* tile_tgt;
+  // Pipelined staging (stage_range): first entry of every tile, the tile
+  // count and the tiles one workgroup runs in turn.
+  const int32_t* tile_ent0;
+  int n_tiles, tiles_per_block;
+  // Slots a staged tile keeps in LDS: a tile with more sources (a row of
+  // exceptional fan-in forms a tile of its own) reads the rest from memory.
+  int stage_cap;
   // Coefficient form with 512-slot rows, degree bound (deg_step == 0: none;
   // narrower rows ignore it).  The state being
   // gathered belongs to output row r (r = *deg_row when deg_row is set, a
@@ -446,6 +453,9 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
   if (r0 < r1) {
     const int nrows = r1 - r0;
     const int rp = (lane <= nrows) ? a.csr.row_ptr[r0 + lane] : 0;
+    // rows in clustered order (evaluation form, never the read-out factor):
+    // position r writes target row tile_tgt[r]
+    const int tg = (!CF && a.tile_tgt && lane < nrows) ? a.tile_tgt[r0 + lane] : 0;
     const int beg = __builtin_amdgcn_readlane(rp, 0);
     const int end = __builtin_amdgcn_readlane(rp, nrows);
     int row = r0;
@@ -457,10 +467,14 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
       else
         horner<V>(v, A, deg, tv, ts, p);
       if (!kBound || live) {
-        if constexpr (WIDE)
+        if constexpr (WIDE) {
           store_row<V>(wide_row<W>(out, static_cast<uint32_t>(row)), boff, v);
-        else
+        } else if constexpr (!CF) {
+          const int dst = a.tile_tgt ? __builtin_amdgcn_readlane(tg, row - r0) : row;
+          store_row<V>(out, static_cast<uint32_t>(dst) * (4u * W) + boff, v);
+        } else {
           store_row<V>(out, static_cast<uint32_t>(row) * (4u * W) + boff, v);
+        }
       }
 #pragma unroll
       for (int k = 0; k < 4; ++k)
@@ -602,12 +616,13 @@ __device__ void stage_tile(const GatherArgs& a, int chunk, int tile, uint32_t* s
   // requests up to R of its slots at once (one round trip for a tile of up
   // to R nw sources), then writes them to LDS in order
   constexpr int R = 16;
-  for (int k0 = wave; k0 < ns; k0 += nw * R) {
-    const int sid = (lane < R) ? a.tile_src[s0 + min(k0 + lane * nw, ns - 1)] : 0;
+  const int nsl = min(ns, a.stage_cap);
+  for (int k0 = wave; k0 < nsl; k0 += nw * R) {
+    const int sid = (lane < R) ? a.tile_src[s0 + min(k0 + lane * nw, nsl - 1)] : 0;
     uint32_t x[R][V];
 #pragma unroll
     for (int u = 0; u < R; ++u) {
-      if (k0 + u * nw < ns) {
+      if (k0 + u * nw < nsl) {
         const uint32_t src = static_cast<uint32_t>(__builtin_amdgcn_readlane(sid, u));
         load_row<V>(in, src * (4u * W) + boff, x[u]);
       }
@@ -615,7 +630,7 @@ __device__ void stage_tile(const GatherArgs& a, int chunk, int tile, uint32_t* s
 #pragma unroll
     for (int u = 0; u < R; ++u) {
       const int k = k0 + u * nw;
-      if (k < ns) {
+      if (k < nsl) {
 #pragma unroll
         for (int j = 0; j < V; ++j) slots[k * W + lane * V + j] = x[u][j];
       }
@@ -657,9 +672,15 @@ __device__ void stage_tile(const GatherArgs& a, int chunk, int tile, uint32_t* s
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           w[u] = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ev), min(k + u, n - 1)));
-          const uint32_t* sl = slots + (w[u] & kEntSrcMask) * W + lane * V;
+          const uint32_t slot = w[u] & kEntSrcMask;
+          if (slot < static_cast<uint32_t>(a.stage_cap)) {
+            const uint32_t* sl = slots + slot * W + lane * V;
 #pragma unroll
-          for (int j = 0; j < V; ++j) x[u][j] = sl[j];
+            for (int j = 0; j < V; ++j) x[u][j] = sl[j];
+          } else {   // past the LDS slots: straight from memory
+            const uint32_t src = static_cast<uint32_t>(a.tile_src[s0 + min(static_cast<int>(slot), ns - 1)]);
+            load_row<V>(in, src * (4u * W) + boff, x[u]);
+          }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {

@@ -752,10 +752,15 @@ StagedCsr build_staged(const Csr& c, int slots, int rows) {
     st.tile_row0.push_back(static_cast<int32_t>(r));
     st.tile_src0.push_back(static_cast<int32_t>(st.src.size()));
   }
+  for (int t = 0; t <= st.n_tiles(); ++t) st.tile_ent0.push_back(c.row_ptr[st.tile_row0[t]]);
+  for (int t = 0; t < st.n_tiles(); ++t) {
+    st.max_rows = std::max(st.max_rows, st.tile_row0[t + 1] - st.tile_row0[t]);
+    st.max_ent = std::max(st.max_ent, st.tile_ent0[t + 1] - st.tile_ent0[t]);
+  }
   return st;
 }
 
-StagedCsr build_clustered(const Csr& c, int slots, int rows) {
+StagedCsr build_clustered(const Csr& c, int slots, int rows, int max_ent) {
   if (slots < 1 || rows < 1) throw std::runtime_error("bad staging limits");
   const int64_t n = c.n_rows, nc = std::max<int64_t>(c.n_cols, 1);
   // readers of every source
@@ -775,15 +780,21 @@ StagedCsr build_clustered(const Csr& c, int slots, int rows) {
   std::vector<char> placed(static_cast<size_t>(n), 0);
   std::vector<int32_t> slot_of(static_cast<size_t>(nc), -1);
   std::vector<int32_t> tsrc, ttgt;
-  int64_t next = 0, done = 0;
-  auto new_sources = [&](int64_t r) {
+  int64_t next = 0, done = 0, tent = 0;
+  auto new_sources_count = [&](int64_t r) {
     int k = 0;
     for (int32_t e = c.row_ptr[r]; e < c.row_ptr[r + 1]; ++e) k += slot_of[c.ent[e] & kSrcMask] == -1;
     return k;   // counts a source twice if the row reads it twice (an upper bound)
   };
+  auto fits = [&](int64_t r) {
+    return static_cast<int>(tsrc.size()) + new_sources_count(r) <= slots &&
+           tent + (c.row_ptr[r + 1] - c.row_ptr[r]) <= max_ent;
+  };
+
   auto add = [&](int64_t r) {
     placed[r] = 1;
     ++done;
+    tent += c.row_ptr[r + 1] - c.row_ptr[r];
     ttgt.push_back(static_cast<int32_t>(r));
     for (int32_t e = c.row_ptr[r]; e < c.row_ptr[r + 1]; ++e) {
       const uint32_t s = c.ent[e] & kSrcMask;
@@ -797,20 +808,21 @@ StagedCsr build_clustered(const Csr& c, int slots, int rows) {
     while (placed[next]) ++next;
     tsrc.clear();
     ttgt.clear();
-    add(next);   // a row with more sources than `slots` forms a tile of its own
+    tent = 0;
+    add(next);   // a row over the limits forms a tile of its own
     size_t qi = 0;
     for (;;) {
       if (static_cast<int>(ttgt.size()) >= rows) break;
       if (qi >= tsrc.size()) {
         while (next < n && placed[next]) ++next;
-        if (next >= n || static_cast<int>(tsrc.size()) + new_sources(next) > slots) break;
+        if (next >= n || !fits(next)) break;
         add(next);
         continue;
       }
       const int32_t s = tsrc[qi++];
       for (int64_t k = cp[s]; k < cp[s + 1] && static_cast<int>(ttgt.size()) < rows; ++k) {
         const int32_t t = rd[k];
-        if (placed[t] || static_cast<int>(tsrc.size()) + new_sources(t) > slots) continue;
+        if (placed[t] || !fits(t)) continue;
         add(t);
       }
     }
@@ -822,6 +834,7 @@ StagedCsr build_clustered(const Csr& c, int slots, int rows) {
       for (int32_t e = c.row_ptr[t]; e < c.row_ptr[t + 1]; ++e) {
         const uint32_t w = c.ent[e];
         st.ent.push_back((w & ~kSrcMask) | static_cast<uint32_t>(slot_of[w & kSrcMask]));
+        st.ent_src.push_back(w);
       }
       st.row_ptr.push_back(static_cast<int32_t>(st.ent.size()));
       st.tgt.push_back(t);
@@ -829,9 +842,12 @@ StagedCsr build_clustered(const Csr& c, int slots, int rows) {
     st.src.insert(st.src.end(), sorted.begin(), sorted.end());
     for (int32_t sv : sorted) slot_of[sv] = -1;
     st.max_slots = std::max(st.max_slots, static_cast<int>(sorted.size()));
+    st.max_rows = std::max(st.max_rows, static_cast<int>(ttgt.size()));
+    st.max_ent = std::max<int>(st.max_ent, static_cast<int>(tent));
     st.tile_row0.push_back(static_cast<int32_t>(st.tgt.size()));
     st.tile_src0.push_back(static_cast<int32_t>(st.src.size()));
   }
+  for (int t = 0; t <= st.n_tiles(); ++t) st.tile_ent0.push_back(st.row_ptr[st.tile_row0[t]]);
   return st;
 }
 

@@ -98,6 +98,10 @@ struct StagedCsr {
   // tgt[k]) and the row pointers of that order.  Empty: tile t holds the
   // consecutive rows tile_row0[t] .. and the map's own row pointers apply.
   std::vector<int32_t> tgt, row_ptr;
+  std::vector<uint32_t> ent_src;   // clustered: the entry words with their sources, in tile order
+  // first entry of each tile (n_tiles + 1), the largest tile's rows and entries
+  std::vector<int32_t> tile_ent0;
+  int max_rows = 0, max_ent = 0;
   int n_tiles() const { return static_cast<int>(tile_row0.size()) - 1; }
 };
 
@@ -109,12 +113,12 @@ StagedCsr build_staged(const Csr& c, int slots, int rows);
 // Clustered tiling: a tile grows from the lowest unplaced target through the
 // sources it reads -- every unplaced reader of a source already in the tile
 // joins while the tile keeps at most `rows` targets and `slots` distinct
-// sources -- and when that search closes, the next unplaced target seeds it
-// again if it fits.  Targets that read the same sources share a tile, so a
+// sources (and at most `max_ent` entries) -- and when that search closes,
+// the next unplaced target seeds it again if it fits.  Targets that read the same sources share a tile, so a
 // tile stages fewer source rows per target than a run of consecutive rows
 // (square m = 14 fused pairs: about 1.5 against 2.8 per target at 64 targets
 // and 96 slots).
-StagedCsr build_clustered(const Csr& c, int slots, int rows);
+StagedCsr build_clustered(const Csr& c, int slots, int rows, int max_ent = 1 << 30);
 
 // Builds every single-factor map of (lattice, m); threads = 0 uses the
 // hardware count; paper_order keeps the paper's state order between the

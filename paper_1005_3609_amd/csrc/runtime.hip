@@ -34,6 +34,7 @@
 #include "devexpand.hpp"
 #include "kernels.hpp"
 #include "maps.hpp"
+#include "pipeline.hpp"
 #include "resident.hpp"
 #include "states.hpp"
 
@@ -96,7 +97,9 @@ struct DevStaged {
   const int32_t* tile_src0 = nullptr;
   const int32_t* src = nullptr;
   const int32_t* tgt = nullptr;   // clustered tiles: row written by each tile position
-  int n_tiles = 0, max_slots = 0;
+  const int32_t* tile_ent0 = nullptr;
+  const uint32_t* ent_src = nullptr;   // clustered: entry words with sources, tile order
+  int n_tiles = 0, max_slots = 0, max_rows = 0, max_ent = 0;
 };
 struct DevStagedSet {
   void* base = nullptr;
@@ -805,6 +808,14 @@ const DevFamily& dev_family(const DevMaps& dm, int k) {
 // Slot limit of a staged tile: 48 KiB of LDS (rows of 64 V words).
 int stage_slots(int V) { return 48 * 1024 / (256 * V); }
 constexpr int kStageMaxLds = 64 * 1024;
+constexpr size_t kPipeMaxLds = 64 * 1024;
+
+// Tiles per workgroup of the pipelined staging: about 8, fewer where that
+// would leave under 2048 workgroups over all chunks; at most 63.
+int pipe_tiles_per_block(int n_tiles, int nchunk) {
+  const long total = static_cast<long>(n_tiles) * std::max(nchunk, 1);
+  return static_cast<int>(std::max<long>(1, std::min<long>(8, total / 2048)));
+}
 
 // Device copies of family fam's factors cut into staged tiles: kind 1 runs
 // of consecutive rows, kind 2 clustered tiles (build_clustered; the factors
@@ -823,7 +834,7 @@ const DevStagedSet& dev_staged(const DevMaps& dm, const DevFamily& fam, int slot
     for (size_t i = 0; i < host.size(); ++i)
       th.emplace_back([&, i] {
         try {
-          st[i] = build_clustered(host[i], slots, rows);
+          st[i] = build_clustered(host[i], slots, rows, kPipeMaxEnt);
         } catch (const std::exception& e) {
           err[i] = e.what();
         }
@@ -838,7 +849,8 @@ const DevStagedSet& dev_staged(const DevMaps& dm, const DevFamily& fam, int slot
   for (size_t i = 0; i < host.size(); ++i)
     bytes += align_up(st[i].ent.size() * 4 + 4) + align_up(st[i].tile_row0.size() * 4 + 4) +
              align_up(st[i].tile_src0.size() * 4 + 4) + align_up(st[i].src.size() * 4 + 4) +
-             align_up(st[i].tgt.size() * 4 + 4) + align_up(st[i].row_ptr.size() * 4 + 4);
+             align_up(st[i].tgt.size() * 4 + 4) + align_up(st[i].row_ptr.size() * 4 + 4) +
+             align_up(st[i].tile_ent0.size() * 4 + 4) + align_up(st[i].ent_src.size() * 4 + 4);
   auto set = std::make_unique<DevStagedSet>();
   if (hipMalloc(&set->base, bytes) != hipSuccess) throw MemError("device allocation of staged maps failed");
   char* cur = static_cast<char*>(set->base);
@@ -859,9 +871,13 @@ const DevStagedSet& dev_staged(const DevMaps& dm, const DevFamily& fam, int slot
     if (kind == 2) {
       d.tgt = static_cast<const int32_t*>(put(st[i].tgt.data(), st[i].tgt.size() * 4));
       d.csr.row_ptr = static_cast<const int32_t*>(put(st[i].row_ptr.data(), st[i].row_ptr.size() * 4));
+      d.ent_src = static_cast<const uint32_t*>(put(st[i].ent_src.data(), st[i].ent_src.size() * 4));
     }
+    d.tile_ent0 = static_cast<const int32_t*>(put(st[i].tile_ent0.data(), st[i].tile_ent0.size() * 4));
     d.n_tiles = st[i].n_tiles();
     d.max_slots = st[i].max_slots;
+    d.max_rows = st[i].max_rows;
+    d.max_ent = st[i].max_ent;
   }
   const DevStagedSet& ref = *set;
   fam.staged.emplace(key, std::move(set));
@@ -1082,7 +1098,7 @@ Tune resolve(const chrom_tuning* t, bool series = false, bool resident = false) 
   if (r.streams < 1 || r.streams > 4) throw ArgError("streams must be in 1..4");
   if (t->fuse) r.fuse = t->fuse;
   if (r.fuse < 1 || r.fuse > kMaxFuse) throw ArgError("fuse must be in 1..3");
-  if (t->stage < 0 || t->stage > 2) throw ArgError("stage must be 0, 1 or 2");
+  if (t->stage < 0 || t->stage > 4) throw ArgError("stage must be in 0..4");
   r.stage = t->stage;
   if (series && r.V == 8) {
     if (r.U != 4) throw ArgError("lanes_v 8 runs with unroll 4");
@@ -1515,9 +1531,18 @@ void add_rows(Program& pg, const JobCtx& j, int r_first, int r_last, int after, 
     for (int i = 1; i <= nf; ++i) {
       const bool fused = (i == nf);
       const DevStaged* sd = (j.stg && !fused) ? &j.stg->fac[i - 1] : nullptr;
-      const int lds = sd ? sd->max_slots * j.L.W * 4 : 0;
+      // LDS slots: the widest tile's sources, at most the staging limit (a
+      // tile of one exceptional row reads the rest from memory)
+      const int cap = sd ? std::min(sd->max_slots, stage_slots(j.L.V)) : 0;
+      const int lds = cap * j.L.W * 4;
       Step g = gather_step(j, j.fam->fac[i - 1], cur, oth, cs_x, fused, j.fam->general);
-      if (sd && sd->max_slots > 0 && lds <= kStageMaxLds) {
+      if (sd && j.t.stage == 4) {
+        // direct gathers over the clustered order: positions of targets that
+        // share sources are adjacent, so the shared rows come from the caches
+        g.u.g.csr.row_ptr = sd->csr.row_ptr;
+        g.u.g.csr.ent = sd->ent_src;
+        g.u.g.tile_tgt = sd->tgt;
+      } else if (sd && sd->max_slots > 0 && lds <= kStageMaxLds) {
         g.ntiles = std::max(1, sd->n_tiles);
         g.lds_bytes = lds;
         g.u.g.csr = sd->csr;
@@ -1525,6 +1550,23 @@ void add_rows(Program& pg, const JobCtx& j, int r_first, int r_last, int after, 
         g.u.g.tile_src0 = sd->tile_src0;
         g.u.g.tile_src = sd->src;
         g.u.g.tile_tgt = sd->tgt;
+        g.u.g.stage_cap = cap;
+        // stage 3: pipelined ranges of clustered tiles, where the tiles fit its limits
+        const int pcap = std::min(cap, kPipeSlotsPerWave * j.t.wpb);
+        const size_t plds = pipe_lds_bytes(pcap, j.L.W);
+        // (each thread copies two of a tile's entry words and one row pointer:
+        // a tile's entries must fit 2 x block and its rows + 1 the block)
+        const int block = 64 * j.t.wpb;
+        if (j.t.stage == 3 && sd->max_rows <= kPipeMaxRows && sd->max_rows + 1 <= block &&
+            sd->max_ent <= std::min(kPipeMaxEnt, 2 * block) && plds <= kPipeMaxLds) {
+          const int tpb = pipe_tiles_per_block(sd->n_tiles, j.L.nchunk);
+          g.u.g.tile_ent0 = sd->tile_ent0;
+          g.u.g.n_tiles = sd->n_tiles;
+          g.u.g.tiles_per_block = tpb;
+          g.ntiles = (sd->n_tiles + tpb - 1) / tpb;
+          g.lds_bytes = static_cast<int>(plds);
+          g.u.g.stage_cap = pcap;
+        }
       }
       tm = push(pg, g, after, fused ? prev_reduce : -1);
       after = tm;
@@ -1573,7 +1615,12 @@ void launch_step_vu(const Step& s, int c0, int nch, int wpb, int xcd, hipStream_
           hipLaunchKernelGGL((k_gather<V, U, false, true>), grid, block, 0, st, cf_args(s, row_ctr), xcd, c0);
       } else if (s.u.g.tile_row0) {
         if constexpr (V <= 2) {
-          if (s.general)
+          if (s.u.g.tile_ent0) {
+            if (s.general)
+              hipLaunchKernelGGL((k_stage_pipe<V, U, true>), grid, block, s.lds_bytes, st, s.u.g, xcd, c0);
+            else
+              hipLaunchKernelGGL((k_stage_pipe<V, U, false>), grid, block, s.lds_bytes, st, s.u.g, xcd, c0);
+          } else if (s.general)
             hipLaunchKernelGGL((k_stage<V, U, true>), grid, block, s.lds_bytes, st, s.u.g, xcd, c0);
           else
             hipLaunchKernelGGL((k_stage<V, U, false>), grid, block, s.lds_bytes, st, s.u.g, xcd, c0);
@@ -2254,7 +2301,9 @@ int rows_tile_of(const Tune& t) { return t.rpw * t.wpb; }
 // Staged tiles for the forward factors of a batched or graph-mode job.
 void bind_staging(JobCtx& j, int mode) {
   if (j.t.stage && j.t.V <= 2 && (mode == CHROM_MODE_BATCHED || mode == CHROM_MODE_GRAPH))
-    j.stg = &dev_staged(*j.dm, *j.fam, stage_slots(j.t.V), rows_tile_of(j.t), j.t.stage);
+    j.stg = &dev_staged(*j.dm, *j.fam, stage_slots(j.t.V), rows_tile_of(j.t), j.t.stage == 1 ? 1 : 2);
+  else if (j.t.stage == 4 && (mode == CHROM_MODE_BATCHED || mode == CHROM_MODE_GRAPH))
+    j.stg = &dev_staged(*j.dm, *j.fam, stage_slots(std::min(j.t.V, 2)), rows_tile_of(j.t), 2);
 }
 
 size_t workspace_bytes(int lattice, int m, int I, int n_max_hint, int mode, const Tune& t) {

@@ -104,6 +104,12 @@ def test_small_widths_all_paths(lat, m):
     dict(lanes_v=1, targets_per_wave=4, waves_per_block=4, stage=2, streams=3),
     dict(lanes_v=2, targets_per_wave=16, waves_per_block=2, fuse=3, stage=2, xcd_order=2),
     dict(lanes_v=1, targets_per_wave=1, waves_per_block=1, fuse=2, stage=2, xcd_order=3),
+    dict(lanes_v=2, targets_per_wave=8, waves_per_block=8, fuse=2, stage=3),
+    dict(lanes_v=1, targets_per_wave=4, waves_per_block=4, stage=3, streams=3),
+    dict(lanes_v=2, targets_per_wave=16, waves_per_block=2, fuse=3, stage=3, xcd_order=2),
+    dict(lanes_v=2, targets_per_wave=8, waves_per_block=8, fuse=2, stage=4, streams=3),
+    dict(lanes_v=1, targets_per_wave=4, waves_per_block=4, stage=4, xcd_order=2),
+    dict(lanes_v=4, targets_per_wave=16, waves_per_block=2, fuse=3, stage=4),
 ])
 def test_tuning_choices_are_bit_identical(tune):
     q = list(range(1, 66))                      # 65 q x 2 p = 130 instances
@@ -282,3 +288,16 @@ def test_resident_largest_widths():
         want = OT.chromatic_grid(lat, m, 4, q, p)
         got = api.strip(lat, m, 4, q, p, mode="resident", tuning=dict(lanes_v=1, waves_per_block=16))
         np.testing.assert_array_equal(got.astype(np.int64), want, err_msg=f"{lat} {m}")
+
+
+@pytest.mark.parametrize("stage", [1, 2, 3, 4])
+def test_staged_tiles_with_rows_past_the_lds_slots(stage):
+    # square m = 11 fused triples have rows reading up to 137 distinct
+    # sources, more than the 96 LDS slots of a staged tile at lanes_v 2:
+    # such a row's tile reads its remaining sources straight from memory
+    q, p = list(range(1, 33)), [P31, 998244353]
+    want = OT.chromatic_grid("square", 11, 4, q, p)
+    for mode in ("batched", "graph"):
+        tune = dict(lanes_v=2, targets_per_wave=8, waves_per_block=8, fuse=3, stage=stage)
+        got = api.strip("square", 11, 4, q, p, mode=mode, tuning=tune).astype(np.int64)
+        np.testing.assert_array_equal(got, want, err_msg=f"{mode} stage {stage}")
