@@ -464,6 +464,82 @@ void reader_order(std::vector<Csr>& facs, int threads) {
   for (int k = 0; k < n; ++k) renumber(facs[k], perm[k + 1], perm[k], threads);
 }
 
+// Site order for the spaces between the forward factors T_1..T_n of one row.
+// T_k (1-based site k) touches points up to k (0-based: the pair (k-1, k)
+// and the vertical edge at k-1, and on the triangular lattice the pair
+// (k-2, k-1)), so the sources a target of T_k reads agree with it on the
+// other points up to a merge of two blocks.  Numbering the targets of T_k --
+// the space after it -- lexicographically by their canonical labelling read
+// from point k+1 to m-1 and then from 0 to k, the touched points last, puts
+// the readers of a source next to each other: a run of targets re-reads its
+// sources while they are still cached.  A fused factor T_hi ... T_lo writes
+// the space after T_hi, numbered for T_hi, which touches the highest points
+// of the product.  The target rows are then also visited in that order.
+void site_order(std::vector<Csr>& fwd, int lattice, int m, int threads) {
+  const int n = static_cast<int>(fwd.size());
+  if (n < 2) return;
+  std::vector<std::vector<int32_t>> perm(n + 1);  // perm[k][old] = new, space after T_k
+  std::exception_ptr err;
+  std::mutex err_mu;
+  // spaces are independent: one thread each, every thread sorts its own
+  std::vector<std::thread> pool;
+  std::atomic<int> next{1};
+  const int nt = std::max(1, std::min(threads, n - 1));
+  for (int t = 0; t < nt; ++t)
+    pool.emplace_back([&] {
+      try {
+        for (int k = next++; k < n; k = next++) {
+          const Space sp = lattice == kSquare ? Space{kSqInter, m, k} : Space{kNcnnn, m, 0};
+          const int64_t ns = sp.size();
+          if (ns != fwd[k - 1].n_rows || ns != fwd[k].n_cols) throw std::runtime_error("site order: space size");
+          std::vector<std::pair<unsigned __int128, int32_t>> key(ns);
+          Part p;
+          for (int64_t r = 0; r < ns; ++r) {
+            sp.unrank(r, p);
+            uint8_t relab[kMaxM + 1];
+            std::memset(relab, 0xff, sizeof relab);
+            uint8_t used = 0;
+            unsigned __int128 x = 0;
+            for (int j = 0; j < m; ++j) {
+              const int pt = (k + 1 + j) % m;
+              uint8_t& c = relab[p.lab[pt]];
+              if (c == 0xff) c = used++;
+              x = (x << 5) | c;
+            }
+            key[r] = {x, static_cast<int32_t>(r)};
+          }
+          std::sort(key.begin(), key.end());
+          std::vector<int32_t> pk(ns);
+          for (int64_t j = 0; j < ns; ++j) pk[key[j].second] = static_cast<int32_t>(j);
+          perm[k] = std::move(pk);
+        }
+      } catch (...) {
+        std::lock_guard<std::mutex> lk(err_mu);
+        if (!err) err = std::current_exception();
+      }
+    });
+  for (auto& th : pool) th.join();
+  if (err) std::rethrow_exception(err);
+  for (int k = 0; k < n; ++k) renumber(fwd[k], perm[k + 1], perm[k], threads);
+}
+
+// The numbering to use: paper_order or CHROMSTRIP_STATE_ORDER, else the
+// site order for the evaluation form and the reader order for the normalised
+// form (whose maps are also built on the device, in that order; it never
+// takes the site order).
+int state_order(bool normalised, bool paper_order) {
+  if (paper_order) return kOrderPaper;
+  const char* env = std::getenv("CHROMSTRIP_STATE_ORDER");
+  if (env && *env) {
+    const std::string v(env);
+    if (v == "paper") return kOrderPaper;
+    if (v == "reader") return kOrderReader;
+    if (v == "site") return normalised ? kOrderReader : kOrderSite;
+    throw std::runtime_error("CHROMSTRIP_STATE_ORDER must be paper, reader or site");
+  }
+  return normalised ? kOrderReader : kOrderSite;
+}
+
 // Adds two polynomials / multiplies them (degrees stay <= kMaxDeg).
 Poly padd(const Poly& a, const Poly& b) {
   Poly r;
@@ -588,8 +664,9 @@ std::unique_ptr<Family> build_family(const MapSet& ms, int k) {
       c.ent[e] = static_cast<uint32_t>(p.col[e]) | (static_cast<uint32_t>(code_of[p.coef[e]]) << kSrcBits);
     fam->fac.push_back(std::move(c));
   }
-  const char* order = std::getenv("CHROMSTRIP_STATE_ORDER");
-  if (!(order && std::string(order) == "paper")) reader_order(fam->fac, threads);
+  // site order: the spaces keep the single factors' numbering, made for the
+  // factor that writes each of them
+  if (ms.order == kOrderReader) reader_order(fam->fac, threads);
   return fam;
 }
 
@@ -696,9 +773,10 @@ std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads, bool normali
     else
       finish(ms->last[i], lkeys[i]);
   }
-  const char* order = std::getenv("CHROMSTRIP_STATE_ORDER");
-  if (!paper_order && !(order && std::string(order) == "paper")) reader_order(ms->fwd, threads);
-  log.line(lattice, m, normalised, "reader order, sites", m);
+  ms->order = state_order(normalised, paper_order);
+  if (ms->order == kOrderReader) reader_order(ms->fwd, threads);
+  if (ms->order == kOrderSite) site_order(ms->fwd, lattice, m, threads);
+  log.line(lattice, m, normalised, ms->order == kOrderSite ? "site order, sites" : "state order, sites", m);
   return ms;
 }
 

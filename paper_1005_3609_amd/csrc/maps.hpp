@@ -56,8 +56,17 @@ struct Family {
   std::vector<Poly> codes;        // extends the base table (same numbers for shared codes)
 };
 
+// Numbering of the spaces between the forward factors of a row (internal to
+// the maps; the NCNNN space before the first and after the last factor keeps
+// the paper's order): the paper's order, the reader order (each space by the
+// first row of the next factor that reads it) or the site order (each space
+// by its states' labels read from the point after the last one the factor
+// writing it touches, round to that point).
+enum StateOrder { kOrderPaper = 0, kOrderReader = 1, kOrderSite = 2 };
+
 struct MapSet {
   int lattice = 0, m = 0;
+  int order = kOrderReader;
   // Coefficients in z = q (false) or in z = x = 1/q, the normalised weights
   // of eq. Z_modified (true).
   bool normalised = false;
@@ -122,8 +131,12 @@ StagedCsr build_clustered(const Csr& c, int slots, int rows, int max_ent = 1 << 
 
 // Builds every single-factor map of (lattice, m); threads = 0 uses the
 // hardware count; paper_order keeps the paper's state order between the
-// forward factors (no reader-order relabelling).  Throws std::runtime_error
-// on failure.
+// forward factors.  Otherwise the evaluation form takes the site order and
+// the normalised form the reader order (the order the device-side builder of
+// the normalised maps reproduces); CHROMSTRIP_STATE_ORDER = paper, reader or
+// site overrides either.  Fused families keep the numbering of the single
+// factors' spaces (site order) or take their own reader order.  Throws
+// std::runtime_error on failure.
 std::unique_ptr<MapSet> build_maps(int lattice, int m, int threads = 0, bool normalised = false,
                                    bool paper_order = false);
 

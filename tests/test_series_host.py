@@ -31,12 +31,39 @@ def test_normalised_maps_reproduce_oracle(lat, m, d, p):
     np.testing.assert_array_equal(_run_series(lat, m, 4, d, p), _oracle_series(lat, m, 4, d, p))
 
 
+SHARE = r"""
+import sys
+import numpy as np
+from paper_1005_3609_amd import api
+lat, m, out = sys.argv[1], int(sys.argv[2]), sys.argv[3]
+arrs = {}
+for i in range(m):
+    for which in (0, 4):
+        rp, cols, codes, nc = api.map_export(lat, m, which, i)
+        arrs[f"{which}_{i}_rp"], arrs[f"{which}_{i}_cols"], arrs[f"{which}_{i}_codes"] = rp, cols, codes
+np.savez(out, **arrs)
+"""
+
+
 @pytest.mark.parametrize("lat", [SQ, TRI])
-def test_normalised_maps_share_the_sparsity(lat):
+def test_normalised_maps_share_the_sparsity(lat, tmp_path):
+    # both forms in one numbering (the paper's order; by default the
+    # evaluation form takes the site order and the normalised one the reader
+    # order)
+    import os
+    import subprocess
+    import sys
     m = 6
+    out = str(tmp_path / "maps.npz")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, PYTHONPATH=root, CHROMSTRIP_STATE_ORDER="paper")
+    r = subprocess.run([sys.executable, "-c", SHARE, lat, str(m), out], env=env, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode == 0, r.stderr
+    z = np.load(out)
     for i in range(m):
-        a = api.map_export(lat, m, 0, i)
-        b = api.map_export(lat, m, 4, i)
+        a = tuple(z[f"0_{i}_{k}"] for k in ("rp", "cols", "codes"))
+        b = tuple(z[f"4_{i}_{k}"] for k in ("rp", "cols", "codes"))
         np.testing.assert_array_equal(a[0], b[0])
         np.testing.assert_array_equal(a[1], b[1])
         # entry by entry the two coefficients agree up to a power of q:

@@ -90,11 +90,12 @@ def test_clustered_tiles_reproduce_the_map(lattice, m, fuse, slots, rows):
 
 
 def test_clustered_tiles_share_sources():
-    # at 64 targets and 96 slots a fused pair's clustered tiles stage well
-    # under two source rows per target, against about 2.8 for consecutive rows
-    rp, cols, _, _ = api.map_export("square", 12, 2, 2)
+    # at 64 targets and 96 slots the last fused pair's clustered tiles stage
+    # well under two source rows per target, against about 2.8 for runs of
+    # consecutive rows (its targets, the NCNNN states, keep the paper's order)
+    rp, cols, _, _ = api.map_export("square", 12, 2, 5)
     n_rows = len(rp) - 1
-    cl = api.cluster_export("square", 12, 2, 2, 96, 64)
-    run = api.stage_export("square", 12, 2, 2, 10 ** 6, 64)
-    assert len(cl["src"]) / n_rows < 1.7
+    cl = api.cluster_export("square", 12, 2, 5, 96, 64)
+    run = api.stage_export("square", 12, 2, 5, 10 ** 6, 64)
+    assert len(cl["src"]) / n_rows < 1.8
     assert len(run["src"]) / n_rows > 2.3
