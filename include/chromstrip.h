@@ -106,7 +106,13 @@ typedef struct chrom_tuning {
                            while it computes the current one (1-3: batched and graph
                            modes, lanes_v 1 or 2); 4: direct gathers over the clustered
                            order of the targets (no LDS; lanes_v 1, 2 or 4); the read-out
-                           factor keeps its order; 0: direct gathers */
+                           factor keeps its order; 5: op-stream gathers, each factor's
+                           entries re-encoded as words carrying their coefficient digits
+                           and row ends, read through the scalar cache (evaluation form,
+                           unit coefficients in powers of t up to t^2 -- the square
+                           lattice's single factors and fused pairs -- else CHROM_EINVAL;
+                           batched and graph modes, lanes_v 1 or 2, a chunk's vector
+                           below 2 GiB); 0: direct gathers */
 } chrom_tuning;
 
 /* ------------------------------------------------------------------------

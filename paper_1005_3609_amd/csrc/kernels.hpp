@@ -182,6 +182,10 @@ struct GatherArgs {
   int deg_step;
   int deg_row0;
   const int* deg_row;
+  // Op-stream gather (opgather.hpp; ops == nullptr: none): the factor's op
+  // words and the first word of every row.
+  const uint32_t* ops;
+  const int32_t* op_row;
 };
 
 struct DotArgs {

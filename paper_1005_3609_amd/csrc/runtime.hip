@@ -34,6 +34,7 @@
 #include "devexpand.hpp"
 #include "kernels.hpp"
 #include "maps.hpp"
+#include "opgather.hpp"
 #include "pipeline.hpp"
 #include "resident.hpp"
 #include "states.hpp"
@@ -111,6 +112,17 @@ struct DevSellSet {
   std::vector<DevSell> fac, last;
 };
 
+// A family's factors as op streams (opgather.hpp).
+struct DevOps {
+  const uint32_t* ops = nullptr;
+  const int32_t* op_row = nullptr;
+  int64_t n_cols = 0;
+};
+struct DevOpSet {
+  void* base = nullptr;
+  std::vector<DevOps> fac;
+};
+
 struct DevFamily {
   int k = 1;
   void* base = nullptr;
@@ -124,6 +136,8 @@ struct DevFamily {
   mutable std::map<std::tuple<int, int, int>, std::unique_ptr<DevStagedSet>> staged;
   // sliced-ELL copies of the factors and read-out maps (resident mode), built on first use
   mutable std::unique_ptr<struct DevSellSet> sell;
+  // op streams of the factors (stage 5), built on first use
+  mutable std::unique_ptr<DevOpSet> ops;
 };
 
 struct DevMaps {
@@ -884,6 +898,72 @@ const DevStagedSet& dev_staged(const DevMaps& dm, const DevFamily& fam, int slot
   return ref;
 }
 
+// Op streams of a family's factors (opgather.hpp): one word per entry,
+// source | unit digits of its coefficient in powers of t = q - shift << 24 |
+// row end << 31, one digit-less word for a row without entries, kOpPad zero
+// words after the last row.  Evaluation form only; refused (ArgError) when
+// a code the factors use has a digit outside -1..1 or a t^3 term, or a
+// source state does not fit the word.
+const DevOpSet& dev_ops(const DevMaps& dm, const DevFamily& fam) {
+  std::lock_guard<std::mutex> lk(fam.st_mu);
+  if (fam.ops) return *fam.ops;
+  if (dm.normalised) throw ArgError("op-stream gathers are for the evaluation form");
+  const MapSet& ms = get_maps(dm.lattice, dm.m);
+  const std::vector<Csr>& host = (fam.k == 1) ? ms.fwd : ms.family(fam.k).fac;
+  uint32_t digits[kMaxCodes];
+  bool unit[kMaxCodes];
+  for (size_t c = 0; c < fam.codes.size(); ++c) {
+    const Poly d = shift_basis(fam.codes[c], fam.shift);
+    unit[c] = d.c[3] == 0;
+    digits[c] = 0;
+    for (int k = 0; k < 3; ++k) {
+      if (d.c[k] > 1 || d.c[k] < -1) unit[c] = false;
+      if (d.c[k] == 1) digits[c] |= 1u << (2 * k);
+      if (d.c[k] == -1) digits[c] |= 2u << (2 * k);
+    }
+  }
+  std::vector<std::vector<uint32_t>> words(host.size());
+  std::vector<std::vector<int32_t>> rows(host.size());
+  for (size_t i = 0; i < host.size(); ++i) {
+    const Csr& c = host[i];
+    if (c.n_cols > static_cast<int64_t>(kOpSrcMask)) throw ArgError("op-stream gathers: source space too large");
+    std::vector<uint32_t>& w = words[i];
+    std::vector<int32_t>& rp = rows[i];
+    w.reserve(c.ent.size() + static_cast<size_t>(c.n_rows) + kOpPad);
+    rp.resize(c.n_rows + 1);
+    for (int64_t r = 0; r < c.n_rows; ++r) {
+      rp[r] = static_cast<int32_t>(w.size());
+      const int32_t e0 = c.row_ptr[r], e1 = c.row_ptr[r + 1];
+      if (e0 == e1) w.push_back(kOpRowEnd);
+      for (int32_t e = e0; e < e1; ++e) {
+        const uint32_t code = c.ent[e] >> kSrcBits;
+        if (!unit[code]) throw ArgError("op-stream gathers need unit coefficients in powers of t, up to t^2");
+        w.push_back((c.ent[e] & kSrcMask) | (digits[code] << 24) | (e + 1 == e1 ? kOpRowEnd : 0u));
+      }
+    }
+    rp[c.n_rows] = static_cast<int32_t>(w.size());
+    if (w.size() + kOpPad > static_cast<size_t>(INT32_MAX)) throw ArgError("op-stream gathers: too many entries");
+    w.resize(w.size() + kOpPad, 0u);
+  }
+  size_t bytes = 0;
+  for (size_t i = 0; i < host.size(); ++i) bytes += align_up(words[i].size() * 4) + align_up(rows[i].size() * 4);
+  auto set = std::make_unique<DevOpSet>();
+  if (hipMalloc(&set->base, bytes) != hipSuccess) throw MemError("device allocation of op streams failed");
+  char* cur = static_cast<char*>(set->base);
+  set->fac.resize(host.size());
+  for (size_t i = 0; i < host.size(); ++i) {
+    HIPX(hipMemcpy(cur, words[i].data(), words[i].size() * 4, hipMemcpyHostToDevice));
+    set->fac[i].ops = reinterpret_cast<const uint32_t*>(cur);
+    cur += align_up(words[i].size() * 4);
+    HIPX(hipMemcpy(cur, rows[i].data(), rows[i].size() * 4, hipMemcpyHostToDevice));
+    set->fac[i].op_row = reinterpret_cast<const int32_t*>(cur);
+    cur += align_up(rows[i].size() * 4);
+    set->fac[i].n_cols = host[i].n_cols;
+  }
+  fam.ops = std::move(set);
+  return *fam.ops;
+}
+
 struct Sizes {
   int64_t s_nc, s_max;
 };
@@ -1098,7 +1178,7 @@ Tune resolve(const chrom_tuning* t, bool series = false, bool resident = false) 
   if (r.streams < 1 || r.streams > 4) throw ArgError("streams must be in 1..4");
   if (t->fuse) r.fuse = t->fuse;
   if (r.fuse < 1 || r.fuse > kMaxFuse) throw ArgError("fuse must be in 1..3");
-  if (t->stage < 0 || t->stage > 4) throw ArgError("stage must be in 0..4");
+  if (t->stage < 0 || t->stage > 5) throw ArgError("stage must be in 0..5");
   r.stage = t->stage;
   if (series && r.V == 8) {
     if (r.U != 4) throw ArgError("lanes_v 8 runs with unroll 4");
@@ -1106,6 +1186,7 @@ Tune resolve(const chrom_tuning* t, bool series = false, bool resident = false) 
     throw ArgError(series ? "lanes_v must be 1, 2, 4 or 8" : "lanes_v must be 1, 2 or 4");
   }
   if (r.rpw < 1 || r.rpw > 63) throw ArgError("targets_per_wave must be in 1..63");
+  if (r.stage == 5 && r.V > 2) throw ArgError("stage 5 (op-stream gathers) takes lanes_v 1 or 2");
   if (r.wpb != 1 && r.wpb != 2 && r.wpb != 4 && r.wpb != 8 && !(resident && r.wpb == 16))
     throw ArgError(resident ? "waves_per_block must be 1, 2, 4, 8 or 16" : "waves_per_block must be 1, 2, 4 or 8");
   return r;
@@ -1347,6 +1428,7 @@ struct JobCtx {
   const DevMaps* dm;
   const DevFamily* fam;   // forward factors (single or fused) and their code table
   const DevStagedSet* stg = nullptr;   // staged tiles of fam's factors (batched / graph modes)
+  const DevOpSet* ops = nullptr;       // op streams of fam's factors (stage 5; batched / graph modes)
   JobLayout L;
   JobPtrs P;
   Tune t;
@@ -1536,6 +1618,13 @@ void add_rows(Program& pg, const JobCtx& j, int r_first, int r_last, int after, 
       const int cap = sd ? std::min(sd->max_slots, stage_slots(j.L.V)) : 0;
       const int lds = cap * j.L.W * 4;
       Step g = gather_step(j, j.fam->fac[i - 1], cur, oth, cs_x, fused, j.fam->general);
+      if (j.ops) {
+        // op-stream gathers: every in-range buffer offset below 2^31
+        if (j.ops->fac[i - 1].n_cols * L.W * 4 >= static_cast<int64_t>(kOpRange))
+          throw ArgError("op-stream gathers: a chunk's input vector exceeds 2 GiB");
+        g.u.g.ops = j.ops->fac[i - 1].ops;
+        g.u.g.op_row = j.ops->fac[i - 1].op_row;
+      }
       if (sd && j.t.stage == 4) {
         // direct gathers over the clustered order: positions of targets that
         // share sources are adjacent, so the shared rows come from the caches
@@ -1627,6 +1716,11 @@ void launch_step_vu(const Step& s, int c0, int nch, int wpb, int xcd, hipStream_
         } else {
           throw std::runtime_error("staged tiles need lanes_v 1 or 2");
         }
+      } else if (s.u.g.ops) {
+        if constexpr (V <= 2)
+          hipLaunchKernelGGL(k_gather_ops<V>, grid, block, 0, st, s.u.g, xcd, c0);
+        else
+          throw std::runtime_error("op-stream gathers need lanes_v 1 or 2");
       } else if (s.general) {
         hipLaunchKernelGGL((k_gather<V, U, true, false>), grid, block, 0, st, s.u.g, xcd, c0);
       } else {
@@ -2300,7 +2394,9 @@ int rows_tile_of(const Tune& t) { return t.rpw * t.wpb; }
 
 // Staged tiles for the forward factors of a batched or graph-mode job.
 void bind_staging(JobCtx& j, int mode) {
-  if (j.t.stage && j.t.V <= 2 && (mode == CHROM_MODE_BATCHED || mode == CHROM_MODE_GRAPH))
+  if (j.t.stage == 5 && (mode == CHROM_MODE_BATCHED || mode == CHROM_MODE_GRAPH))
+    j.ops = &dev_ops(*j.dm, *j.fam);
+  else if (j.t.stage && j.t.stage != 5 && j.t.V <= 2 && (mode == CHROM_MODE_BATCHED || mode == CHROM_MODE_GRAPH))
     j.stg = &dev_staged(*j.dm, *j.fam, stage_slots(j.t.V), rows_tile_of(j.t), j.t.stage == 1 ? 1 : 2);
   else if (j.t.stage == 4 && (mode == CHROM_MODE_BATCHED || mode == CHROM_MODE_GRAPH))
     j.stg = &dev_staged(*j.dm, *j.fam, stage_slots(std::min(j.t.V, 2)), rows_tile_of(j.t), 2);

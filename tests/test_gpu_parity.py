@@ -110,6 +110,11 @@ def test_small_widths_all_paths(lat, m):
     dict(lanes_v=2, targets_per_wave=8, waves_per_block=8, fuse=2, stage=4, streams=3),
     dict(lanes_v=1, targets_per_wave=4, waves_per_block=4, stage=4, xcd_order=2),
     dict(lanes_v=4, targets_per_wave=16, waves_per_block=2, fuse=3, stage=4),
+    dict(lanes_v=2, targets_per_wave=8, waves_per_block=8, fuse=2, stage=5, streams=3),
+    dict(lanes_v=1, targets_per_wave=4, waves_per_block=4, stage=5, xcd_order=2),
+    dict(lanes_v=2, targets_per_wave=16, waves_per_block=2, fuse=2, stage=5),
+    dict(lanes_v=2, targets_per_wave=1, waves_per_block=1, stage=5, xcd_order=4),
+    dict(lanes_v=1, targets_per_wave=63, waves_per_block=8, fuse=2, stage=5),
 ])
 def test_tuning_choices_are_bit_identical(tune):
     q = list(range(1, 66))                      # 65 q x 2 p = 130 instances
@@ -227,19 +232,41 @@ def test_square_14x15_benchmark_configurations():
 
 
 # ---------------------------------------------------------------------------
-# Square 18 x 19 (the large-state run), 640 instances
+# Square 18 x 19 (the large-state run), 640 instances, in the launch shape the
+# benchmark times (graph row replay, tuned): sampled instances against stored
+# oracle residues on every row the file holds, and the q = 3 column of every
+# row and prime against exact 3-colouring counts of the 18 x r rectangles
 # ---------------------------------------------------------------------------
-def test_square_18x19_against_transposed_oracle():
+def _three_colourings(lat, m):
+    want = {}
+    with open(os.path.join(HERE, "golden", f"{lat}_three_colourings_m{m}.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                _, mm, r, qq, val = line.split()
+                assert int(mm) == m and int(qq) == 3
+                want[int(r)] = int(val)
+    return want
+
+
+def test_square_18x19_benchmark_shape_against_oracle():
     import torch
+    from paper_1005_3609_amd import tune as tuner
     w = W.workload("square_18x19")
+    q, p = w["q_points"], w["primes"]
     g = _golden("oracle_square_18x19.json")
-    out, ws = api.strip_async("square", 18, 19, w["q_points"], w["primes"], mode="batched")
+    tune = dict(tuner.lookup_tuned("square", 18, len(q) * len(p), 19) or {})
+    mode = tune.pop("mode", "graph")
+    tune.pop("ms", None)
+    out, ws = api.strip_async("square", 18, 19, q, p, mode=mode, tuning=tune)
     torch.cuda.synchronize()
     res = api.to_u32(out).astype(np.int64)
-    rows = g["rows_present"]
-    np.testing.assert_array_equal(_sampled(res, g)[:rows], np.array(g["z"], dtype=np.int64))
-    z = res.reshape(19, 80, 8)
-    assert (z[:, 0, :] == 0).all() and (z[:, 1, :] == 2).all()
+    rows = g.get("rows_present", 19)
+    np.testing.assert_array_equal(_sampled(res, g)[:rows], np.array(g["z"], dtype=np.int64)[:rows])
+    z = res.reshape(19, len(q), len(p))
+    assert (z[:, q.index(1), :] == 0).all() and (z[:, q.index(2), :] == 2).all()
+    three = _three_colourings("square", 18)
+    want = np.array([[three[r] % pp for pp in p] for r in range(1, 20)], dtype=np.int64)
+    np.testing.assert_array_equal(z[:, q.index(3), :], want)
     del ws
 
 
@@ -301,3 +328,28 @@ def test_staged_tiles_with_rows_past_the_lds_slots(stage):
         tune = dict(lanes_v=2, targets_per_wave=8, waves_per_block=8, fuse=3, stage=stage)
         got = api.strip("square", 11, 4, q, p, mode=mode, tuning=tune).astype(np.int64)
         np.testing.assert_array_equal(got, want, err_msg=f"{mode} stage {stage}")
+
+
+# ---------------------------------------------------------------------------
+# Op-stream gathers (stage 5): unit-coefficient factors only
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("lat,m,fuse", [("square", 11, 2), ("square", 9, 1), ("triangular", 9, 1)])
+def test_op_stream_gathers(lat, m, fuse):
+    # streams of every length (targets_per_wave 1..63 rows), rows longer than
+    # a sixteen-word block (fused pairs at m = 11 read up to 46 sources)
+    q, p = list(range(1, 41)), [P31, 998244353, 1000000007]
+    want = OT.chromatic_grid(lat, m, 4, q, p)
+    for tpw, wpb in ((1, 1), (7, 4), (16, 8), (63, 2)):
+        for mode in ("batched", "graph"):
+            tune = dict(lanes_v=2 if tpw != 7 else 1, targets_per_wave=tpw, waves_per_block=wpb, fuse=fuse,
+                        stage=5)
+            got = api.strip(lat, m, 4, q, p, mode=mode, tuning=tune).astype(np.int64)
+            np.testing.assert_array_equal(got, want, err_msg=f"{mode} {tune}")
+
+
+def test_op_stream_gathers_refuse_other_coefficients():
+    # fused triples of the square lattice and fused pairs of the triangular
+    # lattice have digits beyond +-1 or a t^3 term: refused, not approximated
+    for lat, fuse in (("square", 3), ("triangular", 2)):
+        with pytest.raises(api.ChromError, match="unit coefficients"):
+            api.strip(lat, 7, 3, [1, 2, 3], [P31], mode="batched", tuning=dict(fuse=fuse, stage=5))

@@ -222,3 +222,8 @@ def test_bad_arguments_are_errors_without_touching_a_gpu():
     assert api.lib().chromatic_workspace_bytes(0, 13, 3, 2, 1, 3, None) == 0
     with pytest.raises(api.ChromError, match="waves_per_block"):
         api.strip("square", 4, 3, [1, 2], [P31], mode="batched", tuning={"waves_per_block": 16})
+    # op-stream gathers (stage 5) take lanes_v 1 or 2
+    with pytest.raises(api.ChromError, match="stage 5"):
+        api.strip("square", 4, 3, [1, 2], [P31], mode="batched", tuning={"lanes_v": 4, "stage": 5})
+    with pytest.raises(api.ChromError, match="stage must be"):
+        api.strip("square", 4, 3, [1, 2], [P31], mode="batched", tuning={"stage": 6})
