@@ -629,6 +629,9 @@ def main():
     own_row = per_site_row if fuse == 1 else row_bytes(factor_sizes(lat, m, fuse, nf), ipad, s_nc)
     achieved = R * own_row / (k_ms / 1e3) / 1e9
     achieved_per_site = R * per_site_row / (k_ms / 1e3) / 1e9
+    # the headline step itself: every gather launch's own minimum bytes of the
+    # n - 1 transfer rows over the timed step (its other kernels included)
+    achieved_step = (n - 1) * own_row / (ms_per_step / 1e3) / 1e9
     kname = f"k_gather<{V},{tune.get('unroll') or 4}>"
     log(f"factor kernel {kname}: {launches} launches, avg {avg_us:.1f} us, {achieved:.0f} GB/s of the launches' "
         f"own minimum traffic ({achieved_per_site:.0f} GB/s counting every per-site factor's reads and writes)")
@@ -719,7 +722,10 @@ def main():
                      "bytes": "each launch's own minimum: its input and output vectors once, its map, "
                               "and the read-out vector with the last launch of a row",
                      "own_min_bytes_per_row": own_row, "per_site_bytes_per_row": per_site_row,
-                     "achieved_per_site": achieved_per_site, "frac_per_site": achieved_per_site / HBM_PEAK_GBS},
+                     "achieved_per_site": achieved_per_site, "frac_per_site": achieved_per_site / HBM_PEAK_GBS,
+                     "achieved_step": achieved_step, "frac_step": achieved_step / HBM_PEAK_GBS,
+                     "step_note": "the timed headline step (its own launch shape, every kernel of the step): the "
+                                  "gather launches' own minimum bytes over ms_per_step"},
         "plain": plain,
         "cpu_baseline": cpu,
         "secondary": extra or None,
