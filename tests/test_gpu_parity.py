@@ -353,3 +353,24 @@ def test_op_stream_gathers_refuse_other_coefficients():
     for lat, fuse in (("square", 3), ("triangular", 2)):
         with pytest.raises(api.ChromError, match="unit coefficients"):
             api.strip(lat, 7, 3, [1, 2, 3], [P31], mode="batched", tuning=dict(fuse=fuse, stage=5))
+
+
+# ---------------------------------------------------------------------------
+# The grouped mode's cached graph reads its stage tables from the caller's
+# workspace: an identical call on a workspace overwritten in between (same
+# address, as a caching allocator hands it back) must upload them again
+# ---------------------------------------------------------------------------
+def test_grouped_graph_reuploads_its_tables_into_a_reused_workspace():
+    import torch
+    q, p = list(range(1, 30)), [P31, 998244353]
+    want = OT.chromatic_grid("square", 6, 5, q, p)
+    for mode in ("grouped", "graph"):
+        out, ws = api.strip_async("square", 6, 5, q, p, mode=mode, tuning=dict(fuse=2))
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(api.to_u32(out).astype(np.int64), want, err_msg=mode)
+        for fill in (0xFF, 0x00):
+            ws.fill_(fill)
+            out.zero_()
+            api.strip_async("square", 6, 5, q, p, mode=mode, tuning=dict(fuse=2), workspace=ws, out=out)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(api.to_u32(out).astype(np.int64), want, err_msg=f"{mode} fill {fill}")
