@@ -91,9 +91,10 @@ def _oracle_row(args):
 
 def cpu_baseline(lat, m, q_points, primes):
     """The oracle (unchanged) on the host cores: one transfer row of the
-    strip for all of the workload's instances, (a) one process per prime
-    (the instance groups of the survey's plan) in parallel, (b) all
-    instances in one process.  Returns the cpu_baseline record."""
+    strip for all of the workload's instances, (a) split into one group of
+    instances per host core (at most 16, the GPU machine's share), the groups in
+    parallel processes, (b) all instances in one process.  Returns the
+    cpu_baseline record."""
     import multiprocessing as mp
     import platform
     import subprocess
@@ -102,8 +103,8 @@ def cpu_baseline(lat, m, q_points, primes):
 
     from paper_1005_3609_amd import workloads as W
     inst = W.instances(q_points, primes)
-    groups = [[x for x in inst if x[1] == p] for p in primes]
-    procs = min(len(groups), os.cpu_count() or 1, 16)
+    procs = max(1, min(os.cpu_count() or 1, 16, len(inst)))
+    groups = [inst[len(inst) * k // procs:len(inst) * (k + 1) // procs] for k in range(procs)]
     t0 = time.perf_counter()
     with mp.get_context("spawn").Pool(procs) as pool:
         res = pool.map(_oracle_row, [(lat, m, g, W.SEED_BASE + 77) for g in groups])
@@ -118,8 +119,8 @@ def cpu_baseline(lat, m, q_points, primes):
         pass
     return {"value": upd_all / wall, "unit": "state-updates/s", "cores": procs, "kind": "oracle",
             "sample": f"one transfer row (T_{m}..T_1) of the {lat} m={m} strip applied to a dense seeded vector over "
-                      f"all NCNNN states for all {len(inst)} instances, one process per prime ({procs} processes "
-                      f"of {len(inst) // len(primes)} instances, {wall:.1f} s wall, pool start-up included)",
+                      f"all NCNNN states for all {len(inst)} instances, {procs} processes of about "
+                      f"{len(inst) // procs} instances each ({wall:.1f} s wall, pool start-up included)",
             "single_core": {"value": upd_one / t_one, "unit": "state-updates/s", "seconds": t_one,
                             "sample": f"the same row, all {len(inst)} instances in one process"},
             "host": {"cpu_count": os.cpu_count(), "model": model, "python": platform.python_version(),
