@@ -92,7 +92,8 @@ typedef struct chrom_tuning {
   int targets_per_wave; /* consecutive target states handled by one wavefront, 1..63 */
   int waves_per_block;  /* wavefronts per workgroup: 1, 2, 4 or 8 */
   int xcd_order;        /* 0 = default, 1 = hardware round-robin, 2 = contiguous tile range per XCD,
-                           3 / 4 = runs of 4 / 16 consecutive tiles per XCD, runs round-robin */
+                           3 / 4 / 5 / 6 = runs of 4 / 16 / 64 / 256 consecutive tiles per
+                           XCD, runs round-robin */
   int unroll;           /* source rows loaded ahead per wavefront: 4 or 8 (0 = 4) */
   int streams;          /* instance-chunk groups run on parallel streams, 1..4 (0 = 1);
                            graph and batched modes */

@@ -101,13 +101,14 @@ __device__ __forceinline__ int xcd_contiguous(int b, int nb) {
 }
 
 // Block-id remaps (all bijections on [0, nb)): mode 1 gives each XCD one
-// contiguous range; modes 2 and 3 give each XCD runs of 4 or 16 consecutive
-// ids, the runs dealt round-robin (neighbouring tiles share an L2 while every
-// XCD still samples the whole launch); ids past the last whole round stay.
+// contiguous range; modes 2..5 give each XCD runs of 4, 16, 64 or 256
+// consecutive ids, the runs dealt round-robin (neighbouring tiles share an
+// L2 while the XCDs together sweep one region of the launch); ids past the
+// last whole round stay.
 __device__ __forceinline__ int xcd_remap(int b, int nb, int mode) {
   if (mode == 1) return xcd_contiguous(b, nb);
   constexpr int X = 8;
-  const int G = mode == 2 ? 4 : 16;
+  const int G = 1 << (2 * (mode - 1));
   const int nfull = nb / (X * G) * (X * G);
   if (b >= nfull) return b;
   const int x = b % X, k = b / X;

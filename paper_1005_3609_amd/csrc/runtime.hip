@@ -1170,7 +1170,7 @@ Tune resolve(const chrom_tuning* t, bool series = false, bool resident = false) 
   if (t->lanes_v) r.V = t->lanes_v;
   if (t->targets_per_wave) r.rpw = t->targets_per_wave;
   if (t->waves_per_block) r.wpb = t->waves_per_block;
-  if (t->xcd_order < 0 || t->xcd_order > 4) throw ArgError("xcd_order must be in 0..4");
+  if (t->xcd_order < 0 || t->xcd_order > 6) throw ArgError("xcd_order must be in 0..6");
   if (t->xcd_order) r.xcd = t->xcd_order - 1;
   if (t->unroll) r.U = t->unroll;
   if (t->streams) r.streams = t->streams;

@@ -347,6 +347,18 @@ def test_op_stream_gathers(lat, m, fuse):
             np.testing.assert_array_equal(got, want, err_msg=f"{mode} {tune}")
 
 
+@pytest.mark.parametrize("xcd", [5, 6])
+def test_xcd_runs_of_64_and_256_tiles(xcd):
+    # one wavefront per tile and workgroup: about 8000 tiles per chunk, so
+    # whole rounds of 8 x 64 and 8 x 256 remapped ids and a ragged rest
+    q, p = list(range(1, 70)), [P31]
+    want = OT.chromatic_grid("square", 11, 3, q, p)
+    for mode in ("batched", "graph", "grouped"):
+        tune = dict(lanes_v=1, targets_per_wave=1, waves_per_block=1, xcd_order=xcd, fuse=2)
+        got = api.strip("square", 11, 3, q, p, mode=mode, tuning=tune).astype(np.int64)
+        np.testing.assert_array_equal(got, want, err_msg=f"{mode} {tune}")
+
+
 def test_op_stream_gathers_refuse_other_coefficients():
     # fused triples of the square lattice and fused pairs of the triangular
     # lattice have digits beyond +-1 or a t^3 term: refused, not approximated
