@@ -427,6 +427,18 @@ int chromatic_stage_export(int lattice, int m, int fuse, int idx, int slots, int
                            int32_t* tile_row0, int32_t* tile_src0, int32_t* src,
                            uint32_t* entries);
 
+/* The op-stream form (tuning `stage` = 5) of forward factor idx of the
+ * fuse-sized family, evaluation form: the basis shift s of the family's
+ * kernels, and one word per entry in target row order -- bits 0..22 the
+ * source state, bits 24 + 2k / 25 + 2k set for a digit d_k = +1 / -1 of the
+ * entry's coefficient in powers of t = q - s (k = 0..2), bit 31 on the last
+ * word of a row; a row without entries is one word with only bit 31 -- then
+ * 64 zero words.  row_first[r] (n_rows + 1 entries) is the first word of row
+ * r.  CHROM_EINVAL when a code has a digit outside -1..1 or a t^3 term.
+ * Host-only.  Pass NULL buffers to query n_words (the padding included). */
+int chromatic_op_export(int lattice, int m, int fuse, int idx, int32_t* shift, int64_t* n_words,
+                        int32_t* row_first, uint32_t* words);
+
 /* The clustered staged-tile form (tuning `stage` = 2) of forward factor idx
  * of the fuse-sized family: tiles of target rows that read the same sources.
  * A tile grows from the lowest unplaced target by adding every unplaced

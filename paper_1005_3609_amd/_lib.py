@@ -87,6 +87,8 @@ _SIGS = {
     "chromatic_stage_export": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                          C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "chromatic_op_export": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int64), C.c_void_p, C.c_void_p]),
     "chromatic_cluster_export": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                            C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,

@@ -364,6 +364,20 @@ def cluster_export(lattice, m: int, fuse: int, idx: int, slots: int, rows: int) 
                 max_slots=int(mx.value))
 
 
+def op_export(lattice, m: int, fuse: int, idx: int) -> dict:
+    """Op-stream form (tuning stage 5) of forward factor idx of the
+    fuse-sized family: dict(shift, row_first int32[n_rows+1], words
+    uint32[n_words], padding included)."""
+    L = lib()
+    sh, nw = C.c_int32(), C.c_int64()
+    check(L.chromatic_op_export(lattice_id(lattice), m, fuse, idx, C.byref(sh), C.byref(nw), None, None))
+    rp, _, _, _ = map_export(lattice, m, 0 if fuse == 1 else fuse, idx)
+    rows = np.zeros(len(rp), dtype=np.int32)
+    words = np.zeros(max(nw.value, 1), dtype=np.uint32)
+    check(L.chromatic_op_export(lattice_id(lattice), m, fuse, idx, None, None, _ptr(rows), _ptr(words)))
+    return dict(shift=int(sh.value), row_first=rows, words=words[: nw.value])
+
+
 def map_export(lattice, m: int, which: int, idx: int):
     """(row_ptr int32[n_rows+1], cols int64[nnz], codes int64[nnz], n_cols);
     which: 0 forward factor, 1 read-out factor (transposed), 2/3 fused family,

@@ -898,53 +898,57 @@ const DevStagedSet& dev_staged(const DevMaps& dm, const DevFamily& fam, int slot
   return ref;
 }
 
-// Op streams of a family's factors (opgather.hpp): one word per entry,
-// source | unit digits of its coefficient in powers of t = q - shift << 24 |
-// row end << 31, one digit-less word for a row without entries, kOpPad zero
-// words after the last row.  Evaluation form only; refused (ArgError) when
-// a code the factors use has a digit outside -1..1 or a t^3 term, or a
-// source state does not fit the word.
+// Op stream of one factor (opgather.hpp): one word per entry, source |
+// unit digits of its coefficient in powers of t = q - shift << 24 | row end
+// << 31, one digit-less word for a row without entries, kOpPad zero words
+// after the last row; rows[r] = the first word of row r (n_rows + 1).
+// ArgError when a code the factor uses has a digit outside -1..1 or a t^3
+// term, or a source state does not fit the word.
+void build_op_stream(const Csr& c, const std::vector<Poly>& codes, int shift, std::vector<uint32_t>& w,
+                     std::vector<int32_t>& rp) {
+  uint32_t digits[kMaxCodes];
+  bool unit[kMaxCodes];
+  for (size_t k = 0; k < codes.size(); ++k) {
+    const Poly d = shift_basis(codes[k], shift);
+    unit[k] = d.c[3] == 0;
+    digits[k] = 0;
+    for (int j = 0; j < 3; ++j) {
+      if (d.c[j] > 1 || d.c[j] < -1) unit[k] = false;
+      if (d.c[j] == 1) digits[k] |= 1u << (2 * j);
+      if (d.c[j] == -1) digits[k] |= 2u << (2 * j);
+    }
+  }
+  if (c.n_cols > static_cast<int64_t>(kOpSrcMask)) throw ArgError("op-stream gathers: source space too large");
+  w.clear();
+  w.reserve(c.ent.size() + static_cast<size_t>(c.n_rows) + kOpPad);
+  rp.assign(c.n_rows + 1, 0);
+  for (int64_t r = 0; r < c.n_rows; ++r) {
+    rp[r] = static_cast<int32_t>(w.size());
+    const int32_t e0 = c.row_ptr[r], e1 = c.row_ptr[r + 1];
+    if (e0 == e1) w.push_back(kOpRowEnd);
+    for (int32_t e = e0; e < e1; ++e) {
+      const uint32_t code = c.ent[e] >> kSrcBits;
+      if (code >= codes.size() || !unit[code])
+        throw ArgError("op-stream gathers need unit coefficients in powers of t, up to t^2");
+      w.push_back((c.ent[e] & kSrcMask) | (digits[code] << 24) | (e + 1 == e1 ? kOpRowEnd : 0u));
+    }
+  }
+  rp[c.n_rows] = static_cast<int32_t>(w.size());
+  if (w.size() + kOpPad > static_cast<size_t>(INT32_MAX)) throw ArgError("op-stream gathers: too many entries");
+  w.resize(w.size() + kOpPad, 0u);
+}
+
+// Op streams of a family's factors (stage 5), built on first use.
+// Evaluation form only.
 const DevOpSet& dev_ops(const DevMaps& dm, const DevFamily& fam) {
   std::lock_guard<std::mutex> lk(fam.st_mu);
   if (fam.ops) return *fam.ops;
   if (dm.normalised) throw ArgError("op-stream gathers are for the evaluation form");
   const MapSet& ms = get_maps(dm.lattice, dm.m);
   const std::vector<Csr>& host = (fam.k == 1) ? ms.fwd : ms.family(fam.k).fac;
-  uint32_t digits[kMaxCodes];
-  bool unit[kMaxCodes];
-  for (size_t c = 0; c < fam.codes.size(); ++c) {
-    const Poly d = shift_basis(fam.codes[c], fam.shift);
-    unit[c] = d.c[3] == 0;
-    digits[c] = 0;
-    for (int k = 0; k < 3; ++k) {
-      if (d.c[k] > 1 || d.c[k] < -1) unit[c] = false;
-      if (d.c[k] == 1) digits[c] |= 1u << (2 * k);
-      if (d.c[k] == -1) digits[c] |= 2u << (2 * k);
-    }
-  }
   std::vector<std::vector<uint32_t>> words(host.size());
   std::vector<std::vector<int32_t>> rows(host.size());
-  for (size_t i = 0; i < host.size(); ++i) {
-    const Csr& c = host[i];
-    if (c.n_cols > static_cast<int64_t>(kOpSrcMask)) throw ArgError("op-stream gathers: source space too large");
-    std::vector<uint32_t>& w = words[i];
-    std::vector<int32_t>& rp = rows[i];
-    w.reserve(c.ent.size() + static_cast<size_t>(c.n_rows) + kOpPad);
-    rp.resize(c.n_rows + 1);
-    for (int64_t r = 0; r < c.n_rows; ++r) {
-      rp[r] = static_cast<int32_t>(w.size());
-      const int32_t e0 = c.row_ptr[r], e1 = c.row_ptr[r + 1];
-      if (e0 == e1) w.push_back(kOpRowEnd);
-      for (int32_t e = e0; e < e1; ++e) {
-        const uint32_t code = c.ent[e] >> kSrcBits;
-        if (!unit[code]) throw ArgError("op-stream gathers need unit coefficients in powers of t, up to t^2");
-        w.push_back((c.ent[e] & kSrcMask) | (digits[code] << 24) | (e + 1 == e1 ? kOpRowEnd : 0u));
-      }
-    }
-    rp[c.n_rows] = static_cast<int32_t>(w.size());
-    if (w.size() + kOpPad > static_cast<size_t>(INT32_MAX)) throw ArgError("op-stream gathers: too many entries");
-    w.resize(w.size() + kOpPad, 0u);
-  }
+  for (size_t i = 0; i < host.size(); ++i) build_op_stream(host[i], fam.codes, fam.shift, words[i], rows[i]);
   size_t bytes = 0;
   for (size_t i = 0; i < host.size(); ++i) bytes += align_up(words[i].size() * 4) + align_up(rows[i].size() * 4);
   auto set = std::make_unique<DevOpSet>();
@@ -3280,6 +3284,28 @@ int chromatic_stage_export(int lattice, int m, int fuse, int idx, int slots, int
     if (tile_src0) std::memcpy(tile_src0, st.tile_src0.data(), st.tile_src0.size() * 4);
     if (src && !st.src.empty()) std::memcpy(src, st.src.data(), st.src.size() * 4);
     if (entries && !st.ent.empty()) std::memcpy(entries, st.ent.data(), st.ent.size() * 4);
+    return CHROM_OK;
+  });
+}
+
+int chromatic_op_export(int lattice, int m, int fuse, int idx, int32_t* shift, int64_t* n_words,
+                        int32_t* row_first, uint32_t* words) {
+  return guarded([&] {
+    check_args(lattice, m, 0);
+    if (fuse < 1 || fuse > kMaxFuse) throw ArgError("fuse must be in 1..3");
+    const MapSet& ms = get_maps(lattice, m);
+    const std::vector<Csr>& fac = (fuse == 1) ? ms.fwd : ms.family(fuse).fac;
+    const std::vector<Poly>& codes = (fuse == 1) ? ms.codes : ms.family(fuse).codes;
+    if (idx < 0 || idx >= static_cast<int>(fac.size())) throw ArgError("idx out of range");
+    bool general = false;
+    const int s = choose_shift(codes, fac, general);
+    std::vector<uint32_t> w;
+    std::vector<int32_t> rp;
+    build_op_stream(fac[idx], codes, s, w, rp);
+    if (shift) *shift = s;
+    if (n_words) *n_words = static_cast<int64_t>(w.size());
+    if (row_first) std::memcpy(row_first, rp.data(), rp.size() * 4);
+    if (words) std::memcpy(words, w.data(), w.size() * 4);
     return CHROM_OK;
   });
 }

@@ -99,3 +99,48 @@ def test_clustered_tiles_share_sources():
     run = api.stage_export("square", 12, 2, 5, 10 ** 6, 64)
     assert len(cl["src"]) / n_rows < 1.8
     assert len(run["src"]) / n_rows > 2.3
+
+
+# ---------------------------------------------------------------------------
+# Op streams (tuning stage 5): the kernel's words decoded against the maps
+# ---------------------------------------------------------------------------
+def _shifted(poly, s):
+    """Coefficients of sum_j c_j q^j in powers of t = q - s."""
+    from math import comb
+    return [sum(poly[j] * comb(j, k) * s ** (j - k) for j in range(k, 4)) for k in range(4)]
+
+
+@pytest.mark.parametrize("lat,m,fuse", [("square", 7, 1), ("square", 7, 2), ("triangular", 6, 1),
+                                        ("square", 11, 2)])
+def test_op_streams_encode_the_maps(lat, m, fuse):
+    codes = api.family_info(lat, m, fuse)["codes"]
+    nf = api.family_info(lat, m, fuse)["n_factors"]
+    for idx in range(nf):
+        rp, cols, cc, _ = api.map_export(lat, m, 0 if fuse == 1 else fuse, idx)
+        ox = api.op_export(lat, m, fuse, idx)
+        w, first = ox["words"].astype(np.int64), ox["row_first"]
+        assert (w[-64:] == 0).all() and first[-1] == len(w) - 64
+        digits = {}
+        for c, poly in enumerate(codes):
+            d = _shifted(poly, ox["shift"])
+            digits[c] = (d[3] == 0 and all(abs(x) <= 1 for x in d[:3]),
+                         sum((1 << (24 + 2 * k)) if d[k] == 1 else (1 << (25 + 2 * k)) if d[k] == -1 else 0
+                             for k in range(3)))
+        for r in range(len(rp) - 1):
+            row = w[first[r]:first[r + 1]]
+            ents = range(rp[r], rp[r + 1])
+            if len(ents) == 0:
+                assert list(row) == [1 << 31]
+                continue
+            assert len(row) == len(ents)
+            np.testing.assert_array_equal(row & ((1 << 23) - 1), cols[rp[r]:rp[r + 1]])
+            np.testing.assert_array_equal(row >> 31, [0] * (len(ents) - 1) + [1])
+            for word, e in zip(row, ents):
+                ok, bits = digits[int(cc[e])]
+                assert ok and (int(word) & 0x3F000000) == bits
+
+
+def test_op_streams_refuse_other_coefficients():
+    for lat, fuse in (("square", 3), ("triangular", 2)):
+        with pytest.raises(api.ChromError, match="unit coefficients"):
+            api.op_export(lat, 7, fuse, 1)
