@@ -113,7 +113,11 @@ typedef struct chrom_tuning {
                            unit coefficients in powers of t up to t^2 -- the square
                            lattice's single factors and fused pairs -- else CHROM_EINVAL;
                            batched and graph modes, lanes_v 1 or 2, a chunk's vector
-                           below 2 GiB); 0: direct gathers */
+                           below 2 GiB); 6: direct gathers over an interleaved order, the
+                           k-th row of wavefront w of a workgroup being row k x waves + w
+                           of its tile, so the workgroup's wavefronts work on adjacent rows
+                           at the same time (batched and graph modes; the read-out factor
+                           keeps its order); 0: direct gathers */
 } chrom_tuning;
 
 /* ------------------------------------------------------------------------

@@ -838,6 +838,37 @@ StagedCsr build_staged(const Csr& c, int slots, int rows) {
   return st;
 }
 
+StagedCsr build_interleaved(const Csr& c, int rows_tile, int waves) {
+  if (rows_tile < 1 || waves < 1 || rows_tile % waves != 0) throw std::runtime_error("bad interleave shape");
+  const int64_t n = c.n_rows;
+  const int rpw = rows_tile / waves;
+  StagedCsr st;
+  st.tile_row0.push_back(0);
+  st.tile_src0.push_back(0);
+  st.tgt.resize(n);
+  const int64_t whole = n / rows_tile * rows_tile;
+  for (int64_t pos = 0; pos < n; ++pos) {
+    if (pos < whole) {
+      const int64_t b = pos / rows_tile, o = pos % rows_tile;
+      const int64_t w = o / rpw, k = o % rpw;
+      st.tgt[pos] = static_cast<int32_t>(b * rows_tile + k * waves + w);
+    } else {
+      st.tgt[pos] = static_cast<int32_t>(pos);
+    }
+  }
+  st.row_ptr.assign(n + 1, 0);
+  for (int64_t pos = 0; pos < n; ++pos) {
+    const int32_t r = st.tgt[pos];
+    st.row_ptr[pos + 1] = st.row_ptr[pos] + (c.row_ptr[r + 1] - c.row_ptr[r]);
+  }
+  st.ent_src.resize(c.ent.size());
+  for (int64_t pos = 0; pos < n; ++pos) {
+    const int32_t r = st.tgt[pos];
+    std::copy(c.ent.begin() + c.row_ptr[r], c.ent.begin() + c.row_ptr[r + 1], st.ent_src.begin() + st.row_ptr[pos]);
+  }
+  return st;
+}
+
 StagedCsr build_clustered(const Csr& c, int slots, int rows, int max_ent) {
   if (slots < 1 || rows < 1) throw std::runtime_error("bad staging limits");
   const int64_t n = c.n_rows, nc = std::max<int64_t>(c.n_cols, 1);

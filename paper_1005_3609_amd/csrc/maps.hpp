@@ -129,6 +129,14 @@ StagedCsr build_staged(const Csr& c, int slots, int rows);
 // and 96 slots).
 StagedCsr build_clustered(const Csr& c, int slots, int rows, int max_ent = 1 << 30);
 
+// Interleaved order for direct gathers: within every whole tile of
+// `rows_tile` = waves x rows-per-wavefront consecutive target rows, the k-th
+// row of wavefront w is tile row k * waves + w, so at each step of their row
+// loops the tile's wavefronts work on adjacent rows (which share sources);
+// a last partial tile keeps its order.  Fills tgt, row_ptr and ent_src
+// (tile_row0 = {0}, no slots).
+StagedCsr build_interleaved(const Csr& c, int rows_tile, int waves);
+
 // Builds every single-factor map of (lattice, m); threads = 0 uses the
 // hardware count; paper_order keeps the paper's state order between the
 // forward factors.  Otherwise the evaluation form takes the site order and

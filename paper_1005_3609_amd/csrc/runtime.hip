@@ -842,7 +842,10 @@ const DevStagedSet& dev_staged(const DevMaps& dm, const DevFamily& fam, int slot
   const MapSet& ms = get_maps(dm.lattice, dm.m);
   const std::vector<Csr>& host = (fam.k == 1) ? ms.fwd : ms.family(fam.k).fac;
   std::vector<StagedCsr> st(host.size());
-  if (kind == 2) {
+  if (kind == 3) {
+    // interleaved order: `slots` carries the wavefronts per workgroup
+    for (size_t i = 0; i < host.size(); ++i) st[i] = build_interleaved(host[i], rows, slots);
+  } else if (kind == 2) {
     std::vector<std::thread> th;
     std::vector<std::string> err(host.size());
     for (size_t i = 0; i < host.size(); ++i)
@@ -882,7 +885,7 @@ const DevStagedSet& dev_staged(const DevMaps& dm, const DevFamily& fam, int slot
     d.tile_row0 = static_cast<const int32_t*>(put(st[i].tile_row0.data(), st[i].tile_row0.size() * 4));
     d.tile_src0 = static_cast<const int32_t*>(put(st[i].tile_src0.data(), st[i].tile_src0.size() * 4));
     d.src = static_cast<const int32_t*>(put(st[i].src.data(), st[i].src.size() * 4));
-    if (kind == 2) {
+    if (kind >= 2) {
       d.tgt = static_cast<const int32_t*>(put(st[i].tgt.data(), st[i].tgt.size() * 4));
       d.csr.row_ptr = static_cast<const int32_t*>(put(st[i].row_ptr.data(), st[i].row_ptr.size() * 4));
       d.ent_src = static_cast<const uint32_t*>(put(st[i].ent_src.data(), st[i].ent_src.size() * 4));
@@ -1182,7 +1185,7 @@ Tune resolve(const chrom_tuning* t, bool series = false, bool resident = false) 
   if (r.streams < 1 || r.streams > 4) throw ArgError("streams must be in 1..4");
   if (t->fuse) r.fuse = t->fuse;
   if (r.fuse < 1 || r.fuse > kMaxFuse) throw ArgError("fuse must be in 1..3");
-  if (t->stage < 0 || t->stage > 5) throw ArgError("stage must be in 0..5");
+  if (t->stage < 0 || t->stage > 6) throw ArgError("stage must be in 0..6");
   r.stage = t->stage;
   if (series && r.V == 8) {
     if (r.U != 4) throw ArgError("lanes_v 8 runs with unroll 4");
@@ -1629,7 +1632,7 @@ void add_rows(Program& pg, const JobCtx& j, int r_first, int r_last, int after, 
         g.u.g.ops = j.ops->fac[i - 1].ops;
         g.u.g.op_row = j.ops->fac[i - 1].op_row;
       }
-      if (sd && j.t.stage == 4) {
+      if (sd && (j.t.stage == 4 || j.t.stage == 6)) {
         // direct gathers over the clustered order: positions of targets that
         // share sources are adjacent, so the shared rows come from the caches
         g.u.g.csr.row_ptr = sd->csr.row_ptr;
@@ -2400,7 +2403,10 @@ int rows_tile_of(const Tune& t) { return t.rpw * t.wpb; }
 void bind_staging(JobCtx& j, int mode) {
   if (j.t.stage == 5 && (mode == CHROM_MODE_BATCHED || mode == CHROM_MODE_GRAPH))
     j.ops = &dev_ops(*j.dm, *j.fam);
-  else if (j.t.stage && j.t.stage != 5 && j.t.V <= 2 && (mode == CHROM_MODE_BATCHED || mode == CHROM_MODE_GRAPH))
+  else if (j.t.stage == 6 && (mode == CHROM_MODE_BATCHED || mode == CHROM_MODE_GRAPH))
+    j.stg = &dev_staged(*j.dm, *j.fam, j.t.wpb, rows_tile_of(j.t), 3);
+  else if (j.t.stage && j.t.stage != 5 && j.t.stage != 6 && j.t.V <= 2 &&
+           (mode == CHROM_MODE_BATCHED || mode == CHROM_MODE_GRAPH))
     j.stg = &dev_staged(*j.dm, *j.fam, stage_slots(j.t.V), rows_tile_of(j.t), j.t.stage == 1 ? 1 : 2);
   else if (j.t.stage == 4 && (mode == CHROM_MODE_BATCHED || mode == CHROM_MODE_GRAPH))
     j.stg = &dev_staged(*j.dm, *j.fam, stage_slots(std::min(j.t.V, 2)), rows_tile_of(j.t), 2);

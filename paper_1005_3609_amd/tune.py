@@ -27,7 +27,7 @@ from . import api
 DEFAULT_CACHE = os.environ.get("CHROMSTRIP_TUNE_CACHE",
                                os.path.join(os.path.expanduser("~"), ".cache", "chromstrip", "tune.json"))
 SPACE = dict(lanes_v=[1, 2, 4], targets_per_wave=[4, 8, 16], waves_per_block=[2, 4, 8],
-             xcd_order=[1, 2], unroll=[4, 8], streams=[1, 2], fuse=[1, 2, 3], stage=[0, 1, 2, 3, 4, 5],
+             xcd_order=[1, 2], unroll=[4, 8], streams=[1, 2], fuse=[1, 2, 3], stage=[0, 1, 2, 3, 4, 5, 6],
              mode=["graph", "grouped"])
 
 
@@ -43,7 +43,7 @@ def candidates(space=None) -> list[dict]:
             continue            # its own candidates: resident_candidates
         if mode == "grouped" and s != 1:
             continue            # grouped launches already cover every chunk at once
-        if g and (mode == "grouped" or (v > 2 and g != 4)):
+        if g and (mode == "grouped" or (v > 2 and g not in (4, 6))):
             continue            # staging and op streams apply to graph / batched launches (lanes_v <= 2)
         out.append(dict(lanes_v=v, targets_per_wave=t, waves_per_block=w, xcd_order=x, unroll=u, streams=s,
                         fuse=f, stage=g, mode=mode))

@@ -115,6 +115,9 @@ def test_small_widths_all_paths(lat, m):
     dict(lanes_v=2, targets_per_wave=16, waves_per_block=2, fuse=2, stage=5),
     dict(lanes_v=2, targets_per_wave=1, waves_per_block=1, stage=5, xcd_order=4),
     dict(lanes_v=1, targets_per_wave=63, waves_per_block=8, fuse=2, stage=5),
+    dict(lanes_v=2, targets_per_wave=8, waves_per_block=8, fuse=2, stage=6, streams=3),
+    dict(lanes_v=1, targets_per_wave=3, waves_per_block=4, stage=6, xcd_order=3),
+    dict(lanes_v=4, targets_per_wave=16, waves_per_block=2, fuse=3, stage=6),
 ])
 def test_tuning_choices_are_bit_identical(tune):
     q = list(range(1, 66))                      # 65 q x 2 p = 130 instances

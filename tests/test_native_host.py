@@ -226,4 +226,4 @@ def test_bad_arguments_are_errors_without_touching_a_gpu():
     with pytest.raises(api.ChromError, match="stage 5"):
         api.strip("square", 4, 3, [1, 2], [P31], mode="batched", tuning={"lanes_v": 4, "stage": 5})
     with pytest.raises(api.ChromError, match="stage must be"):
-        api.strip("square", 4, 3, [1, 2], [P31], mode="batched", tuning={"stage": 6})
+        api.strip("square", 4, 3, [1, 2], [P31], mode="batched", tuning={"stage": 7})
