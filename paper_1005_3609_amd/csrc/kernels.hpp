@@ -76,6 +76,25 @@ __device__ __forceinline__ void store_row(uint32_t* base, uint32_t off, const ui
   store_v<V>(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(base) + off), x);
 }
 
+// The same with the non-temporal hint (rows of vectors far larger than the
+// caches, written once and read a launch later).
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+template <int V>
+__device__ __forceinline__ void store_row_nt(uint32_t* base, uint32_t off, const uint32_t (&x)[V]) {
+  char* p = reinterpret_cast<char*>(base) + off;
+  if constexpr (V == 1) {
+    __builtin_nontemporal_store(x[0], reinterpret_cast<uint32_t*>(p));
+  } else if constexpr (V == 2) {
+    __builtin_nontemporal_store(u32x2_t{x[0], x[1]}, reinterpret_cast<u32x2_t*>(p));
+  } else {
+#pragma unroll
+    for (int h = 0; h < V / 4; ++h)
+      __builtin_nontemporal_store(u32x4_t{x[4 * h], x[4 * h + 1], x[4 * h + 2], x[4 * h + 3]},
+                                  reinterpret_cast<u32x4_t*>(p + 16 * h));
+  }
+}
+
 // Row base for vectors whose chunk exceeds 4 GiB: the 64-bit address of row
 // `row` formed in scalar registers (readfirstlane keeps the compiler from
 // folding it into per-lane 64-bit addresses), so every access is that base
@@ -187,6 +206,8 @@ struct GatherArgs {
   // words and the first word of every row.
   const uint32_t* ops;
   const int32_t* op_row;
+  // Evaluation form: store target rows with the non-temporal hint.
+  int nt_store;
 };
 
 struct DotArgs {
@@ -476,7 +497,10 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
           store_row<V>(wide_row<W>(out, static_cast<uint32_t>(row)), boff, v);
         } else if constexpr (!CF) {
           const int dst = a.tile_tgt ? __builtin_amdgcn_readlane(tg, row - r0) : row;
-          store_row<V>(out, static_cast<uint32_t>(dst) * (4u * W) + boff, v);
+          if (a.nt_store)
+            store_row_nt<V>(out, static_cast<uint32_t>(dst) * (4u * W) + boff, v);
+          else
+            store_row<V>(out, static_cast<uint32_t>(dst) * (4u * W) + boff, v);
         } else {
           store_row<V>(out, static_cast<uint32_t>(row) * (4u * W) + boff, v);
         }

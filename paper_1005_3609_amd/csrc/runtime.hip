@@ -1456,6 +1456,9 @@ int push(Program& pg, const Step& s, int d0, int d1) {
   return static_cast<int>(pg.steps.size()) - 1;
 }
 
+// Output vectors past this size take non-temporal row stores.
+constexpr int64_t kNtStoreBytes = int64_t(1) << 30;
+
 Step gather_step(const JobCtx& j, const DevCsr& c, const uint32_t* in, uint32_t* out, long out_cstride, bool fused,
                  bool general) {
   Step s{};
@@ -1476,6 +1479,9 @@ Step gather_step(const JobCtx& j, const DevCsr& c, const uint32_t* in, uint32_t*
     a.partial = j.P.part;
     a.p_cstride = static_cast<long>(j.L.nparts) * j.L.W;
   }
+  // rows of an output far larger than the 256 MiB Infinity Cache: written
+  // once, read a launch later (a fused read-out reads its rows back at once)
+  a.nt_store = (!fused && !j.L.cf && static_cast<int64_t>(c.n_rows) * j.L.W * 4 * j.L.nchunk > kNtStoreBytes) ? 1 : 0;
   return s;
 }
 
