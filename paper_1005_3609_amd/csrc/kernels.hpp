@@ -583,13 +583,16 @@ __device__ void gather_tile(const GatherArgs& a, int chunk, int tile, uint32_t* 
     while (row < r1) flush();
     // Fused read-out, after the entry stream so that its loads never sit
     // behind in-flight gathers: each lane reads back its own just-stored
-    // rows (cache-resident) with their weights, four rows per wait.
+    // rows (cache-resident) with their weights, four rows per wait (with a
+    // target list, the rows it stored at their targets).
     if (fused) {
       for (int r = r0; r < r1; r += 4) {
         uint32_t xo[4][V], wr[4][V];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const uint32_t off = static_cast<uint32_t>(min(r + i, r1 - 1)) * (4u * W) + boff;
+          const int rr = min(r + i, r1 - 1);
+          const int dst = (!CF && a.tile_tgt) ? __builtin_amdgcn_readlane(tg, rr - r0) : rr;
+          const uint32_t off = static_cast<uint32_t>(dst) * (4u * W) + boff;
           load_row<V>(out, off, xo[i]);
           load_row<V>(wv, off, wr[i]);
         }

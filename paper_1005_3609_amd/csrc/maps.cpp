@@ -838,9 +838,27 @@ StagedCsr build_staged(const Csr& c, int slots, int rows) {
   return st;
 }
 
-StagedCsr build_interleaved(const Csr& c, int rows_tile, int waves) {
+std::vector<int32_t> ncnnn_natural_order(int m) {
+  const Space sp{kNcnnn, m, 0};
+  const int64_t n = sp.size();
+  std::vector<std::pair<unsigned __int128, int32_t>> key(n);
+  Part p;
+  for (int64_t r = 0; r < n; ++r) {
+    sp.unrank(r, p);   // canonical: labels numbered by first appearance
+    unsigned __int128 x = 0;
+    for (int j = 0; j < m; ++j) x = (x << 5) | p.lab[j];
+    key[r] = {x, static_cast<int32_t>(r)};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int32_t> order(n);
+  for (int64_t k = 0; k < n; ++k) order[k] = key[k].second;
+  return order;
+}
+
+StagedCsr build_interleaved(const Csr& c, int rows_tile, int waves, const std::vector<int32_t>* order) {
   if (rows_tile < 1 || waves < 1 || rows_tile % waves != 0) throw std::runtime_error("bad interleave shape");
   const int64_t n = c.n_rows;
+  if (order && static_cast<int64_t>(order->size()) != n) throw std::runtime_error("row order of the wrong size");
   const int rpw = rows_tile / waves;
   StagedCsr st;
   st.tile_row0.push_back(0);
@@ -848,13 +866,13 @@ StagedCsr build_interleaved(const Csr& c, int rows_tile, int waves) {
   st.tgt.resize(n);
   const int64_t whole = n / rows_tile * rows_tile;
   for (int64_t pos = 0; pos < n; ++pos) {
+    int64_t q = pos;
     if (pos < whole) {
       const int64_t b = pos / rows_tile, o = pos % rows_tile;
       const int64_t w = o / rpw, k = o % rpw;
-      st.tgt[pos] = static_cast<int32_t>(b * rows_tile + k * waves + w);
-    } else {
-      st.tgt[pos] = static_cast<int32_t>(pos);
+      q = b * rows_tile + k * waves + w;
     }
+    st.tgt[pos] = order ? (*order)[q] : static_cast<int32_t>(q);
   }
   st.row_ptr.assign(n + 1, 0);
   for (int64_t pos = 0; pos < n; ++pos) {

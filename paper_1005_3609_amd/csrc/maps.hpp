@@ -133,9 +133,14 @@ StagedCsr build_clustered(const Csr& c, int slots, int rows, int max_ent = 1 << 
 // `rows_tile` = waves x rows-per-wavefront consecutive target rows, the k-th
 // row of wavefront w is tile row k * waves + w, so at each step of their row
 // loops the tile's wavefronts work on adjacent rows (which share sources);
-// a last partial tile keeps its order.  Fills tgt, row_ptr and ent_src
-// (tile_row0 = {0}, no slots).
-StagedCsr build_interleaved(const Csr& c, int rows_tile, int waves);
+// a last partial tile keeps its order.  With `order`, the rows are first
+// taken in that sequence (order[k] = the k-th row).  Fills tgt, row_ptr and
+// ent_src (tile_row0 = {0}, no slots).
+StagedCsr build_interleaved(const Csr& c, int rows_tile, int waves, const std::vector<int32_t>* order = nullptr);
+
+// The NCNNN states of m points sorted by their canonical labelling read in
+// the natural point order (rank in the paper's order at each position).
+std::vector<int32_t> ncnnn_natural_order(int m);
 
 // Builds every single-factor map of (lattice, m); threads = 0 uses the
 // hardware count; paper_order keeps the paper's state order between the

@@ -843,8 +843,13 @@ const DevStagedSet& dev_staged(const DevMaps& dm, const DevFamily& fam, int slot
   const std::vector<Csr>& host = (fam.k == 1) ? ms.fwd : ms.family(fam.k).fac;
   std::vector<StagedCsr> st(host.size());
   if (kind == 3) {
-    // interleaved order: `slots` carries the wavefronts per workgroup
-    for (size_t i = 0; i < host.size(); ++i) st[i] = build_interleaved(host[i], rows, slots);
+    // interleaved order: `slots` carries the wavefronts per workgroup; the
+    // last factor's targets, the NCNNN states in the paper's order, are
+    // first taken in their natural-label order (its readers' sources then
+    // lie close together, as the site order does for the other spaces)
+    const std::vector<int32_t> nat = ncnnn_natural_order(dm.m);
+    for (size_t i = 0; i < host.size(); ++i)
+      st[i] = build_interleaved(host[i], rows, slots, i + 1 == host.size() ? &nat : nullptr);
   } else if (kind == 2) {
     std::vector<std::thread> th;
     std::vector<std::string> err(host.size());
@@ -1625,7 +1630,10 @@ void add_rows(Program& pg, const JobCtx& j, int r_first, int r_last, int after, 
     }
     for (int i = 1; i <= nf; ++i) {
       const bool fused = (i == nf);
-      const DevStaged* sd = (j.stg && !fused) ? &j.stg->fac[i - 1] : nullptr;
+      // direct gathers over a target order (stages 4, 6) also take the last
+      // factor, whose fused read-out follows the target list
+      const bool ordered = j.t.stage == 4 || j.t.stage == 6;
+      const DevStaged* sd = (j.stg && (!fused || ordered)) ? &j.stg->fac[i - 1] : nullptr;
       // LDS slots: the widest tile's sources, at most the staging limit (a
       // tile of one exceptional row reads the rest from memory)
       const int cap = sd ? std::min(sd->max_slots, stage_slots(j.L.V)) : 0;
