@@ -90,7 +90,7 @@ typedef struct chrom_tuning {
                            the coefficient form also takes 8, with unroll 4; resident
                            mode: instances per workgroup */
   int targets_per_wave; /* consecutive target states handled by one wavefront, 1..63 */
-  int waves_per_block;  /* wavefronts per workgroup: 1, 2, 4 or 8 */
+  int waves_per_block;  /* wavefronts per workgroup: 1, 2, 4 or 8 (resident mode also 16) */
   int xcd_order;        /* 0 = default, 1 = hardware round-robin, 2 = contiguous tile range per XCD,
                            3 / 4 / 5 / 6 = runs of 4 / 16 / 64 / 256 consecutive tiles per
                            XCD, runs round-robin */
@@ -106,8 +106,7 @@ typedef struct chrom_tuning {
                            running a range of them and requesting the next tile's rows
                            while it computes the current one (1-3: batched and graph
                            modes, lanes_v 1 or 2); 4: direct gathers over the clustered
-                           order of the targets (no LDS; lanes_v 1, 2 or 4); the read-out
-                           factor keeps its order; 5: op-stream gathers, each factor's
+                           order of the targets (no LDS; lanes_v 1, 2 or 4); 5: op-stream gathers, each factor's
                            entries re-encoded as words carrying their coefficient digits
                            and row ends, read through the scalar cache (evaluation form,
                            unit coefficients in powers of t up to t^2 -- the square
@@ -116,8 +115,12 @@ typedef struct chrom_tuning {
                            below 2 GiB); 6: direct gathers over an interleaved order, the
                            k-th row of wavefront w of a workgroup being row k x waves + w
                            of its tile, so the workgroup's wavefronts work on adjacent rows
-                           at the same time (batched and graph modes; the read-out factor
-                           keeps its order); 0: direct gathers */
+                           at the same time (batched and graph modes); under 4 and 6 the
+                           last factor of a row, which writes the NCNNN states, first takes
+                           them in the order of their labels read from point 1 to m; 0:
+                           direct gathers.  Resident mode: 0 = exact double accumulation
+                           where every row's sum stays below 2^52 (longest row x max
+                           |c(q)| <= 2^21), else modular; 1 = modular arithmetic throughout */
 } chrom_tuning;
 
 /* ------------------------------------------------------------------------

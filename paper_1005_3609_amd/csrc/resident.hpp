@@ -14,9 +14,22 @@
 // triangular m <= 13 fit at K = 1.
 //
 // Arithmetic.  A factor entry's coefficient is an integer polynomial in q
-// (a code); for one instance it is a fixed residue c, so each entry costs
-// one Shoup product c x mod p (the host precomputes c and floor(c 2^32 / p)
-// per code and instance) and one modular addition.
+// (a code); for one instance it is a fixed integer c(q).  Two forms:
+//  * exact double accumulation (the default wherever its bound holds): a
+//    target row is sum_e c_e(q) x_e over its entries, with x_e < p < 2^31 the
+//    source residues and |c_e(q)| small, so when (row length) x max |c(q)|
+//    <= 2^21 every product and partial sum is an integer below 2^52 in
+//    magnitude and double arithmetic computes it exactly: one conversion and
+//    one fused multiply-add per entry and instance, then one reduction mod p
+//    per row (floor(T / p) from the rounded reciprocal, off by at most one,
+//    then a conditional subtraction);
+//  * modular integer arithmetic: c(q) mod p per entry, one Shoup product
+//    c x mod p (the host precomputes c and floor(c 2^32 / p) per code and
+//    instance) and one modular addition.  Its 32-bit multiplies issue at a
+//    quarter of the rate of the double operations above.
+// The host picks the first form per job when the bound holds for every map
+// of the strip and every instance (tuning stage 0), else, or on request
+// (stage 1), the second.
 //
 // Work split.  Half of a single factor's target rows hold one entry and a
 // few hold ten or more, so with one thread per row in map order most lanes
@@ -25,10 +38,11 @@
 // into slices of 64 (one per wavefront pass, lane l taking the slice's l-th
 // row), each slice's entries padded to its longest row and stored
 // column-major, so a wavefront's loop counts are uniform and its entry loads
-// coalesced.  A slice keeps the entries with coefficient +1 or -1 (about
-// four in five) in columns of their own, ahead of the others: those cost one
-// modular addition or subtraction, the others a Shoup product as well (32-bit
-// integer multiplies issue at a quarter of the rate of additions).  Padding
+// coalesced.  For the modular form a slice keeps the entries with
+// coefficient +1 or -1 in columns of their own, ahead of the others: those
+// cost one modular addition or subtraction, the others a Shoup product as
+// well.  The double form costs the same per entry whatever the coefficient,
+// so its maps keep every entry in one group (fewer padded columns).  Padding
 // entries read a row kept at zero past the end of each vector.
 #pragma once
 
@@ -63,16 +77,20 @@ struct ResidentJob {
   int g0, ngroups;         // first workgroup of the job, workgroups (instance groups of K)
   const uint32_t* coef;    // [I][ncodes]: code c at instance i, mod p_i
   const uint32_t* coefs;   // [I][ncodes]: its Shoup quotient
+  const double* coff;      // [I][ncodes]: code c at instance i as an integer (double form)
+  const double* rcp;       // [I]: 1 / p_i rounded to double (double form)
   const uint32_t* p;       // [I]
   const uint32_t* pinv;    // [I]: -p^{-1} mod 2^32
   const uint32_t* r1;      // [I]: 2^32 mod p
   uint32_t* w;             // [I][s_nc] read-out vector (Montgomery form), written by the kernel
   uint32_t* out;           // [n_max][I]
+  int exact;               // 1: exact double accumulation (maps in one group), 0: modular
 };
 
 // LDS bytes of a workgroup: two vectors of s_max + 1 rows of K words (row
 // s_max stays zero: the padding entries' source), the code table (value and
-// quotient per code and instance) and the reduction slots.
+// quotient per code and instance, or the value as a double) and the
+// reduction slots.
 __host__ __device__ inline size_t resident_lds_bytes(int s_max, int ncodes, int K) {
   return 4u * (2u * (static_cast<size_t>(s_max) + 1) * K + 2u * static_cast<size_t>(ncodes) * K +
                static_cast<size_t>(kResMaxWaves) * K);
@@ -167,6 +185,82 @@ __device__ __forceinline__ void res_apply(const DevSell& c, const uint32_t* in, 
   __syncthreads();
 }
 
+// T mod p for an integer T held exactly in a double, |T| / p < 2^21 (the
+// double form's bound): the quotient estimate floor(T / p - 1/2) from the
+// rounded reciprocal is floor(T / p) or one less, so r = T - estimate x p
+// (one fused multiply-add, exact: an integer in [0, 2p)) needs at most one
+// subtraction.
+__device__ __forceinline__ uint32_t reduce_exact(double t, double pf, double rcp, uint32_t p) {
+  const double qe = __builtin_floor(__builtin_fma(t, rcp, -0.5));
+  const uint32_t r = static_cast<uint32_t>(__builtin_fma(-qe, pf, t));
+  return min(r, r - p);
+}
+
+// Sum of G entries (words w) into acc in the double form: source rows and
+// coefficients (code table cf[code][K]) first, then the products.
+template <int K, int G>
+__device__ __forceinline__ void res_words_exact(double (&acc)[K], const uint32_t (&w)[G], const uint32_t* in,
+                                                const double* cf) {
+  uint32_t x[G][K];
+  double c[G][K];
+#pragma unroll
+  for (int i = 0; i < G; ++i) {
+    load_v<K>(in + (w[i] & kEntSrcMask) * K, x[i]);
+    const double* ci = cf + (w[i] >> kEntSrcBits) * K;
+#pragma unroll
+    for (int k = 0; k < K; ++k) c[i][k] = ci[k];
+  }
+#pragma unroll
+  for (int i = 0; i < G; ++i)
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = __builtin_fma(c[i][k], static_cast<double>(x[i][k]), acc[k]);
+}
+
+// G columns starting at `e` (the lane's word of the first).
+template <int K, int G>
+__device__ __forceinline__ void res_cols_exact(double (&acc)[K], gu32 e, const uint32_t* in, const double* cf) {
+  uint32_t w[G];
+#pragma unroll
+  for (int i = 0; i < G; ++i) w[i] = e[i * 64];
+  res_words_exact<K, G>(acc, w, in, cf);
+}
+
+// out <- c in for one map in the double form (one column group per slice),
+// ending with the workgroup barrier.  Wavefront w takes slices w, w + waves,
+// ...; every loop count in a slice is uniform.  (Requesting the next slice's
+// entry words ahead of the current slice's sum was measured slower.)
+template <int K>
+__device__ __forceinline__ void res_apply_exact(const DevSell& c, const uint32_t* in, uint32_t* out, const double* cf,
+                                                const uint32_t (&p)[K], const double (&pf)[K],
+                                                const double (&rcp)[K]) {
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  const int nw = static_cast<int>(blockDim.x) >> 6;
+  const gi32 slices = (gi32)c.slice;
+  const gi32 perm = (gi32)c.perm;
+  for (int s = wave_id(); s < c.nslice; s += nw) {
+    const int off = slices[4 * s], n = slices[4 * s + 1] + slices[4 * s + 2];
+    const int row = perm[s * 64 + lane];
+    const gu32 e = (gu32)c.ent + off + lane;
+    double acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    int u = 0;
+    for (; u + 4 <= n; u += 4) res_cols_exact<K, 4>(acc, e + u * 64, in, cf);
+    if (u + 2 <= n) {
+      res_cols_exact<K, 2>(acc, e + u * 64, in, cf);
+      u += 2;
+    }
+    if (u < n) res_cols_exact<K, 1>(acc, e + u * 64, in, cf);
+    if (row >= 0) {
+      uint32_t v[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) v[k] = reduce_exact(acc[k], pf[k], rcp[k], p[k]);
+      store_v<K>(out + static_cast<uint32_t>(row) * K, v);
+    }
+  }
+  __syncthreads();
+}
+
 // Row read-out: out_row[k] = sum_s w_k[s] x[s][k] mod p_k over the NCNNN
 // states, w in Montgomery form.  Ends with the workgroup barrier.
 template <int K>
@@ -240,12 +334,33 @@ __global__ void __launch_bounds__(64 * kResMaxWaves) k_resident(const ResidentJo
     xa[static_cast<size_t>(J.s_max) * K + threadIdx.x] = 0u;
     xb[static_cast<size_t>(J.s_max) * K + threadIdx.x] = 0u;
   }
+  // code table: (value, quotient) pairs, or in the double form the value as
+  // a double at the same place (cc is 8-byte aligned: 2 (s_max + 1) K words
+  // in; 16-byte for K >= 2)
+  const bool exact = J.exact != 0;
+  double* cf = reinterpret_cast<double*>(cc);
+  double pf[K], rcp[K];
   for (int idx = threadIdx.x; idx < J.ncodes * K; idx += blockDim.x) {
     const int code = idx / K, k = idx % K;
     const int inst = min(i0 + k, J.I - 1);
-    cc[2 * idx] = J.coef[static_cast<size_t>(inst) * J.ncodes + code];
-    cc[2 * idx + 1] = J.coefs[static_cast<size_t>(inst) * J.ncodes + code];
+    if (exact) {
+      cf[idx] = J.coff[static_cast<size_t>(inst) * J.ncodes + code];
+    } else {
+      cc[2 * idx] = J.coef[static_cast<size_t>(inst) * J.ncodes + code];
+      cc[2 * idx + 1] = J.coefs[static_cast<size_t>(inst) * J.ncodes + code];
+    }
   }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    pf[k] = static_cast<double>(p[k]);
+    rcp[k] = exact ? J.rcp[ik[k]] : 0.0;
+  }
+  auto apply = [&](const DevSell& c, const uint32_t* in, uint32_t* out) {
+    if (exact)
+      res_apply_exact<K>(c, in, out, cf, p, pf, rcp);
+    else
+      res_apply<K>(c, in, out, cc, p);
+  };
   // Read-out vector: R e0 on the first read-out space, then T_m^last ..
   // T_1^last in gather form (transposed), ending on the NCNNN space.
   const int n0 = J.last[J.m - 1].n_cols;
@@ -257,7 +372,7 @@ __global__ void __launch_bounds__(64 * kResMaxWaves) k_resident(const ResidentJo
   uint32_t* cur = xa;
   uint32_t* oth = xb;
   for (int i = J.m; i >= 1; --i) {
-    res_apply<K>(J.last[i - 1], cur, oth, cc, p);
+    apply(J.last[i - 1], cur, oth);
     uint32_t* t = cur;
     cur = oth;
     oth = t;
@@ -277,7 +392,7 @@ __global__ void __launch_bounds__(64 * kResMaxWaves) k_resident(const ResidentJo
   oth = xb;
   for (int r = 1; r < J.n_max; ++r) {
     for (int f = 0; f < J.nf; ++f) {
-      res_apply<K>(J.fac[f], cur, oth, cc, p);
+      apply(J.fac[f], cur, oth);
       uint32_t* t = cur;
       cur = oth;
       oth = t;

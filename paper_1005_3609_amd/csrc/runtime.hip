@@ -110,6 +110,7 @@ struct DevStagedSet {
 struct DevSellSet {
   void* base = nullptr;
   std::vector<DevSell> fac, last;
+  int max_row = 0;   // entries of the longest row over all maps
 };
 
 // A family's factors as op streams (opgather.hpp).
@@ -134,8 +135,10 @@ struct DevFamily {
   // slot limit; rows per tile), built on first use
   mutable std::mutex st_mu;
   mutable std::map<std::tuple<int, int, int>, std::unique_ptr<DevStagedSet>> staged;
-  // sliced-ELL copies of the factors and read-out maps (resident mode), built on first use
-  mutable std::unique_ptr<struct DevSellSet> sell;
+  // sliced-ELL copies of the factors and read-out maps (resident mode), built
+  // on first use: +-1 entries in their own columns (modular form) or every
+  // entry in one group (double form)
+  mutable std::unique_ptr<struct DevSellSet> sell, sell_one;
   // op streams of the factors (stage 5), built on first use
   mutable std::unique_ptr<DevOpSet> ops;
 };
@@ -986,21 +989,22 @@ Sizes space_sizes(int lattice, int m) {
   return s;
 }
 
-// Sliced-ELL form of a gather-form map (resident.hpp): rows sorted by their
-// entries with coefficient other than +-1, then by their +-1 entries (most
-// first, ties in row order), slices of 64 rows; a slice stores its rows' +-1
-// entries column-major, padded to the slice's most, then the others likewise.
-// Padding entries read row `zero_row` with code 0.
+// Sliced-ELL form of a gather-form map (resident.hpp).  With `split`: rows
+// sorted by their entries with coefficient other than +-1, then by their +-1
+// entries (most first, ties in row order), slices of 64 rows; a slice stores
+// its rows' +-1 entries column-major, padded to the slice's most, then the
+// others likewise.  Without: rows sorted by their entry count, every entry in
+// the first group.  Padding entries read row `zero_row` with code 0.
 struct HostSell {
   std::vector<int32_t> perm, slice;   // slice: (offset, unit columns, other columns, 0)
   std::vector<uint32_t> ent;
   int nslice = 0;
 };
 
-HostSell build_sell(const Csr& c, uint32_t zero_row) {
+HostSell build_sell(const Csr& c, uint32_t zero_row, bool split) {
   HostSell h;
   const int64_t n = c.n_rows;
-  auto unit = [](uint32_t w) { return (w >> kEntSrcBits) <= 1u; };
+  auto unit = [split](uint32_t w) { return !split || (w >> kEntSrcBits) <= 1u; };
   std::vector<int32_t> nu(n, 0), ng(n, 0);
   for (int64_t r = 0; r < n; ++r)
     for (int32_t e = c.row_ptr[r]; e < c.row_ptr[r + 1]; ++e) (unit(c.ent[e]) ? nu[r] : ng[r]) += 1;
@@ -1040,9 +1044,10 @@ HostSell build_sell(const Csr& c, uint32_t zero_row) {
 // The family's forward factors and the read-out maps of (lattice, m) in
 // sliced-ELL form on the device, padding entries reading row s_max (kept at
 // zero by the resident kernel).
-const DevSellSet& dev_sell(const DevMaps& dm, const DevFamily& fam) {
+const DevSellSet& dev_sell(const DevMaps& dm, const DevFamily& fam, bool split) {
   std::lock_guard<std::mutex> lk(fam.st_mu);
-  if (fam.sell) return *fam.sell;
+  std::unique_ptr<DevSellSet>& slot = split ? fam.sell : fam.sell_one;
+  if (slot) return *slot;
   if (dm.normalised) throw std::runtime_error("resident mode runs the evaluation form only");
   const MapSet& ms = get_maps(dm.lattice, dm.m);
   const std::vector<Csr>& fwd = (fam.k == 1) ? ms.fwd : ms.family(fam.k).fac;
@@ -1052,11 +1057,13 @@ const DevSellSet& dev_sell(const DevMaps& dm, const DevFamily& fam) {
   for (int i = 0; i < dm.m; ++i) src.push_back(&ms.last[i]);
   size_t bytes = 0;
   for (const Csr* c : src) {
-    hs.push_back(build_sell(*c, static_cast<uint32_t>(space_sizes(dm.lattice, dm.m).s_max)));
+    hs.push_back(build_sell(*c, static_cast<uint32_t>(space_sizes(dm.lattice, dm.m).s_max), split));
     const HostSell& h = hs.back();
     bytes += align_up(h.perm.size() * 4 + 4) + align_up(h.slice.size() * 4 + 4) + align_up(h.ent.size() * 4 + 4);
   }
   auto set = std::make_unique<DevSellSet>();
+  for (const Csr* c : src)
+    for (int64_t r = 0; r < c->n_rows; ++r) set->max_row = std::max(set->max_row, c->row_ptr[r + 1] - c->row_ptr[r]);
   if (hipMalloc(&set->base, bytes) != hipSuccess) throw MemError("device allocation of sliced-ELL maps failed");
   char* cur = static_cast<char*>(set->base);
   auto put = [&](const void* data, size_t n) {
@@ -1076,8 +1083,8 @@ const DevSellSet& dev_sell(const DevMaps& dm, const DevFamily& fam) {
     d.nslice = h.nslice;
     (i < fwd.size() ? set->fac : set->last).push_back(d);
   }
-  fam.sell = std::move(set);
-  return *fam.sell;
+  slot = std::move(set);
+  return *slot;
 }
 
 // Host-side sizes without building device copies.
@@ -1175,7 +1182,9 @@ struct Tune {
 // lanes_v 8 (512 coefficient slots per row) exists for the coefficient form
 // only: `series` admits it.
 // Resident mode (`resident`): lanes_v is the number of instances per
-// workgroup (1, 2 or 4) and waves_per_block may also be 16.
+// workgroup (1, 2 or 4), waves_per_block may also be 16, and stage selects
+// the arithmetic: 0 exact double accumulation where its bound holds, 1
+// modular throughout.
 Tune resolve(const chrom_tuning* t, bool series = false, bool resident = false) {
   Tune r;
   if (!t) return r;
@@ -1199,6 +1208,7 @@ Tune resolve(const chrom_tuning* t, bool series = false, bool resident = false) 
   }
   if (r.rpw < 1 || r.rpw > 63) throw ArgError("targets_per_wave must be in 1..63");
   if (r.stage == 5 && r.V > 2) throw ArgError("stage 5 (op-stream gathers) takes lanes_v 1 or 2");
+  if (resident && r.stage > 1) throw ArgError("resident mode takes stage 0 (exact double accumulation) or 1 (modular)");
   if (r.wpb != 1 && r.wpb != 2 && r.wpb != 4 && r.wpb != 8 && !(resident && r.wpb == 16))
     throw ArgError(resident ? "waves_per_block must be 1, 2, 4, 8 or 16" : "waves_per_block must be 1, 2, 4 or 8");
   return r;
@@ -2244,11 +2254,13 @@ void run_plain(const DevMaps& dm, int lattice, int m, int n_max, const std::vect
 constexpr size_t kResMaxLds = 160 * 1024;
 
 // Workspace of one resident job: per-instance code values and quotients,
-// p, -p^{-1}, 2^32 mod p, and the read-out vector [I][s_nc].
+// p, -p^{-1}, 2^32 mod p, the code values as doubles, 1 / p as a double, and
+// the read-out vector [I][s_nc].  The modular form reads [coef, coff), the
+// double form [p, w).
 struct ResLayout {
   int I = 0, K = 1, ngroups = 0;
   int64_t s_nc = 0, s_max = 0;
-  size_t coef = 0, coefs = 0, p = 0, pinv = 0, r1 = 0, w = 0, bytes = 0;
+  size_t coef = 0, coefs = 0, coff = 0, rcp = 0, p = 0, pinv = 0, r1 = 0, w = 0, bytes = 0;
 };
 
 ResLayout res_layout(int lattice, int m, int I, const Tune& t) {
@@ -2270,9 +2282,40 @@ ResLayout res_layout(int lattice, int m, int I, const Tune& t) {
   L.p = take(static_cast<size_t>(I) * 4);
   L.pinv = take(static_cast<size_t>(I) * 4);
   L.r1 = take(static_cast<size_t>(I) * 4);
+  L.coff = take(static_cast<size_t>(I) * kMaxCodes * 8);
+  L.rcp = take(static_cast<size_t>(I) * 8);
   L.w = take(static_cast<size_t>(I) * L.s_nc * 4);
   L.bytes = off;
   return L;
+}
+
+// The double form's bound (resident.hpp): (longest row) x max |c(q)| <= 2^21.
+constexpr int64_t kExactBound = int64_t(1) << 21;
+constexpr int64_t kExactCode = kExactBound;
+
+// c(q) as an exact integer (Horner; saturated at +-2^80, far past any bound
+// it is compared with: q < 2^32 and the degree is at most 3).
+__int128 code_value(const Poly& c, uint32_t q) {
+  const __int128 cap = static_cast<__int128>(1) << 80;
+  __int128 acc = 0;
+  for (int k = kMaxDeg; k >= 0; --k) {
+    acc = acc * q + c.c[k];
+    if (acc > cap) acc = cap;
+    if (acc < -cap) acc = -cap;
+  }
+  return acc;
+}
+
+// Whether every row of the strip's maps stays within the double form's
+// bound at every instance.
+bool resident_exact(const std::vector<Poly>& codes, const std::vector<Inst>& inst, int max_row) {
+  __int128 big = 0;
+  for (const Inst& in : inst)
+    for (const Poly& c : codes) {
+      const __int128 v = code_value(c, in.q);
+      big = std::max(big, v < 0 ? -v : v);
+    }
+  return big <= kExactCode && static_cast<__int128>(std::max(max_row, 1)) * big <= kExactBound;
 }
 
 // Host image of the constants region [coef .. w) of a resident job: every
@@ -2286,13 +2329,21 @@ std::vector<uint32_t> res_image(const ResLayout& L, const std::vector<Inst>& ins
   uint32_t* p = img.data() + (L.p - L.coef) / 4;
   uint32_t* pinv = img.data() + (L.pinv - L.coef) / 4;
   uint32_t* r1 = img.data() + (L.r1 - L.coef) / 4;
+  char* bytes = reinterpret_cast<char*>(img.data()) - L.coef;
   for (int i = 0; i < L.I; ++i) {
     const Inst& in = inst[i];
     for (int c = 0; c < nc; ++c) {
       const uint32_t v = coef_mod(codes[c], in.q, in.p);
       coef[static_cast<size_t>(i) * nc + c] = v;
       coefs[static_cast<size_t>(i) * nc + c] = shoup_of(v, in.p);
+      // the integer itself where it is small (the double form runs only
+      // when every value is: resident_exact)
+      const __int128 e = code_value(codes[c], in.q);
+      const double d = (e > kExactCode || e < -kExactCode) ? 0.0 : static_cast<double>(static_cast<int64_t>(e));
+      std::memcpy(bytes + L.coff + (static_cast<size_t>(i) * nc + c) * 8, &d, 8);
     }
+    const double rc = 1.0 / static_cast<double>(in.p);
+    std::memcpy(bytes + L.rcp + static_cast<size_t>(i) * 8, &rc, 8);
     p[i] = in.p;
     pinv[i] = neg_inv_2_32(in.p);
     r1[i] = static_cast<uint32_t>((uint64_t(1) << 32) % in.p);
@@ -2306,9 +2357,13 @@ std::vector<uint32_t> res_image(const ResLayout& L, const std::vector<Inst>& ins
 // NCNNN -> ... -> NCNNN, the read-out maps chain from their first space down
 // to the NCNNN space, all within the LDS vectors).
 ResidentJob resident_job(const DevMaps& dm, const DevFamily& fam, const ResLayout& L, void* base, int n_max,
-                         uint32_t* d_out, int g0, size_t& lds) {
+                         uint32_t* d_out, int g0, size_t& lds, const std::vector<Inst>& inst, const Tune& t) {
   if (dm.m > kResMaxM) throw std::runtime_error("resident mode: m above the kernel's limit");
-  const DevSellSet& sell = dev_sell(dm, fam);
+  // the double form unless stage 1 asks for the modular one or a row could
+  // leave its exact range
+  bool exact = false;
+  if (t.stage == 0) exact = resident_exact(fam.codes, inst, dev_sell(dm, fam, false).max_row);
+  const DevSellSet& sell = dev_sell(dm, fam, !exact);
   const int nf = static_cast<int>(sell.fac.size());
   const int nc = static_cast<int>(fam.codes.size());
   if (nf < 1 || nf > kResMaxM || nc > kMaxCodes) throw std::runtime_error("resident mode: factor family out of range");
@@ -2344,6 +2399,9 @@ ResidentJob resident_job(const DevMaps& dm, const DevFamily& fam, const ResLayou
   J.ngroups = L.ngroups;
   J.coef = reinterpret_cast<const uint32_t*>(b + L.coef);
   J.coefs = reinterpret_cast<const uint32_t*>(b + L.coefs);
+  J.coff = reinterpret_cast<const double*>(b + L.coff);
+  J.rcp = reinterpret_cast<const double*>(b + L.rcp);
+  J.exact = exact ? 1 : 0;
   J.p = reinterpret_cast<const uint32_t*>(b + L.p);
   J.pinv = reinterpret_cast<const uint32_t*>(b + L.pinv);
   J.r1 = reinterpret_cast<const uint32_t*>(b + L.r1);
@@ -2461,9 +2519,11 @@ int strip_async_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, c
     const DevFamily& fam = dev_family(dm, t.fuse);
     ResLayout R = res_layout(lattice, m, I, t);
     size_t lds = 0;
-    std::vector<ResidentJob> jobs{resident_job(dm, fam, R, ws, n_max, d_out, 0, lds)};
+    std::vector<ResidentJob> jobs{resident_job(dm, fam, R, ws, n_max, d_out, 0, lds, inst, t)};
     std::vector<uint32_t> img = res_image(R, inst, fam.codes);
-    upload(static_cast<char*>(ws) + R.coef, img.data(), img.size() * 4, st);
+    // only the constants the job's arithmetic reads
+    const size_t lo = jobs[0].exact ? R.p : R.coef, hi = jobs[0].exact ? R.w : R.coff;
+    upload(static_cast<char*>(ws) + lo, img.data() + (lo - R.coef) / 4, hi - lo, st);
     run_resident(jobs, lds, t, static_cast<char*>(ws) + R.bytes, st);
     return CHROM_OK;
   }
@@ -3117,6 +3177,8 @@ void chromatic_release_maps(void) {
       for (auto& fam : kv.second->fam) {
         for (auto& st : fam.second->staged) (void)hipFree(st.second->base);
         if (fam.second->sell) (void)hipFree(fam.second->sell->base);
+        if (fam.second->sell_one) (void)hipFree(fam.second->sell_one->base);
+        if (fam.second->ops) (void)hipFree(fam.second->ops->base);
         if (fam.second->base) (void)hipFree(fam.second->base);
       }
       (void)hipFree(kv.second->base);

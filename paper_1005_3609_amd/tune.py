@@ -52,15 +52,17 @@ def candidates(space=None) -> list[dict]:
 
 # Resident mode (one launch per strip, vectors in LDS): instances per
 # workgroup, wavefronts per workgroup, fused family.
-RESIDENT_SPACE = dict(lanes_v=[1, 2, 4], waves_per_block=[8, 16], fuse=[1, 2, 3])
+# stage: 0 = exact double accumulation where its bound holds, 1 = modular
+RESIDENT_SPACE = dict(lanes_v=[1, 2, 4], waves_per_block=[8, 16], fuse=[1, 2, 3], stage=[0, 1])
 
 
 def resident_candidates(lattice, m, n_inst, n_max, space=None) -> list[dict]:
     """Resident-mode candidates whose two state vectors fit a workgroup's LDS."""
     space = space or RESIDENT_SPACE
     out = []
-    for v, w, f in itertools.product(space["lanes_v"], space["waves_per_block"], space["fuse"]):
-        t = dict(lanes_v=v, waves_per_block=w, fuse=f)
+    for v, w, f, g in itertools.product(space["lanes_v"], space["waves_per_block"], space["fuse"],
+                                        space.get("stage", [0])):
+        t = dict(lanes_v=v, waves_per_block=w, fuse=f, stage=g)
         try:
             api.workspace_bytes(lattice, m, n_max, n_inst, 1, "resident", t)
         except api.ChromError:

@@ -90,6 +90,8 @@ def test_resident_candidates_fit_lds():
     assert all(c["mode"] == "resident" for c in tri)
     sq = tune.resident_candidates("square", 10, 320, 11)
     assert {c["lanes_v"] for c in sq} == {1, 2, 4} and {c["fuse"] for c in sq} == {1, 2, 3}
+    # both arithmetic forms: exact double accumulation (0) and modular (1)
+    assert {c["stage"] for c in sq} == {0, 1}
 
 
 def test_written_residues_of_fused_steps():

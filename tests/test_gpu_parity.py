@@ -300,6 +300,11 @@ def test_resident_small_widths(lat):
     dict(lanes_v=1, waves_per_block=8, fuse=2),
     dict(lanes_v=2, waves_per_block=16, fuse=3),
     dict(lanes_v=1, waves_per_block=4, fuse=3),
+    # modular arithmetic throughout (stage 0 takes exact double accumulation
+    # wherever its bound holds: every case above but some fused triples)
+    dict(lanes_v=1, waves_per_block=16, stage=1),
+    dict(lanes_v=2, waves_per_block=8, fuse=2, stage=1),
+    dict(lanes_v=4, waves_per_block=4, fuse=3, stage=1),
 ])
 @pytest.mark.parametrize("lat", ["square", "triangular"])
 def test_resident_tuning_choices_are_bit_identical(lat, tune):
@@ -308,6 +313,22 @@ def test_resident_tuning_choices_are_bit_identical(lat, tune):
     want = OT.chromatic_grid(lat, 7, 5, q, p)
     got = api.strip(lat, 7, 5, q, p, mode="resident", tuning=tune).astype(np.int64)
     np.testing.assert_array_equal(got, want, err_msg=f"{lat} {tune}")
+
+
+@pytest.mark.parametrize("lat", ["square", "triangular"])
+def test_resident_large_q_leaves_the_double_form(lat):
+    # q near 2^31 and past it: |c(q)| exceeds the double form's bound, so
+    # stage 0 runs these jobs in modular arithmetic; small q alongside
+    q = [2, 5, 2**31 - 1, 3_000_000_000, 4_294_967_295]
+    p = [P31, 998244353]
+    want = OT.chromatic_grid(lat, 6, 5, q, p)
+    for tune in (dict(lanes_v=2, waves_per_block=8), dict(lanes_v=2, waves_per_block=8, stage=1),
+                 dict(lanes_v=1, waves_per_block=8, stage=0)):
+        got = api.strip(lat, 6, 5, q, p, mode="resident", tuning=tune).astype(np.int64)
+        np.testing.assert_array_equal(got, want, err_msg=f"{lat} {tune}")
+    # the small q alone take the double form
+    got = api.strip(lat, 6, 5, q[:2], p, mode="resident").astype(np.int64)
+    np.testing.assert_array_equal(got, OT.chromatic_grid(lat, 6, 5, q[:2], p))
 
 
 def test_resident_largest_widths():

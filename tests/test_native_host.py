@@ -227,3 +227,6 @@ def test_bad_arguments_are_errors_without_touching_a_gpu():
         api.strip("square", 4, 3, [1, 2], [P31], mode="batched", tuning={"lanes_v": 4, "stage": 5})
     with pytest.raises(api.ChromError, match="stage must be"):
         api.strip("square", 4, 3, [1, 2], [P31], mode="batched", tuning={"stage": 7})
+    # resident mode's stage picks the arithmetic: 0 or 1 only
+    with pytest.raises(api.ChromError, match="resident mode takes stage"):
+        api.strip("square", 4, 3, [1, 2], [P31], mode="resident", tuning={"stage": 2})
