@@ -1,0 +1,90 @@
+"""The library's host logic under AddressSanitizer, on the CPU.
+
+The runtime is compiled host-only (no kernels) with AddressSanitizer and
+linked against a stand-in for the HIP runtime (``asan_hip_stub.cpp``) whose
+device memory is host memory, so every upload, copy and fill the library
+issues is a checked access to the allocation it targets.  The replay
+(``asan_replay_driver.cpp``) runs the batch autotuner's whole candidate
+sequence over the square m = 2..14 sweep, graph-mode strips with one to
+three chunk groups, resident strips in both arithmetic forms and the strip
+that allocates nothing.  A second build turns the batch's chunk groups back
+on (they are switched off in the product), so their stage-table layout and
+fork/join are replayed too.
+"""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(ROOT, "paper_1005_3609_amd", "csrc")
+HIPCC = "/opt/rocm/bin/hipcc"
+CLANG = "/opt/rocm/llvm/bin/clang++"
+GROUPS_OFF = "  bp.groups = 1;\n"
+GROUPS_ON = "  bp.groups = std::max(1, std::min(t.streams, 4));\n"
+
+
+def _asan_runtime():
+    try:
+        p = subprocess.run([CLANG, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True,
+                           check=True).stdout.strip()
+    except (OSError, subprocess.CalledProcessError):
+        return None
+    return p if os.path.isfile(p) else None
+
+
+def _run(cmd, cwd, env=None, timeout=600):
+    r = subprocess.run(cmd, cwd=cwd, env=env, capture_output=True, text=True, timeout=timeout)
+    assert r.returncode == 0, f"{' '.join(cmd[:3])} ...: rc {r.returncode}\n{r.stdout[-3000:]}\n{r.stderr[-6000:]}"
+    return r
+
+
+def _build_and_replay(top, groups_on):
+    # the sources include the public header as ../../include/chromstrip.h
+    tmp = os.path.join(top, "pkg", "csrc")
+    os.makedirs(tmp)
+    os.symlink(os.path.join(ROOT, "include"), os.path.join(top, "include"))
+    src = open(os.path.join(CSRC, "runtime.hip")).read()
+    if groups_on:
+        assert src.count(GROUPS_OFF) == 1, "the batch plan's chunk-group line moved; update this test"
+        src = src.replace(GROUPS_OFF, GROUPS_ON)
+    for f in os.listdir(CSRC):
+        if f.endswith((".hpp", ".cpp")):
+            shutil.copy(os.path.join(CSRC, f), tmp)
+    with open(os.path.join(tmp, "runtime.hip"), "w") as fh:
+        fh.write(src)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", tmp]
+    host = ["-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fPIC"]
+    _run([HIPCC, "-x", "hip", "--cuda-host-only", *host, *inc, "-Xarch_host", "-fsanitize=address", "-c",
+          "runtime.hip", "-o", "runtime.o"], tmp)
+    fat = [ln.split()[-1] for ln in _run(["nm", "-u", "runtime.o"], tmp).stdout.splitlines()
+           if "__hip_fatbin" in ln]
+    assert len(fat) == 1, fat
+    for f in ("states", "maps"):
+        _run([CLANG, *host, "-fsanitize=address", *inc, "-c", f"{f}.cpp", "-o", f"{f}.o"], tmp)
+    _run([CLANG, *host, "-fsanitize=address", f"-DHIP_FATBIN_SYMBOL={fat[0]}", "-I", "/opt/rocm/include", "-c",
+          os.path.join(HERE, "asan_hip_stub.cpp"), "-o", "stub.o"], tmp)
+    _run([CLANG, "-shared", "-fsanitize=address", "-shared-libasan", "-o", "libreplay.so", "runtime.o", "states.o",
+          "maps.o", "stub.o", "-lpthread"], tmp)
+    _run([CLANG, *host, "-fsanitize=address", "-shared-libasan", "-Wno-unused-result", "-D__HIP_PLATFORM_AMD__",
+          *inc, "-I", "/opt/rocm/include", os.path.join(HERE, "asan_replay_driver.cpp"), "-o", "replay", "-L", tmp,
+          "-lreplay", f"-Wl,-rpath,{tmp}"], tmp)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0",
+               LD_LIBRARY_PATH=os.path.dirname(_asan_runtime()) + ":" + os.environ.get("LD_LIBRARY_PATH", ""))
+    env.pop("LD_PRELOAD", None)
+    r = _run([os.path.join(tmp, "replay"), "1"], tmp, env=env, timeout=900)
+    lines = r.stdout.splitlines()
+    assert lines[-1] == "done"
+    assert sum(ln.startswith("batch ") for ln in lines) == 48
+    assert sum(ln.startswith("graph strip") for ln in lines) == 18
+    assert sum(ln.startswith("resident") for ln in lines) == 8
+    assert "ERROR: AddressSanitizer" not in r.stderr
+
+
+@pytest.mark.skipif(not (os.path.exists(HIPCC) and os.path.exists(CLANG)) or _asan_runtime() is None,
+                    reason="needs hipcc and clang's AddressSanitizer runtime")
+@pytest.mark.parametrize("groups_on", [False, True], ids=["as_built", "batch_chunk_groups_on"])
+def test_host_logic_is_clean_under_asan(tmp_path, groups_on):
+    _build_and_replay(str(tmp_path), groups_on)
