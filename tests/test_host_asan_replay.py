@@ -1,4 +1,5 @@
-"""The library's host logic under AddressSanitizer, on the CPU.
+"""The library's host logic under AddressSanitizer and ThreadSanitizer, on
+the CPU.
 
 The runtime is compiled host-only (no kernels) with AddressSanitizer and
 linked against a stand-in for the HIP runtime (``asan_hip_stub.cpp``) whose
@@ -9,7 +10,11 @@ sequence over the square m = 2..14 sweep, graph-mode strips with one to
 three chunk groups, resident strips in both arithmetic forms and the strip
 that allocates nothing.  A second build turns the batch's chunk groups back
 on (they are switched off in the product), so their stage-table layout and
-fork/join are replayed too.
+fork/join are replayed too.  Under ThreadSanitizer, ``tsan_replay_driver.cpp``
+builds the coefficient form's host maps on a second thread while the main
+thread runs coefficient-form strips (the concurrent use that preceded a
+crash in Python's garbage collector on the GPU machine): no data race may be
+reported.
 """
 import os
 import shutil
@@ -26,9 +31,9 @@ GROUPS_OFF = "  bp.groups = 1;\n"
 GROUPS_ON = "  bp.groups = std::max(1, std::min(t.streams, 4));\n"
 
 
-def _asan_runtime():
+def _san_runtime(kind="asan"):
     try:
-        p = subprocess.run([CLANG, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True,
+        p = subprocess.run([CLANG, f"-print-file-name=libclang_rt.{kind}-x86_64.so"], capture_output=True, text=True,
                            check=True).stdout.strip()
     except (OSError, subprocess.CalledProcessError):
         return None
@@ -41,7 +46,9 @@ def _run(cmd, cwd, env=None, timeout=600):
     return r
 
 
-def _build_and_replay(top, groups_on):
+def _build(top, san, groups_on, driver):
+    """Builds the host-only library with sanitizer `san` and `driver`; returns
+    (build dir, driver path)."""
     # the sources include the public header as ../../include/chromstrip.h
     tmp = os.path.join(top, "pkg", "csrc")
     os.makedirs(tmp)
@@ -57,24 +64,35 @@ def _build_and_replay(top, groups_on):
         fh.write(src)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", tmp]
     host = ["-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fPIC"]
-    _run([HIPCC, "-x", "hip", "--cuda-host-only", *host, *inc, "-Xarch_host", "-fsanitize=address", "-c",
+    flag = f"-fsanitize={san}"
+    _run([HIPCC, "-x", "hip", "--cuda-host-only", *host, *inc, "-Xarch_host", flag, "-c",
           "runtime.hip", "-o", "runtime.o"], tmp)
     fat = [ln.split()[-1] for ln in _run(["nm", "-u", "runtime.o"], tmp).stdout.splitlines()
            if "__hip_fatbin" in ln]
     assert len(fat) == 1, fat
     for f in ("states", "maps"):
-        _run([CLANG, *host, "-fsanitize=address", *inc, "-c", f"{f}.cpp", "-o", f"{f}.o"], tmp)
-    _run([CLANG, *host, "-fsanitize=address", f"-DHIP_FATBIN_SYMBOL={fat[0]}", "-I", "/opt/rocm/include", "-c",
+        _run([CLANG, *host, flag, *inc, "-c", f"{f}.cpp", "-o", f"{f}.o"], tmp)
+    _run([CLANG, *host, flag, f"-DHIP_FATBIN_SYMBOL={fat[0]}", "-I", "/opt/rocm/include", "-c",
           os.path.join(HERE, "asan_hip_stub.cpp"), "-o", "stub.o"], tmp)
-    _run([CLANG, "-shared", "-fsanitize=address", "-shared-libasan", "-o", "libreplay.so", "runtime.o", "states.o",
+    _run([CLANG, "-shared", flag, "-shared-libsan", "-o", "libreplay.so", "runtime.o", "states.o",
           "maps.o", "stub.o", "-lpthread"], tmp)
-    _run([CLANG, *host, "-fsanitize=address", "-shared-libasan", "-Wno-unused-result", "-D__HIP_PLATFORM_AMD__",
-          *inc, "-I", "/opt/rocm/include", os.path.join(HERE, "asan_replay_driver.cpp"), "-o", "replay", "-L", tmp,
-          "-lreplay", f"-Wl,-rpath,{tmp}"], tmp)
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0",
-               LD_LIBRARY_PATH=os.path.dirname(_asan_runtime()) + ":" + os.environ.get("LD_LIBRARY_PATH", ""))
+    _run([CLANG, *host, flag, "-shared-libsan", "-Wno-unused-result", "-D__HIP_PLATFORM_AMD__",
+          *inc, "-I", "/opt/rocm/include", os.path.join(HERE, driver), "-o", "replay", "-L", tmp,
+          "-lreplay", f"-Wl,-rpath,{tmp}", "-lpthread"], tmp)
+    return tmp, os.path.join(tmp, "replay")
+
+
+def _env(kind, options):
+    env = dict(os.environ, LD_LIBRARY_PATH=os.path.dirname(_san_runtime(kind)) + ":" +
+               os.environ.get("LD_LIBRARY_PATH", ""))
+    env[f"{kind.upper()}_OPTIONS"] = options
     env.pop("LD_PRELOAD", None)
-    r = _run([os.path.join(tmp, "replay"), "1"], tmp, env=env, timeout=900)
+    return env
+
+
+def _build_and_replay(top, groups_on):
+    tmp, exe = _build(top, "address", groups_on, "asan_replay_driver.cpp")
+    r = _run([exe, "1"], tmp, env=_env("asan", "detect_leaks=0:abort_on_error=0"), timeout=900)
     lines = r.stdout.splitlines()
     assert lines[-1] == "done"
     assert sum(ln.startswith("batch ") for ln in lines) == 48
@@ -83,8 +101,19 @@ def _build_and_replay(top, groups_on):
     assert "ERROR: AddressSanitizer" not in r.stderr
 
 
-@pytest.mark.skipif(not (os.path.exists(HIPCC) and os.path.exists(CLANG)) or _asan_runtime() is None,
+@pytest.mark.skipif(not (os.path.exists(HIPCC) and os.path.exists(CLANG)) or _san_runtime("asan") is None,
                     reason="needs hipcc and clang's AddressSanitizer runtime")
 @pytest.mark.parametrize("groups_on", [False, True], ids=["as_built", "batch_chunk_groups_on"])
 def test_host_logic_is_clean_under_asan(tmp_path, groups_on):
     _build_and_replay(str(tmp_path), groups_on)
+
+
+@pytest.mark.skipif(not (os.path.exists(HIPCC) and os.path.exists(CLANG)) or _san_runtime("tsan") is None,
+                    reason="needs hipcc and clang's ThreadSanitizer runtime")
+def test_concurrent_host_map_builds_are_race_free_under_tsan(tmp_path):
+    tmp, exe = _build(str(tmp_path), "thread", False, "tsan_replay_driver.cpp")
+    for lat, m_hi in ((0, 13), (1, 11)):
+        r = _run([exe, str(lat), str(m_hi)], tmp, env=_env("tsan", "halt_on_error=1"), timeout=900)
+        assert r.stdout.splitlines()[-1] == "done"
+        assert sum(ln.startswith("series m") for ln in r.stdout.splitlines()) == m_hi
+        assert "WARNING: ThreadSanitizer" not in r.stderr
