@@ -531,6 +531,8 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=120)
     ap.add_argument("--serve-plain-jobs", type=int, default=20)
     ap.add_argument("--quick", action="store_true", help="headline and roofline only")
+    ap.add_argument("--small", action="store_true",
+                    help="with --quick: also the small configurations (square 4x5 and m=10, triangular 12x13)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default=WORKLOAD, choices=["square_14x15", "square_18x19"],
@@ -660,17 +662,18 @@ def main():
         log(f"plain: {plain['value']:.3e} state-updates/s over {Ik} instances")
 
     extra = {}
-    if not args.quick:
-        extra["plain_configs"] = bench_small_configs(torch, stream, max(2, args.steps // 4))
+    if not args.quick or args.small:
+        extra["plain_configs"] = bench_small_configs(torch, stream, max(5, args.steps // 2))
         log("plain configs: " + ", ".join(f"{k} plain {v['plain']['ms_per_step']:.3f} / graph "
                                           f"{v['graph']['ms_per_step']:.3f} / resident "
                                           f"{v['resident']['ms_per_step']:.3f} ms"
                                           for k, v in extra["plain_configs"].items()))
-        extra["sweep_square_2_14"] = bench_sweep(torch, stream, tune, max(2, args.steps // 4))
-        log(f"sweep m=2..14: {extra['sweep_square_2_14']['value']:.3e} state-updates/s")
-        extra["triangular_12x13"] = bench_triangular(torch, stream, max(2, args.steps // 2))
+        extra["triangular_12x13"] = bench_triangular(torch, stream, max(20, args.steps))
         log(f"triangular m=12: {extra['triangular_12x13']['ms_per_step']:.3f} ms "
             f"(graph row replay {extra['triangular_12x13']['graph_row_replay_ms']:.3f} ms)")
+    if not args.quick:
+        extra["sweep_square_2_14"] = bench_sweep(torch, stream, tune, max(2, args.steps // 4))
+        log(f"sweep m=2..14: {extra['sweep_square_2_14']['value']:.3e} state-updates/s")
         extra["serving"] = bench_serving(torch, args.serve_jobs, args.serve_plain_jobs)
         log(f"serving: {extra['serving']}")
         extra["finite_lattice_square"] = bench_finite_lattice(41)
