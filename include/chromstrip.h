@@ -118,7 +118,8 @@ typedef struct chrom_tuning {
                            at the same time (batched and graph modes); under 4 and 6 the
                            last factor of a row, which writes the NCNNN states, first takes
                            them in the order of their labels read from point 1 to m; 0:
-                           direct gathers.  Resident mode: 0 = exact double accumulation
+                           direct gathers.  Grouped launches (grouped strips, chromatic_batch,
+                           server steps) take 0, 4 or 6.  Resident mode: 0 = exact double accumulation
                            where every row's sum stays below 2^52 (longest row x max
                            |c(q)| <= 2^21), else modular; 1 = modular arithmetic throughout */
 } chrom_tuning;
@@ -308,7 +309,9 @@ size_t chromatic_batch_workspace_bytes(const chrom_job* jobs, int njobs,
  * is split into instance chunks of width 64*lanes_v, and step k of every
  * (job, chunk) item runs in one grouped kernel launch whose workgroups map
  * to (item, tile) pairs, so jobs of uneven state-space size share every
- * launch.  tune->streams is ignored (one launch chain).  The graph is
+ * launch.  tune->streams is ignored (one launch chain); tune->stage must
+ * be 0, 4 or 6 (the grouped kernel gathers directly; 4 and 6 reorder each
+ * factor's targets as for a strip), else CHROM_EINVAL.  The graph is
  * captured once per workspace and job list and replayed on later identical
  * calls.  Same results as chromatic_strip for each job.  The workspace must
  * not be reused for another job list while a launch on it is in flight, and
@@ -340,8 +343,11 @@ size_t chromatic_slot_state_bytes(int lattice, int m, int nq, int np,
 /* Advances every slot by up to `rows` rows (a new slot first runs its
  * set-up and reads out r = 1) on `stream`, and updates rows_done.  Step k of
  * every slot runs in one grouped launch, so slots that differ in lattice, m
- * and instance count share each launch.  Server steps on one device must be
- * issued on one stream (they share a stage-table buffer). */
+ * and instance count share each launch.  tune->stage: 0, 4 or 6 as for
+ * chromatic_batch (the vectors keep their layout, so steps may differ).
+ * Server steps on
+ * one device must be issued on one stream (they share a stage-table
+ * buffer). */
 int chromatic_server_step(chrom_slot* slots, int nslots, int rows,
                           const chrom_tuning* tune, void* stream);
 

@@ -2472,10 +2472,24 @@ size_t resident_workspace_bytes(int lattice, int m, int I, const Tune& t) {
 int rows_tile_of(const Tune& t) { return t.rpw * t.wpb; }
 
 // Staged tiles for the forward factors of a batched or graph-mode job.
+// The grouped kernel runs plain gathers, so grouped launches (batches,
+// server steps, grouped strips) take the target orders of stages 4
+// (clustered) and 6 (interleaved) but not LDS staging or op streams.
+void check_batch_stage(const Tune& t) {
+  if (t.stage != 0 && t.stage != 4 && t.stage != 6)
+    throw ArgError("grouped launches (chromatic_batch, server steps, grouped strips) take stage 0, 4 or 6");
+}
+
+// Stages 4 and 6 only reorder a factor's targets, so grouped launches (whose
+// kernel gathers directly) take them too; LDS staging (1-3) and op streams
+// (5) need their own kernels (batched and graph modes).
 void bind_staging(JobCtx& j, int mode) {
-  if (j.t.stage == 5 && (mode == CHROM_MODE_BATCHED || mode == CHROM_MODE_GRAPH))
+  const bool direct = mode == CHROM_MODE_BATCHED || mode == CHROM_MODE_GRAPH;
+  if (mode == CHROM_MODE_GROUPED && j.t.stage == 4)
+    j.stg = &dev_staged(*j.dm, *j.fam, stage_slots(std::min(j.t.V, 2)), rows_tile_of(j.t), 2);
+  else if (j.t.stage == 5 && direct)
     j.ops = &dev_ops(*j.dm, *j.fam);
-  else if (j.t.stage == 6 && (mode == CHROM_MODE_BATCHED || mode == CHROM_MODE_GRAPH))
+  else if (j.t.stage == 6 && (direct || mode == CHROM_MODE_GROUPED))
     j.stg = &dev_staged(*j.dm, *j.fam, j.t.wpb, rows_tile_of(j.t), 3);
   else if (j.t.stage && j.t.stage != 5 && j.t.stage != 6 && j.t.V <= 2 &&
            (mode == CHROM_MODE_BATCHED || mode == CHROM_MODE_GRAPH))
@@ -2503,6 +2517,7 @@ int strip_async_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, c
   std::vector<Inst> inst = make_instances(q, nq, p, np);
   Tune t = resolve(tune, false, mode == CHROM_MODE_RESIDENT);
   if (mode == CHROM_MODE_RESIDENT) check_resident_fits(lattice, m, t);
+  if (mode == CHROM_MODE_GROUPED) check_batch_stage(t);
   if (n_max == 0) return CHROM_OK;
   if (!ws || !d_out) throw ArgError("null workspace or output");
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) throw ArgError("workspace must be 256-byte aligned");
@@ -2570,6 +2585,7 @@ int strip_sync_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, co
   if (!out) throw ArgError("null output");
   Tune t = resolve(tune, false, mode == CHROM_MODE_RESIDENT);
   if (mode == CHROM_MODE_RESIDENT) check_resident_fits(lattice, m, t);
+  if (mode == CHROM_MODE_GROUPED) check_batch_stage(t);
   const int I = static_cast<int>(inst.size());
   const size_t wsb = workspace_bytes(lattice, m, I, n_max, mode, t);
   DevBuf ws(wsb);
@@ -2770,6 +2786,7 @@ BatchPlan batch_plan(const chrom_job* jobs, int njobs, const Tune& t) {
 
 int batch_impl(const chrom_job* jobs, int njobs, const chrom_tuning* tune, void* ws, size_t ws_bytes, hipStream_t st) {
   Tune t = resolve(tune);
+  check_batch_stage(t);
   BatchPlan bp = batch_plan(jobs, njobs, t);
   if (njobs == 0) return CHROM_OK;
   if (!ws) throw ArgError("null workspace");
@@ -2785,12 +2802,13 @@ int batch_impl(const chrom_job* jobs, int njobs, const chrom_tuning* tune, void*
     JobCtx j;
     j.dm = &dm;
     j.fam = &dev_family(dm, t.fuse);
-      j.t = t;
+    j.t = t;
     j.L = bp.layouts[k];
     void* base = static_cast<char*>(ws) + bp.job_off[k];
     j.P = job_ptrs(j.L, base);
     j.d_out = jb.d_out;
     j.out_row_stride = j.L.I;
+    bind_staging(j, CHROM_MODE_GROUPED);   // stages 4 and 6: the target orders
     if (jb.n_max > 0) {
       std::vector<uint32_t> img = const_image(j.L, inst, j.fam->codes, j.fam->shift);
       upload(static_cast<char*>(base) + j.L.p, img.data(), img.size() * 4, st);
@@ -2829,6 +2847,7 @@ int server_step_impl(chrom_slot* slots, int nslots, int rows, const chrom_tuning
   if (nslots < 0 || (nslots > 0 && !slots)) throw ArgError("bad slot list");
   if (rows < 1) throw ArgError("rows must be >= 1");
   Tune t = resolve(tune);
+  check_batch_stage(t);
   std::vector<Program> progs(nslots);
   std::vector<const Program*> pp;
   std::vector<int> new_done(nslots);
@@ -2848,11 +2867,12 @@ int server_step_impl(chrom_slot* slots, int nslots, int rows, const chrom_tuning
     JobCtx j;
     j.dm = &dm;
     j.fam = &dev_family(dm, t.fuse);
-      j.t = t;
+    j.t = t;
     j.L = L;
     j.P = job_ptrs(L, sl.d_state);
     j.d_out = sl.d_out;
     j.out_row_stride = j.L.I;
+    bind_staging(j, CHROM_MODE_GROUPED);   // stages 4 and 6: the target orders
     progs[k].nchunk = L.nchunk;
     int first = sl.rows_done;
     int last_row = std::min(sl.n_max - 1, first + rows - 1);  // 0-based out rows to produce
@@ -3047,6 +3067,7 @@ size_t chromatic_workspace_bytes(int lattice, int m, int n_max, int nq, int np, 
     if (nq < 1 || np < 1) throw ArgError("need nq, np >= 1");
     check_mode(mode);
     Tune t = resolve(tune, false, mode == CHROM_MODE_RESIDENT);
+    if (mode == CHROM_MODE_GROUPED) check_batch_stage(t);
     r = workspace_bytes(lattice, m, nq * np, n_max, mode, t);
     return CHROM_OK;
   });
@@ -3195,6 +3216,7 @@ size_t chromatic_batch_workspace_bytes(const chrom_job* jobs, int njobs, const c
   size_t r = 0;
   int rc = guarded([&] {
     Tune t = resolve(tune);
+    check_batch_stage(t);
     r = batch_plan(jobs, njobs, t).bytes;
     return CHROM_OK;
   });

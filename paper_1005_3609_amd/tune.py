@@ -43,8 +43,9 @@ def candidates(space=None) -> list[dict]:
             continue            # its own candidates: resident_candidates
         if mode == "grouped" and s != 1:
             continue            # grouped launches already cover every chunk at once
-        if g and (mode == "grouped" or (v > 2 and g not in (4, 6))):
-            continue            # staging and op streams apply to graph / batched launches (lanes_v <= 2)
+        if g and g not in (4, 6) and (mode == "grouped" or v > 2):
+            continue            # staging and op streams apply to graph / batched launches (lanes_v <= 2);
+                                # the target orders (4, 6) to every mode
         out.append(dict(lanes_v=v, targets_per_wave=t, waves_per_block=w, xcd_order=x, unroll=u, streams=s,
                         fuse=f, stage=g, mode=mode))
     return out
@@ -245,7 +246,7 @@ def tune_series(lattice, m, n_max, d_max, primes, space=None, steps=3, path=DEFA
 
 
 BATCH_SPACE = dict(lanes_v=[1, 2], targets_per_wave=[4, 8], waves_per_block=[4, 8], xcd_order=[1], unroll=[4],
-                   fuse=[1, 2])
+                   fuse=[1, 2], stage=[0, 6])
 
 
 def _batch_key(name: str):
@@ -270,10 +271,11 @@ def tune_batch(name: str, jobs, space=None, steps=3, path=DEFAULT_CACHE, log=Non
     dev = torch.device("cuda", torch.cuda.current_device())
     stream = torch.cuda.current_stream(dev)
     table, ref, best = [], None, None
-    for v, t, w, x, u, f, st in itertools.product(space["lanes_v"], space["targets_per_wave"],
-                                                  space["waves_per_block"], space["xcd_order"], space["unroll"],
-                                                  space["fuse"], space.get("streams", [1])):
-        cand = dict(lanes_v=v, targets_per_wave=t, waves_per_block=w, xcd_order=x, unroll=u, fuse=f, streams=st)
+    for v, t, w, x, u, f, st, g in itertools.product(space["lanes_v"], space["targets_per_wave"],
+                                                     space["waves_per_block"], space["xcd_order"], space["unroll"],
+                                                     space["fuse"], space.get("streams", [1]), space.get("stage", [0])):
+        cand = dict(lanes_v=v, targets_per_wave=t, waves_per_block=w, xcd_order=x, unroll=u, fuse=f, streams=st,
+                    stage=g)
         outs, ws = api.batch(jobs, tuning=cand, stream=stream, device=dev)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

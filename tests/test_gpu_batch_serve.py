@@ -26,6 +26,10 @@ GROUPS_OFF = ("chunk groups on parallel graph branches are switched off for chro
 
 
 @pytest.mark.parametrize("tuning", [None, dict(lanes_v=1, fuse=2), dict(targets_per_wave=3),
+                                    # the target orders: interleaved (6) and clustered (4) rows
+                                    dict(stage=6, targets_per_wave=5, waves_per_block=4, fuse=2),
+                                    dict(stage=6, lanes_v=1, targets_per_wave=16, waves_per_block=8),
+                                    dict(stage=4, lanes_v=2, fuse=2),
                                     pytest.param(dict(streams=2), marks=pytest.mark.skip(reason=GROUPS_OFF)),
                                     pytest.param(dict(streams=3, lanes_v=1, fuse=2),
                                                  marks=pytest.mark.skip(reason=GROUPS_OFF))])

@@ -230,3 +230,9 @@ def test_bad_arguments_are_errors_without_touching_a_gpu():
     # resident mode's stage picks the arithmetic: 0 or 1 only
     with pytest.raises(api.ChromError, match="resident mode takes stage"):
         api.strip("square", 4, 3, [1, 2], [P31], mode="resident", tuning={"stage": 2})
+    # a batch's grouped gathers take the target orders (4, 6) but no LDS staging or op streams
+    job = dict(lattice="square", m=4, n_max=3, q_points=[1, 2], primes=[P31])
+    assert api.batch_workspace_bytes([job], tuning={"stage": 6}) == api.batch_workspace_bytes([job])
+    for st in (1, 2, 3, 5):
+        with pytest.raises(api.ChromError, match="stage 0, 4 or 6"):
+            api.batch_workspace_bytes([job], tuning={"stage": st})
