@@ -2254,13 +2254,15 @@ void run_plain(const DevMaps& dm, int lattice, int m, int n_max, const std::vect
 constexpr size_t kResMaxLds = 160 * 1024;
 
 // Workspace of one resident job: per-instance code values and quotients,
-// p, -p^{-1}, 2^32 mod p, the code values as doubles, 1 / p as a double, and
-// the read-out vector [I][s_nc].  The modular form reads [coef, coff), the
-// double form [p, w).
+// the job record, p, -p^{-1}, 2^32 mod p, 1 / p as a double, the code values
+// as doubles, and the read-out vector [I][s_nc].  Code tables hold [I][nc]
+// (nc codes of the family) in room for kMaxCodes.  One upload carries what
+// the job's arithmetic reads, the job record included: [coef, rcp) for the
+// modular form, [table, coff + I nc doubles) for the double form.
 struct ResLayout {
   int I = 0, K = 1, ngroups = 0;
   int64_t s_nc = 0, s_max = 0;
-  size_t coef = 0, coefs = 0, coff = 0, rcp = 0, p = 0, pinv = 0, r1 = 0, w = 0, bytes = 0;
+  size_t coef = 0, coefs = 0, table = 0, p = 0, pinv = 0, r1 = 0, rcp = 0, coff = 0, w = 0, bytes = 0;
 };
 
 ResLayout res_layout(int lattice, int m, int I, const Tune& t) {
@@ -2279,11 +2281,12 @@ ResLayout res_layout(int lattice, int m, int I, const Tune& t) {
   };
   L.coef = take(static_cast<size_t>(I) * kMaxCodes * 4);
   L.coefs = take(static_cast<size_t>(I) * kMaxCodes * 4);
+  L.table = take(sizeof(ResidentJob));
   L.p = take(static_cast<size_t>(I) * 4);
   L.pinv = take(static_cast<size_t>(I) * 4);
   L.r1 = take(static_cast<size_t>(I) * 4);
-  L.coff = take(static_cast<size_t>(I) * kMaxCodes * 8);
   L.rcp = take(static_cast<size_t>(I) * 8);
+  L.coff = take(static_cast<size_t>(I) * kMaxCodes * 8);
   L.w = take(static_cast<size_t>(I) * L.s_nc * 4);
   L.bytes = off;
   return L;
@@ -2424,14 +2427,13 @@ void allow_resident_lds() {
   done[dev] = true;
 }
 
-// Uploads the job table to `table` and launches every job's workgroups at
-// once (one launch: no workgroup waits on another).
-void run_resident(const std::vector<ResidentJob>& jobs, size_t lds, const Tune& t, void* table, hipStream_t st) {
+// Launches every job's workgroups at once (one launch: no workgroup waits on
+// another); `table` holds the job records, uploaded by the caller on `st`.
+void run_resident(const std::vector<ResidentJob>& jobs, size_t lds, const Tune& t, const void* table, hipStream_t st) {
   if (jobs.empty()) return;
   int total = 0;
   for (const ResidentJob& J : jobs) total = std::max(total, J.g0 + J.ngroups);
   if (total < 1) return;
-  upload(table, jobs.data(), jobs.size() * sizeof(ResidentJob), st);
   const ResidentJob* d = static_cast<const ResidentJob*>(table);
   const int nj = static_cast<int>(jobs.size());
   dim3 grid(total), block(64 * t.wpb);
@@ -2463,7 +2465,7 @@ void check_resident_fits(int lattice, int m, const Tune& t) {
 
 size_t resident_workspace_bytes(int lattice, int m, int I, const Tune& t) {
   check_resident_fits(lattice, m, t);
-  return res_layout(lattice, m, I, t).bytes + align_up(sizeof(ResidentJob));
+  return res_layout(lattice, m, I, t).bytes;
 }
 
 // ---------------------------------------------------------------------------
@@ -2536,10 +2538,13 @@ int strip_async_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, c
     size_t lds = 0;
     std::vector<ResidentJob> jobs{resident_job(dm, fam, R, ws, n_max, d_out, 0, lds, inst, t)};
     std::vector<uint32_t> img = res_image(R, inst, fam.codes);
-    // only the constants the job's arithmetic reads
-    const size_t lo = jobs[0].exact ? R.p : R.coef, hi = jobs[0].exact ? R.w : R.coff;
-    upload(static_cast<char*>(ws) + lo, img.data() + (lo - R.coef) / 4, hi - lo, st);
-    run_resident(jobs, lds, t, static_cast<char*>(ws) + R.bytes, st);
+    std::memcpy(reinterpret_cast<char*>(img.data()) + (R.table - R.coef), jobs.data(), sizeof(ResidentJob));
+    // one upload: the job record and the constants the job's arithmetic reads
+    const size_t nc = fam.codes.size();
+    const size_t lo = jobs[0].exact ? R.table : R.coef;
+    const size_t hi = jobs[0].exact ? R.coff + static_cast<size_t>(I) * nc * 8 : R.rcp;
+    upload(static_cast<char*>(ws) + lo, reinterpret_cast<const char*>(img.data()) + (lo - R.coef), hi - lo, st);
+    run_resident(jobs, lds, t, static_cast<char*>(ws) + R.table, st);
     return CHROM_OK;
   }
   JobCtx j;
