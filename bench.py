@@ -55,14 +55,34 @@ def factor_sizes(lat, m, which=0, count=None):
     return out
 
 
-def row_bytes(sizes, ipad, s_nc):
+def split_jobs(I, V):
+    """The jobs a strip of I instances runs as, [(instances, lanes_v)]: at
+    lanes_v 4 the instances past the last multiple of 256 form a second job at
+    lanes_v 2 (1 for at most 64) instead of a padded chunk."""
+    if V == 4 and I > 256 and I % 256:
+        rest = I % 256
+        return [(I - rest, 4), (rest, 1 if rest <= 64 else 2)]
+    return [(I, V)]
+
+
+def padded_instances(I, V):
+    """Instance lanes the strip's launches run (chunks of 64 lanes_v)."""
+    return sum(-(-i // (64 * v)) * 64 * v for i, v in split_jobs(I, V))
+
+
+def kernel_name(I, V, U):
+    return "+".join(f"k_gather<{v},{U}>" for _, v in split_jobs(I, V))
+
+
+def row_bytes(sizes, ipad, s_nc, jobs=1):
     """Bytes of one row of factor applications: for every factor each source
     row read once and each target row written once (4 B per residue per
     instance), its CSR row pointers and entry words, and the read-out vector w
-    read once by the read-out fused into the last launch."""
+    read once by the read-out fused into the last launch.  `jobs`: the launches
+    each factor takes (a lanes_v 4 split reads the map once per job)."""
     total = 0
     for k, (s_in, s_out, nnz) in enumerate(sizes):
-        total += 4 * ipad * (s_in + s_out) + 4 * (s_out + 1) + 4 * nnz
+        total += 4 * ipad * (s_in + s_out) + jobs * (4 * (s_out + 1) + 4 * nnz)
         if k == len(sizes) - 1:
             total += 4 * ipad * s_nc
     return total
@@ -423,7 +443,8 @@ def bench_m18(torch, stream, tune, rows):
     maps_s = time.time() - t0
     V = tune.get("lanes_v") or 2
     fuse = tune.get("fuse") or 1
-    ipad = -(-I // (64 * V)) * 64 * V
+    ipad = padded_instances(I, V)
+    nj = len(split_jobs(I, V))
     out = torch.zeros((n, len(q), len(p)), dtype=torch.int32, device=dev)
     ws = api.alloc_workspace(api.workspace_bytes(lat, m, n, len(q), len(p), "graph", tune), dev)
 
@@ -441,8 +462,8 @@ def bench_m18(torch, stream, tune, rows):
     k_ms = timed(torch, stream, lambda: api.factor_launches(lat, m, q, p, rows, ws_b, rtune, stream))
     del ws_b
     nf = -(-m // fuse)
-    per_site_row = row_bytes(sizes, ipad, s_nc)
-    own_row = per_site_row if fuse == 1 else row_bytes(factor_sizes(lat, m, fuse, nf), ipad, s_nc)
+    per_site_row = row_bytes(sizes, ipad, s_nc, nj)
+    own_row = per_site_row if fuse == 1 else row_bytes(factor_sizes(lat, m, fuse, nf), ipad, s_nc, nj)
     achieved = rows * own_row / (k_ms / 1e3) / 1e9
     # one (q, p) instance through the plain path, two rows
     q1, p1 = q[:1], p[:1]
@@ -460,7 +481,8 @@ def bench_m18(torch, stream, tune, rows):
             "maps_build_s": maps_s, "ms_per_strip": ms,
             "value": written_of(lat, m, n, I, fuse) / (ms / 1e3), "unit": "state-updates/s (residues written)",
             "per_site_factor_updates_per_s": updates_of(lat, m, n, I) / (ms / 1e3),
-            "factor_kernel": {"rows_timed": rows, "launches": rows * nf, "avg_launch_us": k_ms * 1e3 / (rows * nf),
+            "factor_kernel": {"kernel": kernel_name(I, V, tune.get("unroll") or 4), "rows_timed": rows,
+                              "launches": rows * nf * nj, "avg_launch_us": k_ms * 1e3 / (rows * nf * nj),
                               "achieved_GBs": achieved, "frac_of_hbm_peak": achieved / HBM_PEAK_GBS,
                               "own_min_bytes_per_row": own_row, "per_site_bytes_per_row": per_site_row,
                               "frac_per_site": rows * per_site_row / (k_ms / 1e3) / 1e9 / HBM_PEAK_GBS},
@@ -582,7 +604,8 @@ def main():
             tune[k] = v
     V = tune.get("lanes_v") or 2
     fuse = tune.get("fuse") or 1
-    ipad = -(-I // (64 * V)) * 64 * V
+    ipad = padded_instances(I, V)
+    nj = len(split_jobs(I, V))
 
     t0 = time.time()
     api.prepare(lat, m)
@@ -626,16 +649,16 @@ def main():
     R = args.roofline_rows
     k_ms = timed(torch, stream, lambda: api.factor_launches(lat, m, q, p, R, ws_b, rtune, stream))
     nf = -(-m // fuse)
-    launches = R * nf
+    launches = R * nf * nj
     avg_us = k_ms * 1e3 / launches
-    per_site_row = row_bytes(sizes, ipad, s_nc)
-    own_row = per_site_row if fuse == 1 else row_bytes(factor_sizes(lat, m, fuse, nf), ipad, s_nc)
+    per_site_row = row_bytes(sizes, ipad, s_nc, nj)
+    own_row = per_site_row if fuse == 1 else row_bytes(factor_sizes(lat, m, fuse, nf), ipad, s_nc, nj)
     achieved = R * own_row / (k_ms / 1e3) / 1e9
     achieved_per_site = R * per_site_row / (k_ms / 1e3) / 1e9
     # the headline step itself: every gather launch's own minimum bytes of the
     # n - 1 transfer rows over the timed step (its other kernels included)
     achieved_step = (n - 1) * own_row / (ms_per_step / 1e3) / 1e9
-    kname = f"k_gather<{V},{tune.get('unroll') or 4}>"
+    kname = kernel_name(I, V, tune.get("unroll") or 4)
     log(f"factor kernel {kname}: {launches} launches, avg {avg_us:.1f} us, {achieved:.0f} GB/s of the launches' "
         f"own minimum traffic ({achieved_per_site:.0f} GB/s counting every per-site factor's reads and writes)")
     del ws_b

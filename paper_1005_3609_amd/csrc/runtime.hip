@@ -1503,7 +1503,9 @@ Step gather_step(const JobCtx& j, const DevCsr& c, const uint32_t* in, uint32_t*
 ReduceArgs reduce_args(const JobCtx& j, int out_row) {
   return ReduceArgs{j.P.part, static_cast<long>(j.L.nparts) * j.L.W, j.L.nparts, j.P.ic(),
                     j.P.part2, static_cast<long>(j.L.ngroups) * j.L.W, j.L.ngroups,
-                    j.d_out ? j.d_out + static_cast<long>(out_row) * j.L.I : nullptr, j.L.I};
+                    j.d_out ? j.d_out + static_cast<long>(out_row) * (j.out_row_stride ? j.out_row_stride : j.L.I)
+                            : nullptr,
+                    j.L.I};
 }
 
 // The read-out of one row: level-1 then level-2 reduction of the partials.
@@ -2500,9 +2502,8 @@ void bind_staging(JobCtx& j, int mode) {
     j.stg = &dev_staged(*j.dm, *j.fam, stage_slots(std::min(j.t.V, 2)), rows_tile_of(j.t), 2);
 }
 
-size_t workspace_bytes(int lattice, int m, int I, int n_max_hint, int mode, const Tune& t) {
-  if (mode == CHROM_MODE_PLAIN) return plain_layout(lattice, m).bytes;
-  if (mode == CHROM_MODE_RESIDENT) return resident_workspace_bytes(lattice, m, I, t);
+// One job's region: its layout, the graph row counter, grouped stage tables.
+size_t job_workspace_bytes(int lattice, int m, int I, int n_max_hint, int mode, const Tune& t) {
   JobLayout L = job_layout(lattice, m, I, t, kMaxCodes, rows_tile_of(t));
   size_t b = L.bytes + 256;  // + graph row counter
   if (mode == CHROM_MODE_GROUPED) {
@@ -2510,6 +2511,74 @@ size_t workspace_bytes(int lattice, int m, int I, int n_max_hint, int mode, cons
     b += stage_bytes(L.nchunk * len, len);
   }
   return b;
+}
+
+// lanes_v 4 runs chunks of 256 instances.  When the instance count is not a
+// multiple of 256, the lanes of the last chunk past it would compute padding;
+// instead the first floor(I / 256) * 256 instances run at lanes_v 4 and the
+// rest as a second job at lanes_v 2 (1 for at most 64 instances), one chunk
+// group, on a parallel branch (batched and graph modes).  Instances are
+// independent, so the residues are the same.  Each job has its own region
+// of the workspace.
+struct SplitPlan {
+  int n = 1;
+  int I[2] = {0, 0};
+  Tune t[2];
+  size_t off[2] = {0, 0};
+  size_t bytes = 0;
+};
+
+SplitPlan split_plan(int lattice, int m, int I, int n_max_hint, int mode, const Tune& t) {
+  SplitPlan sp;
+  sp.I[0] = I;
+  sp.t[0] = t;
+  if ((mode == CHROM_MODE_BATCHED || mode == CHROM_MODE_GRAPH) && t.V == 4 && I > 256 && I % 256 != 0) {
+    sp.n = 2;
+    sp.I[0] = I / 256 * 256;
+    sp.I[1] = I - sp.I[0];
+    sp.t[1] = t;
+    sp.t[1].V = sp.I[1] <= 64 ? 1 : 2;
+    sp.t[1].streams = 1;
+  }
+  for (int k = 0; k < sp.n; ++k) {
+    sp.off[k] = sp.bytes;
+    sp.bytes += align_up(job_workspace_bytes(lattice, m, sp.I[k], n_max_hint, mode, sp.t[k]));
+  }
+  return sp;
+}
+
+size_t workspace_bytes(int lattice, int m, int I, int n_max_hint, int mode, const Tune& t) {
+  if (mode == CHROM_MODE_PLAIN) return plain_layout(lattice, m).bytes;
+  if (mode == CHROM_MODE_RESIDENT) return resident_workspace_bytes(lattice, m, I, t);
+  return split_plan(lattice, m, I, n_max_hint, mode, t).bytes;
+}
+
+// The second job of a split runs on a library stream forked from and joined
+// back into the caller's (one per device).
+struct SplitStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+std::mutex g_split_mu;
+SplitStream g_split[64];
+
+template <class F>
+void fork_join_split(hipStream_t st, F&& body) {
+  std::lock_guard<std::mutex> lk(g_split_mu);
+  int dev = 0;
+  HIPX(hipGetDevice(&dev));
+  SplitStream& ss = g_split[dev];
+  if (!ss.s) {
+    HIPX(hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking));
+    HIPX(hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming));
+    HIPX(hipEventCreateWithFlags(&ss.join, hipEventDisableTiming));
+  }
+  HIPX(hipEventRecord(ss.fork, st));
+  HIPX(hipStreamWaitEvent(ss.s, ss.fork, 0));
+  body(0, st);
+  body(1, ss.s);
+  HIPX(hipEventRecord(ss.join, ss.s));
+  HIPX(hipStreamWaitEvent(st, ss.join, 0));
 }
 
 int strip_async_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, const uint32_t* p, int np, int mode,
@@ -2547,27 +2616,40 @@ int strip_async_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, c
     run_resident(jobs, lds, t, static_cast<char*>(ws) + R.table, st);
     return CHROM_OK;
   }
-  JobCtx j;
-  j.dm = &dm;
-  j.fam = &dev_family(dm, t.fuse);
-  j.t = t;
-  j.L = job_layout(lattice, m, I, t, kMaxCodes, rows_tile_of(t));
-  j.P = job_ptrs(j.L, ws);
-  j.d_out = d_out;
-  j.out_row_stride = j.L.I;
-  bind_staging(j, mode);
-  std::vector<uint32_t> img = const_image(j.L, inst, j.fam->codes, j.fam->shift);
-  upload(static_cast<char*>(ws) + j.L.p, img.data(), img.size() * 4, st);
-  int* row_ctr = reinterpret_cast<int*>(static_cast<char*>(ws) + j.L.bytes);
-  if (mode == CHROM_MODE_BATCHED) {
-    Program pg = strip_program(j, n_max);
-    run_eager(pg, t, st);
-  } else if (mode == CHROM_MODE_GRAPH) {
-    run_graph(j, n_max, row_ctr, ws, st);
-  } else {
-    Program pg = strip_program(j, n_max);
-    run_grouped({&pg}, t, static_cast<char*>(ws) + j.L.bytes + 256, st, true);
-  }
+  const SplitPlan sp = split_plan(lattice, m, I, n_max, mode, t);
+  // job k: instances [i0, i0 + sp.I[k]) of the list, its own workspace
+  // region, output columns i0.. of rows of I
+  auto run_job = [&](int k, hipStream_t s) {
+    const int i0 = k == 0 ? 0 : sp.I[0];
+    const std::vector<Inst> sub(inst.begin() + i0, inst.begin() + i0 + sp.I[k]);
+    const Tune& tk = sp.t[k];
+    char* wk = static_cast<char*>(ws) + sp.off[k];
+    JobCtx j;
+    j.dm = &dm;
+    j.fam = &dev_family(dm, tk.fuse);
+    j.t = tk;
+    j.L = job_layout(lattice, m, sp.I[k], tk, kMaxCodes, rows_tile_of(tk));
+    j.P = job_ptrs(j.L, wk);
+    j.d_out = d_out + i0;
+    j.out_row_stride = I;
+    bind_staging(j, mode);
+    std::vector<uint32_t> img = const_image(j.L, sub, j.fam->codes, j.fam->shift);
+    upload(wk + j.L.p, img.data(), img.size() * 4, s);
+    int* row_ctr = reinterpret_cast<int*>(wk + j.L.bytes);
+    if (mode == CHROM_MODE_BATCHED) {
+      Program pg = strip_program(j, n_max);
+      run_eager(pg, tk, s);
+    } else if (mode == CHROM_MODE_GRAPH) {
+      run_graph(j, n_max, row_ctr, wk, s);
+    } else {
+      Program pg = strip_program(j, n_max);
+      run_grouped({&pg}, tk, wk + j.L.bytes + 256, s, true);
+    }
+  };
+  if (sp.n == 1)
+    run_job(0, st);
+  else
+    fork_join_split(st, run_job);
   return CHROM_OK;
 }
 
@@ -2734,22 +2816,35 @@ int factor_launches_impl(int lattice, int m, const uint32_t* q, int nq, const ui
   if (!ws || ws_bytes < workspace_bytes(lattice, m, I, 1, CHROM_MODE_BATCHED, t))
     throw MemError("workspace missing or too small");
   const DevMaps& dm = dev_maps(lattice, m);
-  JobCtx j;
-  j.dm = &dm;
-  j.fam = &dev_family(dm, t.fuse);
-  j.t = t;
-  j.L = job_layout(lattice, m, I, t, kMaxCodes, rows_tile_of(t));
-  j.P = job_ptrs(j.L, ws);
-  j.d_out = nullptr;
-  bind_staging(j, CHROM_MODE_BATCHED);
-  Program pg;
-  pg.nchunk = j.L.nchunk;
-  add_rows(pg, j, 1, rows, -1, -1);
-  Program gathers;
-  gathers.nchunk = pg.nchunk;
-  for (const PStep& ps : pg.steps)
-    if (ps.s.op == kOpGather) gathers.steps.push_back(ps);
-  run_eager(gathers, t, st);
+  // the jobs of a lanes_v 4 split, one after the other on `st`: step by
+  // step, the first job's launch then the second's
+  const SplitPlan sp = split_plan(lattice, m, I, 1, CHROM_MODE_BATCHED, t);
+  std::vector<JobCtx> jobs(sp.n);
+  std::vector<Program> gathers(sp.n);
+  for (int k = 0; k < sp.n; ++k) {
+    JobCtx& j = jobs[k];
+    j.dm = &dm;
+    j.fam = &dev_family(dm, sp.t[k].fuse);
+    j.t = sp.t[k];
+    j.L = job_layout(lattice, m, sp.I[k], sp.t[k], kMaxCodes, rows_tile_of(sp.t[k]));
+    j.P = job_ptrs(j.L, static_cast<char*>(ws) + sp.off[k]);
+    j.d_out = nullptr;
+    bind_staging(j, CHROM_MODE_BATCHED);
+    Program pg;
+    pg.nchunk = j.L.nchunk;
+    add_rows(pg, j, 1, rows, -1, -1);
+    gathers[k].nchunk = pg.nchunk;
+    for (const PStep& ps : pg.steps)
+      if (ps.s.op == kOpGather) gathers[k].steps.push_back(ps);
+  }
+  const size_t nsteps = gathers[0].steps.size();
+  for (size_t i = 0; i < nsteps; ++i)
+    for (int k = 0; k < sp.n; ++k) {
+      Program one;
+      one.nchunk = gathers[k].nchunk;
+      one.steps.push_back(gathers[k].steps[i]);
+      run_eager(one, jobs[k].t, st);
+    }
   return CHROM_OK;
 }
 

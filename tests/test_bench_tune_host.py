@@ -98,3 +98,18 @@ def test_written_residues_of_fused_steps():
     # with pairs writes 14 rows x 385 911 targets x 640 instances
     assert bench.written_of("square", 14, 15, 640, 1) == bench.updates_of("square", 14, 15, 640)
     assert bench.written_of("square", 14, 15, 640, 2) == 14 * 385911 * 640
+
+
+def test_lanes_v4_split_jobs():
+    # lanes_v 4 runs chunks of 256 instances; the instances past the last
+    # multiple of 256 form a second job at lanes_v 2 (1 for at most 64)
+    assert bench.split_jobs(640, 4) == [(512, 4), (128, 2)]
+    assert bench.split_jobs(300, 4) == [(256, 4), (44, 1)]
+    assert bench.split_jobs(768, 4) == [(768, 4)]
+    assert bench.split_jobs(200, 4) == [(200, 4)]
+    assert bench.split_jobs(640, 2) == [(640, 2)]
+    assert bench.padded_instances(640, 4) == 640 and bench.padded_instances(200, 4) == 256
+    assert bench.padded_instances(300, 4) == 320
+    assert bench.kernel_name(640, 4, 4) == "k_gather<4,4>+k_gather<2,4>"
+    assert bench.kernel_name(640, 2, 4) == "k_gather<2,4>"
+

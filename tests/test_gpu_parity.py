@@ -133,6 +133,27 @@ def test_tuning_choices_are_bit_identical(tune):
         np.testing.assert_array_equal(got, want, err_msg=f"{mode} {tune}")
 
 
+@pytest.mark.parametrize("nq", [41, 38, 64])
+def test_lanes_v4_instance_split(nq):
+    # 41 q x 8 p = 328 instances: 256 at lanes_v 4 and 72 at lanes_v 2 on a
+    # parallel branch; 38 x 8 = 304: the 48 left run at lanes_v 1; 64 x 8 =
+    # 512: no split.  Same residues as the oracle in every mode and shape.
+    q, p = list(range(1, nq + 1)), [P31, 998244353, 1000000007, 2147483629, 2147483587, 1000000009,
+                                    998244853, 2147483563]
+    want = OT.chromatic_grid("square", 7, 5, q, p)
+    for tune in (dict(lanes_v=4), dict(lanes_v=4, streams=2, fuse=2, stage=6, targets_per_wave=8),
+                 dict(lanes_v=4, streams=3, fuse=2, stage=4)):
+        for mode in ("batched", "graph"):
+            got = api.strip("square", 7, 5, q, p, mode=mode, tuning=tune).astype(np.int64)
+            np.testing.assert_array_equal(got, want, err_msg=f"{nq} {mode} {tune}")
+    # the factor launches alone (the bench's roofline leg) run both jobs
+    import torch
+    tune = dict(lanes_v=4, fuse=2, stage=6)
+    out, ws = api.strip_async("square", 7, 5, q, p, mode="batched", tuning=tune)
+    api.factor_launches("square", 7, q, p, 2, ws, tune)
+    torch.cuda.synchronize()
+
+
 def test_edge_cases():
     # m = 1 paths, n_max = 1, one instance, q >= p, q = 0
     for lat in ("square", "triangular"):

@@ -230,6 +230,12 @@ def test_bad_arguments_are_errors_without_touching_a_gpu():
     # resident mode's stage picks the arithmetic: 0 or 1 only
     with pytest.raises(api.ChromError, match="resident mode takes stage"):
         api.strip("square", 4, 3, [1, 2], [P31], mode="resident", tuning={"stage": 2})
+    # lanes_v 4 at 640 instances: a job of 512 at lanes_v 4 and one of 128 at
+    # lanes_v 2, each with its own workspace region (no padded chunk)
+    w4 = api.workspace_bytes("square", 8, 5, 80, 8, "graph", {"lanes_v": 4})
+    w2 = api.workspace_bytes("square", 8, 5, 16, 8, "graph", {"lanes_v": 2})
+    w4a = api.workspace_bytes("square", 8, 5, 64, 8, "graph", {"lanes_v": 4})
+    assert w4 == -(-w4a // 256) * 256 + -(-w2 // 256) * 256
     # a batch's grouped gathers take the target orders (4, 6) but no LDS staging or op streams
     job = dict(lattice="square", m=4, n_max=3, q_points=[1, 2], primes=[P31])
     assert api.batch_workspace_bytes([job], tuning={"stage": 6}) == api.batch_workspace_bytes([job])
