@@ -1899,9 +1899,10 @@ struct GraphKey {
   uint32_t* out;
   int lattice, m, I, V, rpw, wpb, xcd, rows_per_graph;
   int cf_len;   // coefficient form: coefficients per row and prime (0: evaluation form)
+  int split = 0;  // instances of a lanes_v 4 split's second job (0: one job)
   bool operator<(const GraphKey& o) const {
-    return std::tie(ws, out, lattice, m, I, V, rpw, wpb, xcd, rows_per_graph, cf_len) <
-           std::tie(o.ws, o.out, o.lattice, o.m, o.I, o.V, o.rpw, o.wpb, o.xcd, o.rows_per_graph, o.cf_len);
+    return std::tie(ws, out, lattice, m, I, V, rpw, wpb, xcd, rows_per_graph, cf_len, split) <
+           std::tie(o.ws, o.out, o.lattice, o.m, o.I, o.V, o.rpw, o.wpb, o.xcd, o.rows_per_graph, o.cf_len, o.split);
   }
 };
 struct GraphEntry {
@@ -1977,6 +1978,101 @@ void run_graph(const JobCtx& j, int n_max, int* row_ctr, void* ws, hipStream_t s
     tail_pg.nchunk = j.L.nchunk;
     add_rows(tail_pg, j, n_max - tail, n_max - 1, -1, -1);
     run_eager(tail_pg, j.t, st);
+  }
+}
+
+// Graph row replay of a lanes_v 4 split (split_plan): both jobs' rows are
+// captured into ONE graph as parallel branches (the second forked from the
+// capture stream through a library stream and joined back), each job with
+// its own row counter.  Two graphs on two caller-visible streams would leave
+// their overlap to how the runtime maps streams to hardware queues; branches
+// of one graph do not depend on it.
+struct SplitStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+std::mutex g_split_cap_mu;
+SplitStream g_split_cap[64];
+
+void run_graph_split(const JobCtx& ja, const JobCtx& jb, int n_max, int* ctr_a, int* ctr_b, void* ws,
+                     hipStream_t st) {
+  const JobCtx* js[2] = {&ja, &jb};
+  int* ctrs[2] = {ctr_a, ctr_b};
+  for (int k = 0; k < 2; ++k) {
+    Program setup;
+    setup.nchunk = js[k]->L.nchunk;
+    (void)add_setup(setup, *js[k]);
+    run_eager(setup, js[k]->t, st);
+  }
+  if (n_max <= 1) return;
+  const int per = (static_cast<int>(ja.fam->fac.size()) % 2 == 1) ? 2 : 1;
+  const int rows = n_max - 1;
+  const int replays = rows / per;
+  const int tail = rows - replays * per;
+  for (int k = 0; k < 2; ++k) {
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, ctrs[k], 1);
+    HIPX(hipGetLastError());
+  }
+  if (replays > 0) {
+    GraphKey key{ws, ja.d_out, ja.L.lattice, ja.L.m, ja.L.I, ja.t.V, ja.t.rpw, ja.t.wpb,
+                 ja.t.stage * 10000 + ja.t.fuse * 1000 + ja.t.xcd * 100 + ja.t.U * 10 + ja.t.streams, per, 0,
+                 jb.L.I};
+    hipGraphExec_t exec = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(g_graph_mu);
+      auto it = g_graphs.find(key);
+      if (it != g_graphs.end()) exec = it->second.exec;
+    }
+    if (!exec) {
+      Program rows_pg[2];
+      for (int k = 0; k < 2; ++k) {
+        rows_pg[k].nchunk = js[k]->L.nchunk;
+        add_rows(rows_pg[k], *js[k], 1, per, -1, -1);
+        for (PStep& ps : rows_pg[k].steps)
+          if (ps.s.op == kOpReduce2) ps.s.u.r.out = js[k]->d_out;
+      }
+      std::lock_guard<std::mutex> lk(g_split_cap_mu);
+      int dev = 0;
+      HIPX(hipGetDevice(&dev));
+      SplitStream& cb = g_split_cap[dev];
+      if (!cb.s) {
+        HIPX(hipStreamCreateWithFlags(&cb.s, hipStreamNonBlocking));
+        HIPX(hipEventCreateWithFlags(&cb.fork, hipEventDisableTiming));
+        HIPX(hipEventCreateWithFlags(&cb.join, hipEventDisableTiming));
+      }
+      hipStream_t cs = capture_stream();
+      HIPX(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      HIPX(hipEventRecord(cb.fork, cs));
+      HIPX(hipStreamWaitEvent(cb.s, cb.fork, 0));
+      hipStream_t on[2] = {cs, cb.s};
+      for (int k = 0; k < 2; ++k) {
+        const size_t len = rows_pg[k].steps.size() / per;
+        for (int r = 0; r < per; ++r) {
+          Program one;
+          one.nchunk = rows_pg[k].nchunk;
+          one.steps.assign(rows_pg[k].steps.begin() + r * len, rows_pg[k].steps.begin() + (r + 1) * len);
+          run_eager(one, js[k]->t, on[k], true, ctrs[k], js[k]->out_row_stride);
+          hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, on[k], ctrs[k]);
+        }
+      }
+      HIPX(hipEventRecord(cb.join, cb.s));
+      HIPX(hipStreamWaitEvent(cs, cb.join, 0));
+      hipGraph_t graph = nullptr;
+      HIPX(hipStreamEndCapture(cs, &graph));
+      HIPX(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+      HIPX(hipGraphDestroy(graph));
+      std::lock_guard<std::mutex> lk2(g_graph_mu);
+      g_graphs[key] = GraphEntry{exec, 0};
+    }
+    for (int k = 0; k < replays; ++k) HIPX(hipGraphLaunch(exec, st));
+  }
+  if (tail > 0) {
+    for (int k = 0; k < 2; ++k) {
+      Program tail_pg;
+      tail_pg.nchunk = js[k]->L.nchunk;
+      add_rows(tail_pg, *js[k], n_max - tail, n_max - 1, -1, -1);
+      run_eager(tail_pg, js[k]->t, st);
+    }
   }
 }
 
@@ -2553,12 +2649,8 @@ size_t workspace_bytes(int lattice, int m, int I, int n_max_hint, int mode, cons
   return split_plan(lattice, m, I, n_max_hint, mode, t).bytes;
 }
 
-// The second job of a split runs on a library stream forked from and joined
-// back into the caller's (one per device).
-struct SplitStream {
-  hipStream_t s = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
-};
+// The second job of a split in batched mode runs on a library stream forked
+// from and joined back into the caller's (one per device).
 std::mutex g_split_mu;
 SplitStream g_split[64];
 
@@ -2618,8 +2710,8 @@ int strip_async_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, c
   }
   const SplitPlan sp = split_plan(lattice, m, I, n_max, mode, t);
   // job k: instances [i0, i0 + sp.I[k]) of the list, its own workspace
-  // region, output columns i0.. of rows of I
-  auto run_job = [&](int k, hipStream_t s) {
+  // region, output columns i0.. of rows of I; constants uploaded on `s`
+  auto make_job = [&](int k, hipStream_t s) {
     const int i0 = k == 0 ? 0 : sp.I[0];
     const std::vector<Inst> sub(inst.begin() + i0, inst.begin() + i0 + sp.I[k]);
     const Tune& tk = sp.t[k];
@@ -2635,7 +2727,21 @@ int strip_async_impl(int lattice, int m, int n_max, const uint32_t* q, int nq, c
     bind_staging(j, mode);
     std::vector<uint32_t> img = const_image(j.L, sub, j.fam->codes, j.fam->shift);
     upload(wk + j.L.p, img.data(), img.size() * 4, s);
-    int* row_ctr = reinterpret_cast<int*>(wk + j.L.bytes);
+    return j;
+  };
+  auto row_ctr_of = [&](int k, const JobCtx& j) {
+    return reinterpret_cast<int*>(static_cast<char*>(ws) + sp.off[k] + j.L.bytes);
+  };
+  if (sp.n == 2 && mode == CHROM_MODE_GRAPH) {
+    const JobCtx ja = make_job(0, st), jb = make_job(1, st);
+    run_graph_split(ja, jb, n_max, row_ctr_of(0, ja), row_ctr_of(1, jb), ws, st);
+    return CHROM_OK;
+  }
+  auto run_job = [&](int k, hipStream_t s) {
+    const JobCtx j = make_job(k, s);
+    const Tune& tk = j.t;
+    char* wk = static_cast<char*>(ws) + sp.off[k];
+    int* row_ctr = row_ctr_of(k, j);
     if (mode == CHROM_MODE_BATCHED) {
       Program pg = strip_program(j, n_max);
       run_eager(pg, tk, s);

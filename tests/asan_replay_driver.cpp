@@ -6,7 +6,9 @@
 //     on a fresh workspace, freed before the next (as the tuner's tensors);
 //  2. graph-mode strips of square m = 14 with 1-3 chunk groups over the
 //     target orders of stages 0, 4 and 6, single factors and fused pairs;
-//  3. resident strips (triangular m = 12, square m = 10) in both arithmetic
+//  3. lanes_v 4 strips split into a job of 512 and one of 128 instances
+//     (graph and batched modes, with the factor launches alone);
+//  4. resident strips (triangular m = 12, square m = 10) in both arithmetic
 //     forms, and the strip entry point that allocates nothing.
 // Prints one line per case; exits non-zero on the first library error.
 #include <cstdio>
@@ -75,6 +77,33 @@ int main(int argc, char** argv) {
             return 1;
           }
         printf("graph strip stage %d fuse %d streams %d ok\n", stage, f, s);
+        (void)hipFree(out);
+        (void)hipFree(ws);
+      }
+  // lanes_v 4 at 640 instances: a job of 512 and one of 128 (graph: one
+  // graph with two branches; batched: a forked library stream)
+  for (int mode : {CHROM_MODE_GRAPH, CHROM_MODE_BATCHED})
+    for (int stage : {0, 6})
+      for (int s : {1, 2}) {
+        chrom_tuning t{};
+        t.lanes_v = 4; t.targets_per_wave = 8; t.waves_per_block = 4; t.xcd_order = 4; t.unroll = 4;
+        t.streams = s; t.fuse = 2; t.stage = stage;
+        const size_t bytes = chromatic_workspace_bytes(CHROM_SQUARE, 14, 15, 80, 8, mode, &t);
+        if (!bytes) { printf("split workspace: %s\n", chromatic_last_error()); return 1; }
+        void* ws = dmalloc(bytes);
+        void* out = dmalloc(15u * 640u * 4u);
+        for (int r = 0; r < 1 + steps; ++r)
+          if (chromatic_strip_async(CHROM_SQUARE, 14, 15, q.data(), 80, primes, 8, mode, &t, ws, bytes, nullptr,
+                                    static_cast<uint32_t*>(out)) != CHROM_OK) {
+            printf("split strip: %s\n", chromatic_last_error());
+            return 1;
+          }
+        if (chromatic_factor_launches(CHROM_SQUARE, 14, q.data(), 80, primes, 8, 2, &t, ws, bytes, nullptr) !=
+            CHROM_OK) {
+          printf("split factor launches: %s\n", chromatic_last_error());
+          return 1;
+        }
+        printf("split strip mode %d stage %d streams %d ok\n", mode, stage, s);
         (void)hipFree(out);
         (void)hipFree(ws);
       }

@@ -98,6 +98,7 @@ def _build_and_replay(top, groups_on):
     assert sum(ln.startswith("batch ") for ln in lines) == 48
     assert sum(ln.startswith("graph strip") for ln in lines) == 18
     assert sum(ln.startswith("resident") for ln in lines) == 8
+    assert sum(ln.startswith("split strip") for ln in lines) == 8
     assert "ERROR: AddressSanitizer" not in r.stderr
 
 
