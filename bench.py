@@ -418,6 +418,49 @@ def bench_triangular_series(k):
             "seconds": dt, "primes_used": res["primes_used"], "matches_paper": match}
 
 
+def factor_leg(torch, stream, dev, lat, m, n, q, p, rtune, rows, sizes, s_nc, fuse):
+    """The factor launches of `rows` transfer rows of the strip over the
+    instances (q x p), one launch per fused factor step and job, one stream:
+    {ms, launches, avg_us, own_row, per_site_row, achieved, achieved_per_site}."""
+    from paper_1005_3609_amd import api
+    I = len(q) * len(p)
+    V = rtune.get("lanes_v") or 2
+    jobs = split_jobs(I, V)
+    ipad = padded_instances(I, V)
+    out = torch.zeros((n, len(q), len(p)), dtype=torch.int32, device=dev)
+    ws = api.alloc_workspace(api.workspace_bytes(lat, m, n, len(q), len(p), "batched", rtune), dev)
+    api.strip_async(lat, m, 1, q, p, mode="batched", tuning=rtune, workspace=ws, out=out, stream=stream)
+    api.factor_launches(lat, m, q, p, 1, ws, rtune, stream)
+    k_ms = timed(torch, stream, lambda: api.factor_launches(lat, m, q, p, rows, ws, rtune, stream))
+    del ws, out
+    nf = -(-m // fuse)
+    per_site_row = row_bytes(sizes, ipad, s_nc, len(jobs))
+    own_row = per_site_row if fuse == 1 else row_bytes(factor_sizes(lat, m, fuse, nf), ipad, s_nc, len(jobs))
+    launches = rows * nf * len(jobs)
+    return {"kernel": kernel_name(I, V, rtune.get("unroll") or 4), "instances": I, "ms": k_ms,
+            "launches": launches, "avg_us": k_ms * 1e3 / launches, "own_row": own_row,
+            "per_site_row": per_site_row, "achieved": rows * own_row / (k_ms / 1e3) / 1e9,
+            "achieved_per_site": rows * per_site_row / (k_ms / 1e3) / 1e9}
+
+
+def split_legs(torch, stream, dev, lat, m, n, q, p, rtune, rows, sizes, s_nc, fuse):
+    """(dominant, others): the factor leg of the kernel that carries the
+    strip.  With a lanes_v 4 split (instances past the last multiple of 256
+    as a second job), the dominant kernel is the first job's, timed alone on
+    its own instances; the second job alone and both one after the other are
+    the others."""
+    I = len(q) * len(p)
+    jobs = split_jobs(I, rtune.get("lanes_v") or 2)
+    if len(jobs) == 2 and jobs[0][0] % len(p) == 0:
+        na = jobs[0][0] // len(p)
+        dom = factor_leg(torch, stream, dev, lat, m, n, q[:na], p, rtune, rows, sizes, s_nc, fuse)
+        second = factor_leg(torch, stream, dev, lat, m, n, q[na:], p, dict(rtune, lanes_v=jobs[1][1]), rows,
+                            sizes, s_nc, fuse)
+        both = factor_leg(torch, stream, dev, lat, m, n, q, p, rtune, rows, sizes, s_nc, fuse)
+        return dom, {"second_job": second, "both_jobs_one_stream": both}
+    return factor_leg(torch, stream, dev, lat, m, n, q, p, rtune, rows, sizes, s_nc, fuse), {}
+
+
 def bench_m18(torch, stream, tune, rows):
     """The square 18x19 strip with the workload's 640 instances: one vector is
     8.2 GB, far beyond the 256 MB Infinity Cache, so the factor kernel's
@@ -456,15 +499,8 @@ def bench_m18(torch, stream, tune, rows):
     assert (res[:, 0, :] == 0).all() and (res[:, 1, :] == 2).all(), "invariants P(1)=0, P(2)=2 failed at m=18"
     del ws
     rtune = dict(tune, streams=1)
-    ws_b = api.alloc_workspace(api.workspace_bytes(lat, m, n, len(q), len(p), "batched", rtune), dev)
-    api.strip_async(lat, m, 1, q, p, mode="batched", tuning=rtune, workspace=ws_b, out=out, stream=stream)
-    api.factor_launches(lat, m, q, p, 1, ws_b, rtune, stream)
-    k_ms = timed(torch, stream, lambda: api.factor_launches(lat, m, q, p, rows, ws_b, rtune, stream))
-    del ws_b
-    nf = -(-m // fuse)
-    per_site_row = row_bytes(sizes, ipad, s_nc, nj)
-    own_row = per_site_row if fuse == 1 else row_bytes(factor_sizes(lat, m, fuse, nf), ipad, s_nc, nj)
-    achieved = rows * own_row / (k_ms / 1e3) / 1e9
+    dom, others = split_legs(torch, stream, dev, lat, m, n, q, p, rtune, rows, sizes, s_nc, fuse)
+    achieved = dom["achieved"]
     # one (q, p) instance through the plain path, two rows
     q1, p1 = q[:1], p[:1]
     ws_p = api.alloc_workspace(api.workspace_bytes(lat, m, 3, 1, 1, "plain"), dev)
@@ -481,11 +517,12 @@ def bench_m18(torch, stream, tune, rows):
             "maps_build_s": maps_s, "ms_per_strip": ms,
             "value": written_of(lat, m, n, I, fuse) / (ms / 1e3), "unit": "state-updates/s (residues written)",
             "per_site_factor_updates_per_s": updates_of(lat, m, n, I) / (ms / 1e3),
-            "factor_kernel": {"kernel": kernel_name(I, V, tune.get("unroll") or 4), "rows_timed": rows,
-                              "launches": rows * nf * nj, "avg_launch_us": k_ms * 1e3 / (rows * nf * nj),
+            "factor_kernel": {"kernel": dom["kernel"], "instances": dom["instances"], "rows_timed": rows,
+                              "launches": dom["launches"], "avg_launch_us": dom["avg_us"],
                               "achieved_GBs": achieved, "frac_of_hbm_peak": achieved / HBM_PEAK_GBS,
-                              "own_min_bytes_per_row": own_row, "per_site_bytes_per_row": per_site_row,
-                              "frac_per_site": rows * per_site_row / (k_ms / 1e3) / 1e9 / HBM_PEAK_GBS},
+                              "own_min_bytes_per_row": dom["own_row"], "per_site_bytes_per_row": dom["per_site_row"],
+                              "frac_per_site": dom["achieved_per_site"] / HBM_PEAK_GBS,
+                              **{k: {kk: vv for kk, vv in v.items()} for k, v in others.items()}},
             "plain_single_instance": {"rows": 2, "ms": p_ms,
                                       "value": updates_of(lat, m, 3, 1) / (p_ms / 1e3),
                                       "algorithmic_GBs": p_bytes / (p_ms / 1e3) / 1e9,
@@ -643,25 +680,22 @@ def main():
     # kernel trace reports for this launch shape.
     del ws
     rtune = dict(tune, streams=1)
-    ws_b = api.alloc_workspace(api.workspace_bytes(lat, m, n, len(q), len(p), "batched", rtune), dev)
-    api.strip_async(lat, m, n, q, p, mode="batched", tuning=rtune, workspace=ws_b, out=out, stream=stream)
-    api.factor_launches(lat, m, q, p, 2, ws_b, rtune, stream)
     R = args.roofline_rows
-    k_ms = timed(torch, stream, lambda: api.factor_launches(lat, m, q, p, R, ws_b, rtune, stream))
-    nf = -(-m // fuse)
-    launches = R * nf * nj
-    avg_us = k_ms * 1e3 / launches
-    per_site_row = row_bytes(sizes, ipad, s_nc, nj)
-    own_row = per_site_row if fuse == 1 else row_bytes(factor_sizes(lat, m, fuse, nf), ipad, s_nc, nj)
-    achieved = R * own_row / (k_ms / 1e3) / 1e9
-    achieved_per_site = R * per_site_row / (k_ms / 1e3) / 1e9
+    dom, others = split_legs(torch, stream, dev, lat, m, n, q, p, rtune, R, sizes, s_nc, fuse)
+    launches, avg_us, achieved = dom["launches"], dom["avg_us"], dom["achieved"]
+    achieved_per_site = dom["achieved_per_site"]
+    own_row_all = row_bytes(factor_sizes(lat, m, fuse, -(-m // fuse)) if fuse > 1 else sizes, ipad, s_nc, nj)
+    per_site_row, own_row = dom["per_site_row"], dom["own_row"]
     # the headline step itself: every gather launch's own minimum bytes of the
     # n - 1 transfer rows over the timed step (its other kernels included)
-    achieved_step = (n - 1) * own_row / (ms_per_step / 1e3) / 1e9
-    kname = kernel_name(I, V, tune.get("unroll") or 4)
-    log(f"factor kernel {kname}: {launches} launches, avg {avg_us:.1f} us, {achieved:.0f} GB/s of the launches' "
-        f"own minimum traffic ({achieved_per_site:.0f} GB/s counting every per-site factor's reads and writes)")
-    del ws_b
+    achieved_step = (n - 1) * own_row_all / (ms_per_step / 1e3) / 1e9
+    kname = dom["kernel"]
+    log(f"factor kernel {kname} ({dom['instances']} instances): {launches} launches, avg {avg_us:.1f} us, "
+        f"{achieved:.0f} GB/s of the launches' own minimum traffic ({achieved_per_site:.0f} GB/s counting every "
+        f"per-site factor's reads and writes)")
+    for k, v in others.items():
+        log(f"  {k}: {v['kernel']} ({v['instances']} instances), avg {v['avg_us']:.1f} us per launch, "
+            f"{v['achieved']:.0f} GB/s")
 
     # ---- plain per-instance path on a subset of the instances -------------
     plain = None
@@ -745,7 +779,9 @@ def main():
                                             "intermediate ones a fused launch never writes"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname, rtune, wname),
-                     "kernel": kname, "avg_launch_us": avg_us, "launches_timed": launches,
+                     "kernel": kname, "instances": dom["instances"], "avg_launch_us": avg_us,
+                     "launches_timed": launches,
+                     **({"other_legs": others} if others else {}),
                      "bytes": "each launch's own minimum: its input and output vectors once, its map, "
                               "and the read-out vector with the last launch of a row",
                      "own_min_bytes_per_row": own_row, "per_site_bytes_per_row": per_site_row,
