@@ -87,8 +87,12 @@ enum {
  * choice gives bit-identical results. */
 typedef struct chrom_tuning {
   int lanes_v;          /* instances per lane: 1, 2 or 4 (chunk width W = 64 * lanes_v);
-                           the coefficient form also takes 8, with unroll 4; resident
-                           mode: instances per workgroup */
+                           batched and graph modes at 4: when the instance count is not
+                           a multiple of 256, the instances past the last multiple run
+                           as a second job at 2 (1 for at most 64) beside the first (in
+                           graph mode a parallel branch of the same graph) instead of a
+                           padded chunk; the coefficient form also takes 8, with unroll
+                           4; resident mode: instances per workgroup */
   int targets_per_wave; /* consecutive target states handled by one wavefront, 1..63 */
   int waves_per_block;  /* wavefronts per workgroup: 1, 2, 4 or 8 (resident mode also 16) */
   int xcd_order;        /* 0 = default, 1 = hardware round-robin, 2 = contiguous tile range per XCD,
