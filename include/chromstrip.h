@@ -132,7 +132,9 @@ typedef struct chrom_tuning {
  * Whole-strip calls
  * ---------------------------------------------------------------------- */
 
-/* Plain per-instance path, synchronous.  q_points[nq], primes[np] and
+/* Z_{m x r} = <e0| T_last T^{r-1} |e0> for r = 1..n_max (Sec. 3, eq.
+ * Z_from_T; factors of Sec. 3.2-3.3), one instance at a time.  Plain
+ * per-instance path, synchronous.  q_points[nq], primes[np] and
  * out[n_max*nq*np] are host memory.  Allocates device memory internally and
  * runs on the null stream of the current device. */
 int chromatic_strip(int lattice, int m, int n_max,
@@ -140,9 +142,11 @@ int chromatic_strip(int lattice, int m, int n_max,
                     const uint32_t* primes, int np,
                     uint32_t* out);
 
-/* Same result through the batched path (mode CHROM_MODE_BATCHED, GRAPH,
- * RESIDENT or GROUPED), synchronous, host buffers, internal allocation.
- * tune may be NULL. */
+/* The same Z_{m x r} (eq. Z_from_T) with all instances in shared launches:
+ * each factor T_i (eq. T_sq_decomp; Sec. 3.3) applied to every instance's
+ * state vector by one launch per step, residues mod p (Sec. 3.5).  Mode
+ * CHROM_MODE_BATCHED, GRAPH, RESIDENT or GROUPED; synchronous, host
+ * buffers, internal allocation.  tune may be NULL. */
 int chromatic_strip_batched(int lattice, int m, int n_max,
                             const uint32_t* q_points, int nq,
                             const uint32_t* primes, int np,
@@ -150,8 +154,11 @@ int chromatic_strip_batched(int lattice, int m, int n_max,
                             uint32_t* out);
 
 /* Device-workspace size in bytes needed by chromatic_strip_async for the
- * same arguments (the grouped mode's stage tables grow with n_max).
- * Returns 0 on bad arguments. */
+ * same arguments: two state vectors over the largest space between factors
+ * (NCNNN or square-intermediate states, Sec. 3.4), the read-out vector of
+ * eq. T_last, per-instance constants and read-out partials.  It depends on
+ * mode and tuning (chunk width, fused products, the grouped mode's stage
+ * tables, which grow with n_max).  Returns 0 on bad arguments. */
 size_t chromatic_workspace_bytes(int lattice, int m, int n_max, int nq, int np,
                                  int mode, const chrom_tuning* tune);
 
@@ -191,7 +198,9 @@ int chromatic_series(int lattice, int m, int n_max, int d_max,
                      const uint32_t* primes, int np, int mode,
                      const chrom_tuning* tune, uint32_t* out);
 
-/* Asynchronous strip on `stream` (a hipStream_t; NULL = null stream).
+/* Z_{m x r}, r = 1..n_max (eq. Z_from_T), as chromatic_strip_batched, but
+ * queued on `stream` (a hipStream_t; NULL = null stream) with a
+ * caller-owned workspace.
  * q_points/primes: host memory, read before return.  d_workspace: device
  * memory of at least chromatic_workspace_bytes(...) bytes, 256-byte
  * aligned, owned by the caller and not used by anything else until the
@@ -246,7 +255,8 @@ int chromatic_factor_launches(int lattice, int m,
                               void* d_workspace, size_t ws_bytes, void* stream);
 
 /* Builds (host) and uploads (current device) the factor maps of
- * (lattice, m) ahead of time, so that later calls do no host work. */
+ * (lattice, m) ahead of time (the CSR forms of T_i and T_i^last, Sec.
+ * 3.2-3.4), so that later calls do no host work. */
 int chromatic_prepare(int lattice, int m);
 
 /* Builds the host copy of the factor maps of (lattice, m) only, in the
@@ -305,11 +315,14 @@ typedef struct chrom_job {
   uint32_t* d_out;           /* device, [n_max][nq][np] */
 } chrom_job;
 
-/* Workspace bytes for chromatic_batch over these jobs. */
+/* Workspace bytes for chromatic_batch over these jobs (each job's vectors
+ * as for chromatic_workspace_bytes, plus the stage tables of the grouped
+ * launches). */
 size_t chromatic_batch_workspace_bytes(const chrom_job* jobs, int njobs,
                                        const chrom_tuning* tune);
 
-/* Runs every job to completion on `stream` as ONE hipGraph launch: each job
+/* Z_{m x r} of every job (eq. Z_from_T, factors of Sec. 3.2-3.3, residues
+ * of Sec. 3.5), to completion on `stream` as ONE hipGraph launch: each job
  * is split into instance chunks of width 64*lanes_v, and step k of every
  * (job, chunk) item runs in one grouped kernel launch whose workgroups map
  * to (item, tile) pairs, so jobs of uneven state-space size share every
@@ -340,11 +353,15 @@ typedef struct chrom_slot {
 } chrom_slot;
 
 /* Device bytes a job keeps resident between server steps (two state
- * vectors, the read-out vector, coefficient tables, scratch). */
+ * vectors over the spaces of Sec. 3.4, the read-out vector of eq. T_last,
+ * coefficient tables, scratch). */
 size_t chromatic_slot_state_bytes(int lattice, int m, int nq, int np,
                                   const chrom_tuning* tune);
 
-/* Advances every slot by up to `rows` rows (a new slot first runs its
+/* Continuous batching of strips: the next rows of each slot's Z_{m x r}
+ * (one application of T = T_m ... T_1 and one read-out per row, eqs.
+ * T_sq_decomp, Z_from_T).  Advances every slot by up to `rows` rows (a new
+ * slot first runs its
  * set-up and reads out r = 1) on `stream`, and updates rows_done.  Step k of
  * every slot runs in one grouped launch, so slots that differ in lattice, m
  * and instance count share each launch.  tune->stage: 0, 4 or 6 as for
