@@ -1891,8 +1891,9 @@ void run_eager(const Program& pg, const Tune& t, hipStream_t st, bool capture = 
 }
 
 // ---------------------------------------------------------------------------
-// hipGraph row sweep: one row (two when m is odd, so the ping-pong buffers
-// return to their start) captured once and replayed
+// hipGraph row sweep: a run of rows (rows_per_graph) captured once and
+// replayed; every chunk group is a chain of its own from the start of a
+// replay to its end
 // ---------------------------------------------------------------------------
 struct GraphKey {
   void* ws;
@@ -1920,6 +1921,64 @@ hipStream_t capture_stream() {
   return g_capture_stream[dev];
 }
 
+// One chain of a captured row replay: the rows of one chunk group of one
+// job, on its own stream, with its own row counter.
+struct RowChain {
+  const JobCtx* j;
+  const Program* rows;   // `per` rows, equal lengths
+  int c0, nch;
+  int* ctr;
+  hipStream_t s;
+};
+
+// Records `per` rows of every chain, step by step across the chains, each
+// row ending in a bump of that chain's own counter.  Chains never wait for
+// one another: a chunk group reads and writes only its own chunks, and the
+// counted read-out kernels read its own counter.
+void record_chains(const std::vector<RowChain>& ch, int per) {
+  for (int r = 0; r < per; ++r) {
+    size_t most = 0;
+    for (const RowChain& c : ch) most = std::max(most, c.rows->steps.size() / per);
+    for (size_t i = 0; i < most; ++i)
+      for (const RowChain& c : ch) {
+        const size_t len = c.rows->steps.size() / per;
+        if (i < len)
+          launch_step(c.rows->steps[r * len + i].s, c.j->t, c.c0, c.nch, c.s, c.ctr, c.j->out_row_stride);
+      }
+    for (const RowChain& c : ch) hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, c.s, c.ctr);
+    HIPX(hipGetLastError());
+  }
+}
+
+// The chains of job `j` (one per chunk group; group g counts rows in
+// ctr[g]): group 0 on `s0`, group g > 0 on the capture set's auxiliary
+// stream g - 1.
+void add_chains(std::vector<RowChain>& ch, const JobCtx& j, const Program& rows, int* ctr, hipStream_t s0,
+                const AuxStreams& a) {
+  const ChunkGroups g = chunk_groups(j.L.nchunk, j.t.streams);
+  for (int k = 0; k < g.n; ++k) ch.push_back(RowChain{&j, &rows, g.c0[k], g.nch[k], ctr + k, k ? a.s[k - 1] : s0});
+}
+
+// Sets the row counter of every chunk group of `j` to 1.
+void reset_row_counters(const JobCtx& j, int* ctr, hipStream_t st) {
+  const ChunkGroups g = chunk_groups(j.L.nchunk, j.t.streams);
+  for (int k = 0; k < g.n; ++k) hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, ctr + k, 1);
+  HIPX(hipGetLastError());
+}
+
+// Rows per captured graph: a multiple of the rows after which the ping-pong
+// vectors return to their start (two when a row has an odd number of
+// launches).  The evaluation form captures up to kGraphRows rows at once, so
+// that the chunk groups' chains run independently across those rows instead
+// of meeting at every replay's end; the coefficient form, whose drivers call
+// strips of many heights on one workspace, keeps one period per graph.
+constexpr int kGraphRows = 32;
+int rows_per_graph(const JobCtx& j, int rows) {
+  const int base = (static_cast<int>(j.fam->fac.size()) % 2 == 1) ? 2 : 1;
+  if (j.L.cf) return base;
+  return std::max(base, std::min(rows, kGraphRows) / base * base);
+}
+
 void run_graph(const JobCtx& j, int n_max, int* row_ctr, void* ws, hipStream_t st) {
   Program setup;
   setup.nchunk = j.L.nchunk;
@@ -1927,12 +1986,11 @@ void run_graph(const JobCtx& j, int n_max, int* row_ctr, void* ws, hipStream_t s
   (void)red;
   run_eager(setup, j.t, st);
   if (n_max <= 1) return;
-  const int per = (static_cast<int>(j.fam->fac.size()) % 2 == 1) ? 2 : 1;
   const int rows = n_max - 1;
+  const int per = rows_per_graph(j, rows);
   const int replays = rows / per;
   const int tail = rows - replays * per;
-  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, row_ctr, 1);
-  HIPX(hipGetLastError());
+  reset_row_counters(j, row_ctr, st);
   if (replays > 0) {
     GraphKey key{ws, j.d_out, j.L.lattice, j.L.m, j.L.I, j.t.V, j.t.rpw, j.t.wpb,
                  j.t.stage * 10000 + j.t.fuse * 1000 + j.t.xcd * 100 + j.t.U * 10 + j.t.streams, per,
@@ -1948,21 +2006,24 @@ void run_graph(const JobCtx& j, int n_max, int* row_ctr, void* ws, hipStream_t s
       rows_pg.nchunk = j.L.nchunk;
       // rows 1..per starting from the parity of row 1 (x in x0)
       add_rows(rows_pg, j, 1, per, -1, -1);
-      // reduce2 writes the row given by the device counter; k_bump advances
-      // it once every chunk group has written
+      // reduce2 and emit write the row given by their chunk group's device
+      // counter, which the group's chain advances after each of its rows
       for (PStep& ps : rows_pg.steps) {
         if (ps.s.op == kOpReduce2) ps.s.u.r.out = j.d_out;
         if (ps.s.op == kOpEmit) ps.s.u.e.dst = j.d_out;
       }
+      std::lock_guard<std::mutex> lk_aux(g_aux_mu);
+      AuxStreams& a = aux_streams(true);
+      std::vector<RowChain> ch;
       hipStream_t cs = capture_stream();
+      add_chains(ch, j, rows_pg, row_ctr, cs, a);
       HIPX(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-      for (int r = 0; r < per; ++r) {
-        Program one;
-        one.nchunk = rows_pg.nchunk;
-        const size_t len = rows_pg.steps.size() / per;
-        one.steps.assign(rows_pg.steps.begin() + r * len, rows_pg.steps.begin() + (r + 1) * len);
-        run_eager(one, j.t, cs, true, row_ctr, j.out_row_stride);
-        hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, cs, row_ctr);
+      if (ch.size() > 1) HIPX(hipEventRecord(a.fork, cs));
+      for (size_t k = 1; k < ch.size(); ++k) HIPX(hipStreamWaitEvent(ch[k].s, a.fork, 0));
+      record_chains(ch, per);
+      for (size_t k = 1; k < ch.size(); ++k) {
+        HIPX(hipEventRecord(a.join[k - 1], ch[k].s));
+        HIPX(hipStreamWaitEvent(cs, a.join[k - 1], 0));
       }
       hipGraph_t graph = nullptr;
       HIPX(hipStreamEndCapture(cs, &graph));
@@ -1983,8 +2044,8 @@ void run_graph(const JobCtx& j, int n_max, int* row_ctr, void* ws, hipStream_t s
 
 // Graph row replay of a lanes_v 4 split (split_plan): both jobs' rows are
 // captured into ONE graph as parallel branches (the second forked from the
-// capture stream through a library stream and joined back), each job with
-// its own row counter.  Two graphs on two caller-visible streams would leave
+// capture stream through a library stream and joined back), each chunk
+// group of each job a chain with its own row counter.  Two graphs on two caller-visible streams would leave
 // their overlap to how the runtime maps streams to hardware queues; branches
 // of one graph do not depend on it.
 struct SplitStream {
@@ -2005,14 +2066,11 @@ void run_graph_split(const JobCtx& ja, const JobCtx& jb, int n_max, int* ctr_a, 
     run_eager(setup, js[k]->t, st);
   }
   if (n_max <= 1) return;
-  const int per = (static_cast<int>(ja.fam->fac.size()) % 2 == 1) ? 2 : 1;
   const int rows = n_max - 1;
+  const int per = rows_per_graph(ja, rows);
   const int replays = rows / per;
   const int tail = rows - replays * per;
-  for (int k = 0; k < 2; ++k) {
-    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, ctrs[k], 1);
-    HIPX(hipGetLastError());
-  }
+  for (int k = 0; k < 2; ++k) reset_row_counters(*js[k], ctrs[k], st);
   if (replays > 0) {
     GraphKey key{ws, ja.d_out, ja.L.lattice, ja.L.m, ja.L.I, ja.t.V, ja.t.rpw, ja.t.wpb,
                  ja.t.stage * 10000 + ja.t.fuse * 1000 + ja.t.xcd * 100 + ja.t.U * 10 + ja.t.streams, per, 0,
@@ -2032,6 +2090,7 @@ void run_graph_split(const JobCtx& ja, const JobCtx& jb, int n_max, int* ctr_a, 
           if (ps.s.op == kOpReduce2) ps.s.u.r.out = js[k]->d_out;
       }
       std::lock_guard<std::mutex> lk(g_split_cap_mu);
+      std::lock_guard<std::mutex> lk_aux(g_aux_mu);
       int dev = 0;
       HIPX(hipGetDevice(&dev));
       SplitStream& cb = g_split_cap[dev];
@@ -2040,20 +2099,22 @@ void run_graph_split(const JobCtx& ja, const JobCtx& jb, int n_max, int* ctr_a, 
         HIPX(hipEventCreateWithFlags(&cb.fork, hipEventDisableTiming));
         HIPX(hipEventCreateWithFlags(&cb.join, hipEventDisableTiming));
       }
+      AuxStreams& a = aux_streams(true);
       hipStream_t cs = capture_stream();
+      // the first job's chunk groups on the capture stream and the auxiliary
+      // streams, the second job (one group) on the library stream
+      std::vector<RowChain> ch;
+      add_chains(ch, ja, rows_pg[0], ctrs[0], cs, a);
+      const size_t na = ch.size();
+      add_chains(ch, jb, rows_pg[1], ctrs[1], cb.s, a);
+      if (ch.size() != na + 1) throw std::runtime_error("the second job of a split runs one chunk group");
       HIPX(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       HIPX(hipEventRecord(cb.fork, cs));
-      HIPX(hipStreamWaitEvent(cb.s, cb.fork, 0));
-      hipStream_t on[2] = {cs, cb.s};
-      for (int k = 0; k < 2; ++k) {
-        const size_t len = rows_pg[k].steps.size() / per;
-        for (int r = 0; r < per; ++r) {
-          Program one;
-          one.nchunk = rows_pg[k].nchunk;
-          one.steps.assign(rows_pg[k].steps.begin() + r * len, rows_pg[k].steps.begin() + (r + 1) * len);
-          run_eager(one, js[k]->t, on[k], true, ctrs[k], js[k]->out_row_stride);
-          hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, on[k], ctrs[k]);
-        }
+      for (size_t k = 1; k < ch.size(); ++k) HIPX(hipStreamWaitEvent(ch[k].s, cb.fork, 0));
+      record_chains(ch, per);
+      for (size_t k = 1; k < na; ++k) {
+        HIPX(hipEventRecord(a.join[k - 1], ch[k].s));
+        HIPX(hipStreamWaitEvent(cs, a.join[k - 1], 0));
       }
       HIPX(hipEventRecord(cb.join, cb.s));
       HIPX(hipStreamWaitEvent(cs, cb.join, 0));
