@@ -213,7 +213,8 @@ def bench_sweep(torch, stream, tune, steps):
     from paper_1005_3609_amd import tune as tuner
     t = tuner.lookup_tuned_batch("square_sweep_2_14") or dict(tune)
     t = {k: v for k, v in t.items() if k not in ("mode", "ms", "streams")}
-    outs, ws = api.batch(jobs, tuning=t, stream=stream)
+    outs, ws = api.batch(jobs, tuning=t, stream=stream)          # capture
+    api.batch(jobs, tuning=t, workspace=ws, outs=outs, stream=stream)  # one warm replay, untimed
     ms = timed(torch, stream, lambda: api.batch(jobs, tuning=t, workspace=ws, outs=outs, stream=stream), steps)
     I = len(w["q_points"]) * len(w["primes"])
     upd = sum(updates_of(lat, m, n, I) for lat, m, n in w["strips"])
@@ -231,7 +232,8 @@ def _strip_leg(torch, stream, lat, m, n, q, p, mode, t, steps):
 
     def run():
         api.strip_async(lat, m, n, q, p, mode=mode, tuning=t, workspace=ws, out=res, stream=stream)
-    run()
+    run()                                     # capture (graph mode)
+    run()                                     # one warm replay, untimed
     ms = timed(torch, stream, run, steps)
     return ms, api.to_u32(res).astype("int64").reshape(n, len(q), len(p))
 
@@ -321,6 +323,7 @@ def bench_series(torch, stream, tune, steps):
     t["lanes_v"] = 2
     dev = torch.device("cuda", torch.cuda.current_device())
     out, ws = api.series_async(lat, m, n, d, primes, mode="graph", tuning=t, stream=stream, device=dev)
+    api.series_async(lat, m, n, d, primes, mode="graph", tuning=t, workspace=ws, out=out, stream=stream)  # warm
     ms = timed(torch, stream, lambda: api.series_async(lat, m, n, d, primes, mode="graph", tuning=t,
                                                        workspace=ws, out=out, stream=stream), steps)
     res = api.to_u32(out).astype("int64").reshape(n, len(primes), d + 1)
