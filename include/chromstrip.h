@@ -72,9 +72,9 @@ enum { CHROM_SQUARE = 0, CHROM_TRIANGULAR = 1 };
 enum {
   CHROM_MODE_PLAIN = 0,      /* per-instance vectors [S], one launch per factor per instance */
   CHROM_MODE_BATCHED = 1,    /* instance-minor vectors, one launch per factor for all instances */
-  CHROM_MODE_GRAPH = 2,      /* as BATCHED, the rows captured in a hipGraph (up to 32 per graph,
-                                one or two for the coefficient form) and replayed; each chunk
-                                group runs its rows as an independent chain */
+  CHROM_MODE_GRAPH = 2,      /* as BATCHED, the rows captured in a hipGraph (up to 32 per graph)
+                                and replayed; each chunk group runs its rows as an independent
+                                chain */
   CHROM_MODE_RESIDENT = 3,   /* the whole strip in ONE launch: each workgroup keeps the state
                                 vectors of lanes_v instances in LDS and runs every factor
                                 (Sec. 3.2-3.3) and row read-out (eq. Z_from_T) with workgroup

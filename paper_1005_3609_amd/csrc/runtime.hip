@@ -1968,14 +1968,11 @@ void reset_row_counters(const JobCtx& j, int* ctr, hipStream_t st) {
 
 // Rows per captured graph: a multiple of the rows after which the ping-pong
 // vectors return to their start (two when a row has an odd number of
-// launches).  The evaluation form captures up to kGraphRows rows at once, so
-// that the chunk groups' chains run independently across those rows instead
-// of meeting at every replay's end; the coefficient form, whose drivers call
-// strips of many heights on one workspace, keeps one period per graph.
+// launches), up to kGraphRows, so that the chunk groups' chains run
+// independently across those rows instead of meeting at every replay's end.
 constexpr int kGraphRows = 32;
 int rows_per_graph(const JobCtx& j, int rows) {
   const int base = (static_cast<int>(j.fam->fac.size()) % 2 == 1) ? 2 : 1;
-  if (j.L.cf) return base;
   return std::max(base, std::min(rows, kGraphRows) / base * base);
 }
 
