@@ -154,6 +154,30 @@ def test_lanes_v4_instance_split(nq):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("lat,m,np_", [("square", 5, 8), ("triangular", 4, 3)])
+def test_graph_mode_long_strips(lat, m, np_):
+    # 69 rows: graphs of up to 32 rows (a multiple of two when a row has an
+    # odd number of launches) replayed twice, the remaining rows run eagerly
+    # after them; every chunk group is a chain with its own row counter, and
+    # 41 x 8 = 328 instances split at lanes_v 4.  Every row equals the oracle,
+    # on the first call (capture) and on a replay of the cached graphs.
+    import torch
+    q = list(range(1, 42))
+    p = [P31, 998244353, 1000000007, 2147483629, 2147483587, 1000000009, 998244853, 2147483563][:np_]
+    want = OT.chromatic_grid(lat, m, 70, q, p)
+    for tune in (dict(lanes_v=4, streams=2, fuse=2, stage=6, targets_per_wave=8),
+                 dict(lanes_v=2, streams=3, fuse=1),
+                 dict(lanes_v=1, streams=2, fuse=3, stage=4)):
+        out, ws = api.strip_async(lat, m, 70, q, p, mode="graph", tuning=tune)
+        for call in range(2):
+            if call:
+                out.zero_()
+                api.strip_async(lat, m, 70, q, p, mode="graph", tuning=tune, workspace=ws, out=out)
+            torch.cuda.synchronize()
+            got = api.to_u32(out).astype(np.int64).reshape(70, len(q), len(p))
+            np.testing.assert_array_equal(got, want, err_msg=f"{lat} {m} {tune} call {call}")
+
+
 def test_edge_cases():
     # m = 1 paths, n_max = 1, one instance, q >= p, q = 0
     for lat in ("square", "triangular"):
