@@ -1921,6 +1921,11 @@ hipStream_t capture_stream() {
   return g_capture_stream[dev];
 }
 
+// Held across every capture on a capture stream: two host threads capturing
+// on one stream at once would record into one graph.  Taken before any other
+// lock a capture needs (split stream, auxiliary streams, graph caches).
+std::mutex g_capture_mu;
+
 // One chain of a captured row replay: the rows of one chunk group of one
 // job, on its own stream, with its own row counter.
 struct RowChain {
@@ -2009,6 +2014,7 @@ void run_graph(const JobCtx& j, int n_max, int* row_ctr, void* ws, hipStream_t s
         if (ps.s.op == kOpReduce2) ps.s.u.r.out = j.d_out;
         if (ps.s.op == kOpEmit) ps.s.u.e.dst = j.d_out;
       }
+      std::lock_guard<std::mutex> lk_cap(g_capture_mu);
       std::lock_guard<std::mutex> lk_aux(g_aux_mu);
       AuxStreams& a = aux_streams(true);
       std::vector<RowChain> ch;
@@ -2086,6 +2092,7 @@ void run_graph_split(const JobCtx& ja, const JobCtx& jb, int n_max, int* ctr_a, 
         for (PStep& ps : rows_pg[k].steps)
           if (ps.s.op == kOpReduce2) ps.s.u.r.out = js[k]->d_out;
       }
+      std::lock_guard<std::mutex> lk_cap(g_capture_mu);
       std::lock_guard<std::mutex> lk(g_split_cap_mu);
       std::lock_guard<std::mutex> lk_aux(g_aux_mu);
       int dev = 0;
@@ -2317,6 +2324,7 @@ void run_grouped(const std::vector<const Program*>& progs, const Tune& t, void* 
     }
   }
   if (!exec) {
+    std::lock_guard<std::mutex> lk_cap(g_capture_mu);
     hipStream_t cs = capture_stream();
     HIPX(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     launch_all(cs, true);

@@ -9,8 +9,11 @@
 #include <hip/hip_runtime_api.h>
 
 #include <atomic>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
+#include <set>
 
 extern "C" {
 char HIP_FATBIN_SYMBOL[64] = {0};
@@ -36,8 +39,26 @@ hipError_t hipEventSynchronize(hipEvent_t e) { (void)obj(e); return hipSuccess; 
 hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned int) { *s = reinterpret_cast<hipStream_t>(new int(0)); return hipSuccess; }
 hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
 hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t e, unsigned int) { (void)obj(e); return hipSuccess; }
-hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode) { return hipSuccess; }
-hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t* g) { *g = reinterpret_cast<hipGraph_t>(new int(1)); return hipSuccess; }
+// Streams being captured: a capture begun on a stream that is already
+// capturing (two host threads recording into one graph) aborts the replay.
+static std::mutex g_cap_mu;
+static std::set<hipStream_t>* g_capturing = new std::set<hipStream_t>;
+hipError_t hipStreamBeginCapture(hipStream_t s, hipStreamCaptureMode) {
+  std::lock_guard<std::mutex> lk(g_cap_mu);
+  if (!g_capturing->insert(s).second) {
+    fprintf(stderr, "HIP stand-in: a capture began on a stream that is already capturing\n");
+    abort();
+  }
+  return hipSuccess;
+}
+hipError_t hipStreamEndCapture(hipStream_t s, hipGraph_t* g) {
+  {
+    std::lock_guard<std::mutex> lk(g_cap_mu);
+    g_capturing->erase(s);
+  }
+  *g = reinterpret_cast<hipGraph_t>(new int(1));
+  return hipSuccess;
+}
 hipError_t hipGraphInstantiate(hipGraphExec_t* x, hipGraph_t g, hipGraphNode_t*, char*, size_t) {
   (void)obj(g);
   *x = reinterpret_cast<hipGraphExec_t>(new int(2));

@@ -14,7 +14,9 @@ fork/join are replayed too.  Under ThreadSanitizer, ``tsan_replay_driver.cpp``
 builds the coefficient form's host maps on a second thread while the main
 thread runs coefficient-form strips (the concurrent use that preceded a
 crash in Python's garbage collector on the GPU machine): no data race may be
-reported.
+reported.  ``tsan_capture_driver.cpp`` has three threads capture graph-mode,
+grouped and coefficient-form strips at once; the stand-in aborts when a
+capture begins on a stream that is already capturing.
 """
 import os
 import shutil
@@ -118,3 +120,17 @@ def test_concurrent_host_map_builds_are_race_free_under_tsan(tmp_path):
         assert r.stdout.splitlines()[-1] == "done"
         assert sum(ln.startswith("series m") for ln in r.stdout.splitlines()) == m_hi
         assert "WARNING: ThreadSanitizer" not in r.stderr
+
+
+@pytest.mark.skipif(not (os.path.exists(HIPCC) and os.path.exists(CLANG)) or _san_runtime("tsan") is None,
+                    reason="needs hipcc and clang's ThreadSanitizer runtime")
+def test_concurrent_graph_captures_are_serialised(tmp_path):
+    # three host threads capture graph-mode, grouped and coefficient-form
+    # strips at once; the stand-in aborts if two captures overlap on one stream
+    tmp, exe = _build(str(tmp_path), "thread", False, "tsan_capture_driver.cpp")
+    r = subprocess.run([exe, "6"], cwd=tmp, env=_env("tsan", "halt_on_error=1"), capture_output=True, text=True,
+                       timeout=900)
+    assert "already capturing" not in r.stderr, r.stderr[-2000:]
+    assert r.returncode == 0, f"rc {r.returncode}\n{r.stdout[-2000:]}\n{r.stderr[-4000:]}"
+    assert r.stdout.splitlines()[-1] == "done"
+    assert "WARNING: ThreadSanitizer" not in r.stderr
