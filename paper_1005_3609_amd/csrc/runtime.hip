@@ -1936,6 +1936,25 @@ struct RowChain {
   hipStream_t s;
 };
 
+// The row's last read-out kernel for a chain of one chunk (one workgroup):
+// writes the row its counter names, then advances the counter itself, so a
+// row ends in one launch instead of two.  Every thread reads the counter
+// before the barrier; thread 0 writes it after.
+template <int V>
+__global__ void __launch_bounds__(256) k_reduce2_counted_bump(ReduceArgs a, int chunk, int* row, long row_stride) {
+  const int r = *row;
+  reduce2_tile<V>(a, chunk, a.out + static_cast<long>(r) * row_stride);
+  __syncthreads();
+  if (threadIdx.x == 0) *row = r + 1;
+}
+
+// Whether a chain's rows end in a read-out that can advance the counter
+// itself (evaluation form, one chunk).
+bool ends_in_counted_reduce(const RowChain& c, int per) {
+  const size_t len = c.rows->steps.size() / per;
+  return c.nch == 1 && len > 0 && c.rows->steps[len - 1].s.op == kOpReduce2 && c.j->t.V <= 4;
+}
+
 // Records `per` rows of every chain, step by step across the chains, each
 // row ending in a bump of that chain's own counter.  Chains never wait for
 // one another: a chunk group reads and writes only its own chunks, and the
@@ -1947,10 +1966,22 @@ void record_chains(const std::vector<RowChain>& ch, int per) {
     for (size_t i = 0; i < most; ++i)
       for (const RowChain& c : ch) {
         const size_t len = c.rows->steps.size() / per;
-        if (i < len)
-          launch_step(c.rows->steps[r * len + i].s, c.j->t, c.c0, c.nch, c.s, c.ctr, c.j->out_row_stride);
+        if (i >= len) continue;
+        const Step& s = c.rows->steps[r * len + i].s;
+        if (i + 1 == len && ends_in_counted_reduce(c, per)) {
+          const long stride = c.j->out_row_stride;
+          if (c.j->t.V == 1)
+            hipLaunchKernelGGL(k_reduce2_counted_bump<1>, dim3(1), dim3(256), 0, c.s, s.u.r, c.c0, c.ctr, stride);
+          else if (c.j->t.V == 2)
+            hipLaunchKernelGGL(k_reduce2_counted_bump<2>, dim3(1), dim3(256), 0, c.s, s.u.r, c.c0, c.ctr, stride);
+          else
+            hipLaunchKernelGGL(k_reduce2_counted_bump<4>, dim3(1), dim3(256), 0, c.s, s.u.r, c.c0, c.ctr, stride);
+        } else {
+          launch_step(s, c.j->t, c.c0, c.nch, c.s, c.ctr, c.j->out_row_stride);
+        }
       }
-    for (const RowChain& c : ch) hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, c.s, c.ctr);
+    for (const RowChain& c : ch)
+      if (!ends_in_counted_reduce(c, per)) hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, c.s, c.ctr);
     HIPX(hipGetLastError());
   }
 }
