@@ -1990,9 +1990,11 @@ void record_chains(const std::vector<RowChain>& ch, int per) {
 // ctr[g]): group 0 on `s0`, group g > 0 on the capture set's auxiliary
 // stream g - 1.
 void add_chains(std::vector<RowChain>& ch, const JobCtx& j, const Program& rows, int* ctr, hipStream_t s0,
-                const AuxStreams& a) {
+                const AuxStreams& a, int aux0 = 0) {
   const ChunkGroups g = chunk_groups(j.L.nchunk, j.t.streams);
-  for (int k = 0; k < g.n; ++k) ch.push_back(RowChain{&j, &rows, g.c0[k], g.nch[k], ctr + k, k ? a.s[k - 1] : s0});
+  if (aux0 + g.n - 1 > 3) throw std::runtime_error("more chunk-group chains than auxiliary streams");
+  for (int k = 0; k < g.n; ++k)
+    ch.push_back(RowChain{&j, &rows, g.c0[k], g.nch[k], ctr + k, k ? a.s[aux0 + k - 1] : s0});
 }
 
 // Sets the row counter of every chunk group of `j` to 1.
@@ -2141,15 +2143,19 @@ void run_graph_split(const JobCtx& ja, const JobCtx& jb, int n_max, int* ctr_a, 
       std::vector<RowChain> ch;
       add_chains(ch, ja, rows_pg[0], ctrs[0], cs, a);
       const size_t na = ch.size();
-      add_chains(ch, jb, rows_pg[1], ctrs[1], cb.s, a);
-      if (ch.size() != na + 1) throw std::runtime_error("the second job of a split runs one chunk group");
+      add_chains(ch, jb, rows_pg[1], ctrs[1], cb.s, a, static_cast<int>(na) - 1);
       HIPX(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       HIPX(hipEventRecord(cb.fork, cs));
       for (size_t k = 1; k < ch.size(); ++k) HIPX(hipStreamWaitEvent(ch[k].s, cb.fork, 0));
       record_chains(ch, per);
-      for (size_t k = 1; k < na; ++k) {
-        HIPX(hipEventRecord(a.join[k - 1], ch[k].s));
-        HIPX(hipStreamWaitEvent(cs, a.join[k - 1], 0));
+      // chains on auxiliary streams (all but the two jobs' first) join
+      // through those streams' events, the second job's first through the
+      // split stream's
+      for (size_t k = 1; k < ch.size(); ++k) {
+        if (k == na) continue;
+        const size_t ax = k < na ? k - 1 : k - 2;
+        HIPX(hipEventRecord(a.join[ax], ch[k].s));
+        HIPX(hipStreamWaitEvent(cs, a.join[ax], 0));
       }
       HIPX(hipEventRecord(cb.join, cb.s));
       HIPX(hipStreamWaitEvent(cs, cb.join, 0));
@@ -2709,8 +2715,8 @@ size_t job_workspace_bytes(int lattice, int m, int I, int n_max_hint, int mode, 
 // lanes_v 4 runs chunks of 256 instances.  When the instance count is not a
 // multiple of 256, the lanes of the last chunk past it would compute padding;
 // instead the first floor(I / 256) * 256 instances run at lanes_v 4 and the
-// rest as a second job at lanes_v 2 (1 for at most 64 instances), one chunk
-// group, on a parallel branch (batched and graph modes).  Instances are
+// rest as a second job at lanes_v 2 (1 for at most 64 instances), on a
+// parallel branch (batched and graph modes).  Instances are
 // independent, so the residues are the same.  Each job has its own region
 // of the workspace.
 struct SplitPlan {
@@ -2730,6 +2736,10 @@ SplitPlan split_plan(int lattice, int m, int I, int n_max_hint, int mode, const 
     sp.I[0] = I / 256 * 256;
     sp.I[1] = I - sp.I[0];
     sp.t[1] = t;
+    // lanes_v 1 for at most 64 left, else 2, one chunk group.  (128 left as
+    // two lanes_v 1 chains took the square 14x15 step from 8.32 to 8.25 ms
+    // but the 18x19 strip, whose vectors live in HBM, from about 720 to
+    // 741 ms: 256-byte rows gather less efficiently there.)
     sp.t[1].V = sp.I[1] <= 64 ? 1 : 2;
     sp.t[1].streams = 1;
   }

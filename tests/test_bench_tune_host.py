@@ -106,6 +106,7 @@ def test_lanes_v4_split_jobs():
     # multiple of 256 form a second job at lanes_v 2 (1 for at most 64)
     assert bench.split_jobs(640, 4) == [(512, 4), (128, 2)]
     assert bench.split_jobs(300, 4) == [(256, 4), (44, 1)]
+    assert bench.split_jobs(456, 4) == [(256, 4), (200, 2)]
     assert bench.split_jobs(768, 4) == [(768, 4)]
     assert bench.split_jobs(200, 4) == [(200, 4)]
     assert bench.split_jobs(640, 2) == [(640, 2)]

@@ -133,16 +133,18 @@ def test_tuning_choices_are_bit_identical(tune):
         np.testing.assert_array_equal(got, want, err_msg=f"{mode} {tune}")
 
 
-@pytest.mark.parametrize("nq", [41, 38, 64])
+@pytest.mark.parametrize("nq", [41, 38, 64, 144, 57])
 def test_lanes_v4_instance_split(nq):
     # 41 q x 8 p = 328 instances: 256 at lanes_v 4 and 72 at lanes_v 2 on a
     # parallel branch; 38 x 8 = 304: the 48 left run at lanes_v 1; 64 x 8 =
-    # 512: no split.  Same residues as the oracle in every mode and shape.
+    # 512: no split; 144 x 8 = 1152: four chunks of 256 (four chunk-group
+    # chains at streams 4) and 128 left; 57 x 8 = 456: 200 left.  Same
+    # residues as the oracle in every mode and shape.
     q, p = list(range(1, nq + 1)), [P31, 998244353, 1000000007, 2147483629, 2147483587, 1000000009,
                                     998244853, 2147483563]
     want = OT.chromatic_grid("square", 7, 5, q, p)
     for tune in (dict(lanes_v=4), dict(lanes_v=4, streams=2, fuse=2, stage=6, targets_per_wave=8),
-                 dict(lanes_v=4, streams=3, fuse=2, stage=4)):
+                 dict(lanes_v=4, streams=3, fuse=2, stage=4), dict(lanes_v=4, streams=4, fuse=2, stage=6)):
         for mode in ("batched", "graph"):
             got = api.strip("square", 7, 5, q, p, mode=mode, tuning=tune).astype(np.int64)
             np.testing.assert_array_equal(got, want, err_msg=f"{nq} {mode} {tune}")
