@@ -2320,14 +2320,25 @@ void run_grouped(const std::vector<const Program*>& progs, const Tune& t, void* 
   std::vector<Step*> d_steps;
   std::vector<int*> d_tiles;
   size_t off = 0;
+  // The cached graph depends on what its launches capture: the tuning, and
+  // per stage the table offsets, step and tile counts and the kernel chosen
+  // (general coefficients or not).  The step records themselves are read
+  // from the tables, uploaded before every launch, so their bytes (which
+  // hold padding and unused union members) are not hashed.
   uint64_t h = fnv1a(&t, sizeof(t));
   for (const StageImage& im : ims) {
     d_steps.push_back(reinterpret_cast<Step*>(b + off));
     off += align_up(im.steps.size() * sizeof(Step));
     d_tiles.push_back(reinterpret_cast<int*>(b + off));
     off += align_up(im.tile_start.size() * sizeof(int));
-    h = fnv1a(im.steps.data(), im.steps.size() * sizeof(Step), h);
+    const size_t ns = im.steps.size();
+    h = fnv1a(&ns, sizeof(ns), h);
     h = fnv1a(im.tile_start.data(), im.tile_start.size() * sizeof(int), h);
+    h = fnv1a(im.step_off.data(), im.step_off.size() * sizeof(int), h);
+    h = fnv1a(im.tile_off.data(), im.tile_off.size() * sizeof(int), h);
+    h = fnv1a(im.nsteps.data(), im.nsteps.size() * sizeof(int), h);
+    h = fnv1a(im.ntiles.data(), im.ntiles.size() * sizeof(int), h);
+    for (const Step& st_k : im.steps) h = fnv1a(&st_k.general, sizeof(st_k.general), h);
   }
   auto upload_all = [&]() {
     for (size_t g = 0; g < ims.size(); ++g) {

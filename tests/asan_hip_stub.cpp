@@ -43,7 +43,10 @@ hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t e, unsigned int) { (void)o
 // capturing (two host threads recording into one graph) aborts the replay.
 static std::mutex g_cap_mu;
 static std::set<hipStream_t>* g_capturing = new std::set<hipStream_t>;
+static std::atomic<long> g_captures{0};
+long hip_stub_captures(void) { return g_captures.load(); }
 hipError_t hipStreamBeginCapture(hipStream_t s, hipStreamCaptureMode) {
+  ++g_captures;
   std::lock_guard<std::mutex> lk(g_cap_mu);
   if (!g_capturing->insert(s).second) {
     fprintf(stderr, "HIP stand-in: a capture began on a stream that is already capturing\n");

@@ -134,3 +134,14 @@ def test_concurrent_graph_captures_are_serialised(tmp_path):
     assert r.returncode == 0, f"rc {r.returncode}\n{r.stdout[-2000:]}\n{r.stderr[-4000:]}"
     assert r.stdout.splitlines()[-1] == "done"
     assert "WARNING: ThreadSanitizer" not in r.stderr
+
+
+@pytest.mark.skipif(not (os.path.exists(HIPCC) and os.path.exists(CLANG)) or _san_runtime("asan") is None,
+                    reason="needs hipcc and clang's AddressSanitizer runtime")
+def test_repeated_batch_is_captured_once(tmp_path):
+    # the cached batch graph is keyed by what its launches capture; bytes the
+    # launches never read (padding, unused union members) must not make an
+    # identical batch miss the cache and be captured again
+    tmp, exe = _build(str(tmp_path), "address", False, "asan_batch_cache_driver.cpp")
+    r = _run([exe], tmp, env=_env("asan", "detect_leaks=0:abort_on_error=0"), timeout=600)
+    assert r.stdout.splitlines()[-1] == "captures 1", r.stdout[-500:]
