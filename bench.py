@@ -148,14 +148,23 @@ def cpu_baseline(lat, m, q_points, primes):
 
 
 def timed(torch, stream, fn, reps=1):
-    """Milliseconds per call of fn, HIP events on `stream`."""
+    """Milliseconds per call of fn, HIP events on `stream`.  Python's cyclic
+    garbage collector runs before the timed region and is paused inside it
+    (as timeit does): a collection over the interpreter's heap stalls the
+    host for tens of milliseconds while the device waits for the next call."""
+    import gc
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    gc.collect()
     torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(reps):
-        fn()
-    e1.record(stream)
-    torch.cuda.synchronize()
+    gc.disable()
+    try:
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+    finally:
+        gc.enable()
     return e0.elapsed_time(e1) / reps
 
 
