@@ -148,24 +148,29 @@ def cpu_baseline(lat, m, q_points, primes):
 
 
 def timed(torch, stream, fn, reps=1):
-    """Milliseconds per call of fn, HIP events on `stream`.  Python's cyclic
-    garbage collector runs before the timed region and is paused inside it
-    (as timeit does): a collection over the interpreter's heap stalls the
-    host for tens of milliseconds while the device waits for the next call."""
-    import gc
+    """Milliseconds per call of fn, HIP events on `stream`."""
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    gc.collect()
     torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def timed_no_gc(torch, stream, fn, reps=1):
+    """timed() with Python's cyclic garbage collector run first and paused
+    inside (as timeit does), for legs made of many short host calls: a
+    collection over the interpreter's heap stalls the host for tens of
+    milliseconds while the device waits for the next call."""
+    import gc
+    gc.collect()
     gc.disable()
     try:
-        e0.record(stream)
-        for _ in range(reps):
-            fn()
-        e1.record(stream)
-        torch.cuda.synchronize()
+        return timed(torch, stream, fn, reps)
     finally:
         gc.enable()
-    return e0.elapsed_time(e1) / reps
 
 
 def kernel_source_hash():
@@ -224,7 +229,7 @@ def bench_sweep(torch, stream, tune, steps):
     t = {k: v for k, v in t.items() if k not in ("mode", "ms", "streams")}
     outs, ws = api.batch(jobs, tuning=t, stream=stream)          # capture
     api.batch(jobs, tuning=t, workspace=ws, outs=outs, stream=stream)  # one warm replay, untimed
-    ms = timed(torch, stream, lambda: api.batch(jobs, tuning=t, workspace=ws, outs=outs, stream=stream), steps)
+    ms = timed_no_gc(torch, stream, lambda: api.batch(jobs, tuning=t, workspace=ws, outs=outs, stream=stream), steps)
     I = len(w["q_points"]) * len(w["primes"])
     upd = sum(updates_of(lat, m, n, I) for lat, m, n in w["strips"])
     wr = sum(written_of(lat, m, n, I, t.get("fuse") or 1) for lat, m, n in w["strips"])
